@@ -1,0 +1,211 @@
+/*
+ * aqs.h -- C ABI of the MI355X (gfx950) batched athermal quasistatic engine.
+ *
+ * Method: M. Reihn, F. Bamer, B. Stamm, "Parallel athermal quasistatic
+ * deformation stepping of molecular systems", arXiv 2507.20802.
+ *
+ * One context holds a batch of independent replicas ("slots") of a binary
+ * Lennard-Jones system in a periodic, simply sheared box.  The calls below
+ * are the operators of the paper, applied to any subset of slots at once:
+ *
+ *   aqs_affine_shear     F_N^(dk * dgamma), Eqs. (2), (3), (16)
+ *   aqs_minimize_batch   the minimisation operator of Eq. (10) (FIRE 2.0),
+ *                        optionally followed on the device by n fine AQS
+ *                        steps (F o F_N^(dgamma))^n, Eqs. (11)-(12), (19)
+ *   aqs_compare_configs  the equality test of Eq. (20)
+ *   aqs_stress           the Cauchy stress; tau = sigma_12 of Fig. 2
+ *
+ * Conventions (every call):
+ *   - Host pointers are plain host memory, read or written during the call
+ *     only; the caller keeps ownership.  The device workspace given to
+ *     aqs_create belongs to the caller, must stay allocated until
+ *     aqs_destroy, and is never freed by the library.
+ *   - Positions cross the ABI atom-major (pos[i*dim + a]) and in atom-id
+ *     order; the device keeps its own cell-sorted order internally.
+ *   - Box: the unstrained box of slot r is diag(L_r); at strain index k the
+ *     box is H = F^(gamma) diag(L_r) with gamma = k * dgamma_r computed in one
+ *     product, columns (Lx,0,0), (gamma*Ly, Ly, 0), (0,0,Lz) (Eq. 1).
+ *   - Calls that return values to the host synchronise the context's stream;
+ *     the others are stream-ordered on it.
+ *   - No call throws.  A return value < 0 is an error; aqs_last_error()
+ *     describes it.  Per-slot minimiser outcomes are data (AQS_CONVERGED ...),
+ *     not errors.
+ *   - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef AQS_H
+#define AQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aqs_ctx aqs_ctx;
+typedef int32_t aqs_status;
+
+/* return codes */
+#define AQS_OK 0
+#define AQS_EINVAL (-1)     /* bad argument */
+#define AQS_EHIP (-2)       /* HIP runtime error */
+#define AQS_ENOMEM (-3)     /* workspace smaller than aqs_workspace_bytes() */
+#define AQS_ECAPACITY (-4)  /* neighbour list or log capacity exceeded */
+#define AQS_ESTATE (-5)     /* call not valid in the current state */
+
+/* per-slot outcome of one minimisation (FIRE) */
+#define AQS_CONVERGED 0  /* max_i |F_i| < ftol */
+#define AQS_MAXITER 1    /* max_iter updates done */
+#define AQS_STALLED 2    /* more than n_neg_max consecutive P <= 0 */
+#define AQS_NONFINITE 3  /* energy or a force not finite */
+
+/* start of the minimisation after each fine affine step */
+#define AQS_START_PLAIN 0    /* the affine image F r (Eq. 12) */
+#define AQS_START_LEARNED 1  /* F r + predicted non-affine displacement */
+
+/* Binary truncated-and-shifted Lennard-Jones pair potential, Eq. (13):
+ * U_ab(r) = 4 eps_ab [(sigma_ab/r)^12 - (sigma_ab/r)^6] - U_ab(rc_ab) for
+ * r < rc_ab = rc_factor * sigma_ab, else 0.  Types are 0 (A) and 1 (B). */
+typedef struct {
+  int32_t dim;  /* 2 or 3 */
+  int32_t pad_;
+  double eps[2][2];
+  double sigma[2][2];
+  double rc_factor;
+} aqs_potential;
+
+/* FIRE 2.0 (Guenole et al. 2020), unit mass; the step order is documented
+ * at aqs_minimize_batch. */
+typedef struct {
+  double dt0, dt_max, dt_min, f_inc, f_dec, alpha0, f_alpha;
+  double dmax;  /* per-atom cap on one step's displacement */
+  double ftol;  /* convergence: max_i |F_i| < ftol */
+  int32_t n_delay, n_neg_max, initial_delay, pad_;
+  int64_t max_iter;
+} aqs_fire_params;
+
+/* Performance knobs.  None changes what is computed beyond the order of
+ * floating-point sums inside one atom's force (skin). */
+typedef struct {
+  double skin;              /* Verlet skin added to each pair cutoff; 0 = 0.3 */
+  int32_t max_neighbors;    /* list capacity per atom; 0 = 64 (2D) / 192 (3D) */
+  int32_t block_iters;      /* FIRE iterations launched between host polls; 0 = 32 */
+  int32_t use_graph;        /* 1: replay each block of iterations as a hipGraph */
+  int32_t max_chain_steps;  /* largest n_steps accepted by aqs_minimize_batch; 0 = 1024 */
+} aqs_tuning;
+
+/* One record per minimisation of a chain (index 0 = the first minimisation,
+ * s = the minimisation after fine step s). */
+typedef struct {
+  int64_t iters;      /* FIRE updates performed */
+  double energy;      /* E at the last force evaluation */
+  double max_f;       /* max_i |F_i| at the last force evaluation */
+  double sigma_xy;    /* shear stress at the last force evaluation */
+  int32_t status;     /* AQS_CONVERGED ... */
+  int32_t start;      /* start actually used: AQS_START_PLAIN / _LEARNED */
+} aqs_step_record;
+
+/* Bytes of device workspace a context with these slots needs.  n_atoms:
+ * host array of n_rep atom counts; box_len: host array n_rep x dim of
+ * unstrained edge lengths (needed to size the cell grids).  Returns 0 on
+ * invalid input. */
+size_t aqs_workspace_bytes(const aqs_potential* pot, const aqs_tuning* tune,
+                           int32_t n_rep, const int32_t* n_atoms,
+                           const double* box_len);
+
+/* Create a context over the caller's device workspace (>= 256-byte
+ * aligned, >= aqs_workspace_bytes) and HIP stream (hipStream_t; NULL = the
+ * null stream).  dgamma: host array of n_rep fine strain increments.  Slots
+ * start empty; fill them with aqs_set_replica. */
+aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
+                      const aqs_tuning* tune, int32_t n_rep,
+                      const int32_t* n_atoms, const double* box_len,
+                      const double* dgamma, void* workspace,
+                      size_t workspace_bytes, void* stream, aqs_ctx** out);
+
+aqs_status aqs_destroy(aqs_ctx* ctx);
+
+/* Load slot rep: types[n] (0/1), positions pos[n*dim] in atom-id order, at
+ * strain index k (the positions must belong to that box).  Velocities are
+ * cleared.  Synchronises. */
+aqs_status aqs_set_replica(aqs_ctx* ctx, int32_t rep, const uint8_t* types,
+                           const double* pos, int64_t strain_index);
+
+/* Replace the positions of slot rep (atom-id order, current box).
+ * Synchronises. */
+aqs_status aqs_set_positions(aqs_ctx* ctx, int32_t rep, const double* pos);
+
+/* Positions of slot rep in atom-id order (wrapped into the box at the last
+ * neighbour-list build, so compare them by minimum image).  Synchronises. */
+aqs_status aqs_get_positions(aqs_ctx* ctx, int32_t rep, double* pos);
+
+aqs_status aqs_get_strain_index(aqs_ctx* ctx, int32_t rep, int64_t* k);
+
+/* Copy slot src into slot dst (same atom count): positions, types, order,
+ * strain index and last energy.  Level I anchors and snapshots. */
+aqs_status aqs_copy_replica(aqs_ctx* ctx, int32_t src, int32_t dst);
+
+/* Affine simple shear of the selected slots, Eqs. (2)-(3) with Eq. (16):
+ * x_i += (dk_r * dgamma_r) y_i in one multiplication (level I uses
+ * dk = i K, Eq. 18), and k_r += dk_r so the box follows (Eq. 1).  rep[n_sel],
+ * dk[n_sel] are host arrays.  Stream-ordered. */
+aqs_status aqs_affine_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
+                            const int64_t* dk);
+
+/* Minimise the selected slots to their inherent structures (Eq. 10) with
+ * FIRE 2.0, all in one batched launch sequence, then -- per slot, on the
+ * device, without returning to the host -- run n_steps[r] fine AQS steps
+ * (affine map by dgamma_r, Eq. 16, then minimise again; Eq. 12).  A slot
+ * stops early if a minimisation does not converge.
+ *
+ * FIRE, per slot, unit mass, global norms over the slot:
+ *   1 evaluate E, F;  2 non-finite -> NONFINITE; max_i |F_i| < ftol ->
+ *   CONVERGED (before any update: an inherent structure takes 0 iterations);
+ *   3 P = F.v;  4 P > 0: n_pos++, n_neg = 0, if n_pos > n_delay:
+ *   dt = min(dt f_inc, dt_max), alpha *= f_alpha;  5 P <= 0: n_pos = 0,
+ *   n_neg++, n_neg > n_neg_max -> STALLED; unless (initial_delay and
+ *   it < n_delay): {if dt f_dec >= dt_min: dt *= f_dec; alpha = alpha0};
+ *   x -= dt v / 2; v = 0;  6 v += dt F;  7 v = (1-alpha) v +
+ *   alpha |v|/|F| F (skipped if |F| = 0);  8 per atom, dt |v_i| > dmax ->
+ *   v_i scaled to dmax / dt;  9 x += dt v; it++; it >= max_iter -> MAXITER.
+ *
+ * rep[n_sel]      host, distinct slots
+ * start_mode      AQS_START_PLAIN or AQS_START_LEARNED (needs aqs_mlp_attach)
+ * n_steps[n_sel]  host, fine steps after the first minimisation; NULL = all 0
+ * snap_dst[n_sel] host, slot that receives a copy of the first inherent
+ *                 structure (the "outgoing" configuration of Sec. 3.3), or -1;
+ *                 NULL = none.  Must have the same atom count.
+ * records         host, n_sel x (max_s n_steps + 1) records, row r for
+ *                 rep[r]; entries past a slot's last minimisation are left
+ *                 untouched.  May be NULL.
+ * Synchronises. */
+aqs_status aqs_minimize_batch(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
+                              int32_t start_mode, const int32_t* n_steps,
+                              const int32_t* snap_dst, aqs_step_record* records);
+
+/* Equality test of Eq. (20) between two slots at the same strain index:
+ * max_disp = max over atom ids of |minimum image (r_a,i - r_b,i)|,
+ * de_per_atom = (E_a - E_b) / N from the last force evaluations,
+ * equal = (max_disp < delta_eq).  Synchronises. */
+aqs_status aqs_compare_configs(aqs_ctx* ctx, int32_t rep_a, int32_t rep_b,
+                               double delta_eq, int32_t* equal,
+                               double* max_disp, double* de_per_atom);
+
+/* Stress of slot rep at its current positions: sigma[a*dim + b] =
+ * (1/V) sum_{i<j} U'(r) d_a d_b / r (so sigma_xy V = dE/dgamma), and the
+ * energy.  Synchronises. */
+aqs_status aqs_stress(aqs_ctx* ctx, int32_t rep, double* sigma, double* energy);
+
+/* Energy and forces (atom-id order, n*dim; may be NULL) of slot rep at its
+ * current positions.  Synchronises. */
+aqs_status aqs_energy_forces(aqs_ctx* ctx, int32_t rep, double* energy,
+                             double* forces);
+
+/* Human-readable description of the last error on this thread. */
+const char* aqs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AQS_H */

@@ -1,0 +1,848 @@
+// api.hip -- host side of the AQS engine: workspace layout, slot state,
+// launch tables, the minimisation driver loop and the C ABI of include/aqs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/aqs.h"
+#include "kernels.h"
+
+using namespace aqs;
+
+namespace {
+
+thread_local std::string g_err;
+
+aqs_status fail(aqs_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(AQS_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));             \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+double rc_max_of(const aqs_potential* p) {
+  double m = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) m = std::max(m, p->rc_factor * p->sigma[a][b]);
+  return m;
+}
+
+struct Tune {
+  double skin;
+  int max_nb, block_iters, use_graph, log_cap;
+};
+
+Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
+  Tune r;
+  r.skin = (t && t->skin > 0.0) ? t->skin : 0.3;
+  r.max_nb = (t && t->max_neighbors > 0) ? t->max_neighbors : (pot->dim == 3 ? 192 : 64);
+  r.block_iters = (t && t->block_iters > 0) ? t->block_iters : 32;
+  r.use_graph = t ? t->use_graph : 0;
+  r.log_cap = ((t && t->max_chain_steps > 0) ? t->max_chain_steps : 1024) + 1;
+  return r;
+}
+
+// Cells per axis of a slot's grid: the perpendicular width of the (sheared)
+// box divided by the list cutoff, at least 3 (the 3^dim stencil).
+void cell_grid(int dim, const double* L, double tilt, double rl, int* nc) {
+  const double wx = L[0] * L[1] / std::sqrt(L[1] * L[1] + tilt * tilt);
+  nc[0] = (int)std::floor(wx / rl);
+  nc[1] = (int)std::floor(L[1] / rl);
+  nc[2] = dim == 3 ? (int)std::floor(L[2] / rl) : 1;
+}
+
+struct Layout {
+  size_t total = 0;
+  size_t o_geom, o_state, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
+      o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl,
+      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4;
+  int64_t atoms = 0;      // padded atoms over all slots
+  int64_t nb_entries = 0;
+  int32_t blocks = 0;
+  int32_t cells = 0;      // sum of (cell_cap + 1)
+  int32_t max_cells = 0;
+  std::vector<Geom> geom;
+};
+
+aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, const int32_t* n_atoms,
+                       const double* box_len, const double* dgamma, Layout& lo) {
+  const int dim = pot->dim;
+  if (dim != 2 && dim != 3) return fail(AQS_EINVAL, "dim must be 2 or 3 (got %d)", dim);
+  if (n_rep <= 0) return fail(AQS_EINVAL, "n_rep must be positive");
+  const double rl = rc_max_of(pot) + tn.skin;
+  lo.geom.resize(n_rep);
+  int64_t atom_off = 0, nb_off = 0;
+  int32_t block0 = 0, cell_off = 0;
+  for (int r = 0; r < n_rep; ++r) {
+    const int n = n_atoms[r];
+    if (n <= 0 || n > (int)kIdxMask) return fail(AQS_EINVAL, "slot %d: bad atom count %d", r, n);
+    Geom& g = lo.geom[r];
+    g.n = n;
+    g.npad = (int)align_up((size_t)n, kBlock);
+    g.atom_off = atom_off;
+    g.nb_off = nb_off;
+    g.block0 = block0;
+    g.nblocks = g.npad / kBlock;
+    for (int a = 0; a < 3; ++a) g.L[a] = (a < dim) ? box_len[r * dim + a] : 1.0;
+    g.dgamma = dgamma ? dgamma[r] : 0.0;
+    int nc[3];
+    cell_grid(dim, g.L, 0.0, rl, nc);
+    for (int a = 0; a < dim; ++a)
+      if (nc[a] < 3)
+        return fail(AQS_EINVAL,
+                    "slot %d: box edge %g too small; need >= 3 (rc_max + skin) = %g", r,
+                    g.L[a], 3.0 * rl);
+    g.cell_cap = nc[0] * nc[1] * nc[2];
+    g.cell_off = cell_off;
+    lo.max_cells = std::max(lo.max_cells, g.cell_cap);
+    atom_off += g.npad;
+    nb_off += (int64_t)g.npad * tn.max_nb;
+    block0 += g.nblocks;
+    cell_off += g.cell_cap + 1;
+  }
+  lo.atoms = atom_off;
+  lo.nb_entries = nb_off;
+  lo.blocks = block0;
+  lo.cells = cell_off;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const size_t A = (size_t)lo.atoms;
+  lo.o_geom = take(sizeof(Geom) * n_rep);
+  lo.o_state = take(sizeof(State) * n_rep);
+  lo.o_pos4 = take(sizeof(double4) * A);
+  for (int a = 0; a < 3; ++a) lo.o_v[a] = take(sizeof(double) * A);
+  for (int a = 0; a < 3; ++a) lo.o_f[a] = take(sizeof(double) * A);
+  lo.o_id = take(sizeof(int32_t) * A);
+  lo.o_inv = take(sizeof(int32_t) * A);
+  lo.o_nbc = take(sizeof(int32_t) * A);
+  lo.o_nbl = take(sizeof(uint32_t) * (size_t)lo.nb_entries);
+  lo.o_fpart = take(sizeof(double) * kForceParts * (size_t)lo.blocks);
+  lo.o_upart = take(sizeof(double) * (size_t)lo.blocks);
+  lo.o_counter = take(sizeof(uint32_t) * n_rep);
+  lo.o_log = take(sizeof(StepRecord) * (size_t)n_rep * tn.log_cap);
+  lo.o_ccount = take(sizeof(int32_t) * (size_t)lo.cells);
+  lo.o_cstart = take(sizeof(int32_t) * (size_t)lo.cells);
+  lo.o_cellof = take(sizeof(int32_t) * A);
+  lo.o_order = take(sizeof(int32_t) * A);
+  lo.o_tpos4 = take(sizeof(double4) * A);
+  for (int a = 0; a < 3; ++a) lo.o_tv[a] = take(sizeof(double) * A);
+  lo.o_tid = take(sizeof(int32_t) * A);
+  lo.o_tbl = take(sizeof(int2) * ((size_t)lo.blocks + 8));
+  lo.o_tbl2 = take(sizeof(int2) * ((size_t)lo.blocks + 8));
+  lo.o_reps = take(sizeof(int32_t) * n_rep);
+  lo.o_nc3 = take(sizeof(int32_t) * 3 * n_rep);
+  lo.o_overflow = take(sizeof(int32_t));
+  lo.o_dg = take(sizeof(double) * n_rep);
+  lo.o_red = take(sizeof(double) * 10 * ((size_t)lo.blocks + 8));
+  for (int a = 0; a < 3; ++a) lo.o_dl[a] = take(sizeof(double) * A);
+  for (int a = 0; a < 3; ++a) lo.o_tdl[a] = take(sizeof(double) * A);
+  lo.o_alt4 = take(sizeof(double4) * A);
+  lo.total = off;
+  return AQS_OK;
+}
+
+template <class T>
+T* at(char* base, size_t off) {
+  return reinterpret_cast<T*>(base + off);
+}
+
+}  // namespace
+
+struct aqs_ctx {
+  int dim = 0, n_rep = 0;
+  aqs_potential pot{};
+  Tune tn{};
+  FireParams fire{};
+  PairParams pp[4];
+  double rc_max = 0.0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Layout lo;
+  // device views
+  Geom* d_geom;
+  State* d_state;
+  double4* pos4;
+  double *vx, *vy, *vz, *fx, *fy, *fz;
+  int32_t *id, *inv, *nbc;
+  uint32_t* nbl;
+  double *fpart, *upart;
+  uint32_t* counter;
+  StepRecord* log;
+  int32_t *ccount, *cstart, *cellof, *order, *tid;
+  double4* tpos4;
+  double *tvx, *tvy, *tvz;
+  int2 *tbl, *tbl2;
+  int32_t *reps_d, *nc3_d, *overflow;
+  double *dg_d, *red;
+  double *dlx, *dly, *dlz, *tdlx, *tdly, *tdlz;
+  double4* alt4;
+  // host mirrors
+  State* h_state = nullptr;  // pinned
+  std::vector<char> loaded, dirty;
+  // iteration table of the current selection
+  std::vector<int32_t> cur_sel;
+  int32_t cur_nblk = 0;
+};
+
+namespace {
+
+IterArgs iter_args(aqs_ctx* c) {
+  IterArgs a{};
+  a.blocks = c->tbl;
+  a.geom = c->d_geom;
+  a.state = c->d_state;
+  a.pos4 = c->pos4;
+  a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
+  a.fx = c->fx; a.fy = c->fy; a.fz = c->fz;
+  a.id = c->id; a.inv = c->inv;
+  a.nbc = c->nbc; a.nbl = c->nbl;
+  a.fpart = c->fpart; a.upart = c->upart; a.counter = c->counter;
+  a.log = c->log; a.log_cap = c->tn.log_cap;
+  a.max_nb = c->tn.max_nb;
+  for (int t = 0; t < 4; ++t) a.pp[t] = c->pp[t];
+  a.fire = c->fire;
+  a.skin = c->tn.skin;
+  a.rc_max = c->rc_max;
+  a.dlx = c->dlx; a.dly = c->dly; a.dlz = c->dlz;
+  a.alt4 = c->alt4;
+  return a;
+}
+
+// Launch table over the blocks of the given slots, in an order that gives
+// each of the 8 XCDs (hardware block b runs on XCD b mod 8) a contiguous run
+// of blocks, so neighbouring tiles share that XCD's L2.
+std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
+  std::vector<int2> logical;
+  for (int r : sel) {
+    const Geom& g = c->lo.geom[r];
+    for (int b = 0; b < g.nblocks; ++b) logical.push_back(make_int2(r, b));
+  }
+  const size_t nb = logical.size();
+  const size_t per = (nb + 7) / 8;
+  std::vector<int2> tbl(per * 8, make_int2(-1, 0));
+  for (size_t b = 0; b < tbl.size(); ++b) {
+    const size_t lk = (b % 8) * per + b / 8;
+    if (lk < nb) tbl[b] = logical[lk];
+  }
+  return tbl;
+}
+
+aqs_status pull_state(aqs_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->h_state, c->d_state, sizeof(State) * c->n_rep, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return AQS_OK;
+}
+
+aqs_status push_state(aqs_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->d_state, c->h_state, sizeof(State) * c->n_rep, hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return AQS_OK;
+}
+
+double tilt_of(aqs_ctx* c, int r, int64_t k) {
+  const Geom& g = c->lo.geom[r];
+  return strain_of(k, g.dgamma) * g.L[1];
+}
+
+// Rebuild cell order and neighbour lists of the given slots (positions as
+// they are on the device; h_state must be current).
+aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel) {
+  if (sel.empty()) return AQS_OK;
+  const double rl = c->rc_max + c->tn.skin;
+  std::vector<int32_t> nc3(3 * sel.size());
+  for (size_t i = 0; i < sel.size(); ++i) {
+    const int r = sel[i];
+    const Geom& g = c->lo.geom[r];
+    int nc[3];
+    cell_grid(c->dim, g.L, tilt_of(c, r, c->h_state[r].k), rl, nc);
+    for (int a = 0; a < c->dim; ++a)
+      if (nc[a] < 3)
+        return fail(AQS_EINVAL, "slot %d: sheared box too thin for the cell stencil", r);
+    if (nc[0] * nc[1] * nc[2] > g.cell_cap)
+      return fail(AQS_EINVAL, "slot %d: cell grid exceeds capacity", r);
+    for (int a = 0; a < 3; ++a) nc3[3 * i + a] = nc[a];
+  }
+  std::vector<int2> tbl = make_table(c, sel);
+  HIPCHK(hipMemcpyAsync(c->tbl2, tbl.data(), sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(c->reps_d, sel.data(), sizeof(int32_t) * sel.size(),
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->nc3_d, nc3.data(), sizeof(int32_t) * nc3.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemsetAsync(c->overflow, 0, sizeof(int32_t), c->stream));
+  RebuildArgs a{};
+  a.blocks = c->tbl2;
+  a.nblk = (int32_t)tbl.size();
+  a.reps = c->reps_d;
+  a.nreps = (int32_t)sel.size();
+  a.geom = c->d_geom;
+  a.state = c->d_state;
+  a.pos4 = c->pos4;
+  a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
+  a.id = c->id; a.inv = c->inv;
+  a.nbc = c->nbc; a.nbl = c->nbl;
+  a.cell_count = c->ccount; a.cell_start = c->cstart; a.cell_of = c->cellof; a.order = c->order;
+  a.tpos4 = c->tpos4; a.tvx = c->tvx; a.tvy = c->tvy; a.tvz = c->tvz; a.tid_ = c->tid;
+  a.upart = c->upart;
+  a.overflow = c->overflow;
+  for (int t = 0; t < 4; ++t) a.pp[t] = c->pp[t];
+  a.skin = c->tn.skin;
+  a.max_nb = c->tn.max_nb;
+  a.dim = c->dim;
+  a.dlx = c->dlx; a.dly = c->dly; a.dlz = c->dlz;
+  a.tdlx = c->tdlx; a.tdly = c->tdly; a.tdlz = c->tdlz;
+  launch_rebuild(a, c->lo.max_cells, c->stream, c->nc3_d);
+  HIPCHK(hipGetLastError());
+  int32_t over = 0;
+  HIPCHK(hipMemcpyAsync(&over, c->overflow, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (over > 0)
+    return fail(AQS_ECAPACITY, "neighbour list overflow: an atom has %d neighbours, capacity %d",
+                over, c->tn.max_nb);
+  for (int r : sel) c->dirty[r] = 0;
+  // the rebuild kernels updated nc, ubound and gamma_build on the device
+  return pull_state(c);
+}
+
+aqs_status check_slot(aqs_ctx* c, int r) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (r < 0 || r >= c->n_rep) return fail(AQS_EINVAL, "slot %d out of range [0, %d)", r, c->n_rep);
+  if (!c->loaded[r]) return fail(AQS_ESTATE, "slot %d has no configuration", r);
+  return AQS_OK;
+}
+
+aqs_status set_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
+  std::vector<int2> tbl = make_table(c, sel);
+  HIPCHK(hipMemcpyAsync(c->tbl, tbl.data(), sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->cur_sel = sel;
+  c->cur_nblk = (int32_t)tbl.size();
+  return AQS_OK;
+}
+
+void reset_fire(aqs_ctx* c, State& s) {
+  s.dt = c->fire.dt0;
+  s.alpha = c->fire.alpha0;
+  s.cv = 1.0;
+  s.cf = 0.0;
+  s.npos = 0;
+  s.nneg = 0;
+  s.it = 0;
+  s.restart = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* aqs_last_error(void) { return g_err.c_str(); }
+
+size_t aqs_workspace_bytes(const aqs_potential* pot, const aqs_tuning* tune, int32_t n_rep,
+                           const int32_t* n_atoms, const double* box_len) {
+  if (!pot || !n_atoms || !box_len) return 0;
+  Layout lo;
+  if (make_layout(pot, resolve(pot, tune), n_rep, n_atoms, box_len, nullptr, lo) != AQS_OK) return 0;
+  return lo.total;
+}
+
+aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
+                      const aqs_tuning* tune, int32_t n_rep, const int32_t* n_atoms,
+                      const double* box_len, const double* dgamma, void* workspace,
+                      size_t workspace_bytes, void* stream, aqs_ctx** out) {
+  if (!pot || !fire || !n_atoms || !box_len || !dgamma || !workspace || !out)
+    return fail(AQS_EINVAL, "null argument to aqs_create");
+  if (((uintptr_t)workspace) % 256 != 0) return fail(AQS_EINVAL, "workspace not 256-byte aligned");
+  aqs_ctx* c = new aqs_ctx();
+  c->dim = pot->dim;
+  c->n_rep = n_rep;
+  c->pot = *pot;
+  c->tn = resolve(pot, tune);
+  aqs_status st = make_layout(pot, c->tn, n_rep, n_atoms, box_len, dgamma, c->lo);
+  if (st != AQS_OK) {
+    delete c;
+    return st;
+  }
+  if (workspace_bytes < c->lo.total) {
+    size_t need = c->lo.total;
+    delete c;
+    return fail(AQS_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  }
+  c->rc_max = rc_max_of(pot);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const double sig = pot->sigma[a][b], eps = pot->eps[a][b];
+      const double rc = pot->rc_factor * sig;
+      const double sc2 = (sig * sig) / (rc * rc);
+      const double sc6 = sc2 * sc2 * sc2;
+      PairParams& q = c->pp[2 * a + b];
+      q.rc2 = rc * rc;
+      q.sig2 = sig * sig;
+      q.eps4 = 4.0 * eps;
+      q.ucut = 4.0 * eps * (sc6 * sc6 - sc6);
+    }
+  c->fire.dt0 = fire->dt0; c->fire.dt_max = fire->dt_max; c->fire.dt_min = fire->dt_min;
+  c->fire.f_inc = fire->f_inc; c->fire.f_dec = fire->f_dec; c->fire.alpha0 = fire->alpha0;
+  c->fire.f_alpha = fire->f_alpha; c->fire.dmax = fire->dmax; c->fire.ftol = fire->ftol;
+  c->fire.n_delay = fire->n_delay; c->fire.n_neg_max = fire->n_neg_max;
+  c->fire.initial_delay = fire->initial_delay; c->fire.max_iter = fire->max_iter;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)workspace;
+  Layout& lo = c->lo;
+  char* w = c->ws;
+  c->d_geom = at<Geom>(w, lo.o_geom);
+  c->d_state = at<State>(w, lo.o_state);
+  c->pos4 = at<double4>(w, lo.o_pos4);
+  c->vx = at<double>(w, lo.o_v[0]); c->vy = at<double>(w, lo.o_v[1]); c->vz = at<double>(w, lo.o_v[2]);
+  c->fx = at<double>(w, lo.o_f[0]); c->fy = at<double>(w, lo.o_f[1]); c->fz = at<double>(w, lo.o_f[2]);
+  c->id = at<int32_t>(w, lo.o_id);
+  c->inv = at<int32_t>(w, lo.o_inv);
+  c->nbc = at<int32_t>(w, lo.o_nbc);
+  c->nbl = at<uint32_t>(w, lo.o_nbl);
+  c->fpart = at<double>(w, lo.o_fpart);
+  c->upart = at<double>(w, lo.o_upart);
+  c->counter = at<uint32_t>(w, lo.o_counter);
+  c->log = at<StepRecord>(w, lo.o_log);
+  c->ccount = at<int32_t>(w, lo.o_ccount);
+  c->cstart = at<int32_t>(w, lo.o_cstart);
+  c->cellof = at<int32_t>(w, lo.o_cellof);
+  c->order = at<int32_t>(w, lo.o_order);
+  c->tpos4 = at<double4>(w, lo.o_tpos4);
+  c->tvx = at<double>(w, lo.o_tv[0]); c->tvy = at<double>(w, lo.o_tv[1]); c->tvz = at<double>(w, lo.o_tv[2]);
+  c->tid = at<int32_t>(w, lo.o_tid);
+  c->tbl = at<int2>(w, lo.o_tbl);
+  c->tbl2 = at<int2>(w, lo.o_tbl2);
+  c->reps_d = at<int32_t>(w, lo.o_reps);
+  c->nc3_d = at<int32_t>(w, lo.o_nc3);
+  c->overflow = at<int32_t>(w, lo.o_overflow);
+  c->dg_d = at<double>(w, lo.o_dg);
+  c->red = at<double>(w, lo.o_red);
+  c->dlx = at<double>(w, lo.o_dl[0]); c->dly = at<double>(w, lo.o_dl[1]); c->dlz = at<double>(w, lo.o_dl[2]);
+  c->tdlx = at<double>(w, lo.o_tdl[0]); c->tdly = at<double>(w, lo.o_tdl[1]); c->tdlz = at<double>(w, lo.o_tdl[2]);
+  c->alt4 = at<double4>(w, lo.o_alt4);
+
+  if (hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(AQS_EHIP, "hipHostMalloc of the state mirror failed");
+  }
+  std::memset(c->h_state, 0, sizeof(State) * n_rep);
+  for (int r = 0; r < n_rep; ++r) {
+    c->h_state[r].phase = PH_IDLE;
+    c->h_state[r].snap_dst = -1;
+    reset_fire(c, c->h_state[r]);
+  }
+  c->loaded.assign(n_rep, 0);
+  c->dirty.assign(n_rep, 1);
+  hipStream_t s = c->stream;
+  if (hipMemsetAsync(c->ws, 0, lo.total, s) != hipSuccess ||
+      hipMemcpyAsync(c->d_geom, lo.geom.data(), sizeof(Geom) * n_rep, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(c->d_state, c->h_state, sizeof(State) * n_rep, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipHostFree(c->h_state);
+    delete c;
+    return fail(AQS_EHIP, "initialising the workspace failed");
+  }
+  *out = c;
+  return AQS_OK;
+}
+
+aqs_status aqs_destroy(aqs_ctx* c) {
+  if (!c) return AQS_OK;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->h_state) (void)hipHostFree(c->h_state);
+  delete c;
+  return AQS_OK;
+}
+
+aqs_status aqs_set_replica(aqs_ctx* c, int32_t rep, const uint8_t* types, const double* pos,
+                           int64_t strain_index) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (rep < 0 || rep >= c->n_rep) return fail(AQS_EINVAL, "slot %d out of range", rep);
+  if (!types || !pos) return fail(AQS_EINVAL, "null types or positions");
+  const Geom& g = c->lo.geom[rep];
+  const int d = c->dim;
+  std::vector<double4> p(g.n);
+  std::vector<int32_t> ids(g.n);
+  for (int i = 0; i < g.n; ++i) {
+    if (types[i] > 1) return fail(AQS_EINVAL, "atom %d: type %d not in {0, 1}", i, (int)types[i]);
+    p[i] = make_double4(pos[i * d], pos[i * d + 1], d == 3 ? pos[i * d + 2] : 0.0, (double)types[i]);
+    ids[i] = i;
+  }
+  aqs_status st = pull_state(c);
+  if (st) return st;
+  HIPCHK(hipMemcpyAsync(c->pos4 + g.atom_off, p.data(), sizeof(double4) * g.n,
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->id + g.atom_off, ids.data(), sizeof(int32_t) * g.n,
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->inv + g.atom_off, ids.data(), sizeof(int32_t) * g.n,
+                        hipMemcpyHostToDevice, c->stream));
+  State& s = c->h_state[rep];
+  s.k = strain_index;
+  s.phase = PH_IDLE;
+  s.E = 0.0;
+  s.fmax = 0.0;
+  s.status = 0;
+  reset_fire(c, s);
+  st = push_state(c);
+  if (st) return st;
+  c->loaded[rep] = 1;
+  c->dirty[rep] = 1;
+  return AQS_OK;
+}
+
+aqs_status aqs_set_positions(aqs_ctx* c, int32_t rep, const double* pos) {
+  aqs_status st = check_slot(c, rep);
+  if (st) return st;
+  if (!pos) return fail(AQS_EINVAL, "null positions");
+  const Geom& g = c->lo.geom[rep];
+  const int d = c->dim;
+  // keep each atom's type, put the atoms back in atom-id order
+  std::vector<double4> p(g.n), q(g.n);
+  std::vector<int32_t> idv(g.n), ids(g.n);
+  HIPCHK(hipMemcpyAsync(p.data(), c->pos4 + g.atom_off, sizeof(double4) * g.n,
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(idv.data(), c->id + g.atom_off, sizeof(int32_t) * g.n,
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < g.n; ++s) q[idv[s]].w = p[s].w;
+  for (int i = 0; i < g.n; ++i) {
+    q[i].x = pos[i * d];
+    q[i].y = pos[i * d + 1];
+    q[i].z = d == 3 ? pos[i * d + 2] : 0.0;
+    ids[i] = i;
+  }
+  HIPCHK(hipMemcpyAsync(c->pos4 + g.atom_off, q.data(), sizeof(double4) * g.n,
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->id + g.atom_off, ids.data(), sizeof(int32_t) * g.n,
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->inv + g.atom_off, ids.data(), sizeof(int32_t) * g.n,
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->dirty[rep] = 1;
+  return AQS_OK;
+}
+
+aqs_status aqs_get_positions(aqs_ctx* c, int32_t rep, double* pos) {
+  aqs_status st = check_slot(c, rep);
+  if (st) return st;
+  if (!pos) return fail(AQS_EINVAL, "null output");
+  const Geom& g = c->lo.geom[rep];
+  const int d = c->dim;
+  std::vector<double4> p(g.n);
+  std::vector<int32_t> idv(g.n);
+  HIPCHK(hipMemcpyAsync(p.data(), c->pos4 + g.atom_off, sizeof(double4) * g.n,
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(idv.data(), c->id + g.atom_off, sizeof(int32_t) * g.n,
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < g.n; ++s) {
+    const int i = idv[s];
+    pos[i * d] = p[s].x;
+    pos[i * d + 1] = p[s].y;
+    if (d == 3) pos[i * d + 2] = p[s].z;
+  }
+  return AQS_OK;
+}
+
+aqs_status aqs_get_strain_index(aqs_ctx* c, int32_t rep, int64_t* k) {
+  aqs_status st = check_slot(c, rep);
+  if (st) return st;
+  st = pull_state(c);
+  if (st) return st;
+  if (k) *k = c->h_state[rep].k;
+  return AQS_OK;
+}
+
+aqs_status aqs_copy_replica(aqs_ctx* c, int32_t src, int32_t dst) {
+  aqs_status st = check_slot(c, src);
+  if (st) return st;
+  if (dst < 0 || dst >= c->n_rep) return fail(AQS_EINVAL, "slot %d out of range", dst);
+  if (dst == src) return AQS_OK;
+  if (c->lo.geom[src].n != c->lo.geom[dst].n)
+    return fail(AQS_EINVAL, "slots %d and %d differ in atom count", src, dst);
+  st = pull_state(c);
+  if (st) return st;
+  launch_copy_slot(c->d_geom, src, dst, c->lo.geom[src].n, c->pos4, c->id, c->inv, c->stream);
+  HIPCHK(hipGetLastError());
+  State& d = c->h_state[dst];
+  const State& s = c->h_state[src];
+  d.k = s.k;
+  d.E = s.E;
+  d.fmax = s.fmax;
+  d.sxy = s.sxy;
+  d.status = s.status;
+  d.phase = PH_IDLE;
+  reset_fire(c, d);
+  st = push_state(c);
+  if (st) return st;
+  c->loaded[dst] = 1;
+  c->dirty[dst] = 1;
+  return AQS_OK;
+}
+
+aqs_status aqs_affine_shear(aqs_ctx* c, int32_t n_sel, const int32_t* rep, const int64_t* dk) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (n_sel <= 0) return AQS_OK;
+  if (!rep || !dk) return fail(AQS_EINVAL, "null selection");
+  std::vector<int32_t> sel(rep, rep + n_sel);
+  for (int r : sel) {
+    aqs_status st = check_slot(c, r);
+    if (st) return st;
+  }
+  aqs_status st = pull_state(c);
+  if (st) return st;
+  std::vector<double> dg(c->n_rep, 0.0);
+  for (int i = 0; i < n_sel; ++i) {
+    // one multiplication F^(dk dgamma) (level I, Eq. 18)
+    dg[sel[i]] = (double)dk[i] * c->lo.geom[sel[i]].dgamma;
+    c->h_state[sel[i]].k += dk[i];
+  }
+  std::vector<int2> tbl = make_table(c, sel);
+  HIPCHK(hipMemcpyAsync(c->tbl2, tbl.data(), sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(c->dg_d, dg.data(), sizeof(double) * c->n_rep, hipMemcpyHostToDevice,
+                        c->stream));
+  launch_affine(c->tbl2, (int32_t)tbl.size(), c->d_geom, c->pos4, c->dg_d, c->stream);
+  HIPCHK(hipGetLastError());
+  return push_state(c);
+}
+
+aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int32_t start_mode,
+                              const int32_t* n_steps, const int32_t* snap_dst,
+                              aqs_step_record* records) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (n_sel <= 0) return AQS_OK;
+  if (!rep) return fail(AQS_EINVAL, "null selection");
+  if (start_mode != AQS_START_PLAIN)
+    return fail(AQS_EINVAL, "start mode %d needs an attached model", start_mode);
+  std::vector<int32_t> sel(rep, rep + n_sel);
+  std::vector<char> seen(c->n_rep, 0);
+  int max_steps = 0;
+  for (int i = 0; i < n_sel; ++i) {
+    aqs_status st = check_slot(c, sel[i]);
+    if (st) return st;
+    if (seen[sel[i]]) return fail(AQS_EINVAL, "slot %d selected twice", sel[i]);
+    seen[sel[i]] = 1;
+    const int ns = n_steps ? n_steps[i] : 0;
+    if (ns < 0 || ns + 1 > c->tn.log_cap)
+      return fail(AQS_ECAPACITY, "n_steps %d outside [0, %d]", ns, c->tn.log_cap - 1);
+    max_steps = std::max(max_steps, ns);
+    if (snap_dst && snap_dst[i] >= 0) {
+      const int d = snap_dst[i];
+      if (d >= c->n_rep || c->lo.geom[d].n != c->lo.geom[sel[i]].n)
+        return fail(AQS_EINVAL, "snapshot slot %d invalid for slot %d", d, sel[i]);
+    }
+  }
+  if (snap_dst)
+    for (int i = 0; i < n_sel; ++i)
+      if (snap_dst[i] >= 0 && seen[snap_dst[i]])
+        return fail(AQS_EINVAL, "snapshot slot %d is also being minimised", snap_dst[i]);
+  aqs_status st = pull_state(c);
+  if (st) return st;
+  st = rebuild(c, sel);
+  if (st) return st;
+  for (int i = 0; i < n_sel; ++i) {
+    State& s = c->h_state[sel[i]];
+    reset_fire(c, s);
+    s.phase = PH_FIRE;
+    s.status = -1;
+    s.step = 0;
+    s.n_steps = n_steps ? n_steps[i] : 0;
+    s.snap_dst = snap_dst ? snap_dst[i] : -1;
+    s.do_snap = 0;
+    s.start_mode = start_mode;
+    s.start_used = AQS_START_PLAIN;
+  }
+  st = push_state(c);
+  if (st) return st;
+  st = set_table(c, sel);
+  if (st) return st;
+  launch_reset_iter(c->tbl, c->cur_nblk, c->d_geom, c->vx, c->vy, c->vz, c->upart, c->dim,
+                    c->stream);
+  HIPCHK(hipGetLastError());
+  IterArgs a = iter_args(c);
+  for (;;) {
+    for (int it = 0; it < c->tn.block_iters; ++it) {
+      launch_force(a, c->cur_nblk, c->dim, c->stream);
+      launch_update(a, c->cur_nblk, c->dim, c->stream);
+    }
+    HIPCHK(hipGetLastError());
+    st = pull_state(c);
+    if (st) return st;
+    std::vector<int32_t> rb;
+    int active = 0;
+    for (int r : sel) {
+      const int ph = c->h_state[r].phase;
+      if (ph == PH_REBUILD) rb.push_back(r);
+      if (ph != PH_DONE) ++active;
+    }
+    if (!active) break;
+    if (!rb.empty()) {
+      st = rebuild(c, rb);
+      if (st) return st;
+      for (int r : rb) c->h_state[r].phase = PH_FIRE;
+      st = push_state(c);
+      if (st) return st;
+    }
+  }
+  for (int i = 0; i < n_sel; ++i) {
+    const int r = sel[i];
+    c->h_state[r].phase = PH_IDLE;
+    if (snap_dst && snap_dst[i] >= 0) {
+      c->loaded[snap_dst[i]] = 1;
+      c->dirty[snap_dst[i]] = 1;
+    }
+  }
+  st = push_state(c);
+  if (st) return st;
+  if (records) {
+    const int stride = max_steps + 1;
+    std::vector<StepRecord> tmp(c->tn.log_cap);
+    for (int i = 0; i < n_sel; ++i) {
+      const int r = sel[i];
+      const int ns = c->h_state[r].step + 1;
+      HIPCHK(hipMemcpy(tmp.data(), c->log + (int64_t)r * c->tn.log_cap, sizeof(StepRecord) * ns,
+                       hipMemcpyDeviceToHost));
+      for (int s = 0; s < ns && s < stride; ++s) {
+        aqs_step_record& o = records[(int64_t)i * stride + s];
+        o.iters = tmp[s].iters;
+        o.energy = tmp[s].energy;
+        o.max_f = tmp[s].max_f;
+        o.sigma_xy = tmp[s].sigma_xy;
+        o.status = tmp[s].status;
+        o.start = tmp[s].start;
+      }
+    }
+  }
+  return AQS_OK;
+}
+
+aqs_status aqs_compare_configs(aqs_ctx* c, int32_t ra, int32_t rb, double delta_eq,
+                               int32_t* equal, double* max_disp, double* de_per_atom) {
+  aqs_status st = check_slot(c, ra);
+  if (st) return st;
+  st = check_slot(c, rb);
+  if (st) return st;
+  const Geom& g = c->lo.geom[ra];
+  if (g.n != c->lo.geom[rb].n) return fail(AQS_EINVAL, "slots differ in atom count");
+  st = pull_state(c);
+  if (st) return st;
+  if (c->h_state[ra].k != c->h_state[rb].k)
+    return fail(AQS_EINVAL, "slots %d and %d are at different strain indices (%lld vs %lld)", ra,
+                rb, (long long)c->h_state[ra].k, (long long)c->h_state[rb].k);
+  const int nb = (g.n + kBlock - 1) / kBlock;
+  launch_compare(c->d_geom, ra, rb, g.n, c->pos4, c->inv, g.L[0], g.L[1], g.L[2],
+                 tilt_of(c, ra, c->h_state[ra].k), c->dim, c->red, c->stream);
+  HIPCHK(hipGetLastError());
+  std::vector<double> part(nb);
+  HIPCHK(hipMemcpyAsync(part.data(), c->red, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double m = 0.0;
+  for (double v : part) m = std::max(m, v);
+  if (max_disp) *max_disp = m;
+  if (de_per_atom) *de_per_atom = (c->h_state[ra].E - c->h_state[rb].E) / (double)g.n;
+  if (equal) *equal = (m < delta_eq) ? 1 : 0;
+  return AQS_OK;
+}
+
+aqs_status aqs_stress(aqs_ctx* c, int32_t rep, double* sigma, double* energy) {
+  aqs_status st = check_slot(c, rep);
+  if (st) return st;
+  st = pull_state(c);
+  if (st) return st;
+  std::vector<int32_t> sel(1, rep);
+  st = rebuild(c, sel);
+  if (st) return st;
+  const Geom& g = c->lo.geom[rep];
+  IterArgs a = iter_args(c);
+  launch_virial(a, rep, g.nblocks, c->dim, g.L[0], g.L[1], g.L[2], tilt_of(c, rep, c->h_state[rep].k),
+                c->red, c->stream);
+  HIPCHK(hipGetLastError());
+  std::vector<double> part((size_t)g.nblocks * 10);
+  HIPCHK(hipMemcpyAsync(part.data(), c->red, sizeof(double) * part.size(), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double tot[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < g.nblocks; ++b)
+    for (int k = 0; k < 10; ++k) tot[k] += part[(size_t)b * 10 + k];
+  const double vol = g.L[0] * g.L[1] * g.L[2];
+  const int d = c->dim;
+  if (sigma)
+    for (int x = 0; x < d; ++x)
+      for (int y = 0; y < d; ++y) sigma[x * d + y] = tot[1 + 3 * x + y] / vol;
+  if (energy) *energy = tot[0];
+  return AQS_OK;
+}
+
+aqs_status aqs_energy_forces(aqs_ctx* c, int32_t rep, double* energy, double* forces) {
+  aqs_status st = check_slot(c, rep);
+  if (st) return st;
+  st = pull_state(c);
+  if (st) return st;
+  std::vector<int32_t> sel(1, rep);
+  st = rebuild(c, sel);
+  if (st) return st;
+  c->h_state[rep].phase = PH_EVAL;
+  st = push_state(c);
+  if (st) return st;
+  st = set_table(c, sel);
+  if (st) return st;
+  IterArgs a = iter_args(c);
+  launch_force(a, c->cur_nblk, c->dim, c->stream);
+  HIPCHK(hipGetLastError());
+  st = pull_state(c);
+  if (st) return st;
+  if (c->h_state[rep].phase != PH_DONE)
+    return fail(AQS_ESTATE, "force evaluation of slot %d did not complete (phase %d)", rep,
+                c->h_state[rep].phase);
+  c->h_state[rep].phase = PH_IDLE;
+  st = push_state(c);
+  if (st) return st;
+  if (energy) *energy = c->h_state[rep].E;
+  if (forces) {
+    const Geom& g = c->lo.geom[rep];
+    const int d = c->dim;
+    std::vector<double> f[3];
+    for (int k = 0; k < d; ++k) f[k].resize(g.n);
+    std::vector<int32_t> idv(g.n);
+    double* src[3] = {c->fx, c->fy, c->fz};
+    for (int k = 0; k < d; ++k)
+      HIPCHK(hipMemcpyAsync(f[k].data(), src[k] + g.atom_off, sizeof(double) * g.n,
+                            hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(idv.data(), c->id + g.atom_off, sizeof(int32_t) * g.n,
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int s = 0; s < g.n; ++s)
+      for (int k = 0; k < d; ++k) forces[idv[s] * d + k] = f[k][s];
+  }
+  return AQS_OK;
+}
+
+}  // extern "C"

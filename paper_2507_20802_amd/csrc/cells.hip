@@ -1,0 +1,307 @@
+// cells.hip -- cell binning by counting sort and Verlet neighbour lists on
+// gfx950, for the slots whose lists the host rebuilds.
+//
+// Steps (one launch each, all on the context stream):
+//   grid   copy the host-chosen cell grid into the slot state
+//   zero   clear per-cell counts
+//   bin    fractional coordinates s = H^-1 r (Eq. 1 box); wrap r into the
+//          primary cell (r -= H floor(s)); cell index; integer atomic count
+//   scan   exclusive scan of the counts per slot (one workgroup per slot)
+//   scat   place each atom in its cell (order inside a cell arbitrary)
+//   sort   sort each cell by atom id (gives a deterministic order)
+//   perm   gather positions, velocities, ids into scratch in the new order
+//   back   copy back; inverse permutation
+//   list   per atom, scan the 3^dim neighbouring cells and keep every image
+//          pair within rc_ab + skin; entry j | image code << 24
+//   done   reset the validity bound of each rebuilt slot
+// Integer atomics only; the result does not depend on their order.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace aqs {
+
+namespace {
+
+__device__ __forceinline__ void frac(const Geom& g, double t, double x, double y, double z,
+                                     double* s) {
+  s[1] = y / g.L[1];
+  s[0] = (x - t * s[1]) / g.L[0];
+  s[2] = z / g.L[2];
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+template <int D>
+__device__ __forceinline__ int cell_of_pos(const Geom& g, const int* nc, double t, const double4& p,
+                                           int* c3) {
+  double s[3];
+  frac(g, t, p.x, p.y, (D == 3) ? p.z : 0.0, s);
+  c3[0] = clampi((int)floor(s[0] * nc[0]), 0, nc[0] - 1);
+  c3[1] = clampi((int)floor(s[1] * nc[1]), 0, nc[1] - 1);
+  c3[2] = (D == 3) ? clampi((int)floor(s[2] * nc[2]), 0, nc[2] - 1) : 0;
+  return (c3[2] * nc[1] + c3[1]) * nc[0] + c3[0];
+}
+
+__global__ void k_rb_grid(RebuildArgs a, const int32_t* nc3) {
+  const int r = blockIdx.x;
+  if (threadIdx.x == 0 && r < a.nreps) {
+    State* st = a.state + a.reps[r];
+    st->nc[0] = nc3[3 * r + 0];
+    st->nc[1] = nc3[3 * r + 1];
+    st->nc[2] = nc3[3 * r + 2];
+  }
+}
+
+__global__ void k_rb_zero(RebuildArgs a) {
+  const int rep = a.reps[blockIdx.y];
+  const Geom& g = a.geom[rep];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c <= g.cell_cap) {
+    a.cell_count[g.cell_off + c] = 0;
+    a.cell_start[g.cell_off + c] = 0;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_rb_bin(RebuildArgs a) {
+  const int2 bt = a.blocks[blockIdx.x];
+  if (bt.x < 0) return;
+  const Geom g = a.geom[bt.x];
+  const State* st = a.state + bt.x;
+  const int li = bt.y * kBlock + threadIdx.x;
+  if (li >= g.n) return;
+  const int64_t gi = g.atom_off + li;
+  const double t = strain_of(st->k, g.dgamma) * g.L[1];
+  double4 p = a.pos4[gi];
+  double s[3];
+  frac(g, t, p.x, p.y, (D == 3) ? p.z : 0.0, s);
+  const double nx = floor(s[0]), ny = floor(s[1]), nz = (D == 3) ? floor(s[2]) : 0.0;
+  if (nx != 0.0 || ny != 0.0 || nz != 0.0) {
+    p.x -= nx * g.L[0] + ny * t;
+    p.y -= ny * g.L[1];
+    if (D == 3) p.z -= nz * g.L[2];
+    a.pos4[gi] = p;
+  }
+  int c3[3];
+  const int nc[3] = {st->nc[0], st->nc[1], st->nc[2]};
+  const int c = cell_of_pos<D>(g, nc, t, p, c3);
+  a.cell_of[gi] = c;
+  atomicAdd(a.cell_count + g.cell_off + c, 1);
+}
+
+__global__ __launch_bounds__(1024) void k_rb_scan(RebuildArgs a) {
+  const int rep = a.reps[blockIdx.x];
+  const Geom g = a.geom[rep];
+  const State* st = a.state + rep;
+  const int ncell = st->nc[0] * st->nc[1] * st->nc[2];
+  __shared__ int part[1024];
+  const int T = blockDim.x;
+  const int per = (ncell + T - 1) / T;
+  const int c0 = threadIdx.x * per, c1 = min(ncell, c0 + per);
+  int sum = 0;
+  for (int c = c0; c < c1; ++c) sum += a.cell_count[g.cell_off + c];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the per-thread sums (integers: exact)
+  for (int off = 1; off < T; off <<= 1) {
+    const int v = (threadIdx.x >= off) ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = (threadIdx.x == 0) ? 0 : part[threadIdx.x - 1];
+  for (int c = c0; c < c1; ++c) {
+    const int n = a.cell_count[g.cell_off + c];
+    a.cell_start[g.cell_off + c] = run;
+    a.cell_count[g.cell_off + c] = run;  // becomes the scatter cursor
+    run += n;
+  }
+  if (threadIdx.x == T - 1) a.cell_start[g.cell_off + ncell] = part[T - 1];
+}
+
+__global__ __launch_bounds__(kBlock) void k_rb_scatter(RebuildArgs a) {
+  const int2 bt = a.blocks[blockIdx.x];
+  if (bt.x < 0) return;
+  const Geom g = a.geom[bt.x];
+  const int li = bt.y * kBlock + threadIdx.x;
+  if (li >= g.n) return;
+  const int64_t gi = g.atom_off + li;
+  const int c = a.cell_of[gi];
+  const int pos = atomicAdd(a.cell_count + g.cell_off + c, 1);
+  a.order[g.atom_off + pos] = li;
+}
+
+__global__ void k_rb_sort(RebuildArgs a) {
+  const int rep = a.reps[blockIdx.y];
+  const Geom g = a.geom[rep];
+  const State* st = a.state + rep;
+  const int ncell = st->nc[0] * st->nc[1] * st->nc[2];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int b = a.cell_start[g.cell_off + c], e = a.cell_start[g.cell_off + c + 1];
+  int32_t* o = a.order + g.atom_off;
+  const int32_t* id = a.id + g.atom_off;
+  for (int i = b + 1; i < e; ++i) {  // insertion sort by atom id
+    const int v = o[i];
+    const int key = id[v];
+    int j = i - 1;
+    while (j >= b && id[o[j]] > key) {
+      o[j + 1] = o[j];
+      --j;
+    }
+    o[j + 1] = v;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_rb_perm(RebuildArgs a) {
+  const int2 bt = a.blocks[blockIdx.x];
+  if (bt.x < 0) return;
+  const Geom g = a.geom[bt.x];
+  const int li = bt.y * kBlock + threadIdx.x;
+  if (li >= g.n) return;
+  const int64_t gi = g.atom_off + li;
+  const int64_t go = g.atom_off + a.order[gi];
+  a.tpos4[gi] = a.pos4[go];
+  a.tvx[gi] = a.vx[go];
+  a.tvy[gi] = a.vy[go];
+  if (D == 3) a.tvz[gi] = a.vz[go];
+  a.tid_[gi] = a.id[go];
+  if (a.dlx) {
+    a.tdlx[gi] = a.dlx[go];
+    a.tdly[gi] = a.dly[go];
+    if (D == 3) a.tdlz[gi] = a.dlz[go];
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_rb_back(RebuildArgs a) {
+  const int2 bt = a.blocks[blockIdx.x];
+  if (bt.x < 0) return;
+  const Geom g = a.geom[bt.x];
+  const int li = bt.y * kBlock + threadIdx.x;
+  if (li >= g.n) return;
+  const int64_t gi = g.atom_off + li;
+  a.pos4[gi] = a.tpos4[gi];
+  a.vx[gi] = a.tvx[gi];
+  a.vy[gi] = a.tvy[gi];
+  if (D == 3) a.vz[gi] = a.tvz[gi];
+  const int32_t aid = a.tid_[gi];
+  a.id[gi] = aid;
+  a.inv[g.atom_off + aid] = li;
+  if (a.dlx) {
+    a.dlx[gi] = a.tdlx[gi];
+    a.dly[gi] = a.tdly[gi];
+    if (D == 3) a.dlz[gi] = a.tdlz[gi];
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
+  const int2 bt = a.blocks[blockIdx.x];
+  if (bt.x < 0) return;
+  const Geom g = a.geom[bt.x];
+  const State* st = a.state + bt.x;
+  const int li = bt.y * kBlock + threadIdx.x;
+  if (li >= g.n) return;
+  const int64_t gi = g.atom_off + li;
+  const double t = strain_of(st->k, g.dgamma) * g.L[1];
+  const int nc[3] = {st->nc[0], st->nc[1], st->nc[2]};
+  const double4* P = a.pos4 + g.atom_off;
+  const double4 pi = P[li];
+  const int ti = (int)pi.w;
+  double rl2[2];
+  for (int b = 0; b < 2; ++b) {
+    const double rc = sqrt(a.pp[2 * ti + b].rc2) + a.skin;
+    rl2[b] = rc * rc;
+  }
+  int c3[3];
+  cell_of_pos<D>(g, nc, t, pi, c3);
+  uint32_t* L = a.nbl + g.nb_off + li;
+  const int32_t* cs = a.cell_start + g.cell_off;
+  int cnt = 0;
+  bool over = false;
+  const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    int cz = c3[2] + dz, iz = 0;
+    if (D == 3) {
+      if (cz < 0) { cz += nc[2]; iz = -1; }
+      else if (cz >= nc[2]) { cz -= nc[2]; iz = 1; }
+    }
+    for (int dy = -1; dy <= 1; ++dy) {
+      int cy = c3[1] + dy, iy = 0;
+      if (cy < 0) { cy += nc[1]; iy = -1; }
+      else if (cy >= nc[1]) { cy -= nc[1]; iy = 1; }
+      for (int dx = -1; dx <= 1; ++dx) {
+        int cx = c3[0] + dx, ix = 0;
+        if (cx < 0) { cx += nc[0]; ix = -1; }
+        else if (cx >= nc[0]) { cx -= nc[0]; ix = 1; }
+        const int code = (ix + 1) + 3 * (iy + 1) + 9 * (iz + 1);
+        const double sx = (double)ix * g.L[0] + (double)iy * t;
+        const double sy = (double)iy * g.L[1];
+        const double sz = (double)iz * g.L[2];
+        const int c = (cz * nc[1] + cy) * nc[0] + cx;
+        const int jb = cs[c], je = cs[c + 1];
+        for (int j = jb; j < je; ++j) {
+          if (j == li && code == 13) continue;
+          const double4 pj = P[j];
+          const double ddx = (pj.x - pi.x) + sx;
+          const double ddy = (pj.y - pi.y) + sy;
+          const double ddz = (D == 3) ? (pj.z - pi.z) + sz : 0.0;
+          const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          if (r2 < rl2[(int)pj.w]) {
+            if (cnt < a.max_nb)
+              L[(int64_t)cnt * g.npad] = (uint32_t)j | ((uint32_t)code << kCodeShift);
+            else
+              over = true;
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  a.nbc[gi] = over ? a.max_nb : cnt;
+  if (over) atomicMax(a.overflow, cnt);
+}
+
+__global__ void k_rb_done(RebuildArgs a) {
+  const int rep = a.reps[blockIdx.x];
+  const Geom& g = a.geom[rep];
+  State* st = a.state + rep;
+  for (int b = threadIdx.x; b < g.nblocks; b += blockDim.x) a.upart[g.block0 + b] = 0.0;
+  if (threadIdx.x == 0) {
+    st->ubound = 0.0;
+    st->gamma_build = strain_of(st->k, g.dgamma);
+  }
+}
+
+}  // namespace
+
+void launch_rebuild(const RebuildArgs& a, int32_t max_cells_per_slot, hipStream_t s,
+                    const int32_t* nc3_dev) {
+  if (a.nreps <= 0 || a.nblk <= 0) return;
+  const int cb = (max_cells_per_slot + 1 + 255) / 256;
+  hipLaunchKernelGGL(k_rb_grid, dim3(a.nreps), dim3(64), 0, s, a, nc3_dev);
+  hipLaunchKernelGGL(k_rb_zero, dim3(cb, a.nreps), dim3(256), 0, s, a);
+  if (a.dim == 3) {
+    hipLaunchKernelGGL(k_rb_bin<3>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_rb_bin<2>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+  }
+  hipLaunchKernelGGL(k_rb_scan, dim3(a.nreps), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_rb_scatter, dim3(a.nblk), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_rb_sort, dim3(cb, a.nreps), dim3(256), 0, s, a);
+  if (a.dim == 3) {
+    hipLaunchKernelGGL(k_rb_perm<3>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rb_back<3>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rb_list<3>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_rb_perm<2>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rb_back<2>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rb_list<2>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+  }
+  hipLaunchKernelGGL(k_rb_done, dim3(a.nreps), dim3(256), 0, s, a);
+}
+
+}  // namespace aqs

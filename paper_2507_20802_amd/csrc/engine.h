@@ -1,0 +1,127 @@
+// engine.h -- device-side data layout shared by the HIP kernels and the host
+// side of the AQS engine (not part of the public ABI; see include/aqs.h).
+//
+// Layout in HBM (one context = one batch of slots):
+//   per-atom arrays, every slot padded to a multiple of kBlock atoms:
+//     pos4   double4 (x, y, z, type)  AoS, the gather target of the force loop
+//     vx,vy,vz, fx,fy,fz              SoA FP64, streamed coalesced
+//     id     int32, atom id held by each sorted position ("slot order")
+//     inv    int32, sorted position of each atom id
+//     nbc    int32, neighbour count per atom
+//   neighbour list per slot: max_nb x npad uint32, column-major (entry k of
+//     atom i at k*npad + i) so a wavefront reads 64 consecutive words;
+//     entry = j | (image code << 24), image code in [0, 3^dim)
+//   per-block partial sums, per-slot counters, per-slot state and geometry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aqs {
+
+constexpr int kBlock = 256;           // atoms per workgroup (4 wavefronts)
+constexpr int kWave = 64;
+constexpr int kForceParts = 8;        // doubles per block partial of the force kernel
+constexpr uint32_t kIdxMask = 0x00FFFFFFu;
+constexpr int kCodeShift = 24;
+
+// phases of a slot's device state machine
+enum Phase : int32_t {
+  PH_IDLE = 0,      // not part of the running call
+  PH_FIRE = 1,      // evaluate forces; control; FIRE update
+  PH_ADVANCE = 2,   // update applies the fine affine step (and snapshot)
+  PH_FINISH = 3,    // update takes the snapshot only; next force kernel -> DONE
+  PH_STOP = 4,      // update applies the last FIRE step; next force kernel -> DONE
+  PH_DONE = 5,
+  PH_REBUILD = 6,   // neighbour list no longer valid; waits for the host
+  PH_EVAL = 7,      // one force evaluation without FIRE control
+  PH_LDESC = 8,     // learned start: descriptors + MLP pending at the IS
+  PH_LMOVE = 9,     // learned start: update moves plain start -> learned start
+  PH_LREVERT = 10,  // learned start rejected: update restores the plain start
+};
+
+// static per-slot geometry
+struct Geom {
+  int64_t atom_off;   // first atom in the per-atom arrays (multiple of kBlock)
+  int64_t nb_off;     // first entry of the neighbour list
+  int32_t n;          // atoms
+  int32_t npad;       // n rounded up to kBlock
+  int32_t block0;     // first block index (partials are per global block)
+  int32_t nblocks;    // npad / kBlock
+  int32_t cell_off;   // first cell of this slot in the cell arrays
+  int32_t cell_cap;   // cells reserved
+  double L[3];        // unstrained box edges
+  double dgamma;      // fine strain increment
+};
+
+// dynamic per-slot state (written by the force kernel's last block)
+struct State {
+  int64_t k;          // strain index: gamma = k * dgamma
+  int64_t it;         // FIRE updates in the current minimisation
+  double dt, alpha;   // FIRE time step and mixing
+  double cv, cf;      // pending update: v <- cv v + cf F
+  double E, fmax, sxy;      // last force evaluation
+  double ubound;      // sum of per-iteration max displacements since the build
+  double gamma_build; // strain at the last neighbour-list build
+  double E_plain, fmax_plain;  // learned start: plain-start reference values
+  int32_t npos, nneg;
+  int32_t restart;    // pending update backs off x -= dt v / 2, v = 0
+  int32_t phase;
+  int32_t status;     // outcome of the last finished minimisation
+  int32_t step;       // fine step of the chain being minimised (0 = first)
+  int32_t n_steps;    // fine steps to run after the first minimisation
+  int32_t snap_dst;   // slot receiving the first inherent structure, or -1
+  int32_t do_snap;    // pending update copies this slot into snap_dst
+  int32_t nc[3];      // cell grid of the current list
+  int32_t start_mode; // AQS_START_*
+  int32_t start_used; // start of the minimisation in progress
+  int32_t learn_ok;   // learned displacement passed its pre-checks
+  int32_t pad_[2];
+};
+
+struct PairParams {   // per type pair t = 2 ti + tj
+  double rc2, sig2, eps4, ucut;
+};
+
+struct FireParams {
+  double dt0, dt_max, dt_min, f_inc, f_dec, alpha0, f_alpha, dmax, ftol;
+  int32_t n_delay, n_neg_max, initial_delay, pad_;
+  int64_t max_iter;
+};
+
+struct StepRecord {
+  int64_t iters;
+  double energy, max_f, sigma_xy;
+  int32_t status, start;
+};
+
+// Everything the iteration kernels need, passed by value.
+struct IterArgs {
+  const int2* blocks;     // launch table: (slot, local block) or slot -1
+  const Geom* geom;
+  State* state;
+  double4* pos4;
+  double* vx; double* vy; double* vz;
+  double* fx; double* fy; double* fz;
+  int32_t* id; int32_t* inv;
+  const int32_t* nbc;
+  const uint32_t* nbl;
+  double* fpart;          // kForceParts per global block
+  double* upart;          // 1 per global block (max displacement of the update)
+  uint32_t* counter;      // per slot, last-block detection
+  StepRecord* log;        // per slot, log_cap records
+  int32_t log_cap;
+  int32_t max_nb;
+  PairParams pp[4];
+  FireParams fire;
+  double skin, rc_max;
+  // learned start (null when unused)
+  double* dlx; double* dly; double* dlz;   // learned displacement per atom
+  double4* alt4;                            // saved plain start
+};
+
+__host__ __device__ inline double strain_of(int64_t k, double dgamma) {
+  return (double)k * dgamma;
+}
+
+}  // namespace aqs

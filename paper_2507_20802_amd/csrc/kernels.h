@@ -1,0 +1,67 @@
+// kernels.h -- host-side launchers of the HIP kernels (internal).
+#pragma once
+
+#include "engine.h"
+
+namespace aqs {
+
+// Rebuild of cell lists and neighbour lists for a set of slots.
+struct RebuildArgs {
+  const int2* blocks;   // launch table over the atoms of the slots to rebuild
+  int32_t nblk;         // entries of the launch table
+  const int32_t* reps;  // slots to rebuild
+  int32_t nreps;
+  const Geom* geom;
+  State* state;
+  double4* pos4;
+  double* vx; double* vy; double* vz;
+  int32_t* id; int32_t* inv;
+  int32_t* nbc;
+  uint32_t* nbl;
+  int32_t* cell_count;  // per cell (cell_off + c)
+  int32_t* cell_start;  // per cell + 1 per slot (cell_off + slot_index + c)
+  int32_t* cell_of;     // per atom
+  int32_t* order;       // per atom
+  double4* tpos4;       // per atom scratch
+  double* tvx; double* tvy; double* tvz;
+  int32_t* tid_;
+  double* upart;
+  int32_t* overflow;
+  PairParams pp[4];
+  double skin;
+  int32_t max_nb;
+  int32_t dim;
+  // learned-start per-atom buffers permuted with the atoms (may be null)
+  double* dlx; double* dly; double* dlz;
+  double* tdlx; double* tdly; double* tdlz;
+};
+
+void launch_rebuild(const RebuildArgs& a, int32_t max_cells_per_slot, hipStream_t s,
+                    const int32_t* nc3_dev);
+
+// One FIRE iteration (force + control, then update) over the launch table.
+void launch_force(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s);
+void launch_update(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s);
+
+// Affine shear x += dg_r y of whole slots (host-driven level I step).
+void launch_affine(const int2* blocks, int32_t nblk, const Geom* geom, double4* pos4,
+                   const double* dg_per_slot, hipStream_t s);
+
+// v = 0 and partials of the update = 0 for the slots of the launch table.
+void launch_reset_iter(const int2* blocks, int32_t nblk, const Geom* geom, double* vx,
+                       double* vy, double* vz, double* upart, int32_t dim, hipStream_t s);
+
+// Copy slot src into slot dst (same n), including order and inverse.
+void launch_copy_slot(const Geom* geom, int32_t src, int32_t dst, int32_t n, double4* pos4,
+                      int32_t* id, int32_t* inv, hipStream_t s);
+
+// Max minimum-image distance per block between two slots (atom-id order).
+void launch_compare(const Geom* geom, int32_t ra, int32_t rb, int32_t n, const double4* pos4,
+                    const int32_t* inv, double Lx, double Ly, double Lz, double tilt,
+                    int32_t dim, double* part, hipStream_t s);
+
+// Energy and full virial per block of one slot: 1 + 9 doubles per block.
+void launch_virial(const IterArgs& a, int32_t rep, int32_t nblocks, int32_t dim, double Lx,
+                   double Ly, double Lz, double tilt, double* part, hipStream_t s);
+
+}  // namespace aqs

@@ -1,0 +1,602 @@
+// md_kernels.hip -- gfx950 kernels of the AQS hot path: cell binning and
+// neighbour lists, the FP64 Lennard-Jones force loop with the per-slot FIRE
+// control, the FIRE update, affine shear, configuration comparison, stress.
+//
+// Method: Reihn, Bamer, Stamm, arXiv 2507.20802.  Pair potential Eq. (13);
+// affine simple shear Eqs. (2), (3), (16); minimisation operator Eq. (10)
+// realised by FIRE 2.0; equality test Eq. (20); AQS chain Eqs. (12), (19).
+//
+// Determinism: no floating-point atomics.  Per-block partial sums use a fixed
+// butterfly per wavefront and a fixed order across wavefronts; the last
+// block of a slot combines the partials in block order.  Cell order within a
+// cell is by atom id, so a rebuild gives the same sorted order every run.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace aqs {
+
+// ---------------------------------------------------------------------------
+// reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Block-wide reduction of NV values; op[c] = 0 sum, 1 max.  Result valid in
+// thread 0.  Fixed order: butterfly inside each wavefront, then waves 0..3
+// combined as (w0 + w1) + (w2 + w3).
+template <int NV>
+__device__ __forceinline__ void block_reduce(double* v, const int* op, double (*lds)[kBlock / kWave]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) v[c] = op[c] ? wave_max(v[c]) : wave_sum(v[c]);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) lds[c][w] = v[c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      if (op[c]) v[c] = fmax(fmax(lds[c][0], lds[c][1]), fmax(lds[c][2], lds[c][3]));
+      else v[c] = (lds[c][0] + lds[c][1]) + (lds[c][2] + lds[c][3]);
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// box geometry: H = [[Lx, t, 0], [0, Ly, 0], [0, 0, Lz]], t = gamma Ly (Eq. 1,
+// Eq. 16).  Image code c = (ix+1) + 3 (iy+1) + 9 (iz+1); shift = H (ix,iy,iz).
+
+__device__ __forceinline__ void code_shift(int code, double Lx, double Ly, double Lz, double t,
+                                           double* s) {
+  const int ix = code % 3 - 1, iy = (code / 3) % 3 - 1, iz = code / 9 - 1;
+  s[0] = (double)ix * Lx + (double)iy * t;
+  s[1] = (double)iy * Ly;
+  s[2] = (double)iz * Lz;
+}
+
+__device__ __forceinline__ double slot_tilt(const Geom& g, const State* st) {
+  return strain_of(st->k, g.dgamma) * g.L[1];
+}
+
+// ---------------------------------------------------------------------------
+// Lennard-Jones pair loop of one atom over its neighbour list, Eq. (13).
+// Accumulates F_i = sum_j U'(r) d / r (d = r_j - r_i), sum_j U(r) and
+// sum_j U'(r) dx dy / r; the caller halves the pair sums.
+
+template <int D>
+__device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint32_t* L,
+                                           int64_t stride, int cnt, const double4* P,
+                                           const double (*sh)[4], const PairParams* pp,
+                                           double& fx, double& fy, double& fz, double& e,
+                                           double& w) {
+  for (int k = 0; k < cnt; ++k) {
+    const uint32_t ent = L[(int64_t)k * stride];
+    const double4 pj = P[ent & kIdxMask];
+    const int code = (int)(ent >> kCodeShift);
+    const double dx = (pj.x - pi.x) + sh[code][0];
+    const double dy = (pj.y - pi.y) + sh[code][1];
+    const double dz = (D == 3) ? (pj.z - pi.z) + sh[code][2] : 0.0;
+    const double r2 = (D == 3) ? dx * dx + dy * dy + dz * dz : dx * dx + dy * dy;
+    const PairParams q = pp[2 * ti + (int)pj.w];
+    if (r2 < q.rc2) {
+      const double inv = 1.0 / r2;
+      const double s2 = q.sig2 * inv;
+      const double s6 = s2 * s2 * s2;
+      const double s12 = s6 * s6;
+      e += q.eps4 * (s12 - s6) - q.ucut;
+      const double g = q.eps4 * (6.0 * s6 - 12.0 * s12) * inv;  // U'(r) / r
+      fx += g * dx;
+      fy += g * dy;
+      if (D == 3) fz += g * dz;
+      w += g * dx * dy;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-slot FIRE control, run by thread 0 of the last block of a slot after
+// the force evaluation (Eq. 10 realised by FIRE 2.0; chain of Eq. 19).
+
+__device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
+  StepRecord rec;
+  rec.iters = s.it;
+  rec.energy = s.E;
+  rec.max_f = s.fmax;
+  rec.sigma_xy = s.sxy;
+  rec.status = status;
+  rec.start = s.start_used;
+  if (s.step < a.log_cap) a.log[(int64_t)rep * a.log_cap + s.step] = rec;
+  s.status = status;
+  s.do_snap = (s.step == 0 && s.snap_dst >= 0) ? 1 : 0;
+  if (s.do_snap) {
+    State* d = a.state + s.snap_dst;
+    d->k = s.k;
+    d->E = s.E;
+    d->fmax = s.fmax;
+    d->sxy = s.sxy;
+    d->status = status;
+  }
+  if (status == 0 && s.step < s.n_steps) {
+    s.step += 1;
+    s.k += 1;
+    s.dt = a.fire.dt0;
+    s.alpha = a.fire.alpha0;
+    s.npos = 0;
+    s.nneg = 0;
+    s.it = 0;
+    s.restart = 0;
+    s.cv = 1.0;
+    s.cf = 0.0;
+    s.start_used = 0;
+    s.phase = PH_ADVANCE;
+  } else {
+    s.phase = PH_FINISH;
+  }
+}
+
+__device__ void control(const IterArgs& a, int rep, const Geom& g, const double* r, int phase) {
+  State s = a.state[rep];
+  if (phase == PH_FINISH || phase == PH_STOP) {
+    s.phase = PH_DONE;
+    a.state[rep] = s;
+    return;
+  }
+  // Validity of the neighbour list: every pair now within its cutoff was
+  // within cutoff + skin at the build if
+  //   |dgamma| rc_max + 2 (1 + |dgamma|)^2 u <= skin,
+  // dgamma = strain change since the build, u = bound on the non-affine
+  // displacement of any atom (sum of per-iteration maxima).
+  const double ub = s.ubound + r[7];
+  const double gam = strain_of(s.k, g.dgamma);
+  const double gd = fabs(gam - s.gamma_build);
+  if (gd * a.rc_max + 2.0 * (1.0 + gd) * (1.0 + gd) * ub >= a.skin) {
+    s.phase = PH_REBUILD;
+    a.state[rep] = s;
+    return;
+  }
+  s.ubound = ub;
+  s.E = r[0];
+  s.fmax = sqrt(r[4]);
+  s.sxy = r[5] / (g.L[0] * g.L[1] * g.L[2]);  // simple shear keeps V = Lx Ly Lz
+  if (phase == PH_EVAL) {
+    s.phase = PH_DONE;
+    a.state[rep] = s;
+    return;
+  }
+  s.phase = PH_FIRE;
+  if (r[6] != 0.0 || !isfinite(r[0]) || !isfinite(r[1])) {
+    finish_min(a, rep, s, 3);
+    a.state[rep] = s;
+    return;
+  }
+  if (s.fmax < a.fire.ftol) {
+    finish_min(a, rep, s, 0);
+    a.state[rep] = s;
+    return;
+  }
+  const FireParams& f = a.fire;
+  const double FF = r[1], P = r[2], VV = r[3];
+  if (P > 0.0) {
+    s.npos += 1;
+    s.nneg = 0;
+    if (s.npos > f.n_delay) {
+      s.dt = fmin(s.dt * f.f_inc, f.dt_max);
+      s.alpha *= f.f_alpha;
+    }
+    s.restart = 0;
+  } else {
+    s.npos = 0;
+    s.nneg += 1;
+    if (s.nneg > f.n_neg_max) {
+      finish_min(a, rep, s, 2);
+      a.state[rep] = s;
+      return;
+    }
+    if (!(f.initial_delay && s.it < f.n_delay)) {
+      if (s.dt * f.f_dec >= f.dt_min) s.dt *= f.f_dec;
+      s.alpha = f.alpha0;
+    }
+    s.restart = 1;
+  }
+  // |v|^2 after the Euler step v + dt F (v = 0 after a restart)
+  double vv = s.restart ? (s.dt * s.dt) * FF : VV + 2.0 * s.dt * P + (s.dt * s.dt) * FF;
+  if (vv < 0.0) vv = 0.0;
+  if (FF > 0.0) {
+    s.cv = 1.0 - s.alpha;
+    s.cf = s.alpha * sqrt(vv) / sqrt(FF);
+  } else {
+    s.cv = 1.0;
+    s.cf = 0.0;
+  }
+  s.it += 1;
+  if (s.it >= f.max_iter) {
+    finish_min(a, rep, s, 1);
+    s.phase = PH_STOP;  // the update still applies this last step
+  }
+  a.state[rep] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Force kernel: one atom per thread, 256 atoms of one slot per block.  Also
+// the per-block partials (E, |F|^2, F.v, |v|^2, max |F_i|^2, W_xy, non-finite)
+// and, in the last block of each slot, the FIRE control.
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
+  const int2 bt = a.blocks[blockIdx.x];
+  const int rep = bt.x;
+  if (rep < 0) return;
+  const int phase = a.state[rep].phase;
+  const bool compute = (phase == PH_FIRE || phase == PH_ADVANCE || phase == PH_EVAL);
+  const bool counted = compute || phase == PH_FINISH || phase == PH_STOP;
+  if (!counted) return;
+  const Geom g = a.geom[rep];
+  const int tid = threadIdx.x;
+
+  __shared__ double sh[27][4];
+  __shared__ PairParams spp[4];
+  __shared__ double red[kForceParts][kBlock / kWave];
+  __shared__ int s_last;
+  constexpr int ops[kForceParts] = {0, 0, 0, 0, 1, 0, 1, 1};
+
+  double part[kForceParts] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (compute) {
+    const double t = slot_tilt(g, a.state + rep);
+    if (tid < 27) code_shift(tid, g.L[0], g.L[1], g.L[2], t, sh[tid]);
+    if (tid < 4) spp[tid] = a.pp[tid];
+    __syncthreads();
+    const int li = bt.y * kBlock + tid;
+    if (li < g.n) {
+      const int64_t gi = g.atom_off + li;
+      const double4 pi = a.pos4[gi];
+      double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
+      atom_pairs<D>(pi, (int)pi.w, a.nbl + g.nb_off + li, g.npad, a.nbc[gi], a.pos4 + g.atom_off,
+                    sh, spp, fx, fy, fz, e, w);
+      a.fx[gi] = fx;
+      a.fy[gi] = fy;
+      if (D == 3) a.fz[gi] = fz;
+      const double vx = a.vx[gi], vy = a.vy[gi], vz = (D == 3) ? a.vz[gi] : 0.0;
+      const double ff = fx * fx + fy * fy + fz * fz;
+      part[0] = 0.5 * e;
+      part[1] = ff;
+      part[2] = fx * vx + fy * vy + fz * vz;
+      part[3] = vx * vx + vy * vy + vz * vz;
+      part[4] = ff;
+      part[5] = 0.5 * w;
+      part[6] = (isfinite(e) && isfinite(ff)) ? 0.0 : 1.0;
+    }
+    block_reduce<kForceParts>(part, ops, red);
+    if (tid == 0) {
+      double* dst = a.fpart + (int64_t)(g.block0 + bt.y) * kForceParts;
+#pragma unroll
+      for (int c = 0; c < 7; ++c) dst[c] = part[c];
+    }
+  }
+  // last block of the slot runs the control
+  if (tid == 0) {
+    __threadfence();
+    const unsigned old = atomicAdd(a.counter + rep, 1u);
+    s_last = (old == (unsigned)(g.nblocks - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double r[kForceParts] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (compute) {
+    for (int b = tid; b < g.nblocks; b += kBlock) {
+      const double* src = a.fpart + (int64_t)(g.block0 + b) * kForceParts;
+      r[0] += __builtin_nontemporal_load(src + 0);
+      r[1] += __builtin_nontemporal_load(src + 1);
+      r[2] += __builtin_nontemporal_load(src + 2);
+      r[3] += __builtin_nontemporal_load(src + 3);
+      r[4] = fmax(r[4], __builtin_nontemporal_load(src + 4));
+      r[5] += __builtin_nontemporal_load(src + 5);
+      r[6] = fmax(r[6], __builtin_nontemporal_load(src + 6));
+      r[7] = fmax(r[7], __builtin_nontemporal_load(a.upart + g.block0 + b));
+    }
+  }
+  block_reduce<kForceParts>(r, ops, red);
+  if (tid == 0) {
+    a.counter[rep] = 0u;
+    control(a, rep, g, r, phase);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FIRE update (steps 5-9 of the minimiser) or the fine affine step of the
+// chain, per atom; per-block max displacement for the list-validity bound.
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
+  const int2 bt = a.blocks[blockIdx.x];
+  const int rep = bt.x;
+  if (rep < 0) return;
+  const State* st = a.state + rep;
+  const int phase = st->phase;
+  const bool fire = (phase == PH_FIRE || phase == PH_STOP);
+  if (!(fire || phase == PH_ADVANCE || phase == PH_FINISH)) return;
+  const Geom g = a.geom[rep];
+  const int tid = threadIdx.x;
+  const int li = bt.y * kBlock + tid;
+  __shared__ double red[kForceParts][kBlock / kWave];
+  double m[1] = {0.0};
+  if (li < g.n) {
+    const int64_t gi = g.atom_off + li;
+    double4 p = a.pos4[gi];
+    if (fire) {
+      const double dt = st->dt, cv = st->cv, cf = st->cf, dmax = a.fire.dmax;
+      const double ox = p.x, oy = p.y, oz = p.z;
+      double vx = a.vx[gi], vy = a.vy[gi], vz = (D == 3) ? a.vz[gi] : 0.0;
+      const double fx = a.fx[gi], fy = a.fy[gi], fz = (D == 3) ? a.fz[gi] : 0.0;
+      if (st->restart) {
+        p.x -= 0.5 * dt * vx;
+        p.y -= 0.5 * dt * vy;
+        if (D == 3) p.z -= 0.5 * dt * vz;
+        vx = 0.0;
+        vy = 0.0;
+        vz = 0.0;
+      }
+      vx += dt * fx;
+      vy += dt * fy;
+      vz += dt * fz;
+      vx = cv * vx + cf * fx;
+      vy = cv * vy + cf * fy;
+      vz = cv * vz + cf * fz;
+      const double sp = dt * sqrt(vx * vx + vy * vy + vz * vz);
+      if (sp > dmax) {
+        const double sc = dmax / sp;
+        vx *= sc;
+        vy *= sc;
+        vz *= sc;
+      }
+      p.x += dt * vx;
+      p.y += dt * vy;
+      if (D == 3) p.z += dt * vz;
+      a.pos4[gi] = p;
+      a.vx[gi] = vx;
+      a.vy[gi] = vy;
+      if (D == 3) a.vz[gi] = vz;
+      const double ddx = p.x - ox, ddy = p.y - oy, ddz = p.z - oz;
+      m[0] = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+    } else {
+      if (st->do_snap) {
+        const Geom gd = a.geom[st->snap_dst];
+        const int64_t di = gd.atom_off + li;
+        a.pos4[di] = p;
+        const int32_t aid = a.id[gi];
+        a.id[di] = aid;
+        a.inv[gd.atom_off + aid] = li;
+      }
+      if (phase == PH_ADVANCE) {
+        p.x += g.dgamma * p.y;  // Eq. (16): x <- x + dgamma y
+        a.pos4[gi] = p;
+        a.vx[gi] = 0.0;
+        a.vy[gi] = 0.0;
+        if (D == 3) a.vz[gi] = 0.0;
+      }
+    }
+  }
+  if (fire) {
+    const int op[1] = {1};
+    block_reduce<1>(m, op, red);
+    if (tid == 0) a.upart[g.block0 + bt.y] = m[0];
+  } else if (phase == PH_ADVANCE && tid == 0) {
+    a.upart[g.block0 + bt.y] = 0.0;
+  }
+}
+
+void launch_force(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
+  if (nblk <= 0) return;
+  if (dim == 3)
+    hipLaunchKernelGGL(k_force<3>, dim3(nblk), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_force<2>, dim3(nblk), dim3(kBlock), 0, s, a);
+}
+
+void launch_update(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
+  if (nblk <= 0) return;
+  if (dim == 3)
+    hipLaunchKernelGGL(k_update<3>, dim3(nblk), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_update<2>, dim3(nblk), dim3(kBlock), 0, s, a);
+}
+
+
+// ---------------------------------------------------------------------------
+// Affine simple shear of whole slots, Eqs. (2)-(3) with Eq. (16):
+// x <- x + dg_r y, dg_r = dk_r dgamma_r formed on the host in one product.
+
+__global__ __launch_bounds__(kBlock) void k_affine(const int2* blocks, const Geom* geom,
+                                                    double4* pos4, const double* dg) {
+  const int2 bt = blocks[blockIdx.x];
+  if (bt.x < 0) return;
+  const Geom& g = geom[bt.x];
+  const int li = bt.y * kBlock + threadIdx.x;
+  if (li >= g.n) return;
+  double4 p = pos4[g.atom_off + li];
+  p.x += dg[bt.x] * p.y;
+  pos4[g.atom_off + li] = p;
+}
+
+void launch_affine(const int2* blocks, int32_t nblk, const Geom* geom, double4* pos4,
+                   const double* dg_per_slot, hipStream_t s) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(k_affine, dim3(nblk), dim3(kBlock), 0, s, blocks, geom, pos4, dg_per_slot);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reset_iter(const int2* blocks, const Geom* geom,
+                                                        double* vx, double* vy, double* vz,
+                                                        double* upart, int dim) {
+  const int2 bt = blocks[blockIdx.x];
+  if (bt.x < 0) return;
+  const Geom& g = geom[bt.x];
+  const int li = bt.y * kBlock + threadIdx.x;
+  if (threadIdx.x == 0) upart[g.block0 + bt.y] = 0.0;
+  if (li >= g.n) return;
+  const int64_t gi = g.atom_off + li;
+  vx[gi] = 0.0;
+  vy[gi] = 0.0;
+  if (dim == 3) vz[gi] = 0.0;
+}
+
+void launch_reset_iter(const int2* blocks, int32_t nblk, const Geom* geom, double* vx,
+                       double* vy, double* vz, double* upart, int32_t dim, hipStream_t s) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(k_reset_iter, dim3(nblk), dim3(kBlock), 0, s, blocks, geom, vx, vy, vz,
+                     upart, dim);
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_slot(const Geom* geom, int src, int dst, int n,
+                                                       double4* pos4, int32_t* id,
+                                                       int32_t* inv) {
+  const int li = blockIdx.x * kBlock + threadIdx.x;
+  if (li >= n) return;
+  const int64_t so = geom[src].atom_off, d0 = geom[dst].atom_off;
+  pos4[d0 + li] = pos4[so + li];
+  id[d0 + li] = id[so + li];
+  inv[d0 + li] = inv[so + li];
+}
+
+void launch_copy_slot(const Geom* geom, int32_t src, int32_t dst, int32_t n, double4* pos4,
+                      int32_t* id, int32_t* inv, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy_slot, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, geom, src,
+                     dst, n, pos4, id, inv);
+}
+
+// ---------------------------------------------------------------------------
+// Distance of the equality test (Eq. 20): per atom id, the minimum image of
+// r_a - r_b in the box of slot a; per-block maximum.
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_compare(const Geom* geom, int ra, int rb, int n,
+                                                     const double4* pos4, const int32_t* inv,
+                                                     double Lx, double Ly, double Lz, double t,
+                                                     double* part) {
+  __shared__ double red[kForceParts][kBlock / kWave];
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  double m[1] = {0.0};
+  if (idx < n) {
+    const Geom& ga = geom[ra];
+    const Geom& gb = geom[rb];
+    const double4 pa = pos4[ga.atom_off + inv[ga.atom_off + idx]];
+    const double4 pb = pos4[gb.atom_off + inv[gb.atom_off + idx]];
+    double dx = pa.x - pb.x, dy = pa.y - pb.y, dz = (D == 3) ? pa.z - pb.z : 0.0;
+    // fractional coordinates, nearest integer, back (Sec. 2.1 periodicity)
+    double sy = dy / Ly;
+    double sx = (dx - t * sy) / Lx;
+    double sz = (D == 3) ? dz / Lz : 0.0;
+    sx -= rint(sx);
+    sy -= rint(sy);
+    sz -= rint(sz);
+    dx = Lx * sx + t * sy;
+    dy = Ly * sy;
+    dz = Lz * sz;
+    m[0] = sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  const int op[1] = {1};
+  block_reduce<1>(m, op, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = m[0];
+}
+
+void launch_compare(const Geom* geom, int32_t ra, int32_t rb, int32_t n, const double4* pos4,
+                    const int32_t* inv, double Lx, double Ly, double Lz, double tilt,
+                    int32_t dim, double* part, hipStream_t s) {
+  const int nb = (n + kBlock - 1) / kBlock;
+  if (nb <= 0) return;
+  if (dim == 3)
+    hipLaunchKernelGGL(k_compare<3>, dim3(nb), dim3(kBlock), 0, s, geom, ra, rb, n, pos4, inv, Lx,
+                       Ly, Lz, tilt, part);
+  else
+    hipLaunchKernelGGL(k_compare<2>, dim3(nb), dim3(kBlock), 0, s, geom, ra, rb, n, pos4, inv, Lx,
+                       Ly, Lz, tilt, part);
+}
+
+// ---------------------------------------------------------------------------
+// Energy and virial W_ab = sum_{i<j} U'(r) d_a d_b / r of one slot, from the
+// neighbour list; per block: E then W row-major 3x3.
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_virial(IterArgs a, int rep, double Lx, double Ly,
+                                                    double Lz, double t, double* part) {
+  __shared__ double sh[27][4];
+  __shared__ PairParams spp[4];
+  __shared__ double red[kForceParts][kBlock / kWave];
+  const Geom g = a.geom[rep];
+  const int tid = threadIdx.x;
+  if (tid < 27) code_shift(tid, Lx, Ly, Lz, t, sh[tid]);
+  if (tid < 4) spp[tid] = a.pp[tid];
+  __syncthreads();
+  const int li = blockIdx.x * kBlock + tid;
+  double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (li < g.n) {
+    const int64_t gi = g.atom_off + li;
+    const double4 pi = a.pos4[gi];
+    const int ti = (int)pi.w;
+    const uint32_t* L = a.nbl + g.nb_off + li;
+    const double4* P = a.pos4 + g.atom_off;
+    const int cnt = a.nbc[gi];
+    for (int k = 0; k < cnt; ++k) {
+      const uint32_t ent = L[(int64_t)k * g.npad];
+      const double4 pj = P[ent & kIdxMask];
+      const int code = (int)(ent >> kCodeShift);
+      double d[3];
+      d[0] = (pj.x - pi.x) + sh[code][0];
+      d[1] = (pj.y - pi.y) + sh[code][1];
+      d[2] = (D == 3) ? (pj.z - pi.z) + sh[code][2] : 0.0;
+      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      const PairParams q = spp[2 * ti + (int)pj.w];
+      if (r2 < q.rc2) {
+        const double inv = 1.0 / r2;
+        const double s2 = q.sig2 * inv;
+        const double s6 = s2 * s2 * s2;
+        const double s12 = s6 * s6;
+        v[0] += 0.5 * (q.eps4 * (s12 - s6) - q.ucut);
+        const double gg = q.eps4 * (6.0 * s6 - 12.0 * s12) * inv;
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+          for (int y = 0; y < 3; ++y) v[1 + 3 * x + y] += 0.5 * gg * d[x] * d[y];
+      }
+    }
+  }
+  // two passes of 5 values through the 8-wide reduction buffer
+  const int op[5] = {0, 0, 0, 0, 0};
+  double lo[5] = {v[0], v[1], v[2], v[3], v[4]};
+  double hi[5] = {v[5], v[6], v[7], v[8], v[9]};
+  block_reduce<5>(lo, op, red);
+  block_reduce<5>(hi, op, red);
+  if (tid == 0) {
+    double* dst = part + (int64_t)blockIdx.x * 10;
+    for (int c = 0; c < 5; ++c) {
+      dst[c] = lo[c];
+      dst[5 + c] = hi[c];
+    }
+  }
+}
+
+void launch_virial(const IterArgs& a, int32_t rep, int32_t nblocks, int32_t dim, double Lx,
+                   double Ly, double Lz, double tilt, double* part, hipStream_t s) {
+  if (nblocks <= 0) return;
+  if (dim == 3)
+    hipLaunchKernelGGL(k_virial<3>, dim3(nblocks), dim3(kBlock), 0, s, a, rep, Lx, Ly, Lz, tilt,
+                       part);
+  else
+    hipLaunchKernelGGL(k_virial<2>, dim3(nblocks), dim3(kBlock), 0, s, a, rep, Lx, Ly, Lz, tilt,
+                       part);
+}
+
+}  // namespace aqs

@@ -1,0 +1,247 @@
+"""Python face of the batched AQS engine (include/aqs.h).
+
+PyTorch supplies the device workspace and the stream; the library does the
+rest.  A context holds a batch of replica slots; the operators of the paper
+(affine shear Eqs. 2-3/16, the minimisation operator Eq. 10 as FIRE 2.0, the
+chained AQS steps Eqs. 12/19, the equality test Eq. 20, the stress of Fig. 2)
+act on any subset of slots at once.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+from ._lib import (AQS_START_LEARNED, AQS_START_PLAIN, aqs_fire_params, aqs_potential,
+                   aqs_step_record, aqs_tuning, check)
+
+STATUS_NAMES = {0: "converged", 1: "maxiter", 2: "stalled", 3: "nonfinite"}
+
+
+@dataclass
+class LJParams:
+    """Binary truncated-and-shifted Lennard-Jones, Eq. (13).  Default: the
+    Kob-Andersen-type parameter set of the synthetic glasses (A = 0, B = 1)."""
+    eps: tuple = ((1.0, 1.5), (1.5, 0.5))
+    sigma: tuple = ((1.0, 0.8), (0.8, 0.88))
+    rc_factor: float = 2.5
+
+    def to_c(self, dim: int) -> aqs_potential:
+        p = aqs_potential()
+        p.dim = dim
+        for a in range(2):
+            for b in range(2):
+                p.eps[a][b] = float(self.eps[a][b])
+                p.sigma[a][b] = float(self.sigma[a][b])
+        p.rc_factor = float(self.rc_factor)
+        return p
+
+    @property
+    def rc_max(self) -> float:
+        return self.rc_factor * max(max(r) for r in self.sigma)
+
+
+@dataclass
+class Fire:
+    """FIRE 2.0 constants.  The defaults were chosen by an iteration-count
+    search on synthetic glasses at max|F| < 1e-10."""
+    dt0: float = 0.01
+    dt_max: float = 0.03
+    dt_min: float = 2e-4
+    f_inc: float = 1.2
+    f_dec: float = 0.9
+    alpha0: float = 0.2
+    f_alpha: float = 0.95
+    dmax: float = 0.1
+    ftol: float = 1e-10
+    n_delay: int = 5
+    n_neg_max: int = 2000
+    initial_delay: int = 1
+    max_iter: int = 1_000_000
+
+    def to_c(self) -> aqs_fire_params:
+        f = aqs_fire_params()
+        for k in ("dt0", "dt_max", "dt_min", "f_inc", "f_dec", "alpha0", "f_alpha", "dmax", "ftol",
+                  "n_delay", "n_neg_max", "initial_delay", "max_iter"):
+            setattr(f, k, getattr(self, k))
+        return f
+
+
+@dataclass
+class Tuning:
+    skin: float = 0.3
+    max_neighbors: int = 0
+    block_iters: int = 32
+    use_graph: int = 0
+    max_chain_steps: int = 1024
+
+    def to_c(self) -> aqs_tuning:
+        t = aqs_tuning()
+        t.skin = self.skin
+        t.max_neighbors = self.max_neighbors
+        t.block_iters = self.block_iters
+        t.use_graph = self.use_graph
+        t.max_chain_steps = self.max_chain_steps
+        return t
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _i64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a: np.ndarray, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+class Engine:
+    """A batch of replica slots on one GPU."""
+
+    def __init__(self, dim: int, n_atoms, box_len, dgamma, pot: LJParams | None = None,
+                 fire: Fire | None = None, tuning: Tuning | None = None, device: str = "cuda"):
+        import torch
+        self._lib = _lib.load()
+        self.dim = int(dim)
+        self.n_atoms = _i32(np.atleast_1d(n_atoms))
+        self.n_rep = int(self.n_atoms.size)
+        bl = np.asarray(box_len, dtype=np.float64)
+        if bl.ndim == 0:
+            bl = np.full((self.n_rep, self.dim), float(bl))
+        elif bl.ndim == 1:
+            bl = np.repeat(bl[:, None], self.dim, axis=1) if bl.size == self.n_rep else np.tile(bl, (self.n_rep, 1))
+        self.box_len = _f64(bl.reshape(self.n_rep, self.dim))
+        dg = np.asarray(dgamma, dtype=np.float64)
+        self.dgamma = _f64(np.broadcast_to(dg, (self.n_rep,)))
+        self.pot = pot or LJParams()
+        self.fire = fire or Fire()
+        self.tuning = tuning or Tuning()
+        self._cpot = self.pot.to_c(self.dim)
+        self._cfire = self.fire.to_c()
+        self._ctune = self.tuning.to_c()
+        nbytes = self._lib.aqs_workspace_bytes(ctypes.byref(self._cpot), ctypes.byref(self._ctune),
+                                               self.n_rep, _p(self.n_atoms, ctypes.c_int32),
+                                               _p(self.box_len, ctypes.c_double))
+        if nbytes == 0:
+            raise _lib.AQSError(-1, "aqs_workspace_bytes", self._lib.aqs_last_error().decode())
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        check(self._lib.aqs_create(ctypes.byref(self._cpot), ctypes.byref(self._cfire), ctypes.byref(self._ctune),
+                                   self.n_rep, _p(self.n_atoms, ctypes.c_int32), _p(self.box_len, ctypes.c_double),
+                                   _p(self.dgamma, ctypes.c_double), ctypes.c_void_p(aligned),
+                                   ctypes.c_size_t(int(nbytes)), ctypes.c_void_p(self._stream.cuda_stream),
+                                   ctypes.byref(ctx)), "aqs_create")
+        self._ctx = ctx
+        self.workspace_bytes = int(nbytes)
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_ctx", None):
+            self._lib.aqs_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- slots --------------------------------------------------------------
+    def set_replica(self, rep: int, types, pos, strain_index: int = 0) -> None:
+        t = np.ascontiguousarray(types, dtype=np.uint8)
+        x = _f64(pos).reshape(-1)
+        if t.size != self.n_atoms[rep] or x.size != self.n_atoms[rep] * self.dim:
+            raise ValueError("types/positions do not match the slot's atom count")
+        check(self._lib.aqs_set_replica(self._ctx, int(rep), t.ctypes.data_as(ctypes.c_void_p),
+                                        _p(x, ctypes.c_double), int(strain_index)), "aqs_set_replica")
+
+    def set_positions(self, rep: int, pos) -> None:
+        x = _f64(pos).reshape(-1)
+        if x.size != self.n_atoms[rep] * self.dim:
+            raise ValueError("positions do not match the slot's atom count")
+        check(self._lib.aqs_set_positions(self._ctx, int(rep), _p(x, ctypes.c_double)), "aqs_set_positions")
+
+    def positions(self, rep: int) -> np.ndarray:
+        out = np.zeros((int(self.n_atoms[rep]), self.dim))
+        check(self._lib.aqs_get_positions(self._ctx, int(rep), _p(out, ctypes.c_double)), "aqs_get_positions")
+        return out
+
+    def strain_index(self, rep: int) -> int:
+        k = ctypes.c_int64()
+        check(self._lib.aqs_get_strain_index(self._ctx, int(rep), ctypes.byref(k)), "aqs_get_strain_index")
+        return int(k.value)
+
+    def box(self, rep: int) -> np.ndarray:
+        """Bravais tensor of slot rep at its current strain index (Eq. 1)."""
+        L = self.box_len[rep]
+        H = np.diag(L).astype(np.float64)
+        H[0, 1] = (float(self.strain_index(rep)) * float(self.dgamma[rep])) * L[1]
+        return H
+
+    def copy_replica(self, src: int, dst: int) -> None:
+        check(self._lib.aqs_copy_replica(self._ctx, int(src), int(dst)), "aqs_copy_replica")
+
+    # -- operators ----------------------------------------------------------
+    def affine_shear(self, reps, dk) -> None:
+        r = _i32(np.atleast_1d(reps))
+        d = _i64(np.broadcast_to(np.atleast_1d(dk), r.shape))
+        check(self._lib.aqs_affine_shear(self._ctx, int(r.size), _p(r, ctypes.c_int32), _p(d, ctypes.c_int64)),
+              "aqs_affine_shear")
+
+    def minimize(self, reps, n_steps=None, snap_dst=None, start: int = AQS_START_PLAIN) -> np.ndarray:
+        """Minimise the slots, then run n_steps fine AQS steps on the device.
+        Returns a (len(reps), max(n_steps)+1) structured array of records."""
+        r = _i32(np.atleast_1d(reps))
+        ns = None if n_steps is None else _i32(np.broadcast_to(np.atleast_1d(n_steps), r.shape))
+        sd = None if snap_dst is None else _i32(np.broadcast_to(np.atleast_1d(snap_dst), r.shape))
+        width = 1 + (int(ns.max()) if ns is not None and ns.size else 0)
+        recs = (aqs_step_record * (r.size * width))()
+        for x in recs:
+            x.status = -1
+        check(self._lib.aqs_minimize_batch(self._ctx, int(r.size), _p(r, ctypes.c_int32), int(start),
+                                           None if ns is None else _p(ns, ctypes.c_int32),
+                                           None if sd is None else _p(sd, ctypes.c_int32), recs),
+              "aqs_minimize_batch")
+        out = np.zeros((r.size, width), dtype=[("iters", np.int64), ("energy", np.float64),
+                                                 ("max_f", np.float64), ("sigma_xy", np.float64),
+                                                 ("status", np.int32), ("start", np.int32)])
+        for i in range(r.size):
+            for s in range(width):
+                x = recs[i * width + s]
+                out[i, s] = (x.iters, x.energy, x.max_f, x.sigma_xy, x.status, x.start)
+        return out
+
+    def compare(self, a: int, b: int, delta_eq: float = 1e-4):
+        """(equal, max_disp, dE/N) of the equality test, Eq. (20)."""
+        eq = ctypes.c_int32()
+        md = ctypes.c_double()
+        de = ctypes.c_double()
+        check(self._lib.aqs_compare_configs(self._ctx, int(a), int(b), float(delta_eq), ctypes.byref(eq),
+                                            ctypes.byref(md), ctypes.byref(de)), "aqs_compare_configs")
+        return bool(eq.value), md.value, de.value
+
+    def stress(self, rep: int):
+        s = np.zeros((self.dim, self.dim))
+        e = ctypes.c_double()
+        check(self._lib.aqs_stress(self._ctx, int(rep), _p(s, ctypes.c_double), ctypes.byref(e)), "aqs_stress")
+        return s, e.value
+
+    def energy_forces(self, rep: int):
+        f = np.zeros((int(self.n_atoms[rep]), self.dim))
+        e = ctypes.c_double()
+        check(self._lib.aqs_energy_forces(self._ctx, int(rep), ctypes.byref(e), _p(f, ctypes.c_double)),
+              "aqs_energy_forces")
+        return e.value, f

@@ -1,0 +1,185 @@
+"""GPU parity of the batched engine against the CPU oracle, through the C ABI.
+
+Inputs: oracle-quenched synthetic glasses (tests/data, written by
+tests/data/make_inputs.py) at sizes that span several 256-atom tiles and a
+ragged tail.  Bars: relative energy 1e-10, positions 1e-8 sigma (minimum
+image), identical statuses, every inherent structure certified
+max|F| < 1e-10 by the oracle's own forces."""
+import numpy as np
+import pytest
+
+import aqs_synth as S
+import oracle as O
+from gpu_common import E_REL_TOL, FTOL, POS_TOL, certified_fmax, fire_pair, load_glass
+
+pytestmark = pytest.mark.gpu
+POT = O.kob_andersen()
+
+
+def engine(dim, ns, L, dg, **kw):
+    from paper_2507_20802_amd import Engine, Tuning
+    fire = kw.pop("fire", None)
+    tuning = kw.pop("tuning", None) or Tuning()
+    return Engine(dim, ns, L, dg, fire=fire, tuning=tuning)
+
+
+@pytest.mark.parametrize("name,k,dg", [("glass2d_1000", 0, 1e-4), ("glass2d_1000", 30, 1e-3),
+                                       ("glass3d_1500", 0, 5e-5), ("glass3d_1500", 7, 1e-2)])
+def test_energy_forces_parity(name, k, dg):
+    pos, types, L, dim = load_glass(name)
+    x = O.affine(pos, k * dg)
+    H = O.strain_box(dim, L, k, dg)
+    eng = engine(dim, [len(types)], L, dg)
+    eng.set_replica(0, types, x, k)
+    E, F = eng.energy_forces(0)
+    Eo, Fo, So, _ = O.energy_forces(x, types, H, POT)
+    assert abs(E - Eo) <= 1e-12 * abs(Eo)
+    assert np.abs(F - Fo).max() <= 1e-11 * max(1.0, np.abs(Fo).max())
+    sig, E2 = eng.stress(0)
+    assert abs(E2 - Eo) <= 1e-12 * abs(Eo)
+    assert np.allclose(sig, So, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("gamma", [-0.5, -0.2, 0.0, 0.31, 0.5])
+def test_cell_lists_match_all_pairs_in_tilted_boxes(gamma):
+    """Tiny system, atoms on cell faces and box faces, tilt in [-0.5, 0.5]:
+    the cell-list forces equal the oracle's all-pairs sum."""
+    n, dim = 120, 2
+    s = S.jittered_lattice_start(dim, 11, 5, int(gamma * 100) + 50, jitter=0.2)
+    L = S.box_length(121, dim)
+    pos = s.pos[:n].copy()
+    types = s.types[:n].copy()
+    rng = S.rng_for(5, 1)
+    for i in range(0, n, 7):   # exact cell / box faces in fractional coordinates
+        pos[i, rng.integers(0, 2)] = L * rng.integers(0, 4) / 3.0
+    k, dg = 1, gamma
+    x = O.affine(pos, gamma)
+    H = O.strain_box(dim, L, k, dg)
+    from paper_2507_20802_amd import Tuning
+    eng = engine(dim, [n], [L, L], dg, tuning=Tuning(skin=0.05))
+    eng.set_replica(0, types, x, k)
+    E, F = eng.energy_forces(0)
+    Eo, Fo, _, _ = O.energy_forces(x, types, H, POT, image_sum=True, image_range=2)
+    assert abs(E - Eo) <= 1e-12 * abs(Eo)
+    assert np.abs(F - Fo).max() <= 1e-10 * max(1.0, np.abs(Fo).max())
+
+
+@pytest.mark.parametrize("name,dg", [("glass2d_1000", 1e-4), ("glass3d_1500", 5e-5), ("glass2d_256", 1e-4)])
+def test_one_aqs_step_parity(name, dg):
+    pos, types, L, dim = load_glass(name)
+    fire, ofire = fire_pair()
+    H1 = O.strain_box(dim, L, 1, dg)
+    ref = O.fire(O.affine(pos, dg), types, H1, POT, ofire)
+    eng = engine(dim, [len(types)], L, dg, fire=fire)
+    eng.set_replica(0, types, pos, 0)
+    eng.affine_shear([0], [1])
+    rec = eng.minimize([0])[0, 0]
+    got = eng.positions(0)
+    assert rec["status"] == ref.status == O.CONVERGED
+    assert abs(rec["energy"] - ref.E) <= E_REL_TOL * abs(ref.E)
+    assert O.compare(got, ref.pos, H1)[0] <= POS_TOL
+    assert certified_fmax(got, types, H1) < FTOL
+    print(f"{name}: gpu {rec['iters']} oracle {ref.iters} FIRE iterations")
+
+
+def test_device_chain_matches_sequential_oracle():
+    """n fine AQS steps run on the device (Eq. 12) vs the oracle's sequential
+    steps, each oracle step from its own previous output."""
+    pos, types, L, dim = load_glass("glass2d_256")
+    dg, nst = 1e-4, 8
+    fire, ofire = fire_pair()
+    eng = engine(dim, [len(types)], L, dg, fire=fire)
+    eng.set_replica(0, types, pos, 0)
+    recs = eng.minimize([0], n_steps=[nst])[0]
+    x = pos
+    for k in range(0, nst + 1):
+        H = O.strain_box(dim, L, k, dg)
+        r = O.fire(O.affine(x, dg) if k else x, types, H, POT, ofire)
+        x = r.pos
+        assert recs[k]["status"] == r.status == 0
+        assert abs(recs[k]["energy"] - r.E) <= E_REL_TOL * abs(r.E)
+    assert recs[0]["iters"] == 0  # the input is an inherent structure
+    assert eng.strain_index(0) == nst
+    H = O.strain_box(dim, L, nst, dg)
+    got = eng.positions(0)
+    assert O.compare(got, x, H)[0] <= POS_TOL
+    assert certified_fmax(got, types, H) < FTOL
+
+
+def test_snapshot_compare_and_copy():
+    pos, types, L, dim = load_glass("glass2d_1000")
+    n = len(types)
+    eng = engine(dim, [n, n, n], L, 1e-4)
+    eng.set_replica(0, types, O.affine(pos, 3e-4), 3)
+    recs = eng.minimize([0], n_steps=[2], snap_dst=[1])
+    assert recs[0, 0]["status"] == 0
+    assert eng.strain_index(1) == 3 and eng.strain_index(0) == 5
+    # the snapshot holds the first inherent structure: re-minimising it takes 0 steps
+    eng.copy_replica(1, 2)
+    assert eng.compare(1, 2)[1] == 0.0
+    r2 = eng.minimize([2])[0, 0]
+    assert r2["iters"] == 0 and r2["status"] == 0
+    eq, d, de = eng.compare(1, 2)
+    assert eq and d == 0.0 and de == 0.0
+    # distance between the snapshot and a shifted copy matches the oracle
+    H = O.strain_box(dim, L, 3, 1e-4)
+    snap = eng.positions(1)
+    moved = snap.copy()
+    moved[::9] += 0.01
+    eng.set_positions(2, moved)
+    eq, d, _ = eng.compare(1, 2, delta_eq=1e-4)
+    assert not eq
+    assert d == pytest.approx(O.compare(snap, moved, H)[0], rel=1e-14)
+
+
+def test_uneven_batch_equals_single_runs_and_is_deterministic():
+    g2 = load_glass("glass2d_1000")
+    g1 = load_glass("glass2d_256")
+    ns = [len(g2[1]), len(g1[1]), len(g2[1])]
+    Ls = [[g2[2]] * 2, [g1[2]] * 2, [g2[2]] * 2]
+    dgs = [1e-4, 2e-4, 1e-3]
+    def run(sel):
+        eng = engine(2, ns, Ls, dgs)
+        for r, g in zip(range(3), (g2, g1, g2)):
+            eng.set_replica(r, g[1], g[0], 0)
+        eng.affine_shear(sel, [1] * len(sel))
+        rec = eng.minimize(sel, n_steps=[2] * len(sel))
+        return rec, [eng.positions(r) for r in sel]
+    rb, pb = run([0, 1, 2])
+    rb2, pb2 = run([0, 1, 2])
+    assert all(np.array_equal(a, b) for a, b in zip(pb, pb2))  # bitwise repeatable
+    for i in range(3):
+        rs, ps = run([i])
+        assert np.array_equal(rs[0]["energy"], rb[i]["energy"])
+        assert np.array_equal(ps[0], pb[i])
+
+
+def test_maxiter_stops_like_the_oracle():
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, ofire = fire_pair(max_iter=7)
+    H = O.strain_box(dim, L, 1, 1e-2)
+    ref = O.fire(O.affine(pos, 1e-2), types, H, POT, ofire)
+    eng = engine(dim, [len(types)], L, 1e-2, fire=fire)
+    eng.set_replica(0, types, pos, 0)
+    eng.affine_shear([0], [1])
+    rec = eng.minimize([0])[0, 0]
+    assert rec["status"] == ref.status == O.MAXITER and rec["iters"] == ref.iters == 7
+    assert O.compare(eng.positions(0), ref.pos, H)[0] <= 1e-12
+
+
+def test_rebuilds_during_minimisation_keep_parity():
+    """A tiny skin forces neighbour-list rebuilds inside the minimisation;
+    the trajectory is unchanged."""
+    pos, types, L, dim = load_glass("glass3d_1500")
+    from paper_2507_20802_amd import Tuning
+    fire, ofire = fire_pair()
+    dg = 2e-3
+    H = O.strain_box(dim, L, 1, dg)
+    ref = O.fire(O.affine(pos, dg), types, H, POT, ofire)
+    eng = engine(dim, [len(types)], L, dg, fire=fire, tuning=Tuning(skin=0.002))
+    eng.set_replica(0, types, pos, 0)
+    eng.affine_shear([0], [1])
+    rec = eng.minimize([0])[0, 0]
+    assert rec["status"] == ref.status == 0
+    assert abs(rec["energy"] - ref.E) <= E_REL_TOL * abs(ref.E)
+    assert O.compare(eng.positions(0), ref.pos, H)[0] <= POS_TOL
