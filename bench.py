@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched AQS hot path on one MI355X.
+
+Workload (default): a 3D binary Lennard-Jones glass, N = 32768 atoms
+(Kob-Andersen-type parameters, 80:20, density 1.2, cutoff 2.5 sigma_ab),
+quenched on the GPU from seeded uniform random positions.  One "step" is
+one round of Algorithm 1 (Sec. 3.5) with P = 16 level-II chains of K = 200
+fine AQS steps at dgamma = 5e-5 (level-I anchors at i * 1e-2), every
+minimisation run by FIRE to max|F| < 1e-10, all chains batched on the GPU.
+Each step starts from the same inherent structure (already in HBM).
+
+Prints one JSON line: accepted AQS steps/s (value), FIRE iterations per AQS
+step, the roofline of the dominant kernel (the FP64 force kernel, timed with
+HIP events on its stream inside the timed region) and the CPU oracle timed
+on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "AQS steps/s & FIRE iters/step at N=32k, learned-start vs plain, max|F|<1e-10"
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
+HBM_PEAK_GBS = 8000.0
+FLOPS_PER_PAIR = 29          # one in-cutoff pair, counted once
+FORCE_BYTES_PER_ATOM = {2: 49, 3: 73}
+
+
+def in_cutoff_neighbours(pos, types, L, pot) -> float:
+    """Mean number of neighbours within rc_ab (directed pairs per atom) of
+    an orthogonal periodic box, counted with a k-d tree (host tooling)."""
+    from scipy.spatial import cKDTree
+    n, dim = pos.shape
+    x = np.mod(pos, L)
+    tree = cKDTree(x, boxsize=L)
+    rcm = pot.rc_factor * max(max(r) for r in pot.sigma)
+    pairs = tree.query_pairs(rcm, output_type="ndarray")
+    d = x[pairs[:, 0]] - x[pairs[:, 1]]
+    d -= L * np.round(d / L)
+    r = np.sqrt((d * d).sum(1))
+    sig = np.asarray(pot.sigma)[types[pairs[:, 0]], types[pairs[:, 1]]]
+    inside = r < pot.rc_factor * sig
+    return 2.0 * inside.sum() / n
+
+
+def cpu_baseline(dim, n, dg, iters_per_step, seconds=20.0):
+    """Time the CPU oracle (sequential AQS, O(N^2) pair sums, all host
+    threads) on a bounded sample: a few force evaluations of the same
+    workload size; AQS steps/s = 1 / (t_eval * (iterations per step + 1))."""
+    import oracle as O
+    import aqs_synth as S
+    s = S.jittered_lattice_start(dim, round(n ** (1 / dim)), 3, 9) if round(n ** (1 / dim)) ** dim == n \
+        else S.uniform_glass_start(dim, n, 3, 9)
+    H = O.strain_box(dim, s.L, 1, dg)
+    x = O.affine(s.pos, dg)
+    pot = O.kob_andersen()
+    O.energy_forces(x[:64], s.types[:64], O.box_matrix(dim, 50.0, 0.0), pot)  # load
+    t0 = time.perf_counter()
+    evals = 0
+    while True:
+        O.energy_forces(x, s.types, H, pot)
+        evals += 1
+        if time.perf_counter() - t0 > seconds / 2 or evals >= 50:
+            break
+    t_eval = (time.perf_counter() - t0) / evals
+    rate = 1.0 / (t_eval * (iters_per_step + 1.0))
+    return {"value": rate, "unit": "AQS steps/s", "cores": O.get_threads(), "kind": "oracle",
+            "sample": f"{evals} O(N^2) force evaluations of the N={n} {dim}D workload "
+                      f"({t_eval:.3f} s each) x (GPU-measured {iters_per_step:.1f} FIRE iterations + 1) "
+                      f"per sequential AQS step",
+            "t_eval_s": t_eval}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dim", type=int, default=3)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--P", type=int, default=16)
+    ap.add_argument("--K", type=int, default=200)
+    ap.add_argument("--dgamma", type=float, default=5e-5)
+    ap.add_argument("--warmup-K", type=int, default=20, help="fine steps per chain in warmup rounds")
+    ap.add_argument("--profile-every", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(the multi-GPU sharding is design only).", file=sys.stderr)
+        return 2
+
+    import torch
+    import aqs_synth as S
+    from paper_2507_20802_amd import Engine, Fire, LJParams, Tuning, parallel
+
+    torch.cuda.set_device(0)
+    dim, n, P, K, dg = args.dim, args.n, args.P, args.K, args.dgamma
+    pot = LJParams()
+    s = S.uniform_glass_start(dim, n, 3, 0)
+    nslots = parallel.slots_needed(1, P)
+    eng = Engine(dim, [n] * nslots, s.L, dg, pot=pot, fire=Fire(), tuning=Tuning())
+    glass = parallel.layout(1, P)[0]
+    t0 = time.perf_counter()
+    eng.set_replica(glass.star, s.types, s.pos, 0)
+    q = eng.minimize([glass.star])[0, 0]
+    quench_s = time.perf_counter() - t0
+    if q["status"] != 0:
+        print(f"quench failed: status {q['status']}", file=sys.stderr)
+        return 1
+    is_pos = eng.positions(glass.star)
+    nb = in_cutoff_neighbours(is_pos, s.types, s.L, pot)
+
+    def one_round(Kr):
+        eng.set_replica(glass.star, s.types, is_pos, 0)
+        g = parallel.layout(1, P)[0]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = parallel.run(eng, [g], P * Kr, Kr, P)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, out, g
+
+    for _ in range(args.warmup):
+        one_round(args.warmup_K)
+    eng.counters(reset=True)
+    eng.set_profiling(args.profile_every)
+    tot_t, acc, comp, iters, ok, rounds = 0.0, 0, 0, [], True, []
+    for _ in range(args.steps):
+        dt, out, g = one_round(K)
+        tot_t += dt
+        acc += out["accepted_steps"]
+        comp += out["computed_steps"]
+        iters.extend(g.step_iters)
+        ok = ok and out["statuses_ok"]
+        rounds.append({"wall_s": dt, "accepted": out["accepted_steps"], "computed": out["computed_steps"],
+                       "rounds_of_alg1": out["rounds"], "decisions": [d.equal for d in g.decisions],
+                       "anchor_iters": g.anchor_iters})
+    eng.set_profiling(0)
+    cnt = eng.counters()
+    it = np.asarray(iters, dtype=np.float64)
+    value = acc / tot_t
+    # roofline of the force kernel: algorithmic flops per atom-evaluation
+    atom_evals_per_launch = None
+    flops_per_atom = 0.5 * nb * FLOPS_PER_PAIR
+    avg_ms = cnt["force_ms"] / max(cnt["force_timed"], 1)
+    # active atoms per launch: total force-phase atom evaluations / launches
+    evals = cnt.get("atom_evals", 0)
+    if evals and cnt["force_launches"]:
+        atom_evals_per_launch = evals / cnt["force_launches"]
+    else:
+        atom_evals_per_launch = P * n
+    achieved_tflops = flops_per_atom * atom_evals_per_launch / (avg_ms * 1e-3) / 1e12
+    achieved_gbs = FORCE_BYTES_PER_ATOM[dim] * atom_evals_per_launch / (avg_ms * 1e-3) / 1e9
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "accepted AQS steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * tot_t / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{dim}D binary LJ glass N={n}, Algorithm 1 round: P={P} chains x K={K} "
+                               f"fine AQS steps, dgamma={dg:g}, dgamma_c={K * dg:g}, FIRE to max|F|<1e-10, "
+                               f"plain start",
+                   "dim": dim, "n_atoms": n, "P": P, "K": K, "dgamma": dg},
+        "computed_steps_per_s": comp / tot_t,
+        "fire_iters_per_step": {"mean": float(it.mean()), "median": float(np.median(it)),
+                                "p95": float(np.percentile(it, 95))},
+        "all_converged": bool(ok),
+        "quench_s": quench_s,
+        "mean_neighbours_in_cutoff": nb,
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": f"k_force<{dim}>", "avg_launch_ms": avg_ms,
+                     "atoms_per_launch": atom_evals_per_launch,
+                     "algorithmic_flops_per_atom": flops_per_atom,
+                     "hbm_gbs_algorithmic": achieved_gbs, "hbm_frac": achieved_gbs / HBM_PEAK_GBS},
+        "counters": cnt,
+        "rounds": rounds,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(dim, n, dg, float(it.mean()), args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

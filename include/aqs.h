@@ -84,14 +84,17 @@ typedef struct {
   int64_t max_iter;
 } aqs_fire_params;
 
-/* Performance knobs.  None changes what is computed beyond the order of
- * floating-point sums inside one atom's force (skin). */
+/* Performance knobs.  None changes what is computed beyond the rounding of
+ * one atom's force sum (its order depends on skin and threads_per_atom);
+ * results are bitwise repeatable for fixed knobs. */
 typedef struct {
   double skin;              /* Verlet skin added to each pair cutoff; 0 = 0.3 */
   int32_t max_neighbors;    /* list capacity per atom; 0 = 64 (2D) / 192 (3D) */
   int32_t block_iters;      /* FIRE iterations launched between host polls; 0 = 32 */
   int32_t use_graph;        /* 1: replay each block of iterations as a hipGraph */
   int32_t max_chain_steps;  /* largest n_steps accepted by aqs_minimize_batch; 0 = 1024 */
+  int32_t threads_per_atom; /* force kernel: 1, 2, 4 or 8 lanes per atom; 0 = 2 (2D) / 4 (3D) */
+  int32_t pad_;
 } aqs_tuning;
 
 /* One record per minimisation of a chain (index 0 = the first minimisation,
@@ -200,6 +203,25 @@ aqs_status aqs_stress(aqs_ctx* ctx, int32_t rep, double* sigma, double* energy);
  * current positions.  Synchronises. */
 aqs_status aqs_energy_forces(aqs_ctx* ctx, int32_t rep, double* energy,
                              double* forces);
+
+/* Work counters of a context, accumulated since creation or the last reset.
+ * Kernel times are measured with HIP events on the context stream around
+ * sampled launches (see aqs_set_profiling); launches counts all. */
+typedef struct {
+  double force_ms;          /* summed duration of the timed force launches */
+  int64_t force_timed;      /* force launches timed */
+  double update_ms;         /* summed duration of the timed update launches */
+  int64_t update_timed;
+  int64_t force_launches;   /* force launches issued */
+  int64_t rebuilds;         /* neighbour-list rebuild passes */
+  int64_t host_polls;       /* state read-backs of the minimisation loop */
+  int64_t atom_evals;       /* atoms whose force was evaluated, summed over launches */
+} aqs_counters;
+
+/* Time every n-th block of FIRE iterations (0 = no timing). */
+aqs_status aqs_set_profiling(aqs_ctx* ctx, int32_t every_nth_block);
+
+aqs_status aqs_get_counters(aqs_ctx* ctx, aqs_counters* out, int32_t reset);
 
 /* Human-readable description of the last error on this thread. */
 const char* aqs_last_error(void);

@@ -382,7 +382,7 @@ void orc_affine(int dim, int n, double* pos, double dgamma) {
  * place of the paper's conjugate gradients.  Unit mass.  Steps, in order:
  *
  *   1  evaluate E, F at x
- *   2  if any value is not finite: NONFINITE
+ *   2  if the energy, a force or a position is not finite: NONFINITE
  *      if max_i |F_i| < ftol: CONVERGED (checked before any update, so an
  *      inherent structure takes zero iterations)
  *   3  P = F . v
@@ -416,6 +416,8 @@ int orc_fire(int dim, int n, double* pos, const uint8_t* type, const double* H,
     if (rc != 0) break;
     fmax = 0.0;
     int finite = isfinite(E);
+    for (size_t k = 0; k < nd; ++k)
+      if (!isfinite(pos[k])) finite = 0;
     for (int i = 0; i < n; ++i) {
       double f2 = 0.0;
       for (int a = 0; a < dim; ++a) f2 += F[i * dim + a] * F[i * dim + a];

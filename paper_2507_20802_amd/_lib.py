@@ -38,12 +38,20 @@ class aqs_fire_params(ctypes.Structure):
 class aqs_tuning(ctypes.Structure):
     _fields_ = [("skin", ctypes.c_double), ("max_neighbors", ctypes.c_int32),
                 ("block_iters", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("max_chain_steps", ctypes.c_int32)]
+                ("max_chain_steps", ctypes.c_int32), ("threads_per_atom", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class aqs_step_record(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("energy", ctypes.c_double), ("max_f", ctypes.c_double),
                 ("sigma_xy", ctypes.c_double), ("status", ctypes.c_int32), ("start", ctypes.c_int32)]
+
+
+class aqs_counters(ctypes.Structure):
+    _fields_ = [("force_ms", ctypes.c_double), ("force_timed", ctypes.c_int64),
+                ("update_ms", ctypes.c_double), ("update_timed", ctypes.c_int64),
+                ("force_launches", ctypes.c_int64), ("rebuilds", ctypes.c_int64),
+                ("host_polls", ctypes.c_int64), ("atom_evals", ctypes.c_int64)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/aqs.h
@@ -68,6 +76,8 @@ SIGNATURES = {
                                              ctypes.c_double, c_int32_p, c_double_p, c_double_p]),
     "aqs_stress": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p, c_double_p]),
     "aqs_energy_forces": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p, c_double_p]),
+    "aqs_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "aqs_get_counters": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_counters), ctypes.c_int32]),
     "aqs_last_error": (ctypes.c_char_p, []),
 }
 

@@ -47,7 +47,7 @@ double rc_max_of(const aqs_potential* p) {
 
 struct Tune {
   double skin;
-  int max_nb, block_iters, use_graph, log_cap;
+  int max_nb, block_iters, use_graph, log_cap, tpa;
 };
 
 Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
@@ -57,6 +57,8 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   r.block_iters = (t && t->block_iters > 0) ? t->block_iters : 32;
   r.use_graph = t ? t->use_graph : 0;
   r.log_cap = ((t && t->max_chain_steps > 0) ? t->max_chain_steps : 1024) + 1;
+  const int tp = t ? t->threads_per_atom : 0;
+  r.tpa = (tp == 1 || tp == 2 || tp == 4 || tp == 8) ? tp : (pot->dim == 3 ? 4 : 2);
   return r;
 }
 
@@ -73,7 +75,7 @@ struct Layout {
   size_t total = 0;
   size_t o_geom, o_state, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
       o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl,
-      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4;
+      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_evals, o_xref4, o_ftbl;
   int64_t atoms = 0;      // padded atoms over all slots
   int64_t nb_entries = 0;
   int32_t blocks = 0;
@@ -138,7 +140,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_inv = take(sizeof(int32_t) * A);
   lo.o_nbc = take(sizeof(int32_t) * A);
   lo.o_nbl = take(sizeof(uint32_t) * (size_t)lo.nb_entries);
-  lo.o_fpart = take(sizeof(double) * kForceParts * (size_t)lo.blocks);
+  lo.o_fpart = take(sizeof(double) * kForceParts * kMaxTPA * (size_t)lo.blocks);
   lo.o_upart = take(sizeof(double) * (size_t)lo.blocks);
   lo.o_counter = take(sizeof(uint32_t) * n_rep);
   lo.o_log = take(sizeof(StepRecord) * (size_t)n_rep * tn.log_cap);
@@ -159,6 +161,9 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   for (int a = 0; a < 3; ++a) lo.o_dl[a] = take(sizeof(double) * A);
   for (int a = 0; a < 3; ++a) lo.o_tdl[a] = take(sizeof(double) * A);
   lo.o_alt4 = take(sizeof(double4) * A);
+  lo.o_evals = take(sizeof(unsigned long long));
+  lo.o_xref4 = take(sizeof(double4) * A);
+  lo.o_ftbl = take(sizeof(int2) * ((size_t)lo.blocks * kMaxTPA + 8));
   lo.total = off;
   return AQS_OK;
 }
@@ -193,17 +198,29 @@ struct aqs_ctx {
   int32_t *ccount, *cstart, *cellof, *order, *tid;
   double4* tpos4;
   double *tvx, *tvy, *tvz;
-  int2 *tbl, *tbl2;
+  int2 *tbl, *tbl2, *ftbl;
   int32_t *reps_d, *nc3_d, *overflow;
   double *dg_d, *red;
   double *dlx, *dly, *dlz, *tdlx, *tdly, *tdlz;
   double4* alt4;
+  unsigned long long* evals;
+  double4* xref4;
   // host mirrors
   State* h_state = nullptr;  // pinned
   std::vector<char> loaded, dirty;
   // iteration table of the current selection
   std::vector<int32_t> cur_sel;
   int32_t cur_nblk = 0;
+  int32_t cur_ntiles = 0;
+  // pinned staging of host-to-device uploads (one use per synchronisation)
+  int2 *h_tbl = nullptr, *h_ftbl = nullptr, *h_tbl2 = nullptr;
+  int32_t *h_reps = nullptr, *h_nc3 = nullptr, *h_over = nullptr;
+  double* h_dg = nullptr;
+  // profiling
+  int32_t prof_every = 0;
+  int64_t block_count = 0;
+  std::vector<hipEvent_t> ev;
+  aqs_counters cnt{};
 };
 
 namespace {
@@ -211,6 +228,8 @@ namespace {
 IterArgs iter_args(aqs_ctx* c) {
   IterArgs a{};
   a.blocks = c->tbl;
+  a.ftiles = c->ftbl;
+  a.tpa = c->tn.tpa;
   a.geom = c->d_geom;
   a.state = c->d_state;
   a.pos4 = c->pos4;
@@ -227,17 +246,19 @@ IterArgs iter_args(aqs_ctx* c) {
   a.rc_max = c->rc_max;
   a.dlx = c->dlx; a.dly = c->dly; a.dlz = c->dlz;
   a.alt4 = c->alt4;
+  a.evals = c->evals;
+  a.xref4 = c->xref4;
   return a;
 }
 
 // Launch table over the blocks of the given slots, in an order that gives
 // each of the 8 XCDs (hardware block b runs on XCD b mod 8) a contiguous run
 // of blocks, so neighbouring tiles share that XCD's L2.
-std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
+std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, int per_block = 1) {
   std::vector<int2> logical;
   for (int r : sel) {
     const Geom& g = c->lo.geom[r];
-    for (int b = 0; b < g.nblocks; ++b) logical.push_back(make_int2(r, b));
+    for (int b = 0; b < g.nblocks * per_block; ++b) logical.push_back(make_int2(r, b));
   }
   const size_t nb = logical.size();
   const size_t per = (nb + 7) / 8;
@@ -252,7 +273,22 @@ std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
 aqs_status pull_state(aqs_ctx* c) {
   HIPCHK(hipMemcpyAsync(c->h_state, c->d_state, sizeof(State) * c->n_rep, hipMemcpyDeviceToHost,
                         c->stream));
+  HIPCHK(hipMemcpyAsync(c->h_over, c->overflow, sizeof(int32_t), hipMemcpyDeviceToHost,
+                        c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  return AQS_OK;
+}
+
+// Neighbour-list overflow recorded by a rebuild since the last check.
+aqs_status check_overflow(aqs_ctx* c) {
+  if (*c->h_over > 0) {
+    const int over = *c->h_over;
+    *c->h_over = 0;
+    HIPCHK(hipMemsetAsync(c->overflow, 0, sizeof(int32_t), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return fail(AQS_ECAPACITY, "neighbour list overflow: an atom has %d neighbours, capacity %d",
+                over, c->tn.max_nb);
+  }
   return AQS_OK;
 }
 
@@ -270,7 +306,7 @@ double tilt_of(aqs_ctx* c, int r, int64_t k) {
 
 // Rebuild cell order and neighbour lists of the given slots (positions as
 // they are on the device; h_state must be current).
-aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel) {
+aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = false) {
   if (sel.empty()) return AQS_OK;
   const double rl = c->rc_max + c->tn.skin;
   std::vector<int32_t> nc3(3 * sel.size());
@@ -287,13 +323,15 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel) {
     for (int a = 0; a < 3; ++a) nc3[3 * i + a] = nc[a];
   }
   std::vector<int2> tbl = make_table(c, sel);
-  HIPCHK(hipMemcpyAsync(c->tbl2, tbl.data(), sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
+  std::copy(tbl.begin(), tbl.end(), c->h_tbl2);
+  std::copy(sel.begin(), sel.end(), c->h_reps);
+  std::copy(nc3.begin(), nc3.end(), c->h_nc3);
+  HIPCHK(hipMemcpyAsync(c->tbl2, c->h_tbl2, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
                         c->stream));
-  HIPCHK(hipMemcpyAsync(c->reps_d, sel.data(), sizeof(int32_t) * sel.size(),
+  HIPCHK(hipMemcpyAsync(c->reps_d, c->h_reps, sizeof(int32_t) * sel.size(),
                         hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->nc3_d, nc3.data(), sizeof(int32_t) * nc3.size(), hipMemcpyHostToDevice,
+  HIPCHK(hipMemcpyAsync(c->nc3_d, c->h_nc3, sizeof(int32_t) * nc3.size(), hipMemcpyHostToDevice,
                         c->stream));
-  HIPCHK(hipMemsetAsync(c->overflow, 0, sizeof(int32_t), c->stream));
   RebuildArgs a{};
   a.blocks = c->tbl2;
   a.nblk = (int32_t)tbl.size();
@@ -302,6 +340,7 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel) {
   a.geom = c->d_geom;
   a.state = c->d_state;
   a.pos4 = c->pos4;
+  a.xref4 = c->xref4;
   a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
   a.id = c->id; a.inv = c->inv;
   a.nbc = c->nbc; a.nbl = c->nbl;
@@ -313,19 +352,19 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel) {
   a.skin = c->tn.skin;
   a.max_nb = c->tn.max_nb;
   a.dim = c->dim;
+  a.resume = in_loop ? 1 : 0;
   a.dlx = c->dlx; a.dly = c->dly; a.dlz = c->dlz;
   a.tdlx = c->tdlx; a.tdly = c->tdly; a.tdlz = c->tdlz;
   launch_rebuild(a, c->lo.max_cells, c->stream, c->nc3_d);
   HIPCHK(hipGetLastError());
-  int32_t over = 0;
-  HIPCHK(hipMemcpyAsync(&over, c->overflow, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  if (over > 0)
-    return fail(AQS_ECAPACITY, "neighbour list overflow: an atom has %d neighbours, capacity %d",
-                over, c->tn.max_nb);
+  ++c->cnt.rebuilds;
   for (int r : sel) c->dirty[r] = 0;
-  // the rebuild kernels updated nc, ubound and gamma_build on the device
-  return pull_state(c);
+  // in the minimisation loop the next poll reads the overflow flag and the
+  // state; elsewhere check now
+  if (in_loop) return AQS_OK;
+  aqs_status st = pull_state(c);
+  if (st) return st;
+  return check_overflow(c);
 }
 
 aqs_status check_slot(aqs_ctx* c, int r) {
@@ -337,12 +376,25 @@ aqs_status check_slot(aqs_ctx* c, int r) {
 
 aqs_status set_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
   std::vector<int2> tbl = make_table(c, sel);
-  HIPCHK(hipMemcpyAsync(c->tbl, tbl.data(), sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
+  std::vector<int2> ftbl = make_table(c, sel, c->tn.tpa);
+  std::copy(tbl.begin(), tbl.end(), c->h_tbl);
+  std::copy(ftbl.begin(), ftbl.end(), c->h_ftbl);
+  HIPCHK(hipMemcpyAsync(c->tbl, c->h_tbl, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(c->ftbl, c->h_ftbl, sizeof(int2) * ftbl.size(), hipMemcpyHostToDevice,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->cur_sel = sel;
   c->cur_nblk = (int32_t)tbl.size();
+  c->cur_ntiles = (int32_t)ftbl.size();
   return AQS_OK;
+}
+
+void free_pinned(aqs_ctx* c) {
+  void* ps[] = {c->h_state, c->h_tbl, c->h_ftbl, c->h_tbl2, c->h_reps, c->h_nc3, c->h_over, c->h_dg};
+  for (void* p : ps)
+    if (p) (void)hipHostFree(p);
+  c->h_state = nullptr;
 }
 
 void reset_fire(aqs_ctx* c, State& s) {
@@ -436,6 +488,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->tid = at<int32_t>(w, lo.o_tid);
   c->tbl = at<int2>(w, lo.o_tbl);
   c->tbl2 = at<int2>(w, lo.o_tbl2);
+  c->ftbl = at<int2>(w, lo.o_ftbl);
   c->reps_d = at<int32_t>(w, lo.o_reps);
   c->nc3_d = at<int32_t>(w, lo.o_nc3);
   c->overflow = at<int32_t>(w, lo.o_overflow);
@@ -444,11 +497,23 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->dlx = at<double>(w, lo.o_dl[0]); c->dly = at<double>(w, lo.o_dl[1]); c->dlz = at<double>(w, lo.o_dl[2]);
   c->tdlx = at<double>(w, lo.o_tdl[0]); c->tdly = at<double>(w, lo.o_tdl[1]); c->tdlz = at<double>(w, lo.o_tdl[2]);
   c->alt4 = at<double4>(w, lo.o_alt4);
+  c->evals = at<unsigned long long>(w, lo.o_evals);
+  c->xref4 = at<double4>(w, lo.o_xref4);
 
-  if (hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) != hipSuccess) {
+  const size_t tcap = (size_t)lo.blocks * kMaxTPA + 16;
+  if (hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_tbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_ftbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_tbl2, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_reps, sizeof(int32_t) * n_rep, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_nc3, sizeof(int32_t) * 3 * n_rep, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_over, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_dg, sizeof(double) * n_rep, hipHostMallocDefault) != hipSuccess) {
+    free_pinned(c);
     delete c;
-    return fail(AQS_EHIP, "hipHostMalloc of the state mirror failed");
+    return fail(AQS_EHIP, "hipHostMalloc of the host staging buffers failed");
   }
+  *c->h_over = 0;
   std::memset(c->h_state, 0, sizeof(State) * n_rep);
   for (int r = 0; r < n_rep; ++r) {
     c->h_state[r].phase = PH_IDLE;
@@ -464,7 +529,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
       hipMemcpyAsync(c->d_state, c->h_state, sizeof(State) * n_rep, hipMemcpyHostToDevice, s) !=
           hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
-    (void)hipHostFree(c->h_state);
+    free_pinned(c);
     delete c;
     return fail(AQS_EHIP, "initialising the workspace failed");
   }
@@ -475,7 +540,8 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
 aqs_status aqs_destroy(aqs_ctx* c) {
   if (!c) return AQS_OK;
   (void)hipStreamSynchronize(c->stream);
-  if (c->h_state) (void)hipHostFree(c->h_state);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  free_pinned(c);
   delete c;
   return AQS_OK;
 }
@@ -624,9 +690,11 @@ aqs_status aqs_affine_shear(aqs_ctx* c, int32_t n_sel, const int32_t* rep, const
     c->h_state[sel[i]].k += dk[i];
   }
   std::vector<int2> tbl = make_table(c, sel);
-  HIPCHK(hipMemcpyAsync(c->tbl2, tbl.data(), sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
+  std::copy(tbl.begin(), tbl.end(), c->h_tbl2);
+  std::copy(dg.begin(), dg.end(), c->h_dg);
+  HIPCHK(hipMemcpyAsync(c->tbl2, c->h_tbl2, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
                         c->stream));
-  HIPCHK(hipMemcpyAsync(c->dg_d, dg.data(), sizeof(double) * c->n_rep, hipMemcpyHostToDevice,
+  HIPCHK(hipMemcpyAsync(c->dg_d, c->h_dg, sizeof(double) * c->n_rep, hipMemcpyHostToDevice,
                         c->stream));
   launch_affine(c->tbl2, (int32_t)tbl.size(), c->d_geom, c->pos4, c->dg_d, c->stream);
   HIPCHK(hipGetLastError());
@@ -688,13 +756,41 @@ aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int
   HIPCHK(hipGetLastError());
   IterArgs a = iter_args(c);
   for (;;) {
-    for (int it = 0; it < c->tn.block_iters; ++it) {
-      launch_force(a, c->cur_nblk, c->dim, c->stream);
+    const bool timed = c->prof_every > 0 && (c->block_count % c->prof_every) == 0;
+    const int M = c->tn.block_iters;
+    if (timed && (int)c->ev.size() < 4 * M) {
+      while ((int)c->ev.size() < 4 * M) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c->ev.push_back(e);
+      }
+    }
+    for (int it = 0; it < M; ++it) {
+      if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 0], c->stream));
+      launch_force(a, c->cur_ntiles, c->dim, c->stream);
+      if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 1], c->stream));
       launch_update(a, c->cur_nblk, c->dim, c->stream);
+      if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 2], c->stream));
     }
     HIPCHK(hipGetLastError());
+    c->cnt.force_launches += M;
+    ++c->block_count;
     st = pull_state(c);
     if (st) return st;
+    st = check_overflow(c);
+    if (st) return st;
+    ++c->cnt.host_polls;
+    if (timed) {
+      for (int it = 0; it < M; ++it) {
+        float f = 0.f, u = 0.f;
+        HIPCHK(hipEventElapsedTime(&f, c->ev[4 * it + 0], c->ev[4 * it + 1]));
+        HIPCHK(hipEventElapsedTime(&u, c->ev[4 * it + 1], c->ev[4 * it + 2]));
+        c->cnt.force_ms += f;
+        c->cnt.update_ms += u;
+      }
+      c->cnt.force_timed += M;
+      c->cnt.update_timed += M;
+    }
     std::vector<int32_t> rb;
     int active = 0;
     for (int r : sel) {
@@ -704,10 +800,8 @@ aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int
     }
     if (!active) break;
     if (!rb.empty()) {
-      st = rebuild(c, rb);
-      if (st) return st;
-      for (int r : rb) c->h_state[r].phase = PH_FIRE;
-      st = push_state(c);
+      // rebuilt slots resume FIRE on the device (no host round trip)
+      st = rebuild(c, rb, true);
       if (st) return st;
     }
   }
@@ -815,7 +909,7 @@ aqs_status aqs_energy_forces(aqs_ctx* c, int32_t rep, double* energy, double* fo
   st = set_table(c, sel);
   if (st) return st;
   IterArgs a = iter_args(c);
-  launch_force(a, c->cur_nblk, c->dim, c->stream);
+  launch_force(a, c->cur_ntiles, c->dim, c->stream);
   HIPCHK(hipGetLastError());
   st = pull_state(c);
   if (st) return st;
@@ -841,6 +935,28 @@ aqs_status aqs_energy_forces(aqs_ctx* c, int32_t rep, double* energy, double* fo
     HIPCHK(hipStreamSynchronize(c->stream));
     for (int s = 0; s < g.n; ++s)
       for (int k = 0; k < d; ++k) forces[idv[s] * d + k] = f[k][s];
+  }
+  return AQS_OK;
+}
+
+aqs_status aqs_set_profiling(aqs_ctx* c, int32_t every_nth_block) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  c->prof_every = every_nth_block > 0 ? every_nth_block : 0;
+  c->block_count = 0;
+  return AQS_OK;
+}
+
+aqs_status aqs_get_counters(aqs_ctx* c, aqs_counters* out, int32_t reset) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  unsigned long long ev = 0;
+  HIPCHK(hipMemcpyAsync(&ev, c->evals, sizeof ev, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->cnt.atom_evals = (int64_t)ev;
+  if (out) *out = c->cnt;
+  if (reset) {
+    c->cnt = aqs_counters{};
+    HIPCHK(hipMemsetAsync(c->evals, 0, sizeof ev, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
   }
   return AQS_OK;
 }

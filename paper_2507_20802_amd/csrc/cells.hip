@@ -184,6 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_back(RebuildArgs a) {
   if (li >= g.n) return;
   const int64_t gi = g.atom_off + li;
   a.pos4[gi] = a.tpos4[gi];
+  a.xref4[gi] = a.tpos4[gi];
   a.vx[gi] = a.tvx[gi];
   a.vy[gi] = a.tvy[gi];
   if (D == 3) a.vz[gi] = a.tvz[gi];
@@ -252,7 +253,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
           const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
           if (r2 < rl2[(int)pj.w]) {
             if (cnt < a.max_nb)
-              L[(int64_t)cnt * g.npad] = (uint32_t)j | ((uint32_t)code << kCodeShift);
+              L[(int64_t)cnt * g.npad] = (uint32_t)j | ((uint32_t)code << kCodeShift) |
+                                         ((uint32_t)pj.w << 29);
             else
               over = true;
             ++cnt;
@@ -273,6 +275,7 @@ __global__ void k_rb_done(RebuildArgs a) {
   if (threadIdx.x == 0) {
     st->ubound = 0.0;
     st->gamma_build = strain_of(st->k, g.dgamma);
+    if (a.resume && st->phase == PH_REBUILD) st->phase = PH_FIRE;
   }
 }
 

@@ -10,7 +10,8 @@
 //     nbc    int32, neighbour count per atom
 //   neighbour list per slot: max_nb x npad uint32, column-major (entry k of
 //     atom i at k*npad + i) so a wavefront reads 64 consecutive words;
-//     entry = j | (image code << 24), image code in [0, 3^dim)
+//     entry = j | (image code << 24) | (type of j << 29), code in [0, 27)
+//   xref4  double4, positions at the last list build (validity test)
 //   per-block partial sums, per-slot counters, per-slot state and geometry.
 #pragma once
 
@@ -21,7 +22,8 @@ namespace aqs {
 
 constexpr int kBlock = 256;           // atoms per workgroup (4 wavefronts)
 constexpr int kWave = 64;
-constexpr int kForceParts = 8;        // doubles per block partial of the force kernel
+constexpr int kForceParts = 8;        // doubles per tile partial of the force kernel
+constexpr int kMaxTPA = 8;            // threads per atom of the force kernel: 1, 2, 4 or 8
 constexpr uint32_t kIdxMask = 0x00FFFFFFu;
 constexpr int kCodeShift = 24;
 
@@ -35,6 +37,7 @@ enum Phase : int32_t {
   PH_DONE = 5,
   PH_REBUILD = 6,   // neighbour list no longer valid; waits for the host
   PH_EVAL = 7,      // one force evaluation without FIRE control
+  PH_ENERGY = 11,   // evaluate again with the energy, then record the pending outcome
   PH_LDESC = 8,     // learned start: descriptors + MLP pending at the IS
   PH_LMOVE = 9,     // learned start: update moves plain start -> learned start
   PH_LREVERT = 10,  // learned start rejected: update restores the plain start
@@ -76,7 +79,8 @@ struct State {
   int32_t start_mode; // AQS_START_*
   int32_t start_used; // start of the minimisation in progress
   int32_t learn_ok;   // learned displacement passed its pre-checks
-  int32_t pad_[2];
+  int32_t pending;    // outcome recorded after the PH_ENERGY evaluation
+  int32_t pad_;
 };
 
 struct PairParams {   // per type pair t = 2 ti + tj
@@ -97,7 +101,9 @@ struct StepRecord {
 
 // Everything the iteration kernels need, passed by value.
 struct IterArgs {
-  const int2* blocks;     // launch table: (slot, local block) or slot -1
+  const int2* blocks;     // update launch table: (slot, 256-atom block) or slot -1
+  const int2* ftiles;     // force launch table: (slot, force tile) or slot -1
+  int32_t tpa;            // threads per atom of the force kernel
   const Geom* geom;
   State* state;
   double4* pos4;
@@ -106,9 +112,10 @@ struct IterArgs {
   int32_t* id; int32_t* inv;
   const int32_t* nbc;
   const uint32_t* nbl;
-  double* fpart;          // kForceParts per global block
+  double* fpart;          // kForceParts per force tile (kMaxTPA tiles per 256-atom block)
   double* upart;          // 1 per global block (max displacement of the update)
   uint32_t* counter;      // per slot, last-block detection
+  unsigned long long* evals;  // atoms evaluated by force launches (statistics)
   StepRecord* log;        // per slot, log_cap records
   int32_t log_cap;
   int32_t max_nb;
@@ -118,6 +125,7 @@ struct IterArgs {
   // learned start (null when unused)
   double* dlx; double* dly; double* dlz;   // learned displacement per atom
   double4* alt4;                            // saved plain start
+  const double4* xref4;                     // positions at the last list build
 };
 
 __host__ __device__ inline double strain_of(int64_t k, double dgamma) {

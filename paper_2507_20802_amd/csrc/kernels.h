@@ -14,6 +14,7 @@ struct RebuildArgs {
   const Geom* geom;
   State* state;
   double4* pos4;
+  double4* xref4;       // positions at the build (list validity test)
   double* vx; double* vy; double* vz;
   int32_t* id; int32_t* inv;
   int32_t* nbc;
@@ -31,6 +32,7 @@ struct RebuildArgs {
   double skin;
   int32_t max_nb;
   int32_t dim;
+  int32_t resume;       // 1: slots in PH_REBUILD go back to PH_FIRE
   // learned-start per-atom buffers permuted with the atoms (may be null)
   double* dlx; double* dly; double* dlz;
   double* tdlx; double* tdly; double* tdlz;
@@ -39,8 +41,9 @@ struct RebuildArgs {
 void launch_rebuild(const RebuildArgs& a, int32_t max_cells_per_slot, hipStream_t s,
                     const int32_t* nc3_dev);
 
-// One FIRE iteration (force + control, then update) over the launch table.
-void launch_force(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s);
+// One FIRE iteration: force + control over the force tiles (a.ftiles), then
+// the update over the 256-atom blocks (a.blocks).
+void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s);
 void launch_update(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s);
 
 // Affine shear x += dg_r y of whole slots (host-driven level I step).

@@ -73,35 +73,88 @@ __device__ __forceinline__ double slot_tilt(const Geom& g, const State* st) {
 
 // ---------------------------------------------------------------------------
 // Lennard-Jones pair loop of one atom over its neighbour list, Eq. (13).
-// Accumulates F_i = sum_j U'(r) d / r (d = r_j - r_i), sum_j U(r) and
-// sum_j U'(r) dx dy / r; the caller halves the pair sums.
+// Accumulates F_i = sum_j U'(r) d / r (d = r_j - r_i) and, if WE, the pair
+// energy sum_j U(r) and sum_j U'(r) dx dy / r; the caller halves pair sums.
+//
+// The list is walked in chunks of kChunk entries: the chunk's neighbour
+// positions are gathered together while the next chunk's list entries are
+// already in flight, so one wavefront keeps 2 kChunk loads outstanding
+// instead of waiting on two dependent loads per pair.  1/r^2 is the hardware
+// reciprocal estimate refined by two Newton-Raphson steps (r <- r (2 - x r)),
+// within 1 ulp of the rounded quotient.
 
-template <int D>
-__device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint32_t* L,
-                                           int64_t stride, int cnt, const double4* P,
-                                           const double (*sh)[4], const PairParams* pp,
-                                           double& fx, double& fy, double& fz, double& e,
-                                           double& w) {
-  for (int k = 0; k < cnt; ++k) {
-    const uint32_t ent = L[(int64_t)k * stride];
-    const double4 pj = P[ent & kIdxMask];
-    const int code = (int)(ent >> kCodeShift);
-    const double dx = (pj.x - pi.x) + sh[code][0];
-    const double dy = (pj.y - pi.y) + sh[code][1];
-    const double dz = (D == 3) ? (pj.z - pi.z) + sh[code][2] : 0.0;
-    const double r2 = (D == 3) ? dx * dx + dy * dy + dz * dz : dx * dx + dy * dy;
-    const PairParams q = pp[2 * ti + (int)pj.w];
-    if (r2 < q.rc2) {
-      const double inv = 1.0 / r2;
-      const double s2 = q.sig2 * inv;
-      const double s6 = s2 * s2 * s2;
-      const double s12 = s6 * s6;
-      e += q.eps4 * (s12 - s6) - q.ucut;
-      const double g = q.eps4 * (6.0 * s6 - 12.0 * s12) * inv;  // U'(r) / r
-      fx += g * dx;
-      fy += g * dy;
-      if (D == 3) fz += g * dz;
-      w += g * dx * dy;
+constexpr int kChunk = 4;
+constexpr uint32_t kTypeBit = 1u << 29;
+
+__device__ __forceinline__ double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+template <int D, bool WE, int TPA>
+__device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint32_t* __restrict__ L,
+                                           int64_t stride, int cnt, uint32_t self_ent,
+                                           const double4* __restrict__ P, const double (*sh)[4],
+                                           const PairParams* pp, double& fx, double& fy,
+                                           double& fz, double& e, double& w) {
+  // this lane takes entries sub, sub + TPA, sub + 2 TPA, ... of the atom
+  const int sub = (int)(threadIdx.x % TPA);
+  const int my = cnt > sub ? (cnt - sub + TPA - 1) / TPA : 0;
+  L += (int64_t)sub * stride;
+  const int64_t st = (int64_t)TPA * stride;
+  uint32_t cur[kChunk];
+#pragma unroll
+  for (int u = 0; u < kChunk; ++u) cur[u] = (u < my) ? L[(int64_t)u * st] : self_ent;
+  for (int k0 = 0; k0 < my; k0 += kChunk) {
+    double4 pj[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) pj[u] = P[cur[u] & kIdxMask];
+    uint32_t nxt[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int k = k0 + kChunk + u;
+      nxt[u] = (k < my) ? L[(int64_t)k * st] : self_ent;
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const uint32_t ent = cur[u];
+      const int code = (int)((ent >> kCodeShift) & 31u);
+      const double dx = (pj[u].x - pi.x) + sh[code][0];
+      const double dy = (pj[u].y - pi.y) + sh[code][1];
+      const double dz = (D == 3) ? (pj[u].z - pi.z) + sh[code][2] : 0.0;
+      const double r2 = (D == 3) ? dx * dx + dy * dy + dz * dz : dx * dx + dy * dy;
+      const PairParams q = pp[2 * ti + ((ent & kTypeBit) ? 1 : 0)];
+      if (k0 + u < my && r2 < q.rc2) {
+        const double inv = recip_nr(r2);
+        const double s2 = q.sig2 * inv;
+        const double s6 = s2 * s2 * s2;
+        const double s12 = s6 * s6;
+        const double g = q.eps4 * (6.0 * s6 - 12.0 * s12) * inv;  // U'(r) / r
+        fx += g * dx;
+        fy += g * dy;
+        if (D == 3) fz += g * dz;
+        if (WE) {
+          e += q.eps4 * (s12 - s6) - q.ucut;
+          w += g * dx * dy;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) cur[u] = nxt[u];
+  }
+  // combine the TPA lanes of the atom (fixed butterfly: every lane of the
+  // group ends with the same bits)
+#pragma unroll
+  for (int off = 1; off < TPA; off <<= 1) {
+    fx += __shfl_xor(fx, off, kWave);
+    fy += __shfl_xor(fy, off, kWave);
+    if (D == 3) fz += __shfl_xor(fz, off, kWave);
+    if (WE) {
+      e += __shfl_xor(e, off, kWave);
+      w += __shfl_xor(w, off, kWave);
     }
   }
 }
@@ -109,6 +162,11 @@ __device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint3
 // ---------------------------------------------------------------------------
 // Per-slot FIRE control, run by thread 0 of the last block of a slot after
 // the force evaluation (Eq. 10 realised by FIRE 2.0; chain of Eq. 19).
+//
+// The force loop skips the pair energy during FIRE iterations (FIRE needs
+// only forces).  A minimisation that ends, or reaches max_iter, goes through
+// PH_ENERGY: one more evaluation at the same positions that also sums the
+// energy and the shear virial, after which the pending outcome is recorded.
 
 __device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
   StepRecord rec;
@@ -154,36 +212,45 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     a.state[rep] = s;
     return;
   }
-  // Validity of the neighbour list: every pair now within its cutoff was
-  // within cutoff + skin at the build if
-  //   |dgamma| rc_max + 2 (1 + |dgamma|)^2 u <= skin,
-  // dgamma = strain change since the build, u = bound on the non-affine
-  // displacement of any atom (sum of per-iteration maxima).
-  const double ub = s.ubound + r[7];
+  // Validity of the neighbour list.  With r_i = F x_ref,i + u_i (F the shear
+  // since the build, |gamma - gamma_build| = gd) every pair now closer than
+  // its cutoff was within cutoff + skin at the build if
+  //   gd rc_max + 2 (1 + gd) max_i |u_i| < skin.
+  const double ub = r[7];
   const double gam = strain_of(s.k, g.dgamma);
   const double gd = fabs(gam - s.gamma_build);
-  if (gd * a.rc_max + 2.0 * (1.0 + gd) * (1.0 + gd) * ub >= a.skin) {
+  if (!(gd * a.rc_max + 2.0 * (1.0 + gd) * ub < a.skin)) {
     s.phase = PH_REBUILD;
     a.state[rep] = s;
     return;
   }
   s.ubound = ub;
-  s.E = r[0];
   s.fmax = sqrt(r[4]);
-  s.sxy = r[5] / (g.L[0] * g.L[1] * g.L[2]);  // simple shear keeps V = Lx Ly Lz
-  if (phase == PH_EVAL) {
-    s.phase = PH_DONE;
+  if (phase == PH_EVAL || phase == PH_ENERGY) {
+    s.E = r[0];
+    s.sxy = r[5] / (g.L[0] * g.L[1] * g.L[2]);  // simple shear keeps V = Lx Ly Lz
+    if (phase == PH_EVAL) {
+      s.phase = PH_DONE;
+    } else if (s.pending == 1) {  // max_iter reached: record, then apply the last step
+      finish_min(a, rep, s, 1);
+      s.phase = PH_STOP;
+    } else {
+      finish_min(a, rep, s, s.pending);
+    }
     a.state[rep] = s;
     return;
   }
   s.phase = PH_FIRE;
-  if (r[6] != 0.0 || !isfinite(r[0]) || !isfinite(r[1])) {
+  if (r[6] != 0.0 || !isfinite(r[1]) || !isfinite(r[2])) {
+    s.E = NAN;
+    s.sxy = NAN;
     finish_min(a, rep, s, 3);
     a.state[rep] = s;
     return;
   }
   if (s.fmax < a.fire.ftol) {
-    finish_min(a, rep, s, 0);
+    s.pending = 0;
+    s.phase = PH_ENERGY;
     a.state[rep] = s;
     return;
   }
@@ -201,7 +268,8 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     s.npos = 0;
     s.nneg += 1;
     if (s.nneg > f.n_neg_max) {
-      finish_min(a, rep, s, 2);
+      s.pending = 2;
+      s.phase = PH_ENERGY;
       a.state[rep] = s;
       return;
     }
@@ -223,8 +291,8 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
   }
   s.it += 1;
   if (s.it >= f.max_iter) {
-    finish_min(a, rep, s, 1);
-    s.phase = PH_STOP;  // the update still applies this last step
+    s.pending = 1;
+    s.phase = PH_ENERGY;  // energy at these positions, then the last step
   }
   a.state[rep] = s;
 }
@@ -234,19 +302,51 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
 // the per-block partials (E, |F|^2, F.v, |v|^2, max |F_i|^2, W_xy, non-finite)
 // and, in the last block of each slot, the FIRE control.
 
-template <int D>
+template <int D, bool WE, int TPA>
+__device__ __forceinline__ void force_block(const IterArgs& a, const Geom& g, int tile,
+                                            double (*sh)[4], const PairParams* spp, double* part) {
+  const int li = tile * (kBlock / TPA) + (int)(threadIdx.x / TPA);
+  if (li >= g.n) return;
+  const int64_t gi = g.atom_off + li;
+  const double4 pi = a.pos4[gi];
+  double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
+  const uint32_t self_ent = (uint32_t)li | (13u << kCodeShift);
+  atom_pairs<D, WE, TPA>(pi, (int)pi.w, a.nbl + g.nb_off + li, g.npad, a.nbc[gi], self_ent,
+                         a.pos4 + g.atom_off, sh, spp, fx, fy, fz, e, w);
+  if (threadIdx.x % TPA != 0) return;
+  a.fx[gi] = fx;
+  a.fy[gi] = fy;
+  if (D == 3) a.fz[gi] = fz;
+  const double vx = a.vx[gi], vy = a.vy[gi], vz = (D == 3) ? a.vz[gi] : 0.0;
+  const double ff = fx * fx + fy * fy + fz * fz;
+  part[0] = 0.5 * e;
+  part[1] = ff;
+  part[2] = fx * vx + fy * vy + fz * vz;
+  part[3] = vx * vx + vy * vy + vz * vz;
+  part[4] = ff;
+  part[5] = 0.5 * w;
+  part[6] = (isfinite(e) && isfinite(ff) && isfinite(pi.x + pi.y + pi.z)) ? 0.0 : 1.0;
+}
+
+// Force kernel: TPA threads per atom, kBlock / TPA atoms of one slot per
+// block ("force tile").  Writes F, the per-tile partials (E, |F|^2, F.v,
+// |v|^2, max |F_i|^2, W_xy, non-finite) and, in the last tile of each slot,
+// combines them and runs the FIRE control.
+template <int D, int TPA>
 __global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
-  const int2 bt = a.blocks[blockIdx.x];
+  const int2 bt = a.ftiles[blockIdx.x];
   const int rep = bt.x;
   if (rep < 0) return;
   const int phase = a.state[rep].phase;
-  const bool compute = (phase == PH_FIRE || phase == PH_ADVANCE || phase == PH_EVAL);
+  const bool we = (phase == PH_EVAL || phase == PH_ENERGY);
+  const bool compute = we || phase == PH_FIRE || phase == PH_ADVANCE;
   const bool counted = compute || phase == PH_FINISH || phase == PH_STOP;
   if (!counted) return;
   const Geom g = a.geom[rep];
   const int tid = threadIdx.x;
+  const int ntiles = g.nblocks * TPA;
 
-  __shared__ double sh[27][4];
+  __shared__ double sh[32][4];
   __shared__ PairParams spp[4];
   __shared__ double red[kForceParts][kBlock / kWave];
   __shared__ int s_last;
@@ -258,46 +358,30 @@ __global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
     if (tid < 27) code_shift(tid, g.L[0], g.L[1], g.L[2], t, sh[tid]);
     if (tid < 4) spp[tid] = a.pp[tid];
     __syncthreads();
-    const int li = bt.y * kBlock + tid;
-    if (li < g.n) {
-      const int64_t gi = g.atom_off + li;
-      const double4 pi = a.pos4[gi];
-      double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
-      atom_pairs<D>(pi, (int)pi.w, a.nbl + g.nb_off + li, g.npad, a.nbc[gi], a.pos4 + g.atom_off,
-                    sh, spp, fx, fy, fz, e, w);
-      a.fx[gi] = fx;
-      a.fy[gi] = fy;
-      if (D == 3) a.fz[gi] = fz;
-      const double vx = a.vx[gi], vy = a.vy[gi], vz = (D == 3) ? a.vz[gi] : 0.0;
-      const double ff = fx * fx + fy * fy + fz * fz;
-      part[0] = 0.5 * e;
-      part[1] = ff;
-      part[2] = fx * vx + fy * vy + fz * vz;
-      part[3] = vx * vx + vy * vy + vz * vz;
-      part[4] = ff;
-      part[5] = 0.5 * w;
-      part[6] = (isfinite(e) && isfinite(ff)) ? 0.0 : 1.0;
-    }
+    if (we)
+      force_block<D, true, TPA>(a, g, bt.y, sh, spp, part);
+    else
+      force_block<D, false, TPA>(a, g, bt.y, sh, spp, part);
     block_reduce<kForceParts>(part, ops, red);
     if (tid == 0) {
-      double* dst = a.fpart + (int64_t)(g.block0 + bt.y) * kForceParts;
+      double* dst = a.fpart + ((int64_t)g.block0 * kMaxTPA + bt.y) * kForceParts;
 #pragma unroll
       for (int c = 0; c < 7; ++c) dst[c] = part[c];
     }
   }
-  // last block of the slot runs the control
+  // the last tile of the slot runs the control
   if (tid == 0) {
     __threadfence();
     const unsigned old = atomicAdd(a.counter + rep, 1u);
-    s_last = (old == (unsigned)(g.nblocks - 1)) ? 1 : 0;
+    s_last = (old == (unsigned)(ntiles - 1)) ? 1 : 0;
   }
   __syncthreads();
   if (!s_last) return;
   __threadfence();
   double r[kForceParts] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (compute) {
-    for (int b = tid; b < g.nblocks; b += kBlock) {
-      const double* src = a.fpart + (int64_t)(g.block0 + b) * kForceParts;
+    for (int b = tid; b < ntiles; b += kBlock) {
+      const double* src = a.fpart + ((int64_t)g.block0 * kMaxTPA + b) * kForceParts;
       r[0] += __builtin_nontemporal_load(src + 0);
       r[1] += __builtin_nontemporal_load(src + 1);
       r[2] += __builtin_nontemporal_load(src + 2);
@@ -305,19 +389,21 @@ __global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
       r[4] = fmax(r[4], __builtin_nontemporal_load(src + 4));
       r[5] += __builtin_nontemporal_load(src + 5);
       r[6] = fmax(r[6], __builtin_nontemporal_load(src + 6));
-      r[7] = fmax(r[7], __builtin_nontemporal_load(a.upart + g.block0 + b));
     }
+    for (int b = tid; b < g.nblocks; b += kBlock)
+      r[7] = fmax(r[7], __builtin_nontemporal_load(a.upart + g.block0 + b));
   }
   block_reduce<kForceParts>(r, ops, red);
   if (tid == 0) {
     a.counter[rep] = 0u;
+    if (compute) atomicAdd(a.evals, (unsigned long long)g.n);
     control(a, rep, g, r, phase);
   }
 }
 
 // ---------------------------------------------------------------------------
 // FIRE update (steps 5-9 of the minimiser) or the fine affine step of the
-// chain, per atom; per-block max displacement for the list-validity bound.
+// chain, per atom; per-block max |u_i| = |r_i - F x_ref,i| for the list test.
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
@@ -327,7 +413,8 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
   const State* st = a.state + rep;
   const int phase = st->phase;
   const bool fire = (phase == PH_FIRE || phase == PH_STOP);
-  if (!(fire || phase == PH_ADVANCE || phase == PH_FINISH)) return;
+  const bool adv = (phase == PH_ADVANCE);
+  if (!(fire || adv || phase == PH_FINISH)) return;
   const Geom g = a.geom[rep];
   const int tid = threadIdx.x;
   const int li = bt.y * kBlock + tid;
@@ -336,9 +423,16 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
   if (li < g.n) {
     const int64_t gi = g.atom_off + li;
     double4 p = a.pos4[gi];
+    if (st->do_snap && phase != PH_FIRE) {  // first inherent structure -> snap_dst
+      const Geom gd = a.geom[st->snap_dst];
+      const int64_t di = gd.atom_off + li;
+      a.pos4[di] = p;
+      const int32_t aid = a.id[gi];
+      a.id[di] = aid;
+      a.inv[gd.atom_off + aid] = li;
+    }
     if (fire) {
       const double dt = st->dt, cv = st->cv, cf = st->cf, dmax = a.fire.dmax;
-      const double ox = p.x, oy = p.y, oz = p.z;
       double vx = a.vx[gi], vy = a.vy[gi], vz = (D == 3) ? a.vz[gi] : 0.0;
       const double fx = a.fx[gi], fy = a.fy[gi], fz = (D == 3) ? a.fz[gi] : 0.0;
       if (st->restart) {
@@ -369,41 +463,43 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       a.vx[gi] = vx;
       a.vy[gi] = vy;
       if (D == 3) a.vz[gi] = vz;
-      const double ddx = p.x - ox, ddy = p.y - oy, ddz = p.z - oz;
-      m[0] = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-    } else {
-      if (st->do_snap) {
-        const Geom gd = a.geom[st->snap_dst];
-        const int64_t di = gd.atom_off + li;
-        a.pos4[di] = p;
-        const int32_t aid = a.id[gi];
-        a.id[di] = aid;
-        a.inv[gd.atom_off + aid] = li;
-      }
-      if (phase == PH_ADVANCE) {
-        p.x += g.dgamma * p.y;  // Eq. (16): x <- x + dgamma y
-        a.pos4[gi] = p;
-        a.vx[gi] = 0.0;
-        a.vy[gi] = 0.0;
-        if (D == 3) a.vz[gi] = 0.0;
-      }
+    } else if (adv) {
+      p.x += g.dgamma * p.y;  // Eq. (16): x <- x + dgamma y
+      a.pos4[gi] = p;
+      a.vx[gi] = 0.0;
+      a.vy[gi] = 0.0;
+      if (D == 3) a.vz[gi] = 0.0;
+    }
+    if (fire || adv) {
+      const double4 x0 = a.xref4[gi];
+      const double gd = strain_of(st->k, g.dgamma) - st->gamma_build;
+      const double ux = p.x - (x0.x + gd * x0.y), uy = p.y - x0.y, uz = p.z - x0.z;
+      m[0] = sqrt(ux * ux + uy * uy + uz * uz);
     }
   }
-  if (fire) {
+  if (fire || adv) {
     const int op[1] = {1};
     block_reduce<1>(m, op, red);
     if (tid == 0) a.upart[g.block0 + bt.y] = m[0];
-  } else if (phase == PH_ADVANCE && tid == 0) {
-    a.upart[g.block0 + bt.y] = 0.0;
   }
 }
 
-void launch_force(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
-  if (nblk <= 0) return;
+template <int D>
+void launch_force_d(const IterArgs& a, int32_t ntiles, int32_t tpa, hipStream_t s) {
+  switch (tpa) {
+    case 1: hipLaunchKernelGGL((k_force<D, 1>), dim3(ntiles), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_force<D, 2>), dim3(ntiles), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_force<D, 4>), dim3(ntiles), dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_force<D, 8>), dim3(ntiles), dim3(kBlock), 0, s, a); break;
+  }
+}
+
+void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s) {
+  if (ntiles <= 0) return;
   if (dim == 3)
-    hipLaunchKernelGGL(k_force<3>, dim3(nblk), dim3(kBlock), 0, s, a);
+    launch_force_d<3>(a, ntiles, a.tpa, s);
   else
-    hipLaunchKernelGGL(k_force<2>, dim3(nblk), dim3(kBlock), 0, s, a);
+    launch_force_d<2>(a, ntiles, a.tpa, s);
 }
 
 void launch_update(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
@@ -552,15 +648,15 @@ __global__ __launch_bounds__(kBlock) void k_virial(IterArgs a, int rep, double L
     for (int k = 0; k < cnt; ++k) {
       const uint32_t ent = L[(int64_t)k * g.npad];
       const double4 pj = P[ent & kIdxMask];
-      const int code = (int)(ent >> kCodeShift);
+      const int code = (int)((ent >> kCodeShift) & 31u);
       double d[3];
       d[0] = (pj.x - pi.x) + sh[code][0];
       d[1] = (pj.y - pi.y) + sh[code][1];
       d[2] = (D == 3) ? (pj.z - pi.z) + sh[code][2] : 0.0;
       const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      const PairParams q = spp[2 * ti + (int)pj.w];
+      const PairParams q = spp[2 * ti + ((ent & kTypeBit) ? 1 : 0)];
       if (r2 < q.rc2) {
-        const double inv = 1.0 / r2;
+        const double inv = recip_nr(r2);
         const double s2 = q.sig2 * inv;
         const double s6 = s2 * s2 * s2;
         const double s12 = s6 * s6;

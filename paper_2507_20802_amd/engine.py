@@ -77,6 +77,7 @@ class Tuning:
     block_iters: int = 32
     use_graph: int = 0
     max_chain_steps: int = 1024
+    threads_per_atom: int = 0
 
     def to_c(self) -> aqs_tuning:
         t = aqs_tuning()
@@ -85,6 +86,7 @@ class Tuning:
         t.block_iters = self.block_iters
         t.use_graph = self.use_graph
         t.max_chain_steps = self.max_chain_steps
+        t.threads_per_atom = self.threads_per_atom
         return t
 
 
@@ -245,3 +247,12 @@ class Engine:
         check(self._lib.aqs_energy_forces(self._ctx, int(rep), ctypes.byref(e), _p(f, ctypes.c_double)),
               "aqs_energy_forces")
         return e.value, f
+
+    # -- measurement ------------------------------------------------------
+    def set_profiling(self, every_nth_block: int) -> None:
+        check(self._lib.aqs_set_profiling(self._ctx, int(every_nth_block)), "aqs_set_profiling")
+
+    def counters(self, reset: bool = False) -> dict:
+        c = _lib.aqs_counters()
+        check(self._lib.aqs_get_counters(self._ctx, ctypes.byref(c), int(reset)), "aqs_get_counters")
+        return {k: getattr(c, k) for k, _ in c._fields_}

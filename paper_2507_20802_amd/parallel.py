@@ -1,0 +1,167 @@
+"""Algorithm 1 of the paper (Sec. 3.5, "Parallel calculation scheme") on the
+GPU engine, for one or many independent glasses at once.
+
+Per round and glass, with r_star in its slot:
+  level I   copy r_star into P' chain slots; chain i gets the affine map
+            F_N^(i K dgamma) in one multiplication (Eq. 18)
+  level II  one batched aqs_minimize_batch over every chain of every glass:
+            the anchor minimisation F(r^c_iK) (its result is copied on the
+            device into a snapshot slot: the "outgoing" configuration of
+            Sec. 3.3) followed by the chain's fine AQS steps (Eq. 19), each
+            chain advancing on its own on the device
+  check     for i = 1..P'-1 in order: end of chain i-1 ("incoming") vs the
+            snapshot of chain i ("outgoing"), Eq. (20); first failure stops
+  update    q accepted steps; r_star <- r_q (Algorithm 1)
+
+Readings (the paper is silent): the last round is clamped to the remaining
+steps (P' = ceil(R / K) chains, the last with R - (P'-1) K steps); a round
+with a single chain accepts it; r_q is the end of chain q/K - 1.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+from ._lib import AQS_START_PLAIN
+
+
+def chain_plan(remaining: int, K: int, P: int) -> List[int]:
+    """Fine-step counts of the chains of one round (last round clamped)."""
+    if remaining >= P * K:
+        return [K] * P
+    p = math.ceil(remaining / K)
+    return [K] * (p - 1) + [remaining - (p - 1) * K]
+
+
+@dataclass
+class Decision:
+    round: int
+    index: int          # i of the check (compares end of chain i-1 with outgoing of chain i)
+    strain_index: int   # k of both configurations
+    equal: bool
+    max_disp: float
+    de_per_atom: float
+
+
+@dataclass
+class GlassRun:
+    star: int                   # slot of r_star
+    chains: List[int]           # P chain slots
+    snaps: List[int]            # P snapshot slots (entry 0 unused)
+    n_current: int = 0
+    rounds: List[dict] = field(default_factory=list)
+    decisions: List[Decision] = field(default_factory=list)
+    step_iters: List[int] = field(default_factory=list)     # FIRE iterations of every fine step computed
+    accepted_iters: List[int] = field(default_factory=list)  # ... of the accepted fine steps
+    anchor_iters: List[int] = field(default_factory=list)    # anchor minimisations
+    energies: List[float] = field(default_factory=list)      # accepted trajectory E (per accepted step)
+    sigma_xy: List[float] = field(default_factory=list)
+    statuses_ok: bool = True
+    computed_steps: int = 0
+
+
+def slots_needed(n_glasses: int, P: int) -> int:
+    return n_glasses * (1 + 2 * P)
+
+
+def layout(n_glasses: int, P: int, first: int = 0) -> List[GlassRun]:
+    """Slot assignment: per glass, [star, chain_0..chain_{P-1}, snap_0..snap_{P-1}]."""
+    out = []
+    s = first
+    for _ in range(n_glasses):
+        star = s
+        chains = list(range(s + 1, s + 1 + P))
+        snaps = list(range(s + 1 + P, s + 1 + 2 * P))
+        out.append(GlassRun(star, chains, snaps))
+        s += 1 + 2 * P
+    return out
+
+
+def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq: float = 1e-4,
+        start: int = AQS_START_PLAIN, max_rounds: int | None = None, log=None) -> dict:
+    """Run Algorithm 1 to n_steps accepted fine steps for every glass (each
+    glass's r_star must be loaded in its star slot as an inherent structure).
+    Returns timing and counts; per-glass details are filled into glasses."""
+    if P < 2:
+        raise ValueError("Algorithm 1 needs P >= 2 (Sec. 3.2)")
+    t0 = time.perf_counter()
+    rnd = 0
+    t_min = 0.0
+    t_check = 0.0
+    while any(g.n_current < n_steps for g in glasses):
+        if max_rounds is not None and rnd >= max_rounds:
+            break
+        sel, nst, snp, plans = [], [], [], {}
+        dks, aff = [], []
+        for gi, g in enumerate(glasses):
+            if g.n_current >= n_steps:
+                continue
+            lengths = chain_plan(n_steps - g.n_current, K, P)
+            plans[gi] = lengths
+            for i, ln in enumerate(lengths):
+                engine.copy_replica(g.star, g.chains[i])
+                if i > 0:
+                    aff.append(g.chains[i])
+                    dks.append(i * K)
+                sel.append(g.chains[i])
+                nst.append(ln)
+                snp.append(g.snaps[i] if i > 0 else -1)
+        if aff:
+            engine.affine_shear(aff, dks)           # level I (Eq. 18)
+        t1 = time.perf_counter()
+        recs = engine.minimize(sel, n_steps=nst, snap_dst=snp, start=start)   # level II
+        t2 = time.perf_counter()
+        t_min += t2 - t1
+        row = {s: recs[j] for j, s in enumerate(sel)}
+        for gi, lengths in plans.items():
+            g = glasses[gi]
+            q = lengths[0]
+            last = 0
+            checks = []
+            for i in range(1, len(lengths)):
+                eq, md, de = engine.compare(g.chains[i - 1], g.snaps[i], delta_eq)   # Eq. (20)
+                k = engine.strain_index(g.snaps[i])
+                d = Decision(rnd, i, k, eq, md, de)
+                g.decisions.append(d)
+                checks.append(eq)
+                if eq:
+                    q = i * K + lengths[i]
+                    last = i
+                else:
+                    q = i * K
+                    last = i - 1
+                    break
+            # bookkeeping of iterations (fine steps are records 1..len of each chain)
+            for i, ln in enumerate(lengths):
+                r = row[g.chains[i]]
+                if np.any(r["status"][: ln + 1] != 0):
+                    g.statuses_ok = False
+                g.anchor_iters.append(int(r["iters"][0]))
+                g.step_iters.extend(int(x) for x in r["iters"][1: ln + 1])
+                g.computed_steps += ln
+                if i <= last:
+                    g.accepted_iters.extend(int(x) for x in r["iters"][1: ln + 1])
+                    g.energies.extend(float(x) for x in r["energy"][1: ln + 1])
+                    g.sigma_xy.extend(float(x) for x in r["sigma_xy"][1: ln + 1])
+            engine.copy_replica(g.chains[last], g.star)   # r_star <- r_q
+            g.rounds.append({"round": rnd, "start": g.n_current, "lengths": lengths,
+                             "checks": checks, "q": q})
+            g.n_current += q
+            if log:
+                log(f"round {rnd} glass {gi}: checks {checks} q {q} -> N_current {g.n_current}")
+        t_check += time.perf_counter() - t2
+        rnd += 1
+    wall = time.perf_counter() - t0
+    acc = sum(g.n_current for g in glasses)
+    comp = sum(g.computed_steps for g in glasses)
+    it = np.array([x for g in glasses for x in g.step_iters], dtype=np.int64)
+    return {"wall_s": wall, "minimize_s": t_min, "check_s": t_check, "rounds": rnd,
+            "accepted_steps": acc, "computed_steps": comp,
+            "iters_mean": float(it.mean()) if it.size else 0.0,
+            "iters_median": float(np.median(it)) if it.size else 0.0,
+            "iters_p95": float(np.percentile(it, 95)) if it.size else 0.0,
+            "statuses_ok": all(g.statuses_ok for g in glasses)}

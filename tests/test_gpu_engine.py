@@ -183,3 +183,27 @@ def test_rebuilds_during_minimisation_keep_parity():
     assert rec["status"] == ref.status == 0
     assert abs(rec["energy"] - ref.E) <= E_REL_TOL * abs(ref.E)
     assert O.compare(eng.positions(0), ref.pos, H)[0] <= POS_TOL
+
+
+@pytest.mark.parametrize("tpa", [1, 2, 4, 8])
+def test_threads_per_atom_variants_agree(tpa):
+    """Every lane split of the force loop gives the oracle's forces, and a
+    full AQS step gives the same inherent structure."""
+    from paper_2507_20802_amd import Tuning
+    pos, types, L, dim = load_glass("glass3d_1500")
+    dg = 1e-3
+    x = O.affine(pos, dg)
+    H = O.strain_box(dim, L, 1, dg)
+    eng = engine(dim, [len(types)], L, dg, tuning=Tuning(threads_per_atom=tpa))
+    eng.set_replica(0, types, x, 1)
+    E, F = eng.energy_forces(0)
+    Eo, Fo, _, _ = O.energy_forces(x, types, H, POT)
+    assert abs(E - Eo) <= 1e-12 * abs(Eo)
+    assert np.abs(F - Fo).max() <= 1e-11 * max(1.0, np.abs(Fo).max())
+    fire, ofire = fire_pair()
+    ref = O.fire(x, types, H, POT, ofire)
+    eng2 = engine(dim, [len(types)], L, dg, fire=fire, tuning=Tuning(threads_per_atom=tpa))
+    eng2.set_replica(0, types, x, 1)
+    rec = eng2.minimize([0])[0, 0]
+    assert rec["status"] == 0 and abs(rec["energy"] - ref.E) <= E_REL_TOL * abs(ref.E)
+    assert O.compare(eng2.positions(0), ref.pos, H)[0] <= POS_TOL
