@@ -26,6 +26,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(objdir, exist_ok=True)
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # keep private arrays out of LDS: the force kernel's LDS is its halo
+             "-mllvm", "-disable-promote-alloca-to-lds=true",
              "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
     objs, procs = [], []
     for src in sources():

@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/aqs.h"
+#include "aqs.h"
 #include "kernels.h"
 
 using namespace aqs;
@@ -71,15 +71,24 @@ void cell_grid(int dim, const double* L, double tilt, double rl, int* nc) {
   nc[2] = dim == 3 ? (int)std::floor(L[2] / rl) : 1;
 }
 
+// Segments per cell row of the force tiles: about 90% of a block's atom
+// lanes (kBlock / threads_per_atom) per segment on average.
+int segments_per_row(int n, int rows, int tpa) {
+  const int per = kBlock / tpa;
+  const double mean_row = (double)n / rows;
+  return std::max(1, (int)std::ceil(mean_row / (0.9 * per)));
+}
+
 struct Layout {
   size_t total = 0;
   size_t o_geom, o_state, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
       o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl,
-      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_evals, o_xref4, o_ftbl;
+      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_evals, o_xref4, o_ftbl, o_ttbl, o_thdr, o_truns, o_sel;
   int64_t atoms = 0;      // padded atoms over all slots
   int64_t nb_entries = 0;
   int32_t blocks = 0;
   int32_t cells = 0;      // sum of (cell_cap + 1)
+  int32_t tiles = 0;      // sum of tile_cap
   int32_t max_cells = 0;
   std::vector<Geom> geom;
 };
@@ -114,6 +123,10 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
                     g.L[a], 3.0 * rl);
     g.cell_cap = nc[0] * nc[1] * nc[2];
     g.cell_off = cell_off;
+    // force tiles: rows x segments; rows are fixed by the grid in y, z
+    g.tile_off = lo.tiles;
+    g.tile_cap = nc[1] * nc[2] * segments_per_row(n, nc[1] * nc[2], 8);
+    lo.tiles += g.tile_cap;
     lo.max_cells = std::max(lo.max_cells, g.cell_cap);
     atom_off += g.npad;
     nb_off += (int64_t)g.npad * tn.max_nb;
@@ -140,7 +153,9 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_inv = take(sizeof(int32_t) * A);
   lo.o_nbc = take(sizeof(int32_t) * A);
   lo.o_nbl = take(sizeof(uint32_t) * (size_t)lo.nb_entries);
-  lo.o_fpart = take(sizeof(double) * kForceParts * kMaxTPA * (size_t)lo.blocks);
+  lo.o_fpart = take(sizeof(double) * kForceParts * (size_t)lo.tiles);
+  lo.o_thdr = take(sizeof(TileHdr) * (size_t)lo.tiles);
+  lo.o_truns = take(sizeof(TileRun) * kRuns * (size_t)lo.tiles);
   lo.o_upart = take(sizeof(double) * (size_t)lo.blocks);
   lo.o_counter = take(sizeof(uint32_t) * n_rep);
   lo.o_log = take(sizeof(StepRecord) * (size_t)n_rep * tn.log_cap);
@@ -154,7 +169,8 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_tbl = take(sizeof(int2) * ((size_t)lo.blocks + 8));
   lo.o_tbl2 = take(sizeof(int2) * ((size_t)lo.blocks + 8));
   lo.o_reps = take(sizeof(int32_t) * n_rep);
-  lo.o_nc3 = take(sizeof(int32_t) * 3 * n_rep);
+  lo.o_sel = take(sizeof(int32_t) * n_rep);
+  lo.o_nc3 = take(sizeof(int32_t) * kGridInts * n_rep);
   lo.o_overflow = take(sizeof(int32_t));
   lo.o_dg = take(sizeof(double) * n_rep);
   lo.o_red = take(sizeof(double) * 10 * ((size_t)lo.blocks + 8));
@@ -163,7 +179,8 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_alt4 = take(sizeof(double4) * A);
   lo.o_evals = take(sizeof(unsigned long long));
   lo.o_xref4 = take(sizeof(double4) * A);
-  lo.o_ftbl = take(sizeof(int2) * ((size_t)lo.blocks * kMaxTPA + 8));
+  lo.o_ftbl = take(sizeof(int2) * ((size_t)lo.tiles + 8));
+  lo.o_ttbl = take(sizeof(int2) * ((size_t)lo.tiles + 8));
   lo.total = off;
   return AQS_OK;
 }
@@ -198,13 +215,15 @@ struct aqs_ctx {
   int32_t *ccount, *cstart, *cellof, *order, *tid;
   double4* tpos4;
   double *tvx, *tvy, *tvz;
-  int2 *tbl, *tbl2, *ftbl;
-  int32_t *reps_d, *nc3_d, *overflow;
+  int2 *tbl, *tbl2, *ftbl, *ttbl;
+  int32_t *reps_d, *nc3_d, *overflow, *sel_d;
   double *dg_d, *red;
   double *dlx, *dly, *dlz, *tdlx, *tdly, *tdlz;
   double4* alt4;
   unsigned long long* evals;
   double4* xref4;
+  TileHdr* thdr;
+  TileRun* truns;
   // host mirrors
   State* h_state = nullptr;  // pinned
   std::vector<char> loaded, dirty;
@@ -212,9 +231,11 @@ struct aqs_ctx {
   std::vector<int32_t> cur_sel;
   int32_t cur_nblk = 0;
   int32_t cur_ntiles = 0;
+  std::vector<int32_t> tiles_now;  // force tiles of each slot's current grid
+  bool ftable_stale = false;       // a rebuild changed the tiles of the selection
   // pinned staging of host-to-device uploads (one use per synchronisation)
-  int2 *h_tbl = nullptr, *h_ftbl = nullptr, *h_tbl2 = nullptr;
-  int32_t *h_reps = nullptr, *h_nc3 = nullptr, *h_over = nullptr;
+  int2 *h_tbl = nullptr, *h_ftbl = nullptr, *h_tbl2 = nullptr, *h_ttbl = nullptr;
+  int32_t *h_reps = nullptr, *h_nc3 = nullptr, *h_over = nullptr, *h_sel = nullptr;
   double* h_dg = nullptr;
   // profiling
   int32_t prof_every = 0;
@@ -229,6 +250,8 @@ IterArgs iter_args(aqs_ctx* c) {
   IterArgs a{};
   a.blocks = c->tbl;
   a.ftiles = c->ftbl;
+  a.sel = c->sel_d;
+  a.nsel = (int32_t)c->cur_sel.size();
   a.tpa = c->tn.tpa;
   a.geom = c->d_geom;
   a.state = c->d_state;
@@ -237,6 +260,9 @@ IterArgs iter_args(aqs_ctx* c) {
   a.fx = c->fx; a.fy = c->fy; a.fz = c->fz;
   a.id = c->id; a.inv = c->inv;
   a.nbc = c->nbc; a.nbl = c->nbl;
+  a.cell_start = c->cstart;
+  a.thdr = c->thdr;
+  a.truns = c->truns;
   a.fpart = c->fpart; a.upart = c->upart; a.counter = c->counter;
   a.log = c->log; a.log_cap = c->tn.log_cap;
   a.max_nb = c->tn.max_nb;
@@ -260,6 +286,22 @@ std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, int pe
     const Geom& g = c->lo.geom[r];
     for (int b = 0; b < g.nblocks * per_block; ++b) logical.push_back(make_int2(r, b));
   }
+  const size_t nb = logical.size();
+  const size_t per = (nb + 7) / 8;
+  std::vector<int2> tbl(per * 8, make_int2(-1, 0));
+  for (size_t b = 0; b < tbl.size(); ++b) {
+    const size_t lk = (b % 8) * per + b / 8;
+    if (lk < nb) tbl[b] = logical[lk];
+  }
+  return tbl;
+}
+
+// Launch table over the force tiles of the given slots' current grids,
+// XCD-contiguous.
+std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
+  std::vector<int2> logical;
+  for (int r : sel)
+    for (int t = 0; t < c->tiles_now[r]; ++t) logical.push_back(make_int2(r, t));
   const size_t nb = logical.size();
   const size_t per = (nb + 7) / 8;
   std::vector<int2> tbl(per * 8, make_int2(-1, 0));
@@ -306,10 +348,11 @@ double tilt_of(aqs_ctx* c, int r, int64_t k) {
 
 // Rebuild cell order and neighbour lists of the given slots (positions as
 // they are on the device; h_state must be current).
-aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = false) {
+aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = false,
+                   int list_mode = 0) {
   if (sel.empty()) return AQS_OK;
   const double rl = c->rc_max + c->tn.skin;
-  std::vector<int32_t> nc3(3 * sel.size());
+  std::vector<int32_t> nc3(kGridInts * sel.size());
   for (size_t i = 0; i < sel.size(); ++i) {
     const int r = sel[i];
     const Geom& g = c->lo.geom[r];
@@ -320,10 +363,24 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = f
         return fail(AQS_EINVAL, "slot %d: sheared box too thin for the cell stencil", r);
     if (nc[0] * nc[1] * nc[2] > g.cell_cap)
       return fail(AQS_EINVAL, "slot %d: cell grid exceeds capacity", r);
-    for (int a = 0; a < 3; ++a) nc3[3 * i + a] = nc[a];
+    int32_t* q = &nc3[kGridInts * i];
+    for (int a = 0; a < 3; ++a) q[a] = nc[a];
+    q[3] = segments_per_row(g.n, nc[1] * nc[2], c->tn.tpa);
+    q[4] = q[3] * nc[1] * nc[2];
+    if (q[4] > g.tile_cap) return fail(AQS_EINVAL, "slot %d: force tiles exceed capacity", r);
+    q[5] = list_mode;
+    if (c->tiles_now[r] != q[4]) {
+      c->tiles_now[r] = q[4];
+      if (std::find(c->cur_sel.begin(), c->cur_sel.end(), r) != c->cur_sel.end())
+        c->ftable_stale = true;
+    }
   }
   std::vector<int2> tbl = make_table(c, sel);
+  std::vector<int2> ttbl = make_tile_table(c, sel);
   std::copy(tbl.begin(), tbl.end(), c->h_tbl2);
+  std::copy(ttbl.begin(), ttbl.end(), c->h_ttbl);
+  HIPCHK(hipMemcpyAsync(c->ttbl, c->h_ttbl, sizeof(int2) * ttbl.size(), hipMemcpyHostToDevice,
+                        c->stream));
   std::copy(sel.begin(), sel.end(), c->h_reps);
   std::copy(nc3.begin(), nc3.end(), c->h_nc3);
   HIPCHK(hipMemcpyAsync(c->tbl2, c->h_tbl2, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
@@ -335,6 +392,8 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = f
   RebuildArgs a{};
   a.blocks = c->tbl2;
   a.nblk = (int32_t)tbl.size();
+  a.tiles = c->ttbl;
+  a.ntile_blk = (int32_t)ttbl.size();
   a.reps = c->reps_d;
   a.nreps = (int32_t)sel.size();
   a.geom = c->d_geom;
@@ -344,6 +403,7 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = f
   a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
   a.id = c->id; a.inv = c->inv;
   a.nbc = c->nbc; a.nbl = c->nbl;
+  a.thdr = c->thdr; a.truns = c->truns;
   a.cell_count = c->ccount; a.cell_start = c->cstart; a.cell_of = c->cellof; a.order = c->order;
   a.tpos4 = c->tpos4; a.tvx = c->tvx; a.tvy = c->tvy; a.tvz = c->tvz; a.tid_ = c->tid;
   a.upart = c->upart;
@@ -376,22 +436,27 @@ aqs_status check_slot(aqs_ctx* c, int r) {
 
 aqs_status set_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
   std::vector<int2> tbl = make_table(c, sel);
-  std::vector<int2> ftbl = make_table(c, sel, c->tn.tpa);
+  std::vector<int2> ftbl = make_tile_table(c, sel);
   std::copy(tbl.begin(), tbl.end(), c->h_tbl);
   std::copy(ftbl.begin(), ftbl.end(), c->h_ftbl);
   HIPCHK(hipMemcpyAsync(c->tbl, c->h_tbl, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
                         c->stream));
   HIPCHK(hipMemcpyAsync(c->ftbl, c->h_ftbl, sizeof(int2) * ftbl.size(), hipMemcpyHostToDevice,
                         c->stream));
+  std::copy(sel.begin(), sel.end(), c->h_sel);
+  HIPCHK(hipMemcpyAsync(c->sel_d, c->h_sel, sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice,
+                        c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->cur_sel = sel;
   c->cur_nblk = (int32_t)tbl.size();
   c->cur_ntiles = (int32_t)ftbl.size();
+  c->ftable_stale = false;
   return AQS_OK;
 }
 
 void free_pinned(aqs_ctx* c) {
-  void* ps[] = {c->h_state, c->h_tbl, c->h_ftbl, c->h_tbl2, c->h_reps, c->h_nc3, c->h_over, c->h_dg};
+  void* ps[] = {c->h_state, c->h_tbl, c->h_ftbl, c->h_tbl2, c->h_ttbl, c->h_reps, c->h_sel,
+                c->h_nc3, c->h_over, c->h_dg};
   for (void* p : ps)
     if (p) (void)hipHostFree(p);
   c->h_state = nullptr;
@@ -489,7 +554,11 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->tbl = at<int2>(w, lo.o_tbl);
   c->tbl2 = at<int2>(w, lo.o_tbl2);
   c->ftbl = at<int2>(w, lo.o_ftbl);
+  c->ttbl = at<int2>(w, lo.o_ttbl);
+  c->thdr = at<TileHdr>(w, lo.o_thdr);
+  c->truns = at<TileRun>(w, lo.o_truns);
   c->reps_d = at<int32_t>(w, lo.o_reps);
+  c->sel_d = at<int32_t>(w, lo.o_sel);
   c->nc3_d = at<int32_t>(w, lo.o_nc3);
   c->overflow = at<int32_t>(w, lo.o_overflow);
   c->dg_d = at<double>(w, lo.o_dg);
@@ -500,13 +569,15 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->evals = at<unsigned long long>(w, lo.o_evals);
   c->xref4 = at<double4>(w, lo.o_xref4);
 
-  const size_t tcap = (size_t)lo.blocks * kMaxTPA + 16;
+  const size_t tcap = std::max((size_t)lo.blocks, (size_t)lo.tiles) + 16;
   if (hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_tbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_ftbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_tbl2, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_ttbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_reps, sizeof(int32_t) * n_rep, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_nc3, sizeof(int32_t) * 3 * n_rep, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_sel, sizeof(int32_t) * n_rep, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_nc3, sizeof(int32_t) * kGridInts * n_rep, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_over, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_dg, sizeof(double) * n_rep, hipHostMallocDefault) != hipSuccess) {
     free_pinned(c);
@@ -522,6 +593,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   }
   c->loaded.assign(n_rep, 0);
   c->dirty.assign(n_rep, 1);
+  c->tiles_now.assign(n_rep, 0);
   hipStream_t s = c->stream;
   if (hipMemsetAsync(c->ws, 0, lo.total, s) != hipSuccess ||
       hipMemcpyAsync(c->d_geom, lo.geom.data(), sizeof(Geom) * n_rep, hipMemcpyHostToDevice, s) !=
@@ -803,6 +875,10 @@ aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int
       // rebuilt slots resume FIRE on the device (no host round trip)
       st = rebuild(c, rb, true);
       if (st) return st;
+      if (c->ftable_stale) {  // a grid changed its tile count
+        st = set_table(c, sel);
+        if (st) return st;
+      }
     }
   }
   for (int i = 0; i < n_sel; ++i) {
@@ -872,7 +948,7 @@ aqs_status aqs_stress(aqs_ctx* c, int32_t rep, double* sigma, double* energy) {
   st = pull_state(c);
   if (st) return st;
   std::vector<int32_t> sel(1, rep);
-  st = rebuild(c, sel);
+  st = rebuild(c, sel, false, 1);  // global-index entries for the virial kernel
   if (st) return st;
   const Geom& g = c->lo.geom[rep];
   IterArgs a = iter_args(c);

@@ -11,13 +11,16 @@
 //   sort   sort each cell by atom id (gives a deterministic order)
 //   perm   gather positions, velocities, ids into scratch in the new order
 //   back   copy back; inverse permutation
-//   list   per atom, scan the 3^dim neighbouring cells and keep every image
-//          pair within rc_ab + skin; entry j | image code << 24
+//   list   per force tile (tiles.h): its segment and halo run table, then
+//          per atom the 3^dim neighbouring cells, keeping every image pair
+//          within rc_ab + skin; the entry names the neighbour's halo slot
+//          (or j | image code << 24)
 //   done   reset the validity bound of each rebuilt slot
 // Integer atomics only; the result does not depend on their order.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "tiles.h"
 
 namespace aqs {
 
@@ -43,13 +46,18 @@ __device__ __forceinline__ int cell_of_pos(const Geom& g, const int* nc, double 
   return (c3[2] * nc[1] + c3[1]) * nc[0] + c3[0];
 }
 
+// grid per slot: nc0, nc1, nc2, tile width, tiles, list mode
 __global__ void k_rb_grid(RebuildArgs a, const int32_t* nc3) {
   const int r = blockIdx.x;
   if (threadIdx.x == 0 && r < a.nreps) {
     State* st = a.state + a.reps[r];
-    st->nc[0] = nc3[3 * r + 0];
-    st->nc[1] = nc3[3 * r + 1];
-    st->nc[2] = nc3[3 * r + 2];
+    const int32_t* q = nc3 + kGridInts * r;
+    st->nc[0] = q[0];
+    st->nc[1] = q[1];
+    st->nc[2] = q[2];
+    st->tiles_x = q[3];
+    st->ntiles = q[4];
+    st->list_mode = q[5];
   }
 }
 
@@ -198,73 +206,120 @@ __global__ __launch_bounds__(kBlock) void k_rb_back(RebuildArgs a) {
   }
 }
 
+// Neighbour lists, one block per force tile (tiles.h): the tile's segment
+// and halo run table are computed here and stored for the force kernel, and
+// each entry names the neighbour's halo slot (or, for a tile whose halo does
+// not fit in LDS, its global index and image code).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
-  const int2 bt = a.blocks[blockIdx.x];
+  const int2 bt = a.tiles[blockIdx.x];
   if (bt.x < 0) return;
-  const Geom g = a.geom[bt.x];
   const State* st = a.state + bt.x;
-  const int li = bt.y * kBlock + threadIdx.x;
-  if (li >= g.n) return;
-  const int64_t gi = g.atom_off + li;
+  if (bt.y >= st->ntiles) return;
+  const Geom g = a.geom[bt.x];
   const double t = strain_of(st->k, g.dgamma) * g.L[1];
   const int nc[3] = {st->nc[0], st->nc[1], st->nc[2]};
-  const double4* P = a.pos4 + g.atom_off;
-  const double4 pi = P[li];
-  const int ti = (int)pi.w;
-  double rl2[2];
-  for (int b = 0; b < 2; ++b) {
-    const double rc = sqrt(a.pp[2 * ti + b].rc2) + a.skin;
-    rl2[b] = rc * rc;
-  }
-  int c3[3];
-  cell_of_pos<D>(g, nc, t, pi, c3);
-  uint32_t* L = a.nbl + g.nb_off + li;
   const int32_t* cs = a.cell_start + g.cell_off;
-  int cnt = 0;
-  bool over = false;
-  const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
-  for (int dz = zlo; dz <= zhi; ++dz) {
-    int cz = c3[2] + dz, iz = 0;
-    if (D == 3) {
-      if (cz < 0) { cz += nc[2]; iz = -1; }
-      else if (cz >= nc[2]) { cz -= nc[2]; iz = 1; }
+  const double4* P = a.pos4 + g.atom_off;
+  const int tid = threadIdx.x;
+  __shared__ TileRun runs[kRuns];
+  __shared__ int s_cx0, s_cx1, s_lds;
+  int a0, a1, cy, cz;
+  segment(nc, st->tiles_x, cs, bt.y, a0, a1, cy, cz);
+  if (tid == 0) {
+    int c3[3];
+    s_cx0 = 0;
+    s_cx1 = 0;
+    if (a1 > a0) {
+      cell_of_pos<D>(g, nc, t, P[a0], c3);
+      s_cx0 = c3[0];
+      cell_of_pos<D>(g, nc, t, P[a1 - 1], c3);
+      s_cx1 = c3[0];
     }
-    for (int dy = -1; dy <= 1; ++dy) {
-      int cy = c3[1] + dy, iy = 0;
-      if (cy < 0) { cy += nc[1]; iy = -1; }
-      else if (cy >= nc[1]) { cy -= nc[1]; iy = 1; }
-      for (int dx = -1; dx <= 1; ++dx) {
-        int cx = c3[0] + dx, ix = 0;
-        if (cx < 0) { cx += nc[0]; ix = -1; }
-        else if (cx >= nc[0]) { cx -= nc[0]; ix = 1; }
-        const int code = (ix + 1) + 3 * (iy + 1) + 9 * (iz + 1);
-        const double sx = (double)ix * g.L[0] + (double)iy * t;
-        const double sy = (double)iy * g.L[1];
-        const double sz = (double)iz * g.L[2];
-        const int c = (cz * nc[1] + cy) * nc[0] + cx;
-        const int jb = cs[c], je = cs[c + 1];
-        for (int j = jb; j < je; ++j) {
-          if (j == li && code == 13) continue;
-          const double4 pj = P[j];
-          const double ddx = (pj.x - pi.x) + sx;
-          const double ddy = (pj.y - pi.y) + sy;
-          const double ddz = (D == 3) ? (pj.z - pi.z) + sz : 0.0;
-          const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-          if (r2 < rl2[(int)pj.w]) {
-            if (cnt < a.max_nb)
-              L[(int64_t)cnt * g.npad] = (uint32_t)j | ((uint32_t)code << kCodeShift) |
-                                         ((uint32_t)pj.w << 29);
-            else
-              over = true;
-            ++cnt;
+  }
+  __syncthreads();
+  if (tid < kRuns) runs[tid] = make_run<D>(tid, s_cx0, s_cx1, cy, cz, nc, cs);
+  __syncthreads();
+  constexpr int CAP = (D == 3) ? kHaloCap3 : kHaloCap2;
+  const int64_t tix = g.tile_off + bt.y;
+  if (tid == 0) {
+    int off = 0, nr = 0;
+    for (int r = 0; r < kRuns; ++r) {
+      runs[r].off = off;
+      off += runs[r].count;
+      if (runs[r].count > 0) a.truns[tix * kRuns + nr++] = runs[r];
+    }
+    const bool lds = (st->list_mode == 0) && (off <= CAP);
+    s_lds = lds ? 1 : 0;
+    TileHdr h;
+    h.a0 = a0;
+    h.a1 = a1;
+    h.nruns = nr;
+    h.halo = lds ? off : -1;
+    a.thdr[tix] = h;
+  }
+  __syncthreads();
+  const bool lds = s_lds != 0;
+  for (int li = a0 + tid; li < a1; li += kBlock) {
+    const int64_t gi = g.atom_off + li;
+    const double4 pi = P[li];
+    const int tyi = (int)pi.w;
+    double rl2[2];
+    for (int b = 0; b < 2; ++b) {
+      const double rc = sqrt(a.pp[2 * tyi + b].rc2) + a.skin;
+      rl2[b] = rc * rc;
+    }
+    int c3[3];
+    cell_of_pos<D>(g, nc, t, pi, c3);
+    uint32_t* L = a.nbl + g.nb_off + li;
+    int cnt = 0;
+    bool over = false;
+    const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+      int cz2 = c3[2] + dz, iz = 0;
+      if (D == 3) {
+        if (cz2 < 0) { cz2 += nc[2]; iz = -1; }
+        else if (cz2 >= nc[2]) { cz2 -= nc[2]; iz = 1; }
+      }
+      for (int dy = -1; dy <= 1; ++dy) {
+        int cy2 = c3[1] + dy, iy = 0;
+        if (cy2 < 0) { cy2 += nc[1]; iy = -1; }
+        else if (cy2 >= nc[1]) { cy2 -= nc[1]; iy = 1; }
+        for (int dx = -1; dx <= 1; ++dx) {
+          int cx = c3[0] + dx, ix = 0;
+          if (cx < 0) { cx += nc[0]; ix = -1; }
+          else if (cx >= nc[0]) { cx -= nc[0]; ix = 1; }
+          const int code = (ix + 1) + 3 * (iy + 1) + 9 * (iz + 1);
+          const TileRun& rr = runs[run_of(c3[0], dx, dy, dz, nc[0])];
+          const double sx = (double)ix * g.L[0] + (double)iy * t;
+          const double sy = (double)iy * g.L[1];
+          const double sz = (double)iz * g.L[2];
+          const int c = (cz2 * nc[1] + cy2) * nc[0] + cx;
+          const int jb = cs[c], je = cs[c + 1];
+          for (int j = jb; j < je; ++j) {
+            if (j == li && code == 13) continue;
+            const double4 pj = P[j];
+            const double ddx = (pj.x - pi.x) + sx;
+            const double ddy = (pj.y - pi.y) + sy;
+            const double ddz = (D == 3) ? (pj.z - pi.z) + sz : 0.0;
+            const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            if (r2 < rl2[(int)pj.w]) {
+              const uint32_t tb = ((uint32_t)pj.w << 29);
+              const uint32_t ent = lds ? ((uint32_t)(rr.off + (j - rr.src)) | tb)
+                                       : ((uint32_t)j | ((uint32_t)code << kCodeShift) | tb);
+              if (cnt < a.max_nb)
+                L[(int64_t)cnt * g.npad] = ent;
+              else
+                over = true;
+              ++cnt;
+            }
           }
         }
       }
     }
+    a.nbc[gi] = over ? a.max_nb : cnt;
+    if (over) atomicMax(a.overflow, cnt);
   }
-  a.nbc[gi] = over ? a.max_nb : cnt;
-  if (over) atomicMax(a.overflow, cnt);
 }
 
 __global__ void k_rb_done(RebuildArgs a) {
@@ -298,11 +353,11 @@ void launch_rebuild(const RebuildArgs& a, int32_t max_cells_per_slot, hipStream_
   if (a.dim == 3) {
     hipLaunchKernelGGL(k_rb_perm<3>, dim3(a.nblk), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_rb_back<3>, dim3(a.nblk), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_rb_list<3>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rb_list<3>, dim3(a.ntile_blk), dim3(kBlock), 0, s, a);
   } else {
     hipLaunchKernelGGL(k_rb_perm<2>, dim3(a.nblk), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_rb_back<2>, dim3(a.nblk), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_rb_list<2>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rb_list<2>, dim3(a.ntile_blk), dim3(kBlock), 0, s, a);
   }
   hipLaunchKernelGGL(k_rb_done, dim3(a.nreps), dim3(256), 0, s, a);
 }

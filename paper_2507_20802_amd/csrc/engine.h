@@ -24,6 +24,8 @@ constexpr int kBlock = 256;           // atoms per workgroup (4 wavefronts)
 constexpr int kWave = 64;
 constexpr int kForceParts = 8;        // doubles per tile partial of the force kernel
 constexpr int kMaxTPA = 8;            // threads per atom of the force kernel: 1, 2, 4 or 8
+constexpr int kHaloCap3 = 1920;       // LDS halo capacity (atoms) of a force tile, 3D
+constexpr int kHaloCap2 = 1024;       // ... 2D
 constexpr uint32_t kIdxMask = 0x00FFFFFFu;
 constexpr int kCodeShift = 24;
 
@@ -53,6 +55,8 @@ struct Geom {
   int32_t nblocks;    // npad / kBlock
   int32_t cell_off;   // first cell of this slot in the cell arrays
   int32_t cell_cap;   // cells reserved
+  int32_t tile_off;   // first force tile of this slot in the tile arrays
+  int32_t tile_cap;   // force tiles reserved
   double L[3];        // unstrained box edges
   double dgamma;      // fine strain increment
 };
@@ -80,6 +84,9 @@ struct State {
   int32_t start_used; // start of the minimisation in progress
   int32_t learn_ok;   // learned displacement passed its pre-checks
   int32_t pending;    // outcome recorded after the PH_ENERGY evaluation
+  int32_t tiles_x;    // force tiles (row segments) per cell row
+  int32_t ntiles;     // force tiles of the current grid
+  int32_t list_mode;  // 0: tiles index their LDS halo; 1: global indices only
   int32_t pad_;
 };
 
@@ -103,6 +110,8 @@ struct StepRecord {
 struct IterArgs {
   const int2* blocks;     // update launch table: (slot, 256-atom block) or slot -1
   const int2* ftiles;     // force launch table: (slot, force tile) or slot -1
+  const int32_t* sel;     // slots of the running selection (control kernel)
+  int32_t nsel;
   int32_t tpa;            // threads per atom of the force kernel
   const Geom* geom;
   State* state;
@@ -112,7 +121,10 @@ struct IterArgs {
   int32_t* id; int32_t* inv;
   const int32_t* nbc;
   const uint32_t* nbl;
-  double* fpart;          // kForceParts per force tile (kMaxTPA tiles per 256-atom block)
+  const int32_t* cell_start;  // per slot: cell_off + c, cells of the current grid
+  const void* thdr;           // TileHdr per force tile (tile_off + t)
+  const void* truns;          // TileRun x kRuns per force tile
+  double* fpart;          // kForceParts per force tile (tile_off + tile)
   double* upart;          // 1 per global block (max displacement of the update)
   uint32_t* counter;      // per slot, last-block detection
   unsigned long long* evals;  // atoms evaluated by force launches (statistics)

@@ -2,13 +2,18 @@
 #pragma once
 
 #include "engine.h"
+#include "tiles.h"
 
 namespace aqs {
 
 // Rebuild of cell lists and neighbour lists for a set of slots.
+constexpr int kGridInts = 6;  // per slot: nc0, nc1, nc2, tiles per row, tiles, list mode
+
 struct RebuildArgs {
   const int2* blocks;   // launch table over the atoms of the slots to rebuild
   int32_t nblk;         // entries of the launch table
+  const int2* tiles;    // launch table over the force tiles of those slots
+  int32_t ntile_blk;
   const int32_t* reps;  // slots to rebuild
   int32_t nreps;
   const Geom* geom;
@@ -19,6 +24,8 @@ struct RebuildArgs {
   int32_t* id; int32_t* inv;
   int32_t* nbc;
   uint32_t* nbl;
+  TileHdr* thdr;        // per force tile (tile_off + t)
+  TileRun* truns;       // kRuns per force tile
   int32_t* cell_count;  // per cell (cell_off + c)
   int32_t* cell_start;  // per cell + 1 per slot (cell_off + slot_index + c)
   int32_t* cell_of;     // per atom

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "tiles.h"
 
 namespace aqs {
 
@@ -31,11 +32,11 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Block-wide reduction of NV values; op[c] = 0 sum, 1 max.  Result valid in
-// thread 0.  Fixed order: butterfly inside each wavefront, then waves 0..3
-// combined as (w0 + w1) + (w2 + w3).
-template <int NV>
-__device__ __forceinline__ void block_reduce(double* v, const int* op, double (*lds)[kBlock / kWave]) {
+// Block-wide reduction of NV values over NW wavefronts; op[c] = 0 sum,
+// 1 max.  Result valid in thread 0.  Fixed order: butterfly inside each
+// wavefront, then a pairwise tree over the wavefronts in index order.
+template <int NV, int NW = kBlock / kWave>
+__device__ __forceinline__ void block_reduce(double* v, const int* op, double (*lds)[NW]) {
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
 #pragma unroll
@@ -48,8 +49,14 @@ __device__ __forceinline__ void block_reduce(double* v, const int* op, double (*
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
-      if (op[c]) v[c] = fmax(fmax(lds[c][0], lds[c][1]), fmax(lds[c][2], lds[c][3]));
-      else v[c] = (lds[c][0] + lds[c][1]) + (lds[c][2] + lds[c][3]);
+      double t[NW];
+#pragma unroll
+      for (int i = 0; i < NW; ++i) t[i] = lds[c][i];
+#pragma unroll
+      for (int h = 1; h < NW; h <<= 1)
+#pragma unroll
+        for (int i = 0; i + h < NW; i += 2 * h) t[i] = op[c] ? fmax(t[i], t[i + h]) : t[i] + t[i + h];
+      v[c] = t[0];
     }
   }
   __syncthreads();
@@ -94,6 +101,40 @@ __device__ __forceinline__ double recip_nr(double x) {
   return fma(r, e, r);
 }
 
+// One pair term, branch-free: invalid or out-of-range pairs contribute
+// exact zeros (their 1/r^2 is taken of 1.0 and the result masked), so the
+// kChunk pairs of a chunk interleave without divergence.
+template <int D, bool WE>
+__device__ __forceinline__ void pair_term(bool live, double dx, double dy, double dz,
+                                          const PairParams& q, double& fx, double& fy, double& fz,
+                                          double& e, double& w) {
+  const double r2 = (D == 3) ? dx * dx + dy * dy + dz * dz : dx * dx + dy * dy;
+  const bool in = live && (r2 < q.rc2);
+  const double inv = recip_nr(in ? r2 : 1.0);
+  const double s2 = q.sig2 * inv;
+  const double s6 = s2 * s2 * s2;
+  const double s12 = s6 * s6;
+  const double g = in ? q.eps4 * (6.0 * s6 - 12.0 * s12) * inv : 0.0;  // U'(r) / r
+  fx += g * dx;
+  fy += g * dy;
+  if (D == 3) fz += g * dz;
+  if (WE) {
+    e += in ? q.eps4 * (s12 - s6) - q.ucut : 0.0;
+    w += g * dx * dy;
+  }
+}
+
+// Entries sub, sub + TPA, ... of a list (lane sub of TPA lanes per atom):
+// loads are unconditional (indices clamped into the list), entries past the
+// count become `fill`.
+template <int TPA>
+__device__ __forceinline__ uint32_t list_entry(const uint32_t* L, int64_t st, int k, int my,
+                                               uint32_t fill) {
+  const int kk = min(k, max(my - 1, 0));
+  const uint32_t raw = L[(int64_t)kk * st];
+  return k < my ? raw : fill;
+}
+
 template <int D, bool WE, int TPA>
 __device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint32_t* __restrict__ L,
                                            int64_t stride, int cnt, uint32_t self_ent,
@@ -107,17 +148,14 @@ __device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint3
   const int64_t st = (int64_t)TPA * stride;
   uint32_t cur[kChunk];
 #pragma unroll
-  for (int u = 0; u < kChunk; ++u) cur[u] = (u < my) ? L[(int64_t)u * st] : self_ent;
+  for (int u = 0; u < kChunk; ++u) cur[u] = list_entry<TPA>(L, st, u, my, self_ent);
   for (int k0 = 0; k0 < my; k0 += kChunk) {
     double4 pj[kChunk];
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) pj[u] = P[cur[u] & kIdxMask];
     uint32_t nxt[kChunk];
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u) {
-      const int k = k0 + kChunk + u;
-      nxt[u] = (k < my) ? L[(int64_t)k * st] : self_ent;
-    }
+    for (int u = 0; u < kChunk; ++u) nxt[u] = list_entry<TPA>(L, st, k0 + kChunk + u, my, self_ent);
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) {
       const uint32_t ent = cur[u];
@@ -125,28 +163,58 @@ __device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint3
       const double dx = (pj[u].x - pi.x) + sh[code][0];
       const double dy = (pj[u].y - pi.y) + sh[code][1];
       const double dz = (D == 3) ? (pj[u].z - pi.z) + sh[code][2] : 0.0;
-      const double r2 = (D == 3) ? dx * dx + dy * dy + dz * dz : dx * dx + dy * dy;
       const PairParams q = pp[2 * ti + ((ent & kTypeBit) ? 1 : 0)];
-      if (k0 + u < my && r2 < q.rc2) {
-        const double inv = recip_nr(r2);
-        const double s2 = q.sig2 * inv;
-        const double s6 = s2 * s2 * s2;
-        const double s12 = s6 * s6;
-        const double g = q.eps4 * (6.0 * s6 - 12.0 * s12) * inv;  // U'(r) / r
-        fx += g * dx;
-        fy += g * dy;
-        if (D == 3) fz += g * dz;
-        if (WE) {
-          e += q.eps4 * (s12 - s6) - q.ucut;
-          w += g * dx * dy;
-        }
-      }
+      pair_term<D, WE>(k0 + u < my, dx, dy, dz, q, fx, fy, fz, e, w);
     }
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) cur[u] = nxt[u];
   }
   // combine the TPA lanes of the atom (fixed butterfly: every lane of the
   // group ends with the same bits)
+#pragma unroll
+  for (int off = 1; off < TPA; off <<= 1) {
+    fx += __shfl_xor(fx, off, kWave);
+    fy += __shfl_xor(fy, off, kWave);
+    if (D == 3) fz += __shfl_xor(fz, off, kWave);
+    if (WE) {
+      e += __shfl_xor(e, off, kWave);
+      w += __shfl_xor(w, off, kWave);
+    }
+  }
+}
+
+// Same pair loop with the neighbour positions in the tile's LDS halo (image
+// shifts already applied when staged): entry = halo index | type bit.
+template <int D, bool WE, int TPA>
+__device__ __forceinline__ void atom_pairs_lds(const double4 pi, int ti, const uint32_t* __restrict__ L,
+                                               int64_t stride, int cnt, const double* hx,
+                                               const double* hy, const double* hz,
+                                               const PairParams* pp, double& fx, double& fy,
+                                               double& fz, double& e, double& w) {
+  const int sub = (int)(threadIdx.x % TPA);
+  const int my = cnt > sub ? (cnt - sub + TPA - 1) / TPA : 0;
+  L += (int64_t)sub * stride;
+  const int64_t st = (int64_t)TPA * stride;
+  uint32_t cur[kChunk];
+#pragma unroll
+  for (int u = 0; u < kChunk; ++u) cur[u] = list_entry<TPA>(L, st, u, my, 0u);
+  for (int k0 = 0; k0 < my; k0 += kChunk) {
+    uint32_t nxt[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) nxt[u] = list_entry<TPA>(L, st, k0 + kChunk + u, my, 0u);
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const uint32_t ent = cur[u];
+      const int h = (int)(ent & kIdxMask);
+      const double dx = hx[h] - pi.x;
+      const double dy = hy[h] - pi.y;
+      const double dz = (D == 3) ? hz[h] - pi.z : 0.0;
+      const PairParams q = pp[2 * ti + ((ent & kTypeBit) ? 1 : 0)];
+      pair_term<D, WE>(k0 + u < my, dx, dy, dz, q, fx, fy, fz, e, w);
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) cur[u] = nxt[u];
+  }
 #pragma unroll
   for (int off = 1; off < TPA; off <<= 1) {
     fx += __shfl_xor(fx, off, kWave);
@@ -302,100 +370,177 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
 // the per-block partials (E, |F|^2, F.v, |v|^2, max |F_i|^2, W_xy, non-finite)
 // and, in the last block of each slot, the FIRE control.
 
-template <int D, bool WE, int TPA>
-__device__ __forceinline__ void force_block(const IterArgs& a, const Geom& g, int tile,
-                                            double (*sh)[4], const PairParams* spp, double* part) {
-  const int li = tile * (kBlock / TPA) + (int)(threadIdx.x / TPA);
-  if (li >= g.n) return;
+// Force of one atom li of the tile (TPA lanes), accumulated into the
+// thread's partials (E, |F|^2, F.v, |v|^2, max |F_i|^2, W_xy, non-finite).
+template <int D, bool WE, int TPA, bool LDS>
+__device__ __forceinline__ void force_atom(const IterArgs& a, const Geom& g, int li,
+                                           const double (*sh)[4], const PairParams* spp,
+                                           const double* hx, const double* hy, const double* hz,
+                                           double* part) {
   const int64_t gi = g.atom_off + li;
   const double4 pi = a.pos4[gi];
   double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
-  const uint32_t self_ent = (uint32_t)li | (13u << kCodeShift);
-  atom_pairs<D, WE, TPA>(pi, (int)pi.w, a.nbl + g.nb_off + li, g.npad, a.nbc[gi], self_ent,
-                         a.pos4 + g.atom_off, sh, spp, fx, fy, fz, e, w);
+  if (LDS)
+    atom_pairs_lds<D, WE, TPA>(pi, (int)pi.w, a.nbl + g.nb_off + li, g.npad, a.nbc[gi], hx, hy, hz,
+                               spp, fx, fy, fz, e, w);
+  else
+    atom_pairs<D, WE, TPA>(pi, (int)pi.w, a.nbl + g.nb_off + li, g.npad, a.nbc[gi],
+                           (uint32_t)li | (13u << kCodeShift), a.pos4 + g.atom_off, sh, spp, fx, fy,
+                           fz, e, w);
   if (threadIdx.x % TPA != 0) return;
   a.fx[gi] = fx;
   a.fy[gi] = fy;
   if (D == 3) a.fz[gi] = fz;
   const double vx = a.vx[gi], vy = a.vy[gi], vz = (D == 3) ? a.vz[gi] : 0.0;
   const double ff = fx * fx + fy * fy + fz * fz;
-  part[0] = 0.5 * e;
-  part[1] = ff;
-  part[2] = fx * vx + fy * vy + fz * vz;
-  part[3] = vx * vx + vy * vy + vz * vz;
-  part[4] = ff;
-  part[5] = 0.5 * w;
-  part[6] = (isfinite(e) && isfinite(ff) && isfinite(pi.x + pi.y + pi.z)) ? 0.0 : 1.0;
+  part[0] += 0.5 * e;
+  part[1] += ff;
+  part[2] += fx * vx + fy * vy + fz * vz;
+  part[3] += vx * vx + vy * vy + vz * vz;
+  part[4] = fmax(part[4], ff);
+  part[5] += 0.5 * w;
+  if (!(isfinite(e) && isfinite(ff) && isfinite(pi.x + pi.y + pi.z))) part[6] = 1.0;
 }
 
-// Force kernel: TPA threads per atom, kBlock / TPA atoms of one slot per
-// block ("force tile").  Writes F, the per-tile partials (E, |F|^2, F.v,
-// |v|^2, max |F_i|^2, W_xy, non-finite) and, in the last tile of each slot,
-// combines them and runs the FIRE control.
+template <int D, bool WE, int TPA, bool LDS>
+__device__ __forceinline__ void force_tile(const IterArgs& a, const Geom& g, int a0, int a1,
+                                           const double (*sh)[4], const PairParams* spp,
+                                           const double* hx, const double* hy, const double* hz,
+                                           double* part) {
+  constexpr int per = kBlock / TPA;
+  for (int b = a0; b < a1; b += per) {
+    const int li = b + (int)(threadIdx.x / TPA);
+    if (li < a1) force_atom<D, WE, TPA, LDS>(a, g, li, sh, spp, hx, hy, hz, part);
+  }
+}
+
+// Force kernel: one block per force tile (a segment of a cell row, tiles.h).
+// The block reads the tile's header and halo run table, stages the halo into
+// LDS (image shifts applied), then TPA lanes per atom walk each neighbour
+// list.  Writes F and the tile partials (E, |F|^2, F.v, |v|^2, max |F_i|^2,
+// W_xy, non-finite); k_control combines them.
 template <int D, int TPA>
 __global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
   const int2 bt = a.ftiles[blockIdx.x];
   const int rep = bt.x;
   if (rep < 0) return;
-  const int phase = a.state[rep].phase;
+  const State* stp = a.state + rep;
+  const int phase = stp->phase;
+  const bool we = (phase == PH_EVAL || phase == PH_ENERGY);
+  const bool compute = we || phase == PH_FIRE || phase == PH_ADVANCE;
+  if (!compute) return;
+  const int ntiles = stp->ntiles;
+  if (bt.y >= ntiles) return;
+  const Geom g = a.geom[rep];
+  const int tid = threadIdx.x;
+  constexpr int CAP = (D == 3) ? kHaloCap3 : kHaloCap2;
+
+  __shared__ double hx[CAP];
+  __shared__ double hy[CAP];
+  __shared__ double hz[D == 3 ? CAP : 1];
+  __shared__ double sh[32][4];
+  __shared__ PairParams spp[4];
+  __shared__ TileRun runs[kRuns];
+  __shared__ double red[kForceParts][kBlock / kWave];
+  constexpr int ops[kForceParts] = {0, 0, 0, 0, 1, 0, 1, 1};
+
+  double part[kForceParts] = {0, 0, 0, 0, 0, 0, 0, 0};
+  {
+    const int64_t tix = g.tile_off + bt.y;
+    const TileHdr hdr = reinterpret_cast<const TileHdr*>(a.thdr)[tix];
+    const double t = slot_tilt(g, stp);
+    if (tid < hdr.nruns) runs[tid] = reinterpret_cast<const TileRun*>(a.truns)[tix * kRuns + tid];
+    if (tid >= 32 && tid < 32 + 27) code_shift(tid - 32, g.L[0], g.L[1], g.L[2], t, sh[tid - 32]);
+    if (tid >= 64 && tid < 68) spp[tid - 64] = a.pp[tid - 64];
+    __syncthreads();
+    if (hdr.halo >= 0) {
+      // stage the halo: thread tid takes halo slots tid, tid + kBlock, ...;
+      // the run of a slot is found by binary search over the run offsets,
+      // then all of the thread's loads are issued before its LDS stores
+      const double4* P = a.pos4 + g.atom_off;
+      constexpr int SU = (CAP + kBlock - 1) / kBlock;
+      constexpr int SB = SU;  // slots per pass (loads in flight per thread)
+      for (int u0 = 0; u0 < SU; u0 += SB) {
+      double4 p[SB];
+      int rix[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int h = tid + (u0 + u) * kBlock;
+        rix[u] = -1;
+        if (h < hdr.halo) {
+          int lo = 0, hi = hdr.nruns - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (runs[mid].off <= h) lo = mid; else hi = mid - 1;
+          }
+          rix[u] = lo;
+          p[u] = P[runs[lo].src + (h - runs[lo].off)];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        if (rix[u] >= 0) {
+          const int h = tid + (u0 + u) * kBlock;
+          const int code = runs[rix[u]].code;
+          hx[h] = p[u].x + sh[code][0];
+          hy[h] = p[u].y + sh[code][1];
+          if (D == 3) hz[h] = p[u].z + sh[code][2];
+        }
+      }
+      }
+      __syncthreads();
+      if (we)
+        force_tile<D, true, TPA, true>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, part);
+      else
+        force_tile<D, false, TPA, true>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, part);
+    } else {
+      if (we)
+        force_tile<D, true, TPA, false>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, part);
+      else
+        force_tile<D, false, TPA, false>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, part);
+    }
+    block_reduce<kForceParts>(part, ops, red);
+    if (tid == 0) {
+      double* dst = a.fpart + tix * kForceParts;
+#pragma unroll
+      for (int c = 0; c < 7; ++c) dst[c] = part[c];
+    }
+  }
+}
+
+// Per-slot reduction and FIRE control, one block per slot of the running
+// selection, launched after the force kernel (the kernel boundary makes the
+// tile partials visible; no device-scope fences inside the force kernel).
+// The tile partials are combined in tile order, then a fixed tree.
+__global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
+  const int rep = a.sel[blockIdx.x];
+  const State* stp = a.state + rep;
+  const int phase = stp->phase;
   const bool we = (phase == PH_EVAL || phase == PH_ENERGY);
   const bool compute = we || phase == PH_FIRE || phase == PH_ADVANCE;
   const bool counted = compute || phase == PH_FINISH || phase == PH_STOP;
   if (!counted) return;
   const Geom g = a.geom[rep];
   const int tid = threadIdx.x;
-  const int ntiles = g.nblocks * TPA;
-
-  __shared__ double sh[32][4];
-  __shared__ PairParams spp[4];
+  const int ntiles = stp->ntiles;
   __shared__ double red[kForceParts][kBlock / kWave];
-  __shared__ int s_last;
   constexpr int ops[kForceParts] = {0, 0, 0, 0, 1, 0, 1, 1};
-
-  double part[kForceParts] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (compute) {
-    const double t = slot_tilt(g, a.state + rep);
-    if (tid < 27) code_shift(tid, g.L[0], g.L[1], g.L[2], t, sh[tid]);
-    if (tid < 4) spp[tid] = a.pp[tid];
-    __syncthreads();
-    if (we)
-      force_block<D, true, TPA>(a, g, bt.y, sh, spp, part);
-    else
-      force_block<D, false, TPA>(a, g, bt.y, sh, spp, part);
-    block_reduce<kForceParts>(part, ops, red);
-    if (tid == 0) {
-      double* dst = a.fpart + ((int64_t)g.block0 * kMaxTPA + bt.y) * kForceParts;
-#pragma unroll
-      for (int c = 0; c < 7; ++c) dst[c] = part[c];
-    }
-  }
-  // the last tile of the slot runs the control
-  if (tid == 0) {
-    __threadfence();
-    const unsigned old = atomicAdd(a.counter + rep, 1u);
-    s_last = (old == (unsigned)(ntiles - 1)) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
   double r[kForceParts] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (compute) {
     for (int b = tid; b < ntiles; b += kBlock) {
-      const double* src = a.fpart + ((int64_t)g.block0 * kMaxTPA + b) * kForceParts;
-      r[0] += __builtin_nontemporal_load(src + 0);
-      r[1] += __builtin_nontemporal_load(src + 1);
-      r[2] += __builtin_nontemporal_load(src + 2);
-      r[3] += __builtin_nontemporal_load(src + 3);
-      r[4] = fmax(r[4], __builtin_nontemporal_load(src + 4));
-      r[5] += __builtin_nontemporal_load(src + 5);
-      r[6] = fmax(r[6], __builtin_nontemporal_load(src + 6));
+      const double* src = a.fpart + ((int64_t)g.tile_off + b) * kForceParts;
+      r[0] += src[0];
+      r[1] += src[1];
+      r[2] += src[2];
+      r[3] += src[3];
+      r[4] = fmax(r[4], src[4]);
+      r[5] += src[5];
+      r[6] = fmax(r[6], src[6]);
     }
-    for (int b = tid; b < g.nblocks; b += kBlock)
-      r[7] = fmax(r[7], __builtin_nontemporal_load(a.upart + g.block0 + b));
+    for (int b = tid; b < g.nblocks; b += kBlock) r[7] = fmax(r[7], a.upart[g.block0 + b]);
   }
   block_reduce<kForceParts>(r, ops, red);
   if (tid == 0) {
-    a.counter[rep] = 0u;
     if (compute) atomicAdd(a.evals, (unsigned long long)g.n);
     control(a, rep, g, r, phase);
   }
@@ -500,6 +645,7 @@ void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s)
     launch_force_d<3>(a, ntiles, a.tpa, s);
   else
     launch_force_d<2>(a, ntiles, a.tpa, s);
+  hipLaunchKernelGGL(k_control, dim3(a.nsel), dim3(kBlock), 0, s, a);
 }
 
 void launch_update(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {

@@ -1,0 +1,98 @@
+// tiles.h -- force tiles and their LDS halos.
+//
+// A force tile is a segment of one cell row (fixed y, z): the atoms of a row
+// (one contiguous range of the cell-sorted order) are cut into tiles_per_row
+// segments of nearly equal atom counts (about kTileAtoms each).  Its halo is
+// every (cell, periodic image) pair within one cell of the segment's cells
+// [cx0, cx1]: for each of the 3^(dim-1) neighbouring rows (dy, dz) the cells
+// x = cx0-1 .. cx1+1, as up to three runs -- the cells inside the box ("M")
+// and, when the segment touches an x face, the wrapped cell on the other side
+// ("L", image -1; "R", image +1).  Each run is a contiguous atom range.
+//
+// The neighbour-list builder writes, per tile, a header and its run table
+// (TileHdr, TileRun).  The force kernel loads them with one read, stages the
+// halo positions (image shift H n added) into LDS, and the neighbour entries
+// of the tile's atoms hold halo indices.  A tile whose halo exceeds the LDS
+// capacity (rare: dense fluctuations) keeps global indices and image codes
+// and its force loop gathers from global memory.
+#pragma once
+
+#include "engine.h"
+
+namespace aqs {
+
+constexpr int kRuns = 27;  // (dz, dy, part): 3 x 3 x 3 (2D uses dz = 0 only)
+
+struct TileHdr {
+  int32_t a0, a1;   // atom range [a0, a1) of the tile
+  int32_t nruns;    // runs in the table (non-empty ones, in halo order)
+  int32_t halo;     // halo atoms; -1: halo too large, entries are global
+};
+
+struct TileRun {
+  int32_t src;      // first atom of the run (slot-local)
+  int32_t count;
+  int32_t off;      // halo offset of the run
+  int32_t code;     // image code (ix+1) + 3 (iy+1) + 9 (iz+1)
+};
+
+// Run r = ((dz+1) * 3 + (dy+1)) * 3 + part, part 0 = L, 1 = M, 2 = R, of a
+// segment with cells [cx0, cx1] in row (cy, cz).  count = 0 if absent.
+template <int D>
+__device__ __forceinline__ TileRun make_run(int r, int cx0, int cx1, int cy, int cz, const int* nc,
+                                            const int32_t* cs) {
+  TileRun run;
+  run.src = 0;
+  run.count = 0;
+  run.off = 0;
+  run.code = 13;
+  const int part = r % 3, dy = (r / 3) % 3 - 1, dz = r / 9 - 1;
+  if (D == 2 && dz != 0) return run;
+  int ry = cy + dy, iy = 0;
+  if (ry < 0) { ry += nc[1]; iy = -1; }
+  else if (ry >= nc[1]) { ry -= nc[1]; iy = 1; }
+  int rz = cz + dz, iz = 0;
+  if (D == 3) {
+    if (rz < 0) { rz += nc[2]; iz = -1; }
+    else if (rz >= nc[2]) { rz -= nc[2]; iz = 1; }
+  }
+  const int c0 = (rz * nc[1] + ry) * nc[0];
+  int xlo, xhi, ix = 0;
+  if (part == 1) {
+    xlo = max(0, cx0 - 1);
+    xhi = min(nc[0] - 1, cx1 + 1);
+  } else if (part == 0) {
+    if (cx0 != 0) return run;
+    xlo = xhi = nc[0] - 1;
+    ix = -1;
+  } else {
+    if (cx1 != nc[0] - 1) return run;
+    xlo = xhi = 0;
+    ix = 1;
+  }
+  run.src = cs[c0 + xlo];
+  run.count = cs[c0 + xhi + 1] - run.src;
+  run.code = (ix + 1) + 3 * (iy + 1) + 9 * (iz + 1);
+  return run;
+}
+
+// Run of the neighbour cell (cx + dx, row + dy, dz) of a segment cell cx.
+__device__ __forceinline__ int run_of(int cx, int dx, int dy, int dz, int nc0) {
+  const int x = cx + dx;
+  const int part = x < 0 ? 0 : (x >= nc0 ? 2 : 1);
+  return ((dz + 1) * 3 + (dy + 1)) * 3 + part;
+}
+
+// Atom range of segment s of row `row` (rows cut into m segments).
+__device__ __forceinline__ void segment(const int* nc, int m, const int32_t* cs, int t, int& a0,
+                                        int& a1, int& cy, int& cz) {
+  const int row = t / m, s = t % m;
+  cy = row % nc[1];
+  cz = row / nc[1];
+  const int c0 = (cz * nc[1] + cy) * nc[0];
+  const int r0 = cs[c0], len = cs[c0 + nc[0]] - r0;
+  a0 = r0 + (int)(((int64_t)s * len) / m);
+  a1 = r0 + (int)(((int64_t)(s + 1) * len) / m);
+}
+
+}  // namespace aqs
