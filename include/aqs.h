@@ -93,7 +93,7 @@ typedef struct {
   int32_t block_iters;      /* FIRE iterations launched between host polls; 0 = 32 */
   int32_t use_graph;        /* 1: replay each block of iterations as a hipGraph */
   int32_t max_chain_steps;  /* largest n_steps accepted by aqs_minimize_batch; 0 = 1024 */
-  int32_t threads_per_atom; /* force kernel: 1, 2, 4 or 8 lanes per atom; 0 = 2 (2D) / 4 (3D) */
+  int32_t threads_per_atom; /* force kernel: 1, 2, 4 or 8 lanes per atom; 0 = 2 */
   int32_t pad_;
 } aqs_tuning;
 

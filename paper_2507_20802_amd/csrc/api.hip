@@ -58,7 +58,7 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   r.use_graph = t ? t->use_graph : 0;
   r.log_cap = ((t && t->max_chain_steps > 0) ? t->max_chain_steps : 1024) + 1;
   const int tp = t ? t->threads_per_atom : 0;
-  r.tpa = (tp == 1 || tp == 2 || tp == 4 || tp == 8) ? tp : (pot->dim == 3 ? 4 : 2);
+  r.tpa = (tp == 1 || tp == 2 || tp == 4 || tp == 8) ? tp : 2;
   return r;
 }
 

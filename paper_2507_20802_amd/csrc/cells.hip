@@ -140,25 +140,55 @@ __global__ __launch_bounds__(kBlock) void k_rb_scatter(RebuildArgs a) {
   a.order[g.atom_off + pos] = li;
 }
 
-__global__ void k_rb_sort(RebuildArgs a) {
+// Sort each cell by atom id: one wavefront per cell (4 cells per block).
+// Each atom's new place is its rank among the cell's ids (ids are distinct),
+// counted against a copy of the cell in LDS.  Cells larger than kSortCap
+// (only possible for very dense random starts) fall back to an insertion
+// sort by one lane.
+constexpr int kSortCap = 192;
+
+__global__ __launch_bounds__(256) void k_rb_sort(RebuildArgs a) {
   const int rep = a.reps[blockIdx.y];
   const Geom g = a.geom[rep];
   const State* st = a.state + rep;
   const int ncell = st->nc[0] * st->nc[1] * st->nc[2];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const int b = a.cell_start[g.cell_off + c], e = a.cell_start[g.cell_off + c + 1];
+  const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int c = blockIdx.x * 4 + wv;
+  __shared__ int keys[4][kSortCap];
+  __shared__ int vals[4][kSortCap];
+  int b = 0, n = 0;
   int32_t* o = a.order + g.atom_off;
   const int32_t* id = a.id + g.atom_off;
-  for (int i = b + 1; i < e; ++i) {  // insertion sort by atom id
-    const int v = o[i];
-    const int key = id[v];
-    int j = i - 1;
-    while (j >= b && id[o[j]] > key) {
-      o[j + 1] = o[j];
-      --j;
+  if (c < ncell) {
+    b = a.cell_start[g.cell_off + c];
+    n = a.cell_start[g.cell_off + c + 1] - b;
+  }
+  const bool fits = n <= kSortCap;
+  if (fits)
+    for (int k = lane; k < n; k += kWave) {
+      const int v = o[b + k];
+      vals[wv][k] = v;
+      keys[wv][k] = id[v];
     }
-    o[j + 1] = v;
+  __syncthreads();
+  if (fits) {
+    for (int k = lane; k < n; k += kWave) {
+      const int key = keys[wv][k];
+      int r = 0;
+      for (int q = 0; q < n; ++q) r += (keys[wv][q] < key) ? 1 : 0;
+      o[b + r] = vals[wv][k];
+    }
+  } else if (lane == 0) {
+    for (int i = b + 1; i < b + n; ++i) {  // insertion sort by atom id
+      const int v = o[i];
+      const int key = id[v];
+      int j = i - 1;
+      while (j >= b && id[o[j]] > key) {
+        o[j + 1] = o[j];
+        --j;
+      }
+      o[j + 1] = v;
+    }
   }
 }
 
@@ -349,7 +379,7 @@ void launch_rebuild(const RebuildArgs& a, int32_t max_cells_per_slot, hipStream_
   }
   hipLaunchKernelGGL(k_rb_scan, dim3(a.nreps), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(k_rb_scatter, dim3(a.nblk), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_rb_sort, dim3(cb, a.nreps), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_rb_sort, dim3((max_cells_per_slot + 3) / 4, a.nreps), dim3(256), 0, s, a);
   if (a.dim == 3) {
     hipLaunchKernelGGL(k_rb_perm<3>, dim3(a.nblk), dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_rb_back<3>, dim3(a.nblk), dim3(kBlock), 0, s, a);
