@@ -7,7 +7,9 @@ quenched on the GPU from seeded uniform random positions.  One "step" is
 one round of Algorithm 1 (Sec. 3.5) with P = 16 level-II chains of K = 200
 fine AQS steps at dgamma = 5e-5 (level-I anchors at i * 1e-2), every
 minimisation run by FIRE to max|F| < 1e-10, all chains batched on the GPU.
-Each step starts from the same inherent structure (already in HBM).
+Each step starts from the same inherent structure (already in HBM); the
+accepted steps of a round are q of Algorithm 1 (at least K), the computed
+ones P * K plus the anchor minimisations.
 
 Prints one JSON line: accepted AQS steps/s (value), FIRE iterations per AQS
 step, the roofline of the dominant kernel (the FP64 force kernel, timed with
@@ -80,6 +82,25 @@ def cpu_baseline(dim, n, dg, iters_per_step, seconds=20.0):
             "t_eval_s": t_eval}
 
 
+def copy_calibration(mib: int) -> int:
+    """Plain streaming kernels of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters: three device copies and three negations of MIB MiB
+    (each reads and writes MIB MiB)."""
+    import torch
+    torch.cuda.set_device(0)
+    n = mib * (1 << 20) // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,7 +115,11 @@ def main() -> int:
     ap.add_argument("--profile-every", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only stream MIB MiB device-to-device (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -127,7 +152,7 @@ def main() -> int:
         g = parallel.layout(1, P)[0]
         torch.cuda.synchronize()
         t = time.perf_counter()
-        out = parallel.run(eng, [g], P * Kr, Kr, P)
+        out = parallel.run(eng, [g], P * Kr, Kr, P, max_rounds=1)
         torch.cuda.synchronize()
         return time.perf_counter() - t, out, g
 
