@@ -92,3 +92,22 @@ def choice_of(values, count: int, *seed: int) -> np.ndarray:
     """count draws, equally likely, from a short list of values."""
     rng = rng_for(*seed)
     return np.asarray(values)[rng.integers(0, len(values), size=count)]
+
+
+def mlp_init(dim: int, *seed: int, n_in: int = 64, hidden: int = 128) -> dict:
+    """Initial parameters of the per-atom network n_in -> hidden -> hidden ->
+    dim: every weight and bias drawn uniform in (-1/sqrt(fan_in),
+    1/sqrt(fan_in)) (FP32), weights in the [in, out] layout."""
+    rng = rng_for(*seed)
+    out = {}
+    for name, fi, fo in (("1", n_in, hidden), ("2", hidden, hidden), ("3", hidden, dim)):
+        k = 1.0 / math.sqrt(fi)
+        out["w" + name] = rng.uniform(-k, k, size=(fi, fo)).astype(np.float32)
+        out["b" + name] = rng.uniform(-k, k, size=fo).astype(np.float32)
+    return out
+
+
+def epoch_orders(n: int, epochs: int, *seed: int) -> np.ndarray:
+    """One random order of the n training samples per epoch, int32 [epochs, n]."""
+    rng = rng_for(*seed)
+    return np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)

@@ -37,6 +37,36 @@ FLOPS_PER_PAIR = 29          # one in-cutoff pair, counted once
 FORCE_BYTES_PER_ATOM = {2: 49, 3: 73}
 
 
+TRAFFIC_SOURCES = ("md_kernels.hip", "cells.hip", "tiles.h", "engine.h")
+
+
+def kernel_sources_sha256() -> str:
+    """Hash of the sources that decide the force kernel's memory traffic."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2507_20802_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def force_traffic(dim: int, atoms_per_launch: float):
+    """HBM bytes per force launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter summary (bytes per atom, copy-calibrated), or None when there is
+    none or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_force_{dim}d_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic_json:"):
+                t = json.loads(line.split(":", 1)[1])
+                if t.get("sources_sha256") != kernel_sources_sha256():
+                    return None
+                return (t["fetch_bytes_per_atom"] + t["write_bytes_per_atom"]) * atoms_per_launch
+    return None
+
+
 def in_cutoff_neighbours(pos, types, L, pot) -> float:
     """Mean number of neighbours within rc_ab (directed pairs per atom) of
     an orthogonal periodic box, counted with a k-d tree (host tooling)."""
@@ -211,7 +241,8 @@ def main() -> int:
         "quench_s": quench_s,
         "mean_neighbours_in_cutoff": nb,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved_tflops / FP64_PEAK_TFLOPS,
+                     "traffic": force_traffic(dim, atom_evals_per_launch),
                      "kernel": f"k_force<{dim}>", "avg_launch_ms": avg_ms,
                      "atoms_per_launch": atom_evals_per_launch,
                      "algorithmic_flops_per_atom": flops_per_atom,

@@ -838,11 +838,14 @@ aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int
       }
     }
     for (int it = 0; it < M; ++it) {
+      // events bracket the force kernel alone and the update kernel alone
       if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 0], c->stream));
       launch_force(a, c->cur_ntiles, c->dim, c->stream);
       if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 1], c->stream));
-      launch_update(a, c->cur_nblk, c->dim, c->stream);
+      launch_control(a, c->stream);
       if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 2], c->stream));
+      launch_update(a, c->cur_nblk, c->dim, c->stream);
+      if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 3], c->stream));
     }
     HIPCHK(hipGetLastError());
     c->cnt.force_launches += M;
@@ -856,7 +859,7 @@ aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int
       for (int it = 0; it < M; ++it) {
         float f = 0.f, u = 0.f;
         HIPCHK(hipEventElapsedTime(&f, c->ev[4 * it + 0], c->ev[4 * it + 1]));
-        HIPCHK(hipEventElapsedTime(&u, c->ev[4 * it + 1], c->ev[4 * it + 2]));
+        HIPCHK(hipEventElapsedTime(&u, c->ev[4 * it + 2], c->ev[4 * it + 3]));
         c->cnt.force_ms += f;
         c->cnt.update_ms += u;
       }
@@ -986,6 +989,7 @@ aqs_status aqs_energy_forces(aqs_ctx* c, int32_t rep, double* energy, double* fo
   if (st) return st;
   IterArgs a = iter_args(c);
   launch_force(a, c->cur_ntiles, c->dim, c->stream);
+  launch_control(a, c->stream);
   HIPCHK(hipGetLastError());
   st = pull_state(c);
   if (st) return st;

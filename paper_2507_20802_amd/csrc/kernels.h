@@ -51,6 +51,8 @@ void launch_rebuild(const RebuildArgs& a, int32_t max_cells_per_slot, hipStream_
 // One FIRE iteration: force + control over the force tiles (a.ftiles), then
 // the update over the 256-atom blocks (a.blocks).
 void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s);
+// per-slot reduction of the force partials and the FIRE control (after launch_force)
+void launch_control(const IterArgs& a, hipStream_t s);
 void launch_update(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s);
 
 // Affine shear x += dg_r y of whole slots (host-driven level I step).

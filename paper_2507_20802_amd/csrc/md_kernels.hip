@@ -645,6 +645,9 @@ void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s)
     launch_force_d<3>(a, ntiles, a.tpa, s);
   else
     launch_force_d<2>(a, ntiles, a.tpa, s);
+}
+
+void launch_control(const IterArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_control, dim3(a.nsel), dim3(kBlock), 0, s, a);
 }
 
