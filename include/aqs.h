@@ -62,6 +62,7 @@ typedef int32_t aqs_status;
 /* start of the minimisation after each fine affine step */
 #define AQS_START_PLAIN 0    /* the affine image F r (Eq. 12) */
 #define AQS_START_LEARNED 1  /* F r + predicted non-affine displacement */
+#define AQS_START_FALLBACK 2 /* record only: learned start rejected, F r used */
 
 /* Binary truncated-and-shifted Lennard-Jones pair potential, Eq. (13):
  * U_ab(r) = 4 eps_ab [(sigma_ab/r)^12 - (sigma_ab/r)^6] - U_ab(rc_ab) for
@@ -94,7 +95,8 @@ typedef struct {
   int32_t use_graph;        /* 1: replay each block of iterations as a hipGraph */
   int32_t max_chain_steps;  /* largest n_steps accepted by aqs_minimize_batch; 0 = 1024 */
   int32_t threads_per_atom; /* force kernel: 1, 2, 4 or 8 lanes per atom; 0 = 2 */
-  int32_t pad_;
+  int32_t learn_every;      /* learned start: FIRE iterations between launches of the
+                               descriptor / network kernels; 0 = 8 */
 } aqs_tuning;
 
 /* One record per minimisation of a chain (index 0 = the first minimisation,
@@ -105,7 +107,8 @@ typedef struct {
   double max_f;       /* max_i |F_i| at the last force evaluation */
   double sigma_xy;    /* shear stress at the last force evaluation */
   int32_t status;     /* AQS_CONVERGED ... */
-  int32_t start;      /* start actually used: AQS_START_PLAIN / _LEARNED */
+  int32_t start;      /* start used: AQS_START_PLAIN, AQS_START_LEARNED, or
+                         AQS_START_FALLBACK (learned start asked for, rejected) */
 } aqs_step_record;
 
 /* Bytes of device workspace a context with these slots needs.  n_atoms:
@@ -173,7 +176,9 @@ aqs_status aqs_affine_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
  *   v_i scaled to dmax / dt;  9 x += dt v; it++; it >= max_iter -> MAXITER.
  *
  * rep[n_sel]      host, distinct slots
- * start_mode      AQS_START_PLAIN or AQS_START_LEARNED (needs aqs_mlp_attach)
+ * start_mode      AQS_START_PLAIN or AQS_START_LEARNED (needs aqs_learned_load);
+ *                 with AQS_START_LEARNED the fine steps start as documented at
+ *                 aqs_learned_load (the first minimisation starts as given)
  * n_steps[n_sel]  host, fine steps after the first minimisation; NULL = all 0
  * snap_dst[n_sel] host, slot that receives a copy of the first inherent
  *                 structure (the "outgoing" configuration of Sec. 3.3), or -1;
@@ -222,6 +227,91 @@ typedef struct {
 aqs_status aqs_set_profiling(aqs_ctx* ctx, int32_t every_nth_block);
 
 aqs_status aqs_get_counters(aqs_ctx* ctx, aqs_counters* out, int32_t reset);
+
+/* ------------------------------------------------------------------------
+ * Learned start (the paper starts every minimisation at F r, Eq. 12, and
+ * names better starting points as an outlook, Sec. 5).
+ *
+ * Descriptors of atom i at an inherent structure (64, FP64 sums, minimum
+ * image in the current box, neighbours j within the pair cutoff r_d =
+ * rc_ab of the potential, f_c(r) = (cos(pi r / r_d) + 1) / 2):
+ *   f[24 s + b] = sum over neighbours of species s of
+ *                 exp(-(r - mu_b)^2 / (2 w^2)) f_c(r),
+ *                 mu_b = 0.6 + b w, w = (2.5 - 0.6) / 23, b = 0..23;
+ *   f[48 + k]   = sum_j f_c(r) max(0, n_k . r_ij / r)^2, k = 0..15, n_k at
+ *                 angles 2 pi k / 16 (2D) or the 16 points
+ *                 (sqrt(1-z^2) cos phi, sqrt(1-z^2) sin phi, z),
+ *                 z = 1 - (2k+1)/16, phi = k pi (3 - sqrt 5) (3D).
+ * Network: z = bf16((f - feat_mean) / feat_std) (FP32 arithmetic, round to
+ * nearest even); h1 = bf16(silu(z W1 + b1)); h2 = bf16(silu(h1 W2 + b2));
+ * y = h2 W3 + b3 (BF16 operands, FP32 sums); u_hat = y tgt_std + tgt_mean,
+ * the non-affine displacement per unit strain.  silu(a) = a / (1 + e^-a).
+ * Learned start of a fine step from inherent structure r: F r + dgamma
+ * (u_hat - mean u_hat), kept only if every u_hat is finite, max_i dgamma
+ * |u_hat_i| <= 0.1, and E and max_i |F_i| there do not exceed their values at
+ * F r; otherwise F r (record start AQS_START_FALLBACK). */
+
+typedef struct {
+  int32_t dim;               /* outputs d = 2 or 3 (the context's dim) */
+  int32_t pad_;
+  float w1[64 * 128];        /* [in][out] */
+  float b1[128];
+  float w2[128 * 128];
+  float b2[128];
+  float w3[128 * 3];         /* [in][out]; column 2 unused when d = 2 */
+  float b3[3];
+  float feat_mean[64], feat_std[64];
+  float tgt_mean[3], tgt_std[3];
+} aqs_mlp;
+
+typedef struct {
+  float lr, beta1, beta2, eps;  /* Adam (Kingma and Ba) */
+  float huber_delta;            /* Huber loss threshold, standardised units */
+  int32_t batch;                /* samples per Adam step (the last one may be short) */
+  int32_t epochs;
+  int32_t pad_;
+} aqs_train_params;
+
+/* Load a trained network into the context (copied; the caller keeps m). */
+aqs_status aqs_learned_load(aqs_ctx* ctx, const aqs_mlp* m);
+
+/* Descriptors of slot rep at its current positions: feat is a DEVICE
+ * pointer to n x 64 floats, atom-id order.  Rebuilds the slot's cell lists.
+ * Synchronises. */
+aqs_status aqs_learned_features(aqs_ctx* ctx, int32_t rep, float* feat);
+
+/* u_hat of the loaded network for slot rep: DEVICE pointer, n x dim
+ * floats, atom-id order.  Synchronises. */
+aqs_status aqs_learned_predict(aqs_ctx* ctx, int32_t rep, float* u_hat);
+
+/* Training targets from two inherent structures of one system: slot
+ * rep_next at strain index k_b > k_a of slot rep_prev, same dgamma.
+ * target (DEVICE, n x dim floats, atom-id order) = u / (s dgamma),
+ * u = minimum image of (r_next - F^(s dgamma) r_prev) in the box of
+ * rep_next, s = k_b - k_a.  Synchronises. */
+aqs_status aqs_learned_targets(aqs_ctx* ctx, int32_t rep_prev, int32_t rep_next,
+                               float* target);
+
+/* Train a network on the GPU.  feat (n x 64), target (n x dim) and order
+ * (epochs x n sample indices, one permutation per epoch) are DEVICE
+ * pointers.  model: in, the initial weights (dim set); out, the trained
+ * weights and the standardisation (mean and population std per column of
+ * feat and target, FP64 sums).  Each epoch takes the samples in its order,
+ * cut into consecutive batches; each batch is one Adam step on the mean
+ * Huber loss over its samples and outputs.  loss_hist (host, epochs, may be
+ * NULL): mean batch loss per epoch.  stream: hipStream_t or NULL.
+ * Allocates and frees its own device buffers.  Synchronises. */
+aqs_status aqs_mlp_train(const aqs_train_params* p, int64_t n, const float* feat,
+                         const float* target, const int32_t* order, aqs_mlp* model,
+                         float* loss_hist, void* stream);
+
+/* Gradient of the mean Huber loss over n <= 65536 samples (one batch, in
+ * order) at the weights and standardisation of model: grad receives model
+ * with the parameters replaced by their gradients; loss the loss.  DEVICE
+ * feat and target as for aqs_mlp_train.  Synchronises. */
+aqs_status aqs_mlp_gradients(const aqs_mlp* model, int64_t n, const float* feat,
+                             const float* target, float huber_delta, aqs_mlp* grad,
+                             float* loss, void* stream);
 
 /* Human-readable description of the last error on this thread. */
 const char* aqs_last_error(void);

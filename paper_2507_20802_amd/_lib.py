@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libaqs.so")
 
 AQS_OK, AQS_EINVAL, AQS_EHIP, AQS_ENOMEM, AQS_ECAPACITY, AQS_ESTATE = 0, -1, -2, -3, -4, -5
 AQS_CONVERGED, AQS_MAXITER, AQS_STALLED, AQS_NONFINITE = 0, 1, 2, 3
-AQS_START_PLAIN, AQS_START_LEARNED = 0, 1
+AQS_START_PLAIN, AQS_START_LEARNED, AQS_START_FALLBACK = 0, 1, 2
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -39,7 +39,7 @@ class aqs_tuning(ctypes.Structure):
     _fields_ = [("skin", ctypes.c_double), ("max_neighbors", ctypes.c_int32),
                 ("block_iters", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("max_chain_steps", ctypes.c_int32), ("threads_per_atom", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("learn_every", ctypes.c_int32)]
 
 
 class aqs_step_record(ctypes.Structure):
@@ -53,6 +53,23 @@ class aqs_counters(ctypes.Structure):
                 ("force_launches", ctypes.c_int64), ("rebuilds", ctypes.c_int64),
                 ("host_polls", ctypes.c_int64), ("atom_evals", ctypes.c_int64)]
 
+
+class aqs_mlp(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("w1", ctypes.c_float * (64 * 128)), ("b1", ctypes.c_float * 128),
+                ("w2", ctypes.c_float * (128 * 128)), ("b2", ctypes.c_float * 128),
+                ("w3", ctypes.c_float * (128 * 3)), ("b3", ctypes.c_float * 3),
+                ("feat_mean", ctypes.c_float * 64), ("feat_std", ctypes.c_float * 64),
+                ("tgt_mean", ctypes.c_float * 3), ("tgt_std", ctypes.c_float * 3)]
+
+
+class aqs_train_params(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("huber_delta", ctypes.c_float), ("batch", ctypes.c_int32),
+                ("epochs", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+c_float_p = ctypes.POINTER(ctypes.c_float)
 
 # name -> (restype, argtypes); every symbol declared in include/aqs.h
 SIGNATURES = {
@@ -78,6 +95,17 @@ SIGNATURES = {
     "aqs_energy_forces": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p, c_double_p]),
     "aqs_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "aqs_get_counters": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_counters), ctypes.c_int32]),
+    "aqs_learned_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_mlp)]),
+    "aqs_learned_features": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "aqs_learned_predict": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "aqs_learned_targets": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_void_p]),
+    "aqs_mlp_train": (ctypes.c_int32, [ctypes.POINTER(aqs_train_params), ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(aqs_mlp),
+                                       c_float_p, ctypes.c_void_p]),
+    "aqs_mlp_gradients": (ctypes.c_int32, [ctypes.POINTER(aqs_mlp), ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_float, ctypes.POINTER(aqs_mlp),
+                                           c_float_p, ctypes.c_void_p]),
     "aqs_last_error": (ctypes.c_char_p, []),
 }
 

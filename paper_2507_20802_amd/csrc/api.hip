@@ -12,6 +12,7 @@
 
 #include "aqs.h"
 #include "kernels.h"
+#include "learned.h"
 
 using namespace aqs;
 
@@ -47,7 +48,7 @@ double rc_max_of(const aqs_potential* p) {
 
 struct Tune {
   double skin;
-  int max_nb, block_iters, use_graph, log_cap, tpa;
+  int max_nb, block_iters, use_graph, log_cap, tpa, learn_every;
 };
 
 Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
@@ -59,6 +60,7 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   r.log_cap = ((t && t->max_chain_steps > 0) ? t->max_chain_steps : 1024) + 1;
   const int tp = t ? t->threads_per_atom : 0;
   r.tpa = (tp == 1 || tp == 2 || tp == 4 || tp == 8) ? tp : 2;
+  r.learn_every = (t && t->learn_every > 0) ? t->learn_every : 8;
   return r;
 }
 
@@ -83,7 +85,8 @@ struct Layout {
   size_t total = 0;
   size_t o_geom, o_state, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
       o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl,
-      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_evals, o_xref4, o_ftbl, o_ttbl, o_thdr, o_truns, o_sel;
+      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_evals, o_xref4, o_ftbl, o_ttbl, o_thdr, o_truns, o_sel,
+      o_zbuf, o_lpart, o_mlp, o_mlpw;
   int64_t atoms = 0;      // padded atoms over all slots
   int64_t nb_entries = 0;
   int32_t blocks = 0;
@@ -181,6 +184,10 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_xref4 = take(sizeof(double4) * A);
   lo.o_ftbl = take(sizeof(int2) * ((size_t)lo.tiles + 8));
   lo.o_ttbl = take(sizeof(int2) * ((size_t)lo.tiles + 8));
+  lo.o_zbuf = take(sizeof(uint16_t) * kFeat * A);
+  lo.o_lpart = take(sizeof(double) * kLearnParts * ((size_t)lo.blocks + 8));
+  lo.o_mlp = take(sizeof(MlpDev));
+  lo.o_mlpw = take(sizeof(float) * kNumParams);
   lo.total = off;
   return AQS_OK;
 }
@@ -224,6 +231,13 @@ struct aqs_ctx {
   double4* xref4;
   TileHdr* thdr;
   TileRun* truns;
+  // learned start
+  uint16_t* zbuf;
+  double* lpart;
+  MlpDev* mlp;
+  float* mlpw;
+  int mlp_dim = 0;           // 0: no network loaded
+  double rd[4], rd2[4], dirs[16][3];
   // host mirrors
   State* h_state = nullptr;  // pinned
   std::vector<char> loaded, dirty;
@@ -274,6 +288,35 @@ IterArgs iter_args(aqs_ctx* c) {
   a.alt4 = c->alt4;
   a.evals = c->evals;
   a.xref4 = c->xref4;
+  return a;
+}
+
+LearnArgs learn_args(aqs_ctx* c, int mode, float* out = nullptr) {
+  LearnArgs a{};
+  a.blocks = c->tbl;
+  a.sel = c->sel_d;
+  a.nsel = (int32_t)c->cur_sel.size();
+  a.mode = mode;
+  a.geom = c->d_geom;
+  a.state = c->d_state;
+  a.pos4 = c->pos4;
+  a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
+  a.id = c->id; a.inv = c->inv;
+  a.cell_start = c->cstart;
+  a.xref4 = c->xref4;
+  a.upart = c->upart;
+  a.lpart = c->lpart;
+  a.zbuf = c->zbuf;
+  a.dlx = c->dlx; a.dly = c->dly; a.dlz = c->dlz;
+  a.out = out;
+  a.mlp = c->mlp;
+  for (int t = 0; t < 4; ++t) {
+    a.rd[t] = c->rd[t];
+    a.rd2[t] = c->rd2[t];
+  }
+  for (int k = 0; k < 16; ++k)
+    for (int q = 0; q < 3; ++q) a.dirs[k][q] = c->dirs[k][q];
+  a.max_move = 0.1;
   return a;
 }
 
@@ -521,7 +564,26 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
       q.sig2 = sig * sig;
       q.eps4 = 4.0 * eps;
       q.ucut = 4.0 * eps * (sc6 * sc6 - sc6);
+      c->rd[2 * a + b] = rc;      // descriptor cutoff = the pair cutoff
+      c->rd2[2 * a + b] = rc * rc;
     }
+  // directions of the angular descriptors: 16 angles 2 pi k / 16 (2D),
+  // the 16 points of a Fibonacci sphere (3D)
+  for (int k = 0; k < 16; ++k) {
+    if (pot->dim == 2) {
+      const double an = 2.0 * M_PI * k / 16.0;
+      c->dirs[k][0] = std::cos(an);
+      c->dirs[k][1] = std::sin(an);
+      c->dirs[k][2] = 0.0;
+    } else {
+      const double z = 1.0 - (2.0 * k + 1.0) / 16.0;
+      const double rho = std::sqrt(1.0 - z * z);
+      const double phi = (k * M_PI) * (3.0 - std::sqrt(5.0));
+      c->dirs[k][0] = rho * std::cos(phi);
+      c->dirs[k][1] = rho * std::sin(phi);
+      c->dirs[k][2] = z;
+    }
+  }
   c->fire.dt0 = fire->dt0; c->fire.dt_max = fire->dt_max; c->fire.dt_min = fire->dt_min;
   c->fire.f_inc = fire->f_inc; c->fire.f_dec = fire->f_dec; c->fire.alpha0 = fire->alpha0;
   c->fire.f_alpha = fire->f_alpha; c->fire.dmax = fire->dmax; c->fire.ftol = fire->ftol;
@@ -568,6 +630,10 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->alt4 = at<double4>(w, lo.o_alt4);
   c->evals = at<unsigned long long>(w, lo.o_evals);
   c->xref4 = at<double4>(w, lo.o_xref4);
+  c->zbuf = at<uint16_t>(w, lo.o_zbuf);
+  c->lpart = at<double>(w, lo.o_lpart);
+  c->mlp = at<MlpDev>(w, lo.o_mlp);
+  c->mlpw = at<float>(w, lo.o_mlpw);
 
   const size_t tcap = std::max((size_t)lo.blocks, (size_t)lo.tiles) + 16;
   if (hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) != hipSuccess ||
@@ -779,8 +845,10 @@ aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int
   if (!c) return fail(AQS_EINVAL, "null context");
   if (n_sel <= 0) return AQS_OK;
   if (!rep) return fail(AQS_EINVAL, "null selection");
-  if (start_mode != AQS_START_PLAIN)
-    return fail(AQS_EINVAL, "start mode %d needs an attached model", start_mode);
+  if (start_mode != AQS_START_PLAIN && start_mode != AQS_START_LEARNED)
+    return fail(AQS_EINVAL, "unknown start mode %d", start_mode);
+  if (start_mode == AQS_START_LEARNED && c->mlp_dim != c->dim)
+    return fail(AQS_ESTATE, "the learned start needs a network (aqs_learned_load)");
   std::vector<int32_t> sel(rep, rep + n_sel);
   std::vector<char> seen(c->n_rep, 0);
   int max_steps = 0;
@@ -837,7 +905,14 @@ aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int
         c->ev.push_back(e);
       }
     }
+    const LearnArgs la = learn_args(c, 0);
     for (int it = 0; it < M; ++it) {
+      // slots waiting in PH_LDESC get descriptors, network and plain start
+      if (start_mode == AQS_START_LEARNED && it % c->tn.learn_every == 0) {
+        launch_ldesc(la, c->cur_nblk, c->dim, c->stream);
+        launch_lmlp(la, c->cur_nblk, c->dim, c->stream);
+        launch_lctl(la, c->stream);
+      }
       // events bracket the force kernel alone and the update kernel alone
       if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 0], c->stream));
       launch_force(a, c->cur_ntiles, c->dim, c->stream);
@@ -1038,6 +1113,283 @@ aqs_status aqs_get_counters(aqs_ctx* c, aqs_counters* out, int32_t reset) {
     HIPCHK(hipMemsetAsync(c->evals, 0, sizeof ev, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }
+  return AQS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned start
+
+namespace {
+
+// Device buffers of one training or gradient call (freed by the destructor).
+struct TrainBufs {
+  uint16_t* z = nullptr;
+  float *t = nullptr, *stats = nullptr, *part = nullptr, *master = nullptr, *m = nullptr,
+        *v = nullptr, *grad = nullptr;
+  double *stat_part = nullptr, *loss = nullptr;
+  int32_t* order = nullptr;
+  MlpDev* mlp = nullptr;
+  ~TrainBufs() {
+    void* ps[] = {z, t, stats, part, master, m, v, grad, stat_part, loss, order, mlp};
+    for (void* p : ps)
+      if (p) (void)hipFree(p);
+  }
+};
+
+aqs_status train_alloc(TrainBufs& b, int64_t n, int32_t blocks, int32_t epochs, bool adam) {
+  auto al = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 256)); };
+  if (al((void**)&b.z, sizeof(uint16_t) * kFeat * n) != hipSuccess ||
+      al((void**)&b.t, sizeof(float) * 4 * n) != hipSuccess ||
+      al((void**)&b.stats, sizeof(float) * 2 * 68 + sizeof(double) * 68) != hipSuccess ||
+      al((void**)&b.stat_part, sizeof(double) * 64 * 256) != hipSuccess ||
+      al((void**)&b.part, sizeof(float) * (size_t)(kNumParams + 1) * blocks) != hipSuccess ||
+      al((void**)&b.master, sizeof(float) * kNumParams) != hipSuccess ||
+      al((void**)&b.loss, sizeof(double) * std::max(epochs, 1)) != hipSuccess ||
+      al((void**)&b.mlp, sizeof(MlpDev)) != hipSuccess)
+    return fail(AQS_EHIP, "device allocation for the network failed");
+  if (adam && (al((void**)&b.m, sizeof(float) * kNumParams) != hipSuccess ||
+               al((void**)&b.v, sizeof(float) * kNumParams) != hipSuccess))
+    return fail(AQS_EHIP, "device allocation for the optimiser failed");
+  if (!adam && al((void**)&b.grad, sizeof(float) * kNumParams) != hipSuccess)
+    return fail(AQS_EHIP, "device allocation for the gradient failed");
+  return AQS_OK;
+}
+
+// Network parameters (flat FP32, the order of aqs_mlp) of a model.
+const float* params_of(const aqs_mlp* m) { return &m->w1[0]; }
+float* params_of(aqs_mlp* m) { return &m->w1[0]; }
+
+aqs_status upload_mlp(hipStream_t s, const aqs_mlp* m, float* master, MlpDev* dev, bool stats) {
+  HIPCHK(hipMemcpyAsync(master, params_of(m), sizeof(float) * kNumParams, hipMemcpyHostToDevice, s));
+  const int32_t dim = m->dim;
+  HIPCHK(hipMemcpyAsync(&dev->dim, &dim, sizeof dim, hipMemcpyHostToDevice, s));
+  if (stats) {
+    float tm[4] = {0, 0, 0, 0}, ts[4] = {1, 1, 1, 1};
+    for (int k = 0; k < dim; ++k) {
+      tm[k] = m->tgt_mean[k];
+      ts[k] = m->tgt_std[k];
+    }
+    HIPCHK(hipMemcpyAsync(dev->fmean, m->feat_mean, sizeof(float) * kFeat, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dev->fstd, m->feat_std, sizeof(float) * kFeat, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dev->tmean, tm, sizeof tm, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dev->tstd, ts, sizeof ts, hipMemcpyHostToDevice, s));
+  }
+  launch_mlp_sync(master, dev, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return AQS_OK;
+}
+
+aqs_status check_mlp(const aqs_mlp* m) {
+  if (!m) return fail(AQS_EINVAL, "null network");
+  if (m->dim != 2 && m->dim != 3) return fail(AQS_EINVAL, "network dim must be 2 or 3");
+  return AQS_OK;
+}
+
+// Slot rep alone as the current table, cells and lists rebuilt.
+aqs_status prepare_single(aqs_ctx* c, int32_t rep) {
+  aqs_status st = check_slot(c, rep);
+  if (st) return st;
+  st = pull_state(c);
+  if (st) return st;
+  std::vector<int32_t> sel{rep};
+  st = rebuild(c, sel);
+  if (st) return st;
+  return set_table(c, sel);
+}
+
+}  // namespace
+
+extern "C" {
+
+aqs_status aqs_learned_load(aqs_ctx* c, const aqs_mlp* m) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  aqs_status st = check_mlp(m);
+  if (st) return st;
+  if (m->dim != c->dim) return fail(AQS_EINVAL, "network has %d outputs, context dim %d", m->dim, c->dim);
+  for (int f = 0; f < kFeat; ++f)
+    if (!(m->feat_std[f] > 0.0f)) return fail(AQS_EINVAL, "feature std %d not positive", f);
+  for (int k = 0; k < m->dim; ++k)
+    if (!(m->tgt_std[k] > 0.0f)) return fail(AQS_EINVAL, "target std %d not positive", k);
+  st = upload_mlp(c->stream, m, c->mlpw, c->mlp, true);
+  if (st) return st;
+  c->mlp_dim = m->dim;
+  return AQS_OK;
+}
+
+aqs_status aqs_learned_features(aqs_ctx* c, int32_t rep, float* feat) {
+  if (!c || !feat) return fail(AQS_EINVAL, "null argument");
+  aqs_status st = prepare_single(c, rep);
+  if (st) return st;
+  launch_ldesc(learn_args(c, 1, feat), c->cur_nblk, c->dim, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return AQS_OK;
+}
+
+aqs_status aqs_learned_predict(aqs_ctx* c, int32_t rep, float* u_hat) {
+  if (!c || !u_hat) return fail(AQS_EINVAL, "null argument");
+  if (c->mlp_dim != c->dim) return fail(AQS_ESTATE, "no network loaded");
+  aqs_status st = prepare_single(c, rep);
+  if (st) return st;
+  launch_ldesc(learn_args(c, 2), c->cur_nblk, c->dim, c->stream);
+  launch_lmlp(learn_args(c, 1, u_hat), c->cur_nblk, c->dim, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return AQS_OK;
+}
+
+aqs_status aqs_learned_targets(aqs_ctx* c, int32_t rep_prev, int32_t rep_next, float* target) {
+  if (!c || !target) return fail(AQS_EINVAL, "null argument");
+  aqs_status st = check_slot(c, rep_prev);
+  if (st) return st;
+  st = check_slot(c, rep_next);
+  if (st) return st;
+  const Geom& ga = c->lo.geom[rep_prev];
+  const Geom& gb = c->lo.geom[rep_next];
+  if (ga.n != gb.n) return fail(AQS_EINVAL, "slots %d and %d differ in size", rep_prev, rep_next);
+  if (ga.dgamma != gb.dgamma) return fail(AQS_EINVAL, "slots differ in dgamma");
+  st = pull_state(c);
+  if (st) return st;
+  const int64_t steps = c->h_state[rep_next].k - c->h_state[rep_prev].k;
+  if (steps <= 0 || ga.dgamma == 0.0)
+    return fail(AQS_EINVAL, "slot %d is not strained beyond slot %d", rep_next, rep_prev);
+  launch_ltargets(c->d_geom, rep_prev, rep_next, ga.n, c->pos4, c->inv, c->dim,
+                  (double)steps * ga.dgamma, gb.L[0], gb.L[1], gb.L[2],
+                  tilt_of(c, rep_next, c->h_state[rep_next].k), target, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return AQS_OK;
+}
+
+aqs_status aqs_mlp_train(const aqs_train_params* p, int64_t n, const float* feat,
+                         const float* target, const int32_t* order, aqs_mlp* model,
+                         float* loss_hist, void* stream) {
+  if (!p || !feat || !target || !order) return fail(AQS_EINVAL, "null argument");
+  aqs_status st = check_mlp(model);
+  if (st) return st;
+  if (n <= 0 || p->batch <= 0 || p->epochs <= 0 || n > (int64_t)INT32_MAX)
+    return fail(AQS_EINVAL, "bad training sizes");
+  if (!(p->huber_delta > 0.0f) || !(p->lr > 0.0f))
+    return fail(AQS_EINVAL, "bad training parameters");
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t bsz = (int32_t)std::min<int64_t>(p->batch, n);
+  const int32_t maxblk = (bsz + 63) / 64;
+  TrainBufs b;
+  st = train_alloc(b, n, maxblk, p->epochs, true);
+  if (st) return st;
+  HIPCHK(hipMemsetAsync(b.m, 0, sizeof(float) * kNumParams, s));
+  HIPCHK(hipMemsetAsync(b.v, 0, sizeof(float) * kNumParams, s));
+  HIPCHK(hipMemsetAsync(b.loss, 0, sizeof(double) * p->epochs, s));
+  st = upload_mlp(s, model, b.master, b.mlp, false);
+  if (st) return st;
+  TrainArgs a{};
+  a.feat = feat;
+  a.tgt = target;
+  a.n = n;
+  a.dim = model->dim;
+  a.z = b.z;
+  a.t = b.t;
+  a.stat_part = b.stat_part;
+  a.stats = b.stats;
+  a.delta = p->huber_delta;
+  a.part = b.part;
+  a.master = b.master;
+  a.m = b.m;
+  a.v = b.v;
+  a.mlp = b.mlp;
+  a.lr = p->lr;
+  a.beta1 = p->beta1;
+  a.beta2 = p->beta2;
+  a.eps = p->eps;
+  launch_train_stats(a, s);
+  launch_train_prep(a, s);
+  HIPCHK(hipGetLastError());
+  int64_t step = 0, batches = 0;
+  for (int e = 0; e < p->epochs; ++e) {
+    batches = 0;
+    for (int64_t b0 = 0; b0 < n; b0 += bsz) {
+      a.order = order;
+      a.b0 = (int64_t)e * n + b0;
+      a.rows = (int32_t)std::min<int64_t>(bsz, n - b0);
+      a.nblk = (a.rows + 63) / 64;
+      a.loss_acc = b.loss + e;
+      ++step;
+      a.c1 = 1.0f - powf(p->beta1, (float)step);
+      a.c2 = 1.0f - powf(p->beta2, (float)step);
+      launch_train_batch(a, s);
+      launch_train_update(a, s);
+      ++batches;
+    }
+    HIPCHK(hipGetLastError());
+  }
+  std::vector<double> lh(p->epochs);
+  HIPCHK(hipMemcpyAsync(params_of(model), b.master, sizeof(float) * kNumParams,
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(model->feat_mean, b.mlp->fmean, sizeof(float) * kFeat, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(model->feat_std, b.mlp->fstd, sizeof(float) * kFeat, hipMemcpyDeviceToHost, s));
+  float tm[4], ts[4];
+  HIPCHK(hipMemcpyAsync(tm, b.mlp->tmean, sizeof tm, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ts, b.mlp->tstd, sizeof ts, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(lh.data(), b.loss, sizeof(double) * p->epochs, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int k = 0; k < 3; ++k) {
+    model->tgt_mean[k] = k < model->dim ? tm[k] : 0.0f;
+    model->tgt_std[k] = k < model->dim ? ts[k] : 1.0f;
+  }
+  if (loss_hist)
+    for (int e = 0; e < p->epochs; ++e) loss_hist[e] = (float)(lh[e] / (double)batches);
+  return AQS_OK;
+}
+
+aqs_status aqs_mlp_gradients(const aqs_mlp* model, int64_t n, const float* feat,
+                             const float* target, float huber_delta, aqs_mlp* grad,
+                             float* loss, void* stream) {
+  if (!feat || !target || !grad) return fail(AQS_EINVAL, "null argument");
+  aqs_status st = check_mlp(model);
+  if (st) return st;
+  if (n <= 0 || n > 65536) return fail(AQS_EINVAL, "gradient batch must hold 1..65536 samples");
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t nblk = (int32_t)((n + 63) / 64);
+  TrainBufs b;
+  st = train_alloc(b, n, nblk, 1, false);
+  if (st) return st;
+  if (hipMalloc((void**)&b.order, sizeof(int32_t) * n) != hipSuccess)
+    return fail(AQS_EHIP, "device allocation failed");
+  std::vector<int32_t> iota(n);
+  for (int64_t i = 0; i < n; ++i) iota[i] = (int32_t)i;
+  HIPCHK(hipMemcpyAsync(b.order, iota.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(b.loss, 0, sizeof(double), s));
+  st = upload_mlp(s, model, b.master, b.mlp, true);
+  if (st) return st;
+  TrainArgs a{};
+  a.feat = feat;
+  a.tgt = target;
+  a.n = n;
+  a.dim = model->dim;
+  a.z = b.z;
+  a.t = b.t;
+  a.delta = huber_delta;
+  a.part = b.part;
+  a.mlp = b.mlp;
+  a.order = b.order;
+  a.b0 = 0;
+  a.rows = (int32_t)n;
+  a.nblk = nblk;
+  a.grad_out = b.grad;
+  a.loss_acc = b.loss;
+  launch_train_prep(a, s);
+  launch_train_batch(a, s);
+  launch_train_update(a, s);
+  HIPCHK(hipGetLastError());
+  double lv = 0.0;
+  *grad = *model;
+  HIPCHK(hipMemcpyAsync(params_of(grad), b.grad, sizeof(float) * kNumParams, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&lv, b.loss, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (loss) *loss = (float)lv;
   return AQS_OK;
 }
 

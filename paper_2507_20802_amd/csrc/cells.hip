@@ -19,32 +19,13 @@
 // Integer atomics only; the result does not depend on their order.
 #include <hip/hip_runtime.h>
 
+#include "cellgeom.h"
 #include "kernels.h"
 #include "tiles.h"
 
 namespace aqs {
 
 namespace {
-
-__device__ __forceinline__ void frac(const Geom& g, double t, double x, double y, double z,
-                                     double* s) {
-  s[1] = y / g.L[1];
-  s[0] = (x - t * s[1]) / g.L[0];
-  s[2] = z / g.L[2];
-}
-
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-template <int D>
-__device__ __forceinline__ int cell_of_pos(const Geom& g, const int* nc, double t, const double4& p,
-                                           int* c3) {
-  double s[3];
-  frac(g, t, p.x, p.y, (D == 3) ? p.z : 0.0, s);
-  c3[0] = clampi((int)floor(s[0] * nc[0]), 0, nc[0] - 1);
-  c3[1] = clampi((int)floor(s[1] * nc[1]), 0, nc[1] - 1);
-  c3[2] = (D == 3) ? clampi((int)floor(s[2] * nc[2]), 0, nc[2] - 1) : 0;
-  return (c3[2] * nc[1] + c3[1]) * nc[0] + c3[0];
-}
 
 // grid per slot: nc0, nc1, nc2, tile width, tiles, list mode
 __global__ void k_rb_grid(RebuildArgs a, const int32_t* nc3) {
@@ -360,7 +341,9 @@ __global__ void k_rb_done(RebuildArgs a) {
   if (threadIdx.x == 0) {
     st->ubound = 0.0;
     st->gamma_build = strain_of(st->k, g.dgamma);
-    if (a.resume && st->phase == PH_REBUILD) st->phase = PH_FIRE;
+    if (a.resume && st->phase == PH_REBUILD)
+      st->phase = (st->resume_phase == PH_LPLAIN || st->resume_phase == PH_LMOVE ||
+                   st->resume_phase == PH_LREVERT) ? st->resume_phase : PH_FIRE;
   }
 }
 

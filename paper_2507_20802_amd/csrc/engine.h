@@ -40,10 +40,23 @@ enum Phase : int32_t {
   PH_REBUILD = 6,   // neighbour list no longer valid; waits for the host
   PH_EVAL = 7,      // one force evaluation without FIRE control
   PH_ENERGY = 11,   // evaluate again with the energy, then record the pending outcome
-  PH_LDESC = 8,     // learned start: descriptors + MLP pending at the IS
-  PH_LMOVE = 9,     // learned start: update moves plain start -> learned start
+  PH_LDESC = 8,     // learned start: descriptors + network pending at the IS
+  PH_LMOVE = 9,     // learned start: update moved plain start -> learned start;
+                    // evaluate there, then accept (FIRE) or revert
   PH_LREVERT = 10,  // learned start rejected: update restores the plain start
+  PH_LPLAIN = 12,   // learned start: evaluate at the plain start (reference E, max |F|)
 };
+
+// start of a minimisation (StepRecord::start): the affine image, the learned
+// start, or the affine image after the learned start was rejected
+constexpr int32_t kStartPlain = 0, kStartLearned = 1, kStartFallback = 2;
+
+__host__ __device__ inline bool phase_energy(int32_t ph) {  // evaluation also sums E
+  return ph == PH_EVAL || ph == PH_ENERGY || ph == PH_LPLAIN || ph == PH_LMOVE;
+}
+__host__ __device__ inline bool phase_force(int32_t ph) {   // the force kernel evaluates
+  return phase_energy(ph) || ph == PH_FIRE || ph == PH_ADVANCE || ph == PH_LREVERT;
+}
 
 // static per-slot geometry
 struct Geom {
@@ -71,6 +84,7 @@ struct State {
   double ubound;      // sum of per-iteration max displacements since the build
   double gamma_build; // strain at the last neighbour-list build
   double E_plain, fmax_plain;  // learned start: plain-start reference values
+  double lmean[3];    // learned start: mean predicted displacement per unit strain
   int32_t npos, nneg;
   int32_t restart;    // pending update backs off x -= dt v / 2, v = 0
   int32_t phase;
@@ -87,7 +101,7 @@ struct State {
   int32_t tiles_x;    // force tiles (row segments) per cell row
   int32_t ntiles;     // force tiles of the current grid
   int32_t list_mode;  // 0: tiles index their LDS halo; 1: global indices only
-  int32_t pad_;
+  int32_t resume_phase;  // phase to resume after a neighbour-list rebuild
 };
 
 struct PairParams {   // per type pair t = 2 ti + tj

@@ -257,7 +257,6 @@ __device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
   }
   if (status == 0 && s.step < s.n_steps) {
     s.step += 1;
-    s.k += 1;
     s.dt = a.fire.dt0;
     s.alpha = a.fire.alpha0;
     s.npos = 0;
@@ -266,8 +265,16 @@ __device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
     s.restart = 0;
     s.cv = 1.0;
     s.cf = 0.0;
-    s.start_used = 0;
-    s.phase = PH_ADVANCE;
+    if (s.start_mode == kStartLearned) {
+      // descriptors and network at this inherent structure first; the
+      // strain index advances with the plain start (learned kernels)
+      s.start_used = kStartFallback;
+      s.phase = PH_LDESC;
+    } else {
+      s.k += 1;
+      s.start_used = kStartPlain;
+      s.phase = PH_ADVANCE;
+    }
   } else {
     s.phase = PH_FINISH;
   }
@@ -288,6 +295,8 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
   const double gam = strain_of(s.k, g.dgamma);
   const double gd = fabs(gam - s.gamma_build);
   if (!(gd * a.rc_max + 2.0 * (1.0 + gd) * ub < a.skin)) {
+    s.resume_phase =
+        (phase == PH_LPLAIN || phase == PH_LMOVE || phase == PH_LREVERT) ? phase : PH_FIRE;
     s.phase = PH_REBUILD;
     a.state[rep] = s;
     return;
@@ -307,6 +316,28 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     }
     a.state[rep] = s;
     return;
+  }
+  // learned start: the plain start's E and max |F| are the reference; the
+  // learned start is kept only if it is no worse in both, else reverted
+  if (phase == PH_LPLAIN) {
+    s.E_plain = r[0];
+    s.fmax_plain = s.fmax;
+    if (s.learn_ok && r[6] == 0.0 && isfinite(r[0]) && isfinite(r[4])) {
+      s.phase = PH_LMOVE;
+      a.state[rep] = s;
+      return;
+    }
+    s.start_used = kStartFallback;
+  } else if (phase == PH_LMOVE) {
+    const bool worse = r[6] != 0.0 || !isfinite(r[0]) || !isfinite(r[4]) ||
+                       r[0] > s.E_plain || s.fmax > s.fmax_plain;
+    if (worse) {
+      s.start_used = kStartFallback;
+      s.phase = PH_LREVERT;
+      a.state[rep] = s;
+      return;
+    }
+    s.start_used = kStartLearned;
   }
   s.phase = PH_FIRE;
   if (r[6] != 0.0 || !isfinite(r[1]) || !isfinite(r[2])) {
@@ -426,8 +457,8 @@ __global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
   if (rep < 0) return;
   const State* stp = a.state + rep;
   const int phase = stp->phase;
-  const bool we = (phase == PH_EVAL || phase == PH_ENERGY);
-  const bool compute = we || phase == PH_FIRE || phase == PH_ADVANCE;
+  const bool we = phase_energy(phase);
+  const bool compute = phase_force(phase);
   if (!compute) return;
   const int ntiles = stp->ntiles;
   if (bt.y >= ntiles) return;
@@ -516,8 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
   const int rep = a.sel[blockIdx.x];
   const State* stp = a.state + rep;
   const int phase = stp->phase;
-  const bool we = (phase == PH_EVAL || phase == PH_ENERGY);
-  const bool compute = we || phase == PH_FIRE || phase == PH_ADVANCE;
+  const bool compute = phase_force(phase);
   const bool counted = compute || phase == PH_FINISH || phase == PH_STOP;
   if (!counted) return;
   const Geom g = a.geom[rep];
@@ -559,7 +589,9 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
   const int phase = st->phase;
   const bool fire = (phase == PH_FIRE || phase == PH_STOP);
   const bool adv = (phase == PH_ADVANCE);
-  if (!(fire || adv || phase == PH_FINISH)) return;
+  // learned start: move to F r + dgamma (u_hat - mean u_hat), or back
+  const bool lmove = (phase == PH_LMOVE || phase == PH_LREVERT);
+  if (!(fire || adv || lmove || phase == PH_FINISH)) return;
   const Geom g = a.geom[rep];
   const int tid = threadIdx.x;
   const int li = bt.y * kBlock + tid;
@@ -568,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
   if (li < g.n) {
     const int64_t gi = g.atom_off + li;
     double4 p = a.pos4[gi];
-    if (st->do_snap && phase != PH_FIRE) {  // first inherent structure -> snap_dst
+    if (st->do_snap && (adv || phase == PH_FINISH)) {  // first inherent structure -> snap_dst
       const Geom gd = a.geom[st->snap_dst];
       const int64_t di = gd.atom_off + li;
       a.pos4[di] = p;
@@ -614,15 +646,29 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       a.vx[gi] = 0.0;
       a.vy[gi] = 0.0;
       if (D == 3) a.vz[gi] = 0.0;
+    } else if (lmove) {
+      const double ux = g.dgamma * (a.dlx[gi] - st->lmean[0]);
+      const double uy = g.dgamma * (a.dly[gi] - st->lmean[1]);
+      const double uz = (D == 3) ? g.dgamma * (a.dlz[gi] - st->lmean[2]) : 0.0;
+      if (phase == PH_LMOVE) {
+        p.x += ux;
+        p.y += uy;
+        if (D == 3) p.z += uz;
+      } else {
+        p.x -= ux;
+        p.y -= uy;
+        if (D == 3) p.z -= uz;
+      }
+      a.pos4[gi] = p;
     }
-    if (fire || adv) {
+    if (fire || adv || lmove) {
       const double4 x0 = a.xref4[gi];
       const double gd = strain_of(st->k, g.dgamma) - st->gamma_build;
       const double ux = p.x - (x0.x + gd * x0.y), uy = p.y - x0.y, uz = p.z - x0.z;
       m[0] = sqrt(ux * ux + uy * uy + uz * uz);
     }
   }
-  if (fire || adv) {
+  if (fire || adv || lmove) {
     const int op[1] = {1};
     block_reduce<1>(m, op, red);
     if (tid == 0) a.upart[g.block0 + bt.y] = m[0];

@@ -78,6 +78,7 @@ class Tuning:
     use_graph: int = 0
     max_chain_steps: int = 1024
     threads_per_atom: int = 0
+    learn_every: int = 0
 
     def to_c(self) -> aqs_tuning:
         t = aqs_tuning()
@@ -87,6 +88,7 @@ class Tuning:
         t.use_graph = self.use_graph
         t.max_chain_steps = self.max_chain_steps
         t.threads_per_atom = self.threads_per_atom
+        t.learn_every = self.learn_every
         return t
 
 
@@ -256,3 +258,41 @@ class Engine:
         c = _lib.aqs_counters()
         check(self._lib.aqs_get_counters(self._ctx, ctypes.byref(c), int(reset)), "aqs_get_counters")
         return {k: getattr(c, k) for k, _ in c._fields_}
+
+    # -- learned start ----------------------------------------------------
+    def _dev_f32(self, rows: int, cols: int, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((rows, cols), dtype=torch.float32, device=self.device)
+        if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() < rows * cols \
+                or out.device != self.device:
+            raise ValueError("output must be a contiguous float32 tensor on the engine's device")
+        return out
+
+    def learned_features(self, rep: int, out=None):
+        """Descriptors of slot rep (n x 64 float32 tensor on the device,
+        atom-id order)."""
+        n = int(self.n_atoms[rep])
+        out = self._dev_f32(n, 64, out)
+        check(self._lib.aqs_learned_features(self._ctx, int(rep), ctypes.c_void_p(out.data_ptr())),
+              "aqs_learned_features")
+        return out
+
+    def learned_targets(self, rep_prev: int, rep_next: int, out=None):
+        """Non-affine displacement per unit strain from slot rep_prev to
+        slot rep_next (n x dim float32 tensor on the device, atom-id order)."""
+        n = int(self.n_atoms[rep_next])
+        out = self._dev_f32(n, self.dim, out)
+        check(self._lib.aqs_learned_targets(self._ctx, int(rep_prev), int(rep_next),
+                                            ctypes.c_void_p(out.data_ptr())), "aqs_learned_targets")
+        return out
+
+    def learned_load(self, model: "_lib.aqs_mlp") -> None:
+        check(self._lib.aqs_learned_load(self._ctx, ctypes.byref(model)), "aqs_learned_load")
+
+    def learned_predict(self, rep: int, out=None):
+        n = int(self.n_atoms[rep])
+        out = self._dev_f32(n, self.dim, out)
+        check(self._lib.aqs_learned_predict(self._ctx, int(rep), ctypes.c_void_p(out.data_ptr())),
+              "aqs_learned_predict")
+        return out

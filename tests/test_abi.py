@@ -47,6 +47,28 @@ def test_struct_sizes_match_the_header_layout():
     assert ctypes.sizeof(_lib.aqs_potential) == 8 + 32 + 32 + 8
     assert ctypes.sizeof(_lib.aqs_fire_params) == 9 * 8 + 4 * 4 + 8
     assert ctypes.sizeof(_lib.aqs_step_record) == 8 * 4 + 8
+    n_params = 64 * 128 + 128 + 128 * 128 + 128 + 128 * 3 + 3
+    assert ctypes.sizeof(_lib.aqs_mlp) == 8 + 4 * (n_params + 64 + 64 + 3 + 3)
+
+
+def test_struct_sizes_match_a_c_compiler(tmp_path):
+    """sizeof of every ABI struct as gcc lays it out from include/aqs.h."""
+    import shutil
+    import subprocess
+    from paper_2507_20802_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    names = ["aqs_potential", "aqs_fire_params", "aqs_tuning", "aqs_step_record", "aqs_counters",
+             "aqs_mlp", "aqs_train_params"]
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "aqs.h"\nint main(void){' +
+                   "".join(f'printf("%zu\\n", sizeof({n}));' for n in names) + "return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    sizes = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                            text=True).stdout.split()]
+    assert sizes == [ctypes.sizeof(getattr(_lib, n)) for n in names]
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
