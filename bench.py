@@ -131,6 +131,32 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
+def train_network(eng, dim, n, dg, slot_a, slot_b, steps, epochs, seed):
+    """Learned start: descriptors and non-affine targets from `steps` plain
+    AQS steps of a separately seeded glass, then the network trained on the
+    GPU (Adam, Huber loss, batch 4096).  Returns the model and a summary."""
+    import torch
+    import aqs_synth as S
+    from paper_2507_20802_amd import learned
+    s = S.uniform_glass_start(dim, n, 3, seed)
+    eng.set_replica(slot_a, s.types, s.pos, 0)
+    t0 = time.perf_counter()
+    q = eng.minimize([slot_a])[0, 0]
+    if q["status"] != 0:
+        raise RuntimeError("quench of the training glass failed")
+    feat, tgt, recs = learned.collect_samples(eng, slot_a, slot_b, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    orders = torch.from_numpy(S.epoch_orders(feat.shape[0], epochs, 3, seed, 7)).cuda()
+    model = learned.make_mlp(dim, S.mlp_init(dim, 3, seed, 8))
+    hist = learned.train(model, feat, tgt, orders, learned.TrainParams(batch=4096, epochs=epochs))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return model, {"samples": int(feat.shape[0]), "plain_steps": steps, "epochs": epochs,
+                   "data_s": t1 - t0, "train_s": t2 - t1, "loss_first": float(hist[0]),
+                   "loss_last": float(hist[-1])}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +169,9 @@ def main() -> int:
     ap.add_argument("--dgamma", type=float, default=5e-5)
     ap.add_argument("--warmup-K", type=int, default=20, help="fine steps per chain in warmup rounds")
     ap.add_argument("--profile-every", type=int, default=4)
+    ap.add_argument("--train-steps", type=int, default=7, help="plain AQS steps of training data")
+    ap.add_argument("--epochs", type=int, default=50)
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-start reference rounds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -158,14 +187,16 @@ def main() -> int:
 
     import torch
     import aqs_synth as S
-    from paper_2507_20802_amd import Engine, Fire, LJParams, Tuning, parallel
+    from paper_2507_20802_amd import (AQS_START_LEARNED, AQS_START_PLAIN, Engine, Fire, LJParams,
+                                      Tuning, parallel)
 
     torch.cuda.set_device(0)
     dim, n, P, K, dg = args.dim, args.n, args.P, args.K, args.dgamma
     pot = LJParams()
     s = S.uniform_glass_start(dim, n, 3, 0)
     nslots = parallel.slots_needed(1, P)
-    eng = Engine(dim, [n] * nslots, s.L, dg, pot=pot, fire=Fire(), tuning=Tuning())
+    ref_slot = nslots              # final r_star of the plain round, for the IS comparison
+    eng = Engine(dim, [n] * (nslots + 1), s.L, dg, pot=pot, fire=Fire(), tuning=Tuning())
     glass = parallel.layout(1, P)[0]
     t0 = time.perf_counter()
     eng.set_replica(glass.star, s.types, s.pos, 0)
@@ -176,55 +207,79 @@ def main() -> int:
         return 1
     is_pos = eng.positions(glass.star)
     nb = in_cutoff_neighbours(is_pos, s.types, s.L, pot)
+    model, train_info = train_network(eng, dim, n, dg, glass.chains[0], glass.chains[1],
+                                      args.train_steps, args.epochs, 1)
+    eng.learned_load(model)
 
-    def one_round(Kr):
+    def one_round(Kr, start):
         eng.set_replica(glass.star, s.types, is_pos, 0)
         g = parallel.layout(1, P)[0]
         torch.cuda.synchronize()
         t = time.perf_counter()
-        out = parallel.run(eng, [g], P * Kr, Kr, P, max_rounds=1)
+        out = parallel.run(eng, [g], P * Kr, Kr, P, start=start, max_rounds=1)
         torch.cuda.synchronize()
         return time.perf_counter() - t, out, g
 
+    forms = ([] if args.no_plain else [("plain", AQS_START_PLAIN)]) + [("learned", AQS_START_LEARNED)]
     for _ in range(args.warmup):
-        one_round(args.warmup_K)
-    eng.counters(reset=True)
-    eng.set_profiling(args.profile_every)
-    tot_t, acc, comp, iters, ok, rounds = 0.0, 0, 0, [], True, []
-    for _ in range(args.steps):
-        dt, out, g = one_round(K)
-        tot_t += dt
-        acc += out["accepted_steps"]
-        comp += out["computed_steps"]
-        iters.extend(g.step_iters)
-        ok = ok and out["statuses_ok"]
-        rounds.append({"wall_s": dt, "accepted": out["accepted_steps"], "computed": out["computed_steps"],
-                       "rounds_of_alg1": out["rounds"], "decisions": [d.equal for d in g.decisions],
-                       "anchor_iters": g.anchor_iters})
-    eng.set_profiling(0)
-    cnt = eng.counters()
-    it = np.asarray(iters, dtype=np.float64)
-    value = acc / tot_t
-    # roofline of the force kernel: algorithmic flops per atom-evaluation
-    atom_evals_per_launch = None
+        for _, st in forms:
+            one_round(args.warmup_K, st)
+    res_forms = {}
+    for name, st in forms:
+        eng.counters(reset=True)
+        eng.set_profiling(args.profile_every)
+        tot_t, acc, comp, iters, ok, rounds, starts = 0.0, 0, 0, [], True, [], []
+        for _ in range(args.steps):
+            dt, out, g = one_round(K, st)
+            tot_t += dt
+            acc += out["accepted_steps"]
+            comp += out["computed_steps"]
+            iters.extend(g.step_iters)
+            starts.extend(g.step_starts)
+            ok = ok and out["statuses_ok"]
+            rounds.append({"wall_s": dt, "accepted": out["accepted_steps"], "computed": out["computed_steps"],
+                           "rounds_of_alg1": out["rounds"], "decisions": [d.equal for d in g.decisions],
+                           "anchor_iters": g.anchor_iters})
+        eng.set_profiling(0)
+        if name == "plain":
+            eng.copy_replica(glass.star, ref_slot)
+        it = np.asarray(iters, dtype=np.float64)
+        res_forms[name] = {"value": acc / tot_t, "ms_per_step": 1e3 * tot_t / args.steps,
+                           "computed_steps_per_s": comp / tot_t,
+                           "fire_iters_per_step": {"mean": float(it.mean()), "median": float(np.median(it)),
+                                                   "p95": float(np.percentile(it, 95))},
+                           "all_converged": bool(ok), "rounds": rounds, "counters": eng.counters(),
+                           "starts": {"plain": starts.count(0), "learned": starts.count(1),
+                                      "fallback": starts.count(2)}}
+    lr = res_forms["learned"]
+    cnt = lr["counters"]
+    # inherent-structure agreement of the two forms: same decisions, same final r_star (Eq. 20)
+    comparison = None
+    if "plain" in res_forms:
+        pl = res_forms["plain"]
+        same_dec = [r["decisions"] for r in lr["rounds"]] == [r["decisions"] for r in pl["rounds"]]
+        eq, md, de = eng.compare(glass.star, ref_slot, 1e-4)   # r_star after the last round of each form
+        comparison = {"same_decisions": bool(same_dec), "final_star_equal": bool(eq),
+                      "final_star_max_disp": md, "final_star_de_per_atom": de,
+                      "is_mismatches": int((not eq) + (not same_dec)),
+                      "iters_ratio_learned_over_plain": lr["fire_iters_per_step"]["mean"]
+                      / pl["fire_iters_per_step"]["mean"],
+                      "wall_ratio_learned_over_plain": lr["ms_per_step"] / pl["ms_per_step"]}
+    # roofline of the force kernel in the learned-start rounds
     flops_per_atom = 0.5 * nb * FLOPS_PER_PAIR
     avg_ms = cnt["force_ms"] / max(cnt["force_timed"], 1)
-    # active atoms per launch: total force-phase atom evaluations / launches
     evals = cnt.get("atom_evals", 0)
-    if evals and cnt["force_launches"]:
-        atom_evals_per_launch = evals / cnt["force_launches"]
-    else:
-        atom_evals_per_launch = P * n
+    atom_evals_per_launch = evals / cnt["force_launches"] if evals and cnt["force_launches"] else P * n
     achieved_tflops = flops_per_atom * atom_evals_per_launch / (avg_ms * 1e-3) / 1e12
     achieved_gbs = FORCE_BYTES_PER_ATOM[dim] * atom_evals_per_launch / (avg_ms * 1e-3) / 1e9
     res = {
         "metric": METRIC,
-        "value": value,
+        "value": lr["value"],
         "unit": "accepted AQS steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * tot_t / args.steps,
+        "ms_per_step": lr["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -232,12 +287,14 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{dim}D binary LJ glass N={n}, Algorithm 1 round: P={P} chains x K={K} "
                                f"fine AQS steps, dgamma={dg:g}, dgamma_c={K * dg:g}, FIRE to max|F|<1e-10, "
-                               f"plain start",
+                               f"learned start (plain start timed alongside)",
                    "dim": dim, "n_atoms": n, "P": P, "K": K, "dgamma": dg},
-        "computed_steps_per_s": comp / tot_t,
-        "fire_iters_per_step": {"mean": float(it.mean()), "median": float(np.median(it)),
-                                "p95": float(np.percentile(it, 95))},
-        "all_converged": bool(ok),
+        "computed_steps_per_s": lr["computed_steps_per_s"],
+        "fire_iters_per_step": lr["fire_iters_per_step"],
+        "all_converged": lr["all_converged"],
+        "learned_start": {"starts": lr["starts"], "training": train_info},
+        "plain": {k: v for k, v in res_forms.get("plain", {}).items() if k != "counters"},
+        "learned_vs_plain": comparison,
         "quench_s": quench_s,
         "mean_neighbours_in_cutoff": nb,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -248,10 +305,10 @@ def main() -> int:
                      "algorithmic_flops_per_atom": flops_per_atom,
                      "hbm_gbs_algorithmic": achieved_gbs, "hbm_frac": achieved_gbs / HBM_PEAK_GBS},
         "counters": cnt,
-        "rounds": rounds,
+        "rounds": lr["rounds"],
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(dim, n, dg, float(it.mean()), args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(dim, n, dg, float(lr["fire_iters_per_step"]["mean"]), args.cpu_seconds)
     print(json.dumps(res), flush=True)
     return 0
 

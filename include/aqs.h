@@ -295,10 +295,13 @@ aqs_status aqs_learned_targets(aqs_ctx* ctx, int32_t rep_prev, int32_t rep_next,
 /* Train a network on the GPU.  feat (n x 64), target (n x dim) and order
  * (epochs x n sample indices, one permutation per epoch) are DEVICE
  * pointers.  model: in, the initial weights (dim set); out, the trained
- * weights and the standardisation (mean and population std per column of
- * feat and target, FP64 sums).  Each epoch takes the samples in its order,
- * cut into consecutive batches; each batch is one Adam step on the mean
- * Huber loss over its samples and outputs.  loss_hist (host, epochs, may be
+ * weights and the standardisation: mean and population std per column of
+ * feat (FP64 sums); for target the same statistics trimmed three times to
+ * the samples whose every component lies within 5 std of the mean (the
+ * samples outside the final window -- plastic jumps -- are left out of the
+ * loss).  Each epoch takes the samples in its order, cut into consecutive
+ * batches; each batch is one Adam step on the Huber loss summed over its
+ * kept samples and outputs, divided by (batch size x dim).  loss_hist (host, epochs, may be
  * NULL): mean batch loss per epoch.  stream: hipStream_t or NULL.
  * Allocates and frees its own device buffers.  Synchronises. */
 aqs_status aqs_mlp_train(const aqs_train_params* p, int64_t n, const float* feat,

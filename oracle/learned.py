@@ -22,8 +22,10 @@ inherent structure.  Definitions (this project's, see the functions):
   activations at the layer inputs, FP32 accumulation, biases and SiLU
   (``mlp_forward`` with ``emulate=True`` rounds where the GPU rounds);
 * target: u_i / dgamma with u_i = minimg(r_i(IS_k) - F r_i(IS_(k-1))) from
-  plain AQS steps; features and targets standardised with training-set
-  mean and std (FP32), features rounded to BF16;
+  plain AQS steps; features standardised with training-set mean and std
+  (FP32) and rounded to BF16, targets with trimmed statistics (samples
+  farther than 5 std from the mean, recomputed three times, are left out:
+  plastic jumps);
 * loss: Huber (delta in standardised units), mean over samples and
   components; optimiser: Adam.
 
@@ -219,9 +221,11 @@ def huber(e, delta: float):
 
 
 def loss_and_grads(z: np.ndarray, t: np.ndarray, m: MLP, delta: float = 1.0,
-                   emulate: bool = True):
+                   emulate: bool = True, weight=None):
     """Mean Huber loss over samples and components and its gradients with
-    respect to (w1, b1, w2, b2, w3, b3), by back-propagation.
+    respect to (w1, b1, w2, b2, w3, b3), by back-propagation.  weight: 0/1
+    per sample (samples of weight 0 add nothing; the mean still divides by
+    the batch size).
 
     emulate=True rounds the back-propagated signals to BF16 where they enter
     a matrix product (the output error, dL/da2, dL/da1), as the GPU's matrix
@@ -229,10 +233,11 @@ def loss_and_grads(z: np.ndarray, t: np.ndarray, m: MLP, delta: float = 1.0,
     y, (zz, a1, h1, a2, h2) = mlp_forward(z, m, emulate)
     B, d = y.shape
     e = y - t
-    loss = float(np.sum(huber(e.astype(np.float64), delta)) / (B * d))
+    w = np.ones(B) if weight is None else np.asarray(weight, dtype=np.float64)
+    loss = float(np.sum(w[:, None] * huber(e.astype(np.float64), delta)) / (B * d))
     if emulate:
         f32 = np.float32
-        g = (np.clip(e, -delta, delta) / f32(B * d)).astype(f32)
+        g = (np.clip(e, -delta, delta) / f32(B * d)).astype(f32) * w[:, None].astype(f32)
         gb = bf16(g)
         w2b, w3b = bf16(m.w2), bf16(m.w3)
         dw3 = _mm(h2.T, gb)
@@ -248,7 +253,7 @@ def loss_and_grads(z: np.ndarray, t: np.ndarray, m: MLP, delta: float = 1.0,
         dw1 = _mm(zz.T, dz1b)
         db1 = dz1.astype(np.float64).sum(0).astype(f32)
     else:
-        g = np.clip(e, -delta, delta) / (B * d)
+        g = np.clip(e, -delta, delta) / (B * d) * w[:, None]
         dw3 = h2.T @ g
         db3 = g.sum(0)
         dh2 = g @ m.w3.astype(np.float64).T
@@ -295,26 +300,55 @@ def adam_step(model: MLP, grads: dict, st: AdamState) -> None:
         st.m[k], st.v[k] = m, v
 
 
+def _stats64(x: np.ndarray, mask=None):
+    if mask is not None:
+        x = x[mask]
+    mean = x.mean(0)
+    std = np.sqrt(((x - mean) ** 2).mean(0))
+    return mean, std
+
+
 def feature_stats(raw: np.ndarray):
     """Mean and population std per column (FP64 sums, FP32 result); a
     column with zero spread gets std 1."""
-    x = np.asarray(raw, dtype=np.float64)
-    mean = x.mean(0)
-    std = np.sqrt(((x - mean) ** 2).mean(0))
+    mean, std = _stats64(np.asarray(raw, dtype=np.float64))
     std = np.where(std > 0.0, std, 1.0)
     return mean.astype(np.float32), std.astype(np.float32)
+
+
+TRIM_KAPPA = 5.0
+TRIM_ROUNDS = 3
+
+
+def target_stats(raw: np.ndarray, kappa: float = TRIM_KAPPA, rounds: int = TRIM_ROUNDS):
+    """Trimmed statistics of the targets: mean and std over all samples,
+    then `rounds` times over the samples whose every component lies within
+    kappa std of the mean (FP64).  The samples outside the last window
+    (plastic rearrangements: displacements that no smooth predictor can
+    follow) get weight 0 in the loss.  Returns FP32 mean, std and the
+    boolean mask of kept samples."""
+    x = np.asarray(raw, dtype=np.float64)
+    mean, std = _stats64(x)
+    mask = np.ones(len(x), dtype=bool)
+    for _ in range(rounds):
+        mask = np.all(np.abs(x - mean) <= kappa * std, axis=1)
+        mean, std = _stats64(x, mask)
+    mask = np.all(np.abs(x - mean) <= kappa * std, axis=1)
+    std = np.where(std > 0.0, std, 1.0)
+    return mean.astype(np.float32), std.astype(np.float32), mask
 
 
 def train(raw_feat: np.ndarray, raw_tgt: np.ndarray, model: MLP, perms: np.ndarray,
           batch: int = 4096, delta: float = 1.0, adam: AdamState | None = None,
           emulate: bool = True):
-    """Fit the network: statistics from the whole set, then for each epoch e
-    the samples in the order perms[e], cut into consecutive batches (the
-    last one may be short), one Adam step per batch.  Returns the mean batch
-    loss of every epoch."""
+    """Fit the network: feature statistics from the whole set, trimmed
+    target statistics (``target_stats``; trimmed samples get weight 0),
+    then for each epoch e the samples in the order perms[e], cut into
+    consecutive batches (the last one may be short), one Adam step per
+    batch.  Returns the mean batch loss of every epoch."""
     adam = adam or AdamState()
     model.feat_mean, model.feat_std = feature_stats(raw_feat)
-    tm, ts = feature_stats(raw_tgt)
+    tm, ts, keep = target_stats(raw_tgt)
     d = model.dim
     model.tgt_mean = np.zeros(3, np.float32)
     model.tgt_std = np.ones(3, np.float32)
@@ -326,7 +360,7 @@ def train(raw_feat: np.ndarray, raw_tgt: np.ndarray, model: MLP, perms: np.ndarr
         losses = []
         for b0 in range(0, len(p), batch):
             sel = p[b0:b0 + batch]
-            loss, g = loss_and_grads(z_all[sel], t_all[sel], model, delta, emulate)
+            loss, g = loss_and_grads(z_all[sel], t_all[sel], model, delta, emulate, keep[sel])
             adam_step(model, g, adam)
             losses.append(loss)
         hist.append(float(np.mean(losses)))

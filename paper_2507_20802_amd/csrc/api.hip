@@ -1126,13 +1126,14 @@ namespace {
 // Device buffers of one training or gradient call (freed by the destructor).
 struct TrainBufs {
   uint16_t* z = nullptr;
-  float *t = nullptr, *stats = nullptr, *part = nullptr, *master = nullptr, *m = nullptr,
-        *v = nullptr, *grad = nullptr;
-  double *stat_part = nullptr, *loss = nullptr;
+  float *t = nullptr, *part = nullptr, *master = nullptr, *m = nullptr, *v = nullptr,
+        *grad = nullptr;
+  double *stats = nullptr, *stat_part = nullptr, *loss = nullptr;
   int32_t* order = nullptr;
+  uint8_t* keep = nullptr;
   MlpDev* mlp = nullptr;
   ~TrainBufs() {
-    void* ps[] = {z, t, stats, part, master, m, v, grad, stat_part, loss, order, mlp};
+    void* ps[] = {z, t, stats, part, master, m, v, grad, stat_part, loss, order, keep, mlp};
     for (void* p : ps)
       if (p) (void)hipFree(p);
   }
@@ -1142,8 +1143,9 @@ aqs_status train_alloc(TrainBufs& b, int64_t n, int32_t blocks, int32_t epochs, 
   auto al = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 256)); };
   if (al((void**)&b.z, sizeof(uint16_t) * kFeat * n) != hipSuccess ||
       al((void**)&b.t, sizeof(float) * 4 * n) != hipSuccess ||
-      al((void**)&b.stats, sizeof(float) * 2 * 68 + sizeof(double) * 68) != hipSuccess ||
-      al((void**)&b.stat_part, sizeof(double) * 64 * 256) != hipSuccess ||
+      al((void**)&b.stats, sizeof(double) * 2 * 68) != hipSuccess ||
+      al((void**)&b.stat_part, sizeof(double) * 65 * 256) != hipSuccess ||
+      al((void**)&b.keep, sizeof(uint8_t) * n) != hipSuccess ||
       al((void**)&b.part, sizeof(float) * (size_t)(kNumParams + 1) * blocks) != hipSuccess ||
       al((void**)&b.master, sizeof(float) * kNumParams) != hipSuccess ||
       al((void**)&b.loss, sizeof(double) * std::max(epochs, 1)) != hipSuccess ||
@@ -1294,6 +1296,7 @@ aqs_status aqs_mlp_train(const aqs_train_params* p, int64_t n, const float* feat
   a.t = b.t;
   a.stat_part = b.stat_part;
   a.stats = b.stats;
+  a.keep = b.keep;
   a.delta = p->huber_delta;
   a.part = b.part;
   a.master = b.master;

@@ -65,7 +65,9 @@ struct LearnArgs {
   double max_move;          // largest accepted |dgamma u_hat| (sigma_AA)
 };
 
-constexpr int kLearnParts = 6;   // sum u_hat (3), max |u_hat|^2, non-finite, max displacement
+constexpr int kLearnParts = 6;
+constexpr double kTrimKappa = 5.0;  // target window of the trimmed statistics, in std
+constexpr int kTrimRounds = 3;   // sum u_hat (3), max |u_hat|^2, non-finite, max displacement
 
 // mode 0: slots in PH_LDESC, standardised BF16 features into zbuf;
 // mode 1: every slot of the table, raw FP32 features into out[id * 64 + f];
@@ -92,8 +94,9 @@ struct TrainArgs {
   int32_t dim;
   uint16_t* z;              // [n][64] standardised BF16 features
   float* t;                 // [n][4] standardised targets
-  double* stat_part;        // [blocks][2 * 68] partial sums
-  float* stats;             // mean[68], std[68] (64 features then 4 target columns)
+  double* stat_part;        // [blocks][64] partial sums, then [blocks] sample counts
+  double* stats;            // FP64 mean[68], std[68] (64 features then 4 target columns)
+  uint8_t* keep;            // per sample: 1 = in the loss (trimmed target statistics)
   const int32_t* order;     // sample order of the epoch
   int64_t b0;               // first position of the batch in order
   int32_t rows;             // samples in the batch

@@ -422,48 +422,77 @@ __global__ __launch_bounds__(kBlock) void k_ltargets(const Geom* geom, int ra, i
 // ---------------------------------------------------------------------------
 // Training.
 
-// Column sums of x ([n][ld], columns c < C) over row chunks, FP64; pass 1
-// sums (x - mean)^2 with the FP64 mean of pass 0.
+// Column sums of x ([n][ld], columns c < C) over row chunks, FP64, over the
+// rows with keep[r] = 1 (all rows if keep is null); pass 1 (mean given)
+// sums (x - mean)^2.  part[blk * 64 + c]; the chunk's row count at
+// part[kStatBlocks * 64 + blk].
+constexpr int kStatBlocks = 256;
+
 __global__ __launch_bounds__(kBlock) void k_colsum(const float* x, int64_t n, int C, int ld,
-                                                   const double* mean, double* part) {
+                                                   const double* mean, const uint8_t* keep,
+                                                   double* part) {
   const int tid = threadIdx.x;
   const int cols = (C > 4) ? 64 : 4;
   const int col = tid % cols, rg = tid / cols, ngr = kBlock / cols;
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(n, r0 + chunk);
-  double s = 0.0;
+  double s = 0.0, cnt = 0.0;
   if (col < C) {
     const double mu = mean ? mean[col] : 0.0;
     for (int64_t r = r0 + rg; r < r1; r += ngr) {
+      if (keep && !keep[r]) continue;
       const double v = (double)x[r * ld + col];
       s += mean ? (v - mu) * (v - mu) : v;
+      cnt += 1.0;
     }
   }
-  __shared__ double sh[kBlock];
+  __shared__ double sh[kBlock], shc[kBlock];
   sh[tid] = s;
+  shc[tid] = cnt;
   __syncthreads();
   if (tid < cols && tid < C) {
-    double t = 0.0;
-    for (int g = 0; g < ngr; ++g) t += sh[g * cols + tid];
+    double t = 0.0, tc = 0.0;
+    for (int g = 0; g < ngr; ++g) {
+      t += sh[g * cols + tid];
+      tc += shc[g * cols + tid];
+    }
     part[(int64_t)blockIdx.x * 64 + tid] = t;
+    if (tid == 0) part[(int64_t)kStatBlocks * 64 + blockIdx.x] = tc;
   }
 }
 
 // Combine the chunk sums in chunk order: pass 0 -> FP64 mean; pass 1 ->
-// FP32 mean and population std (1 where the spread is zero).
-__global__ void k_colfin(const double* part, int nblk, int C, int64_t n, int pass, double* mean64,
-                         float* fmean, float* fstd) {
+// FP64 std (population) and the FP32 mean and std of the network (std 1
+// where the spread is zero).
+__global__ void k_colfin(const double* part, int nblk, int C, int pass, double* mean64,
+                         double* std64, float* fmean, float* fstd) {
   const int c = threadIdx.x;
   if (c >= C) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * 64 + c];
+  double s = 0.0, cnt = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    s += part[(int64_t)b * 64 + c];
+    cnt += part[(int64_t)kStatBlocks * 64 + b];
+  }
   if (pass == 0) {
-    mean64[c] = s / (double)n;
+    mean64[c] = s / cnt;
   } else {
-    const double sd = sqrt(s / (double)n);
+    const double sd = sqrt(s / cnt);
+    std64[c] = sd;
     fmean[c] = (float)mean64[c];
     fstd[c] = (float)(sd > 0.0 ? sd : 1.0);
   }
+}
+
+// keep[r] = 1 if every component of sample r lies within kappa std of the mean.
+__global__ __launch_bounds__(kBlock) void k_trim(const float* t, int64_t n, int C,
+                                                 const double* mean64, const double* std64,
+                                                 double kappa, uint8_t* keep) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n) return;
+  bool in = true;
+  for (int c = 0; c < C; ++c)
+    in = in && fabs((double)t[r * C + c] - mean64[c]) <= kappa * std64[c];
+  keep[r] = in ? 1 : 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_tprep(TrainArgs a) {
@@ -572,7 +601,7 @@ __global__ __launch_bounds__(kBlock) void k_tfb(TrainArgs a) {
   for (int i = 0; i < 4; ++i) {
     const int row = blockIdx.x * 64 + rw + 4 * lg + i;
     float gv = 0.0f;
-    if (c < a.dim && row < a.rows) {
+    if (c < a.dim && row < a.rows && (!a.keep || a.keep[a.order[a.b0 + row]])) {
       const int64_t s = a.order[a.b0 + row];
       const float e = (y[i] + M->b3[c]) - a.t[s * 4 + c];
       const float ae = fabsf(e);
@@ -779,28 +808,31 @@ void launch_ltargets(const Geom* geom, int32_t ra, int32_t rb, int32_t n, const 
                        shear, Lx, Ly, Lz, tilt_b, out);
 }
 
-constexpr int kStatBlocks = 256;
-
 void launch_train_stats(const TrainArgs& a, hipStream_t s) {
-  // stats layout: [0, 68) FP32 means, [68, 136) FP32 stds, then 68 FP64 means
-  double* mean64 = reinterpret_cast<double*>(a.stats + 2 * 68);
+  double* mean64 = a.stats;
+  double* std64 = a.stats + 68;
   const int nb = (int)std::min<int64_t>(kStatBlocks, std::max<int64_t>(1, (a.n + 255) / 256));
-  hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(kBlock), 0, s, a.feat, a.n, kFeat, kFeat,
-                     (const double*)nullptr, a.stat_part);
-  hipLaunchKernelGGL(k_colfin, dim3(1), dim3(64), 0, s, a.stat_part, nb, kFeat, a.n, 0, mean64,
-                     (float*)nullptr, (float*)nullptr);
-  hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(kBlock), 0, s, a.feat, a.n, kFeat, kFeat,
-                     (const double*)mean64, a.stat_part);
-  hipLaunchKernelGGL(k_colfin, dim3(1), dim3(64), 0, s, a.stat_part, nb, kFeat, a.n, 1, mean64,
-                     a.mlp->fmean, a.mlp->fstd);
-  hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(kBlock), 0, s, a.tgt, a.n, a.dim, a.dim,
-                     (const double*)nullptr, a.stat_part);
-  hipLaunchKernelGGL(k_colfin, dim3(1), dim3(64), 0, s, a.stat_part, nb, a.dim, a.n, 0,
-                     mean64 + 64, (float*)nullptr, (float*)nullptr);
-  hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(kBlock), 0, s, a.tgt, a.n, a.dim, a.dim,
-                     (const double*)(mean64 + 64), a.stat_part);
-  hipLaunchKernelGGL(k_colfin, dim3(1), dim3(64), 0, s, a.stat_part, nb, a.dim, a.n, 1,
-                     mean64 + 64, a.mlp->tmean, a.mlp->tstd);
+  auto stats = [&](const float* x, int C, int off, const uint8_t* keep, float* fm, float* fs) {
+    hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(kBlock), 0, s, x, a.n, C, C, (const double*)nullptr,
+                       keep, a.stat_part);
+    hipLaunchKernelGGL(k_colfin, dim3(1), dim3(64), 0, s, a.stat_part, nb, C, 0, mean64 + off,
+                       std64 + off, fm, fs);
+    hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(kBlock), 0, s, x, a.n, C, C,
+                       (const double*)(mean64 + off), keep, a.stat_part);
+    hipLaunchKernelGGL(k_colfin, dim3(1), dim3(64), 0, s, a.stat_part, nb, C, 1, mean64 + off,
+                       std64 + off, fm, fs);
+  };
+  stats(a.feat, kFeat, 0, nullptr, a.mlp->fmean, a.mlp->fstd);
+  // targets: trimmed statistics; the final window decides which samples train
+  stats(a.tgt, a.dim, 64, nullptr, a.mlp->tmean, a.mlp->tstd);
+  const unsigned tb = (unsigned)((a.n + kBlock - 1) / kBlock);
+  for (int r = 0; r < kTrimRounds; ++r) {
+    hipLaunchKernelGGL(k_trim, dim3(tb), dim3(kBlock), 0, s, a.tgt, a.n, a.dim,
+                       (const double*)(mean64 + 64), (const double*)(std64 + 64), kTrimKappa, a.keep);
+    stats(a.tgt, a.dim, 64, a.keep, a.mlp->tmean, a.mlp->tstd);
+  }
+  hipLaunchKernelGGL(k_trim, dim3(tb), dim3(kBlock), 0, s, a.tgt, a.n, a.dim,
+                     (const double*)(mean64 + 64), (const double*)(std64 + 64), kTrimKappa, a.keep);
 }
 
 void launch_train_prep(const TrainArgs& a, hipStream_t s) {

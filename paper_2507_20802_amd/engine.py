@@ -265,7 +265,7 @@ class Engine:
         if out is None:
             out = torch.empty((rows, cols), dtype=torch.float32, device=self.device)
         if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() < rows * cols \
-                or out.device != self.device:
+                or not out.is_cuda:
             raise ValueError("output must be a contiguous float32 tensor on the engine's device")
         return out
 

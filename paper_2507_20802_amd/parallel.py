@@ -56,6 +56,7 @@ class GlassRun:
     rounds: List[dict] = field(default_factory=list)
     decisions: List[Decision] = field(default_factory=list)
     step_iters: List[int] = field(default_factory=list)     # FIRE iterations of every fine step computed
+    step_starts: List[int] = field(default_factory=list)    # start used by every fine step (0/1/2)
     accepted_iters: List[int] = field(default_factory=list)  # ... of the accepted fine steps
     anchor_iters: List[int] = field(default_factory=list)    # anchor minimisations
     energies: List[float] = field(default_factory=list)      # accepted trajectory E (per accepted step)
@@ -142,6 +143,7 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
                     g.statuses_ok = False
                 g.anchor_iters.append(int(r["iters"][0]))
                 g.step_iters.extend(int(x) for x in r["iters"][1: ln + 1])
+                g.step_starts.extend(int(x) for x in r["start"][1: ln + 1])
                 g.computed_steps += ln
                 if i <= last:
                     g.accepted_iters.extend(int(x) for x in r["iters"][1: ln + 1])

@@ -129,6 +129,7 @@ def test_training_steps_match_oracle():
     torch = _torch()
     dim, n = 2, 2500
     x, y = _train_set(dim, n, 7)
+    y[::97] += 500.0    # plastic jumps: trimmed out of the statistics and the loss
     init = S.mlp_init(dim, 304)
     orders = S.epoch_orders(n, 1, 305)
     m = Lr.mlp_from_arrays(dim, init)
@@ -140,13 +141,15 @@ def test_training_steps_match_oracle():
     assert np.allclose(got["feat_mean"], m.feat_mean, rtol=1e-6, atol=1e-7)
     assert np.allclose(got["feat_std"], m.feat_std, rtol=1e-6)
     assert np.allclose(got["tgt_mean"], m.tgt_mean[:dim], rtol=1e-6, atol=1e-7)
+    assert np.allclose(got["tgt_std"], m.tgt_std[:dim], rtol=1e-6)
+    assert np.all(m.tgt_std[:dim] < 10.0)   # the jumps are out of the statistics
     assert abs(hist[0] - hist_ref[0]) <= 1e-4 * abs(hist_ref[0])
     for k in Lr.MLP.PARAMS:
         d = np.abs(got[k] - getattr(m, k))
         # Adam moves every weight by about lr per step; rounding can only flip
         # the sign of steps whose gradient is at the rounding level
         assert d.max() <= 6.1e-3, (k, d.max())
-        assert np.mean(d > 1e-6) < 0.02, (k, np.mean(d > 1e-6))
+        assert np.mean(d > 1e-5) < 0.01, (k, np.mean(d > 1e-5))
 
 
 def test_training_learns_and_is_deterministic():

@@ -257,3 +257,18 @@ def test_learned_start_rules():
     Ex, Fx = O.energy_forces(x, types, H, POT)[:2]
     assert Ex <= Ep and np.sqrt((Fx ** 2).sum(1)).max() <= np.sqrt((Fp ** 2).sum(1)).max()
     assert which in (Lr.LEARNED, Lr.FALLBACK)
+
+
+def test_trimmed_target_statistics_drop_plastic_outliers():
+    """Gaussian targets plus a few huge jumps: the trimmed statistics are
+    those of the Gaussian part and exactly the jumps are left out."""
+    rng = S.rng_for(106)
+    t = rng.normal(size=(20000, 3)) * np.array([2.0, 0.5, 1.0]) + np.array([0.3, -1.0, 0.0])
+    jumps = rng.choice(20000, 25, replace=False)
+    t[jumps] += rng.choice([-1, 1], size=(25, 3)) * 4000.0
+    mean, std, keep = Lr.target_stats(t)
+    assert set(np.nonzero(~keep)[0]) == set(jumps)
+    assert np.allclose(mean, [0.3, -1.0, 0.0], atol=0.05)
+    assert np.allclose(std, [2.0, 0.5, 1.0], rtol=0.03)
+    full = Lr.feature_stats(t)[1]
+    assert np.all(full > 50 * std)   # the untrimmed std is useless
