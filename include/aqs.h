@@ -95,8 +95,7 @@ typedef struct {
   int32_t use_graph;        /* 1: replay each block of iterations as a hipGraph */
   int32_t max_chain_steps;  /* largest n_steps accepted by aqs_minimize_batch; 0 = 1024 */
   int32_t threads_per_atom; /* force kernel: 1, 2, 4 or 8 lanes per atom; 0 = 2 */
-  int32_t learn_every;      /* learned start: FIRE iterations between launches of the
-                               descriptor / network kernels; 0 = 8 */
+  int32_t pad_;
 } aqs_tuning;
 
 /* One record per minimisation of a chain (index 0 = the first minimisation,

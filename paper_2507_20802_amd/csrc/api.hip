@@ -48,7 +48,7 @@ double rc_max_of(const aqs_potential* p) {
 
 struct Tune {
   double skin;
-  int max_nb, block_iters, use_graph, log_cap, tpa, learn_every;
+  int max_nb, block_iters, use_graph, log_cap, tpa;
 };
 
 Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
@@ -60,7 +60,6 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   r.log_cap = ((t && t->max_chain_steps > 0) ? t->max_chain_steps : 1024) + 1;
   const int tp = t ? t->threads_per_atom : 0;
   r.tpa = (tp == 1 || tp == 2 || tp == 4 || tp == 8) ? tp : 2;
-  r.learn_every = (t && t->learn_every > 0) ? t->learn_every : 8;
   return r;
 }
 
@@ -86,7 +85,7 @@ struct Layout {
   size_t o_geom, o_state, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
       o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl,
       o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_evals, o_xref4, o_ftbl, o_ttbl, o_thdr, o_truns, o_sel,
-      o_zbuf, o_lpart, o_mlp, o_mlpw;
+      o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl, o_lftbl, o_lsel;
   int64_t atoms = 0;      // padded atoms over all slots
   int64_t nb_entries = 0;
   int32_t blocks = 0;
@@ -188,6 +187,9 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_lpart = take(sizeof(double) * kLearnParts * ((size_t)lo.blocks + 8));
   lo.o_mlp = take(sizeof(MlpDev));
   lo.o_mlpw = take(sizeof(float) * kNumParams);
+  lo.o_ltbl = take(sizeof(int2) * ((size_t)lo.blocks + 8));
+  lo.o_lftbl = take(sizeof(int2) * ((size_t)lo.tiles + 8));
+  lo.o_lsel = take(sizeof(int32_t) * n_rep);
   lo.total = off;
   return AQS_OK;
 }
@@ -236,6 +238,8 @@ struct aqs_ctx {
   double* lpart;
   MlpDev* mlp;
   float* mlpw;
+  int2 *ltbl, *lftbl;        // launch tables of the slots getting a learned start
+  int32_t* lsel_d;
   int mlp_dim = 0;           // 0: no network loaded
   double rd[4], rd2[4], dirs[16][3];
   // host mirrors
@@ -249,6 +253,8 @@ struct aqs_ctx {
   bool ftable_stale = false;       // a rebuild changed the tiles of the selection
   // pinned staging of host-to-device uploads (one use per synchronisation)
   int2 *h_tbl = nullptr, *h_ftbl = nullptr, *h_tbl2 = nullptr, *h_ttbl = nullptr;
+  int2 *h_ltbl = nullptr, *h_lftbl = nullptr;
+  int32_t* h_lsel = nullptr;
   int32_t *h_reps = nullptr, *h_nc3 = nullptr, *h_over = nullptr, *h_sel = nullptr;
   double* h_dg = nullptr;
   // profiling
@@ -294,6 +300,11 @@ IterArgs iter_args(aqs_ctx* c) {
 LearnArgs learn_args(aqs_ctx* c, int mode, float* out = nullptr) {
   LearnArgs a{};
   a.blocks = c->tbl;
+  a.ftiles = c->ftbl;
+  a.thdr = c->thdr;
+  a.truns = c->truns;
+  a.nbl = c->nbl;
+  a.nbc = c->nbc;
   a.sel = c->sel_d;
   a.nsel = (int32_t)c->cur_sel.size();
   a.mode = mode;
@@ -320,10 +331,39 @@ LearnArgs learn_args(aqs_ctx* c, int mode, float* out = nullptr) {
   return a;
 }
 
+std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, int per_block = 1);
+std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel);
+
+// Learned start of the slots waiting in PH_LDESC (known from the last
+// state read-back): descriptors, network, plain start and the checks, with
+// launch tables over exactly those slots.
+aqs_status learned_group(aqs_ctx* c, const std::vector<int32_t>& ls) {
+  const std::vector<int2> tb = make_table(c, ls);
+  const std::vector<int2> ft = make_tile_table(c, ls);
+  std::copy(tb.begin(), tb.end(), c->h_ltbl);
+  std::copy(ft.begin(), ft.end(), c->h_lftbl);
+  std::copy(ls.begin(), ls.end(), c->h_lsel);
+  HIPCHK(hipMemcpyAsync(c->ltbl, c->h_ltbl, sizeof(int2) * tb.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->lftbl, c->h_lftbl, sizeof(int2) * ft.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(c->lsel_d, c->h_lsel, sizeof(int32_t) * ls.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  LearnArgs la = learn_args(c, 0);
+  la.blocks = c->ltbl;
+  la.ftiles = c->lftbl;
+  la.sel = c->lsel_d;
+  la.nsel = (int32_t)ls.size();
+  launch_ldesc(la, (int32_t)ft.size(), c->dim, c->stream);
+  launch_lmlp(la, (int32_t)tb.size(), c->dim, c->stream);
+  launch_lctl(la, c->stream);
+  HIPCHK(hipGetLastError());
+  return AQS_OK;
+}
+
 // Launch table over the blocks of the given slots, in an order that gives
 // each of the 8 XCDs (hardware block b runs on XCD b mod 8) a contiguous run
 // of blocks, so neighbouring tiles share that XCD's L2.
-std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, int per_block = 1) {
+std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, int per_block) {
   std::vector<int2> logical;
   for (int r : sel) {
     const Geom& g = c->lo.geom[r];
@@ -499,7 +539,7 @@ aqs_status set_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
 
 void free_pinned(aqs_ctx* c) {
   void* ps[] = {c->h_state, c->h_tbl, c->h_ftbl, c->h_tbl2, c->h_ttbl, c->h_reps, c->h_sel,
-                c->h_nc3, c->h_over, c->h_dg};
+                c->h_nc3, c->h_over, c->h_dg, c->h_ltbl, c->h_lftbl, c->h_lsel};
   for (void* p : ps)
     if (p) (void)hipHostFree(p);
   c->h_state = nullptr;
@@ -634,6 +674,9 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->lpart = at<double>(w, lo.o_lpart);
   c->mlp = at<MlpDev>(w, lo.o_mlp);
   c->mlpw = at<float>(w, lo.o_mlpw);
+  c->ltbl = at<int2>(w, lo.o_ltbl);
+  c->lftbl = at<int2>(w, lo.o_lftbl);
+  c->lsel_d = at<int32_t>(w, lo.o_lsel);
 
   const size_t tcap = std::max((size_t)lo.blocks, (size_t)lo.tiles) + 16;
   if (hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) != hipSuccess ||
@@ -645,7 +688,10 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
       hipHostMalloc((void**)&c->h_sel, sizeof(int32_t) * n_rep, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_nc3, sizeof(int32_t) * kGridInts * n_rep, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_over, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_dg, sizeof(double) * n_rep, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->h_dg, sizeof(double) * n_rep, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_ltbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_lftbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_lsel, sizeof(int32_t) * n_rep, hipHostMallocDefault) != hipSuccess) {
     free_pinned(c);
     delete c;
     return fail(AQS_EHIP, "hipHostMalloc of the host staging buffers failed");
@@ -905,14 +951,18 @@ aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int
         c->ev.push_back(e);
       }
     }
-    const LearnArgs la = learn_args(c, 0);
-    for (int it = 0; it < M; ++it) {
-      // slots waiting in PH_LDESC get descriptors, network and plain start
-      if (start_mode == AQS_START_LEARNED && it % c->tn.learn_every == 0) {
-        launch_ldesc(la, c->cur_nblk, c->dim, c->stream);
-        launch_lmlp(la, c->cur_nblk, c->dim, c->stream);
-        launch_lctl(la, c->stream);
+    if (start_mode == AQS_START_LEARNED) {
+      // slots that finished a minimisation since the last read-back wait in
+      // PH_LDESC: descriptors, network and plain start for them now
+      std::vector<int32_t> ls;
+      for (int r : sel)
+        if (c->h_state[r].phase == PH_LDESC) ls.push_back(r);
+      if (!ls.empty()) {
+        st = learned_group(c, ls);
+        if (st) return st;
       }
+    }
+    for (int it = 0; it < M; ++it) {
       // events bracket the force kernel alone and the update kernel alone
       if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 0], c->stream));
       launch_force(a, c->cur_ntiles, c->dim, c->stream);
@@ -1225,7 +1275,7 @@ aqs_status aqs_learned_features(aqs_ctx* c, int32_t rep, float* feat) {
   if (!c || !feat) return fail(AQS_EINVAL, "null argument");
   aqs_status st = prepare_single(c, rep);
   if (st) return st;
-  launch_ldesc(learn_args(c, 1, feat), c->cur_nblk, c->dim, c->stream);
+  launch_ldesc(learn_args(c, 1, feat), c->cur_ntiles, c->dim, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   return AQS_OK;
@@ -1236,7 +1286,7 @@ aqs_status aqs_learned_predict(aqs_ctx* c, int32_t rep, float* u_hat) {
   if (c->mlp_dim != c->dim) return fail(AQS_ESTATE, "no network loaded");
   aqs_status st = prepare_single(c, rep);
   if (st) return st;
-  launch_ldesc(learn_args(c, 2), c->cur_nblk, c->dim, c->stream);
+  launch_ldesc(learn_args(c, 2), c->cur_ntiles, c->dim, c->stream);
   launch_lmlp(learn_args(c, 1, u_hat), c->cur_nblk, c->dim, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));

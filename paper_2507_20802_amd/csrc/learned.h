@@ -43,6 +43,11 @@ struct MlpDev {
 // Arguments of the descriptor / inference kernels of the engine.
 struct LearnArgs {
   const int2* blocks;       // (slot, 256-atom block) launch table
+  const int2* ftiles;       // (slot, force tile) launch table
+  const void* thdr;         // TileHdr per force tile
+  const void* truns;        // TileRun x kRuns per force tile
+  const uint32_t* nbl;      // neighbour lists (engine.h)
+  const int32_t* nbc;
   const int32_t* sel;       // slots of the running selection
   int32_t nsel;
   int32_t mode;             // see the launchers
@@ -69,10 +74,11 @@ constexpr int kLearnParts = 6;
 constexpr double kTrimKappa = 5.0;  // target window of the trimmed statistics, in std
 constexpr int kTrimRounds = 3;   // sum u_hat (3), max |u_hat|^2, non-finite, max displacement
 
+// Over the force-tile table (a.ftiles, ntiles entries):
 // mode 0: slots in PH_LDESC, standardised BF16 features into zbuf;
 // mode 1: every slot of the table, raw FP32 features into out[id * 64 + f];
 // mode 2: every slot of the table, standardised BF16 features into zbuf.
-void launch_ldesc(const LearnArgs& a, int32_t nblk, int32_t dim, hipStream_t s);
+void launch_ldesc(const LearnArgs& a, int32_t ntiles, int32_t dim, hipStream_t s);
 // mode 0: slots in PH_LDESC: u_hat into dl, partials, snapshot, plain start;
 // mode 1: every slot of the table: u_hat into out[id * d + c] (FP32).
 void launch_lmlp(const LearnArgs& a, int32_t nblk, int32_t dim, hipStream_t s);

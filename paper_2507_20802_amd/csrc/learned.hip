@@ -17,9 +17,9 @@
 // 16-byte load.
 #include <hip/hip_runtime.h>
 
-#include "cellgeom.h"
 #include "kernels.h"
 #include "learned.h"
+#include "tiles.h"
 
 namespace aqs {
 
@@ -75,105 +75,140 @@ __device__ __forceinline__ void block_reduce_fixed(double* v, const int* op, dou
 }
 
 constexpr double kMuLo = 0.6, kMuHi = 2.5;
+// e^-(b - 1/2), b = 0..23 (entry 0 unused)
+__constant__ double kGaussStep[24] = {
+    1.6487212707001282, 0.6065306597126334, 0.22313016014842982, 0.0820849986238988,
+    0.0301973834223185, 0.011108996538242306, 0.004086771438464067, 0.0015034391929775724,
+    0.0005530843701478336, 0.00020346836901064417, 7.48518298877006e-05, 2.7536449349747158e-05,
+    1.013009359863071e-05, 3.726653172078671e-06, 1.3709590863840845e-06, 5.04347662567888e-07,
+    1.8553913626159784e-07, 6.82560337633487e-08, 2.510999155743982e-08, 9.237449661970594e-09,
+    3.398267819495071e-09, 1.2501528663867426e-09, 4.5990553786523166e-10, 1.6918979226151304e-10};
 
 // ---------------------------------------------------------------------------
-// Descriptors: one thread per atom over the 3^d neighbouring cells.
+// Descriptors, one block per force tile (tiles.h): the tile's halo is staged
+// in LDS as for the force kernel and kLDescTPA lanes per atom walk its
+// neighbour list (every pair within the pair cutoff r_d is in the list).
 // Radial: species of j x 24 Gaussians exp(-(r - mu_b)^2 / (2 w^2)) f_c(r);
-// angular: f_c(r) max(0, n_k . r_ij / r)^2; f_c(r) = (cos(pi r / r_d) + 1)/2,
-// r_d the pair's cutoff.  FP64 sums in the order of the cell scan.
+// angular: f_c(r) max(0, n_k . r_ij / r)^2; f_c(r) = (cos(pi r / r_d) + 1)/2.
+// FP64 sums; the lanes' partial sums are combined by a fixed butterfly.
+constexpr int kLDescTPA = 4;
+
+template <int D>
+__device__ __forceinline__ void desc_pair(double dx, double dy, double dz, int pt, int tj,
+                                          const LearnArgs& a, double w, double* acc) {
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  if (!(r2 < a.rd2[pt])) return;
+  const double r = sqrt(r2);
+  const double fc = 0.5 * (cos(M_PI * r / a.rd[pt]) + 1.0);
+  const double s1 = (tj == 1) ? 1.0 : 0.0, s0 = 1.0 - s1;
+  // Gaussians by recurrence: with x = (r - mu_0) / w,
+  // g_b / g_(b-1) = e^x e^-(b - 1/2), so two exponentials per pair
+  const double x0 = (r - kMuLo) / w;
+  const double ex = exp(x0);
+  double gb = exp(-0.5 * (x0 * x0)) * fc;
+  acc[0] += s0 * gb;
+  acc[24] += s1 * gb;
+#pragma unroll
+  for (int b = 1; b < 24; ++b) {
+    gb *= ex * kGaussStep[b];
+    acc[b] += s0 * gb;
+    acc[24 + b] += s1 * gb;
+  }
+  const double ux = dx / r, uy = dy / r, uz = (D == 3) ? dz / r : 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    double cth = ux * a.dirs[k][0] + uy * a.dirs[k][1];
+    if (D == 3) cth += uz * a.dirs[k][2];
+    cth = fmax(cth, 0.0);
+    acc[48 + k] += fc * (cth * cth);
+  }
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_ldesc(LearnArgs a) {
-  const int2 bt = a.blocks[blockIdx.x];
-  if (bt.x < 0) return;
-  const State* st = a.state + bt.x;
+  const int2 bt = a.ftiles[blockIdx.x];
+  const int rep = bt.x;
+  if (rep < 0) return;
+  const State* st = a.state + rep;
   if (a.mode == 0 && st->phase != PH_LDESC) return;
-  const Geom g = a.geom[bt.x];
-  const int li = bt.y * kBlock + threadIdx.x;
-  if (li >= g.n) return;
+  if (bt.y >= st->ntiles) return;
+  const Geom g = a.geom[rep];
+  const int tid = threadIdx.x;
+  constexpr int CAP = (D == 3) ? kHaloCap3 : kHaloCap2;
+  __shared__ double hx[CAP];
+  __shared__ double hy[CAP];
+  __shared__ double hz[D == 3 ? CAP : 1];
+  __shared__ double sh[32][4];
+  __shared__ TileRun runs[kRuns];
+  const int64_t tix = g.tile_off + bt.y;
+  const TileHdr hdr = reinterpret_cast<const TileHdr*>(a.thdr)[tix];
   const double t = strain_of(st->k, g.dgamma) * g.L[1];
-  const int nc[3] = {st->nc[0], st->nc[1], st->nc[2]};
+  if (tid < hdr.nruns) runs[tid] = reinterpret_cast<const TileRun*>(a.truns)[tix * kRuns + tid];
+  if (tid >= 32 && tid < 32 + 27) code_shift(tid - 32, g.L[0], g.L[1], g.L[2], t, sh[tid - 32]);
+  __syncthreads();
   const double4* P = a.pos4 + g.atom_off;
-  const int32_t* cs = a.cell_start + g.cell_off;
-  const double4 pi = P[li];
-  const int ti = (int)pi.w;
+  const bool lds = hdr.halo >= 0;
+  if (lds) stage_halo<D, CAP>(hdr, runs, sh, P, hx, hy, hz);
+  __syncthreads();
   const double w = (kMuHi - kMuLo) / 23.0;
-  const double two_w2 = 2.0 * w * w;
-  double acc[kFeat];
+  constexpr int per = kBlock / kLDescTPA;
+  const int sub = tid % kLDescTPA;
+  for (int b0 = hdr.a0; b0 < hdr.a1; b0 += per) {
+    const int li = b0 + tid / kLDescTPA;
+    // every lane of the wavefront runs the loop; lanes past the tile do no pairs
+    const bool live = li < hdr.a1;
+    const int lic = live ? li : hdr.a0;
+    const int64_t gi = g.atom_off + lic;
+    const double4 pi = P[lic];
+    const int ti = (int)pi.w;
+    const int cnt = live ? a.nbc[gi] : 0;
+    const uint32_t* L = a.nbl + g.nb_off + lic;
+    double acc[kFeat];
 #pragma unroll
-  for (int f = 0; f < kFeat; ++f) acc[f] = 0.0;
-  int c3[3];
-  cell_of_pos<D>(g, nc, t, pi, c3);
-  const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
-  for (int dz = zlo; dz <= zhi; ++dz) {
-    int cz2 = c3[2] + dz, iz = 0;
-    if (D == 3) {
-      if (cz2 < 0) { cz2 += nc[2]; iz = -1; }
-      else if (cz2 >= nc[2]) { cz2 -= nc[2]; iz = 1; }
-    }
-    for (int dy = -1; dy <= 1; ++dy) {
-      int cy2 = c3[1] + dy, iy = 0;
-      if (cy2 < 0) { cy2 += nc[1]; iy = -1; }
-      else if (cy2 >= nc[1]) { cy2 -= nc[1]; iy = 1; }
-      for (int dx = -1; dx <= 1; ++dx) {
-        int cx = c3[0] + dx, ix = 0;
-        if (cx < 0) { cx += nc[0]; ix = -1; }
-        else if (cx >= nc[0]) { cx -= nc[0]; ix = 1; }
-        const bool self = (ix == 0 && iy == 0 && iz == 0 && dx == 0 && dy == 0 && dz == 0);
-        const double sx = (double)ix * g.L[0] + (double)iy * t;
-        const double sy = (double)iy * g.L[1];
-        const double sz = (double)iz * g.L[2];
-        const int c = (cz2 * nc[1] + cy2) * nc[0] + cx;
-        const int jb = cs[c], je = cs[c + 1];
-        for (int j = jb; j < je; ++j) {
-          if (self && j == li) continue;
-          const double4 pj = P[j];
-          const double ddx = (pj.x - pi.x) + sx;
-          const double ddy = (pj.y - pi.y) + sy;
-          const double ddz = (D == 3) ? (pj.z - pi.z) + sz : 0.0;
-          const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-          const int tj = (int)pj.w;
-          const int pt = 2 * ti + tj;
-          if (!(r2 < a.rd2[pt])) continue;
-          const double r = sqrt(r2);
-          const double fc = 0.5 * (cos(M_PI * r / a.rd[pt]) + 1.0);
-          const double s1 = (tj == 1) ? 1.0 : 0.0, s0 = 1.0 - s1;
-#pragma unroll
-          for (int b = 0; b < 24; ++b) {
-            const double e = r - (kMuLo + w * (double)b);
-            const double gb = exp(-(e * e) / two_w2) * fc;
-            acc[b] += s0 * gb;
-            acc[24 + b] += s1 * gb;
-          }
-          const double ux = ddx / r, uy = ddy / r, uz = (D == 3) ? ddz / r : 0.0;
-#pragma unroll
-          for (int k = 0; k < 16; ++k) {
-            double cth = ux * a.dirs[k][0] + uy * a.dirs[k][1];
-            if (D == 3) cth += uz * a.dirs[k][2];
-            cth = fmax(cth, 0.0);
-            acc[48 + k] += fc * (cth * cth);
-          }
-        }
+    for (int f = 0; f < kFeat; ++f) acc[f] = 0.0;
+    for (int k = sub; k < cnt; k += kLDescTPA) {
+      const uint32_t ent = L[(int64_t)k * g.npad];
+      const int tj = (ent >> 29) & 1;
+      double dx, dy, dz;
+      if (lds) {
+        const int h = (int)(ent & kIdxMask);
+        dx = hx[h] - pi.x;
+        dy = hy[h] - pi.y;
+        dz = (D == 3) ? hz[h] - pi.z : 0.0;
+      } else {
+        const double4 pj = P[ent & kIdxMask];
+        const int code = (int)((ent >> kCodeShift) & 31u);
+        dx = (pj.x - pi.x) + sh[code][0];
+        dy = (pj.y - pi.y) + sh[code][1];
+        dz = (D == 3) ? (pj.z - pi.z) + sh[code][2] : 0.0;
       }
+      desc_pair<D>(dx, dy, dz, 2 * ti + tj, tj, a, w, acc);
     }
-  }
-  if (a.mode == 1) {
-    float* o = a.out + (int64_t)a.id[g.atom_off + li] * kFeat;
 #pragma unroll
-    for (int f = 0; f < kFeat; ++f) o[f] = (float)acc[f];
-  } else {
-    uint16_t zz[kFeat];
+    for (int f = 0; f < kFeat; ++f) {
 #pragma unroll
-    for (int f = 0; f < kFeat; ++f)
-      zz[f] = f2bf(((float)acc[f] - a.mlp->fmean[f]) / a.mlp->fstd[f]);
-    uint4* o = reinterpret_cast<uint4*>(a.zbuf + (g.atom_off + li) * kFeat);
+      for (int off = 1; off < kLDescTPA; off <<= 1) acc[f] += __shfl_xor(acc[f], off, 64);
+    }
+    if (!live || sub != 0) continue;
+    if (a.mode == 1) {
+      float* o = a.out + (int64_t)a.id[gi] * kFeat;
 #pragma unroll
-    for (int q = 0; q < kFeat / 8; ++q) {
-      uint4 v;
-      v.x = zz[8 * q + 0] | ((uint32_t)zz[8 * q + 1] << 16);
-      v.y = zz[8 * q + 2] | ((uint32_t)zz[8 * q + 3] << 16);
-      v.z = zz[8 * q + 4] | ((uint32_t)zz[8 * q + 5] << 16);
-      v.w = zz[8 * q + 6] | ((uint32_t)zz[8 * q + 7] << 16);
-      o[q] = v;
+      for (int f = 0; f < kFeat; ++f) o[f] = (float)acc[f];
+    } else {
+      uint16_t zz[kFeat];
+#pragma unroll
+      for (int f = 0; f < kFeat; ++f)
+        zz[f] = f2bf(((float)acc[f] - a.mlp->fmean[f]) / a.mlp->fstd[f]);
+      uint4* o = reinterpret_cast<uint4*>(a.zbuf + gi * kFeat);
+#pragma unroll
+      for (int q = 0; q < kFeat / 8; ++q) {
+        uint4 v;
+        v.x = zz[8 * q + 0] | ((uint32_t)zz[8 * q + 1] << 16);
+        v.y = zz[8 * q + 2] | ((uint32_t)zz[8 * q + 3] << 16);
+        v.z = zz[8 * q + 4] | ((uint32_t)zz[8 * q + 5] << 16);
+        v.w = zz[8 * q + 6] | ((uint32_t)zz[8 * q + 7] << 16);
+        o[q] = v;
+      }
     }
   }
 }
@@ -775,12 +810,12 @@ __global__ __launch_bounds__(kBlock) void k_mlp_sync(const float* master, MlpDev
 
 }  // namespace
 
-void launch_ldesc(const LearnArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
-  if (nblk <= 0) return;
+void launch_ldesc(const LearnArgs& a, int32_t ntiles, int32_t dim, hipStream_t s) {
+  if (ntiles <= 0) return;
   if (dim == 3)
-    hipLaunchKernelGGL(k_ldesc<3>, dim3(nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_ldesc<3>, dim3(ntiles), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(k_ldesc<2>, dim3(nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_ldesc<2>, dim3(ntiles), dim3(kBlock), 0, s, a);
 }
 
 void launch_lmlp(const LearnArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {

@@ -66,14 +66,6 @@ __device__ __forceinline__ void block_reduce(double* v, const int* op, double (*
 // box geometry: H = [[Lx, t, 0], [0, Ly, 0], [0, 0, Lz]], t = gamma Ly (Eq. 1,
 // Eq. 16).  Image code c = (ix+1) + 3 (iy+1) + 9 (iz+1); shift = H (ix,iy,iz).
 
-__device__ __forceinline__ void code_shift(int code, double Lx, double Ly, double Lz, double t,
-                                           double* s) {
-  const int ix = code % 3 - 1, iy = (code / 3) % 3 - 1, iz = code / 9 - 1;
-  s[0] = (double)ix * Lx + (double)iy * t;
-  s[1] = (double)iy * Ly;
-  s[2] = (double)iz * Lz;
-}
-
 __device__ __forceinline__ double slot_tilt(const Geom& g, const State* st) {
   return strain_of(st->k, g.dgamma) * g.L[1];
 }
@@ -485,40 +477,7 @@ __global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
     if (tid >= 64 && tid < 68) spp[tid - 64] = a.pp[tid - 64];
     __syncthreads();
     if (hdr.halo >= 0) {
-      // stage the halo: thread tid takes halo slots tid, tid + kBlock, ...;
-      // the run of a slot is found by binary search over the run offsets,
-      // then all of the thread's loads are issued before its LDS stores
-      const double4* P = a.pos4 + g.atom_off;
-      constexpr int SU = (CAP + kBlock - 1) / kBlock;
-      constexpr int SB = SU;  // slots per pass (loads in flight per thread)
-      for (int u0 = 0; u0 < SU; u0 += SB) {
-      double4 p[SB];
-      int rix[SB];
-#pragma unroll
-      for (int u = 0; u < SB; ++u) {
-        const int h = tid + (u0 + u) * kBlock;
-        rix[u] = -1;
-        if (h < hdr.halo) {
-          int lo = 0, hi = hdr.nruns - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (runs[mid].off <= h) lo = mid; else hi = mid - 1;
-          }
-          rix[u] = lo;
-          p[u] = P[runs[lo].src + (h - runs[lo].off)];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < SB; ++u) {
-        if (rix[u] >= 0) {
-          const int h = tid + (u0 + u) * kBlock;
-          const int code = runs[rix[u]].code;
-          hx[h] = p[u].x + sh[code][0];
-          hy[h] = p[u].y + sh[code][1];
-          if (D == 3) hz[h] = p[u].z + sh[code][2];
-        }
-      }
-      }
+      stage_halo<D, CAP>(hdr, runs, sh, a.pos4 + g.atom_off, hx, hy, hz);
       __syncthreads();
       if (we)
         force_tile<D, true, TPA, true>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, part);

@@ -83,6 +83,55 @@ __device__ __forceinline__ int run_of(int cx, int dx, int dy, int dz, int nc0) {
   return ((dz + 1) * 3 + (dy + 1)) * 3 + part;
 }
 
+// Image code c = (ix+1) + 3 (iy+1) + 9 (iz+1); shift = H (ix, iy, iz) for the
+// box H = [[Lx, t, 0], [0, Ly, 0], [0, 0, Lz]] (t = gamma Ly).
+__device__ __forceinline__ void code_shift(int code, double Lx, double Ly, double Lz, double t,
+                                           double* s) {
+  const int ix = code % 3 - 1, iy = (code / 3) % 3 - 1, iz = code / 9 - 1;
+  s[0] = (double)ix * Lx + (double)iy * t;
+  s[1] = (double)iy * Ly;
+  s[2] = (double)iz * Lz;
+}
+
+// Stage a tile's halo into LDS (image shifts sh[code] applied), by the whole
+// block of kBlock threads: thread tid takes halo slots tid, tid + kBlock, ...;
+// the run of a slot is found by binary search over the run offsets, then all
+// of the thread's loads are issued before its LDS stores.  The caller
+// synchronises the block afterwards.
+template <int D, int CAP>
+__device__ __forceinline__ void stage_halo(const TileHdr& hdr, const TileRun* runs,
+                                           const double (*sh)[4], const double4* P, double* hx,
+                                           double* hy, double* hz) {
+  const int tid = threadIdx.x;
+  constexpr int SU = (CAP + kBlock - 1) / kBlock;
+  double4 p[SU];
+  int rix[SU];
+#pragma unroll
+  for (int u = 0; u < SU; ++u) {
+    const int h = tid + u * kBlock;
+    rix[u] = -1;
+    if (h < hdr.halo) {
+      int lo = 0, hi = hdr.nruns - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (runs[mid].off <= h) lo = mid; else hi = mid - 1;
+      }
+      rix[u] = lo;
+      p[u] = P[runs[lo].src + (h - runs[lo].off)];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < SU; ++u) {
+    if (rix[u] >= 0) {
+      const int h = tid + u * kBlock;
+      const int code = runs[rix[u]].code;
+      hx[h] = p[u].x + sh[code][0];
+      hy[h] = p[u].y + sh[code][1];
+      if (D == 3) hz[h] = p[u].z + sh[code][2];
+    }
+  }
+}
+
 // Atom range of segment s of row `row` (rows cut into m segments).
 __device__ __forceinline__ void segment(const int* nc, int m, const int32_t* cs, int t, int& a0,
                                         int& a1, int& cy, int& cz) {

@@ -78,7 +78,6 @@ class Tuning:
     use_graph: int = 0
     max_chain_steps: int = 1024
     threads_per_atom: int = 0
-    learn_every: int = 0
 
     def to_c(self) -> aqs_tuning:
         t = aqs_tuning()
@@ -88,7 +87,6 @@ class Tuning:
         t.use_graph = self.use_graph
         t.max_chain_steps = self.max_chain_steps
         t.threads_per_atom = self.threads_per_atom
-        t.learn_every = self.learn_every
         return t
 
 
