@@ -172,6 +172,8 @@ def main() -> int:
     ap.add_argument("--train-steps", type=int, default=7, help="plain AQS steps of training data")
     ap.add_argument("--epochs", type=int, default=50)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-start reference rounds")
+    ap.add_argument("--only-plain", action="store_true", help="time the plain start only (no network)")
+    ap.add_argument("--skin", type=float, default=0.3, help="Verlet skin (sigma_AA)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -196,7 +198,7 @@ def main() -> int:
     s = S.uniform_glass_start(dim, n, 3, 0)
     nslots = parallel.slots_needed(1, P)
     ref_slot = nslots              # final r_star of the plain round, for the IS comparison
-    eng = Engine(dim, [n] * (nslots + 1), s.L, dg, pot=pot, fire=Fire(), tuning=Tuning())
+    eng = Engine(dim, [n] * (nslots + 1), s.L, dg, pot=pot, fire=Fire(), tuning=Tuning(skin=args.skin))
     glass = parallel.layout(1, P)[0]
     t0 = time.perf_counter()
     eng.set_replica(glass.star, s.types, s.pos, 0)
@@ -207,9 +209,11 @@ def main() -> int:
         return 1
     is_pos = eng.positions(glass.star)
     nb = in_cutoff_neighbours(is_pos, s.types, s.L, pot)
-    model, train_info = train_network(eng, dim, n, dg, glass.chains[0], glass.chains[1],
-                                      args.train_steps, args.epochs, 1)
-    eng.learned_load(model)
+    train_info = None
+    if not args.only_plain:
+        model, train_info = train_network(eng, dim, n, dg, glass.chains[0], glass.chains[1],
+                                          args.train_steps, args.epochs, 1)
+        eng.learned_load(model)
 
     def one_round(Kr, start):
         eng.set_replica(glass.star, s.types, is_pos, 0)
@@ -220,7 +224,8 @@ def main() -> int:
         torch.cuda.synchronize()
         return time.perf_counter() - t, out, g
 
-    forms = ([] if args.no_plain else [("plain", AQS_START_PLAIN)]) + [("learned", AQS_START_LEARNED)]
+    forms = ([] if args.no_plain else [("plain", AQS_START_PLAIN)]) + \
+        ([] if args.only_plain else [("learned", AQS_START_LEARNED)])
     for _ in range(args.warmup):
         for _, st in forms:
             one_round(args.warmup_K, st)
@@ -251,11 +256,12 @@ def main() -> int:
                            "all_converged": bool(ok), "rounds": rounds, "counters": eng.counters(),
                            "starts": {"plain": starts.count(0), "learned": starts.count(1),
                                       "fallback": starts.count(2)}}
-    lr = res_forms["learned"]
+    main_form = "plain" if args.only_plain else "learned"
+    lr = res_forms[main_form]
     cnt = lr["counters"]
     # inherent-structure agreement of the two forms: same decisions, same final r_star (Eq. 20)
     comparison = None
-    if "plain" in res_forms:
+    if "plain" in res_forms and "learned" in res_forms:
         pl = res_forms["plain"]
         same_dec = [r["decisions"] for r in lr["rounds"]] == [r["decisions"] for r in pl["rounds"]]
         eq, md, de = eng.compare(glass.star, ref_slot, 1e-4)   # r_star after the last round of each form
@@ -287,13 +293,15 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{dim}D binary LJ glass N={n}, Algorithm 1 round: P={P} chains x K={K} "
                                f"fine AQS steps, dgamma={dg:g}, dgamma_c={K * dg:g}, FIRE to max|F|<1e-10, "
-                               f"learned start (plain start timed alongside)",
+                               + ("plain start" if args.only_plain else
+                                  "learned start (plain start timed alongside)"),
                    "dim": dim, "n_atoms": n, "P": P, "K": K, "dgamma": dg},
         "computed_steps_per_s": lr["computed_steps_per_s"],
         "fire_iters_per_step": lr["fire_iters_per_step"],
         "all_converged": lr["all_converged"],
         "learned_start": {"starts": lr["starts"], "training": train_info},
-        "plain": {k: v for k, v in res_forms.get("plain", {}).items() if k != "counters"},
+        "plain": None if args.only_plain else
+        {k: v for k, v in res_forms.get("plain", {}).items() if k != "counters"},
         "learned_vs_plain": comparison,
         "quench_s": quench_s,
         "mean_neighbours_in_cutoff": nb,

@@ -85,7 +85,7 @@ struct Layout {
   size_t o_geom, o_state, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
       o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl,
       o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_evals, o_xref4, o_ftbl, o_ttbl, o_thdr, o_truns, o_sel,
-      o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl, o_lftbl, o_lsel;
+      o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl, o_lftbl, o_lsel, o_tord;
   int64_t atoms = 0;      // padded atoms over all slots
   int64_t nb_entries = 0;
   int32_t blocks = 0;
@@ -190,6 +190,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_ltbl = take(sizeof(int2) * ((size_t)lo.blocks + 8));
   lo.o_lftbl = take(sizeof(int2) * ((size_t)lo.tiles + 8));
   lo.o_lsel = take(sizeof(int32_t) * n_rep);
+  lo.o_tord = take(sizeof(int32_t) * A);
   lo.total = off;
   return AQS_OK;
 }
@@ -238,6 +239,7 @@ struct aqs_ctx {
   double* lpart;
   MlpDev* mlp;
   float* mlpw;
+  int32_t* tord;             // per tile: atoms by decreasing list length
   int2 *ltbl, *lftbl;        // launch tables of the slots getting a learned start
   int32_t* lsel_d;
   int mlp_dim = 0;           // 0: no network loaded
@@ -283,6 +285,7 @@ IterArgs iter_args(aqs_ctx* c) {
   a.cell_start = c->cstart;
   a.thdr = c->thdr;
   a.truns = c->truns;
+  a.tord = c->tord;
   a.fpart = c->fpart; a.upart = c->upart; a.counter = c->counter;
   a.log = c->log; a.log_cap = c->tn.log_cap;
   a.max_nb = c->tn.max_nb;
@@ -305,6 +308,7 @@ LearnArgs learn_args(aqs_ctx* c, int mode, float* out = nullptr) {
   a.truns = c->truns;
   a.nbl = c->nbl;
   a.nbc = c->nbc;
+  a.max_nb = c->tn.max_nb;
   a.sel = c->sel_d;
   a.nsel = (int32_t)c->cur_sel.size();
   a.mode = mode;
@@ -486,7 +490,7 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = f
   a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
   a.id = c->id; a.inv = c->inv;
   a.nbc = c->nbc; a.nbl = c->nbl;
-  a.thdr = c->thdr; a.truns = c->truns;
+  a.thdr = c->thdr; a.truns = c->truns; a.tord = c->tord;
   a.cell_count = c->ccount; a.cell_start = c->cstart; a.cell_of = c->cellof; a.order = c->order;
   a.tpos4 = c->tpos4; a.tvx = c->tvx; a.tvy = c->tvy; a.tvz = c->tvz; a.tid_ = c->tid;
   a.upart = c->upart;
@@ -674,6 +678,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->lpart = at<double>(w, lo.o_lpart);
   c->mlp = at<MlpDev>(w, lo.o_mlp);
   c->mlpw = at<float>(w, lo.o_mlpw);
+  c->tord = at<int32_t>(w, lo.o_tord);
   c->ltbl = at<int2>(w, lo.o_ltbl);
   c->lftbl = at<int2>(w, lo.o_lftbl);
   c->lsel_d = at<int32_t>(w, lo.o_lsel);

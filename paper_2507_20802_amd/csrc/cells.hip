@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
     int c3[3];
     cell_of_pos<D>(g, nc, t, pi, c3);
     uint32_t* L = a.nbl + g.nb_off + li;
-    int cnt = 0;
+    int na = 0, nb = 0;   // A neighbours from row 0 up, B neighbours from row max_nb - 1 down
     bool over = false;
     const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
     for (int dz = zlo; dz <= zhi; ++dz) {
@@ -318,18 +318,33 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
               const uint32_t tb = ((uint32_t)pj.w << 29);
               const uint32_t ent = lds ? ((uint32_t)(rr.off + (j - rr.src)) | tb)
                                        : ((uint32_t)j | ((uint32_t)code << kCodeShift) | tb);
-              if (cnt < a.max_nb)
-                L[(int64_t)cnt * g.npad] = ent;
-              else
+              if (na + nb < a.max_nb) {
+                const int row = (pj.w == 0.0) ? na : a.max_nb - 1 - nb;
+                L[(int64_t)row * g.npad] = ent;
+              } else {
                 over = true;
-              ++cnt;
+              }
+              if (pj.w == 0.0) ++na; else ++nb;
             }
           }
         }
       }
     }
-    a.nbc[gi] = over ? a.max_nb : cnt;
-    if (over) atomicMax(a.overflow, cnt);
+    a.nbc[gi] = na | (nb << 16);
+    if (over) atomicMax(a.overflow, na + nb);
+  }
+  // the force kernel walks the tile's atoms by decreasing list length (ties
+  // by position), so the lanes of a wavefront have lists of similar length
+  __syncthreads();
+  const int32_t* nbc = a.nbc + g.atom_off;
+  for (int li = a0 + tid; li < a1; li += kBlock) {
+    const int ci = (nbc[li] & 0xffff) + (nbc[li] >> 16);
+    int rank = 0;
+    for (int j = a0; j < a1; ++j) {
+      const int cj = (nbc[j] & 0xffff) + (nbc[j] >> 16);
+      rank += (cj > ci || (cj == ci && j < li)) ? 1 : 0;
+    }
+    a.tord[g.atom_off + a0 + rank] = li;
   }
 }
 

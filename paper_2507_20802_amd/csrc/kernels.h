@@ -26,6 +26,7 @@ struct RebuildArgs {
   uint32_t* nbl;
   TileHdr* thdr;        // per force tile (tile_off + t)
   TileRun* truns;       // kRuns per force tile
+  int32_t* tord;        // per atom: the tile's atoms by decreasing list length
   int32_t* cell_count;  // per cell (cell_off + c)
   int32_t* cell_start;  // per cell + 1 per slot (cell_off + slot_index + c)
   int32_t* cell_of;     // per atom

@@ -48,6 +48,7 @@ struct LearnArgs {
   const void* truns;        // TileRun x kRuns per force tile
   const uint32_t* nbl;      // neighbour lists (engine.h)
   const int32_t* nbc;
+  int32_t max_nb;
   const int32_t* sel;       // slots of the running selection
   int32_t nsel;
   int32_t mode;             // see the launchers

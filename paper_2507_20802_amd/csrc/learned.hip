@@ -161,12 +161,15 @@ __global__ __launch_bounds__(kBlock) void k_ldesc(LearnArgs a) {
     const int64_t gi = g.atom_off + lic;
     const double4 pi = P[lic];
     const int ti = (int)pi.w;
-    const int cnt = live ? a.nbc[gi] : 0;
+    const int32_t counts = live ? a.nbc[gi] : 0;
+    const int na = counts & 0xffff, nbn = (counts >> 16) & 0xffff;
     const uint32_t* L = a.nbl + g.nb_off + lic;
     double acc[kFeat];
 #pragma unroll
     for (int f = 0; f < kFeat; ++f) acc[f] = 0.0;
-    for (int k = sub; k < cnt; k += kLDescTPA) {
+    // A neighbours in rows 0.., B neighbours in rows max_nb - 1 down
+    for (int kk = sub; kk < na + nbn; kk += kLDescTPA) {
+      const int k = kk < na ? kk : a.max_nb - 1 - (kk - na);
       const uint32_t ent = L[(int64_t)k * g.npad];
       const int tj = (ent >> 29) & 1;
       double dx, dy, dz;

@@ -116,97 +116,88 @@ __device__ __forceinline__ void pair_term(bool live, double dx, double dy, doubl
   }
 }
 
-// Entries sub, sub + TPA, ... of a list (lane sub of TPA lanes per atom):
-// loads are unconditional (indices clamped into the list), entries past the
-// count become `fill`.
+// Entry k of this lane's share of a list (rows sub, sub + TPA, ...): the
+// load is unconditional and its row index wave-uniform (clamped below the
+// list capacity kcap, so the address needs no per-lane arithmetic); entries
+// past the lane's count become `fill`.
 template <int TPA>
 __device__ __forceinline__ uint32_t list_entry(const uint32_t* L, int64_t st, int k, int my,
-                                               uint32_t fill) {
-  const int kk = min(k, max(my - 1, 0));
+                                               int kcap, uint32_t fill) {
+  const int kk = min(k, kcap - 1);
   const uint32_t raw = L[(int64_t)kk * st];
   return k < my ? raw : fill;
 }
 
-template <int D, bool WE, int TPA>
-__device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint32_t* __restrict__ L,
-                                           int64_t stride, int cnt, uint32_t self_ent,
-                                           const double4* __restrict__ P, const double (*sh)[4],
-                                           const PairParams* pp, double& fx, double& fy,
-                                           double& fz, double& e, double& w) {
-  // this lane takes entries sub, sub + TPA, sub + 2 TPA, ... of the atom
-  const int sub = (int)(threadIdx.x % TPA);
-  const int my = cnt > sub ? (cnt - sub + TPA - 1) / TPA : 0;
-  L += (int64_t)sub * stride;
-  const int64_t st = (int64_t)TPA * stride;
+// One segment of a list: this lane's entries k = 0 .. my - 1 sit at rows
+// L + k st (st < 0 walks the B segment down from the top); all neighbours of
+// the segment have the same type, so the pair parameters q are fixed.
+template <int D, bool WE, int TPA, bool LDS>
+__device__ __forceinline__ void pair_segment(const double4 pi, const uint32_t* __restrict__ L,
+                                             int64_t st, int my, int kcap, uint32_t fill,
+                                             const PairParams q, const double4* __restrict__ P,
+                                             const double (*sh)[4], const double* hx,
+                                             const double* hy, const double* hz, double& fx,
+                                             double& fy, double& fz, double& e, double& w) {
   uint32_t cur[kChunk];
 #pragma unroll
-  for (int u = 0; u < kChunk; ++u) cur[u] = list_entry<TPA>(L, st, u, my, self_ent);
+  for (int u = 0; u < kChunk; ++u) cur[u] = list_entry<TPA>(L, st, u, my, kcap, fill);
   for (int k0 = 0; k0 < my; k0 += kChunk) {
     double4 pj[kChunk];
+    if (!LDS) {
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u) pj[u] = P[cur[u] & kIdxMask];
+      for (int u = 0; u < kChunk; ++u) pj[u] = P[cur[u] & kIdxMask];
+    }
     uint32_t nxt[kChunk];
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u) nxt[u] = list_entry<TPA>(L, st, k0 + kChunk + u, my, self_ent);
+    for (int u = 0; u < kChunk; ++u)
+      nxt[u] = list_entry<TPA>(L, st, k0 + kChunk + u, my, kcap, fill);
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) {
       const uint32_t ent = cur[u];
-      const int code = (int)((ent >> kCodeShift) & 31u);
-      const double dx = (pj[u].x - pi.x) + sh[code][0];
-      const double dy = (pj[u].y - pi.y) + sh[code][1];
-      const double dz = (D == 3) ? (pj[u].z - pi.z) + sh[code][2] : 0.0;
-      const PairParams q = pp[2 * ti + ((ent & kTypeBit) ? 1 : 0)];
+      double dx, dy, dz;
+      if (LDS) {
+        const int h = (int)(ent & kIdxMask);
+        dx = hx[h] - pi.x;
+        dy = hy[h] - pi.y;
+        dz = (D == 3) ? hz[h] - pi.z : 0.0;
+      } else {
+        const int code = (int)((ent >> kCodeShift) & 31u);
+        dx = (pj[u].x - pi.x) + sh[code][0];
+        dy = (pj[u].y - pi.y) + sh[code][1];
+        dz = (D == 3) ? (pj[u].z - pi.z) + sh[code][2] : 0.0;
+      }
       pair_term<D, WE>(k0 + u < my, dx, dy, dz, q, fx, fy, fz, e, w);
     }
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) cur[u] = nxt[u];
-  }
-  // combine the TPA lanes of the atom (fixed butterfly: every lane of the
-  // group ends with the same bits)
-#pragma unroll
-  for (int off = 1; off < TPA; off <<= 1) {
-    fx += __shfl_xor(fx, off, kWave);
-    fy += __shfl_xor(fy, off, kWave);
-    if (D == 3) fz += __shfl_xor(fz, off, kWave);
-    if (WE) {
-      e += __shfl_xor(e, off, kWave);
-      w += __shfl_xor(w, off, kWave);
-    }
   }
 }
 
-// Same pair loop with the neighbour positions in the tile's LDS halo (image
-// shifts already applied when staged): entry = halo index | type bit.
-template <int D, bool WE, int TPA>
-__device__ __forceinline__ void atom_pairs_lds(const double4 pi, int ti, const uint32_t* __restrict__ L,
-                                               int64_t stride, int cnt, const double* hx,
-                                               const double* hy, const double* hz,
-                                               const PairParams* pp, double& fx, double& fy,
-                                               double& fz, double& e, double& w) {
+// Lennard-Jones sum of one atom over its list, TPA lanes per atom.  The list
+// (engine.h) holds the nA neighbours of type A in rows 0 .. nA - 1 and the
+// nB of type B in rows max_nb - 1 down to max_nb - nB; lane sub takes rows
+// sub, sub + TPA, ... of each.  LDS: entries index the tile's halo (image
+// shifts applied when staged); else entries are j | image code.
+template <int D, bool WE, int TPA, bool LDS>
+__device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint32_t* __restrict__ L,
+                                           int64_t stride, int32_t counts, int max_nb,
+                                           uint32_t fill, const double4* __restrict__ P,
+                                           const double (*sh)[4], const double* hx,
+                                           const double* hy, const double* hz,
+                                           const PairParams* pp, double& fx, double& fy,
+                                           double& fz, double& e, double& w) {
   const int sub = (int)(threadIdx.x % TPA);
-  const int my = cnt > sub ? (cnt - sub + TPA - 1) / TPA : 0;
-  L += (int64_t)sub * stride;
+  const int na = counts & 0xffff, nb = (counts >> 16) & 0xffff;
+  const int kcap = max_nb / TPA;
+  const int my_a = na > sub ? (na - sub + TPA - 1) / TPA : 0;
+  const int my_b = nb > sub ? (nb - sub + TPA - 1) / TPA : 0;
   const int64_t st = (int64_t)TPA * stride;
-  uint32_t cur[kChunk];
-#pragma unroll
-  for (int u = 0; u < kChunk; ++u) cur[u] = list_entry<TPA>(L, st, u, my, 0u);
-  for (int k0 = 0; k0 < my; k0 += kChunk) {
-    uint32_t nxt[kChunk];
-#pragma unroll
-    for (int u = 0; u < kChunk; ++u) nxt[u] = list_entry<TPA>(L, st, k0 + kChunk + u, my, 0u);
-#pragma unroll
-    for (int u = 0; u < kChunk; ++u) {
-      const uint32_t ent = cur[u];
-      const int h = (int)(ent & kIdxMask);
-      const double dx = hx[h] - pi.x;
-      const double dy = hy[h] - pi.y;
-      const double dz = (D == 3) ? hz[h] - pi.z : 0.0;
-      const PairParams q = pp[2 * ti + ((ent & kTypeBit) ? 1 : 0)];
-      pair_term<D, WE>(k0 + u < my, dx, dy, dz, q, fx, fy, fz, e, w);
-    }
-#pragma unroll
-    for (int u = 0; u < kChunk; ++u) cur[u] = nxt[u];
-  }
+  pair_segment<D, WE, TPA, LDS>(pi, L + (int64_t)sub * stride, st, my_a, kcap, fill, pp[2 * ti],
+                                P, sh, hx, hy, hz, fx, fy, fz, e, w);
+  pair_segment<D, WE, TPA, LDS>(pi, L + (int64_t)(max_nb - 1 - sub) * stride, -st, my_b, kcap,
+                                fill, pp[2 * ti + 1], P, sh, hx, hy, hz, fx, fy, fz, e, w);
+  // combine the TPA lanes of the atom (fixed butterfly: every lane of the
+  // group ends with the same bits)
 #pragma unroll
   for (int off = 1; off < TPA; off <<= 1) {
     fx += __shfl_xor(fx, off, kWave);
@@ -403,13 +394,9 @@ __device__ __forceinline__ void force_atom(const IterArgs& a, const Geom& g, int
   const int64_t gi = g.atom_off + li;
   const double4 pi = a.pos4[gi];
   double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
-  if (LDS)
-    atom_pairs_lds<D, WE, TPA>(pi, (int)pi.w, a.nbl + g.nb_off + li, g.npad, a.nbc[gi], hx, hy, hz,
-                               spp, fx, fy, fz, e, w);
-  else
-    atom_pairs<D, WE, TPA>(pi, (int)pi.w, a.nbl + g.nb_off + li, g.npad, a.nbc[gi],
-                           (uint32_t)li | (13u << kCodeShift), a.pos4 + g.atom_off, sh, spp, fx, fy,
-                           fz, e, w);
+  atom_pairs<D, WE, TPA, LDS>(pi, (int)pi.w, a.nbl + g.nb_off + li, g.npad, a.nbc[gi], a.max_nb,
+                              LDS ? 0u : ((uint32_t)li | (13u << kCodeShift)), a.pos4 + g.atom_off,
+                              sh, hx, hy, hz, spp, fx, fy, fz, e, w);
   if (threadIdx.x % TPA != 0) return;
   a.fx[gi] = fx;
   a.fy[gi] = fy;
@@ -432,8 +419,8 @@ __device__ __forceinline__ void force_tile(const IterArgs& a, const Geom& g, int
                                            double* part) {
   constexpr int per = kBlock / TPA;
   for (int b = a0; b < a1; b += per) {
-    const int li = b + (int)(threadIdx.x / TPA);
-    if (li < a1) force_atom<D, WE, TPA, LDS>(a, g, li, sh, spp, hx, hy, hz, part);
+    const int k = b + (int)(threadIdx.x / TPA);
+    if (k < a1) force_atom<D, WE, TPA, LDS>(a, g, a.tord[g.atom_off + k], sh, spp, hx, hy, hz, part);
   }
 }
 
@@ -798,8 +785,10 @@ __global__ __launch_bounds__(kBlock) void k_virial(IterArgs a, int rep, double L
     const int ti = (int)pi.w;
     const uint32_t* L = a.nbl + g.nb_off + li;
     const double4* P = a.pos4 + g.atom_off;
-    const int cnt = a.nbc[gi];
-    for (int k = 0; k < cnt; ++k) {
+    const int32_t counts = a.nbc[gi];
+    const int na = counts & 0xffff, nb = (counts >> 16) & 0xffff;
+    for (int kk = 0; kk < na + nb; ++kk) {
+      const int k = kk < na ? kk : a.max_nb - 1 - (kk - na);   // A rows, then B rows
       const uint32_t ent = L[(int64_t)k * g.npad];
       const double4 pj = P[ent & kIdxMask];
       const int code = (int)((ent >> kCodeShift) & 31u);
