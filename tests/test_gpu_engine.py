@@ -207,3 +207,37 @@ def test_threads_per_atom_variants_agree(tpa):
     rec = eng2.minimize([0])[0, 0]
     assert rec["status"] == 0 and abs(rec["energy"] - ref.E) <= E_REL_TOL * abs(ref.E)
     assert O.compare(eng2.positions(0), ref.pos, H)[0] <= POS_TOL
+
+
+def test_full_size_forces_sampled_and_inherent_structure_certified():
+    """The benchmark's workload size (3D, 32768 atoms, 16 slots in one
+    launch, the default lane split): sampled forces at a strained state
+    against the oracle atom by atom, then one AQS step of every slot
+    certified by the oracle's own forces (max|F| < 1e-10) and the slots'
+    energies equal to the oracle's at those positions."""
+    n, P, dg = 32768, 16, 5e-5
+    s = S.uniform_glass_start(3, n, 3, 0)
+    eng = engine(3, [n] * P, s.L, dg)
+    eng.set_replica(0, s.types, s.pos, 0)
+    assert eng.minimize([0])[0, 0]["status"] == 0
+    is_pos = eng.positions(0)
+    for i in range(1, P):
+        eng.copy_replica(0, i)
+    k = [0] + [i * 20 for i in range(1, P)]
+    eng.affine_shear(list(range(1, P)), k[1:])
+    idx = S.rng_for(310).choice(n, 200, replace=False)
+    for r in (0, 7, P - 1):
+        x = O.affine(is_pos, k[r] * dg)
+        H = O.strain_box(3, s.L, k[r], dg)
+        _, F = eng.energy_forces(r)
+        Fo = O.forces_on(x, s.types, H, POT, idx)
+        assert np.abs(F[idx] - Fo).max() <= 1e-11 * max(1.0, np.abs(Fo).max())
+    eng.affine_shear(list(range(P)), [1] * P)
+    rec = eng.minimize(list(range(P)))
+    assert np.all(rec[:, 0]["status"] == 0)
+    for r in (0, P - 1):
+        H = O.strain_box(3, s.L, k[r] + 1, dg)
+        got = eng.positions(r)
+        Eo, Fo, _, _ = O.energy_forces(got, s.types, H, POT)
+        assert np.sqrt((Fo * Fo).sum(1)).max() < FTOL
+        assert abs(rec[r, 0]["energy"] - Eo) <= E_REL_TOL * abs(Eo)

@@ -69,3 +69,25 @@ def test_gpu_algorithm1_matches_oracle(dg, K, P, n):
             assert d.max_disp < 1e-6
         else:
             assert abs(d.de_per_atom) > 1e-10
+
+
+def test_two_glasses_in_one_batch_match_the_oracle():
+    """Two systems (different shear increments) run Algorithm 1 together in
+    one batched launch; each matches its own oracle run."""
+    from paper_2507_20802_amd import Engine, parallel
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, ofire = fire_pair()
+    K, P, n = 4, 3, 12
+    dgs = [2e-3, 4e-3]
+    per = parallel.slots_needed(1, P)
+    eng = Engine(dim, [len(types)] * (2 * per), L, [dgs[0]] * per + [dgs[1]] * per, fire=fire)
+    gl = parallel.layout(2, P)
+    for g in gl:
+        eng.set_replica(g.star, types, pos, 0)
+    out = parallel.run(eng, gl, n, K, P, delta_eq=1e-4)
+    assert out["statuses_ok"] and out["accepted_steps"] == 2 * n
+    for g, dg in zip(gl, dgs):
+        ref, _ = oracle_run(pos, types, L, dim, dg, K, P, n, ofire, 1e-4)
+        assert [r["checks"] for r in g.rounds] == [r.checks for r in ref.rounds]
+        H = O.strain_box(dim, L, n, dg)
+        assert O.compare(eng.positions(g.star), ref.r_star[1], H)[0] < 1e-8
