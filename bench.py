@@ -174,6 +174,7 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-start reference rounds")
     ap.add_argument("--only-plain", action="store_true", help="time the plain start only (no network)")
     ap.add_argument("--skin", type=float, default=0.3, help="Verlet skin (sigma_AA)")
+    ap.add_argument("--graph", type=int, default=0, help="replay iteration blocks as hipGraphs (1/0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -198,7 +199,7 @@ def main() -> int:
     s = S.uniform_glass_start(dim, n, 3, 0)
     nslots = parallel.slots_needed(1, P)
     ref_slot = nslots              # final r_star of the plain round, for the IS comparison
-    eng = Engine(dim, [n] * (nslots + 1), s.L, dg, pot=pot, fire=Fire(), tuning=Tuning(skin=args.skin))
+    eng = Engine(dim, [n] * (nslots + 1), s.L, dg, pot=pot, fire=Fire(), tuning=Tuning(skin=args.skin, use_graph=args.graph))
     glass = parallel.layout(1, P)[0]
     t0 = time.perf_counter()
     eng.set_replica(glass.star, s.types, s.pos, 0)

@@ -259,6 +259,10 @@ struct aqs_ctx {
   int32_t* h_lsel = nullptr;
   int32_t *h_reps = nullptr, *h_nc3 = nullptr, *h_over = nullptr, *h_sel = nullptr;
   double* h_dg = nullptr;
+  // a captured block of FIRE iterations (use_graph), valid for the current
+  // launch tables and block length
+  hipGraphExec_t gexec = nullptr;
+  int32_t g_iters = 0;
   // profiling
   int32_t prof_every = 0;
   int64_t block_count = 0;
@@ -521,6 +525,51 @@ aqs_status check_slot(aqs_ctx* c, int r) {
   return AQS_OK;
 }
 
+void drop_graph(aqs_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->g_iters = 0;
+}
+
+// M FIRE iterations (force, control, update per iteration) on the context
+// stream: replayed from a captured hipGraph when use_graph is set and the
+// stream can be captured, else launched directly.  The captured graph holds
+// kernel launches only (no memset nodes).
+aqs_status launch_block(aqs_ctx* c, const IterArgs& a, int M) {
+  if (c->tn.use_graph && c->stream != nullptr) {
+    if (!c->gexec || c->g_iters != M) {
+      drop_graph(c);
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      for (int it = 0; it < M; ++it) {
+        launch_force(a, c->cur_ntiles, c->dim, c->stream);
+        launch_control(a, c->stream);
+        launch_update(a, c->cur_nblk, c->dim, c->stream);
+      }
+      const hipError_t ce = hipStreamEndCapture(c->stream, &graph);
+      if (ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(AQS_EHIP, "capturing the iteration block failed: %s", hipGetErrorString(ce));
+      }
+      const hipError_t ie = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        c->gexec = nullptr;
+        return fail(AQS_EHIP, "instantiating the iteration block failed: %s", hipGetErrorString(ie));
+      }
+      c->g_iters = M;
+    }
+    HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+    return AQS_OK;
+  }
+  for (int it = 0; it < M; ++it) {
+    launch_force(a, c->cur_ntiles, c->dim, c->stream);
+    launch_control(a, c->stream);
+    launch_update(a, c->cur_nblk, c->dim, c->stream);
+  }
+  return AQS_OK;
+}
+
 aqs_status set_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
   std::vector<int2> tbl = make_table(c, sel);
   std::vector<int2> ftbl = make_tile_table(c, sel);
@@ -534,6 +583,7 @@ aqs_status set_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
   HIPCHK(hipMemcpyAsync(c->sel_d, c->h_sel, sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graph(c);   // the captured launches bake in the table sizes
   c->cur_sel = sel;
   c->cur_nblk = (int32_t)tbl.size();
   c->cur_ntiles = (int32_t)ftbl.size();
@@ -729,6 +779,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
 aqs_status aqs_destroy(aqs_ctx* c) {
   if (!c) return AQS_OK;
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   free_pinned(c);
   delete c;
@@ -967,15 +1018,20 @@ aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int
         if (st) return st;
       }
     }
-    for (int it = 0; it < M; ++it) {
-      // events bracket the force kernel alone and the update kernel alone
-      if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 0], c->stream));
-      launch_force(a, c->cur_ntiles, c->dim, c->stream);
-      if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 1], c->stream));
-      launch_control(a, c->stream);
-      if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 2], c->stream));
-      launch_update(a, c->cur_nblk, c->dim, c->stream);
-      if (timed) HIPCHK(hipEventRecord(c->ev[4 * it + 3], c->stream));
+    if (timed) {
+      for (int it = 0; it < M; ++it) {
+        // events bracket the force kernel alone and the update kernel alone
+        HIPCHK(hipEventRecord(c->ev[4 * it + 0], c->stream));
+        launch_force(a, c->cur_ntiles, c->dim, c->stream);
+        HIPCHK(hipEventRecord(c->ev[4 * it + 1], c->stream));
+        launch_control(a, c->stream);
+        HIPCHK(hipEventRecord(c->ev[4 * it + 2], c->stream));
+        launch_update(a, c->cur_nblk, c->dim, c->stream);
+        HIPCHK(hipEventRecord(c->ev[4 * it + 3], c->stream));
+      }
+    } else {
+      st = launch_block(c, a, M);
+      if (st) return st;
     }
     HIPCHK(hipGetLastError());
     c->cnt.force_launches += M;

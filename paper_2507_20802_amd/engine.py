@@ -139,7 +139,10 @@ class Engine:
         self.workspace = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         aligned = (base + 255) // 256 * 256
-        self._stream = torch.cuda.current_stream(self.device)
+        # a captured iteration block needs a stream of its own (the default
+        # stream cannot be captured); default priority
+        self._stream = torch.cuda.Stream(self.device) if self.tuning.use_graph \
+            else torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
         check(self._lib.aqs_create(ctypes.byref(self._cpot), ctypes.byref(self._cfire), ctypes.byref(self._ctune),
                                    self.n_rep, _p(self.n_atoms, ctypes.c_int32), _p(self.box_len, ctypes.c_double),

@@ -241,3 +241,26 @@ def test_full_size_forces_sampled_and_inherent_structure_certified():
         Eo, Fo, _, _ = O.energy_forces(got, s.types, H, POT)
         assert np.sqrt((Fo * Fo).sum(1)).max() < FTOL
         assert abs(rec[r, 0]["energy"] - Eo) <= E_REL_TOL * abs(Eo)
+
+
+def test_graph_replay_equals_direct_launches():
+    """Iteration blocks replayed from a captured hipGraph (many replays, with
+    state read-backs, list rebuilds and table changes in between) give the
+    bitwise results of direct launches."""
+    from paper_2507_20802_amd import Tuning
+    pos, types, L, dim = load_glass("glass2d_1000")
+    fire, _ = fire_pair()
+    out = []
+    for g in (0, 1):
+        eng = engine(dim, [len(types)] * 3, L, [1e-3, 2e-3, 1e-3], fire=fire,
+                     tuning=Tuning(use_graph=g, block_iters=16))
+        for r in range(3):
+            eng.set_replica(r, types, pos, 0)
+        r1 = eng.minimize([0, 1, 2], n_steps=[3, 2, 0])
+        eng.affine_shear([2], [5])
+        r2 = eng.minimize([2, 0], n_steps=[2, 1])
+        out.append((r1, r2, [eng.positions(r) for r in range(3)]))
+    (a1, a2, pa), (b1, b2, pb) = out
+    assert np.array_equal(a1, b1) and np.array_equal(a2, b2)
+    assert all(np.array_equal(x, y) for x, y in zip(pa, pb))
+    assert np.all(a1[:, 0]["status"] == 0)
