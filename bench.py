@@ -175,6 +175,8 @@ def main() -> int:
     ap.add_argument("--only-plain", action="store_true", help="time the plain start only (no network)")
     ap.add_argument("--skin", type=float, default=0.3, help="Verlet skin (sigma_AA)")
     ap.add_argument("--graph", type=int, default=0, help="replay iteration blocks as hipGraphs (1/0)")
+    ap.add_argument("--tuning", choices=("default", "auto", "autotune"), default="default",
+                    help="launch knobs: the defaults, the autotuner's cache, or tune when not cached")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -199,7 +201,8 @@ def main() -> int:
     s = S.uniform_glass_start(dim, n, 3, 0)
     nslots = parallel.slots_needed(1, P)
     ref_slot = nslots              # final r_star of the plain round, for the IS comparison
-    eng = Engine(dim, [n] * (nslots + 1), s.L, dg, pot=pot, fire=Fire(), tuning=Tuning(skin=args.skin, use_graph=args.graph))
+    tuning = Tuning(skin=args.skin, use_graph=args.graph) if args.tuning == "default" else args.tuning
+    eng = Engine(dim, [n] * (nslots + 1), s.L, dg, pot=pot, fire=Fire(), tuning=tuning)
     glass = parallel.layout(1, P)[0]
     t0 = time.perf_counter()
     eng.set_replica(glass.star, s.types, s.pos, 0)
@@ -296,7 +299,10 @@ def main() -> int:
                                f"fine AQS steps, dgamma={dg:g}, dgamma_c={K * dg:g}, FIRE to max|F|<1e-10, "
                                + ("plain start" if args.only_plain else
                                   "learned start (plain start timed alongside)"),
-                   "dim": dim, "n_atoms": n, "P": P, "K": K, "dgamma": dg},
+                   "dim": dim, "n_atoms": n, "P": P, "K": K, "dgamma": dg,
+                   "knobs": {"threads_per_atom": eng.tuning.threads_per_atom, "skin": eng.tuning.skin,
+                             "block_iters": eng.tuning.block_iters, "use_graph": eng.tuning.use_graph,
+                             "source": args.tuning}},
         "computed_steps_per_s": lr["computed_steps_per_s"],
         "fire_iters_per_step": lr["fire_iters_per_step"],
         "all_converged": lr["all_converged"],

@@ -110,7 +110,10 @@ class Engine:
     """A batch of replica slots on one GPU."""
 
     def __init__(self, dim: int, n_atoms, box_len, dgamma, pot: LJParams | None = None,
-                 fire: Fire | None = None, tuning: Tuning | None = None, device: str = "cuda"):
+                 fire: Fire | None = None, tuning: "Tuning | str | None" = None, device: str = "cuda"):
+        """tuning: knobs, None (defaults), "auto" (the autotuner's cached
+        knobs for this shape, else the defaults) or "autotune" (run the
+        autotuner when the shape is not cached)."""
         import torch
         self._lib = _lib.load()
         self.dim = int(dim)
@@ -126,6 +129,10 @@ class Engine:
         self.dgamma = _f64(np.broadcast_to(dg, (self.n_rep,)))
         self.pot = pot or LJParams()
         self.fire = fire or Fire()
+        if isinstance(tuning, str):   # "auto": the autotuner's cached knobs for this shape
+            from . import autotune
+            tuning = autotune.tuned(self.dim, self.n_atoms, self.n_rep,
+                                    run_if_missing=(tuning == "autotune"))
         self.tuning = tuning or Tuning()
         self._cpot = self.pot.to_c(self.dim)
         self._cfire = self.fire.to_c()

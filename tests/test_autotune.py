@@ -1,0 +1,50 @@
+"""The autotuner: shape buckets, the cache, and (on the GPU) a short tuning
+run whose winner is re-checked against the defaults."""
+import os
+
+import pytest
+
+from paper_2507_20802_amd import autotune as A
+
+
+def test_bucket_keys_round_sizes_to_powers_of_two():
+    assert A.bucket_key(3, 32768, 33, "MI355X") == "d3_n2^15_r2^5_MI355X"
+    assert A.bucket_key(3, 30000, 32, "MI355X") == A.bucket_key(3, 32768, 33, "MI355X")
+    assert A.bucket_key(2, 4096, 32, "a b") == "d2_n2^12_r2^5_a_b"
+    assert A.bucket_key(2, 4096, 32, "x") != A.bucket_key(3, 4096, 32, "x")
+
+
+def test_cache_round_trip_and_tuning(tmp_path):
+    path = str(tmp_path / "t.json")
+    assert A.load_cache(path) == {}
+    A.save_cache({"k": {"knobs": {"threads_per_atom": 4, "skin": 0.25, "block_iters": 16}}}, path)
+    e = A.load_cache(path)["k"]
+    t = A.tuning_of(e["knobs"])
+    assert (t.threads_per_atom, t.skin, t.block_iters) == (4, 0.25, 16)
+    assert A.tuning_of(A.DEFAULT).threads_per_atom == A.DEFAULT["threads_per_atom"]
+
+
+def test_every_knob_value_is_tried_once_per_pass():
+    seen = [(k, v) for k, vals in A.coordinate_order() for v in vals]
+    assert len(seen) == sum(len(v) for v in A.KNOBS.values())
+    assert all(v[0] == A.DEFAULT[k] for k, v in A.KNOBS.items())
+
+
+@pytest.mark.gpu
+def test_tuning_run_picks_a_checked_winner(tmp_path):
+    path = str(tmp_path / "tune.json")
+    entry = A.tune(2, 1000, 4, iters=60, repeats=1, cache=path)
+    assert entry["parity"]["ok"]
+    for k, v in entry["knobs"].items():
+        assert v in A.KNOBS[k]
+    assert entry["ms"] <= entry["default_ms"] * 1.0001
+    os.environ["AQS_TUNE_CACHE"] = path
+    try:
+        from paper_2507_20802_amd import Engine
+        import aqs_synth as S
+        s = S.uniform_glass_start(2, 1000, 3, 11)
+        eng = Engine(2, [1000] * 4, s.L, 1e-4, tuning="auto")
+        assert eng.tuning.threads_per_atom == entry["knobs"]["threads_per_atom"]
+        assert eng.tuning.skin == entry["knobs"]["skin"]
+    finally:
+        del os.environ["AQS_TUNE_CACHE"]
