@@ -175,7 +175,7 @@ def main() -> int:
     ap.add_argument("--only-plain", action="store_true", help="time the plain start only (no network)")
     ap.add_argument("--skin", type=float, default=0.3, help="Verlet skin (sigma_AA)")
     ap.add_argument("--graph", type=int, default=0, help="replay iteration blocks as hipGraphs (1/0)")
-    ap.add_argument("--tuning", choices=("default", "auto", "autotune"), default="default",
+    ap.add_argument("--tuning", choices=("default", "auto", "autotune"), default="auto",
                     help="launch knobs: the defaults, the autotuner's cache, or tune when not cached")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)

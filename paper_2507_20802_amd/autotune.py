@@ -45,12 +45,24 @@ def cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "aqs_mi355x", "tune.json"))
 
 
+# results of tuning runs on MI355X shipped with the package; a user cache
+# (cache_path()) takes precedence entry by entry
+PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
+
+
 def load_cache(path: str | None = None) -> dict:
     path = path or cache_path()
     if not os.path.exists(path):
         return {}
     with open(path) as fh:
         return json.load(fh)
+
+
+def lookup(key: str, cache: str | None = None):
+    entry = load_cache(cache).get(key)
+    if entry is None and cache is None:
+        entry = load_cache(PACKAGED).get(key)
+    return entry
 
 
 def save_cache(entries: dict, path: str | None = None) -> None:
@@ -93,12 +105,13 @@ def _glass(dim: int, n: int, seed: int):
 
 
 def _trial(dim, n, n_rep, s, is_pos, knobs, iters, dg):
-    """Wall time of `iters` FIRE iterations of n_rep sheared copies."""
+    """Wall time of the first `iters` FIRE iterations of an AQS step (one
+    shear increment dg from the inherent structure) of n_rep copies."""
     import torch
     eng = Engine(dim, [n] * n_rep, s.L, dg, fire=Fire(max_iter=iters), tuning=tuning_of(knobs))
     for r in range(n_rep):
         eng.set_replica(r, s.types, is_pos, 0)
-    eng.affine_shear(list(range(n_rep)), [20 * (r + 1) for r in range(n_rep)])
+    eng.affine_shear(list(range(n_rep)), [1] * n_rep)
     torch.cuda.synchronize()
     t = time.perf_counter()
     eng.minimize(list(range(n_rep)))
@@ -123,7 +136,7 @@ def _same_inherent_structure(dim, n, s, is_pos, knobs, dg) -> dict:
     return {"ok": bool(ok), "energy_rel": float(rel), "max_disp": float(d)}
 
 
-def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 150, repeats: int = 2, passes: int = 1,
+def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 300, repeats: int = 2, passes: int = 1,
          dg: float = 5e-5, seed: int = 11, cache: str | None = None, log=None) -> dict:
     """Tune the knobs for the shape, store and return the cache entry."""
     s, is_pos = _glass(dim, n_atoms, seed)
@@ -164,7 +177,7 @@ def tuned(dim: int, n_atoms, n_rep: int, cache: str | None = None, run_if_missin
     run_if_missing, else the defaults."""
     n = int(np.max(np.atleast_1d(n_atoms)))
     key = bucket_key(dim, n, n_rep, device_name())
-    entry = load_cache(cache).get(key)
+    entry = lookup(key, cache)
     if entry is None and run_if_missing:
         entry = tune(dim, n, n_rep, cache=cache, log=log)
     return tuning_of(entry["knobs"]) if entry else Tuning()
