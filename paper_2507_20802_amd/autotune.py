@@ -105,8 +105,9 @@ def _glass(dim: int, n: int, seed: int):
 
 
 def _trial(dim, n, n_rep, s, is_pos, knobs, iters, dg):
-    """Wall time of the first `iters` FIRE iterations of an AQS step (one
-    shear increment dg from the inherent structure) of n_rep copies."""
+    """Wall time per batched FIRE iteration of two complete AQS steps (one
+    shear increment dg from the inherent structure, minimised, then one
+    device chain step) of n_rep copies; `iters` caps each minimisation."""
     import torch
     eng = Engine(dim, [n] * n_rep, s.L, dg, fire=Fire(max_iter=iters), tuning=tuning_of(knobs))
     for r in range(n_rep):
@@ -114,9 +115,9 @@ def _trial(dim, n, n_rep, s, is_pos, knobs, iters, dg):
     eng.affine_shear(list(range(n_rep)), [1] * n_rep)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    eng.minimize(list(range(n_rep)))
+    rec = eng.minimize(list(range(n_rep)), n_steps=[1] * n_rep)
     torch.cuda.synchronize()
-    return time.perf_counter() - t
+    return (time.perf_counter() - t) / max(1, int(rec["iters"].sum(axis=1).max()))
 
 
 def _same_inherent_structure(dim, n, s, is_pos, knobs, dg) -> dict:
@@ -136,7 +137,7 @@ def _same_inherent_structure(dim, n, s, is_pos, knobs, dg) -> dict:
     return {"ok": bool(ok), "energy_rel": float(rel), "max_disp": float(d)}
 
 
-def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 300, repeats: int = 2, passes: int = 1,
+def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 5000, repeats: int = 2, passes: int = 1,
          dg: float = 5e-5, seed: int = 11, cache: str | None = None, log=None) -> dict:
     """Tune the knobs for the shape, store and return the cache entry."""
     s, is_pos = _glass(dim, n_atoms, seed)
@@ -148,7 +149,7 @@ def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 300, repeats: int = 2,
         if key not in timed:
             timed[key] = min(_trial(dim, n_atoms, n_rep, s, is_pos, kn, iters, dg) for _ in range(repeats))
             if log:
-                log(f"{kn}: {timed[key] * 1e3:.1f} ms")
+                log(f"{kn}: {timed[key] * 1e6:.1f} us per iteration")
         return timed[key]
 
     best_t = run(best)
@@ -162,8 +163,8 @@ def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 300, repeats: int = 2,
     check = _same_inherent_structure(dim, n_atoms, s, is_pos, best, dg)
     if not check["ok"]:
         best, best_t = dict(DEFAULT), run(DEFAULT)
-    entry = {"knobs": best, "ms": best_t * 1e3, "default_ms": run(DEFAULT) * 1e3, "trials": len(timed),
-             "iters": iters, "parity": check}
+    entry = {"knobs": best, "us_per_iter": best_t * 1e6, "default_us_per_iter": run(DEFAULT) * 1e6,
+             "trials": len(timed), "max_iter": iters, "parity": check}
     key = bucket_key(dim, n_atoms, n_rep, device_name())
     entries = load_cache(cache)
     entries[key] = entry

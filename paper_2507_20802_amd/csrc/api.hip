@@ -84,7 +84,7 @@ struct Layout {
   size_t total = 0;
   size_t o_geom, o_state, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
       o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl,
-      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_evals, o_xref4, o_ftbl, o_ttbl, o_thdr, o_truns, o_sel,
+      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_talt4, o_evals, o_xref4, o_ftbl, o_ttbl, o_thdr, o_truns, o_sel,
       o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl, o_lftbl, o_lsel, o_tord;
   int64_t atoms = 0;      // padded atoms over all slots
   int64_t nb_entries = 0;
@@ -179,6 +179,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   for (int a = 0; a < 3; ++a) lo.o_dl[a] = take(sizeof(double) * A);
   for (int a = 0; a < 3; ++a) lo.o_tdl[a] = take(sizeof(double) * A);
   lo.o_alt4 = take(sizeof(double4) * A);
+  lo.o_talt4 = take(sizeof(double4) * A);
   lo.o_evals = take(sizeof(unsigned long long));
   lo.o_xref4 = take(sizeof(double4) * A);
   lo.o_ftbl = take(sizeof(int2) * ((size_t)lo.tiles + 8));
@@ -229,7 +230,7 @@ struct aqs_ctx {
   int32_t *reps_d, *nc3_d, *overflow, *sel_d;
   double *dg_d, *red;
   double *dlx, *dly, *dlz, *tdlx, *tdly, *tdlz;
-  double4* alt4;
+  double4 *alt4, *talt4;
   unsigned long long* evals;
   double4* xref4;
   TileHdr* thdr;
@@ -327,6 +328,7 @@ LearnArgs learn_args(aqs_ctx* c, int mode, float* out = nullptr) {
   a.lpart = c->lpart;
   a.zbuf = c->zbuf;
   a.dlx = c->dlx; a.dly = c->dly; a.dlz = c->dlz;
+  a.alt4 = c->alt4;
   a.out = out;
   a.mlp = c->mlp;
   for (int t = 0; t < 4; ++t) {
@@ -506,6 +508,7 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = f
   a.resume = in_loop ? 1 : 0;
   a.dlx = c->dlx; a.dly = c->dly; a.dlz = c->dlz;
   a.tdlx = c->tdlx; a.tdly = c->tdly; a.tdlz = c->tdlz;
+  a.alt4 = c->alt4; a.talt4 = c->talt4;
   launch_rebuild(a, c->lo.max_cells, c->stream, c->nc3_d);
   HIPCHK(hipGetLastError());
   ++c->cnt.rebuilds;
@@ -722,6 +725,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->dlx = at<double>(w, lo.o_dl[0]); c->dly = at<double>(w, lo.o_dl[1]); c->dlz = at<double>(w, lo.o_dl[2]);
   c->tdlx = at<double>(w, lo.o_tdl[0]); c->tdly = at<double>(w, lo.o_tdl[1]); c->tdlz = at<double>(w, lo.o_tdl[2]);
   c->alt4 = at<double4>(w, lo.o_alt4);
+  c->talt4 = at<double4>(w, lo.o_talt4);
   c->evals = at<unsigned long long>(w, lo.o_evals);
   c->xref4 = at<double4>(w, lo.o_xref4);
   c->zbuf = at<uint16_t>(w, lo.o_zbuf);

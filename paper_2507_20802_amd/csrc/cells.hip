@@ -71,6 +71,13 @@ __global__ __launch_bounds__(kBlock) void k_rb_bin(RebuildArgs a) {
     p.y -= ny * g.L[1];
     if (D == 3) p.z -= nz * g.L[2];
     a.pos4[gi] = p;
+    if (a.alt4) {
+      double4 q = a.alt4[gi];
+      q.x -= nx * g.L[0] + ny * t;
+      q.y -= ny * g.L[1];
+      if (D == 3) q.z -= nz * g.L[2];
+      a.alt4[gi] = q;
+    }
   }
   int c3[3];
   const int nc[3] = {st->nc[0], st->nc[1], st->nc[2]};
@@ -192,6 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_perm(RebuildArgs a) {
     a.tdly[gi] = a.dly[go];
     if (D == 3) a.tdlz[gi] = a.dlz[go];
   }
+  if (a.alt4) a.talt4[gi] = a.alt4[go];
 }
 
 template <int D>
@@ -215,6 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_back(RebuildArgs a) {
     a.dly[gi] = a.tdly[gi];
     if (D == 3) a.dlz[gi] = a.tdlz[gi];
   }
+  if (a.alt4) a.alt4[gi] = a.talt4[gi];
 }
 
 // Neighbour lists, one block per force tile (tiles.h): the tile's segment

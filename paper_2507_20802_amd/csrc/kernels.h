@@ -41,9 +41,12 @@ struct RebuildArgs {
   int32_t max_nb;
   int32_t dim;
   int32_t resume;       // 1: slots in PH_REBUILD go back to PH_FIRE
-  // learned-start per-atom buffers permuted with the atoms (may be null)
+  // learned-start per-atom buffers permuted with the atoms (may be null):
+  // predicted displacement, and the saved plain start (also wrapped with
+  // the positions, so a revert restores the wrapped plain start bit for bit)
   double* dlx; double* dly; double* dlz;
   double* tdlx; double* tdly; double* tdlz;
+  double4* alt4; double4* talt4;
 };
 
 void launch_rebuild(const RebuildArgs& a, int32_t max_cells_per_slot, hipStream_t s,

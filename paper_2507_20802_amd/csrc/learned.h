@@ -63,6 +63,7 @@ struct LearnArgs {
   double* lpart;            // per global block: 6 doubles
   uint16_t* zbuf;           // per atom 64 BF16 features (slot order)
   double* dlx; double* dly; double* dlz;
+  double4* alt4;            // saved plain start (restored on a rejected learned start)
   float* out;               // API output (atom-id order)
   const MlpDev* mlp;
   double rd2[4];            // descriptor cutoff^2 per type pair (2 ti + tj)

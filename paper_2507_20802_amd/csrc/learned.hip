@@ -365,6 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_lmlp(LearnArgs a) {
     }
     p.x += g.dgamma * p.y;  // plain start, Eq. (16)
     a.pos4[gi] = p;
+    a.alt4[gi] = p;          // restored bit for bit if the learned start is rejected
     a.vx[gi] = 0.0;
     a.vy[gi] = 0.0;
     if (D == 3) a.vz[gi] = 0.0;

@@ -601,9 +601,10 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
         p.y += uy;
         if (D == 3) p.z += uz;
       } else {
-        p.x -= ux;
-        p.y -= uy;
-        if (D == 3) p.z -= uz;
+        const double4 q = a.alt4[gi];   // the plain start, bit for bit
+        p.x = q.x;
+        p.y = q.y;
+        p.z = q.z;
       }
       a.pos4[gi] = p;
     }

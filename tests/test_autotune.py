@@ -33,11 +33,11 @@ def test_every_knob_value_is_tried_once_per_pass():
 @pytest.mark.gpu
 def test_tuning_run_picks_a_checked_winner(tmp_path):
     path = str(tmp_path / "tune.json")
-    entry = A.tune(2, 1000, 4, iters=60, repeats=1, cache=path)
+    entry = A.tune(2, 1000, 4, iters=400, repeats=1, cache=path)
     assert entry["parity"]["ok"]
     for k, v in entry["knobs"].items():
         assert v in A.KNOBS[k]
-    assert entry["ms"] <= entry["default_ms"] * 1.0001
+    assert entry["us_per_iter"] <= entry["default_us_per_iter"] * 1.0001
     os.environ["AQS_TUNE_CACHE"] = path
     try:
         from paper_2507_20802_amd import Engine
