@@ -5,8 +5,8 @@ the rounding order of one atom's force sum: lanes per atom of the force
 kernel (which also sets the force-tile length), the Verlet skin (list length
 against rebuild frequency) and the FIRE iterations launched between state
 read-backs.  For a shape (dim, atoms per slot, slots) the tuner times short
-batched minimisations of a seeded glass on the GPU (coordinate descent from
-the defaults), re-checks that the winner reaches the same inherent structure
+device chains of AQS steps of a seeded glass on the GPU (coordinate descent
+from the defaults), re-checks that the winner reaches the same inherent structure
 as the defaults, and caches the result as JSON keyed by the shape bucket and
 the device name.
 
@@ -104,10 +104,11 @@ def _glass(dim: int, n: int, seed: int):
     return s, eng.positions(0)
 
 
-def _trial(dim, n, n_rep, s, is_pos, knobs, iters, dg):
-    """Wall time per batched FIRE iteration of two complete AQS steps (one
-    shear increment dg from the inherent structure, minimised, then one
-    device chain step) of n_rep copies; `iters` caps each minimisation."""
+def _trial(dim, n, n_rep, s, is_pos, knobs, iters, dg, steps=3):
+    """Wall time of a short device chain of every copy: one shear increment
+    dg from the inherent structure, minimised, then `steps` more AQS steps
+    (the batched loop's tail, rebuilds and polls included); `iters` caps
+    each minimisation."""
     import torch
     eng = Engine(dim, [n] * n_rep, s.L, dg, fire=Fire(max_iter=iters), tuning=tuning_of(knobs))
     for r in range(n_rep):
@@ -115,9 +116,9 @@ def _trial(dim, n, n_rep, s, is_pos, knobs, iters, dg):
     eng.affine_shear(list(range(n_rep)), [1] * n_rep)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    rec = eng.minimize(list(range(n_rep)), n_steps=[1] * n_rep)
+    eng.minimize(list(range(n_rep)), n_steps=[steps] * n_rep)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t) / max(1, int(rec["iters"].sum(axis=1).max()))
+    return time.perf_counter() - t
 
 
 def _same_inherent_structure(dim, n, s, is_pos, knobs, dg) -> dict:
@@ -149,7 +150,7 @@ def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 5000, repeats: int = 2
         if key not in timed:
             timed[key] = min(_trial(dim, n_atoms, n_rep, s, is_pos, kn, iters, dg) for _ in range(repeats))
             if log:
-                log(f"{kn}: {timed[key] * 1e6:.1f} us per iteration")
+                log(f"{kn}: {timed[key] * 1e3:.1f} ms")
         return timed[key]
 
     best_t = run(best)
@@ -163,7 +164,7 @@ def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 5000, repeats: int = 2
     check = _same_inherent_structure(dim, n_atoms, s, is_pos, best, dg)
     if not check["ok"]:
         best, best_t = dict(DEFAULT), run(DEFAULT)
-    entry = {"knobs": best, "us_per_iter": best_t * 1e6, "default_us_per_iter": run(DEFAULT) * 1e6,
+    entry = {"knobs": best, "ms": best_t * 1e3, "default_ms": run(DEFAULT) * 1e3,
              "trials": len(timed), "max_iter": iters, "parity": check}
     key = bucket_key(dim, n_atoms, n_rep, device_name())
     entries = load_cache(cache)
