@@ -313,6 +313,7 @@ LearnArgs learn_args(aqs_ctx* c, int mode, float* out = nullptr) {
   a.truns = c->truns;
   a.nbl = c->nbl;
   a.nbc = c->nbc;
+  a.tord = c->tord;
   a.max_nb = c->tn.max_nb;
   a.sel = c->sel_d;
   a.nsel = (int32_t)c->cur_sel.size();

@@ -342,18 +342,54 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
     a.nbc[gi] = na | (nb << 16);
     if (over) atomicMax(a.overflow, na + nb);
   }
-  // the force kernel walks the tile's atoms by decreasing list length (ties
-  // by position), so the lanes of a wavefront have lists of similar length
+  // The consumers walk the tile's atoms by decreasing list length (ties by
+  // position), so the lanes of a wavefront have lists of similar length:
+  // tord[a0 + k] is the k-th atom, and the list columns and counts are
+  // permuted to that order (column a0 + k holds that atom's list), so a
+  // wavefront still reads consecutive list words.
   __syncthreads();
-  const int32_t* nbc = a.nbc + g.atom_off;
+  __shared__ int s_src[kTileSort];
+  __shared__ uint32_t s_row[kTileSort];
+  __shared__ int s_max[2];
+  const int nt = a1 - a0;
+  const bool sortable = nt <= kTileSort;
+  int32_t* nbc = a.nbc + g.atom_off;
+  if (tid == 0) {
+    s_max[0] = 0;
+    s_max[1] = 0;
+  }
+  __syncthreads();
   for (int li = a0 + tid; li < a1; li += kBlock) {
     const int ci = (nbc[li] & 0xffff) + (nbc[li] >> 16);
-    int rank = 0;
-    for (int j = a0; j < a1; ++j) {
-      const int cj = (nbc[j] & 0xffff) + (nbc[j] >> 16);
-      rank += (cj > ci || (cj == ci && j < li)) ? 1 : 0;
+    int rank = li - a0;
+    if (sortable) {
+      rank = 0;
+      for (int j = a0; j < a1; ++j) {
+        const int cj = (nbc[j] & 0xffff) + (nbc[j] >> 16);
+        rank += (cj > ci || (cj == ci && j < li)) ? 1 : 0;
+      }
+      s_src[rank] = li - a0;
     }
     a.tord[g.atom_off + a0 + rank] = li;
+    atomicMax(&s_max[0], nbc[li] & 0xffff);
+    atomicMax(&s_max[1], nbc[li] >> 16);
+  }
+  __syncthreads();
+  if (!sortable) return;
+  // counts, then every used row, through LDS
+  for (int k = tid; k < nt; k += kBlock) s_row[k] = (uint32_t)nbc[a0 + k];
+  __syncthreads();
+  for (int k = tid; k < nt; k += kBlock) nbc[a0 + k] = (int32_t)s_row[s_src[k]];
+  __syncthreads();
+  uint32_t* Lt = a.nbl + g.nb_off + a0;
+  const int rows_a = min(s_max[0], a.max_nb), rows_b = min(s_max[1], a.max_nb);
+  for (int q = 0; q < rows_a + rows_b; ++q) {
+    const int r = q < rows_a ? q : a.max_nb - 1 - (q - rows_a);
+    uint32_t* row = Lt + (int64_t)r * g.npad;
+    for (int k = tid; k < nt; k += kBlock) s_row[k] = row[k];
+    __syncthreads();
+    for (int k = tid; k < nt; k += kBlock) row[k] = s_row[s_src[k]];
+    __syncthreads();
   }
 }
 

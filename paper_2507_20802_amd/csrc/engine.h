@@ -9,7 +9,9 @@
 //     inv    int32, sorted position of each atom id
 //     nbc    int32, neighbour counts per atom (A | B << 16)
 //   neighbour list per slot: max_nb x npad uint32, column-major (row k of
-//     atom i at k*npad + i) so a wavefront reads 64 consecutive words; the nA
+//     column c at k*npad + c) so a wavefront reads 64 consecutive words;
+//     column c belongs to atom tord[c] (each force tile's atoms ordered by
+//     decreasing list length; nbc is indexed by column too); the nA
 //     neighbours of type A fill rows 0.. upward, the nB of type B rows
 //     max_nb - 1 downward, nbc = nA | nB << 16; entry = halo index | type
 //     << 29 (tiles with an LDS halo) or j | (image code << 24) | (type << 29)
@@ -140,7 +142,7 @@ struct IterArgs {
   const int32_t* cell_start;  // per slot: cell_off + c, cells of the current grid
   const void* thdr;           // TileHdr per force tile (tile_off + t)
   const void* truns;          // TileRun x kRuns per force tile
-  const int32_t* tord;        // per tile, its atoms by decreasing list length (slot order)
+  const int32_t* tord;        // list column -> atom: each tile's atoms by decreasing list length
   double* fpart;          // kForceParts per force tile (tile_off + tile)
   double* upart;          // 1 per global block (max displacement of the update)
   uint32_t* counter;      // per slot, last-block detection

@@ -48,6 +48,7 @@ struct LearnArgs {
   const void* truns;        // TileRun x kRuns per force tile
   const uint32_t* nbl;      // neighbour lists (engine.h)
   const int32_t* nbc;
+  const int32_t* tord;      // per tile: atoms in list order (list column -> atom)
   int32_t max_nb;
   const int32_t* sel;       // slots of the running selection
   int32_t nsel;

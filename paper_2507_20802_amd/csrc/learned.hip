@@ -154,16 +154,17 @@ __global__ __launch_bounds__(kBlock) void k_ldesc(LearnArgs a) {
   constexpr int per = kBlock / kLDescTPA;
   const int sub = tid % kLDescTPA;
   for (int b0 = hdr.a0; b0 < hdr.a1; b0 += per) {
-    const int li = b0 + tid / kLDescTPA;
+    const int col = b0 + tid / kLDescTPA;      // list column (the tile's walk order)
     // every lane of the wavefront runs the loop; lanes past the tile do no pairs
-    const bool live = li < hdr.a1;
-    const int lic = live ? li : hdr.a0;
+    const bool live = col < hdr.a1;
+    const int colc = live ? col : hdr.a0;
+    const int lic = a.tord[g.atom_off + colc];
     const int64_t gi = g.atom_off + lic;
     const double4 pi = P[lic];
     const int ti = (int)pi.w;
-    const int32_t counts = live ? a.nbc[gi] : 0;
+    const int32_t counts = live ? a.nbc[g.atom_off + colc] : 0;
     const int na = counts & 0xffff, nbn = (counts >> 16) & 0xffff;
-    const uint32_t* L = a.nbl + g.nb_off + lic;
+    const uint32_t* L = a.nbl + g.nb_off + colc;
     double acc[kFeat];
 #pragma unroll
     for (int f = 0; f < kFeat; ++f) acc[f] = 0.0;

@@ -387,14 +387,15 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
 // Force of one atom li of the tile (TPA lanes), accumulated into the
 // thread's partials (E, |F|^2, F.v, |v|^2, max |F_i|^2, W_xy, non-finite).
 template <int D, bool WE, int TPA, bool LDS>
-__device__ __forceinline__ void force_atom(const IterArgs& a, const Geom& g, int li,
+__device__ __forceinline__ void force_atom(const IterArgs& a, const Geom& g, int li, int col,
                                            const double (*sh)[4], const PairParams* spp,
                                            const double* hx, const double* hy, const double* hz,
                                            double* part) {
   const int64_t gi = g.atom_off + li;
   const double4 pi = a.pos4[gi];
   double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
-  atom_pairs<D, WE, TPA, LDS>(pi, (int)pi.w, a.nbl + g.nb_off + li, g.npad, a.nbc[gi], a.max_nb,
+  atom_pairs<D, WE, TPA, LDS>(pi, (int)pi.w, a.nbl + g.nb_off + col, g.npad,
+                              a.nbc[g.atom_off + col], a.max_nb,
                               LDS ? 0u : ((uint32_t)li | (13u << kCodeShift)), a.pos4 + g.atom_off,
                               sh, hx, hy, hz, spp, fx, fy, fz, e, w);
   if (threadIdx.x % TPA != 0) return;
@@ -420,7 +421,8 @@ __device__ __forceinline__ void force_tile(const IterArgs& a, const Geom& g, int
   constexpr int per = kBlock / TPA;
   for (int b = a0; b < a1; b += per) {
     const int k = b + (int)(threadIdx.x / TPA);
-    if (k < a1) force_atom<D, WE, TPA, LDS>(a, g, a.tord[g.atom_off + k], sh, spp, hx, hy, hz, part);
+    if (k < a1)
+      force_atom<D, WE, TPA, LDS>(a, g, a.tord[g.atom_off + k], k, sh, spp, hx, hy, hz, part);
   }
 }
 
@@ -778,15 +780,16 @@ __global__ __launch_bounds__(kBlock) void k_virial(IterArgs a, int rep, double L
   if (tid < 27) code_shift(tid, Lx, Ly, Lz, t, sh[tid]);
   if (tid < 4) spp[tid] = a.pp[tid];
   __syncthreads();
-  const int li = blockIdx.x * kBlock + tid;
+  const int col = blockIdx.x * kBlock + tid;   // list column (the tiles' walk order)
   double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (li < g.n) {
+  if (col < g.n) {
+    const int li = a.tord[g.atom_off + col];
     const int64_t gi = g.atom_off + li;
     const double4 pi = a.pos4[gi];
     const int ti = (int)pi.w;
-    const uint32_t* L = a.nbl + g.nb_off + li;
+    const uint32_t* L = a.nbl + g.nb_off + col;
     const double4* P = a.pos4 + g.atom_off;
-    const int32_t counts = a.nbc[gi];
+    const int32_t counts = a.nbc[g.atom_off + col];
     const int na = counts & 0xffff, nb = (counts >> 16) & 0xffff;
     for (int kk = 0; kk < na + nb; ++kk) {
       const int k = kk < na ? kk : a.max_nb - 1 - (kk - na);   // A rows, then B rows

@@ -22,6 +22,7 @@
 namespace aqs {
 
 constexpr int kRuns = 27;  // (dz, dy, part): 3 x 3 x 3 (2D uses dz = 0 only)
+constexpr int kTileSort = 1024;  // tiles up to this many atoms are walked by list length
 
 struct TileHdr {
   int32_t a0, a1;   // atom range [a0, a1) of the tile
