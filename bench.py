@@ -280,8 +280,9 @@ def main() -> int:
     avg_ms = cnt["force_ms"] / max(cnt["force_timed"], 1)
     evals = cnt.get("atom_evals", 0)
     atom_evals_per_launch = evals / cnt["force_launches"] if evals and cnt["force_launches"] else P * n
-    achieved_tflops = flops_per_atom * atom_evals_per_launch / (avg_ms * 1e-3) / 1e12
-    achieved_gbs = FORCE_BYTES_PER_ATOM[dim] * atom_evals_per_launch / (avg_ms * 1e-3) / 1e9
+    # no HIP-event samples (--profile-every 0): no achieved rate
+    achieved_tflops = flops_per_atom * atom_evals_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else None
+    achieved_gbs = FORCE_BYTES_PER_ATOM[dim] * atom_evals_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
     res = {
         "metric": METRIC,
         "value": lr["value"],
@@ -313,12 +314,13 @@ def main() -> int:
         "quench_s": quench_s,
         "mean_neighbours_in_cutoff": nb,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP64_PEAK_TFLOPS,
+                     "frac": achieved_tflops / FP64_PEAK_TFLOPS if achieved_tflops else None,
                      "traffic": force_traffic(dim, atom_evals_per_launch),
                      "kernel": f"k_force<{dim}>", "avg_launch_ms": avg_ms,
                      "atoms_per_launch": atom_evals_per_launch,
                      "algorithmic_flops_per_atom": flops_per_atom,
-                     "hbm_gbs_algorithmic": achieved_gbs, "hbm_frac": achieved_gbs / HBM_PEAK_GBS},
+                     "hbm_gbs_algorithmic": achieved_gbs,
+                     "hbm_frac": achieved_gbs / HBM_PEAK_GBS if achieved_gbs else None},
         "counters": cnt,
         "rounds": lr["rounds"],
     }

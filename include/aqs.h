@@ -121,7 +121,9 @@ size_t aqs_workspace_bytes(const aqs_potential* pot, const aqs_tuning* tune,
 /* Create a context over the caller's device workspace (>= 256-byte
  * aligned, >= aqs_workspace_bytes) and HIP stream (hipStream_t; NULL = the
  * null stream).  dgamma: host array of n_rep fine strain increments.  Slots
- * start empty; fill them with aqs_set_replica. */
+ * start empty; fill them with aqs_set_replica.  AQS_ECAPACITY if a slot's
+ * neighbour list (atoms rounded up to 256, times max_neighbors) reaches 2^30
+ * entries. */
 aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
                       const aqs_tuning* tune, int32_t n_rep,
                       const int32_t* n_atoms, const double* box_len,

@@ -123,6 +123,10 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
         return fail(AQS_EINVAL,
                     "slot %d: box edge %g too small; need >= 3 (rc_max + skin) = %g", r,
                     g.L[a], 3.0 * rl);
+    // the force kernel addresses a slot's list with 32-bit byte offsets
+    if ((int64_t)g.npad * tn.max_nb >= (int64_t(1) << 30))
+      return fail(AQS_ECAPACITY, "slot %d: neighbour list of %d atoms x %d entries exceeds 2^30 words",
+                  r, g.npad, tn.max_nb);
     g.cell_cap = nc[0] * nc[1] * nc[2];
     g.cell_off = cell_off;
     // force tiles: rows x segments; rows are fixed by the grid in y, z

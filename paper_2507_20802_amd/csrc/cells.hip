@@ -13,8 +13,8 @@
 //   back   copy back; inverse permutation
 //   list   per force tile (tiles.h): its segment and halo run table, then
 //          per atom the 3^dim neighbouring cells, keeping every image pair
-//          within rc_ab + skin; the entry names the neighbour's halo slot
-//          (or j | image code << 24)
+//          within rc_ab + skin; the entry is the byte offset 8 h of the
+//          neighbour's halo slot h (or j | image code << 24)
 //   done   reset the validity bound of each rebuilt slot
 // Integer atomics only; the result does not depend on their order.
 #include <hip/hip_runtime.h>
@@ -269,7 +269,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
       off += runs[r].count;
       if (runs[r].count > 0) a.truns[tix * kRuns + nr++] = runs[r];
     }
-    const bool lds = (st->list_mode == 0) && (off <= CAP);
+    // LDS halo slot CAP - 1 is the force kernel's far fill slot
+    const bool lds = (st->list_mode == 0) && (off < CAP);
     s_lds = lds ? 1 : 0;
     TileHdr h;
     h.a0 = a0;
@@ -324,9 +325,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
             const double ddz = (D == 3) ? (pj.z - pi.z) + sz : 0.0;
             const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
             if (r2 < rl2[(int)pj.w]) {
-              const uint32_t tb = ((uint32_t)pj.w << 29);
-              const uint32_t ent = lds ? ((uint32_t)(rr.off + (j - rr.src)) | tb)
-                                       : ((uint32_t)j | ((uint32_t)code << kCodeShift) | tb);
+              const uint32_t ent = lds ? 8u * (uint32_t)(rr.off + (j - rr.src))
+                                       : ((uint32_t)j | ((uint32_t)code << kCodeShift));
               if (na + nb < a.max_nb) {
                 const int row = (pj.w == 0.0) ? na : a.max_nb - 1 - nb;
                 L[(int64_t)row * g.npad] = ent;

@@ -13,8 +13,10 @@
 //     column c belongs to atom tord[c] (each force tile's atoms ordered by
 //     decreasing list length; nbc is indexed by column too); the nA
 //     neighbours of type A fill rows 0.. upward, the nB of type B rows
-//     max_nb - 1 downward, nbc = nA | nB << 16; entry = halo index | type
-//     << 29 (tiles with an LDS halo) or j | (image code << 24) | (type << 29)
+//     max_nb - 1 downward, nbc = nA | nB << 16 (the neighbour's type is
+//     that of its segment); entry = 8 x halo slot, the byte offset of the
+//     slot in the halo coordinate arrays (tiles with an LDS halo), or
+//     j | (image code << 24)
 //   xref4  double4, positions at the last list build (validity test)
 //   per-block partial sums, per-slot counters, per-slot state and geometry.
 #pragma once

@@ -172,10 +172,10 @@ __global__ __launch_bounds__(kBlock) void k_ldesc(LearnArgs a) {
     for (int kk = sub; kk < na + nbn; kk += kLDescTPA) {
       const int k = kk < na ? kk : a.max_nb - 1 - (kk - na);
       const uint32_t ent = L[(int64_t)k * g.npad];
-      const int tj = (ent >> 29) & 1;
+      const int tj = kk < na ? 0 : 1;
       double dx, dy, dz;
       if (lds) {
-        const int h = (int)(ent & kIdxMask);
+        const int h = (int)(ent >> 3);   // entries are byte offsets 8 h
         dx = hx[h] - pi.x;
         dy = hy[h] - pi.y;
         dz = (D == 3) ? hz[h] - pi.z : 0.0;

@@ -83,7 +83,12 @@ __device__ __forceinline__ double slot_tilt(const Geom& g, const State* st) {
 // within 1 ulp of the rounded quotient.
 
 constexpr int kChunk = 4;
-constexpr uint32_t kTypeBit = 1u << 29;
+// Fourth word of a buffer resource on gfx9-family GPUs (raw 32-bit data,
+// offsets in bytes).
+constexpr int kBufferFlags = 0x00020000;
+// Coordinate of the far fill slot, the last LDS halo slot: list entries past
+// a lane's count name it, and its distance from any atom is beyond every cutoff.
+constexpr double kFarFill = 1.0e20;
 
 __device__ __forceinline__ double recip_nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
@@ -93,54 +98,66 @@ __device__ __forceinline__ double recip_nr(double x) {
   return fma(r, e, r);
 }
 
-// One pair term, branch-free: invalid or out-of-range pairs contribute
-// exact zeros (their 1/r^2 is taken of 1.0 and the result masked), so the
-// kChunk pairs of a chunk interleave without divergence.
-template <int D, bool WE>
+// One pair term, branch-free: out-of-range pairs contribute exact zeros (the
+// result is selected away), so the kChunk pairs of a chunk interleave
+// without divergence.  SAFE: the entry may be this atom itself or a stale
+// fill entry (distance 0), so it is masked by `live` and its 1/r^2 taken of
+// 1.0; otherwise every entry is another atom or the far fill slot, at a
+// positive distance.  U'(r)/r = eps4 s6 (6 - 12 s6) / r^2 with s6 = (s/r)^6.
+template <int D, bool WE, bool SAFE>
 __device__ __forceinline__ void pair_term(bool live, double dx, double dy, double dz,
                                           const PairParams& q, double& fx, double& fy, double& fz,
                                           double& e, double& w) {
   const double r2 = (D == 3) ? dx * dx + dy * dy + dz * dz : dx * dx + dy * dy;
-  const bool in = live && (r2 < q.rc2);
-  const double inv = recip_nr(in ? r2 : 1.0);
+  const bool in = SAFE ? (live && (r2 < q.rc2)) : (r2 < q.rc2);
+  const double inv = recip_nr(SAFE ? (in ? r2 : 1.0) : r2);
   const double s2 = q.sig2 * inv;
   const double s6 = s2 * s2 * s2;
-  const double s12 = s6 * s6;
-  const double g = in ? q.eps4 * (6.0 * s6 - 12.0 * s12) * inv : 0.0;  // U'(r) / r
+  const double gv = s6 * fma(-12.0 * q.eps4, s6, 6.0 * q.eps4) * inv;
+  const double g = in ? gv : 0.0;
   fx += g * dx;
   fy += g * dy;
   if (D == 3) fz += g * dz;
   if (WE) {
-    e += in ? q.eps4 * (s12 - s6) - q.ucut : 0.0;
+    e += in ? q.eps4 * (s6 * s6 - s6) - q.ucut : 0.0;
     w += g * dx * dy;
   }
 }
 
-// Entry k of this lane's share of a list (rows sub, sub + TPA, ...): the
-// load is unconditional and its row index wave-uniform (clamped below the
-// list capacity kcap, so the address needs no per-lane arithmetic); entries
-// past the lane's count become `fill`.
-template <int TPA>
-__device__ __forceinline__ uint32_t list_entry(const uint32_t* L, int64_t st, int k, int my,
-                                               int kcap, uint32_t fill) {
-  const int kk = min(k, kcap - 1);
-  const uint32_t raw = L[(int64_t)kk * st];
+// Halo coordinate at byte offset `off` (an LDS list entry).
+__device__ __forceinline__ double lds_at(const double* h, uint32_t off) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(h) + off);
+}
+
+// Entry k of this lane's share of a list (rows sub, sub + TPA, ...), read
+// as a buffer load from the slot's list: the step kk is clamped below the
+// list capacity kcap, so the byte offset splits into a wave-uniform part
+// sb + kk ss (scalar offset) and the lane's fixed part lb (vector offset)
+// and needs no per-lane address arithmetic; entries past the lane's count
+// become `fill`.  Offsets are taken modulo 2^32 (ss < 0 for B segments).
+__device__ __forceinline__ uint32_t list_entry(__amdgpu_buffer_rsrc_t rs, uint32_t lb, uint32_t sb,
+                                               uint32_t ss, int k, int my, int kcap,
+                                               uint32_t fill) {
+  const uint32_t kk = (uint32_t)min(k, kcap - 1);
+  const uint32_t raw = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)lb, (int)(sb + kk * ss), 0);
   return k < my ? raw : fill;
 }
 
-// One segment of a list: this lane's entries k = 0 .. my - 1 sit at rows
-// L + k st (st < 0 walks the B segment down from the top); all neighbours of
-// the segment have the same type, so the pair parameters q are fixed.
+// One segment of a list: this lane's entry k (k = 0 .. my - 1) sits at byte
+// offset lb + sb + k ss of the slot's list (ss < 0 walks the B segment down
+// from the top); all neighbours of the segment have the same type, so the
+// pair parameters q are fixed.
 template <int D, bool WE, int TPA, bool LDS>
-__device__ __forceinline__ void pair_segment(const double4 pi, const uint32_t* __restrict__ L,
-                                             int64_t st, int my, int kcap, uint32_t fill,
+__device__ __forceinline__ void pair_segment(const double4 pi, __amdgpu_buffer_rsrc_t rs,
+                                             uint32_t lb, uint32_t sb, uint32_t ss, int my,
+                                             int kcap, uint32_t fill,
                                              const PairParams q, const double4* __restrict__ P,
                                              const double (*sh)[4], const double* hx,
                                              const double* hy, const double* hz, double& fx,
                                              double& fy, double& fz, double& e, double& w) {
   uint32_t cur[kChunk];
 #pragma unroll
-  for (int u = 0; u < kChunk; ++u) cur[u] = list_entry<TPA>(L, st, u, my, kcap, fill);
+  for (int u = 0; u < kChunk; ++u) cur[u] = list_entry(rs, lb, sb, ss, u, my, kcap, fill);
   for (int k0 = 0; k0 < my; k0 += kChunk) {
     double4 pj[kChunk];
     if (!LDS) {
@@ -150,23 +167,22 @@ __device__ __forceinline__ void pair_segment(const double4 pi, const uint32_t* _
     uint32_t nxt[kChunk];
 #pragma unroll
     for (int u = 0; u < kChunk; ++u)
-      nxt[u] = list_entry<TPA>(L, st, k0 + kChunk + u, my, kcap, fill);
+      nxt[u] = list_entry(rs, lb, sb, ss, k0 + kChunk + u, my, kcap, fill);
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) {
       const uint32_t ent = cur[u];
       double dx, dy, dz;
       if (LDS) {
-        const int h = (int)(ent & kIdxMask);
-        dx = hx[h] - pi.x;
-        dy = hy[h] - pi.y;
-        dz = (D == 3) ? hz[h] - pi.z : 0.0;
+        dx = lds_at(hx, ent) - pi.x;
+        dy = lds_at(hy, ent) - pi.y;
+        dz = (D == 3) ? lds_at(hz, ent) - pi.z : 0.0;
       } else {
         const int code = (int)((ent >> kCodeShift) & 31u);
         dx = (pj[u].x - pi.x) + sh[code][0];
         dy = (pj[u].y - pi.y) + sh[code][1];
         dz = (D == 3) ? (pj[u].z - pi.z) + sh[code][2] : 0.0;
       }
-      pair_term<D, WE>(k0 + u < my, dx, dy, dz, q, fx, fy, fz, e, w);
+      pair_term<D, WE, !LDS>(k0 + u < my, dx, dy, dz, q, fx, fy, fz, e, w);
     }
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) cur[u] = nxt[u];
@@ -179,8 +195,8 @@ __device__ __forceinline__ void pair_segment(const double4 pi, const uint32_t* _
 // sub, sub + TPA, ... of each.  LDS: entries index the tile's halo (image
 // shifts applied when staged); else entries are j | image code.
 template <int D, bool WE, int TPA, bool LDS>
-__device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint32_t* __restrict__ L,
-                                           int64_t stride, int32_t counts, int max_nb,
+__device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint32_t* __restrict__ Ls,
+                                           int col, int64_t stride, int32_t counts, int max_nb,
                                            uint32_t fill, const double4* __restrict__ P,
                                            const double (*sh)[4], const double* hx,
                                            const double* hy, const double* hz,
@@ -191,11 +207,21 @@ __device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint3
   const int kcap = max_nb / TPA;
   const int my_a = na > sub ? (na - sub + TPA - 1) / TPA : 0;
   const int my_b = nb > sub ? (nb - sub + TPA - 1) / TPA : 0;
-  const int64_t st = (int64_t)TPA * stride;
-  pair_segment<D, WE, TPA, LDS>(pi, L + (int64_t)sub * stride, st, my_a, kcap, fill, pp[2 * ti],
-                                P, sh, hx, hy, hz, fx, fy, fz, e, w);
-  pair_segment<D, WE, TPA, LDS>(pi, L + (int64_t)(max_nb - 1 - sub) * stride, -st, my_b, kcap,
-                                fill, pp[2 * ti + 1], P, sh, hx, hy, hz, fx, fy, fz, e, w);
+  // Row of step k: A  k TPA + sub,  B  max_nb - 1 - sub - k TPA
+  //   = (max_nb - TPA - k TPA) + (TPA - 1 - sub); the first term is
+  // wave-uniform (scalar offset), the second the lane's (vector offset).
+  // Byte offsets stay below 2^32: a slot's list has under 2^30 words.
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint32_t*>(Ls), (short)0, (int)(4u * (uint32_t)stride * (uint32_t)max_nb),
+      kBufferFlags);
+  const uint32_t row_bytes = 4u * (uint32_t)stride;
+  const uint32_t step = (uint32_t)TPA * row_bytes;
+  const uint32_t lba = 4u * (uint32_t)col + (uint32_t)sub * row_bytes;
+  const uint32_t lbb = 4u * (uint32_t)col + (uint32_t)(TPA - 1 - sub) * row_bytes;
+  pair_segment<D, WE, TPA, LDS>(pi, rs, lba, 0u, step, my_a, kcap, fill, pp[2 * ti], P, sh, hx, hy,
+                                hz, fx, fy, fz, e, w);
+  pair_segment<D, WE, TPA, LDS>(pi, rs, lbb, (uint32_t)(max_nb - TPA) * row_bytes, 0u - step, my_b,
+                                kcap, fill, pp[2 * ti + 1], P, sh, hx, hy, hz, fx, fy, fz, e, w);
   // combine the TPA lanes of the atom (fixed butterfly: every lane of the
   // group ends with the same bits)
 #pragma unroll
@@ -391,12 +417,14 @@ __device__ __forceinline__ void force_atom(const IterArgs& a, const Geom& g, int
                                            const double (*sh)[4], const PairParams* spp,
                                            const double* hx, const double* hy, const double* hz,
                                            double* part) {
+  constexpr int CAP = (D == 3) ? kHaloCap3 : kHaloCap2;
   const int64_t gi = g.atom_off + li;
   const double4 pi = a.pos4[gi];
   double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
-  atom_pairs<D, WE, TPA, LDS>(pi, (int)pi.w, a.nbl + g.nb_off + col, g.npad,
+  atom_pairs<D, WE, TPA, LDS>(pi, (int)pi.w, a.nbl + g.nb_off, col, g.npad,
                               a.nbc[g.atom_off + col], a.max_nb,
-                              LDS ? 0u : ((uint32_t)li | (13u << kCodeShift)), a.pos4 + g.atom_off,
+                              LDS ? 8u * (uint32_t)(CAP - 1) : ((uint32_t)li | (13u << kCodeShift)),
+                              a.pos4 + g.atom_off,
                               sh, hx, hy, hz, spp, fx, fy, fz, e, w);
   if (threadIdx.x % TPA != 0) return;
   a.fx[gi] = fx;
@@ -467,6 +495,11 @@ __global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
     __syncthreads();
     if (hdr.halo >= 0) {
       stage_halo<D, CAP>(hdr, runs, sh, a.pos4 + g.atom_off, hx, hy, hz);
+      if (tid == kBlock - 1) {   // the far fill slot (the builder keeps halos below CAP)
+        hx[CAP - 1] = kFarFill;
+        hy[CAP - 1] = kFarFill;
+        if (D == 3) hz[CAP - 1] = kFarFill;
+      }
       __syncthreads();
       if (we)
         force_tile<D, true, TPA, true>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, part);
@@ -801,7 +834,7 @@ __global__ __launch_bounds__(kBlock) void k_virial(IterArgs a, int rep, double L
       d[1] = (pj.y - pi.y) + sh[code][1];
       d[2] = (D == 3) ? (pj.z - pi.z) + sh[code][2] : 0.0;
       const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      const PairParams q = spp[2 * ti + ((ent & kTypeBit) ? 1 : 0)];
+      const PairParams q = spp[2 * ti + (kk < na ? 0 : 1)];
       if (r2 < q.rc2) {
         const double inv = recip_nr(r2);
         const double s2 = q.sig2 * inv;
