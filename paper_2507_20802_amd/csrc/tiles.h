@@ -95,36 +95,47 @@ __device__ __forceinline__ void code_shift(int code, double Lx, double Ly, doubl
 }
 
 // Stage a tile's halo into LDS (image shifts sh[code] applied), by the whole
-// block of kBlock threads: thread tid takes halo slots tid, tid + kBlock, ...;
-// the run of a slot is found by binary search over the run offsets, then all
-// of the thread's loads are issued before its LDS stores.  The caller
-// synchronises the block afterwards.
+// block of kBlock threads: thread tid takes halo slots tid, tid + kBlock, ...
+// The run of each slot is found by a fixed five-step binary search over the
+// run offsets (kRuns <= 32), all of the thread's slots advancing together so
+// that their LDS reads overlap; then all of the thread's loads are issued
+// before its LDS stores.  The caller synchronises the block afterwards.
 template <int D, int CAP>
 __device__ __forceinline__ void stage_halo(const TileHdr& hdr, const TileRun* runs,
                                            const double (*sh)[4], const double4* P, double* hx,
                                            double* hy, double* hz) {
+  static_assert(kRuns <= 32, "the run search takes five steps");
   const int tid = threadIdx.x;
   constexpr int SU = (CAP + kBlock - 1) / kBlock;
-  double4 p[SU];
+  const int last = hdr.nruns - 1;
   int rix[SU];
+#pragma unroll
+  for (int u = 0; u < SU; ++u) rix[u] = 0;
+  // largest r with runs[r].off <= h (runs[0].off = 0)
+#pragma unroll
+  for (int step = 16; step >= 1; step >>= 1) {
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int h = tid + u * kBlock;
+      const int c = rix[u] + step;
+      const int oc = runs[max(min(c, last), 0)].off;   // read unconditionally
+      const bool take = (c <= last) & (oc <= h);
+      rix[u] = take ? c : rix[u];
+    }
+  }
+  double4 p[SU];
 #pragma unroll
   for (int u = 0; u < SU; ++u) {
     const int h = tid + u * kBlock;
-    rix[u] = -1;
     if (h < hdr.halo) {
-      int lo = 0, hi = hdr.nruns - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (runs[mid].off <= h) lo = mid; else hi = mid - 1;
-      }
-      rix[u] = lo;
-      p[u] = P[runs[lo].src + (h - runs[lo].off)];
+      const TileRun r = runs[rix[u]];
+      p[u] = P[r.src + (h - r.off)];
     }
   }
 #pragma unroll
   for (int u = 0; u < SU; ++u) {
-    if (rix[u] >= 0) {
-      const int h = tid + u * kBlock;
+    const int h = tid + u * kBlock;
+    if (h < hdr.halo) {
       const int code = runs[rix[u]].code;
       hx[h] = p[u].x + sh[code][0];
       hy[h] = p[u].y + sh[code][1];
