@@ -84,7 +84,7 @@ struct Layout {
   size_t total = 0;
   size_t o_geom, o_state, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
       o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl,
-      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_talt4, o_evals, o_xref4, o_ftbl, o_ttbl, o_thdr, o_truns, o_sel,
+      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_talt4, o_evals, o_xref4, o_ftbl, o_ttbl, o_thdr, o_hidx, o_sel,
       o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl, o_lftbl, o_lsel, o_tord;
   int64_t atoms = 0;      // padded atoms over all slots
   int64_t nb_entries = 0;
@@ -161,7 +161,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_nbl = take(sizeof(uint32_t) * (size_t)lo.nb_entries);
   lo.o_fpart = take(sizeof(double) * kForceParts * (size_t)lo.tiles);
   lo.o_thdr = take(sizeof(TileHdr) * (size_t)lo.tiles);
-  lo.o_truns = take(sizeof(TileRun) * kRuns * (size_t)lo.tiles);
+  lo.o_hidx = take(sizeof(uint32_t) * (size_t)halo_cap(dim) * (size_t)lo.tiles);
   lo.o_upart = take(sizeof(double) * (size_t)lo.blocks);
   lo.o_counter = take(sizeof(uint32_t) * n_rep);
   lo.o_log = take(sizeof(StepRecord) * (size_t)n_rep * tn.log_cap);
@@ -238,7 +238,7 @@ struct aqs_ctx {
   unsigned long long* evals;
   double4* xref4;
   TileHdr* thdr;
-  TileRun* truns;
+  uint32_t* hidx;
   // learned start
   uint16_t* zbuf;
   double* lpart;
@@ -293,7 +293,7 @@ IterArgs iter_args(aqs_ctx* c) {
   a.nbc = c->nbc; a.nbl = c->nbl;
   a.cell_start = c->cstart;
   a.thdr = c->thdr;
-  a.truns = c->truns;
+  a.hidx = c->hidx;
   a.tord = c->tord;
   a.fpart = c->fpart; a.upart = c->upart; a.counter = c->counter;
   a.log = c->log; a.log_cap = c->tn.log_cap;
@@ -314,7 +314,7 @@ LearnArgs learn_args(aqs_ctx* c, int mode, float* out = nullptr) {
   a.blocks = c->tbl;
   a.ftiles = c->ftbl;
   a.thdr = c->thdr;
-  a.truns = c->truns;
+  a.hidx = c->hidx;
   a.nbl = c->nbl;
   a.nbc = c->nbc;
   a.tord = c->tord;
@@ -501,7 +501,7 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = f
   a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
   a.id = c->id; a.inv = c->inv;
   a.nbc = c->nbc; a.nbl = c->nbl;
-  a.thdr = c->thdr; a.truns = c->truns; a.tord = c->tord;
+  a.thdr = c->thdr; a.hidx = c->hidx; a.tord = c->tord;
   a.cell_count = c->ccount; a.cell_start = c->cstart; a.cell_of = c->cellof; a.order = c->order;
   a.tpos4 = c->tpos4; a.tvx = c->tvx; a.tvy = c->tvy; a.tvz = c->tvz; a.tid_ = c->tid;
   a.upart = c->upart;
@@ -720,7 +720,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->ftbl = at<int2>(w, lo.o_ftbl);
   c->ttbl = at<int2>(w, lo.o_ttbl);
   c->thdr = at<TileHdr>(w, lo.o_thdr);
-  c->truns = at<TileRun>(w, lo.o_truns);
+  c->hidx = at<uint32_t>(w, lo.o_hidx);
   c->reps_d = at<int32_t>(w, lo.o_reps);
   c->sel_d = at<int32_t>(w, lo.o_sel);
   c->nc3_d = at<int32_t>(w, lo.o_nc3);

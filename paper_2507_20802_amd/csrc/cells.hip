@@ -227,9 +227,11 @@ __global__ __launch_bounds__(kBlock) void k_rb_back(RebuildArgs a) {
 }
 
 // Neighbour lists, one block per force tile (tiles.h): the tile's segment
-// and halo run table are computed here and stored for the force kernel, and
-// each entry names the neighbour's halo slot (or, for a tile whose halo does
-// not fit in LDS, its global index and image code).
+// and candidate runs are computed here; the scan marks every candidate some
+// list names, the marked candidates numbered in order form the compact halo
+// (stored for the force kernel as j | code << 24), and each entry is the
+// byte offset of its compact halo slot (or, for a tile whose compact halo
+// does not fit in LDS, the neighbour's global index and image code).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   const int2 bt = a.tiles[blockIdx.x];
@@ -243,7 +245,9 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   const double4* P = a.pos4 + g.atom_off;
   const int tid = threadIdx.x;
   __shared__ TileRun runs[kRuns];
-  __shared__ int s_cx0, s_cx1, s_lds;
+  __shared__ int s_cx0, s_cx1, s_cand, s_lds, s_ncand;
+  __shared__ uint32_t s_bits[kHaloWords];   // candidates named by some list
+  __shared__ int s_pre[kHaloWords];          // marked candidates before each word
   int a0, a1, cy, cz;
   segment(nc, st->tiles_x, cs, bt.y, a0, a1, cy, cz);
   if (tid == 0) {
@@ -259,28 +263,25 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   }
   __syncthreads();
   if (tid < kRuns) runs[tid] = make_run<D>(tid, s_cx0, s_cx1, cy, cz, nc, cs);
+  for (int w = tid; w < kHaloWords; w += kBlock) s_bits[w] = 0u;
   __syncthreads();
   constexpr int CAP = (D == 3) ? kHaloCap3 : kHaloCap2;
   const int64_t tix = g.tile_off + bt.y;
+  const int nt = a1 - a0;
+  const bool sortable = nt <= kTileSort;
   if (tid == 0) {
-    int off = 0, nr = 0;
+    int off = 0;
     for (int r = 0; r < kRuns; ++r) {
       runs[r].off = off;
       off += runs[r].count;
-      if (runs[r].count > 0) a.truns[tix * kRuns + nr++] = runs[r];
     }
-    // LDS halo slot CAP - 1 is the force kernel's far fill slot
-    const bool lds = (st->list_mode == 0) && (off < CAP);
-    s_lds = lds ? 1 : 0;
-    TileHdr h;
-    h.a0 = a0;
-    h.a1 = a1;
-    h.nruns = nr;
-    h.halo = lds ? off : -1;
-    a.thdr[tix] = h;
+    s_ncand = off;
+    s_cand = (st->list_mode == 0 && off <= 32 * kHaloWords && sortable) ? 1 : 0;
   }
   __syncthreads();
-  const bool lds = s_lds != 0;
+  // cand: entries hold candidate numbers during the scan and become compact
+  // halo offsets (or global entries) below
+  const bool cand = s_cand != 0;
   for (int li = a0 + tid; li < a1; li += kBlock) {
     const int64_t gi = g.atom_off + li;
     const double4 pi = P[li];
@@ -325,8 +326,9 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
             const double ddz = (D == 3) ? (pj.z - pi.z) + sz : 0.0;
             const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
             if (r2 < rl2[(int)pj.w]) {
-              const uint32_t ent = lds ? 8u * (uint32_t)(rr.off + (j - rr.src))
-                                       : ((uint32_t)j | ((uint32_t)code << kCodeShift));
+              const uint32_t hc = (uint32_t)(rr.off + (j - rr.src));
+              const uint32_t ent = cand ? hc : ((uint32_t)j | ((uint32_t)code << kCodeShift));
+              if (cand) atomicOr(&s_bits[hc >> 5], 1u << (hc & 31));
               if (na + nb < a.max_nb) {
                 const int row = (pj.w == 0.0) ? na : a.max_nb - 1 - nb;
                 L[(int64_t)row * g.npad] = ent;
@@ -351,8 +353,6 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   __shared__ int s_src[kTileSort];
   __shared__ uint32_t s_row[kTileSort];
   __shared__ int s_max[2];
-  const int nt = a1 - a0;
-  const bool sortable = nt <= kTileSort;
   int32_t* nbc = a.nbc + g.atom_off;
   if (tid == 0) {
     s_max[0] = 0;
@@ -374,8 +374,55 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
     atomicMax(&s_max[0], nbc[li] & 0xffff);
     atomicMax(&s_max[1], nbc[li] >> 16);
   }
+  // compact halo: the marked candidates, numbered in candidate order
+  if (tid < kHaloWords) s_pre[tid] = __popc(s_bits[tid]);
   __syncthreads();
-  if (!sortable) return;
+  if (tid == 0) {
+    int acc = 0;
+    for (int w = 0; w < kHaloWords; ++w) {
+      const int c = s_pre[w];
+      s_pre[w] = acc;
+      acc += c;
+    }
+    // LDS halo slot CAP - 1 is the force kernel's far fill slot
+    const bool lds = cand && acc < CAP;
+    s_lds = lds ? 1 : 0;
+    TileHdr h;
+    h.a0 = a0;
+    h.a1 = a1;
+    h.pad_ = 0;
+    h.halo = lds ? acc : -1;
+    a.thdr[tix] = h;
+  }
+  __syncthreads();
+  const bool lds = s_lds != 0;
+  const int ncand = s_ncand;
+  if (lds) {
+    uint32_t* hx = a.hidx + tix * CAP;
+    for (int hc = tid; hc < ncand; hc += kBlock) {
+      const uint32_t w = s_bits[hc >> 5], bit = 1u << (hc & 31);
+      if (!(w & bit)) continue;
+      int r = 0;
+      while (r < kRuns - 1 && !(hc >= runs[r].off && hc < runs[r].off + runs[r].count)) ++r;
+      hx[s_pre[hc >> 5] + __popc(w & (bit - 1u))] =
+          (uint32_t)(runs[r].src + (hc - runs[r].off)) | ((uint32_t)runs[r].code << kCodeShift);
+    }
+  }
+  if (!sortable) return;   // entries are global (cand is false)
+  // Entry of candidate number hc: the byte offset of its compact halo slot,
+  // or, for a tile whose compact halo does not fit, j | code.  Rows past an
+  // atom's count hold stale words; they are mapped too (bounded) and never read.
+  auto final_entry = [&](uint32_t hc) -> uint32_t {
+    if (!cand) return hc;
+    hc = min(hc, (uint32_t)(ncand > 0 ? ncand - 1 : 0));
+    const uint32_t w = s_bits[hc >> 5], bit = 1u << (hc & 31);
+    if (lds) return 8u * (uint32_t)(s_pre[hc >> 5] + __popc(w & (bit - 1u)));
+    for (int r = 0; r < kRuns; ++r)
+      if ((int)hc >= runs[r].off && (int)hc < runs[r].off + runs[r].count)
+        return (uint32_t)(runs[r].src + ((int)hc - runs[r].off)) |
+               ((uint32_t)runs[r].code << kCodeShift);
+    return 0u;
+  };
   // counts, then every used row, through LDS
   for (int k = tid; k < nt; k += kBlock) s_row[k] = (uint32_t)nbc[a0 + k];
   __syncthreads();
@@ -388,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
     uint32_t* row = Lt + (int64_t)r * g.npad;
     for (int k = tid; k < nt; k += kBlock) s_row[k] = row[k];
     __syncthreads();
-    for (int k = tid; k < nt; k += kBlock) row[k] = s_row[s_src[k]];
+    for (int k = tid; k < nt; k += kBlock) row[k] = final_entry(s_row[s_src[k]]);
     __syncthreads();
   }
 }

@@ -30,8 +30,11 @@ constexpr int kBlock = 256;           // atoms per workgroup (4 wavefronts)
 constexpr int kWave = 64;
 constexpr int kForceParts = 8;        // doubles per tile partial of the force kernel
 constexpr int kMaxTPA = 8;            // threads per atom of the force kernel: 1, 2, 4 or 8
-constexpr int kHaloCap3 = 1920;       // LDS halo capacity (atoms) of a force tile, 3D
-constexpr int kHaloCap2 = 1024;       // ... 2D
+// LDS halo capacity (atoms) of a force tile: its compact halo (the atoms
+// some list of the tile names) plus the far fill slot
+constexpr int kHaloCap3 = 1536;       // 3D
+constexpr int kHaloCap2 = 1024;       // 2D
+__host__ __device__ constexpr int halo_cap(int dim) { return dim == 3 ? kHaloCap3 : kHaloCap2; }
 constexpr uint32_t kIdxMask = 0x00FFFFFFu;
 constexpr int kCodeShift = 24;
 
@@ -143,7 +146,7 @@ struct IterArgs {
   const uint32_t* nbl;
   const int32_t* cell_start;  // per slot: cell_off + c, cells of the current grid
   const void* thdr;           // TileHdr per force tile (tile_off + t)
-  const void* truns;          // TileRun x kRuns per force tile
+  const uint32_t* hidx;       // compact halo per force tile (kHaloCap slots): j | code << 24
   const int32_t* tord;        // list column -> atom: each tile's atoms by decreasing list length
   double* fpart;          // kForceParts per force tile (tile_off + tile)
   double* upart;          // 1 per global block (max displacement of the update)

@@ -25,7 +25,7 @@ struct RebuildArgs {
   int32_t* nbc;
   uint32_t* nbl;
   TileHdr* thdr;        // per force tile (tile_off + t)
-  TileRun* truns;       // kRuns per force tile
+  uint32_t* hidx;       // compact halo per force tile (kHaloCap slots): j | code << 24
   int32_t* tord;        // per atom: the tile's atoms by decreasing list length
   int32_t* cell_count;  // per cell (cell_off + c)
   int32_t* cell_start;  // per cell + 1 per slot (cell_off + slot_index + c)

@@ -45,7 +45,7 @@ struct LearnArgs {
   const int2* blocks;       // (slot, 256-atom block) launch table
   const int2* ftiles;       // (slot, force tile) launch table
   const void* thdr;         // TileHdr per force tile
-  const void* truns;        // TileRun x kRuns per force tile
+  const uint32_t* hidx;     // compact halo per force tile (kHaloCap slots): j | code << 24
   const uint32_t* nbl;      // neighbour lists (engine.h)
   const int32_t* nbc;
   const int32_t* tord;      // per tile: atoms in list order (list column -> atom)

@@ -139,16 +139,14 @@ __global__ __launch_bounds__(kBlock) void k_ldesc(LearnArgs a) {
   __shared__ double hy[CAP];
   __shared__ double hz[D == 3 ? CAP : 1];
   __shared__ double sh[32][4];
-  __shared__ TileRun runs[kRuns];
   const int64_t tix = g.tile_off + bt.y;
   const TileHdr hdr = reinterpret_cast<const TileHdr*>(a.thdr)[tix];
   const double t = strain_of(st->k, g.dgamma) * g.L[1];
-  if (tid < hdr.nruns) runs[tid] = reinterpret_cast<const TileRun*>(a.truns)[tix * kRuns + tid];
   if (tid >= 32 && tid < 32 + 27) code_shift(tid - 32, g.L[0], g.L[1], g.L[2], t, sh[tid - 32]);
   __syncthreads();
   const double4* P = a.pos4 + g.atom_off;
   const bool lds = hdr.halo >= 0;
-  if (lds) stage_halo<D, CAP>(hdr, runs, sh, P, hx, hy, hz);
+  if (lds) stage_halo<D, CAP>(hdr, a.hidx + tix * CAP, sh, P, hx, hy, hz);
   __syncthreads();
   const double w = (kMuHi - kMuLo) / 23.0;
   constexpr int per = kBlock / kLDescTPA;

@@ -480,7 +480,6 @@ __global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
   __shared__ double hz[D == 3 ? CAP : 1];
   __shared__ double sh[32][4];
   __shared__ PairParams spp[4];
-  __shared__ TileRun runs[kRuns];
   __shared__ double red[kForceParts][kBlock / kWave];
   constexpr int ops[kForceParts] = {0, 0, 0, 0, 1, 0, 1, 1};
 
@@ -489,12 +488,11 @@ __global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
     const int64_t tix = g.tile_off + bt.y;
     const TileHdr hdr = reinterpret_cast<const TileHdr*>(a.thdr)[tix];
     const double t = slot_tilt(g, stp);
-    if (tid < hdr.nruns) runs[tid] = reinterpret_cast<const TileRun*>(a.truns)[tix * kRuns + tid];
     if (tid >= 32 && tid < 32 + 27) code_shift(tid - 32, g.L[0], g.L[1], g.L[2], t, sh[tid - 32]);
     if (tid >= 64 && tid < 68) spp[tid - 64] = a.pp[tid - 64];
     __syncthreads();
     if (hdr.halo >= 0) {
-      stage_halo<D, CAP>(hdr, runs, sh, a.pos4 + g.atom_off, hx, hy, hz);
+      stage_halo<D, CAP>(hdr, a.hidx + tix * CAP, sh, a.pos4 + g.atom_off, hx, hy, hz);
       if (tid == kBlock - 1) {   // the far fill slot (the builder keeps halos below CAP)
         hx[CAP - 1] = kFarFill;
         hy[CAP - 1] = kFarFill;

@@ -3,18 +3,21 @@
 // A force tile is a segment of one cell row (fixed y, z): the atoms of a row
 // (one contiguous range of the cell-sorted order) are cut into tiles_per_row
 // segments of nearly equal atom counts (about kTileAtoms each).  Its halo is
-// every (cell, periodic image) pair within one cell of the segment's cells
-// [cx0, cx1]: for each of the 3^(dim-1) neighbouring rows (dy, dz) the cells
-// x = cx0-1 .. cx1+1, as up to three runs -- the cells inside the box ("M")
-// and, when the segment touches an x face, the wrapped cell on the other side
-// ("L", image -1; "R", image +1).  Each run is a contiguous atom range.
+// candidates are every (cell, periodic image) pair within one cell of the
+// segment's cells [cx0, cx1]: for each of the 3^(dim-1) neighbouring rows
+// (dy, dz) the cells x = cx0-1 .. cx1+1, as up to three runs -- the cells
+// inside the box ("M") and, when the segment touches an x face, the wrapped
+// cell on the other side ("L", image -1; "R", image +1).  Each run is a
+// contiguous atom range; the runs number the candidates.
 //
-// The neighbour-list builder writes, per tile, a header and its run table
-// (TileHdr, TileRun).  The force kernel loads them with one read, stages the
-// halo positions (image shift H n added) into LDS, and the neighbour entries
-// of the tile's atoms hold halo indices.  A tile whose halo exceeds the LDS
-// capacity (rare: dense fluctuations) keeps global indices and image codes
-// and its force loop gathers from global memory.
+// The neighbour-list builder keeps, per tile, the candidates that some list
+// of the tile names -- its compact halo, about half of the candidates -- and
+// writes a header (TileHdr) and the compact halo as j | image code << 24.
+// The force kernel stages the compact halo positions (image shift H n added)
+// into LDS, and the neighbour entries of the tile's atoms hold byte offsets
+// of compact halo slots.  A tile whose compact halo exceeds the LDS capacity
+// (rare: dense fluctuations) keeps global indices and image codes and its
+// force loop gathers from global memory.
 #pragma once
 
 #include "engine.h"
@@ -23,17 +26,19 @@ namespace aqs {
 
 constexpr int kRuns = 27;  // (dz, dy, part): 3 x 3 x 3 (2D uses dz = 0 only)
 constexpr int kTileSort = 1024;  // tiles up to this many atoms are walked by list length
+constexpr int kHaloWords = 128;  // candidate bitmap of the builder: tiles with more candidates
+                                 // (32 kHaloWords) keep global entries
 
 struct TileHdr {
   int32_t a0, a1;   // atom range [a0, a1) of the tile
-  int32_t nruns;    // runs in the table (non-empty ones, in halo order)
-  int32_t halo;     // halo atoms; -1: halo too large, entries are global
+  int32_t pad_;
+  int32_t halo;     // atoms of the compact halo; -1: too large, entries are global
 };
 
 struct TileRun {
   int32_t src;      // first atom of the run (slot-local)
   int32_t count;
-  int32_t off;      // halo offset of the run
+  int32_t off;      // candidate number of the run's first atom
   int32_t code;     // image code (ix+1) + 3 (iy+1) + 9 (iz+1)
 };
 
@@ -94,49 +99,34 @@ __device__ __forceinline__ void code_shift(int code, double Lx, double Ly, doubl
   s[2] = (double)iz * Lz;
 }
 
-// Stage a tile's halo into LDS (image shifts sh[code] applied), by the whole
-// block of kBlock threads: thread tid takes halo slots tid, tid + kBlock, ...
-// The run of each slot is found by a fixed five-step binary search over the
-// run offsets (kRuns <= 32), all of the thread's slots advancing together so
-// that their LDS reads overlap; then all of the thread's loads are issued
-// before its LDS stores.  The caller synchronises the block afterwards.
+// Stage a tile's compact halo into LDS (image shifts sh[code] applied), by
+// the whole block of kBlock threads: thread tid takes halo slots tid,
+// tid + kBlock, ...; hidx holds the tile's slots as j | code << 24.  All of
+// the thread's index loads, then all of its position loads are issued before
+// its LDS stores.  The caller synchronises the block afterwards.
 template <int D, int CAP>
-__device__ __forceinline__ void stage_halo(const TileHdr& hdr, const TileRun* runs,
+__device__ __forceinline__ void stage_halo(const TileHdr& hdr, const uint32_t* hidx,
                                            const double (*sh)[4], const double4* P, double* hx,
                                            double* hy, double* hz) {
-  static_assert(kRuns <= 32, "the run search takes five steps");
   const int tid = threadIdx.x;
   constexpr int SU = (CAP + kBlock - 1) / kBlock;
-  const int last = hdr.nruns - 1;
-  int rix[SU];
+  uint32_t e[SU];
 #pragma unroll
-  for (int u = 0; u < SU; ++u) rix[u] = 0;
-  // largest r with runs[r].off <= h (runs[0].off = 0)
-#pragma unroll
-  for (int step = 16; step >= 1; step >>= 1) {
-#pragma unroll
-    for (int u = 0; u < SU; ++u) {
-      const int h = tid + u * kBlock;
-      const int c = rix[u] + step;
-      const int oc = runs[max(min(c, last), 0)].off;   // read unconditionally
-      const bool take = (c <= last) & (oc <= h);
-      rix[u] = take ? c : rix[u];
-    }
+  for (int u = 0; u < SU; ++u) {
+    const int h = tid + u * kBlock;
+    e[u] = h < hdr.halo ? hidx[h] : 0u;
   }
   double4 p[SU];
 #pragma unroll
   for (int u = 0; u < SU; ++u) {
     const int h = tid + u * kBlock;
-    if (h < hdr.halo) {
-      const TileRun r = runs[rix[u]];
-      p[u] = P[r.src + (h - r.off)];
-    }
+    if (h < hdr.halo) p[u] = P[e[u] & kIdxMask];
   }
 #pragma unroll
   for (int u = 0; u < SU; ++u) {
     const int h = tid + u * kBlock;
     if (h < hdr.halo) {
-      const int code = runs[rix[u]].code;
+      const int code = (int)(e[u] >> kCodeShift);
       hx[h] = p[u].x + sh[code][0];
       hy[h] = p[u].y + sh[code][1];
       if (D == 3) hz[h] = p[u].z + sh[code][2];
