@@ -32,7 +32,7 @@ constexpr int kForceParts = 8;        // doubles per tile partial of the force k
 constexpr int kMaxTPA = 8;            // threads per atom of the force kernel: 1, 2, 4 or 8
 // LDS halo capacity (atoms) of a force tile: its compact halo (the atoms
 // some list of the tile names) plus the far fill slot
-constexpr int kHaloCap3 = 1536;       // 3D
+constexpr int kHaloCap3 = 1248;       // 3D (with the rest of the force kernel's LDS: 5 blocks per CU)
 constexpr int kHaloCap2 = 1024;       // 2D
 __host__ __device__ constexpr int halo_cap(int dim) { return dim == 3 ? kHaloCap3 : kHaloCap2; }
 constexpr uint32_t kIdxMask = 0x00FFFFFFu;

@@ -82,7 +82,7 @@ __device__ __forceinline__ double slot_tilt(const Geom& g, const State* st) {
 // reciprocal estimate refined by two Newton-Raphson steps (r <- r (2 - x r)),
 // within 1 ulp of the rounded quotient.
 
-constexpr int kChunk = 4;
+constexpr int kChunk = 2;
 // Fourth word of a buffer resource on gfx9-family GPUs (raw 32-bit data,
 // offsets in bytes).
 constexpr int kBufferFlags = 0x00020000;
@@ -455,12 +455,14 @@ __device__ __forceinline__ void force_tile(const IterArgs& a, const Geom& g, int
 }
 
 // Force kernel: one block per force tile (a segment of a cell row, tiles.h).
+// Sized for five wavefronts per SIMD: at most 96 VGPRs (pairs walked two at
+// a time) and under 32 KB of LDS per block (the compact halo capacity).
 // The block reads the tile's header and halo run table, stages the halo into
 // LDS (image shifts applied), then TPA lanes per atom walk each neighbour
 // list.  Writes F and the tile partials (E, |F|^2, F.v, |v|^2, max |F_i|^2,
 // W_xy, non-finite); k_control combines them.
 template <int D, int TPA>
-__global__ __launch_bounds__(kBlock) void k_force(IterArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_force(IterArgs a) {
   const int2 bt = a.ftiles[blockIdx.x];
   const int rep = bt.x;
   if (rep < 0) return;
