@@ -428,14 +428,25 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   __syncthreads();
   for (int k = tid; k < nt; k += kBlock) nbc[a0 + k] = (int32_t)s_row[s_src[k]];
   __syncthreads();
+  // the used rows (A rows up, then B rows down) go through LDS as many at a
+  // time as fit in s_row, so each thread keeps several loads in flight
   uint32_t* Lt = a.nbl + g.nb_off + a0;
   const int rows_a = min(s_max[0], a.max_nb), rows_b = min(s_max[1], a.max_nb);
-  for (int q = 0; q < rows_a + rows_b; ++q) {
-    const int r = q < rows_a ? q : a.max_nb - 1 - (q - rows_a);
-    uint32_t* row = Lt + (int64_t)r * g.npad;
-    for (int k = tid; k < nt; k += kBlock) s_row[k] = row[k];
+  const int nq = rows_a + rows_b;
+  const int per = max(1, kTileSort / max(nt, 1));
+  for (int q0 = 0; q0 < nq; q0 += per) {
+    const int ne = min(per, nq - q0) * nt;
+    for (int e = tid; e < ne; e += kBlock) {
+      const int q = q0 + e / nt;
+      const int r = q < rows_a ? q : a.max_nb - 1 - (q - rows_a);
+      s_row[e] = Lt[(int64_t)r * g.npad + e % nt];
+    }
     __syncthreads();
-    for (int k = tid; k < nt; k += kBlock) row[k] = final_entry(s_row[s_src[k]]);
+    for (int e = tid; e < ne; e += kBlock) {
+      const int q = q0 + e / nt, k = e % nt;
+      const int r = q < rows_a ? q : a.max_nb - 1 - (q - rows_a);
+      Lt[(int64_t)r * g.npad + k] = final_entry(s_row[(e / nt) * nt + s_src[k]]);
+    }
     __syncthreads();
   }
 }
