@@ -175,6 +175,9 @@ def main() -> int:
     ap.add_argument("--only-plain", action="store_true", help="time the plain start only (no network)")
     ap.add_argument("--skin", type=float, default=0.3, help="Verlet skin (sigma_AA)")
     ap.add_argument("--graph", type=int, default=0, help="replay iteration blocks as hipGraphs (1/0)")
+    ap.add_argument("--live", type=int, default=1,
+                    help="live checks (1/0): checks as soon as possible, the critical chain on a stream of "
+                         "its own, rejected chains stopped; the learned form is also timed without them")
     ap.add_argument("--tuning", choices=("default", "auto", "autotune"), default="auto",
                     help="launch knobs: the defaults, the autotuner's cache, or tune when not cached")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -219,27 +222,34 @@ def main() -> int:
                                           args.train_steps, args.epochs, 1)
         eng.learned_load(model)
 
-    def one_round(Kr, start):
+    def one_round(Kr, start, live):
         eng.set_replica(glass.star, s.types, is_pos, 0)
         g = parallel.layout(1, P)[0]
         torch.cuda.synchronize()
         t = time.perf_counter()
-        out = parallel.run(eng, [g], P * Kr, Kr, P, start=start, max_rounds=1)
+        out = parallel.run(eng, [g], P * Kr, Kr, P, start=start, max_rounds=1, live=live)
         torch.cuda.synchronize()
         return time.perf_counter() - t, out, g
 
-    forms = ([] if args.no_plain else [("plain", AQS_START_PLAIN)]) + \
-        ([] if args.only_plain else [("learned", AQS_START_LEARNED)])
+    live = bool(args.live)
+    forms = ([] if args.no_plain else [("plain", AQS_START_PLAIN, live)]) + \
+        ([] if args.only_plain else [("learned", AQS_START_LEARNED, live)])
+    # the batched round without live checks, timed last: the force-kernel
+    # roofline is taken there (one stream, every chain in each launch)
+    main_form = "plain" if args.only_plain else "learned"
+    roof_form = main_form + "_batched" if live else main_form
+    if live:
+        forms.append((roof_form, AQS_START_PLAIN if args.only_plain else AQS_START_LEARNED, False))
     for _ in range(args.warmup):
-        for _, st in forms:
-            one_round(args.warmup_K, st)
+        for _, st, lv in forms:
+            one_round(args.warmup_K, st, lv)
     res_forms = {}
-    for name, st in forms:
+    for name, st, lv in forms:
         eng.counters(reset=True)
         eng.set_profiling(args.profile_every)
         tot_t, acc, comp, iters, ok, rounds, starts = 0.0, 0, 0, [], True, [], []
         for _ in range(args.steps):
-            dt, out, g = one_round(K, st)
+            dt, out, g = one_round(K, st, lv)
             tot_t += dt
             acc += out["accepted_steps"]
             comp += out["computed_steps"]
@@ -250,8 +260,12 @@ def main() -> int:
                            "rounds_of_alg1": out["rounds"], "decisions": [d.equal for d in g.decisions],
                            "anchor_iters": g.anchor_iters})
         eng.set_profiling(0)
+        star_vs_plain = None
         if name == "plain":
             eng.copy_replica(glass.star, ref_slot)
+        elif "plain" in res_forms:
+            eq, md, de = eng.compare(glass.star, ref_slot, 1e-4)   # r_star after the last round (Eq. 20)
+            star_vs_plain = {"equal": bool(eq), "max_disp": md, "de_per_atom": de}
         it = np.asarray(iters, dtype=np.float64)
         res_forms[name] = {"value": acc / tot_t, "ms_per_step": 1e3 * tot_t / args.steps,
                            "computed_steps_per_s": comp / tot_t,
@@ -259,23 +273,27 @@ def main() -> int:
                                                    "p95": float(np.percentile(it, 95))},
                            "all_converged": bool(ok), "rounds": rounds, "counters": eng.counters(),
                            "starts": {"plain": starts.count(0), "learned": starts.count(1),
-                                      "fallback": starts.count(2)}}
-    main_form = "plain" if args.only_plain else "learned"
+                                      "fallback": starts.count(2)},
+                           "live_checks": bool(lv), "final_star_vs_plain": star_vs_plain}
     lr = res_forms[main_form]
-    cnt = lr["counters"]
+    cnt = res_forms[roof_form]["counters"]
     # inherent-structure agreement of the two forms: same decisions, same final r_star (Eq. 20)
     comparison = None
     if "plain" in res_forms and "learned" in res_forms:
         pl = res_forms["plain"]
         same_dec = [r["decisions"] for r in lr["rounds"]] == [r["decisions"] for r in pl["rounds"]]
-        eq, md, de = eng.compare(glass.star, ref_slot, 1e-4)   # r_star after the last round of each form
-        comparison = {"same_decisions": bool(same_dec), "final_star_equal": bool(eq),
-                      "final_star_max_disp": md, "final_star_de_per_atom": de,
-                      "is_mismatches": int((not eq) + (not same_dec)),
+        fs = lr["final_star_vs_plain"]
+        eq = all(f["final_star_vs_plain"]["equal"] for k, f in res_forms.items() if k != "plain")
+        same_all = all([r["decisions"] for r in f["rounds"]] == [r["decisions"] for r in pl["rounds"]]
+                       for f in res_forms.values())
+        comparison = {"same_decisions": bool(same_dec), "final_star_equal": bool(fs["equal"]),
+                      "final_star_max_disp": fs["max_disp"], "final_star_de_per_atom": fs["de_per_atom"],
+                      "every_form_same_decisions_and_final_star": bool(eq and same_all),
+                      "is_mismatches": int((not fs["equal"]) + (not same_dec)),
                       "iters_ratio_learned_over_plain": lr["fire_iters_per_step"]["mean"]
                       / pl["fire_iters_per_step"]["mean"],
                       "wall_ratio_learned_over_plain": lr["ms_per_step"] / pl["ms_per_step"]}
-    # roofline of the force kernel in the learned-start rounds
+    # roofline of the force kernel in the batched round (one stream)
     flops_per_atom = 0.5 * nb * FLOPS_PER_PAIR
     avg_ms = cnt["force_ms"] / max(cnt["force_timed"], 1)
     evals = cnt.get("atom_evals", 0)
@@ -299,8 +317,9 @@ def main() -> int:
         "config": {"workload": f"{dim}D binary LJ glass N={n}, Algorithm 1 round: P={P} chains x K={K} "
                                f"fine AQS steps, dgamma={dg:g}, dgamma_c={K * dg:g}, FIRE to max|F|<1e-10, "
                                + ("plain start" if args.only_plain else
-                                  "learned start (plain start timed alongside)"),
-                   "dim": dim, "n_atoms": n, "P": P, "K": K, "dgamma": dg,
+                                  "learned start (plain start timed alongside)")
+                               + (", live checks" if live else ""),
+                   "dim": dim, "n_atoms": n, "P": P, "K": K, "dgamma": dg, "live_checks": live,
                    "knobs": {"threads_per_atom": eng.tuning.threads_per_atom, "skin": eng.tuning.skin,
                              "block_iters": eng.tuning.block_iters, "use_graph": eng.tuning.use_graph,
                              "source": args.tuning}},
@@ -310,6 +329,8 @@ def main() -> int:
         "learned_start": {"starts": lr["starts"], "training": train_info},
         "plain": None if args.only_plain else
         {k: v for k, v in res_forms.get("plain", {}).items() if k != "counters"},
+        "batched": None if not live else
+        {k: v for k, v in res_forms[roof_form].items() if k != "counters"},
         "learned_vs_plain": comparison,
         "quench_s": quench_s,
         "mean_neighbours_in_cutoff": nb,

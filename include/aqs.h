@@ -58,6 +58,8 @@ typedef int32_t aqs_status;
 #define AQS_MAXITER 1    /* max_iter updates done */
 #define AQS_STALLED 2    /* more than n_neg_max consecutive P <= 0 */
 #define AQS_NONFINITE 3  /* energy or a force not finite */
+#define AQS_CANCELLED 4  /* record only: not run, the chain was stopped after a
+                            failed check of aqs_run_round */
 
 /* start of the minimisation after each fine affine step */
 #define AQS_START_PLAIN 0    /* the affine image F r (Eq. 12) */
@@ -191,6 +193,42 @@ aqs_status aqs_affine_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
 aqs_status aqs_minimize_batch(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
                               int32_t start_mode, const int32_t* n_steps,
                               const int32_t* snap_dst, aqs_step_record* records);
+
+/* Outcome of check i of a round (Algorithm 1, Sec. 3.5): the end of chain
+ * i-1 against the first inherent structure of chain i, Eq. (20). */
+typedef struct {
+  int32_t decided;     /* 1: evaluated; 0: not reached (a check before it failed) */
+  int32_t equal;       /* max_disp < delta_eq */
+  double max_disp;     /* max over atom ids of the minimum-image distance */
+  double de_per_atom;  /* (E_end(i-1) - E_first(i)) / N */
+} aqs_check;
+
+/* Level II and the sequential checks of one round of Algorithm 1 (Sec. 3.5):
+ * chain i (slot chain[i], already at its level-I start) gets its first
+ * minimisation, then n_steps[i] fine AQS steps, as in aqs_minimize_batch;
+ * the first inherent structure of chain i >= 1 is copied into snap[i].
+ * Check i = 1 .. P-1 compares the end of chain i-1 with snap[i] (Eq. 20);
+ * the first check that fails rejects chains i .. P-1.
+ *
+ * live = 0: every chain runs to completion in one batched launch sequence on
+ * the context stream, then the checks are taken in order.
+ * live = 1: the checks are taken as soon as both of their configurations
+ * exist, and after a failed check the rejected chains are stopped at their
+ * next read-back (the live check the paper proposes in its discussion of
+ * load balance, Sec. 4).  The chain whose end the next check needs runs on a
+ * second stream of its own, the other chains in one batch on the context
+ * stream, so the critical chain does not wait on the batch.  Decisions,
+ * accepted steps and every kept inherent structure are those of live = 0
+ * (the minimisations do not depend on which slots share a launch).
+ *
+ * chain[P], snap[P] (snap[0] unused), n_steps[P]: host arrays; distinct slots
+ * of equal atom count.  records: host, P x (max n_steps + 1), as in
+ * aqs_minimize_batch; entries of a stopped chain after its last finished
+ * minimisation read AQS_CANCELLED.  checks: host, P entries (entry 0 unused).
+ * Synchronises. */
+aqs_status aqs_run_round(aqs_ctx* ctx, int32_t P, const int32_t* chain, const int32_t* snap,
+                         const int32_t* n_steps, int32_t start_mode, double delta_eq,
+                         int32_t live, aqs_step_record* records, aqs_check* checks);
 
 /* Equality test of Eq. (20) between two slots at the same strain index:
  * max_disp = max over atom ids of |minimum image (r_a,i - r_b,i)|,

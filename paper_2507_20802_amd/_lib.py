@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaqs.so")
 
 AQS_OK, AQS_EINVAL, AQS_EHIP, AQS_ENOMEM, AQS_ECAPACITY, AQS_ESTATE = 0, -1, -2, -3, -4, -5
-AQS_CONVERGED, AQS_MAXITER, AQS_STALLED, AQS_NONFINITE = 0, 1, 2, 3
+AQS_CONVERGED, AQS_MAXITER, AQS_STALLED, AQS_NONFINITE, AQS_CANCELLED = 0, 1, 2, 3, 4
 AQS_START_PLAIN, AQS_START_LEARNED, AQS_START_FALLBACK = 0, 1, 2
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -45,6 +45,11 @@ class aqs_tuning(ctypes.Structure):
 class aqs_step_record(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("energy", ctypes.c_double), ("max_f", ctypes.c_double),
                 ("sigma_xy", ctypes.c_double), ("status", ctypes.c_int32), ("start", ctypes.c_int32)]
+
+
+class aqs_check(ctypes.Structure):
+    _fields_ = [("decided", ctypes.c_int32), ("equal", ctypes.c_int32), ("max_disp", ctypes.c_double),
+                ("de_per_atom", ctypes.c_double)]
 
 
 class aqs_counters(ctypes.Structure):
@@ -89,6 +94,9 @@ SIGNATURES = {
     "aqs_affine_shear": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int32_p, c_int64_p]),
     "aqs_minimize_batch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int32_p, ctypes.c_int32,
                                             c_int32_p, c_int32_p, ctypes.POINTER(aqs_step_record)]),
+    "aqs_run_round": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int32_p, c_int32_p, c_int32_p,
+                                       ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.POINTER(aqs_step_record), ctypes.POINTER(aqs_check)]),
     "aqs_compare_configs": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                              ctypes.c_double, c_int32_p, c_double_p, c_double_p]),
     "aqs_stress": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p, c_double_p]),

@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "aqs.h"
@@ -83,9 +85,9 @@ int segments_per_row(int n, int rows, int tpa) {
 struct Layout {
   size_t total = 0;
   size_t o_geom, o_state, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
-      o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl,
-      o_tbl2, o_reps, o_nc3, o_overflow, o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_talt4, o_evals, o_xref4, o_ftbl, o_ttbl, o_thdr, o_hidx, o_sel,
-      o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl, o_lftbl, o_lsel, o_tord;
+      o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl[2],
+      o_tbl2[2], o_reps[2], o_nc3[2], o_overflow[2], o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_talt4, o_evals, o_xref4, o_ftbl[2], o_ttbl[2], o_thdr, o_hidx, o_sel[2],
+      o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl[2], o_lftbl[2], o_lsel[2], o_tord;
   int64_t atoms = 0;      // padded atoms over all slots
   int64_t nb_entries = 0;
   int32_t blocks = 0;
@@ -172,12 +174,19 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_tpos4 = take(sizeof(double4) * A);
   for (int a = 0; a < 3; ++a) lo.o_tv[a] = take(sizeof(double) * A);
   lo.o_tid = take(sizeof(int32_t) * A);
-  lo.o_tbl = take(sizeof(int2) * ((size_t)lo.blocks + 8));
-  lo.o_tbl2 = take(sizeof(int2) * ((size_t)lo.blocks + 8));
-  lo.o_reps = take(sizeof(int32_t) * n_rep);
-  lo.o_sel = take(sizeof(int32_t) * n_rep);
-  lo.o_nc3 = take(sizeof(int32_t) * kGridInts * n_rep);
-  lo.o_overflow = take(sizeof(int32_t));
+  for (int l = 0; l < 2; ++l) {   // per driver lane
+    lo.o_tbl[l] = take(sizeof(int2) * ((size_t)lo.blocks + 8));
+    lo.o_tbl2[l] = take(sizeof(int2) * ((size_t)lo.blocks + 8));
+    lo.o_reps[l] = take(sizeof(int32_t) * n_rep);
+    lo.o_sel[l] = take(sizeof(int32_t) * n_rep);
+    lo.o_nc3[l] = take(sizeof(int32_t) * kGridInts * n_rep);
+    lo.o_overflow[l] = take(sizeof(int32_t));
+    lo.o_ftbl[l] = take(sizeof(int2) * ((size_t)lo.tiles + 8));
+    lo.o_ttbl[l] = take(sizeof(int2) * ((size_t)lo.tiles + 8));
+    lo.o_ltbl[l] = take(sizeof(int2) * ((size_t)lo.blocks + 8));
+    lo.o_lftbl[l] = take(sizeof(int2) * ((size_t)lo.tiles + 8));
+    lo.o_lsel[l] = take(sizeof(int32_t) * n_rep);
+  }
   lo.o_dg = take(sizeof(double) * n_rep);
   lo.o_red = take(sizeof(double) * 10 * ((size_t)lo.blocks + 8));
   for (int a = 0; a < 3; ++a) lo.o_dl[a] = take(sizeof(double) * A);
@@ -186,15 +195,10 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_talt4 = take(sizeof(double4) * A);
   lo.o_evals = take(sizeof(unsigned long long));
   lo.o_xref4 = take(sizeof(double4) * A);
-  lo.o_ftbl = take(sizeof(int2) * ((size_t)lo.tiles + 8));
-  lo.o_ttbl = take(sizeof(int2) * ((size_t)lo.tiles + 8));
   lo.o_zbuf = take(sizeof(uint16_t) * kFeat * A);
   lo.o_lpart = take(sizeof(double) * kLearnParts * ((size_t)lo.blocks + 8));
   lo.o_mlp = take(sizeof(MlpDev));
   lo.o_mlpw = take(sizeof(float) * kNumParams);
-  lo.o_ltbl = take(sizeof(int2) * ((size_t)lo.blocks + 8));
-  lo.o_lftbl = take(sizeof(int2) * ((size_t)lo.tiles + 8));
-  lo.o_lsel = take(sizeof(int32_t) * n_rep);
   lo.o_tord = take(sizeof(int32_t) * A);
   lo.total = off;
   return AQS_OK;
@@ -204,6 +208,31 @@ template <class T>
 T* at(char* base, size_t off) {
   return reinterpret_cast<T*>(base + off);
 }
+
+// Launch state of one stream of the minimisation driver: launch tables
+// (device, and pinned host staging) over its selection of slots, the rebuild
+// and learned-start tables, its neighbour-list overflow flag and a captured
+// iteration block.  Lane 0 runs on the context stream; lane 1, on a stream of
+// its own, carries the critical chain of a live round (aqs_run_round).
+struct Lane {
+  hipStream_t s = nullptr;
+  int2 *tbl = nullptr, *ftbl = nullptr, *tbl2 = nullptr, *ttbl = nullptr;
+  int2 *ltbl = nullptr, *lftbl = nullptr;
+  int32_t *sel_d = nullptr, *reps_d = nullptr, *nc3_d = nullptr, *lsel_d = nullptr;
+  int32_t* overflow = nullptr;
+  int2 *h_tbl = nullptr, *h_ftbl = nullptr, *h_tbl2 = nullptr, *h_ttbl = nullptr;
+  int2 *h_ltbl = nullptr, *h_lftbl = nullptr;
+  int32_t *h_sel = nullptr, *h_reps = nullptr, *h_nc3 = nullptr, *h_lsel = nullptr;
+  int32_t* h_over = nullptr;
+  std::vector<int32_t> cur_sel;    // slots of the current iteration tables
+  int32_t cur_nblk = 0;
+  int32_t cur_ntiles = 0;
+  bool ftable_stale = false;       // a rebuild changed the tiles of the selection
+  hipGraphExec_t gexec = nullptr;  // captured block of FIRE iterations (use_graph)
+  int32_t g_iters = 0;
+  bool in_flight = false;          // a block of iterations launched, not yet polled
+  bool timed = false;              // ... with HIP events around its kernels
+};
 
 }  // namespace
 
@@ -230,8 +259,6 @@ struct aqs_ctx {
   int32_t *ccount, *cstart, *cellof, *order, *tid;
   double4* tpos4;
   double *tvx, *tvy, *tvz;
-  int2 *tbl, *tbl2, *ftbl, *ttbl;
-  int32_t *reps_d, *nc3_d, *overflow, *sel_d;
   double *dg_d, *red;
   double *dlx, *dly, *dlz, *tdlx, *tdly, *tdlz;
   double4 *alt4, *talt4;
@@ -245,29 +272,15 @@ struct aqs_ctx {
   MlpDev* mlp;
   float* mlpw;
   int32_t* tord;             // per tile: atoms by decreasing list length
-  int2 *ltbl, *lftbl;        // launch tables of the slots getting a learned start
-  int32_t* lsel_d;
   int mlp_dim = 0;           // 0: no network loaded
   double rd[4], rd2[4], dirs[16][3];
   // host mirrors
   State* h_state = nullptr;  // pinned
   std::vector<char> loaded, dirty;
-  // iteration table of the current selection
-  std::vector<int32_t> cur_sel;
-  int32_t cur_nblk = 0;
-  int32_t cur_ntiles = 0;
   std::vector<int32_t> tiles_now;  // force tiles of each slot's current grid
-  bool ftable_stale = false;       // a rebuild changed the tiles of the selection
-  // pinned staging of host-to-device uploads (one use per synchronisation)
-  int2 *h_tbl = nullptr, *h_ftbl = nullptr, *h_tbl2 = nullptr, *h_ttbl = nullptr;
-  int2 *h_ltbl = nullptr, *h_lftbl = nullptr;
-  int32_t* h_lsel = nullptr;
-  int32_t *h_reps = nullptr, *h_nc3 = nullptr, *h_over = nullptr, *h_sel = nullptr;
+  // driver lanes (pinned staging: one use per synchronisation of the lane)
+  Lane ln[2];
   double* h_dg = nullptr;
-  // a captured block of FIRE iterations (use_graph), valid for the current
-  // launch tables and block length
-  hipGraphExec_t gexec = nullptr;
-  int32_t g_iters = 0;
   // profiling
   int32_t prof_every = 0;
   int64_t block_count = 0;
@@ -277,12 +290,12 @@ struct aqs_ctx {
 
 namespace {
 
-IterArgs iter_args(aqs_ctx* c) {
+IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   IterArgs a{};
-  a.blocks = c->tbl;
-  a.ftiles = c->ftbl;
-  a.sel = c->sel_d;
-  a.nsel = (int32_t)c->cur_sel.size();
+  a.blocks = L.tbl;
+  a.ftiles = L.ftbl;
+  a.sel = L.sel_d;
+  a.nsel = (int32_t)L.cur_sel.size();
   a.tpa = c->tn.tpa;
   a.geom = c->d_geom;
   a.state = c->d_state;
@@ -309,18 +322,18 @@ IterArgs iter_args(aqs_ctx* c) {
   return a;
 }
 
-LearnArgs learn_args(aqs_ctx* c, int mode, float* out = nullptr) {
+LearnArgs learn_args(aqs_ctx* c, const Lane& L, int mode, float* out = nullptr) {
   LearnArgs a{};
-  a.blocks = c->tbl;
-  a.ftiles = c->ftbl;
+  a.blocks = L.tbl;
+  a.ftiles = L.ftbl;
   a.thdr = c->thdr;
   a.hidx = c->hidx;
   a.nbl = c->nbl;
   a.nbc = c->nbc;
   a.tord = c->tord;
   a.max_nb = c->tn.max_nb;
-  a.sel = c->sel_d;
-  a.nsel = (int32_t)c->cur_sel.size();
+  a.sel = L.sel_d;
+  a.nsel = (int32_t)L.cur_sel.size();
   a.mode = mode;
   a.geom = c->d_geom;
   a.state = c->d_state;
@@ -352,25 +365,24 @@ std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel);
 // Learned start of the slots waiting in PH_LDESC (known from the last
 // state read-back): descriptors, network, plain start and the checks, with
 // launch tables over exactly those slots.
-aqs_status learned_group(aqs_ctx* c, const std::vector<int32_t>& ls) {
+aqs_status learned_group(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls) {
   const std::vector<int2> tb = make_table(c, ls);
   const std::vector<int2> ft = make_tile_table(c, ls);
-  std::copy(tb.begin(), tb.end(), c->h_ltbl);
-  std::copy(ft.begin(), ft.end(), c->h_lftbl);
-  std::copy(ls.begin(), ls.end(), c->h_lsel);
-  HIPCHK(hipMemcpyAsync(c->ltbl, c->h_ltbl, sizeof(int2) * tb.size(), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->lftbl, c->h_lftbl, sizeof(int2) * ft.size(), hipMemcpyHostToDevice,
-                        c->stream));
-  HIPCHK(hipMemcpyAsync(c->lsel_d, c->h_lsel, sizeof(int32_t) * ls.size(), hipMemcpyHostToDevice,
-                        c->stream));
-  LearnArgs la = learn_args(c, 0);
-  la.blocks = c->ltbl;
-  la.ftiles = c->lftbl;
-  la.sel = c->lsel_d;
+  std::copy(tb.begin(), tb.end(), L.h_ltbl);
+  std::copy(ft.begin(), ft.end(), L.h_lftbl);
+  std::copy(ls.begin(), ls.end(), L.h_lsel);
+  HIPCHK(hipMemcpyAsync(L.ltbl, L.h_ltbl, sizeof(int2) * tb.size(), hipMemcpyHostToDevice, L.s));
+  HIPCHK(hipMemcpyAsync(L.lftbl, L.h_lftbl, sizeof(int2) * ft.size(), hipMemcpyHostToDevice, L.s));
+  HIPCHK(hipMemcpyAsync(L.lsel_d, L.h_lsel, sizeof(int32_t) * ls.size(), hipMemcpyHostToDevice,
+                        L.s));
+  LearnArgs la = learn_args(c, L, 0);
+  la.blocks = L.ltbl;
+  la.ftiles = L.lftbl;
+  la.sel = L.lsel_d;
   la.nsel = (int32_t)ls.size();
-  launch_ldesc(la, (int32_t)ft.size(), c->dim, c->stream);
-  launch_lmlp(la, (int32_t)tb.size(), c->dim, c->stream);
-  launch_lctl(la, c->stream);
+  launch_ldesc(la, (int32_t)ft.size(), c->dim, L.s);
+  launch_lmlp(la, (int32_t)tb.size(), c->dim, L.s);
+  launch_lctl(la, L.s);
   HIPCHK(hipGetLastError());
   return AQS_OK;
 }
@@ -410,22 +422,43 @@ std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
   return tbl;
 }
 
+// Host copy of every slot's state (and lane 0's overflow flag), on the
+// context stream.
 aqs_status pull_state(aqs_ctx* c) {
+  Lane& L = c->ln[0];
   HIPCHK(hipMemcpyAsync(c->h_state, c->d_state, sizeof(State) * c->n_rep, hipMemcpyDeviceToHost,
-                        c->stream));
-  HIPCHK(hipMemcpyAsync(c->h_over, c->overflow, sizeof(int32_t), hipMemcpyDeviceToHost,
-                        c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
+                        L.s));
+  HIPCHK(hipMemcpyAsync(L.h_over, L.overflow, sizeof(int32_t), hipMemcpyDeviceToHost, L.s));
+  HIPCHK(hipStreamSynchronize(L.s));
   return AQS_OK;
 }
 
-// Neighbour-list overflow recorded by a rebuild since the last check.
-aqs_status check_overflow(aqs_ctx* c) {
-  if (*c->h_over > 0) {
-    const int over = *c->h_over;
-    *c->h_over = 0;
-    HIPCHK(hipMemsetAsync(c->overflow, 0, sizeof(int32_t), c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+// Host copy of the states of the given slots (and the lane's overflow flag)
+// on the lane's stream: the only states that lane's kernels write.
+aqs_status pull_slots(aqs_ctx* c, Lane& L, const std::vector<int32_t>& slots) {
+  for (int r : slots)
+    HIPCHK(hipMemcpyAsync(c->h_state + r, c->d_state + r, sizeof(State), hipMemcpyDeviceToHost,
+                          L.s));
+  HIPCHK(hipMemcpyAsync(L.h_over, L.overflow, sizeof(int32_t), hipMemcpyDeviceToHost, L.s));
+  HIPCHK(hipStreamSynchronize(L.s));
+  return AQS_OK;
+}
+
+aqs_status push_slots(aqs_ctx* c, Lane& L, const std::vector<int32_t>& slots) {
+  for (int r : slots)
+    HIPCHK(hipMemcpyAsync(c->d_state + r, c->h_state + r, sizeof(State), hipMemcpyHostToDevice,
+                          L.s));
+  HIPCHK(hipStreamSynchronize(L.s));
+  return AQS_OK;
+}
+
+// Neighbour-list overflow recorded by a rebuild of the lane since the last check.
+aqs_status check_overflow(aqs_ctx* c, Lane& L) {
+  if (*L.h_over > 0) {
+    const int over = *L.h_over;
+    *L.h_over = 0;
+    HIPCHK(hipMemsetAsync(L.overflow, 0, sizeof(int32_t), L.s));
+    HIPCHK(hipStreamSynchronize(L.s));
     return fail(AQS_ECAPACITY, "neighbour list overflow: an atom has %d neighbours, capacity %d",
                 over, c->tn.max_nb);
   }
@@ -446,7 +479,7 @@ double tilt_of(aqs_ctx* c, int r, int64_t k) {
 
 // Rebuild cell order and neighbour lists of the given slots (positions as
 // they are on the device; h_state must be current).
-aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = false,
+aqs_status rebuild(aqs_ctx* c, Lane& L, const std::vector<int32_t>& sel, bool in_loop = false,
                    int list_mode = 0) {
   if (sel.empty()) return AQS_OK;
   const double rl = c->rc_max + c->tn.skin;
@@ -469,30 +502,28 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = f
     q[5] = list_mode;
     if (c->tiles_now[r] != q[4]) {
       c->tiles_now[r] = q[4];
-      if (std::find(c->cur_sel.begin(), c->cur_sel.end(), r) != c->cur_sel.end())
-        c->ftable_stale = true;
+      if (std::find(L.cur_sel.begin(), L.cur_sel.end(), r) != L.cur_sel.end())
+        L.ftable_stale = true;
     }
   }
   std::vector<int2> tbl = make_table(c, sel);
   std::vector<int2> ttbl = make_tile_table(c, sel);
-  std::copy(tbl.begin(), tbl.end(), c->h_tbl2);
-  std::copy(ttbl.begin(), ttbl.end(), c->h_ttbl);
-  HIPCHK(hipMemcpyAsync(c->ttbl, c->h_ttbl, sizeof(int2) * ttbl.size(), hipMemcpyHostToDevice,
-                        c->stream));
-  std::copy(sel.begin(), sel.end(), c->h_reps);
-  std::copy(nc3.begin(), nc3.end(), c->h_nc3);
-  HIPCHK(hipMemcpyAsync(c->tbl2, c->h_tbl2, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
-                        c->stream));
-  HIPCHK(hipMemcpyAsync(c->reps_d, c->h_reps, sizeof(int32_t) * sel.size(),
-                        hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->nc3_d, c->h_nc3, sizeof(int32_t) * nc3.size(), hipMemcpyHostToDevice,
-                        c->stream));
+  std::copy(tbl.begin(), tbl.end(), L.h_tbl2);
+  std::copy(ttbl.begin(), ttbl.end(), L.h_ttbl);
+  HIPCHK(hipMemcpyAsync(L.ttbl, L.h_ttbl, sizeof(int2) * ttbl.size(), hipMemcpyHostToDevice, L.s));
+  std::copy(sel.begin(), sel.end(), L.h_reps);
+  std::copy(nc3.begin(), nc3.end(), L.h_nc3);
+  HIPCHK(hipMemcpyAsync(L.tbl2, L.h_tbl2, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice, L.s));
+  HIPCHK(hipMemcpyAsync(L.reps_d, L.h_reps, sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice,
+                        L.s));
+  HIPCHK(hipMemcpyAsync(L.nc3_d, L.h_nc3, sizeof(int32_t) * nc3.size(), hipMemcpyHostToDevice,
+                        L.s));
   RebuildArgs a{};
-  a.blocks = c->tbl2;
+  a.blocks = L.tbl2;
   a.nblk = (int32_t)tbl.size();
-  a.tiles = c->ttbl;
+  a.tiles = L.ttbl;
   a.ntile_blk = (int32_t)ttbl.size();
-  a.reps = c->reps_d;
+  a.reps = L.reps_d;
   a.nreps = (int32_t)sel.size();
   a.geom = c->d_geom;
   a.state = c->d_state;
@@ -505,7 +536,7 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = f
   a.cell_count = c->ccount; a.cell_start = c->cstart; a.cell_of = c->cellof; a.order = c->order;
   a.tpos4 = c->tpos4; a.tvx = c->tvx; a.tvy = c->tvy; a.tvz = c->tvz; a.tid_ = c->tid;
   a.upart = c->upart;
-  a.overflow = c->overflow;
+  a.overflow = L.overflow;
   for (int t = 0; t < 4; ++t) a.pp[t] = c->pp[t];
   a.skin = c->tn.skin;
   a.max_nb = c->tn.max_nb;
@@ -514,7 +545,7 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = f
   a.dlx = c->dlx; a.dly = c->dly; a.dlz = c->dlz;
   a.tdlx = c->tdlx; a.tdly = c->tdly; a.tdlz = c->tdlz;
   a.alt4 = c->alt4; a.talt4 = c->talt4;
-  launch_rebuild(a, c->lo.max_cells, c->stream, c->nc3_d);
+  launch_rebuild(a, c->lo.max_cells, L.s, L.nc3_d);
   HIPCHK(hipGetLastError());
   ++c->cnt.rebuilds;
   for (int r : sel) c->dirty[r] = 0;
@@ -523,7 +554,7 @@ aqs_status rebuild(aqs_ctx* c, const std::vector<int32_t>& sel, bool in_loop = f
   if (in_loop) return AQS_OK;
   aqs_status st = pull_state(c);
   if (st) return st;
-  return check_overflow(c);
+  return check_overflow(c, L);
 }
 
 aqs_status check_slot(aqs_ctx* c, int r) {
@@ -533,78 +564,308 @@ aqs_status check_slot(aqs_ctx* c, int r) {
   return AQS_OK;
 }
 
-void drop_graph(aqs_ctx* c) {
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  c->gexec = nullptr;
-  c->g_iters = 0;
+void drop_graph(Lane& L) {
+  if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
+  L.gexec = nullptr;
+  L.g_iters = 0;
 }
 
 // M FIRE iterations (force, control, update per iteration) on the context
 // stream: replayed from a captured hipGraph when use_graph is set and the
 // stream can be captured, else launched directly.  The captured graph holds
 // kernel launches only (no memset nodes).
-aqs_status launch_block(aqs_ctx* c, const IterArgs& a, int M) {
-  if (c->tn.use_graph && c->stream != nullptr) {
-    if (!c->gexec || c->g_iters != M) {
-      drop_graph(c);
+aqs_status launch_block(aqs_ctx* c, Lane& L, const IterArgs& a, int M) {
+  if (c->tn.use_graph && L.s != nullptr) {
+    if (!L.gexec || L.g_iters != M) {
+      drop_graph(L);
       hipGraph_t graph = nullptr;
-      HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      HIPCHK(hipStreamBeginCapture(L.s, hipStreamCaptureModeThreadLocal));
       for (int it = 0; it < M; ++it) {
-        launch_force(a, c->cur_ntiles, c->dim, c->stream);
-        launch_control(a, c->stream);
-        launch_update(a, c->cur_nblk, c->dim, c->stream);
+        launch_force(a, L.cur_ntiles, c->dim, L.s);
+        launch_control(a, L.s);
+        launch_update(a, L.cur_nblk, c->dim, L.s);
       }
-      const hipError_t ce = hipStreamEndCapture(c->stream, &graph);
+      const hipError_t ce = hipStreamEndCapture(L.s, &graph);
       if (ce != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
         return fail(AQS_EHIP, "capturing the iteration block failed: %s", hipGetErrorString(ce));
       }
-      const hipError_t ie = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+      const hipError_t ie = hipGraphInstantiate(&L.gexec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (ie != hipSuccess) {
-        c->gexec = nullptr;
+        L.gexec = nullptr;
         return fail(AQS_EHIP, "instantiating the iteration block failed: %s", hipGetErrorString(ie));
       }
-      c->g_iters = M;
+      L.g_iters = M;
     }
-    HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+    HIPCHK(hipGraphLaunch(L.gexec, L.s));
     return AQS_OK;
   }
   for (int it = 0; it < M; ++it) {
-    launch_force(a, c->cur_ntiles, c->dim, c->stream);
-    launch_control(a, c->stream);
-    launch_update(a, c->cur_nblk, c->dim, c->stream);
+    launch_force(a, L.cur_ntiles, c->dim, L.s);
+    launch_control(a, L.s);
+    launch_update(a, L.cur_nblk, c->dim, L.s);
   }
   return AQS_OK;
 }
 
-aqs_status set_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
+aqs_status set_table(aqs_ctx* c, Lane& L, const std::vector<int32_t>& sel) {
   std::vector<int2> tbl = make_table(c, sel);
   std::vector<int2> ftbl = make_tile_table(c, sel);
-  std::copy(tbl.begin(), tbl.end(), c->h_tbl);
-  std::copy(ftbl.begin(), ftbl.end(), c->h_ftbl);
-  HIPCHK(hipMemcpyAsync(c->tbl, c->h_tbl, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
-                        c->stream));
-  HIPCHK(hipMemcpyAsync(c->ftbl, c->h_ftbl, sizeof(int2) * ftbl.size(), hipMemcpyHostToDevice,
-                        c->stream));
-  std::copy(sel.begin(), sel.end(), c->h_sel);
-  HIPCHK(hipMemcpyAsync(c->sel_d, c->h_sel, sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice,
-                        c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  drop_graph(c);   // the captured launches bake in the table sizes
-  c->cur_sel = sel;
-  c->cur_nblk = (int32_t)tbl.size();
-  c->cur_ntiles = (int32_t)ftbl.size();
-  c->ftable_stale = false;
+  std::copy(tbl.begin(), tbl.end(), L.h_tbl);
+  std::copy(ftbl.begin(), ftbl.end(), L.h_ftbl);
+  HIPCHK(hipMemcpyAsync(L.tbl, L.h_tbl, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice, L.s));
+  HIPCHK(hipMemcpyAsync(L.ftbl, L.h_ftbl, sizeof(int2) * ftbl.size(), hipMemcpyHostToDevice, L.s));
+  std::copy(sel.begin(), sel.end(), L.h_sel);
+  HIPCHK(hipMemcpyAsync(L.sel_d, L.h_sel, sizeof(int32_t) * sel.size(), hipMemcpyHostToDevice,
+                        L.s));
+  HIPCHK(hipStreamSynchronize(L.s));
+  drop_graph(L);   // the captured launches bake in the table sizes
+  L.cur_sel = sel;
+  L.cur_nblk = (int32_t)tbl.size();
+  L.cur_ntiles = (int32_t)ftbl.size();
+  L.ftable_stale = false;
   return AQS_OK;
 }
 
 void free_pinned(aqs_ctx* c) {
-  void* ps[] = {c->h_state, c->h_tbl, c->h_ftbl, c->h_tbl2, c->h_ttbl, c->h_reps, c->h_sel,
-                c->h_nc3, c->h_over, c->h_dg, c->h_ltbl, c->h_lftbl, c->h_lsel};
+  std::vector<void*> ps = {c->h_state, c->h_dg};
+  for (Lane& L : c->ln) {
+    for (void* p : {(void*)L.h_tbl, (void*)L.h_ftbl, (void*)L.h_tbl2, (void*)L.h_ttbl,
+                    (void*)L.h_ltbl, (void*)L.h_lftbl, (void*)L.h_sel, (void*)L.h_reps,
+                    (void*)L.h_nc3, (void*)L.h_lsel, (void*)L.h_over})
+      ps.push_back(p);
+    L.h_tbl = L.h_ftbl = L.h_tbl2 = L.h_ttbl = L.h_ltbl = L.h_lftbl = nullptr;
+    L.h_sel = L.h_reps = L.h_nc3 = L.h_lsel = L.h_over = nullptr;
+  }
   for (void* p : ps)
     if (p) (void)hipHostFree(p);
   c->h_state = nullptr;
+  c->h_dg = nullptr;
+}
+
+void reset_fire(aqs_ctx* c, State& s);
+
+// Checks and initial state of the chains of a minimisation call: slot rep
+// r = sel[i] gets its FIRE state reset, n_steps[i] fine steps and the
+// snapshot slot snap_dst[i]; lists are rebuilt.
+aqs_status start_chains(aqs_ctx* c, const std::vector<int32_t>& sel, int32_t start_mode,
+                        const int32_t* n_steps, const int32_t* snap_dst) {
+  if (start_mode != AQS_START_PLAIN && start_mode != AQS_START_LEARNED)
+    return fail(AQS_EINVAL, "unknown start mode %d", start_mode);
+  if (start_mode == AQS_START_LEARNED && c->mlp_dim != c->dim)
+    return fail(AQS_ESTATE, "the learned start needs a network (aqs_learned_load)");
+  const int n_sel = (int)sel.size();
+  std::vector<char> seen(c->n_rep, 0);
+  for (int i = 0; i < n_sel; ++i) {
+    aqs_status st = check_slot(c, sel[i]);
+    if (st) return st;
+    if (seen[sel[i]]) return fail(AQS_EINVAL, "slot %d selected twice", sel[i]);
+    seen[sel[i]] = 1;
+    const int ns = n_steps ? n_steps[i] : 0;
+    if (ns < 0 || ns + 1 > c->tn.log_cap)
+      return fail(AQS_ECAPACITY, "n_steps %d outside [0, %d]", ns, c->tn.log_cap - 1);
+    if (snap_dst && snap_dst[i] >= 0) {
+      const int d = snap_dst[i];
+      if (d >= c->n_rep || c->lo.geom[d].n != c->lo.geom[sel[i]].n)
+        return fail(AQS_EINVAL, "snapshot slot %d invalid for slot %d", d, sel[i]);
+    }
+  }
+  if (snap_dst)
+    for (int i = 0; i < n_sel; ++i)
+      if (snap_dst[i] >= 0 && seen[snap_dst[i]])
+        return fail(AQS_EINVAL, "snapshot slot %d is also being minimised", snap_dst[i]);
+  aqs_status st = pull_state(c);
+  if (st) return st;
+  st = rebuild(c, c->ln[0], sel);
+  if (st) return st;
+  for (int i = 0; i < n_sel; ++i) {
+    State& s = c->h_state[sel[i]];
+    reset_fire(c, s);
+    s.phase = PH_FIRE;
+    s.status = -1;
+    s.step = 0;
+    s.n_steps = n_steps ? n_steps[i] : 0;
+    s.snap_dst = snap_dst ? snap_dst[i] : -1;
+    s.do_snap = 0;
+    s.start_mode = start_mode;
+    s.start_used = AQS_START_PLAIN;
+  }
+  return push_state(c);
+}
+
+bool lane_active(const aqs_ctx* c, const Lane& L) {
+  for (int r : L.cur_sel)
+    if (c->h_state[r].phase != PH_DONE) return true;
+  return false;
+}
+
+// One block of block_iters FIRE iterations over the lane's selection (after
+// the learned-start kernels for its slots waiting in PH_LDESC); with
+// allow_timed, every prof_every-th block brackets its kernels with events.
+aqs_status lane_launch(aqs_ctx* c, Lane& L, int32_t start_mode, bool allow_timed) {
+  const bool timed = allow_timed && c->prof_every > 0 && (c->block_count % c->prof_every) == 0;
+  const int M = c->tn.block_iters;
+  if (timed) {
+    while ((int)c->ev.size() < 4 * M) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      c->ev.push_back(e);
+    }
+  }
+  if (start_mode == AQS_START_LEARNED) {
+    // slots that finished a minimisation since the last read-back wait in
+    // PH_LDESC: descriptors, network and plain start for them now
+    std::vector<int32_t> ls;
+    for (int r : L.cur_sel)
+      if (c->h_state[r].phase == PH_LDESC) ls.push_back(r);
+    if (!ls.empty()) {
+      aqs_status st = learned_group(c, L, ls);
+      if (st) return st;
+    }
+  }
+  const IterArgs a = iter_args(c, L);
+  if (timed) {
+    for (int it = 0; it < M; ++it) {
+      // events bracket the force kernel alone and the update kernel alone
+      HIPCHK(hipEventRecord(c->ev[4 * it + 0], L.s));
+      launch_force(a, L.cur_ntiles, c->dim, L.s);
+      HIPCHK(hipEventRecord(c->ev[4 * it + 1], L.s));
+      launch_control(a, L.s);
+      HIPCHK(hipEventRecord(c->ev[4 * it + 2], L.s));
+      launch_update(a, L.cur_nblk, c->dim, L.s);
+      HIPCHK(hipEventRecord(c->ev[4 * it + 3], L.s));
+    }
+  } else {
+    aqs_status st = launch_block(c, L, a, M);
+    if (st) return st;
+  }
+  HIPCHK(hipGetLastError());
+  c->cnt.force_launches += M;
+  if (allow_timed) ++c->block_count;
+  L.in_flight = true;
+  L.timed = timed;
+  return AQS_OK;
+}
+
+// Read-back after a lane's block: its slots' states (all_states: every
+// slot's, on the context stream), the overflow flag, event times; then the
+// rebuilds its slots asked for (they resume on the device).  active: slots
+// of the lane not yet done.
+aqs_status lane_poll(aqs_ctx* c, Lane& L, bool all_states, int& active) {
+  aqs_status st = all_states ? pull_state(c) : pull_slots(c, L, L.cur_sel);
+  if (st) return st;
+  st = check_overflow(c, L);
+  if (st) return st;
+  ++c->cnt.host_polls;
+  L.in_flight = false;
+  if (L.timed) {
+    const int M = c->tn.block_iters;
+    for (int it = 0; it < M; ++it) {
+      float f = 0.f, u = 0.f;
+      HIPCHK(hipEventElapsedTime(&f, c->ev[4 * it + 0], c->ev[4 * it + 1]));
+      HIPCHK(hipEventElapsedTime(&u, c->ev[4 * it + 2], c->ev[4 * it + 3]));
+      c->cnt.force_ms += f;
+      c->cnt.update_ms += u;
+    }
+    c->cnt.force_timed += M;
+    c->cnt.update_timed += M;
+    L.timed = false;
+  }
+  std::vector<int32_t> rb;
+  active = 0;
+  for (int r : L.cur_sel) {
+    const int ph = c->h_state[r].phase;
+    if (ph == PH_REBUILD) rb.push_back(r);
+    if (ph != PH_DONE) ++active;
+  }
+  if (!active || rb.empty()) return AQS_OK;
+  st = rebuild(c, L, rb, true);
+  if (st) return st;
+  if (L.ftable_stale) return set_table(c, L, L.cur_sel);   // a grid changed its tile count
+  return AQS_OK;
+}
+
+// Equality test of Eq. (20) between two idle slots, on the lane's stream
+// (their states are read on that stream first).
+aqs_status compare_slots(aqs_ctx* c, Lane& L, int32_t ra, int32_t rb, double delta_eq,
+                         aqs_check* out) {
+  const Geom& g = c->lo.geom[ra];
+  aqs_status st = pull_slots(c, L, std::vector<int32_t>{ra, rb});
+  if (st) return st;
+  if (c->h_state[ra].k != c->h_state[rb].k)
+    return fail(AQS_EINVAL, "slots %d and %d are at different strain indices (%lld vs %lld)", ra,
+                rb, (long long)c->h_state[ra].k, (long long)c->h_state[rb].k);
+  const int nb = (g.n + kBlock - 1) / kBlock;
+  launch_compare(c->d_geom, ra, rb, g.n, c->pos4, c->inv, g.L[0], g.L[1], g.L[2],
+                 tilt_of(c, ra, c->h_state[ra].k), c->dim, c->red, L.s);
+  HIPCHK(hipGetLastError());
+  std::vector<double> part(nb);
+  HIPCHK(hipMemcpyAsync(part.data(), c->red, sizeof(double) * nb, hipMemcpyDeviceToHost, L.s));
+  HIPCHK(hipStreamSynchronize(L.s));
+  double m = 0.0;
+  for (double v : part) m = std::max(m, v);
+  out->decided = 1;
+  out->equal = (m < delta_eq) ? 1 : 0;
+  out->max_disp = m;
+  out->de_per_atom = (c->h_state[ra].E - c->h_state[rb].E) / (double)g.n;
+  return AQS_OK;
+}
+
+// End of a minimisation call (all lanes idle): slots back to PH_IDLE,
+// snapshot slots marked loaded, records copied.  A cancelled chain keeps the
+// records of its finished minimisations; its later ones read AQS_CANCELLED.
+aqs_status finish_chains(aqs_ctx* c, const std::vector<int32_t>& sel, const int32_t* n_steps,
+                         const int32_t* snap_dst, const std::vector<char>& cancelled,
+                         aqs_step_record* records) {
+  const int n_sel = (int)sel.size();
+  int max_steps = 0;
+  for (int i = 0; i < n_sel; ++i) max_steps = std::max(max_steps, n_steps ? n_steps[i] : 0);
+  std::vector<int> done(n_sel);
+  for (int i = 0; i < n_sel; ++i) {
+    const int r = sel[i];
+    // minimisations finished: 0 .. step, or 0 .. step - 1 when stopped early
+    done[i] = cancelled[i] ? c->h_state[r].step : c->h_state[r].step + 1;
+    c->h_state[r].phase = PH_IDLE;
+    if (snap_dst && snap_dst[i] >= 0 && done[i] >= 1) {
+      c->loaded[snap_dst[i]] = 1;
+      c->dirty[snap_dst[i]] = 1;
+    }
+  }
+  aqs_status st = push_state(c);
+  if (st) return st;
+  if (!records) return AQS_OK;
+  const int stride = max_steps + 1;
+  std::vector<StepRecord> tmp(c->tn.log_cap);
+  for (int i = 0; i < n_sel; ++i) {
+    const int r = sel[i];
+    const int ns = done[i];
+    if (ns > 0)
+      HIPCHK(hipMemcpy(tmp.data(), c->log + (int64_t)r * c->tn.log_cap, sizeof(StepRecord) * ns,
+                       hipMemcpyDeviceToHost));
+    for (int s = 0; s < ns && s < stride; ++s) {
+      aqs_step_record& o = records[(int64_t)i * stride + s];
+      o.iters = tmp[s].iters;
+      o.energy = tmp[s].energy;
+      o.max_f = tmp[s].max_f;
+      o.sigma_xy = tmp[s].sigma_xy;
+      o.status = tmp[s].status;
+      o.start = tmp[s].start;
+    }
+    if (cancelled[i]) {
+      const int last = n_steps ? n_steps[i] : 0;
+      for (int s = ns; s <= last && s < stride; ++s) {
+        aqs_step_record& o = records[(int64_t)i * stride + s];
+        o.iters = 0;
+        o.energy = 0.0;
+        o.max_f = 0.0;
+        o.sigma_xy = 0.0;
+        o.status = AQS_CANCELLED;
+        o.start = AQS_START_PLAIN;
+      }
+    }
+  }
+  return AQS_OK;
 }
 
 void reset_fire(aqs_ctx* c, State& s) {
@@ -715,16 +976,23 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->tpos4 = at<double4>(w, lo.o_tpos4);
   c->tvx = at<double>(w, lo.o_tv[0]); c->tvy = at<double>(w, lo.o_tv[1]); c->tvz = at<double>(w, lo.o_tv[2]);
   c->tid = at<int32_t>(w, lo.o_tid);
-  c->tbl = at<int2>(w, lo.o_tbl);
-  c->tbl2 = at<int2>(w, lo.o_tbl2);
-  c->ftbl = at<int2>(w, lo.o_ftbl);
-  c->ttbl = at<int2>(w, lo.o_ttbl);
   c->thdr = at<TileHdr>(w, lo.o_thdr);
   c->hidx = at<uint32_t>(w, lo.o_hidx);
-  c->reps_d = at<int32_t>(w, lo.o_reps);
-  c->sel_d = at<int32_t>(w, lo.o_sel);
-  c->nc3_d = at<int32_t>(w, lo.o_nc3);
-  c->overflow = at<int32_t>(w, lo.o_overflow);
+  for (int l = 0; l < 2; ++l) {
+    Lane& L = c->ln[l];
+    L.tbl = at<int2>(w, lo.o_tbl[l]);
+    L.tbl2 = at<int2>(w, lo.o_tbl2[l]);
+    L.ftbl = at<int2>(w, lo.o_ftbl[l]);
+    L.ttbl = at<int2>(w, lo.o_ttbl[l]);
+    L.reps_d = at<int32_t>(w, lo.o_reps[l]);
+    L.sel_d = at<int32_t>(w, lo.o_sel[l]);
+    L.nc3_d = at<int32_t>(w, lo.o_nc3[l]);
+    L.overflow = at<int32_t>(w, lo.o_overflow[l]);
+    L.ltbl = at<int2>(w, lo.o_ltbl[l]);
+    L.lftbl = at<int2>(w, lo.o_lftbl[l]);
+    L.lsel_d = at<int32_t>(w, lo.o_lsel[l]);
+  }
+  c->ln[0].s = c->stream;   // lane 1's stream is created by the first live round
   c->dg_d = at<double>(w, lo.o_dg);
   c->red = at<double>(w, lo.o_red);
   c->dlx = at<double>(w, lo.o_dl[0]); c->dly = at<double>(w, lo.o_dl[1]); c->dlz = at<double>(w, lo.o_dl[2]);
@@ -738,29 +1006,29 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->mlp = at<MlpDev>(w, lo.o_mlp);
   c->mlpw = at<float>(w, lo.o_mlpw);
   c->tord = at<int32_t>(w, lo.o_tord);
-  c->ltbl = at<int2>(w, lo.o_ltbl);
-  c->lftbl = at<int2>(w, lo.o_lftbl);
-  c->lsel_d = at<int32_t>(w, lo.o_lsel);
 
   const size_t tcap = std::max((size_t)lo.blocks, (size_t)lo.tiles) + 16;
-  if (hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_tbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_ftbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_tbl2, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_ttbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_reps, sizeof(int32_t) * n_rep, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_sel, sizeof(int32_t) * n_rep, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_nc3, sizeof(int32_t) * kGridInts * n_rep, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_over, sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_dg, sizeof(double) * n_rep, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_ltbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_lftbl, sizeof(int2) * tcap, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_lsel, sizeof(int32_t) * n_rep, hipHostMallocDefault) != hipSuccess) {
+  bool pinned = hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) == hipSuccess &&
+                hipHostMalloc((void**)&c->h_dg, sizeof(double) * n_rep, hipHostMallocDefault) == hipSuccess;
+  for (Lane& L : c->ln)
+    pinned = pinned &&
+             hipHostMalloc((void**)&L.h_tbl, sizeof(int2) * tcap, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&L.h_ftbl, sizeof(int2) * tcap, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&L.h_tbl2, sizeof(int2) * tcap, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&L.h_ttbl, sizeof(int2) * tcap, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&L.h_ltbl, sizeof(int2) * tcap, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&L.h_lftbl, sizeof(int2) * tcap, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&L.h_reps, sizeof(int32_t) * n_rep, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&L.h_sel, sizeof(int32_t) * n_rep, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&L.h_lsel, sizeof(int32_t) * n_rep, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&L.h_nc3, sizeof(int32_t) * kGridInts * n_rep, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&L.h_over, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
+  if (!pinned) {
     free_pinned(c);
     delete c;
     return fail(AQS_EHIP, "hipHostMalloc of the host staging buffers failed");
   }
-  *c->h_over = 0;
+  for (Lane& L : c->ln) *L.h_over = 0;
   std::memset(c->h_state, 0, sizeof(State) * n_rep);
   for (int r = 0; r < n_rep; ++r) {
     c->h_state[r].phase = PH_IDLE;
@@ -788,7 +1056,11 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
 aqs_status aqs_destroy(aqs_ctx* c) {
   if (!c) return AQS_OK;
   (void)hipStreamSynchronize(c->stream);
-  drop_graph(c);
+  if (c->ln[1].s) {
+    (void)hipStreamSynchronize(c->ln[1].s);
+    (void)hipStreamDestroy(c->ln[1].s);
+  }
+  for (Lane& L : c->ln) drop_graph(L);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   free_pinned(c);
   delete c;
@@ -939,13 +1211,14 @@ aqs_status aqs_affine_shear(aqs_ctx* c, int32_t n_sel, const int32_t* rep, const
     c->h_state[sel[i]].k += dk[i];
   }
   std::vector<int2> tbl = make_table(c, sel);
-  std::copy(tbl.begin(), tbl.end(), c->h_tbl2);
+  Lane& L = c->ln[0];
+  std::copy(tbl.begin(), tbl.end(), L.h_tbl2);
   std::copy(dg.begin(), dg.end(), c->h_dg);
-  HIPCHK(hipMemcpyAsync(c->tbl2, c->h_tbl2, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
+  HIPCHK(hipMemcpyAsync(L.tbl2, L.h_tbl2, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
                         c->stream));
   HIPCHK(hipMemcpyAsync(c->dg_d, c->h_dg, sizeof(double) * c->n_rep, hipMemcpyHostToDevice,
                         c->stream));
-  launch_affine(c->tbl2, (int32_t)tbl.size(), c->d_geom, c->pos4, c->dg_d, c->stream);
+  launch_affine(L.tbl2, (int32_t)tbl.size(), c->d_geom, c->pos4, c->dg_d, c->stream);
   HIPCHK(hipGetLastError());
   return push_state(c);
 }
@@ -956,159 +1229,143 @@ aqs_status aqs_minimize_batch(aqs_ctx* c, int32_t n_sel, const int32_t* rep, int
   if (!c) return fail(AQS_EINVAL, "null context");
   if (n_sel <= 0) return AQS_OK;
   if (!rep) return fail(AQS_EINVAL, "null selection");
-  if (start_mode != AQS_START_PLAIN && start_mode != AQS_START_LEARNED)
-    return fail(AQS_EINVAL, "unknown start mode %d", start_mode);
-  if (start_mode == AQS_START_LEARNED && c->mlp_dim != c->dim)
-    return fail(AQS_ESTATE, "the learned start needs a network (aqs_learned_load)");
   std::vector<int32_t> sel(rep, rep + n_sel);
-  std::vector<char> seen(c->n_rep, 0);
-  int max_steps = 0;
-  for (int i = 0; i < n_sel; ++i) {
-    aqs_status st = check_slot(c, sel[i]);
-    if (st) return st;
-    if (seen[sel[i]]) return fail(AQS_EINVAL, "slot %d selected twice", sel[i]);
-    seen[sel[i]] = 1;
-    const int ns = n_steps ? n_steps[i] : 0;
-    if (ns < 0 || ns + 1 > c->tn.log_cap)
-      return fail(AQS_ECAPACITY, "n_steps %d outside [0, %d]", ns, c->tn.log_cap - 1);
-    max_steps = std::max(max_steps, ns);
-    if (snap_dst && snap_dst[i] >= 0) {
-      const int d = snap_dst[i];
-      if (d >= c->n_rep || c->lo.geom[d].n != c->lo.geom[sel[i]].n)
-        return fail(AQS_EINVAL, "snapshot slot %d invalid for slot %d", d, sel[i]);
-    }
-  }
-  if (snap_dst)
-    for (int i = 0; i < n_sel; ++i)
-      if (snap_dst[i] >= 0 && seen[snap_dst[i]])
-        return fail(AQS_EINVAL, "snapshot slot %d is also being minimised", snap_dst[i]);
-  aqs_status st = pull_state(c);
+  aqs_status st = start_chains(c, sel, start_mode, n_steps, snap_dst);
   if (st) return st;
-  st = rebuild(c, sel);
+  Lane& L = c->ln[0];
+  st = set_table(c, L, sel);
   if (st) return st;
-  for (int i = 0; i < n_sel; ++i) {
-    State& s = c->h_state[sel[i]];
-    reset_fire(c, s);
-    s.phase = PH_FIRE;
-    s.status = -1;
-    s.step = 0;
-    s.n_steps = n_steps ? n_steps[i] : 0;
-    s.snap_dst = snap_dst ? snap_dst[i] : -1;
-    s.do_snap = 0;
-    s.start_mode = start_mode;
-    s.start_used = AQS_START_PLAIN;
-  }
-  st = push_state(c);
-  if (st) return st;
-  st = set_table(c, sel);
-  if (st) return st;
-  launch_reset_iter(c->tbl, c->cur_nblk, c->d_geom, c->vx, c->vy, c->vz, c->upart, c->dim,
-                    c->stream);
+  launch_reset_iter(L.tbl, L.cur_nblk, c->d_geom, c->vx, c->vy, c->vz, c->upart, c->dim, L.s);
   HIPCHK(hipGetLastError());
-  IterArgs a = iter_args(c);
   for (;;) {
-    const bool timed = c->prof_every > 0 && (c->block_count % c->prof_every) == 0;
-    const int M = c->tn.block_iters;
-    if (timed && (int)c->ev.size() < 4 * M) {
-      while ((int)c->ev.size() < 4 * M) {
-        hipEvent_t e;
-        HIPCHK(hipEventCreate(&e));
-        c->ev.push_back(e);
-      }
-    }
-    if (start_mode == AQS_START_LEARNED) {
-      // slots that finished a minimisation since the last read-back wait in
-      // PH_LDESC: descriptors, network and plain start for them now
-      std::vector<int32_t> ls;
-      for (int r : sel)
-        if (c->h_state[r].phase == PH_LDESC) ls.push_back(r);
-      if (!ls.empty()) {
-        st = learned_group(c, ls);
-        if (st) return st;
-      }
-    }
-    if (timed) {
-      for (int it = 0; it < M; ++it) {
-        // events bracket the force kernel alone and the update kernel alone
-        HIPCHK(hipEventRecord(c->ev[4 * it + 0], c->stream));
-        launch_force(a, c->cur_ntiles, c->dim, c->stream);
-        HIPCHK(hipEventRecord(c->ev[4 * it + 1], c->stream));
-        launch_control(a, c->stream);
-        HIPCHK(hipEventRecord(c->ev[4 * it + 2], c->stream));
-        launch_update(a, c->cur_nblk, c->dim, c->stream);
-        HIPCHK(hipEventRecord(c->ev[4 * it + 3], c->stream));
-      }
-    } else {
-      st = launch_block(c, a, M);
-      if (st) return st;
-    }
-    HIPCHK(hipGetLastError());
-    c->cnt.force_launches += M;
-    ++c->block_count;
-    st = pull_state(c);
+    st = lane_launch(c, L, start_mode, true);
     if (st) return st;
-    st = check_overflow(c);
-    if (st) return st;
-    ++c->cnt.host_polls;
-    if (timed) {
-      for (int it = 0; it < M; ++it) {
-        float f = 0.f, u = 0.f;
-        HIPCHK(hipEventElapsedTime(&f, c->ev[4 * it + 0], c->ev[4 * it + 1]));
-        HIPCHK(hipEventElapsedTime(&u, c->ev[4 * it + 2], c->ev[4 * it + 3]));
-        c->cnt.force_ms += f;
-        c->cnt.update_ms += u;
-      }
-      c->cnt.force_timed += M;
-      c->cnt.update_timed += M;
-    }
-    std::vector<int32_t> rb;
     int active = 0;
-    for (int r : sel) {
-      const int ph = c->h_state[r].phase;
-      if (ph == PH_REBUILD) rb.push_back(r);
-      if (ph != PH_DONE) ++active;
-    }
+    st = lane_poll(c, L, true, active);
+    if (st) return st;
     if (!active) break;
-    if (!rb.empty()) {
-      // rebuilt slots resume FIRE on the device (no host round trip)
-      st = rebuild(c, rb, true);
+  }
+  return finish_chains(c, sel, n_steps, snap_dst, std::vector<char>(sel.size(), 0), records);
+}
+
+
+aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int32_t* snap,
+                         const int32_t* n_steps, int32_t start_mode, double delta_eq,
+                         int32_t live, aqs_step_record* records, aqs_check* checks) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (P <= 0 || !chain || !n_steps || !checks) return fail(AQS_EINVAL, "bad round arguments");
+  if (P > 1 && !snap) return fail(AQS_EINVAL, "a round of several chains needs snapshot slots");
+  for (int i = 1; i < P; ++i)
+    if (snap[i] < 0) return fail(AQS_EINVAL, "chain %d has no snapshot slot", i);
+  std::vector<int32_t> sel(chain, chain + P), snp(P, -1);
+  for (int i = 1; i < P; ++i) snp[i] = snap[i];
+  for (int i = 0; i < P; ++i) checks[i] = aqs_check{0, 0, 0.0, 0.0};
+  aqs_status st = start_chains(c, sel, start_mode, n_steps, snp.data());
+  if (st) return st;
+  std::vector<char> cancelled(P, 0);
+  Lane& B = c->ln[0];
+  if (!live || P == 1) {
+    // all chains to completion on the context stream, then the checks in order
+    st = set_table(c, B, sel);
+    if (st) return st;
+    launch_reset_iter(B.tbl, B.cur_nblk, c->d_geom, c->vx, c->vy, c->vz, c->upart, c->dim, B.s);
+    HIPCHK(hipGetLastError());
+    for (;;) {
+      st = lane_launch(c, B, start_mode, true);
       if (st) return st;
-      if (c->ftable_stale) {  // a grid changed its tile count
-        st = set_table(c, sel);
+      int active = 0;
+      st = lane_poll(c, B, true, active);
+      if (st) return st;
+      if (!active) break;
+    }
+    for (int i = 1; i < P; ++i) {
+      st = compare_slots(c, B, chain[i - 1], snp[i], delta_eq, &checks[i]);
+      if (st) return st;
+      if (!checks[i].equal) break;
+    }
+    return finish_chains(c, sel, n_steps, snp.data(), cancelled, records);
+  }
+  // live: the critical chain (the first one whose end a pending check needs)
+  // runs alone on lane 1, the others on lane 0; each check is taken as soon
+  // as both of its configurations exist; a failed check stops the chains
+  // after it.
+  Lane& C = c->ln[1];
+  if (!C.s) HIPCHK(hipStreamCreateWithFlags(&C.s, hipStreamNonBlocking));
+  st = set_table(c, C, std::vector<int32_t>{chain[0]});
+  if (st) return st;
+  st = set_table(c, B, std::vector<int32_t>(chain + 1, chain + P));
+  if (st) return st;
+  for (Lane* L : {&C, &B}) {
+    launch_reset_iter(L->tbl, L->cur_nblk, c->d_geom, c->vx, c->vy, c->vz, c->upart, c->dim, L->s);
+    HIPCHK(hipGetLastError());
+  }
+  int next = 1;   // next check
+  for (;;) {
+    for (Lane* L : {&C, &B})
+      if (!L->in_flight && lane_active(c, *L)) {
+        st = lane_launch(c, *L, start_mode, L == &B);
         if (st) return st;
       }
-    }
-  }
-  for (int i = 0; i < n_sel; ++i) {
-    const int r = sel[i];
-    c->h_state[r].phase = PH_IDLE;
-    if (snap_dst && snap_dst[i] >= 0) {
-      c->loaded[snap_dst[i]] = 1;
-      c->dirty[snap_dst[i]] = 1;
-    }
-  }
-  st = push_state(c);
-  if (st) return st;
-  if (records) {
-    const int stride = max_steps + 1;
-    std::vector<StepRecord> tmp(c->tn.log_cap);
-    for (int i = 0; i < n_sel; ++i) {
-      const int r = sel[i];
-      const int ns = c->h_state[r].step + 1;
-      HIPCHK(hipMemcpy(tmp.data(), c->log + (int64_t)r * c->tn.log_cap, sizeof(StepRecord) * ns,
-                       hipMemcpyDeviceToHost));
-      for (int s = 0; s < ns && s < stride; ++s) {
-        aqs_step_record& o = records[(int64_t)i * stride + s];
-        o.iters = tmp[s].iters;
-        o.energy = tmp[s].energy;
-        o.max_f = tmp[s].max_f;
-        o.sigma_xy = tmp[s].sigma_xy;
-        o.status = tmp[s].status;
-        o.start = tmp[s].start;
+    if (!C.in_flight && !B.in_flight) break;
+    // wait for either lane's block
+    Lane* done = nullptr;
+    while (!done) {
+      for (Lane* L : {&C, &B}) {
+        if (!L->in_flight) continue;
+        const hipError_t q = hipStreamQuery(L->s);
+        if (q == hipSuccess) {
+          done = L;
+          break;
+        }
+        if (q != hipErrorNotReady) return fail(AQS_EHIP, "hipStreamQuery: %s", hipGetErrorString(q));
       }
+      if (!done) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    int active = 0;
+    st = lane_poll(c, *done, false, active);
+    if (st) return st;
+    // checks whose configurations are ready, in order
+    while (next < P) {
+      const int i = next;
+      if (c->h_state[chain[i - 1]].phase != PH_DONE) break;         // end of chain i-1
+      const State& si = c->h_state[chain[i]];
+      if (!(si.step >= 1 || si.phase == PH_DONE)) break;             // first IS of chain i
+      st = compare_slots(c, C, chain[i - 1], snp[i], delta_eq, &checks[i]);
+      if (st) return st;
+      // lane 0 idle before its selection changes
+      if (B.in_flight) {
+        HIPCHK(hipStreamSynchronize(B.s));
+        st = lane_poll(c, B, false, active);
+        if (st) return st;
+      }
+      ++next;
+      std::vector<int32_t> rest;
+      if (checks[i].equal) {
+        // chain i becomes the critical chain
+        for (int r : B.cur_sel)
+          if (r != chain[i]) rest.push_back(r);
+        st = set_table(c, C, std::vector<int32_t>{chain[i]});
+        if (st) return st;
+      } else {
+        // chains i .. P-1 are rejected by Algorithm 1: stop them
+        std::vector<int32_t> stop;
+        for (int j = i; j < P; ++j)
+          if (c->h_state[chain[j]].phase != PH_DONE) {
+            c->h_state[chain[j]].phase = PH_DONE;
+            cancelled[j] = 1;
+            stop.push_back(chain[j]);
+          }
+        st = push_slots(c, B, stop);
+        if (st) return st;
+        next = P;
+      }
+      st = set_table(c, B, rest);
+      if (st) return st;
     }
   }
-  return AQS_OK;
+  HIPCHK(hipStreamSynchronize(C.s));
+  HIPCHK(hipStreamSynchronize(B.s));
+  return finish_chains(c, sel, n_steps, snp.data(), cancelled, records);
 }
 
 aqs_status aqs_compare_configs(aqs_ctx* c, int32_t ra, int32_t rb, double delta_eq,
@@ -1146,10 +1403,10 @@ aqs_status aqs_stress(aqs_ctx* c, int32_t rep, double* sigma, double* energy) {
   st = pull_state(c);
   if (st) return st;
   std::vector<int32_t> sel(1, rep);
-  st = rebuild(c, sel, false, 1);  // global-index entries for the virial kernel
+  st = rebuild(c, c->ln[0], sel, false, 1);  // global-index entries for the virial kernel
   if (st) return st;
   const Geom& g = c->lo.geom[rep];
-  IterArgs a = iter_args(c);
+  IterArgs a = iter_args(c, c->ln[0]);
   launch_virial(a, rep, g.nblocks, c->dim, g.L[0], g.L[1], g.L[2], tilt_of(c, rep, c->h_state[rep].k),
                 c->red, c->stream);
   HIPCHK(hipGetLastError());
@@ -1175,15 +1432,16 @@ aqs_status aqs_energy_forces(aqs_ctx* c, int32_t rep, double* energy, double* fo
   st = pull_state(c);
   if (st) return st;
   std::vector<int32_t> sel(1, rep);
-  st = rebuild(c, sel);
+  Lane& L = c->ln[0];
+  st = rebuild(c, L, sel);
   if (st) return st;
   c->h_state[rep].phase = PH_EVAL;
   st = push_state(c);
   if (st) return st;
-  st = set_table(c, sel);
+  st = set_table(c, L, sel);
   if (st) return st;
-  IterArgs a = iter_args(c);
-  launch_force(a, c->cur_ntiles, c->dim, c->stream);
+  IterArgs a = iter_args(c, L);
+  launch_force(a, L.cur_ntiles, c->dim, c->stream);
   launch_control(a, c->stream);
   HIPCHK(hipGetLastError());
   st = pull_state(c);
@@ -1317,9 +1575,9 @@ aqs_status prepare_single(aqs_ctx* c, int32_t rep) {
   st = pull_state(c);
   if (st) return st;
   std::vector<int32_t> sel{rep};
-  st = rebuild(c, sel);
+  st = rebuild(c, c->ln[0], sel);
   if (st) return st;
-  return set_table(c, sel);
+  return set_table(c, c->ln[0], sel);
 }
 
 }  // namespace
@@ -1345,7 +1603,7 @@ aqs_status aqs_learned_features(aqs_ctx* c, int32_t rep, float* feat) {
   if (!c || !feat) return fail(AQS_EINVAL, "null argument");
   aqs_status st = prepare_single(c, rep);
   if (st) return st;
-  launch_ldesc(learn_args(c, 1, feat), c->cur_ntiles, c->dim, c->stream);
+  launch_ldesc(learn_args(c, c->ln[0], 1, feat), c->ln[0].cur_ntiles, c->dim, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   return AQS_OK;
@@ -1356,8 +1614,8 @@ aqs_status aqs_learned_predict(aqs_ctx* c, int32_t rep, float* u_hat) {
   if (c->mlp_dim != c->dim) return fail(AQS_ESTATE, "no network loaded");
   aqs_status st = prepare_single(c, rep);
   if (st) return st;
-  launch_ldesc(learn_args(c, 2), c->cur_ntiles, c->dim, c->stream);
-  launch_lmlp(learn_args(c, 1, u_hat), c->cur_nblk, c->dim, c->stream);
+  launch_ldesc(learn_args(c, c->ln[0], 2), c->ln[0].cur_ntiles, c->dim, c->stream);
+  launch_lmlp(learn_args(c, c->ln[0], 1, u_hat), c->ln[0].cur_nblk, c->dim, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   return AQS_OK;

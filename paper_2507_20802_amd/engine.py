@@ -15,10 +15,10 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _lib
-from ._lib import (AQS_START_LEARNED, AQS_START_PLAIN, aqs_fire_params, aqs_potential,
+from ._lib import (AQS_START_LEARNED, AQS_START_PLAIN, aqs_check, aqs_fire_params, aqs_potential,
                    aqs_step_record, aqs_tuning, check)
 
-STATUS_NAMES = {0: "converged", 1: "maxiter", 2: "stalled", 3: "nonfinite"}
+STATUS_NAMES = {0: "converged", 1: "maxiter", 2: "stalled", 3: "nonfinite", 4: "cancelled"}
 
 
 @dataclass
@@ -88,6 +88,17 @@ class Tuning:
         t.max_chain_steps = self.max_chain_steps
         t.threads_per_atom = self.threads_per_atom
         return t
+
+
+def _records(recs, n: int, width: int) -> np.ndarray:
+    out = np.zeros((n, width), dtype=[("iters", np.int64), ("energy", np.float64),
+                                      ("max_f", np.float64), ("sigma_xy", np.float64),
+                                      ("status", np.int32), ("start", np.int32)])
+    for i in range(n):
+        for s in range(width):
+            x = recs[i * width + s]
+            out[i, s] = (x.iters, x.energy, x.max_f, x.sigma_xy, x.status, x.start)
+    return out
 
 
 def _i32(a) -> np.ndarray:
@@ -227,14 +238,31 @@ class Engine:
                                            None if ns is None else _p(ns, ctypes.c_int32),
                                            None if sd is None else _p(sd, ctypes.c_int32), recs),
               "aqs_minimize_batch")
-        out = np.zeros((r.size, width), dtype=[("iters", np.int64), ("energy", np.float64),
-                                                 ("max_f", np.float64), ("sigma_xy", np.float64),
-                                                 ("status", np.int32), ("start", np.int32)])
-        for i in range(r.size):
-            for s in range(width):
-                x = recs[i * width + s]
-                out[i, s] = (x.iters, x.energy, x.max_f, x.sigma_xy, x.status, x.start)
-        return out
+        return _records(recs, r.size, width)
+
+    def run_round(self, chains, snaps, n_steps, start: int = AQS_START_PLAIN, delta_eq: float = 1e-4,
+                  live: bool = False):
+        """Level II and the checks of one round of Algorithm 1 (aqs_run_round):
+        chain i (already at its level-I start) is minimised, then runs
+        n_steps[i] fine steps; check i compares the end of chain i-1 with the
+        first inherent structure of chain i, copied into snaps[i].  With live,
+        checks are taken as soon as possible and chains after a failed check
+        stop.  Returns (records (P, max n_steps + 1), checks) where checks[i] =
+        (decided, equal, max_disp, dE/N) for i >= 1."""
+        c = _i32(np.atleast_1d(chains))
+        P = int(c.size)
+        sn = _i32(np.broadcast_to(np.atleast_1d(snaps), c.shape))
+        ns = _i32(np.broadcast_to(np.atleast_1d(n_steps), c.shape))
+        width = 1 + int(ns.max())
+        recs = (aqs_step_record * (P * width))()
+        for x in recs:
+            x.status = -1
+        chk = (aqs_check * P)()
+        check(self._lib.aqs_run_round(self._ctx, P, _p(c, ctypes.c_int32), _p(sn, ctypes.c_int32),
+                                      _p(ns, ctypes.c_int32), int(start), float(delta_eq), int(bool(live)),
+                                      recs, chk), "aqs_run_round")
+        checks = [(bool(x.decided), bool(x.equal), x.max_disp, x.de_per_atom) for x in chk]
+        return _records(recs, P, width), checks
 
     def compare(self, a: int, b: int, delta_eq: float = 1e-4):
         """(equal, max_disp, dE/N) of the equality test, Eq. (20)."""

@@ -16,6 +16,13 @@ Per round and glass, with r_star in its slot:
 Readings (the paper is silent): the last round is clamped to the remaining
 steps (P' = ceil(R / K) chains, the last with R - (P'-1) K steps); a round
 with a single chain accepts it; r_q is the end of chain q/K - 1.
+
+live=True runs each glass's round through aqs_run_round with live checks
+(the improvement the paper proposes in Sec. 4): a check is taken as soon as
+both of its configurations exist, the chain the next check waits on runs on a
+stream of its own, and the chains after a failed check are stopped.  The
+decisions, q and r_star are those of the batched round; glasses are then
+processed one after another.
 """
 from __future__ import annotations
 
@@ -26,7 +33,7 @@ from typing import List
 
 import numpy as np
 
-from ._lib import AQS_START_PLAIN
+from ._lib import AQS_CANCELLED, AQS_START_PLAIN
 
 
 def chain_plan(remaining: int, K: int, P: int) -> List[int]:
@@ -83,7 +90,7 @@ def layout(n_glasses: int, P: int, first: int = 0) -> List[GlassRun]:
 
 
 def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq: float = 1e-4,
-        start: int = AQS_START_PLAIN, max_rounds: int | None = None, log=None) -> dict:
+        start: int = AQS_START_PLAIN, max_rounds: int | None = None, log=None, live: bool = False) -> dict:
     """Run Algorithm 1 to n_steps accepted fine steps for every glass (each
     glass's r_star must be loaded in its star slot as an inherent structure).
     Returns timing and counts; per-glass details are filled into glasses."""
@@ -114,17 +121,33 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
         if aff:
             engine.affine_shear(aff, dks)           # level I (Eq. 18)
         t1 = time.perf_counter()
-        recs = engine.minimize(sel, n_steps=nst, snap_dst=snp, start=start)   # level II
+        rows, outcomes = {}, {}
+        if live:
+            for gi, lengths in plans.items():        # level II + live checks, glass by glass
+                g = glasses[gi]
+                p = len(lengths)
+                recs, chk = engine.run_round(g.chains[:p], [-1] + g.snaps[1:p], lengths, start=start,
+                                             delta_eq=delta_eq, live=True)
+                for i in range(p):
+                    rows[g.chains[i]] = recs[i]
+                outcomes[gi] = [(c[1], c[2], c[3]) for c in chk[1:] if c[0]]
+        else:
+            recs = engine.minimize(sel, n_steps=nst, snap_dst=snp, start=start)   # level II
+            rows = {s: recs[j] for j, s in enumerate(sel)}
         t2 = time.perf_counter()
         t_min += t2 - t1
-        row = {s: recs[j] for j, s in enumerate(sel)}
         for gi, lengths in plans.items():
             g = glasses[gi]
             q = lengths[0]
             last = 0
             checks = []
             for i in range(1, len(lengths)):
-                eq, md, de = engine.compare(g.chains[i - 1], g.snaps[i], delta_eq)   # Eq. (20)
+                if live:
+                    if i - 1 >= len(outcomes[gi]):
+                        break
+                    eq, md, de = outcomes[gi][i - 1]
+                else:
+                    eq, md, de = engine.compare(g.chains[i - 1], g.snaps[i], delta_eq)   # Eq. (20)
                 k = engine.strain_index(g.snaps[i])
                 d = Decision(rnd, i, k, eq, md, de)
                 g.decisions.append(d)
@@ -136,15 +159,20 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
                     q = i * K
                     last = i - 1
                     break
-            # bookkeeping of iterations (fine steps are records 1..len of each chain)
+            # bookkeeping of iterations (fine steps are records 1..len of each
+            # chain; a chain stopped after a failed check keeps its finished ones)
             for i, ln in enumerate(lengths):
-                r = row[g.chains[i]]
-                if np.any(r["status"][: ln + 1] != 0):
+                r = rows[g.chains[i]]
+                ran = r["status"][: ln + 1] != AQS_CANCELLED
+                if np.any(r["status"][: ln + 1][ran] != 0):
                     g.statuses_ok = False
+                if not ran[0]:
+                    continue
                 g.anchor_iters.append(int(r["iters"][0]))
-                g.step_iters.extend(int(x) for x in r["iters"][1: ln + 1])
-                g.step_starts.extend(int(x) for x in r["start"][1: ln + 1])
-                g.computed_steps += ln
+                fine = np.nonzero(ran[1:])[0] + 1
+                g.step_iters.extend(int(r["iters"][s]) for s in fine)
+                g.step_starts.extend(int(r["start"][s]) for s in fine)
+                g.computed_steps += int(fine.size)
                 if i <= last:
                     g.accepted_iters.extend(int(x) for x in r["iters"][1: ln + 1])
                     g.energies.extend(float(x) for x in r["energy"][1: ln + 1])

@@ -60,7 +60,7 @@ def test_struct_sizes_match_a_c_compiler(tmp_path):
     if gcc is None:
         pytest.skip("no C compiler")
     names = ["aqs_potential", "aqs_fire_params", "aqs_tuning", "aqs_step_record", "aqs_counters",
-             "aqs_mlp", "aqs_train_params"]
+             "aqs_mlp", "aqs_train_params", "aqs_check"]
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include "aqs.h"\nint main(void){' +
                    "".join(f'printf("%zu\\n", sizeof({n}));' for n in names) + "return 0;}\n")

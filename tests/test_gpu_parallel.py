@@ -91,3 +91,69 @@ def test_two_glasses_in_one_batch_match_the_oracle():
         assert [r["checks"] for r in g.rounds] == [r.checks for r in ref.rounds]
         H = O.strain_box(dim, L, n, dg)
         assert O.compare(eng.positions(g.star), ref.r_star[1], H)[0] < 1e-8
+
+
+@pytest.mark.parametrize("dg,K,P,n", [(4e-3, 5, 4, 20), (1e-3, 3, 3, 12)])
+def test_live_rounds_match_the_oracle(dg, K, P, n):
+    """Algorithm 1 with live checks (checks as soon as their configurations
+    exist, the critical chain on its own stream, rejected chains stopped):
+    the oracle's decisions, accepted steps per round and final r_star."""
+    from paper_2507_20802_amd import Engine, parallel
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, ofire = fire_pair()
+    ref, _ = oracle_run(pos, types, L, dim, dg, K, P, n, ofire, 1e-4)
+    eng = Engine(dim, [len(types)] * parallel.slots_needed(1, P), L, dg, fire=fire)
+    g = parallel.layout(1, P)[0]
+    eng.set_replica(g.star, types, pos, 0)
+    out = parallel.run(eng, [g], n, K, P, delta_eq=1e-4, live=True)
+    assert [r["checks"] for r in g.rounds] == [r.checks for r in ref.rounds]
+    assert [r["q"] for r in g.rounds] == [r.q for r in ref.rounds]
+    assert out["accepted_steps"] == n and out["statuses_ok"]
+    H = O.strain_box(dim, L, n, dg)
+    assert O.compare(eng.positions(g.star), ref.r_star[1], H)[0] < 1e-8
+
+
+def _round(eng, g, P, K, dg_steps, delta_eq, live):
+    """Level I from the glass in g.star, then one round through aqs_run_round."""
+    for i in range(P):
+        eng.copy_replica(g.star, g.chains[i])
+    eng.affine_shear(g.chains[1:P], [i * K for i in range(1, P)])
+    return eng.run_round(g.chains[:P], [-1] + g.snaps[1:P], [dg_steps] * P, delta_eq=delta_eq, live=live)
+
+
+@pytest.mark.parametrize("delta_eq", [1e-4, 1e-300, 1e3])
+def test_live_round_equals_batched_round(delta_eq):
+    """The same round with and without live checks: identical decisions; every
+    minimisation the live round finished has bitwise the batched round's
+    record; after the first failed check the later chains read CANCELLED
+    after their finished minimisations.  delta_eq 1e-300 fails every check
+    (all chains after chain 0 are stopped); 1e3 passes every check (the
+    critical chain moves through all chains)."""
+    from paper_2507_20802_amd import Engine, parallel
+    from paper_2507_20802_amd._lib import AQS_CANCELLED
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, _ = fire_pair()
+    P, K, dg = 4, 6, 2e-3
+    eng = Engine(dim, [len(types)] * parallel.slots_needed(1, P), L, dg, fire=fire)
+    g = parallel.layout(1, P)[0]
+    eng.set_replica(g.star, types, pos, 0)
+    rb, cb = _round(eng, g, P, K, K, delta_eq, live=False)
+    ends_b = [eng.positions(g.chains[i]) for i in range(P)]
+    rl, cl = _round(eng, g, P, K, K, delta_eq, live=True)
+    assert [c[:2] for c in cl] == [c[:2] for c in cb]
+    decided = [c for c in cb[1:] if c[0]]
+    fail = next((i for i, c in enumerate(cb[1:], 1) if c[0] and not c[1]), None)
+    if delta_eq == 1e-300:
+        assert fail == 1 and len(decided) == 1
+    if delta_eq == 1e3:
+        assert fail is None and len(decided) == P - 1
+    for i in range(P):
+        ran = rl[i]["status"] != AQS_CANCELLED
+        assert np.array_equal(rl[i][ran], rb[i][ran])
+        if fail is None or i < fail:
+            assert ran.all()
+            assert np.array_equal(eng.positions(g.chains[i]), ends_b[i])
+        else:
+            # a stopped chain: finished minimisations first, then cancelled ones
+            k = int(ran.sum())
+            assert not ran[k:].any()
