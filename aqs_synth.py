@@ -111,3 +111,19 @@ def epoch_orders(n: int, epochs: int, *seed: int) -> np.ndarray:
     """One random order of the n training samples per epoch, int32 [epochs, n]."""
     rng = rng_for(*seed)
     return np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)
+
+
+# The paper's benchmark problem (Sec. 2.2): 400 atoms of two types at one
+# atom per unit area (square cell of side 20), large to small in the golden
+# mean ratio N_L / N_S = (1 + sqrt 5) / 4.  Type 0 = small (S), 1 = large (L).
+PAPER_N = 400
+PAPER_DENSITY = 1.0
+PAPER_RATIO_LS = (1.0 + math.sqrt(5.0)) / 4.0
+
+
+def paper_sample_start(*seed: int) -> Sample:
+    """Uniform random positions in the paper's 20 x 20 cell with round(400 x_S)
+    small atoms, x_S = 1 / (1 + r), r = N_L / N_S; the melt-quenched samples
+    of the paper are not available, the caller minimises this start."""
+    x_s = 1.0 / (1.0 + PAPER_RATIO_LS)
+    return uniform_glass_start(2, PAPER_N, *seed, density=PAPER_DENSITY, x_a=x_s)

@@ -1,0 +1,150 @@
+"""Speed-up of Algorithm 1 over sequential AQS on the paper's benchmark
+problem (Sec. 2.2; Sec. 4, Eqs. 21-23), on one GPU.
+
+Workload: the 2D binary Lennard-Jones glass of Sec. 2.2 -- 400 atoms in a
+20 x 20 periodic cell, large : small = (1 + sqrt 5) / 4, sigma_SS =
+2 sin(pi/10), sigma_LL = 2 sin(pi/5), sigma_SL = 1, eps_SS = eps_SL = 1/2,
+eps_LL = 1 (Eqs. 14-15), cut at 2.5 sigma_ab -- sheared by dgamma = 1/200 for
+200 steps.  The paper's melt-quenched samples are not available: each sample
+is a seeded uniform random start minimised to an inherent structure.
+
+For every sample j and every (P, K): C_j^(S) is the wall time of the 200
+sequential AQS steps (one chain run on the device), C_j^(P,K) that of
+Algorithm 1 with P chains of K steps (parallel.run), S_j = C_j^(S) /
+C_j^(P,K), and mu, sigma are the mean and the population standard deviation
+of S_j over the samples.  The final configuration of every parallel run is
+compared with the sequential one (Eq. 20); the paper reports all of them
+equal.
+
+Everything it times runs in libaqs.so; this module only sets up the runs.
+Run as python -m paper_2507_20802_amd.speedup (prints one JSON line).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import parallel
+from ._lib import AQS_START_PLAIN
+from .engine import Engine, Fire, LJParams
+
+# Eqs. (14)-(15), type 0 = small (S), type 1 = large (L)
+SIGMA_LL = 2.0 * math.sin(math.pi / 5.0)
+SIGMA_SS = 2.0 * math.sin(math.pi / 10.0)
+SIGMA_SL = 1.0
+EPS_LL, EPS_SS, EPS_SL = 1.0, 0.5, 0.5
+N_STEPS = 200
+DGAMMA = 1.0 / 200.0
+
+
+def paper_potential() -> LJParams:
+    return LJParams(eps=((EPS_SS, EPS_SL), (EPS_SL, EPS_LL)),
+                    sigma=((SIGMA_SS, SIGMA_SL), (SIGMA_SL, SIGMA_LL)), rc_factor=2.5)
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def inherent_structure(seed: int, fire: Fire | None = None):
+    """Sample `seed` (aqs_synth.paper_sample_start(21, seed)) minimised."""
+    import aqs_synth as S
+    smp = S.paper_sample_start(21, seed)
+    eng = Engine(2, [smp.n], smp.L, DGAMMA, pot=paper_potential(), fire=fire or Fire())
+    eng.set_replica(0, smp.types, smp.pos, 0)
+    rec = eng.minimize([0])[0, 0]
+    if rec["status"] != 0:
+        raise RuntimeError(f"sample {seed}: quench status {rec['status']}")
+    return smp, eng.positions(0)
+
+
+def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq: float = 1e-4,
+             fire: Fire | None = None, log=None) -> dict:
+    """S_j^(P,K) for every sample seed and (P, K); mu and sigma per (P, K)."""
+    fire = fire or Fire()
+    pot = paper_potential()
+    per = {(P, K): {"S": [], "final_equal": [], "max_disp": [], "t_par": [], "computed": []}
+           for P in Ps for K in Ks}
+    t_seq_all, seq_iters = [], []
+    engines = {}
+    for seed in seeds:
+        smp, is_pos = inherent_structure(seed, fire)
+        n = smp.n
+        # sequential AQS: one chain of n_steps fine steps on the device
+        seq = Engine(2, [n], smp.L, DGAMMA, pot=pot, fire=fire)
+        seq.set_replica(0, smp.types, is_pos, 0)
+        seq.minimize([0], n_steps=[2])                      # warm-up
+        seq.set_replica(0, smp.types, is_pos, 0)
+        _sync()
+        t = time.perf_counter()
+        rec = seq.minimize([0], n_steps=[n_steps])
+        _sync()
+        t_seq = time.perf_counter() - t
+        seq_final = seq.positions(0)
+        t_seq_all.append(t_seq)
+        seq_iters.extend(int(x) for x in rec[0]["iters"][1:])
+        for P in Ps:
+            if P not in engines:
+                engines[P] = Engine(2, [n] * (parallel.slots_needed(1, P) + 1), smp.L, DGAMMA, pot=pot,
+                                    fire=fire)
+            eng = engines[P]
+            ref = parallel.slots_needed(1, P)
+            for K in Ks:
+                g = parallel.layout(1, P)[0]
+                eng.set_replica(g.star, smp.types, is_pos, 0)
+                _sync()
+                t = time.perf_counter()
+                out = parallel.run(eng, [g], n_steps, K, P, delta_eq=delta_eq, start=AQS_START_PLAIN,
+                                   live=live)
+                _sync()
+                t_par = time.perf_counter() - t
+                eng.set_replica(ref, smp.types, seq_final, n_steps)
+                eq, md, _ = eng.compare(g.star, ref, delta_eq)
+                d = per[(P, K)]
+                d["S"].append(t_seq / t_par)
+                d["final_equal"].append(bool(eq and out["accepted_steps"] == n_steps))
+                d["max_disp"].append(md)
+                d["t_par"].append(t_par)
+                d["computed"].append(out["computed_steps"])
+                if log:
+                    log(f"sample {seed} P {P} K {K}: S {t_seq / t_par:.2f} (seq {t_seq:.3f} s, par {t_par:.3f} s), "
+                        f"final equal {bool(eq)}")
+    table = []
+    for (P, K), d in per.items():
+        s = np.asarray(d["S"])
+        table.append({"P": P, "K": K, "mu": float(s.mean()), "sigma": float(np.sqrt(np.mean((s - s.mean()) ** 2))),
+                      "min": float(s.min()), "max": float(s.max()),
+                      "final_equal": int(sum(d["final_equal"])), "samples": int(s.size),
+                      "computed_steps_mean": float(np.mean(d["computed"])),
+                      "t_par_mean_s": float(np.mean(d["t_par"]))})
+    it = np.asarray(seq_iters, dtype=np.float64)
+    return {"table": table, "samples": len(list(seeds)), "n_steps": n_steps, "dgamma": DGAMMA,
+            "live_checks": bool(live), "t_seq_mean_s": float(np.mean(t_seq_all)),
+            "fire_iters_per_step": {"mean": float(it.mean()), "median": float(np.median(it)),
+                                    "p95": float(np.percentile(it, 95))}}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--samples", type=int, default=8)
+    ap.add_argument("--P", type=int, nargs="+", default=[4, 8, 16, 32])
+    ap.add_argument("--K", type=int, nargs="+", default=[1, 2, 6, 10, 14, 16])
+    ap.add_argument("--steps", type=int, default=N_STEPS)
+    ap.add_argument("--live", type=int, default=1)
+    args = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    res = speedups(range(args.samples), args.P, args.K, n_steps=args.steps, live=bool(args.live),
+                   log=lambda s: print(s, file=sys.stderr, flush=True))
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
