@@ -264,3 +264,42 @@ def test_graph_replay_equals_direct_launches():
     assert np.array_equal(a1, b1) and np.array_equal(a2, b2)
     assert all(np.array_equal(x, y) for x, y in zip(pa, pb))
     assert np.all(a1[:, 0]["status"] == 0)
+
+
+def test_uneven_batch_at_full_size():
+    """The uneven batch at its full size: 24 3D replicas with N drawn
+    log-uniform in [2048, 131072] and dgamma in {1e-5, 1e-4} (seeded), all in
+    one launch sequence with hipGraph-replayed iteration blocks and the tuned
+    knobs.  The quench and two AQS steps of every replica converge; sampled
+    forces of every replica match the oracle atom by atom; the smallest, the
+    median and the largest replica are certified by the oracle's own forces
+    (max|F| < 1e-10) with energies equal to the oracle's."""
+    from paper_2507_20802_amd import Tuning, autotune
+    rng = S.rng_for(5)
+    ns = [int(round(np.exp(rng.uniform(np.log(2048), np.log(131072))))) for _ in range(24)]
+    dgs = [float(rng.choice([1e-5, 1e-4])) for _ in range(24)]
+    samples = [S.uniform_glass_start(3, n, 5, r) for r, n in enumerate(ns)]
+    tn = autotune.tuned(3, ns, 24)
+    tn.use_graph = 1
+    eng = engine(3, ns, np.array([[s.L] * 3 for s in samples]), dgs, tuning=tn)
+    for r, s in enumerate(samples):
+        eng.set_replica(r, s.types, s.pos, 0)
+    q = eng.minimize(list(range(24)))
+    assert np.all(q[:, 0]["status"] == 0)
+    rec = eng.minimize(list(range(24)), n_steps=[2] * 24)
+    assert np.all(rec["status"] == 0)
+    for r, s in enumerate(samples):
+        H = O.strain_box(3, s.L, 2, dgs[r])
+        x = eng.positions(r)
+        assert eng.strain_index(r) == 2
+        idx = S.rng_for(311, r).choice(s.n, 40, replace=False)
+        _, F = eng.energy_forces(r)
+        Fo = O.forces_on(x, s.types, H, POT, idx)
+        assert np.abs(F[idx] - Fo).max() <= 1e-11 * max(1.0, np.abs(Fo).max())
+    order = np.argsort(ns)
+    for r in (order[0], order[len(order) // 2], order[-1]):
+        s = samples[r]
+        H = O.strain_box(3, s.L, 2, dgs[r])
+        Eo, Fo, _, _ = O.energy_forces(eng.positions(r), s.types, H, POT)
+        assert np.sqrt((Fo * Fo).sum(1)).max() < FTOL
+        assert abs(rec[r, 2]["energy"] - Eo) <= E_REL_TOL * abs(Eo)
