@@ -41,6 +41,12 @@ class _Fire(ctypes.Structure):
                 ("max_iter", ctypes.c_int64)]
 
 
+class _Cg(ctypes.Structure):
+    _fields_ = [("a_init", ctypes.c_double), ("sigma", ctypes.c_double), ("grow", ctypes.c_double),
+                ("dmax", ctypes.c_double), ("ftol", ctypes.c_double),
+                ("ls_max", ctypes.c_int32), ("n_fail_max", ctypes.c_int32), ("max_iter", ctypes.c_int64)]
+
+
 @dataclass
 class Potential:
     """Binary truncated-and-shifted LJ, Eq. (13); cutoff rc_ab = rc_factor sigma_ab."""
@@ -97,6 +103,29 @@ class FireParams:
         return f
 
 
+@dataclass
+class CgParams:
+    """Nonlinear conjugate gradients (see orc_cg in oracle.c): first trial
+    step, curvature constant of the line search, largest extrapolation
+    factor, largest displacement of an atom per line search, force
+    tolerance, evaluations per line search, consecutive failed searches
+    before STALLED, iteration limit."""
+    a_init: float = 0.01
+    sigma: float = 0.1
+    grow: float = 4.0
+    dmax: float = 0.1
+    ftol: float = 1e-10
+    ls_max: int = 20
+    n_fail_max: int = 5
+    max_iter: int = 1_000_000
+
+    def c(self) -> _Cg:
+        g = _Cg()
+        for k in ("a_init", "sigma", "grow", "dmax", "ftol", "ls_max", "n_fail_max", "max_iter"):
+            setattr(g, k, getattr(self, k))
+        return g
+
+
 def lib():
     global _LIB
     if _LIB is None:
@@ -108,6 +137,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_eval.restype = ctypes.c_int
         L.orc_fire.restype = ctypes.c_int
+        L.orc_cg.restype = ctypes.c_int
+        L.orc_cg_quadratic.restype = ctypes.c_int
         L.orc_compare.restype = ctypes.c_int
         L.orc_forces_on.restype = ctypes.c_int
         L.orc_min_image_valid.restype = ctypes.c_int
@@ -241,6 +272,50 @@ def fire(pos: np.ndarray, types: np.ndarray, H: np.ndarray, pot: Potential,
         raise ValueError(f"orc_fire failed ({rc})")
     ntr = min(int(it.value) + 1, trace_cap)
     return FireResult(x, int(it.value), E.value, fm.value, int(st.value), tr[:ntr].copy())
+
+
+@dataclass
+class CgResult:
+    pos: np.ndarray
+    iters: int
+    dirs: int
+    E: float
+    fmax: float
+    status: int
+
+
+def cg(pos: np.ndarray, types: np.ndarray, H: np.ndarray, pot: Potential,
+       params: CgParams | None = None) -> CgResult:
+    """The minimisation operator of Eq. (10) by nonlinear conjugate gradients
+    (Polak-Ribiere+, force-only line search; see oracle.c).  Pinned by: finite
+    termination on quadratics (at most one search direction per distinct
+    stiffness, two evaluations per search), the dimer reaching
+    2^(1/6) sigma, zero iterations at an inherent structure, E_end <=
+    E_start, the end state certified by the independent force evaluation,
+    and the same inherent structure as FIRE (Eq. 20)."""
+    params = params or CgParams()
+    x = np.ascontiguousarray(pos, dtype=np.float64).copy()
+    n, dim = x.shape
+    it, nd, E, fm, st = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    rc = lib().orc_cg(dim, n, _d(x), np.ascontiguousarray(types, dtype=np.uint8).ctypes.data_as(ctypes.c_void_p),
+                      _d(np.ascontiguousarray(H, dtype=np.float64)), ctypes.byref(pot.c(dim)),
+                      ctypes.byref(params.c()), ctypes.byref(it), ctypes.byref(nd), ctypes.byref(E),
+                      ctypes.byref(fm), ctypes.byref(st))
+    if rc != 0:
+        raise ValueError(f"orc_cg failed ({rc})")
+    return CgResult(x, int(it.value), int(nd.value), E.value, fm.value, int(st.value))
+
+
+def cg_quadratic(x0: np.ndarray, kk: np.ndarray, params: CgParams | None = None) -> CgResult:
+    """The same conjugate-gradient core on E = sum k x^2 / 2 (x0, kk: [n, dim])."""
+    params = params or CgParams()
+    x = np.ascontiguousarray(x0, dtype=np.float64).copy()
+    n, dim = x.shape
+    kk = np.ascontiguousarray(kk, dtype=np.float64)
+    it, nd, E, fm, st = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    lib().orc_cg_quadratic(dim, n, _d(x), _d(kk), ctypes.byref(params.c()), ctypes.byref(it), ctypes.byref(nd),
+                           ctypes.byref(E), ctypes.byref(fm), ctypes.byref(st))
+    return CgResult(x, int(it.value), int(nd.value), E.value, fm.value, int(st.value))
 
 
 def compare(pos_a: np.ndarray, pos_b: np.ndarray, H: np.ndarray):

@@ -495,6 +495,225 @@ int orc_fire(int dim, int n, double* pos, const uint8_t* type, const double* H,
 }
 
 /* ------------------------------------------------------------------------ */
+/* The minimisation operator of Eq. (10) by nonlinear conjugate gradients,
+ * the minimiser the paper itself uses (Sec. 2.1).  The paper names the method
+ * only; this is the Polak-Ribiere variant with non-negative beta (automatic
+ * restart) and a line search that needs forces only: it walks along the
+ * direction d to the first point where the directional derivative
+ * phi'(a) = -F(x0 + a d) . d changes sign (the nearest minimum along d, in
+ * keeping with the search for the adjacent minimum of Eq. (9)).
+ *
+ * One force evaluation per iteration.  State of a line search: origin
+ * derivative p0 = phi'(0) < 0, trial step a, the last point still descending
+ * (a_lo, p_lo) and, once found, the first point past the minimum
+ * (a_hi, p_hi).  Steps, in order, at every evaluation:
+ *
+ *   1  evaluate E, F at x
+ *   2  if the energy, a force or a position is not finite: NONFINITE
+ *      if max_i |F_i| < ftol: CONVERGED (before any update)
+ *   3  with a direction: p = -F . d, dn = max_i |d_i|, a_max = dmax / dn;
+ *      the line search ends if |p| <= sigma |p0| (the curvature condition of
+ *      strong Wolfe) or if p < 0 with a >= a_max (the displacement cap);
+ *      then beta = max(0, (|F|^2 - F . F_0) / |F_0|^2), F_0 the force at the
+ *      origin (Polak-Ribiere, non-negative), and a new direction follows (6)
+ *   4  otherwise one more evaluation in this line search; after ls_max of
+ *      them the search has failed: beta = 0 (steepest descent from x, 6) and,
+ *      after more than n_fail_max consecutive failures, STALLED
+ *   5  next trial: p < 0 -> (a_lo, p_lo) = (a, p), else (a_hi, p_hi) = (a, p);
+ *      no upper point yet: the secant through the previous and the new lower
+ *      point extrapolates, a' = a - p (a - a_lo_prev) / (p - p_lo_prev),
+ *      clamped to [1.1 a, grow a] (grow a if p <= p_lo_prev), then to a_max;
+ *      with an upper point: the secant root between the lower and the upper
+ *      point, clamped to the middle 80 % of the bracket; x += (a' - a) d
+ *   6  new direction: F . (F + beta d) = |F|^2 - beta p; if it is not
+ *      positive, beta = 0;  d = F + beta d (d = F if beta = 0);
+ *      p0 = -F . d; first trial a1 = a_prev p0_prev / p0 (the previous
+ *      search's accepted step a_prev and origin derivative p0_prev), or
+ *      a_init for the first search and after a failed one, capped at
+ *      dmax / (max_i |F_i| + beta dn) so that no atom moves more than dmax;
+ *      F_0 = F; x += a1 d
+ *   7  it += 1; if it >= max_iter: MAXITER
+ *
+ * The core takes the force field as a callback (the tests also run it on a
+ * quadratic); orc_cg applies it to the Lennard-Jones system.  On return x
+ * holds the final positions; E and fmax are those of the last evaluation.  */
+typedef struct {
+  double a_init, sigma, grow, dmax, ftol;
+  int32_t ls_max, n_fail_max;
+  int64_t max_iter;
+} orc_cg_params;
+
+typedef int (*orc_force_fn)(void* ctx, const double* x, double* F, double* E);
+
+static int cg_core(int dim, int n, double* x, orc_force_fn fn, void* ctx,
+                   const orc_cg_params* cp, int64_t* iters, int64_t* n_dirs,
+                   double* E_out, double* fmax_out, int32_t* status) {
+  const size_t nd = (size_t)n * dim;
+  double* F = (double*)calloc(nd, sizeof(double));
+  double* F0 = (double*)calloc(nd, sizeof(double));
+  double* d = (double*)calloc(nd, sizeof(double));
+  double E = 0.0, fm = 0.0;
+  int have_dir = 0;
+  double a = 0.0, a_lo = 0.0, p_lo = 0.0, a_hi = -1.0, p_hi = 0.0, p0 = 0.0, ff0 = 0.0;
+  double a_prev = 0.0, p0_prev = 0.0;
+  int64_t it = 0, dirs = 0, nls = 0, nfail = 0;
+  int st = ORC_MAXITER, rc = 0;
+  for (;;) {
+    rc = fn(ctx, x, F, &E);                                  /* 1 */
+    if (rc != 0) break;
+    int finite = isfinite(E);                                /* 2 */
+    for (size_t k = 0; k < nd; ++k)
+      if (!isfinite(x[k])) finite = 0;
+    fm = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double f2 = 0.0;
+      for (int c = 0; c < dim; ++c) f2 += F[i * dim + c] * F[i * dim + c];
+      const double fi = sqrt(f2);
+      if (!isfinite(fi)) finite = 0;
+      if (fi > fm) fm = fi;
+    }
+    if (!finite) {
+      st = ORC_NONFINITE;
+      break;
+    }
+    if (fm < cp->ftol) {
+      st = ORC_CONVERGED;
+      break;
+    }
+    double ff = 0.0;
+    for (size_t k = 0; k < nd; ++k) ff += F[k] * F[k];
+    double beta = 0.0, p = 0.0, dn = 0.0;
+    if (have_dir) {                                          /* 3 */
+      for (size_t k = 0; k < nd; ++k) p -= F[k] * d[k];
+      for (int i = 0; i < n; ++i) {
+        double d2 = 0.0;
+        for (int c = 0; c < dim; ++c) d2 += d[i * dim + c] * d[i * dim + c];
+        if (sqrt(d2) > dn) dn = sqrt(d2);
+      }
+      const double a_max = cp->dmax / dn;
+      if (fabs(p) <= cp->sigma * fabs(p0) || (p < 0.0 && a >= a_max)) {
+        double fg = 0.0;
+        for (size_t k = 0; k < nd; ++k) fg += F[k] * F0[k];
+        beta = fmax(0.0, (ff - fg) / ff0);
+        a_prev = a;
+        p0_prev = p0;
+        nfail = 0;
+      } else if (++nls > cp->ls_max) {                       /* 4 */
+        if (++nfail > cp->n_fail_max) {
+          st = ORC_STALLED;
+          break;
+        }
+        a_prev = 0.0;
+      } else {                                               /* 5 */
+        const double a_old = a_lo, p_old = p_lo;
+        if (p < 0.0) {
+          a_lo = a;
+          p_lo = p;
+        } else {
+          a_hi = a;
+          p_hi = p;
+        }
+        double an;
+        if (a_hi < 0.0) {
+          an = cp->grow * a;
+          if (p > p_old) an = fmin(fmax(a - p * (a - a_old) / (p - p_old), 1.1 * a), cp->grow * a);
+          an = fmin(an, a_max);
+        } else {
+          const double w = a_hi - a_lo;
+          an = fmin(fmax(a_lo - p_lo * w / (p_hi - p_lo), a_lo + 0.1 * w), a_hi - 0.1 * w);
+        }
+        for (size_t k = 0; k < nd; ++k) x[k] += (an - a) * d[k];
+        a = an;
+        it += 1;                                             /* 7 */
+        if (it >= cp->max_iter) {
+          st = ORC_MAXITER;
+          break;
+        }
+        continue;
+      }
+    }
+    double fd = ff - beta * p;                               /* 6 */
+    if (!(fd > 0.0)) beta = 0.0;
+    if (beta == 0.0) fd = ff;
+    double a1 = (a_prev > 0.0) ? a_prev * p0_prev / (-fd) : cp->a_init;
+    const double cap = cp->dmax / (fm + beta * dn);
+    if (a1 > cap) a1 = cap;
+    for (size_t k = 0; k < nd; ++k) {
+      d[k] = (beta == 0.0) ? F[k] : F[k] + beta * d[k];
+      F0[k] = F[k];
+      x[k] += a1 * d[k];
+    }
+    p0 = -fd;
+    ff0 = ff;
+    a = a1;
+    a_lo = 0.0;
+    p_lo = p0;
+    a_hi = -1.0;
+    nls = 0;
+    have_dir = 1;
+    dirs += 1;
+    it += 1;                                                 /* 7 */
+    if (it >= cp->max_iter) {
+      st = ORC_MAXITER;
+      break;
+    }
+  }
+  free(F);
+  free(F0);
+  free(d);
+  if (iters) *iters = it;
+  if (n_dirs) *n_dirs = dirs;
+  if (E_out) *E_out = E;
+  if (fmax_out) *fmax_out = fm;
+  if (status) *status = st;
+  return rc;
+}
+
+typedef struct {
+  int dim, n;
+  const uint8_t* type;
+  const double* H;
+  const orc_pot* p;
+} lj_system;
+
+static int lj_forces(void* ctx, const double* x, double* F, double* E) {
+  const lj_system* s = (const lj_system*)ctx;
+  return orc_eval(s->dim, s->n, x, s->type, s->H, s->p, 0, 0, E, F, NULL, NULL);
+}
+
+int orc_cg(int dim, int n, double* pos, const uint8_t* type, const double* H,
+           const orc_pot* p, const orc_cg_params* cp, int64_t* iters, int64_t* n_dirs,
+           double* E, double* fmax, int32_t* status) {
+  lj_system s = {dim, n, type, H, p};
+  return cg_core(dim, n, pos, lj_forces, &s, cp, iters, n_dirs, E, fmax, status);
+}
+
+/* E = sum_k kk_k x_k^2 / 2, F = -kk x: a test problem with a closed-form
+ * behaviour (exact secant line searches; finite termination of CG).       */
+typedef struct {
+  size_t nd;
+  const double* kk;
+} quad_system;
+
+static int quad_forces(void* ctx, const double* x, double* F, double* E) {
+  const quad_system* q = (const quad_system*)ctx;
+  double e = 0.0;
+  for (size_t k = 0; k < q->nd; ++k) {
+    F[k] = -q->kk[k] * x[k];
+    e += 0.5 * q->kk[k] * x[k] * x[k];
+  }
+  *E = e;
+  return 0;
+}
+
+int orc_cg_quadratic(int dim, int n, double* x, const double* kk, const orc_cg_params* cp,
+                     int64_t* iters, int64_t* n_dirs, double* E, double* fmax,
+                     int32_t* status) {
+  quad_system q = {(size_t)n * dim, kk};
+  return cg_core(dim, n, x, quad_forces, &q, cp, iters, n_dirs, E, fmax, status);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Configuration comparison for the equality test of Eq. (20): largest
  * minimum-image displacement between the same atom in two configurations of
  * the same box, and the mean displacement vector (a rigid-translation check).*/
