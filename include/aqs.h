@@ -53,13 +53,18 @@ typedef int32_t aqs_status;
 #define AQS_ECAPACITY (-4)  /* neighbour list or log capacity exceeded */
 #define AQS_ESTATE (-5)     /* call not valid in the current state */
 
-/* per-slot outcome of one minimisation (FIRE) */
+/* per-slot outcome of one minimisation */
 #define AQS_CONVERGED 0  /* max_i |F_i| < ftol */
 #define AQS_MAXITER 1    /* max_iter updates done */
-#define AQS_STALLED 2    /* more than n_neg_max consecutive P <= 0 */
+#define AQS_STALLED 2    /* FIRE: more than n_neg_max consecutive P <= 0;
+                            CG: more than n_fail_max failed line searches in a row */
 #define AQS_NONFINITE 3  /* energy or a force not finite */
 #define AQS_CANCELLED 4  /* record only: not run, the chain was stopped after a
                             failed check of aqs_run_round */
+
+/* minimiser of the minimisation operator of Eq. (10) (aqs_set_minimizer) */
+#define AQS_MIN_FIRE 0  /* FIRE 2.0, aqs_fire_params (the default) */
+#define AQS_MIN_CG 1    /* nonlinear conjugate gradients, aqs_cg_params */
 
 /* start of the minimisation after each fine affine step */
 #define AQS_START_PLAIN 0    /* the affine image F r (Eq. 12) */
@@ -86,6 +91,19 @@ typedef struct {
   int32_t n_delay, n_neg_max, initial_delay, pad_;
   int64_t max_iter;
 } aqs_fire_params;
+
+/* Nonlinear conjugate gradients, the paper's own minimiser (Sec. 2.1); the
+ * step order is documented at aqs_set_minimizer. */
+typedef struct {
+  double a_init;      /* first trial step of the first line search (x += a F) */
+  double sigma;       /* line search ends at |phi'(a)| <= sigma |phi'(0)|, in (0, 1) */
+  double grow;        /* largest extrapolation factor of a trial step, > 1.1 */
+  double dmax;        /* largest displacement of an atom within one line search */
+  double ftol;        /* convergence: max_i |F_i| < ftol */
+  int32_t ls_max;     /* evaluations per line search before it counts as failed */
+  int32_t n_fail_max; /* consecutive failed line searches before STALLED */
+  int64_t max_iter;
+} aqs_cg_params;
 
 /* Performance knobs.  None changes what is computed beyond the rounding of
  * one atom's force sum (its order depends on skin and threads_per_atom);
@@ -162,7 +180,8 @@ aqs_status aqs_affine_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
                             const int64_t* dk);
 
 /* Minimise the selected slots to their inherent structures (Eq. 10) with
- * FIRE 2.0, all in one batched launch sequence, then -- per slot, on the
+ * FIRE 2.0 (or the minimiser set by aqs_set_minimizer), all in one batched
+ * launch sequence, then -- per slot, on the
  * device, without returning to the host -- run n_steps[r] fine AQS steps
  * (affine map by dgamma_r, Eq. 16, then minimise again; Eq. 12).  A slot
  * stops early if a minimisation does not converge.
@@ -193,6 +212,29 @@ aqs_status aqs_affine_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
 aqs_status aqs_minimize_batch(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
                               int32_t start_mode, const int32_t* n_steps,
                               const int32_t* snap_dst, aqs_step_record* records);
+
+/* Minimiser of the later aqs_minimize_batch and aqs_run_round calls of ctx:
+ * AQS_MIN_FIRE (cg may be NULL) or AQS_MIN_CG with cg (copied).  The paper
+ * minimises with conjugate gradients (Sec. 2.1) and names no variant; this
+ * one is Polak-Ribiere with beta >= 0 and a line search on the directional
+ * derivative phi'(a) = -F(x0 + a d).d only, which stops at the nearest
+ * minimum along d.  Per slot, one force evaluation per iteration:
+ *   1 evaluate F;  2 non-finite -> NONFINITE; max_i |F_i| < ftol ->
+ *   CONVERGED (before any update);  3 with a direction d: p = phi'(a),
+ *   the search ends if |p| <= sigma |p0| or if p < 0 and a >= dmax /
+ *   max_i |d_i|; then beta = max(0, (|F|^2 - F.F0) / |F0|^2);  4 after
+ *   ls_max evaluations it has failed: beta = 0, and more than n_fail_max
+ *   failures in a row -> STALLED;  5 else the next trial: a secant step from
+ *   the last two descending points, kept in [1.1 a, grow a] and under
+ *   dmax / max_i |d_i|, or, once a point past the minimum exists, the secant
+ *   root of the bracket kept in its middle 80 %; x += (a' - a) d;
+ *   6 new direction: beta = 0 unless |F|^2 - beta p > 0; d = F + beta d;
+ *   p0 = -F.d; first trial a1 = a_prev p0_prev / p0 (a_init for the first
+ *   search and after a failed one), at most dmax / (max_i |F_i| + beta
+ *   max_i |d_old,i|); F0 = F; x += a1 d;  7 it++; it >= max_iter -> MAXITER.
+ * Records count iterations (= force evaluations before convergence) as for
+ * FIRE.  AQS_EINVAL for an unknown minimiser or parameters out of range. */
+aqs_status aqs_set_minimizer(aqs_ctx* ctx, int32_t minimizer, const aqs_cg_params* cg);
 
 /* Outcome of check i of a round (Algorithm 1, Sec. 3.5): the end of chain
  * i-1 against the first inherent structure of chain i, Eq. (20). */

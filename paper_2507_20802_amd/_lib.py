@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libaqs.so")
 AQS_OK, AQS_EINVAL, AQS_EHIP, AQS_ENOMEM, AQS_ECAPACITY, AQS_ESTATE = 0, -1, -2, -3, -4, -5
 AQS_CONVERGED, AQS_MAXITER, AQS_STALLED, AQS_NONFINITE, AQS_CANCELLED = 0, 1, 2, 3, 4
 AQS_START_PLAIN, AQS_START_LEARNED, AQS_START_FALLBACK = 0, 1, 2
+AQS_MIN_FIRE, AQS_MIN_CG = 0, 1
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -33,6 +34,12 @@ class aqs_fire_params(ctypes.Structure):
                 ("n_delay", ctypes.c_int32), ("n_neg_max", ctypes.c_int32),
                 ("initial_delay", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("max_iter", ctypes.c_int64)]
+
+
+class aqs_cg_params(ctypes.Structure):
+    _fields_ = [("a_init", ctypes.c_double), ("sigma", ctypes.c_double), ("grow", ctypes.c_double),
+                ("dmax", ctypes.c_double), ("ftol", ctypes.c_double), ("ls_max", ctypes.c_int32),
+                ("n_fail_max", ctypes.c_int32), ("max_iter", ctypes.c_int64)]
 
 
 class aqs_tuning(ctypes.Structure):
@@ -102,6 +109,7 @@ SIGNATURES = {
     "aqs_stress": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p, c_double_p]),
     "aqs_energy_forces": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p, c_double_p]),
     "aqs_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "aqs_set_minimizer": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(aqs_cg_params)]),
     "aqs_get_counters": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_counters), ctypes.c_int32]),
     "aqs_learned_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_mlp)]),
     "aqs_learned_features": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),

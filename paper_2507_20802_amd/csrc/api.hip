@@ -241,6 +241,8 @@ struct aqs_ctx {
   aqs_potential pot{};
   Tune tn{};
   FireParams fire{};
+  CgParams cg{};
+  int32_t minimizer = kMinFire;   // of later minimisation calls
   PairParams pp[4];
   double rc_max = 0.0;
   hipStream_t stream = nullptr;
@@ -313,10 +315,12 @@ IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   a.max_nb = c->tn.max_nb;
   for (int t = 0; t < 4; ++t) a.pp[t] = c->pp[t];
   a.fire = c->fire;
+  a.cg = c->cg;
   a.skin = c->tn.skin;
   a.rc_max = c->rc_max;
   a.dlx = c->dlx; a.dly = c->dly; a.dlz = c->dlz;
   a.alt4 = c->alt4;
+  a.gx = c->dlx; a.gy = c->dly; a.gz = c->dlz;
   a.evals = c->evals;
   a.xref4 = c->xref4;
   return a;
@@ -644,7 +648,7 @@ void free_pinned(aqs_ctx* c) {
   c->h_dg = nullptr;
 }
 
-void reset_fire(aqs_ctx* c, State& s);
+void reset_minimizer(aqs_ctx* c, State& s);
 
 // Checks and initial state of the chains of a minimisation call: slot rep
 // r = sel[i] gets its FIRE state reset, n_steps[i] fine steps and the
@@ -681,8 +685,9 @@ aqs_status start_chains(aqs_ctx* c, const std::vector<int32_t>& sel, int32_t sta
   if (st) return st;
   for (int i = 0; i < n_sel; ++i) {
     State& s = c->h_state[sel[i]];
-    reset_fire(c, s);
-    s.phase = PH_FIRE;
+    reset_minimizer(c, s);
+    s.minimizer = c->minimizer;
+    s.phase = (c->minimizer == kMinCG) ? PH_CG : PH_FIRE;
     s.status = -1;
     s.step = 0;
     s.n_steps = n_steps ? n_steps[i] : 0;
@@ -868,7 +873,7 @@ aqs_status finish_chains(aqs_ctx* c, const std::vector<int32_t>& sel, const int3
   return AQS_OK;
 }
 
-void reset_fire(aqs_ctx* c, State& s) {
+void reset_minimizer(aqs_ctx* c, State& s) {
   s.dt = c->fire.dt0;
   s.alpha = c->fire.alpha0;
   s.cv = 1.0;
@@ -877,6 +882,10 @@ void reset_fire(aqs_ctx* c, State& s) {
   s.nneg = 0;
   s.it = 0;
   s.restart = 0;
+  s.cg_dir = 0;
+  s.cg_newdir = 0;
+  s.cg_nfail = 0;
+  s.cg_aprev = 0.0;
 }
 
 }  // namespace
@@ -1033,7 +1042,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   for (int r = 0; r < n_rep; ++r) {
     c->h_state[r].phase = PH_IDLE;
     c->h_state[r].snap_dst = -1;
-    reset_fire(c, c->h_state[r]);
+    reset_minimizer(c, c->h_state[r]);
   }
   c->loaded.assign(n_rep, 0);
   c->dirty.assign(n_rep, 1);
@@ -1095,7 +1104,7 @@ aqs_status aqs_set_replica(aqs_ctx* c, int32_t rep, const uint8_t* types, const 
   s.E = 0.0;
   s.fmax = 0.0;
   s.status = 0;
-  reset_fire(c, s);
+  reset_minimizer(c, s);
   st = push_state(c);
   if (st) return st;
   c->loaded[rep] = 1;
@@ -1185,7 +1194,7 @@ aqs_status aqs_copy_replica(aqs_ctx* c, int32_t src, int32_t dst) {
   d.sxy = s.sxy;
   d.status = s.status;
   d.phase = PH_IDLE;
-  reset_fire(c, d);
+  reset_minimizer(c, d);
   st = push_state(c);
   if (st) return st;
   c->loaded[dst] = 1;
@@ -1469,6 +1478,33 @@ aqs_status aqs_energy_forces(aqs_ctx* c, int32_t rep, double* energy, double* fo
     for (int s = 0; s < g.n; ++s)
       for (int k = 0; k < d; ++k) forces[idv[s] * d + k] = f[k][s];
   }
+  return AQS_OK;
+}
+
+aqs_status aqs_set_minimizer(aqs_ctx* c, int32_t minimizer, const aqs_cg_params* cg) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (minimizer == AQS_MIN_FIRE) {
+    c->minimizer = kMinFire;
+    return AQS_OK;
+  }
+  if (minimizer != AQS_MIN_CG) return fail(AQS_EINVAL, "unknown minimizer %d", minimizer);
+  if (!cg) return fail(AQS_EINVAL, "AQS_MIN_CG needs its parameters");
+  if (!(cg->a_init > 0.0) || !(cg->sigma > 0.0 && cg->sigma < 1.0) || !(cg->grow > 1.1) ||
+      !(cg->dmax > 0.0) || !(cg->ftol > 0.0) || cg->ls_max < 1 || cg->n_fail_max < 0 ||
+      cg->max_iter < 1)
+    return fail(AQS_EINVAL, "conjugate-gradient parameters out of range");
+  CgParams p{};
+  p.a_init = cg->a_init;
+  p.sigma = cg->sigma;
+  p.grow = cg->grow;
+  p.dmax = cg->dmax;
+  p.ftol = cg->ftol;
+  p.ls_max = cg->ls_max;
+  p.n_fail_max = cg->n_fail_max;
+  p.max_iter = cg->max_iter;
+  c->cg = p;
+  c->minimizer = kMinCG;
+  for (Lane& L : c->ln) drop_graph(L);   // captured launches hold the parameters
   return AQS_OK;
 }
 

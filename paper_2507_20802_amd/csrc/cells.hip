@@ -461,7 +461,9 @@ __global__ void k_rb_done(RebuildArgs a) {
     st->gamma_build = strain_of(st->k, g.dgamma);
     if (a.resume && st->phase == PH_REBUILD)
       st->phase = (st->resume_phase == PH_LPLAIN || st->resume_phase == PH_LMOVE ||
-                   st->resume_phase == PH_LREVERT) ? st->resume_phase : PH_FIRE;
+                   st->resume_phase == PH_LREVERT || st->resume_phase == PH_CG)
+                      ? st->resume_phase
+                      : PH_FIRE;
   }
 }
 

@@ -54,7 +54,11 @@ enum Phase : int32_t {
                     // evaluate there, then accept (FIRE) or revert
   PH_LREVERT = 10,  // learned start rejected: update restores the plain start
   PH_LPLAIN = 12,   // learned start: evaluate at the plain start (reference E, max |F|)
+  PH_CG = 13,       // evaluate forces; conjugate-gradient control; CG update
 };
+
+// minimiser of a slot (State::minimizer; AQS_MIN_* of the public header)
+constexpr int32_t kMinFire = 0, kMinCG = 1;
 
 // start of a minimisation (StepRecord::start): the affine image, the learned
 // start, or the affine image after the learned start was rejected
@@ -64,7 +68,8 @@ __host__ __device__ inline bool phase_energy(int32_t ph) {  // evaluation also s
   return ph == PH_EVAL || ph == PH_ENERGY || ph == PH_LPLAIN || ph == PH_LMOVE;
 }
 __host__ __device__ inline bool phase_force(int32_t ph) {   // the force kernel evaluates
-  return phase_energy(ph) || ph == PH_FIRE || ph == PH_ADVANCE || ph == PH_LREVERT;
+  return phase_energy(ph) || ph == PH_FIRE || ph == PH_CG || ph == PH_ADVANCE ||
+         ph == PH_LREVERT;
 }
 
 // static per-slot geometry
@@ -94,6 +99,13 @@ struct State {
   double gamma_build; // strain at the last neighbour-list build
   double E_plain, fmax_plain;  // learned start: plain-start reference values
   double lmean[3];    // learned start: mean predicted displacement per unit strain
+  // conjugate gradients: line search along d (held in v) from x0 = x - a d
+  double cg_a;              // trial step a
+  double cg_alo, cg_plo;    // last point still descending: step, phi'(step)
+  double cg_ahi, cg_phi;    // first point past the minimum (cg_ahi < 0: none yet)
+  double cg_p0, cg_ff0;     // phi'(0) = -F(x0).d and |F(x0)|^2
+  double cg_aprev, cg_p0prev;  // accepted step and phi'(0) of the previous search
+  double cg_beta, cg_step;  // pending update: d <- F + beta d (new direction), x += step d
   int32_t npos, nneg;
   int32_t restart;    // pending update backs off x -= dt v / 2, v = 0
   int32_t phase;
@@ -111,6 +123,11 @@ struct State {
   int32_t ntiles;     // force tiles of the current grid
   int32_t list_mode;  // 0: tiles index their LDS halo; 1: global indices only
   int32_t resume_phase;  // phase to resume after a neighbour-list rebuild
+  int32_t minimizer;  // kMinFire or kMinCG
+  int32_t cg_dir;     // a search direction exists
+  int32_t cg_newdir;  // the pending update starts a new direction
+  int32_t cg_nls;     // evaluations in the current line search
+  int32_t cg_nfail;   // consecutive failed line searches
 };
 
 struct PairParams {   // per type pair t = 2 ti + tj
@@ -120,6 +137,12 @@ struct PairParams {   // per type pair t = 2 ti + tj
 struct FireParams {
   double dt0, dt_max, dt_min, f_inc, f_dec, alpha0, f_alpha, dmax, ftol;
   int32_t n_delay, n_neg_max, initial_delay, pad_;
+  int64_t max_iter;
+};
+
+struct CgParams {
+  double a_init, sigma, grow, dmax, ftol;
+  int32_t ls_max, n_fail_max;
   int64_t max_iter;
 };
 
@@ -157,10 +180,15 @@ struct IterArgs {
   int32_t max_nb;
   PairParams pp[4];
   FireParams fire;
+  CgParams cg;
   double skin, rc_max;
   // learned start (null when unused)
   double* dlx; double* dly; double* dlz;   // learned displacement per atom
   double4* alt4;                            // saved plain start
+  // conjugate gradients: F at the line-search origin.  Shares the learned
+  // displacement's arrays, which are dead once a minimisation runs (and are
+  // permuted with the atoms by every list rebuild).
+  double* gx; double* gy; double* gz;
   const double4* xref4;                     // positions at the last list build
 };
 

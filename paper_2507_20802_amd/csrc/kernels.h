@@ -40,7 +40,7 @@ struct RebuildArgs {
   double skin;
   int32_t max_nb;
   int32_t dim;
-  int32_t resume;       // 1: slots in PH_REBUILD go back to PH_FIRE
+  int32_t resume;       // 1: slots in PH_REBUILD go back to the phase they left
   // learned-start per-atom buffers permuted with the atoms (may be null):
   // predicted displacement, and the saved plain start (also wrapped with
   // the positions, so a revert restores the wrapped plain start bit for bit)

@@ -274,6 +274,10 @@ __device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
     s.restart = 0;
     s.cv = 1.0;
     s.cf = 0.0;
+    s.cg_dir = 0;
+    s.cg_newdir = 0;
+    s.cg_nfail = 0;
+    s.cg_aprev = 0.0;
     if (s.start_mode == kStartLearned) {
       // descriptors and network at this inherent structure first; the
       // strain index advances with the plain start (learned kernels)
@@ -287,6 +291,85 @@ __device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
   } else {
     s.phase = PH_FINISH;
   }
+}
+
+// Conjugate-gradient control (Eq. 10 by the paper's own minimiser, Sec. 2.1):
+// Polak-Ribiere with beta >= 0, and a line search on the directional
+// derivative phi'(a) = -F(x0 + a d).d alone (no energies) that stops at the
+// nearest minimum along d.  One evaluation per iteration; the update kernel
+// then either starts a new direction (d = F + beta d, F0 = F, x += a1 d) or
+// moves to the next trial (x += (a' - a) d).  Steps 3-6 of the minimiser:
+//   3  p = phi'(a); the search ends if |p| <= sigma |p0| or, still
+//      descending, the step has reached a_max = dmax / max_i |d_i|; then
+//      beta = max(0, (|F|^2 - F.F0) / |F0|^2)
+//   4  after ls_max evaluations in one search: beta = 0 (steepest descent);
+//      more than n_fail_max such failures in a row: STALLED
+//   5  next trial: secant extrapolation from the last two descending points,
+//      kept in [1.1 a, grow a] and under a_max; once a point past the
+//      minimum exists, the secant root of the bracket, kept in its middle 80 %
+//   6  new direction: F.d = |F|^2 - beta p (beta = 0 unless positive);
+//      first trial a_prev p0_prev / p0 (a_init for the first search and after
+//      a failed one), at most dmax / (max|F_i| + beta max|d_i|)
+// r: [1] |F|^2, [2] F.d, [3] F.F0, [8] max |d_i|^2.  Returns false if the
+// minimisation has stalled.
+__device__ bool control_cg(const CgParams& c, State& s, const double* r) {
+  const double ff = r[1];
+  double beta = 0.0, p = 0.0, dn = 0.0;
+  if (s.cg_dir) {
+    p = -r[2];
+    dn = sqrt(r[8]);
+    const double a_max = c.dmax / dn;
+    if (fabs(p) <= c.sigma * fabs(s.cg_p0) || (p < 0.0 && s.cg_a >= a_max)) {
+      beta = fmax(0.0, (ff - r[3]) / s.cg_ff0);
+      s.cg_aprev = s.cg_a;
+      s.cg_p0prev = s.cg_p0;
+      s.cg_nfail = 0;
+    } else if (++s.cg_nls > c.ls_max) {
+      if (++s.cg_nfail > c.n_fail_max) return false;
+      s.cg_aprev = 0.0;
+    } else {
+      const double at = s.cg_a, a_old = s.cg_alo, p_old = s.cg_plo;
+      if (p < 0.0) {
+        s.cg_alo = at;
+        s.cg_plo = p;
+      } else {
+        s.cg_ahi = at;
+        s.cg_phi = p;
+      }
+      double an;
+      if (s.cg_ahi < 0.0) {
+        an = c.grow * at;
+        if (p > p_old) an = fmin(fmax(at - p * (at - a_old) / (p - p_old), 1.1 * at), c.grow * at);
+        an = fmin(an, a_max);
+      } else {
+        const double w = s.cg_ahi - s.cg_alo;
+        an = fmin(fmax(s.cg_alo - s.cg_plo * w / (s.cg_phi - s.cg_plo), s.cg_alo + 0.1 * w),
+                  s.cg_ahi - 0.1 * w);
+      }
+      s.cg_newdir = 0;
+      s.cg_step = an - at;
+      s.cg_a = an;
+      return true;
+    }
+  }
+  double fd = ff - beta * p;
+  if (!(fd > 0.0)) beta = 0.0;
+  if (beta == 0.0) fd = ff;
+  double a1 = (s.cg_aprev > 0.0) ? s.cg_aprev * s.cg_p0prev / (-fd) : c.a_init;
+  const double cap = c.dmax / (s.fmax + beta * dn);
+  if (a1 > cap) a1 = cap;
+  s.cg_newdir = 1;
+  s.cg_beta = beta;
+  s.cg_step = a1;
+  s.cg_p0 = -fd;
+  s.cg_ff0 = ff;
+  s.cg_a = a1;
+  s.cg_alo = 0.0;
+  s.cg_plo = -fd;
+  s.cg_ahi = -1.0;
+  s.cg_nls = 0;
+  s.cg_dir = 1;
+  return true;
 }
 
 __device__ void control(const IterArgs& a, int rep, const Geom& g, const double* r, int phase) {
@@ -303,9 +386,11 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
   const double ub = r[7];
   const double gam = strain_of(s.k, g.dgamma);
   const double gd = fabs(gam - s.gamma_build);
+  const bool cg = (s.minimizer == kMinCG);
   if (!(gd * a.rc_max + 2.0 * (1.0 + gd) * ub < a.skin)) {
-    s.resume_phase =
-        (phase == PH_LPLAIN || phase == PH_LMOVE || phase == PH_LREVERT) ? phase : PH_FIRE;
+    s.resume_phase = (phase == PH_LPLAIN || phase == PH_LMOVE || phase == PH_LREVERT)
+                         ? phase
+                         : (cg ? PH_CG : PH_FIRE);
     s.phase = PH_REBUILD;
     a.state[rep] = s;
     return;
@@ -348,7 +433,7 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     }
     s.start_used = kStartLearned;
   }
-  s.phase = PH_FIRE;
+  s.phase = cg ? PH_CG : PH_FIRE;
   if (r[6] != 0.0 || !isfinite(r[1]) || !isfinite(r[2])) {
     s.E = NAN;
     s.sxy = NAN;
@@ -356,9 +441,23 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     a.state[rep] = s;
     return;
   }
-  if (s.fmax < a.fire.ftol) {
+  if (s.fmax < (cg ? a.cg.ftol : a.fire.ftol)) {
     s.pending = 0;
     s.phase = PH_ENERGY;
+    a.state[rep] = s;
+    return;
+  }
+  if (cg) {
+    if (!control_cg(a.cg, s, r)) {
+      s.pending = 2;
+      s.phase = PH_ENERGY;
+    } else {
+      s.it += 1;
+      if (s.it >= a.cg.max_iter) {
+        s.pending = 1;
+        s.phase = PH_ENERGY;  // energy at these positions, then the last step
+      }
+    }
     a.state[rep] = s;
     return;
   }
@@ -411,12 +510,13 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
 // and, in the last block of each slot, the FIRE control.
 
 // Force of one atom li of the tile (TPA lanes), accumulated into the
-// thread's partials (E, |F|^2, F.v, |v|^2, max |F_i|^2, W_xy, non-finite).
+// thread's partials: E, |F|^2, F.v, |v|^2 (conjugate gradients: F.F0, F0 the
+// force at the line-search origin), max |F_i|^2, W_xy, non-finite, max |v_i|^2.
 template <int D, bool WE, int TPA, bool LDS>
 __device__ __forceinline__ void force_atom(const IterArgs& a, const Geom& g, int li, int col,
                                            const double (*sh)[4], const PairParams* spp,
                                            const double* hx, const double* hy, const double* hz,
-                                           double* part) {
+                                           bool cg, double* part) {
   constexpr int CAP = (D == 3) ? kHaloCap3 : kHaloCap2;
   const int64_t gi = g.atom_off + li;
   const double4 pi = a.pos4[gi];
@@ -432,25 +532,30 @@ __device__ __forceinline__ void force_atom(const IterArgs& a, const Geom& g, int
   if (D == 3) a.fz[gi] = fz;
   const double vx = a.vx[gi], vy = a.vy[gi], vz = (D == 3) ? a.vz[gi] : 0.0;
   const double ff = fx * fx + fy * fy + fz * fz;
+  const double vv = vx * vx + vy * vy + vz * vz;
   part[0] += 0.5 * e;
   part[1] += ff;
   part[2] += fx * vx + fy * vy + fz * vz;
-  part[3] += vx * vx + vy * vy + vz * vz;
+  if (cg)
+    part[3] += fx * a.gx[gi] + fy * a.gy[gi] + ((D == 3) ? fz * a.gz[gi] : 0.0);
+  else
+    part[3] += vv;
   part[4] = fmax(part[4], ff);
   part[5] += 0.5 * w;
   if (!(isfinite(e) && isfinite(ff) && isfinite(pi.x + pi.y + pi.z))) part[6] = 1.0;
+  part[7] = fmax(part[7], vv);
 }
 
 template <int D, bool WE, int TPA, bool LDS>
 __device__ __forceinline__ void force_tile(const IterArgs& a, const Geom& g, int a0, int a1,
                                            const double (*sh)[4], const PairParams* spp,
                                            const double* hx, const double* hy, const double* hz,
-                                           double* part) {
+                                           bool cg, double* part) {
   constexpr int per = kBlock / TPA;
   for (int b = a0; b < a1; b += per) {
     const int k = b + (int)(threadIdx.x / TPA);
     if (k < a1)
-      force_atom<D, WE, TPA, LDS>(a, g, a.tord[g.atom_off + k], k, sh, spp, hx, hy, hz, part);
+      force_atom<D, WE, TPA, LDS>(a, g, a.tord[g.atom_off + k], k, sh, spp, hx, hy, hz, cg, part);
   }
 }
 
@@ -459,8 +564,8 @@ __device__ __forceinline__ void force_tile(const IterArgs& a, const Geom& g, int
 // a time) and under 32 KB of LDS per block (the compact halo capacity).
 // The block reads the tile's header and halo run table, stages the halo into
 // LDS (image shifts applied), then TPA lanes per atom walk each neighbour
-// list.  Writes F and the tile partials (E, |F|^2, F.v, |v|^2, max |F_i|^2,
-// W_xy, non-finite); k_control combines them.
+// list.  Writes F and the tile partials (force_atom); k_control combines
+// them.
 template <int D, int TPA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_force(IterArgs a) {
   const int2 bt = a.ftiles[blockIdx.x];
@@ -471,6 +576,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   const bool we = phase_energy(phase);
   const bool compute = phase_force(phase);
   if (!compute) return;
+  const bool cg = (phase == PH_CG);
   const int ntiles = stp->ntiles;
   if (bt.y >= ntiles) return;
   const Geom g = a.geom[rep];
@@ -502,20 +608,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
       }
       __syncthreads();
       if (we)
-        force_tile<D, true, TPA, true>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, part);
+        force_tile<D, true, TPA, true>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, cg, part);
       else
-        force_tile<D, false, TPA, true>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, part);
+        force_tile<D, false, TPA, true>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, cg, part);
     } else {
       if (we)
-        force_tile<D, true, TPA, false>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, part);
+        force_tile<D, true, TPA, false>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, cg, part);
       else
-        force_tile<D, false, TPA, false>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, part);
+        force_tile<D, false, TPA, false>(a, g, hdr.a0, hdr.a1, sh, spp, hx, hy, hz, cg, part);
     }
     block_reduce<kForceParts>(part, ops, red);
     if (tid == 0) {
       double* dst = a.fpart + tix * kForceParts;
 #pragma unroll
-      for (int c = 0; c < 7; ++c) dst[c] = part[c];
+      for (int c = 0; c < kForceParts; ++c) dst[c] = part[c];
     }
   }
 }
@@ -534,9 +640,10 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
   const Geom g = a.geom[rep];
   const int tid = threadIdx.x;
   const int ntiles = stp->ntiles;
-  __shared__ double red[kForceParts][kBlock / kWave];
-  constexpr int ops[kForceParts] = {0, 0, 0, 0, 1, 0, 1, 1};
-  double r[kForceParts] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // r: the tile partials 0-6, the update's max displacement, max |v_i|^2
+  __shared__ double red[kForceParts + 1][kBlock / kWave];
+  constexpr int ops[kForceParts + 1] = {0, 0, 0, 0, 1, 0, 1, 1, 1};
+  double r[kForceParts + 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (compute) {
     for (int b = tid; b < ntiles; b += kBlock) {
       const double* src = a.fpart + ((int64_t)g.tile_off + b) * kForceParts;
@@ -547,10 +654,11 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
       r[4] = fmax(r[4], src[4]);
       r[5] += src[5];
       r[6] = fmax(r[6], src[6]);
+      r[8] = fmax(r[8], src[7]);
     }
     for (int b = tid; b < g.nblocks; b += kBlock) r[7] = fmax(r[7], a.upart[g.block0 + b]);
   }
-  block_reduce<kForceParts>(r, ops, red);
+  block_reduce<kForceParts + 1>(r, ops, red);
   if (tid == 0) {
     if (compute) atomicAdd(a.evals, (unsigned long long)g.n);
     control(a, rep, g, r, phase);
@@ -558,8 +666,9 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// FIRE update (steps 5-9 of the minimiser) or the fine affine step of the
-// chain, per atom; per-block max |u_i| = |r_i - F x_ref,i| for the list test.
+// FIRE update (steps 5-9 of the minimiser), the conjugate-gradient move, or
+// the fine affine step of the chain, per atom; per-block max
+// |u_i| = |r_i - F x_ref,i| for the list test.
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
@@ -568,11 +677,13 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
   if (rep < 0) return;
   const State* st = a.state + rep;
   const int phase = st->phase;
-  const bool fire = (phase == PH_FIRE || phase == PH_STOP);
+  const bool cgmin = (st->minimizer == kMinCG);
+  const bool fire = (phase == PH_FIRE || (phase == PH_STOP && !cgmin));
+  const bool cg = (phase == PH_CG || (phase == PH_STOP && cgmin));
   const bool adv = (phase == PH_ADVANCE);
   // learned start: move to F r + dgamma (u_hat - mean u_hat), or back
   const bool lmove = (phase == PH_LMOVE || phase == PH_LREVERT);
-  if (!(fire || adv || lmove || phase == PH_FINISH)) return;
+  if (!(fire || cg || adv || lmove || phase == PH_FINISH)) return;
   const Geom g = a.geom[rep];
   const int tid = threadIdx.x;
   const int li = bt.y * kBlock + tid;
@@ -621,6 +732,33 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       a.vx[gi] = vx;
       a.vy[gi] = vy;
       if (D == 3) a.vz[gi] = vz;
+    } else if (cg) {
+      // conjugate gradients: d lives in v; a new direction also saves F0
+      double dx = a.vx[gi], dy = a.vy[gi], dz = (D == 3) ? a.vz[gi] : 0.0;
+      if (st->cg_newdir) {
+        const double fx = a.fx[gi], fy = a.fy[gi], fz = (D == 3) ? a.fz[gi] : 0.0;
+        const double b = st->cg_beta;
+        if (b == 0.0) {
+          dx = fx;
+          dy = fy;
+          dz = fz;
+        } else {
+          dx = fx + b * dx;
+          dy = fy + b * dy;
+          dz = fz + b * dz;
+        }
+        a.gx[gi] = fx;
+        a.gy[gi] = fy;
+        if (D == 3) a.gz[gi] = fz;
+        a.vx[gi] = dx;
+        a.vy[gi] = dy;
+        if (D == 3) a.vz[gi] = dz;
+      }
+      const double da = st->cg_step;
+      p.x += da * dx;
+      p.y += da * dy;
+      if (D == 3) p.z += da * dz;
+      a.pos4[gi] = p;
     } else if (adv) {
       p.x += g.dgamma * p.y;  // Eq. (16): x <- x + dgamma y
       a.pos4[gi] = p;
@@ -643,14 +781,14 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       }
       a.pos4[gi] = p;
     }
-    if (fire || adv || lmove) {
+    if (fire || cg || adv || lmove) {
       const double4 x0 = a.xref4[gi];
       const double gd = strain_of(st->k, g.dgamma) - st->gamma_build;
       const double ux = p.x - (x0.x + gd * x0.y), uy = p.y - x0.y, uz = p.z - x0.z;
       m[0] = sqrt(ux * ux + uy * uy + uz * uz);
     }
   }
-  if (fire || adv || lmove) {
+  if (fire || cg || adv || lmove) {
     const int op[1] = {1};
     block_reduce<1>(m, op, red);
     if (tid == 0) a.upart[g.block0 + bt.y] = m[0];

@@ -71,6 +71,29 @@ class Fire:
 
 
 @dataclass
+class Cg:
+    """Nonlinear conjugate gradients (aqs_set_minimizer): first trial step,
+    curvature constant of the line search, largest extrapolation factor,
+    largest displacement of an atom per line search, force tolerance,
+    evaluations per line search, consecutive failed searches before
+    STALLED, iteration limit."""
+    a_init: float = 0.01
+    sigma: float = 0.1
+    grow: float = 4.0
+    dmax: float = 0.1
+    ftol: float = 1e-10
+    ls_max: int = 20
+    n_fail_max: int = 5
+    max_iter: int = 1_000_000
+
+    def to_c(self) -> "_lib.aqs_cg_params":
+        g = _lib.aqs_cg_params()
+        for k in ("a_init", "sigma", "grow", "dmax", "ftol", "ls_max", "n_fail_max", "max_iter"):
+            setattr(g, k, getattr(self, k))
+        return g
+
+
+@dataclass
 class Tuning:
     skin: float = 0.3
     max_neighbors: int = 0
@@ -140,6 +163,7 @@ class Engine:
         self.dgamma = _f64(np.broadcast_to(dg, (self.n_rep,)))
         self.pot = pot or LJParams()
         self.fire = fire or Fire()
+        self.minimizer, self.cg = "fire", None
         if isinstance(tuning, str):   # "auto": the autotuner's cached knobs for this shape
             from . import autotune
             tuning = autotune.tuned(self.dim, self.n_atoms, self.n_rep,
@@ -287,6 +311,19 @@ class Engine:
         return e.value, f
 
     # -- measurement ------------------------------------------------------
+    def set_minimizer(self, kind: str = "fire", cg: "Cg | None" = None) -> None:
+        """Minimiser of the later minimisations: "fire" (FIRE 2.0) or "cg"
+        (nonlinear conjugate gradients with the constants cg)."""
+        if kind == "fire":
+            check(self._lib.aqs_set_minimizer(self._ctx, _lib.AQS_MIN_FIRE, None), "aqs_set_minimizer")
+        elif kind == "cg":
+            self.cg = cg or Cg()
+            check(self._lib.aqs_set_minimizer(self._ctx, _lib.AQS_MIN_CG, ctypes.byref(self.cg.to_c())),
+                  "aqs_set_minimizer")
+        else:
+            raise ValueError(f"unknown minimiser {kind!r}")
+        self.minimizer = kind
+
     def set_profiling(self, every_nth_block: int) -> None:
         check(self._lib.aqs_set_profiling(self._ctx, int(every_nth_block)), "aqs_set_profiling")
 

@@ -47,6 +47,7 @@ def test_struct_sizes_match_the_header_layout():
     assert ctypes.sizeof(_lib.aqs_potential) == 8 + 32 + 32 + 8
     assert ctypes.sizeof(_lib.aqs_fire_params) == 9 * 8 + 4 * 4 + 8
     assert ctypes.sizeof(_lib.aqs_step_record) == 8 * 4 + 8
+    assert ctypes.sizeof(_lib.aqs_cg_params) == 5 * 8 + 2 * 4 + 8
     n_params = 64 * 128 + 128 + 128 * 128 + 128 + 128 * 3 + 3
     assert ctypes.sizeof(_lib.aqs_mlp) == 8 + 4 * (n_params + 64 + 64 + 3 + 3)
 
@@ -60,7 +61,7 @@ def test_struct_sizes_match_a_c_compiler(tmp_path):
     if gcc is None:
         pytest.skip("no C compiler")
     names = ["aqs_potential", "aqs_fire_params", "aqs_tuning", "aqs_step_record", "aqs_counters",
-             "aqs_mlp", "aqs_train_params", "aqs_check"]
+             "aqs_mlp", "aqs_train_params", "aqs_check", "aqs_cg_params"]
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include "aqs.h"\nint main(void){' +
                    "".join(f'printf("%zu\\n", sizeof({n}));' for n in names) + "return 0;}\n")
