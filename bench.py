@@ -180,6 +180,8 @@ def main() -> int:
                          "its own, rejected chains stopped; the learned form is also timed without them")
     ap.add_argument("--tuning", choices=("default", "auto", "autotune"), default="auto",
                     help="launch knobs: the defaults, the autotuner's cache, or tune when not cached")
+    ap.add_argument("--cg", type=int, default=1,
+                    help="also time the plain start with the conjugate-gradient minimiser (1/0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -195,7 +197,7 @@ def main() -> int:
 
     import torch
     import aqs_synth as S
-    from paper_2507_20802_amd import (AQS_START_LEARNED, AQS_START_PLAIN, Engine, Fire, LJParams,
+    from paper_2507_20802_amd import (AQS_START_LEARNED, AQS_START_PLAIN, Cg, Engine, Fire, LJParams,
                                       Tuning, parallel)
 
     torch.cuda.set_device(0)
@@ -232,19 +234,24 @@ def main() -> int:
         return time.perf_counter() - t, out, g
 
     live = bool(args.live)
-    forms = ([] if args.no_plain else [("plain", AQS_START_PLAIN, live)]) + \
-        ([] if args.only_plain else [("learned", AQS_START_LEARNED, live)])
+    forms = ([] if args.no_plain else [("plain", AQS_START_PLAIN, live, "fire")]) + \
+        ([] if args.only_plain else [("learned", AQS_START_LEARNED, live, "fire")])
+    # the paper's own minimiser on the same round (plain start)
+    if args.cg and not args.no_plain:
+        forms.append(("cg", AQS_START_PLAIN, live, "cg"))
     # the batched round without live checks, timed last: the force-kernel
     # roofline is taken there (one stream, every chain in each launch)
     main_form = "plain" if args.only_plain else "learned"
     roof_form = main_form + "_batched" if live else main_form
     if live:
-        forms.append((roof_form, AQS_START_PLAIN if args.only_plain else AQS_START_LEARNED, False))
+        forms.append((roof_form, AQS_START_PLAIN if args.only_plain else AQS_START_LEARNED, False, "fire"))
     for _ in range(args.warmup):
-        for _, st, lv in forms:
+        for _, st, lv, mz in forms:
+            eng.set_minimizer(mz, Cg() if mz == "cg" else None)
             one_round(args.warmup_K, st, lv)
     res_forms = {}
-    for name, st, lv in forms:
+    for name, st, lv, mz in forms:
+        eng.set_minimizer(mz, Cg() if mz == "cg" else None)
         eng.counters(reset=True)
         eng.set_profiling(args.profile_every)
         tot_t, acc, comp, iters, ok, rounds, starts = 0.0, 0, 0, [], True, [], []
@@ -274,7 +281,9 @@ def main() -> int:
                            "all_converged": bool(ok), "rounds": rounds, "counters": eng.counters(),
                            "starts": {"plain": starts.count(0), "learned": starts.count(1),
                                       "fallback": starts.count(2)},
-                           "live_checks": bool(lv), "final_star_vs_plain": star_vs_plain}
+                           "live_checks": bool(lv), "minimizer": mz, "final_star_vs_plain": star_vs_plain}
+    eng.set_minimizer("fire")
+    cg_form = res_forms.pop("cg", None)
     lr = res_forms[main_form]
     cnt = res_forms[roof_form]["counters"]
     # inherent-structure agreement of the two forms: same decisions, same final r_star (Eq. 20)
@@ -332,6 +341,18 @@ def main() -> int:
         "batched": None if not live else
         {k: v for k, v in res_forms[roof_form].items() if k != "counters"},
         "learned_vs_plain": comparison,
+        "cg": None if cg_form is None else
+        {"value": cg_form["value"], "ms_per_step": cg_form["ms_per_step"],
+         "computed_steps_per_s": cg_form["computed_steps_per_s"],
+         "iters_per_step": cg_form["fire_iters_per_step"], "all_converged": cg_form["all_converged"],
+         "final_star_vs_plain_fire": cg_form["final_star_vs_plain"],
+         "same_decisions_as_plain_fire": [r["decisions"] for r in cg_form["rounds"]]
+         == [r["decisions"] for r in res_forms["plain"]["rounds"]],
+         "iters_ratio_cg_over_fire": cg_form["fire_iters_per_step"]["mean"]
+         / res_forms["plain"]["fire_iters_per_step"]["mean"],
+         "wall_ratio_cg_over_fire": cg_form["ms_per_step"] / res_forms["plain"]["ms_per_step"],
+         "params": vars(Cg()),
+         "rounds": cg_form["rounds"]},
         "quench_s": quench_s,
         "mean_neighbours_in_cutoff": nb,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",

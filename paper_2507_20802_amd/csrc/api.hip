@@ -84,7 +84,7 @@ int segments_per_row(int n, int rows, int tpa) {
 
 struct Layout {
   size_t total = 0;
-  size_t o_geom, o_state, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
+  size_t o_geom, o_state, o_cgst, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
       o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl[2],
       o_tbl2[2], o_reps[2], o_nc3[2], o_overflow[2], o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_talt4, o_evals, o_xref4, o_ftbl[2], o_ttbl[2], o_thdr, o_hidx, o_sel[2],
       o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl[2], o_lftbl[2], o_lsel[2], o_tord;
@@ -154,6 +154,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   const size_t A = (size_t)lo.atoms;
   lo.o_geom = take(sizeof(Geom) * n_rep);
   lo.o_state = take(sizeof(State) * n_rep);
+  lo.o_cgst = take(sizeof(CgState) * n_rep);
   lo.o_pos4 = take(sizeof(double4) * A);
   for (int a = 0; a < 3; ++a) lo.o_v[a] = take(sizeof(double) * A);
   for (int a = 0; a < 3; ++a) lo.o_f[a] = take(sizeof(double) * A);
@@ -251,6 +252,7 @@ struct aqs_ctx {
   // device views
   Geom* d_geom;
   State* d_state;
+  CgState* cgst;
   double4* pos4;
   double *vx, *vy, *vz, *fx, *fy, *fz;
   int32_t *id, *inv, *nbc;
@@ -316,6 +318,8 @@ IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   for (int t = 0; t < 4; ++t) a.pp[t] = c->pp[t];
   a.fire = c->fire;
   a.cg = c->cg;
+  a.cgst = c->cgst;
+  a.minimizer = c->minimizer;
   a.skin = c->tn.skin;
   a.rc_max = c->rc_max;
   a.dlx = c->dlx; a.dly = c->dly; a.dlz = c->dlz;
@@ -686,7 +690,6 @@ aqs_status start_chains(aqs_ctx* c, const std::vector<int32_t>& sel, int32_t sta
   for (int i = 0; i < n_sel; ++i) {
     State& s = c->h_state[sel[i]];
     reset_minimizer(c, s);
-    s.minimizer = c->minimizer;
     s.phase = (c->minimizer == kMinCG) ? PH_CG : PH_FIRE;
     s.status = -1;
     s.step = 0;
@@ -882,10 +885,6 @@ void reset_minimizer(aqs_ctx* c, State& s) {
   s.nneg = 0;
   s.it = 0;
   s.restart = 0;
-  s.cg_dir = 0;
-  s.cg_newdir = 0;
-  s.cg_nfail = 0;
-  s.cg_aprev = 0.0;
 }
 
 }  // namespace
@@ -967,6 +966,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   char* w = c->ws;
   c->d_geom = at<Geom>(w, lo.o_geom);
   c->d_state = at<State>(w, lo.o_state);
+  c->cgst = at<CgState>(w, lo.o_cgst);
   c->pos4 = at<double4>(w, lo.o_pos4);
   c->vx = at<double>(w, lo.o_v[0]); c->vy = at<double>(w, lo.o_v[1]); c->vz = at<double>(w, lo.o_v[2]);
   c->fx = at<double>(w, lo.o_f[0]); c->fy = at<double>(w, lo.o_f[1]); c->fz = at<double>(w, lo.o_f[2]);

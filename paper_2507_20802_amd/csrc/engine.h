@@ -99,13 +99,6 @@ struct State {
   double gamma_build; // strain at the last neighbour-list build
   double E_plain, fmax_plain;  // learned start: plain-start reference values
   double lmean[3];    // learned start: mean predicted displacement per unit strain
-  // conjugate gradients: line search along d (held in v) from x0 = x - a d
-  double cg_a;              // trial step a
-  double cg_alo, cg_plo;    // last point still descending: step, phi'(step)
-  double cg_ahi, cg_phi;    // first point past the minimum (cg_ahi < 0: none yet)
-  double cg_p0, cg_ff0;     // phi'(0) = -F(x0).d and |F(x0)|^2
-  double cg_aprev, cg_p0prev;  // accepted step and phi'(0) of the previous search
-  double cg_beta, cg_step;  // pending update: d <- F + beta d (new direction), x += step d
   int32_t npos, nneg;
   int32_t restart;    // pending update backs off x -= dt v / 2, v = 0
   int32_t phase;
@@ -123,11 +116,22 @@ struct State {
   int32_t ntiles;     // force tiles of the current grid
   int32_t list_mode;  // 0: tiles index their LDS halo; 1: global indices only
   int32_t resume_phase;  // phase to resume after a neighbour-list rebuild
-  int32_t minimizer;  // kMinFire or kMinCG
-  int32_t cg_dir;     // a search direction exists
-  int32_t cg_newdir;  // the pending update starts a new direction
-  int32_t cg_nls;     // evaluations in the current line search
-  int32_t cg_nfail;   // consecutive failed line searches
+};
+
+// Conjugate-gradient state of a slot, kept apart from State so that the FIRE
+// kernels never load it.  A line search runs along d (held in v) from
+// x0 = x - a d; reset at the first evaluation of every minimisation (it = 0).
+struct CgState {
+  double a;                 // trial step
+  double alo, plo;          // last point still descending: step, phi'(step)
+  double ahi, phi;          // first point past the minimum (ahi < 0: none yet)
+  double p0, ff0;           // phi'(0) = -F(x0).d and |F(x0)|^2
+  double aprev, p0prev;     // accepted step and phi'(0) of the previous search
+  double beta, step;        // pending update: d <- F + beta d (new direction), x += step d
+  int32_t dir;              // a search direction exists
+  int32_t newdir;           // the pending update starts a new direction
+  int32_t nls;              // evaluations in the current line search
+  int32_t nfail;            // consecutive failed line searches
 };
 
 struct PairParams {   // per type pair t = 2 ti + tj
@@ -181,6 +185,8 @@ struct IterArgs {
   PairParams pp[4];
   FireParams fire;
   CgParams cg;
+  CgState* cgst;          // per slot (conjugate gradients)
+  int32_t minimizer;      // kMinFire or kMinCG: every slot of the launch
   double skin, rc_max;
   // learned start (null when unused)
   double* dlx; double* dly; double* dlz;   // learned displacement per atom

@@ -274,10 +274,6 @@ __device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
     s.restart = 0;
     s.cv = 1.0;
     s.cf = 0.0;
-    s.cg_dir = 0;
-    s.cg_newdir = 0;
-    s.cg_nfail = 0;
-    s.cg_aprev = 0.0;
     if (s.start_mode == kStartLearned) {
       // descriptors and network at this inherent structure first; the
       // strain index advances with the plain start (learned kernels)
@@ -310,68 +306,76 @@ __device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
 //   6  new direction: F.d = |F|^2 - beta p (beta = 0 unless positive);
 //      first trial a_prev p0_prev / p0 (a_init for the first search and after
 //      a failed one), at most dmax / (max|F_i| + beta max|d_i|)
-// r: [1] |F|^2, [2] F.d, [3] F.F0, [8] max |d_i|^2.  Returns false if the
-// minimisation has stalled.
-__device__ bool control_cg(const CgParams& c, State& s, const double* r) {
+// r: [1] |F|^2, [2] F.d, [3] F.F0, [8] max |d_i|^2; fmx = max_i |F_i|; it =
+// iterations of this minimisation so far (0: reset the search state).
+// Returns false if the minimisation has stalled.
+__device__ bool control_cg(const CgParams& c, CgState& q, double fmx, int64_t it,
+                           const double* r) {
+  if (it == 0) {  // first evaluation of a minimisation
+    q.dir = 0;
+    q.nfail = 0;
+    q.aprev = 0.0;
+  }
   const double ff = r[1];
   double beta = 0.0, p = 0.0, dn = 0.0;
-  if (s.cg_dir) {
+  if (q.dir) {
     p = -r[2];
     dn = sqrt(r[8]);
     const double a_max = c.dmax / dn;
-    if (fabs(p) <= c.sigma * fabs(s.cg_p0) || (p < 0.0 && s.cg_a >= a_max)) {
-      beta = fmax(0.0, (ff - r[3]) / s.cg_ff0);
-      s.cg_aprev = s.cg_a;
-      s.cg_p0prev = s.cg_p0;
-      s.cg_nfail = 0;
-    } else if (++s.cg_nls > c.ls_max) {
-      if (++s.cg_nfail > c.n_fail_max) return false;
-      s.cg_aprev = 0.0;
+    if (fabs(p) <= c.sigma * fabs(q.p0) || (p < 0.0 && q.a >= a_max)) {
+      beta = fmax(0.0, (ff - r[3]) / q.ff0);
+      q.aprev = q.a;
+      q.p0prev = q.p0;
+      q.nfail = 0;
+    } else if (++q.nls > c.ls_max) {
+      if (++q.nfail > c.n_fail_max) return false;
+      q.aprev = 0.0;
     } else {
-      const double at = s.cg_a, a_old = s.cg_alo, p_old = s.cg_plo;
+      const double at = q.a, a_old = q.alo, p_old = q.plo;
       if (p < 0.0) {
-        s.cg_alo = at;
-        s.cg_plo = p;
+        q.alo = at;
+        q.plo = p;
       } else {
-        s.cg_ahi = at;
-        s.cg_phi = p;
+        q.ahi = at;
+        q.phi = p;
       }
       double an;
-      if (s.cg_ahi < 0.0) {
+      if (q.ahi < 0.0) {
         an = c.grow * at;
         if (p > p_old) an = fmin(fmax(at - p * (at - a_old) / (p - p_old), 1.1 * at), c.grow * at);
         an = fmin(an, a_max);
       } else {
-        const double w = s.cg_ahi - s.cg_alo;
-        an = fmin(fmax(s.cg_alo - s.cg_plo * w / (s.cg_phi - s.cg_plo), s.cg_alo + 0.1 * w),
-                  s.cg_ahi - 0.1 * w);
+        const double w = q.ahi - q.alo;
+        an = fmin(fmax(q.alo - q.plo * w / (q.phi - q.plo), q.alo + 0.1 * w),
+                  q.ahi - 0.1 * w);
       }
-      s.cg_newdir = 0;
-      s.cg_step = an - at;
-      s.cg_a = an;
+      q.newdir = 0;
+      q.step = an - at;
+      q.a = an;
       return true;
     }
   }
   double fd = ff - beta * p;
   if (!(fd > 0.0)) beta = 0.0;
   if (beta == 0.0) fd = ff;
-  double a1 = (s.cg_aprev > 0.0) ? s.cg_aprev * s.cg_p0prev / (-fd) : c.a_init;
-  const double cap = c.dmax / (s.fmax + beta * dn);
+  double a1 = (q.aprev > 0.0) ? q.aprev * q.p0prev / (-fd) : c.a_init;
+  const double cap = c.dmax / (fmx + beta * dn);
   if (a1 > cap) a1 = cap;
-  s.cg_newdir = 1;
-  s.cg_beta = beta;
-  s.cg_step = a1;
-  s.cg_p0 = -fd;
-  s.cg_ff0 = ff;
-  s.cg_a = a1;
-  s.cg_alo = 0.0;
-  s.cg_plo = -fd;
-  s.cg_ahi = -1.0;
-  s.cg_nls = 0;
-  s.cg_dir = 1;
+  q.newdir = 1;
+  q.beta = beta;
+  q.step = a1;
+  q.p0 = -fd;
+  q.ff0 = ff;
+  q.a = a1;
+  q.alo = 0.0;
+  q.plo = -fd;
+  q.ahi = -1.0;
+  q.nls = 0;
+  q.dir = 1;
   return true;
 }
 
+template <bool CG>
 __device__ void control(const IterArgs& a, int rep, const Geom& g, const double* r, int phase) {
   State s = a.state[rep];
   if (phase == PH_FINISH || phase == PH_STOP) {
@@ -386,7 +390,7 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
   const double ub = r[7];
   const double gam = strain_of(s.k, g.dgamma);
   const double gd = fabs(gam - s.gamma_build);
-  const bool cg = (s.minimizer == kMinCG);
+  constexpr bool cg = CG;
   if (!(gd * a.rc_max + 2.0 * (1.0 + gd) * ub < a.skin)) {
     s.resume_phase = (phase == PH_LPLAIN || phase == PH_LMOVE || phase == PH_LREVERT)
                          ? phase
@@ -448,7 +452,10 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     return;
   }
   if (cg) {
-    if (!control_cg(a.cg, s, r)) {
+    CgState q = a.cgst[rep];
+    const bool going = control_cg(a.cg, q, s.fmax, s.it, r);
+    a.cgst[rep] = q;
+    if (!going) {
       s.pending = 2;
       s.phase = PH_ENERGY;
     } else {
@@ -630,6 +637,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 // selection, launched after the force kernel (the kernel boundary makes the
 // tile partials visible; no device-scope fences inside the force kernel).
 // The tile partials are combined in tile order, then a fixed tree.
+template <bool CG>
 __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
   const int rep = a.sel[blockIdx.x];
   const State* stp = a.state + rep;
@@ -661,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
   block_reduce<kForceParts + 1>(r, ops, red);
   if (tid == 0) {
     if (compute) atomicAdd(a.evals, (unsigned long long)g.n);
-    control(a, rep, g, r, phase);
+    control<CG>(a, rep, g, r, phase);
   }
 }
 
@@ -670,16 +678,15 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
 // the fine affine step of the chain, per atom; per-block max
 // |u_i| = |r_i - F x_ref,i| for the list test.
 
-template <int D>
+template <int D, bool CG>
 __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
   const int2 bt = a.blocks[blockIdx.x];
   const int rep = bt.x;
   if (rep < 0) return;
   const State* st = a.state + rep;
   const int phase = st->phase;
-  const bool cgmin = (st->minimizer == kMinCG);
-  const bool fire = (phase == PH_FIRE || (phase == PH_STOP && !cgmin));
-  const bool cg = (phase == PH_CG || (phase == PH_STOP && cgmin));
+  const bool fire = !CG && (phase == PH_FIRE || phase == PH_STOP);
+  const bool cg = CG && (phase == PH_CG || phase == PH_STOP);
   const bool adv = (phase == PH_ADVANCE);
   // learned start: move to F r + dgamma (u_hat - mean u_hat), or back
   const bool lmove = (phase == PH_LMOVE || phase == PH_LREVERT);
@@ -734,10 +741,11 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       if (D == 3) a.vz[gi] = vz;
     } else if (cg) {
       // conjugate gradients: d lives in v; a new direction also saves F0
+      const CgState* q = a.cgst + rep;
       double dx = a.vx[gi], dy = a.vy[gi], dz = (D == 3) ? a.vz[gi] : 0.0;
-      if (st->cg_newdir) {
+      if (q->newdir) {
         const double fx = a.fx[gi], fy = a.fy[gi], fz = (D == 3) ? a.fz[gi] : 0.0;
-        const double b = st->cg_beta;
+        const double b = q->beta;
         if (b == 0.0) {
           dx = fx;
           dy = fy;
@@ -754,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
         a.vy[gi] = dy;
         if (D == 3) a.vz[gi] = dz;
       }
-      const double da = st->cg_step;
+      const double da = q->step;
       p.x += da * dx;
       p.y += da * dy;
       if (D == 3) p.z += da * dz;
@@ -814,15 +822,26 @@ void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s)
 }
 
 void launch_control(const IterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_control, dim3(a.nsel), dim3(kBlock), 0, s, a);
+  if (a.minimizer == kMinCG)
+    hipLaunchKernelGGL(k_control<true>, dim3(a.nsel), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_control<false>, dim3(a.nsel), dim3(kBlock), 0, s, a);
 }
 
 void launch_update(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
   if (nblk <= 0) return;
-  if (dim == 3)
-    hipLaunchKernelGGL(k_update<3>, dim3(nblk), dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_update<2>, dim3(nblk), dim3(kBlock), 0, s, a);
+  const bool cg = (a.minimizer == kMinCG);
+  if (dim == 3) {
+    if (cg)
+      hipLaunchKernelGGL((k_update<3, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_update<3, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+  } else {
+    if (cg)
+      hipLaunchKernelGGL((k_update<2, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_update<2, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+  }
 }
 
 
