@@ -397,6 +397,16 @@ def learned_start(is_pos: np.ndarray, u_hat: np.ndarray, dgamma: float):
     return x, x + dgamma * (u - mean), True
 
 
+def extrapolated_uhat(prev_is: np.ndarray, is_pos: np.ndarray, H: np.ndarray,
+                      dgamma: float) -> np.ndarray:
+    """The extrapolation the paper's conclusion (Sec. 5) proposes: the next
+    step's non-affine displacement per unit strain is predicted by the last
+    one, u_hat = minimg(r(IS_k) - F r(IS_(k-1))) / dgamma in the box of IS_k.
+    The start then follows learned_start / choose_start; the first fine step
+    has no history and starts from F r."""
+    return nonaffine_targets(prev_is, is_pos, H, dgamma)
+
+
 def choose_start(plain, learned, ok, types, H, pot, energy_forces):
     """The start FIRE begins from: the learned one unless it was rejected or
     its energy or max |F_i| exceeds the plain start's."""
