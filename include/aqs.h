@@ -69,7 +69,10 @@ typedef int32_t aqs_status;
 /* start of the minimisation after each fine affine step */
 #define AQS_START_PLAIN 0    /* the affine image F r (Eq. 12) */
 #define AQS_START_LEARNED 1  /* F r + predicted non-affine displacement */
-#define AQS_START_FALLBACK 2 /* record only: learned start rejected, F r used */
+#define AQS_START_FALLBACK 2 /* record only: learned or extrapolated start
+                                rejected, F r used */
+#define AQS_START_EXTRAPOLATED 3 /* F r + the previous step's non-affine
+                                    displacement (see aqs_minimize_batch) */
 
 /* Binary truncated-and-shifted Lennard-Jones pair potential, Eq. (13):
  * U_ab(r) = 4 eps_ab [(sigma_ab/r)^12 - (sigma_ab/r)^6] - U_ab(rc_ab) for
@@ -126,8 +129,9 @@ typedef struct {
   double max_f;       /* max_i |F_i| at the last force evaluation */
   double sigma_xy;    /* shear stress at the last force evaluation */
   int32_t status;     /* AQS_CONVERGED ... */
-  int32_t start;      /* start used: AQS_START_PLAIN, AQS_START_LEARNED, or
-                         AQS_START_FALLBACK (learned start asked for, rejected) */
+  int32_t start;      /* start used: AQS_START_PLAIN, AQS_START_LEARNED,
+                         AQS_START_EXTRAPOLATED, or AQS_START_FALLBACK (a
+                         predicted start asked for and rejected) */
 } aqs_step_record;
 
 /* Bytes of device workspace a context with these slots needs.  n_atoms:
@@ -198,9 +202,17 @@ aqs_status aqs_affine_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
  *   v_i scaled to dmax / dt;  9 x += dt v; it++; it >= max_iter -> MAXITER.
  *
  * rep[n_sel]      host, distinct slots
- * start_mode      AQS_START_PLAIN or AQS_START_LEARNED (needs aqs_learned_load);
- *                 with AQS_START_LEARNED the fine steps start as documented at
- *                 aqs_learned_load (the first minimisation starts as given)
+ * start_mode      AQS_START_PLAIN, AQS_START_LEARNED (needs aqs_learned_load)
+ *                 or AQS_START_EXTRAPOLATED; with AQS_START_LEARNED the fine
+ *                 steps start as documented at aqs_learned_load (the first
+ *                 minimisation starts as given).  AQS_START_EXTRAPOLATED (the
+ *                 extrapolation the paper's conclusion, Sec. 5, proposes to
+ *                 cut the minimiser's iterations): fine step s >= 2 of the call
+ *                 starts from F r + dgamma (u_hat - mean u_hat), u_hat =
+ *                 (r(IS_(s-1)) - F r(IS_(s-2))) / dgamma, the non-affine
+ *                 displacement of the step before, with the acceptance rules
+ *                 of the learned start; step 1 has no history and starts from
+ *                 F r (record AQS_START_FALLBACK)
  * n_steps[n_sel]  host, fine steps after the first minimisation; NULL = all 0
  * snap_dst[n_sel] host, slot that receives a copy of the first inherent
  *                 structure (the "outgoing" configuration of Sec. 3.3), or -1;

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libaqs.so")
 
 AQS_OK, AQS_EINVAL, AQS_EHIP, AQS_ENOMEM, AQS_ECAPACITY, AQS_ESTATE = 0, -1, -2, -3, -4, -5
 AQS_CONVERGED, AQS_MAXITER, AQS_STALLED, AQS_NONFINITE, AQS_CANCELLED = 0, 1, 2, 3, 4
-AQS_START_PLAIN, AQS_START_LEARNED, AQS_START_FALLBACK = 0, 1, 2
+AQS_START_PLAIN, AQS_START_LEARNED, AQS_START_FALLBACK, AQS_START_EXTRAPOLATED = 0, 1, 2, 3
 AQS_MIN_FIRE, AQS_MIN_CG = 0, 1
 
 c_double_p = ctypes.POINTER(ctypes.c_double)

@@ -370,10 +370,11 @@ LearnArgs learn_args(aqs_ctx* c, const Lane& L, int mode, float* out = nullptr) 
 std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, int per_block = 1);
 std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel);
 
-// Learned start of the slots waiting in PH_LDESC (known from the last
-// state read-back): descriptors, network, plain start and the checks, with
-// launch tables over exactly those slots.
-aqs_status learned_group(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls) {
+// Learned (or extrapolated) start of the slots waiting in PH_LDESC (known
+// from the last state read-back): descriptors and network, or the
+// extrapolation; plain start and the checks, with launch tables over exactly
+// those slots.
+aqs_status learned_group(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls, bool extrap) {
   const std::vector<int2> tb = make_table(c, ls);
   const std::vector<int2> ft = make_tile_table(c, ls);
   std::copy(tb.begin(), tb.end(), L.h_ltbl);
@@ -388,8 +389,12 @@ aqs_status learned_group(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls) {
   la.ftiles = L.lftbl;
   la.sel = L.lsel_d;
   la.nsel = (int32_t)ls.size();
-  launch_ldesc(la, (int32_t)ft.size(), c->dim, L.s);
-  launch_lmlp(la, (int32_t)tb.size(), c->dim, L.s);
+  if (extrap) {
+    launch_lextrap(la, (int32_t)tb.size(), c->dim, L.s);
+  } else {
+    launch_ldesc(la, (int32_t)ft.size(), c->dim, L.s);
+    launch_lmlp(la, (int32_t)tb.size(), c->dim, L.s);
+  }
   launch_lctl(la, L.s);
   HIPCHK(hipGetLastError());
   return AQS_OK;
@@ -659,7 +664,8 @@ void reset_minimizer(aqs_ctx* c, State& s);
 // snapshot slot snap_dst[i]; lists are rebuilt.
 aqs_status start_chains(aqs_ctx* c, const std::vector<int32_t>& sel, int32_t start_mode,
                         const int32_t* n_steps, const int32_t* snap_dst) {
-  if (start_mode != AQS_START_PLAIN && start_mode != AQS_START_LEARNED)
+  if (start_mode != AQS_START_PLAIN && start_mode != AQS_START_LEARNED &&
+      start_mode != AQS_START_EXTRAPOLATED)
     return fail(AQS_EINVAL, "unknown start mode %d", start_mode);
   if (start_mode == AQS_START_LEARNED && c->mlp_dim != c->dim)
     return fail(AQS_ESTATE, "the learned start needs a network (aqs_learned_load)");
@@ -721,14 +727,14 @@ aqs_status lane_launch(aqs_ctx* c, Lane& L, int32_t start_mode, bool allow_timed
       c->ev.push_back(e);
     }
   }
-  if (start_mode == AQS_START_LEARNED) {
+  if (start_mode == AQS_START_LEARNED || start_mode == AQS_START_EXTRAPOLATED) {
     // slots that finished a minimisation since the last read-back wait in
-    // PH_LDESC: descriptors, network and plain start for them now
+    // PH_LDESC: the predicted displacement and plain start for them now
     std::vector<int32_t> ls;
     for (int r : L.cur_sel)
       if (c->h_state[r].phase == PH_LDESC) ls.push_back(r);
     if (!ls.empty()) {
-      aqs_status st = learned_group(c, L, ls);
+      aqs_status st = learned_group(c, L, ls, start_mode == AQS_START_EXTRAPOLATED);
       if (st) return st;
     }
   }

@@ -60,9 +60,10 @@ enum Phase : int32_t {
 // minimiser of a slot (State::minimizer; AQS_MIN_* of the public header)
 constexpr int32_t kMinFire = 0, kMinCG = 1;
 
-// start of a minimisation (StepRecord::start): the affine image, the learned
-// start, or the affine image after the learned start was rejected
-constexpr int32_t kStartPlain = 0, kStartLearned = 1, kStartFallback = 2;
+// start of a minimisation (StepRecord::start; State::start_mode): the affine
+// image, the learned start, the affine image after a learned or extrapolated
+// start was rejected, the extrapolated start
+constexpr int32_t kStartPlain = 0, kStartLearned = 1, kStartFallback = 2, kStartExtrap = 3;
 
 __host__ __device__ inline bool phase_energy(int32_t ph) {  // evaluation also sums E
   return ph == PH_EVAL || ph == PH_ENERGY || ph == PH_LPLAIN || ph == PH_LMOVE;

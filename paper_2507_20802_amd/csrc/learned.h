@@ -85,6 +85,9 @@ void launch_ldesc(const LearnArgs& a, int32_t ntiles, int32_t dim, hipStream_t s
 // mode 0: slots in PH_LDESC: u_hat into dl, partials, snapshot, plain start;
 // mode 1: every slot of the table: u_hat into out[id * d + c] (FP32).
 void launch_lmlp(const LearnArgs& a, int32_t nblk, int32_t dim, hipStream_t s);
+// slots in PH_LDESC: the extrapolated start (previous step's non-affine
+// displacement per unit strain) into dl, partials, snapshot, plain start
+void launch_lextrap(const LearnArgs& a, int32_t nblk, int32_t dim, hipStream_t s);
 // per slot of the selection in PH_LDESC: mean u_hat, checks, k + 1, PH_LPLAIN
 void launch_lctl(const LearnArgs& a, hipStream_t s);
 

@@ -272,6 +272,57 @@ __device__ __forceinline__ f32x4 mlp16(const uint16_t* zrow, const uint16_t* sw1
   return y;
 }
 
+// Tail of a predicted start, per atom li of block bt of a slot in PH_LDESC:
+// the predicted displacement per unit strain u into dl, block partials (sum
+// u, max |u|^2, non-finite, max displacement since the list build), the
+// snapshot of the inherent structure if pending, then the plain start
+// x <- x + dgamma y with v = 0, also saved in alt4.  Every thread of the
+// block calls it (live = atom exists).
+template <int D>
+__device__ void predicted_start(const LearnArgs& a, const State* st, const Geom& g, int2 bt,
+                                int li, bool live, double ux, double uy, double uz,
+                                double (*red)[4]) {
+  double part[kLearnParts] = {0, 0, 0, 0, 0, 0};
+  if (live) {
+    const int64_t gi = g.atom_off + li;
+    a.dlx[gi] = ux;
+    a.dly[gi] = uy;
+    if (D == 3) a.dlz[gi] = uz;
+    part[0] = ux;
+    part[1] = uy;
+    part[2] = uz;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    part[3] = uu;
+    part[4] = isfinite(uu) ? 0.0 : 1.0;
+    double4 p = a.pos4[gi];
+    if (st->do_snap) {  // first inherent structure of the chain -> snap_dst
+      const Geom gd = a.geom[st->snap_dst];
+      const int64_t di = gd.atom_off + li;
+      a.pos4[di] = p;
+      const int32_t aid = a.id[gi];
+      a.id[di] = aid;
+      a.inv[gd.atom_off + aid] = li;
+    }
+    p.x += g.dgamma * p.y;  // plain start, Eq. (16)
+    a.pos4[gi] = p;
+    a.alt4[gi] = p;          // restored bit for bit if the predicted start is rejected
+    a.vx[gi] = 0.0;
+    a.vy[gi] = 0.0;
+    if (D == 3) a.vz[gi] = 0.0;
+    const double4 x0 = a.xref4[gi];
+    const double gdl = strain_of(st->k + 1, g.dgamma) - st->gamma_build;
+    const double dx = p.x - (x0.x + gdl * x0.y), dy = p.y - x0.y, dz = p.z - x0.z;
+    part[5] = sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  const int ops[kLearnParts] = {0, 0, 0, 1, 1, 1};
+  block_reduce_fixed<kLearnParts>(part, ops, red);
+  if (threadIdx.x == 0) {
+    double* dst = a.lpart + (int64_t)(g.block0 + bt.y) * kLearnParts;
+    for (int k = 0; k < kLearnParts; ++k) dst[k] = part[k];
+    a.upart[g.block0 + bt.y] = part[5];
+  }
+}
+
 // Inference over a (slot, 256-atom block): 4 wavefronts x 4 groups of 16.
 // mode 0 (engine, slots in PH_LDESC): u_hat into dl, block partials, the
 // snapshot of the inherent structure if pending, then the plain start
@@ -341,50 +392,45 @@ __global__ __launch_bounds__(kBlock) void k_lmlp(LearnArgs a) {
     }
     return;
   }
-  double part[kLearnParts] = {0, 0, 0, 0, 0, 0};
-  if (live) {
-    const double ux = uo[tid][0], uy = uo[tid][1], uz = (D == 3) ? (double)uo[tid][2] : 0.0;
-    a.dlx[gi] = ux;
-    a.dly[gi] = uy;
-    if (D == 3) a.dlz[gi] = uz;
-    part[0] = ux;
-    part[1] = uy;
-    part[2] = uz;
-    const double uu = ux * ux + uy * uy + uz * uz;
-    part[3] = uu;
-    part[4] = isfinite(uu) ? 0.0 : 1.0;
-    double4 p = a.pos4[gi];
-    if (st->do_snap) {  // first inherent structure of the chain -> snap_dst
-      const Geom gd = a.geom[st->snap_dst];
-      const int64_t di = gd.atom_off + li;
-      a.pos4[di] = p;
-      const int32_t aid = a.id[gi];
-      a.id[di] = aid;
-      a.inv[gd.atom_off + aid] = li;
-    }
-    p.x += g.dgamma * p.y;  // plain start, Eq. (16)
-    a.pos4[gi] = p;
-    a.alt4[gi] = p;          // restored bit for bit if the learned start is rejected
-    a.vx[gi] = 0.0;
-    a.vy[gi] = 0.0;
-    if (D == 3) a.vz[gi] = 0.0;
-    const double4 x0 = a.xref4[gi];
-    const double gdl = strain_of(st->k + 1, g.dgamma) - st->gamma_build;
-    const double dx = p.x - (x0.x + gdl * x0.y), dy = p.y - x0.y, dz = p.z - x0.z;
-    part[5] = sqrt(dx * dx + dy * dy + dz * dz);
+  // one call site for every thread (the tail synchronises the block)
+  const double ux = live ? (double)uo[tid][0] : 0.0, uy = live ? (double)uo[tid][1] : 0.0;
+  const double uz = (live && D == 3) ? (double)uo[tid][2] : 0.0;
+  predicted_start<D>(a, st, g, bt, li, live, ux, uy, uz, red);
+}
+
+// Extrapolated start (the extrapolation the paper's conclusion, Sec. 5,
+// proposes to cut the minimiser's iterations): the non-affine displacement
+// of the step just finished, u_(k-1) = r(IS_(k-1)) - F r(IS_(k-2)), per unit
+// strain, predicts the next one.  alt4 still holds the plain start
+// F r(IS_(k-2)) of that step (written by the previous start, permuted and
+// wrapped with the atoms by every list rebuild), so u is a plain difference.
+// From the second fine step of a call on; before that there is no history
+// and u = 0 (k_lctl then rejects the start).  Same tail as the network:
+// dl, partials, snapshot, plain start.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_lextrap(LearnArgs a) {
+  const int2 bt = a.blocks[blockIdx.x];
+  if (bt.x < 0) return;
+  const State* st = a.state + bt.x;
+  if (st->phase != PH_LDESC) return;
+  const Geom g = a.geom[bt.x];
+  __shared__ double red[kLearnParts][4];
+  const int li = bt.y * kBlock + threadIdx.x;
+  const bool live = li < g.n;
+  double ux = 0.0, uy = 0.0, uz = 0.0;
+  if (live && st->step >= 2) {
+    const int64_t gi = g.atom_off + li;
+    const double4 p = a.pos4[gi], q = a.alt4[gi];
+    ux = (p.x - q.x) / g.dgamma;
+    uy = (p.y - q.y) / g.dgamma;
+    if (D == 3) uz = (p.z - q.z) / g.dgamma;
   }
-  const int ops[kLearnParts] = {0, 0, 0, 1, 1, 1};
-  block_reduce_fixed<kLearnParts>(part, ops, red);
-  if (tid == 0) {
-    double* dst = a.lpart + (int64_t)(g.block0 + bt.y) * kLearnParts;
-    for (int k = 0; k < kLearnParts; ++k) dst[k] = part[k];
-    a.upart[g.block0 + bt.y] = part[5];
-  }
+  predicted_start<D>(a, st, g, bt, li, live, ux, uy, uz, red);
 }
 
 // Per slot of the selection in PH_LDESC: mean u_hat over the slot (block
-// partials in block order), the pre-checks of the learned start, strain
-// index k + 1 (the plain start is in place), phase PH_LPLAIN.
+// partials in block order), the pre-checks of the learned (or extrapolated)
+// start, strain index k + 1 (the plain start is in place), phase PH_LPLAIN.
 __global__ __launch_bounds__(kBlock) void k_lctl(LearnArgs a) {
   const int rep = a.sel[blockIdx.x];
   State* st = a.state + rep;
@@ -420,7 +466,9 @@ __global__ __launch_bounds__(kBlock) void k_lctl(LearnArgs a) {
     st->lmean[0] = s[0] / (double)g.n;
     st->lmean[1] = s[1] / (double)g.n;
     st->lmean[2] = s[2] / (double)g.n;
-    const bool ok = s[4] == 0.0 && isfinite(s[0] + s[1] + s[2]) &&
+    // the extrapolated start needs the previous step's displacement
+    const bool hist = st->start_mode != kStartExtrap || st->step >= 2;
+    const bool ok = hist && s[4] == 0.0 && isfinite(s[0] + s[1] + s[2]) &&
                     sqrt(s[3]) * g.dgamma <= a.max_move;
     st->learn_ok = ok ? 1 : 0;
     st->k += 1;
@@ -827,6 +875,14 @@ void launch_lmlp(const LearnArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
     hipLaunchKernelGGL(k_lmlp<3>, dim3(nblk), dim3(kBlock), 0, s, a);
   else
     hipLaunchKernelGGL(k_lmlp<2>, dim3(nblk), dim3(kBlock), 0, s, a);
+}
+
+void launch_lextrap(const LearnArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
+  if (nblk <= 0) return;
+  if (dim == 3)
+    hipLaunchKernelGGL(k_lextrap<3>, dim3(nblk), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_lextrap<2>, dim3(nblk), dim3(kBlock), 0, s, a);
 }
 
 void launch_lctl(const LearnArgs& a, hipStream_t s) {

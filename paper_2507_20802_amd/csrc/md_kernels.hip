@@ -274,9 +274,10 @@ __device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
     s.restart = 0;
     s.cv = 1.0;
     s.cf = 0.0;
-    if (s.start_mode == kStartLearned) {
-      // descriptors and network at this inherent structure first; the
-      // strain index advances with the plain start (learned kernels)
+    if (s.start_mode == kStartLearned || s.start_mode == kStartExtrap) {
+      // the predicted displacement at this inherent structure first (the
+      // network or the extrapolation); the strain index advances with the
+      // plain start (learned kernels)
       s.start_used = kStartFallback;
       s.phase = PH_LDESC;
     } else {
@@ -435,7 +436,7 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
       a.state[rep] = s;
       return;
     }
-    s.start_used = kStartLearned;
+    s.start_used = (s.start_mode == kStartExtrap) ? kStartExtrap : kStartLearned;
   }
   s.phase = cg ? PH_CG : PH_FIRE;
   if (r[6] != 0.0 || !isfinite(r[1]) || !isfinite(r[2])) {
