@@ -180,6 +180,8 @@ def main() -> int:
                          "its own, rejected chains stopped; the learned form is also timed without them")
     ap.add_argument("--tuning", choices=("default", "auto", "autotune"), default="auto",
                     help="launch knobs: the defaults, the autotuner's cache, or tune when not cached")
+    ap.add_argument("--extrap", type=int, default=1,
+                    help="also time the extrapolated start (previous step's non-affine displacement) (1/0)")
     ap.add_argument("--cg", type=int, default=1,
                     help="also time the plain start with the conjugate-gradient minimiser (1/0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -197,8 +199,8 @@ def main() -> int:
 
     import torch
     import aqs_synth as S
-    from paper_2507_20802_amd import (AQS_START_LEARNED, AQS_START_PLAIN, Cg, Engine, Fire, LJParams,
-                                      Tuning, parallel)
+    from paper_2507_20802_amd import (AQS_START_EXTRAPOLATED, AQS_START_LEARNED, AQS_START_PLAIN, Cg, Engine,
+                                      Fire, LJParams, Tuning, parallel)
 
     torch.cuda.set_device(0)
     dim, n, P, K, dg = args.dim, args.n, args.P, args.K, args.dgamma
@@ -236,7 +238,9 @@ def main() -> int:
     live = bool(args.live)
     forms = ([] if args.no_plain else [("plain", AQS_START_PLAIN, live, "fire")]) + \
         ([] if args.only_plain else [("learned", AQS_START_LEARNED, live, "fire")])
-    # the paper's own minimiser on the same round (plain start)
+    # the extrapolated start and the paper's own minimiser on the same round
+    if args.extrap and not args.no_plain:
+        forms.append(("extrapolated", AQS_START_EXTRAPOLATED, live, "fire"))
     if args.cg and not args.no_plain:
         forms.append(("cg", AQS_START_PLAIN, live, "cg"))
     # the batched round without live checks, timed last: the force-kernel
@@ -280,10 +284,11 @@ def main() -> int:
                                                    "p95": float(np.percentile(it, 95))},
                            "all_converged": bool(ok), "rounds": rounds, "counters": eng.counters(),
                            "starts": {"plain": starts.count(0), "learned": starts.count(1),
-                                      "fallback": starts.count(2)},
+                                      "fallback": starts.count(2), "extrapolated": starts.count(3)},
                            "live_checks": bool(lv), "minimizer": mz, "final_star_vs_plain": star_vs_plain}
     eng.set_minimizer("fire")
     cg_form = res_forms.pop("cg", None)
+    ex_form = res_forms.pop("extrapolated", None)
     lr = res_forms[main_form]
     cnt = res_forms[roof_form]["counters"]
     # inherent-structure agreement of the two forms: same decisions, same final r_star (Eq. 20)
@@ -341,6 +346,17 @@ def main() -> int:
         "batched": None if not live else
         {k: v for k, v in res_forms[roof_form].items() if k != "counters"},
         "learned_vs_plain": comparison,
+        "extrapolated": None if ex_form is None else
+        {"value": ex_form["value"], "ms_per_step": ex_form["ms_per_step"],
+         "computed_steps_per_s": ex_form["computed_steps_per_s"],
+         "fire_iters_per_step": ex_form["fire_iters_per_step"], "starts": ex_form["starts"],
+         "all_converged": ex_form["all_converged"], "final_star_vs_plain": ex_form["final_star_vs_plain"],
+         "same_decisions_as_plain": [r["decisions"] for r in ex_form["rounds"]]
+         == [r["decisions"] for r in res_forms["plain"]["rounds"]],
+         "iters_ratio_over_plain": ex_form["fire_iters_per_step"]["mean"]
+         / res_forms["plain"]["fire_iters_per_step"]["mean"],
+         "wall_ratio_over_plain": ex_form["ms_per_step"] / res_forms["plain"]["ms_per_step"],
+         "rounds": ex_form["rounds"]},
         "cg": None if cg_form is None else
         {"value": cg_form["value"], "ms_per_step": cg_form["ms_per_step"],
          "computed_steps_per_s": cg_form["computed_steps_per_s"],

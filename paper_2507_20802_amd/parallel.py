@@ -63,7 +63,7 @@ class GlassRun:
     rounds: List[dict] = field(default_factory=list)
     decisions: List[Decision] = field(default_factory=list)
     step_iters: List[int] = field(default_factory=list)     # FIRE iterations of every fine step computed
-    step_starts: List[int] = field(default_factory=list)    # start used by every fine step (0/1/2)
+    step_starts: List[int] = field(default_factory=list)    # start used by every fine step (AQS_START_*)
     accepted_iters: List[int] = field(default_factory=list)  # ... of the accepted fine steps
     anchor_iters: List[int] = field(default_factory=list)    # anchor minimisations
     energies: List[float] = field(default_factory=list)      # accepted trajectory E (per accepted step)
