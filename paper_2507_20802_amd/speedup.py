@@ -8,6 +8,10 @@ eps_LL = 1 (Eqs. 14-15), cut at 2.5 sigma_ab -- sheared by dgamma = 1/200 for
 200 steps.  The paper's melt-quenched samples are not available: each sample
 is a seeded uniform random start minimised to an inherent structure.
 
+Every minimisation after the initial quench uses FIRE or, with
+--minimizer cg, the paper's own conjugate gradients; --start extrapolated
+starts every fine step from the extrapolated start.
+
 For every sample j and every (P, K): C_j^(S) is the wall time of the 200
 sequential AQS steps (one chain run on the device), C_j^(P,K) that of
 Algorithm 1 with P chains of K steps (parallel.run), S_j = C_j^(S) /
@@ -30,8 +34,8 @@ import time
 import numpy as np
 
 from . import parallel
-from ._lib import AQS_START_PLAIN
-from .engine import Engine, Fire, LJParams
+from ._lib import AQS_START_EXTRAPOLATED, AQS_START_PLAIN
+from .engine import Cg, Engine, Fire, LJParams
 
 # Eqs. (14)-(15), type 0 = small (S), type 1 = large (L)
 SIGMA_LL = 2.0 * math.sin(math.pi / 5.0)
@@ -65,8 +69,11 @@ def inherent_structure(seed: int, fire: Fire | None = None):
 
 
 def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq: float = 1e-4,
-             fire: Fire | None = None, log=None) -> dict:
-    """S_j^(P,K) for every sample seed and (P, K); mu and sigma per (P, K)."""
+             fire: Fire | None = None, log=None, minimizer: str = "fire", start: int = AQS_START_PLAIN) -> dict:
+    """S_j^(P,K) for every sample seed and (P, K); mu and sigma per (P, K).
+    minimizer: "fire" or "cg" (the paper's conjugate gradients) for every
+    minimisation after the initial quench; start: the start of every fine
+    step, sequential and parallel alike."""
     fire = fire or Fire()
     pot = paper_potential()
     per = {(P, K): {"S": [], "final_equal": [], "max_disp": [], "t_par": [], "computed": []}
@@ -78,12 +85,13 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
         n = smp.n
         # sequential AQS: one chain of n_steps fine steps on the device
         seq = Engine(2, [n], smp.L, DGAMMA, pot=pot, fire=fire)
+        seq.set_minimizer(minimizer, Cg() if minimizer == "cg" else None)
         seq.set_replica(0, smp.types, is_pos, 0)
-        seq.minimize([0], n_steps=[2])                      # warm-up
+        seq.minimize([0], n_steps=[2], start=start)         # warm-up
         seq.set_replica(0, smp.types, is_pos, 0)
         _sync()
         t = time.perf_counter()
-        rec = seq.minimize([0], n_steps=[n_steps])
+        rec = seq.minimize([0], n_steps=[n_steps], start=start)
         _sync()
         t_seq = time.perf_counter() - t
         seq_final = seq.positions(0)
@@ -93,6 +101,7 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
             if P not in engines:
                 engines[P] = Engine(2, [n] * (parallel.slots_needed(1, P) + 1), smp.L, DGAMMA, pot=pot,
                                     fire=fire)
+                engines[P].set_minimizer(minimizer, Cg() if minimizer == "cg" else None)
             eng = engines[P]
             ref = parallel.slots_needed(1, P)
             for K in Ks:
@@ -100,8 +109,7 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
                 eng.set_replica(g.star, smp.types, is_pos, 0)
                 _sync()
                 t = time.perf_counter()
-                out = parallel.run(eng, [g], n_steps, K, P, delta_eq=delta_eq, start=AQS_START_PLAIN,
-                                   live=live)
+                out = parallel.run(eng, [g], n_steps, K, P, delta_eq=delta_eq, start=start, live=live)
                 _sync()
                 t_par = time.perf_counter() - t
                 eng.set_replica(ref, smp.types, seq_final, n_steps)
@@ -125,7 +133,8 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
                       "t_par_mean_s": float(np.mean(d["t_par"]))})
     it = np.asarray(seq_iters, dtype=np.float64)
     return {"table": table, "samples": len(list(seeds)), "n_steps": n_steps, "dgamma": DGAMMA,
-            "live_checks": bool(live), "t_seq_mean_s": float(np.mean(t_seq_all)),
+            "live_checks": bool(live), "minimizer": minimizer, "start": int(start),
+            "t_seq_mean_s": float(np.mean(t_seq_all)),
             "fire_iters_per_step": {"mean": float(it.mean()), "median": float(np.median(it)),
                                     "p95": float(np.percentile(it, 95))}}
 
@@ -137,11 +146,14 @@ def main(argv=None) -> int:
     ap.add_argument("--K", type=int, nargs="+", default=[1, 2, 6, 10, 14, 16])
     ap.add_argument("--steps", type=int, default=N_STEPS)
     ap.add_argument("--live", type=int, default=1)
+    ap.add_argument("--minimizer", choices=("fire", "cg"), default="fire")
+    ap.add_argument("--start", choices=("plain", "extrapolated"), default="plain")
     args = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
     res = speedups(range(args.samples), args.P, args.K, n_steps=args.steps, live=bool(args.live),
-                   log=lambda s: print(s, file=sys.stderr, flush=True))
+                   log=lambda s: print(s, file=sys.stderr, flush=True), minimizer=args.minimizer,
+                   start=AQS_START_EXTRAPOLATED if args.start == "extrapolated" else AQS_START_PLAIN)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -56,3 +56,13 @@ def test_short_speedup_run_keeps_the_sequential_trajectory():
         for row in res["table"]:
             assert row["final_equal"] == row["samples"] == 2
             assert row["mu"] > 0.0 and math.isfinite(row["sigma"])
+
+
+def test_short_speedup_run_with_the_papers_minimiser():
+    """The same protocol with conjugate gradients (the paper's minimiser):
+    Algorithm 1 still ends in the sequential run's configuration."""
+    from paper_2507_20802_amd import speedup
+    res = speedup.speedups(range(2), [4], [3], n_steps=12, live=True, minimizer="cg")
+    assert res["minimizer"] == "cg"
+    for row in res["table"]:
+        assert row["final_equal"] == row["samples"] == 2
