@@ -58,6 +58,7 @@ def test_short_speedup_run_keeps_the_sequential_trajectory():
             assert row["mu"] > 0.0 and math.isfinite(row["sigma"])
 
 
+@pytest.mark.gpu
 def test_short_speedup_run_with_the_papers_minimiser():
     """The same protocol with conjugate gradients (the paper's minimiser):
     Algorithm 1 still ends in the sequential run's configuration."""
