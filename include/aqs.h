@@ -118,7 +118,11 @@ typedef struct {
   int32_t use_graph;        /* 1: replay each block of iterations as a hipGraph */
   int32_t max_chain_steps;  /* largest n_steps accepted by aqs_minimize_batch; 0 = 1024 */
   int32_t threads_per_atom; /* force kernel: 1, 2, 4 or 8 lanes per atom; 0 = 2 */
-  int32_t pad_;
+  int32_t live_batch_blocks;/* aqs_run_round with live = 1: while a chain runs alone on
+                               the second stream, the batch's force launches hold at
+                               most this many blocks per compute unit, so that every
+                               compute unit keeps room for a block of the critical
+                               chain (1-4; 0 = 3; < 0 = no limit).  Changes no result. */
 } aqs_tuning;
 
 /* One record per minimisation of a chain (index 0 = the first minimisation,

@@ -46,7 +46,7 @@ class aqs_tuning(ctypes.Structure):
     _fields_ = [("skin", ctypes.c_double), ("max_neighbors", ctypes.c_int32),
                 ("block_iters", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("max_chain_steps", ctypes.c_int32), ("threads_per_atom", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("live_batch_blocks", ctypes.c_int32)]
 
 
 class aqs_step_record(ctypes.Structure):

@@ -51,6 +51,7 @@ double rc_max_of(const aqs_potential* p) {
 struct Tune {
   double skin;
   int max_nb, block_iters, use_graph, log_cap, tpa;
+  int live_blocks;   // batch force blocks per CU beside a critical chain (0: no limit)
 };
 
 Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
@@ -62,6 +63,8 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   r.log_cap = ((t && t->max_chain_steps > 0) ? t->max_chain_steps : 1024) + 1;
   const int tp = t ? t->threads_per_atom : 0;
   r.tpa = (tp == 1 || tp == 2 || tp == 4 || tp == 8) ? tp : 2;
+  const int lb = t ? t->live_batch_blocks : 0;
+  r.live_blocks = lb < 0 ? 0 : (lb == 0 ? 3 : std::min(lb, 4));
   return r;
 }
 
@@ -231,6 +234,7 @@ struct Lane {
   bool ftable_stale = false;       // a rebuild changed the tiles of the selection
   hipGraphExec_t gexec = nullptr;  // captured block of FIRE iterations (use_graph)
   int32_t g_iters = 0;
+  int32_t g_pad = 0;               // its force launches' dynamic LDS
   bool in_flight = false;          // a block of iterations launched, not yet polled
   bool timed = false;              // ... with HIP events around its kernels
 };
@@ -244,6 +248,8 @@ struct aqs_ctx {
   FireParams fire{};
   CgParams cg{};
   int32_t minimizer = kMinFire;   // of later minimisation calls
+  bool live = false;              // a live round runs (aqs_run_round, live = 1)
+  int32_t live_pad = -1;          // force_lds_pad of the live reservation (-1: not yet known)
   PairParams pp[4];
   double rc_max = 0.0;
   hipStream_t stream = nullptr;
@@ -293,6 +299,17 @@ struct aqs_ctx {
 };
 
 namespace {
+bool lane_active(const aqs_ctx* c, const Lane& L);
+
+// Dynamic LDS of the batch lane's force blocks: during a live round, while
+// the critical chain runs on lane 1, the batch yields part of every compute
+// unit to it (stream priorities and CU masks are not used).
+int32_t batch_pad(aqs_ctx* c, const Lane& L) {
+  if (!c->live || c->tn.live_blocks <= 0 || &L != &c->ln[0] || !lane_active(c, c->ln[1]))
+    return 0;
+  if (c->live_pad < 0) c->live_pad = force_lds_pad(c->dim, c->tn.tpa, c->tn.live_blocks);
+  return c->live_pad;
+}
 
 IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   IterArgs a{};
@@ -301,6 +318,7 @@ IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   a.sel = L.sel_d;
   a.nsel = (int32_t)L.cur_sel.size();
   a.tpa = c->tn.tpa;
+  a.lds_pad = batch_pad(c, L);
   a.geom = c->d_geom;
   a.state = c->d_state;
   a.pos4 = c->pos4;
@@ -589,8 +607,9 @@ void drop_graph(Lane& L) {
 // kernel launches only (no memset nodes).
 aqs_status launch_block(aqs_ctx* c, Lane& L, const IterArgs& a, int M) {
   if (c->tn.use_graph && L.s != nullptr) {
-    if (!L.gexec || L.g_iters != M) {
+    if (!L.gexec || L.g_iters != M || L.g_pad != a.lds_pad) {
       drop_graph(L);
+      L.g_pad = a.lds_pad;
       hipGraph_t graph = nullptr;
       HIPCHK(hipStreamBeginCapture(L.s, hipStreamCaptureModeThreadLocal));
       for (int it = 0; it < M; ++it) {
@@ -1315,6 +1334,11 @@ aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int3
     HIPCHK(hipGetLastError());
   }
   int next = 1;   // next check
+  c->live = true;
+  struct LiveOff {
+    aqs_ctx* c;
+    ~LiveOff() { c->live = false; }
+  } live_off{c};
   for (;;) {
     for (Lane* L : {&C, &B})
       if (!L->in_flight && lane_active(c, *L)) {

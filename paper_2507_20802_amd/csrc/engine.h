@@ -164,6 +164,7 @@ struct IterArgs {
   const int32_t* sel;     // slots of the running selection (control kernel)
   int32_t nsel;
   int32_t tpa;            // threads per atom of the force kernel
+  int32_t lds_pad;        // dynamic LDS bytes added to each force block (CU reservation)
   const Geom* geom;
   State* state;
   double4* pos4;

@@ -58,6 +58,9 @@ void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s)
 // per-slot reduction of the force partials and the FIRE control (after launch_force)
 void launch_control(const IterArgs& a, hipStream_t s);
 void launch_update(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s);
+// dynamic LDS bytes per force block that leave at most `blocks` force blocks
+// per CU plus room for one more (0 if none can)
+int32_t force_lds_pad(int32_t dim, int32_t tpa, int32_t blocks);
 
 // Affine shear x += dg_r y of whole slots (host-driven level I step).
 void launch_affine(const int2* blocks, int32_t nblk, const Geom* geom, double4* pos4,

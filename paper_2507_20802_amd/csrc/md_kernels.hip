@@ -12,6 +12,8 @@
 // cell is by atom id, so a rebuild gives the same sorted order every run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "tiles.h"
 
@@ -807,10 +809,48 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
 template <int D>
 void launch_force_d(const IterArgs& a, int32_t ntiles, int32_t tpa, hipStream_t s) {
   switch (tpa) {
-    case 1: hipLaunchKernelGGL((k_force<D, 1>), dim3(ntiles), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_force<D, 2>), dim3(ntiles), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_force<D, 4>), dim3(ntiles), dim3(kBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_force<D, 8>), dim3(ntiles), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_force<D, 1>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a); break;
+    case 2: hipLaunchKernelGGL((k_force<D, 2>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a); break;
+    case 4: hipLaunchKernelGGL((k_force<D, 4>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a); break;
+    default: hipLaunchKernelGGL((k_force<D, 8>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a); break;
+  }
+}
+
+// Dynamic LDS to add to each force block so that at most `blocks` of them
+// fit on a CU and one more block of the same kernel still does: with static
+// LDS S per block and LDS C per CU, the padded size X satisfies
+// (blocks + 1) X > C and blocks X + S <= C.  0 if no such X exists.
+template <int D, int TPA>
+int32_t force_pad_d(int32_t blocks) {
+  hipFuncAttributes fa{};
+  int dev = 0, cu_lds = 0;
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_force<D, TPA>)) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+          hipSuccess)
+    return 0;
+  const int64_t S = (int64_t)fa.sharedSizeBytes, C = cu_lds;
+  const int64_t lo = C / (blocks + 1) + 1;              // smallest X with (blocks + 1) X > C
+  const int64_t hi = (C - S) / blocks;                  // largest X with blocks X + S <= C
+  if (blocks < 1 || lo > hi || lo <= S) return 0;
+  const int64_t X = std::min(hi, (lo + 511) / 512 * 512);  // a 512-byte multiple when one fits
+  return (int32_t)(X - S);
+}
+
+int32_t force_lds_pad(int32_t dim, int32_t tpa, int32_t blocks) {
+  if (dim == 3) {
+    switch (tpa) {
+      case 1: return force_pad_d<3, 1>(blocks);
+      case 2: return force_pad_d<3, 2>(blocks);
+      case 4: return force_pad_d<3, 4>(blocks);
+      default: return force_pad_d<3, 8>(blocks);
+    }
+  }
+  switch (tpa) {
+    case 1: return force_pad_d<2, 1>(blocks);
+    case 2: return force_pad_d<2, 2>(blocks);
+    case 4: return force_pad_d<2, 4>(blocks);
+    default: return force_pad_d<2, 8>(blocks);
   }
 }
 

@@ -101,6 +101,7 @@ class Tuning:
     use_graph: int = 0
     max_chain_steps: int = 1024
     threads_per_atom: int = 0
+    live_batch_blocks: int = 0   # live rounds: batch force blocks per CU (0: 3; < 0: no limit)
 
     def to_c(self) -> aqs_tuning:
         t = aqs_tuning()
@@ -110,6 +111,7 @@ class Tuning:
         t.use_graph = self.use_graph
         t.max_chain_steps = self.max_chain_steps
         t.threads_per_atom = self.threads_per_atom
+        t.live_batch_blocks = self.live_batch_blocks
         return t
 
 

@@ -157,3 +157,33 @@ def test_live_round_equals_batched_round(delta_eq):
             # a stopped chain: finished minimisations first, then cancelled ones
             k = int(ran.sum())
             assert not ran[k:].any()
+
+
+def test_live_cu_reservation_changes_no_result():
+    """The batch's force launches yield compute units to the critical chain
+    during live rounds (live_batch_blocks); with no limit, the default and
+    the tightest limit the decisions, every minimisation both runs finished
+    and the ends of the chains that ran to completion are bitwise the same.  3D slots, so that the force launches
+    fill the GPU."""
+    from paper_2507_20802_amd import Engine, Tuning, parallel
+    pos, types, L, dim = load_glass("glass3d_1500")
+    fire, _ = fire_pair()
+    P, K, dg = 4, 5, 1e-3
+    out = []
+    for blocks in (-1, 0, 1):
+        eng = Engine(dim, [len(types)] * parallel.slots_needed(1, P), L, dg, fire=fire,
+                     tuning=Tuning(live_batch_blocks=blocks))
+        g = parallel.layout(1, P)[0]
+        eng.set_replica(g.star, types, pos, 0)
+        recs, checks = _round(eng, g, P, K, K, 1e-4, live=True)
+        out.append((recs, [c[:2] for c in checks], [eng.positions(g.chains[i]) for i in range(P)]))
+    from paper_2507_20802_amd._lib import AQS_CANCELLED
+    r0, c0, e0 = out[0]
+    for recs, checks, ends in out[1:]:
+        assert checks == c0
+        for i in range(P):
+            # a stopped chain's last finished minimisation depends on timing
+            both = (recs[i]["status"] != AQS_CANCELLED) & (r0[i]["status"] != AQS_CANCELLED)
+            assert np.array_equal(recs[i][both], r0[i][both])
+            if both.all():
+                assert np.array_equal(ends[i], e0[i])
