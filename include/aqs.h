@@ -252,6 +252,11 @@ aqs_status aqs_minimize_batch(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
  * FIRE.  AQS_EINVAL for an unknown minimiser or parameters out of range. */
 aqs_status aqs_set_minimizer(aqs_ctx* ctx, int32_t minimizer, const aqs_cg_params* cg);
 
+/* Change the tuning field live_batch_blocks of ctx (same meaning, same
+ * default for 0) for later live rounds, e.g. from how often earlier checks
+ * passed.  Changes no result. */
+aqs_status aqs_set_live_batch_blocks(aqs_ctx* ctx, int32_t blocks);
+
 /* Outcome of check i of a round (Algorithm 1, Sec. 3.5): the end of chain
  * i-1 against the first inherent structure of chain i, Eq. (20). */
 typedef struct {

@@ -109,6 +109,7 @@ SIGNATURES = {
     "aqs_stress": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p, c_double_p]),
     "aqs_energy_forces": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p, c_double_p]),
     "aqs_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "aqs_set_live_batch_blocks": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "aqs_set_minimizer": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(aqs_cg_params)]),
     "aqs_get_counters": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_counters), ctypes.c_int32]),
     "aqs_learned_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_mlp)]),

@@ -1538,6 +1538,13 @@ aqs_status aqs_set_minimizer(aqs_ctx* c, int32_t minimizer, const aqs_cg_params*
   return AQS_OK;
 }
 
+aqs_status aqs_set_live_batch_blocks(aqs_ctx* c, int32_t blocks) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  c->tn.live_blocks = blocks < 0 ? 0 : (blocks == 0 ? 3 : std::min(blocks, 4));
+  c->live_pad = -1;   // recomputed for the new limit at the next live launch
+  return AQS_OK;
+}
+
 aqs_status aqs_set_profiling(aqs_ctx* c, int32_t every_nth_block) {
   if (!c) return fail(AQS_EINVAL, "null context");
   c->prof_every = every_nth_block > 0 ? every_nth_block : 0;

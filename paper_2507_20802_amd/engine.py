@@ -326,6 +326,11 @@ class Engine:
             raise ValueError(f"unknown minimiser {kind!r}")
         self.minimizer = kind
 
+    def set_live_batch_blocks(self, blocks: int) -> None:
+        """Batch force blocks per CU beside the critical chain of later live
+        rounds (0: the default, 3; < 0: no limit); changes no result."""
+        check(self._lib.aqs_set_live_batch_blocks(self._ctx, int(blocks)), "aqs_set_live_batch_blocks")
+
     def set_profiling(self, every_nth_block: int) -> None:
         check(self._lib.aqs_set_profiling(self._ctx, int(every_nth_block)), "aqs_set_profiling")
 

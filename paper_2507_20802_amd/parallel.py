@@ -89,17 +89,38 @@ def layout(n_glasses: int, P: int, first: int = 0) -> List[GlassRun]:
     return out
 
 
+def reservation_for(last_checks: List[bool]) -> int:
+    """Batch force blocks per CU for the next live round (aqs_tuning
+    live_batch_blocks) from the decided checks of the last round: speculation
+    that paid (at least three quarters passed) runs unthrottled (-1); checks
+    that mostly failed (under a quarter passed) leave two blocks per CU to
+    the batch; otherwise, and with no history, the default (0, i.e. 3)."""
+    if not last_checks:
+        return 0
+    f = sum(bool(c) for c in last_checks) / len(last_checks)
+    if f >= 0.75:
+        return -1
+    if f < 0.25:
+        return 2
+    return 0
+
+
 def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq: float = 1e-4,
-        start: int = AQS_START_PLAIN, max_rounds: int | None = None, log=None, live: bool = False) -> dict:
+        start: int = AQS_START_PLAIN, max_rounds: int | None = None, log=None, live: bool = False,
+        adaptive_reservation: bool = True) -> dict:
     """Run Algorithm 1 to n_steps accepted fine steps for every glass (each
     glass's r_star must be loaded in its star slot as an inherent structure).
-    Returns timing and counts; per-glass details are filled into glasses."""
+    With live checks and adaptive_reservation, each round's CU reservation
+    for the critical chain follows the previous round's checks
+    (reservation_for).  Returns timing and counts; per-glass details are
+    filled into glasses."""
     if P < 2:
         raise ValueError("Algorithm 1 needs P >= 2 (Sec. 3.2)")
     t0 = time.perf_counter()
     rnd = 0
     t_min = 0.0
     t_check = 0.0
+    last_checks: List[bool] = []
     while any(g.n_current < n_steps for g in glasses):
         if max_rounds is not None and rnd >= max_rounds:
             break
@@ -122,6 +143,9 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
             engine.affine_shear(aff, dks)           # level I (Eq. 18)
         t1 = time.perf_counter()
         rows, outcomes = {}, {}
+        if live and adaptive_reservation:
+            engine.set_live_batch_blocks(reservation_for(last_checks))
+        last_checks = []
         if live:
             for gi, lengths in plans.items():        # level II + live checks, glass by glass
                 g = glasses[gi]
@@ -180,11 +204,14 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
             engine.copy_replica(g.chains[last], g.star)   # r_star <- r_q
             g.rounds.append({"round": rnd, "start": g.n_current, "lengths": lengths,
                              "checks": checks, "q": q})
+            last_checks.extend(checks)
             g.n_current += q
             if log:
                 log(f"round {rnd} glass {gi}: checks {checks} q {q} -> N_current {g.n_current}")
         t_check += time.perf_counter() - t2
         rnd += 1
+    if live and adaptive_reservation:
+        engine.set_live_batch_blocks(engine.tuning.live_batch_blocks)
     wall = time.perf_counter() - t0
     acc = sum(g.n_current for g in glasses)
     comp = sum(g.computed_steps for g in glasses)

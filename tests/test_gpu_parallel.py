@@ -187,3 +187,22 @@ def test_live_cu_reservation_changes_no_result():
             assert np.array_equal(recs[i][both], r0[i][both])
             if both.all():
                 assert np.array_equal(ends[i], e0[i])
+
+
+def test_adaptive_reservation_changes_no_result():
+    """parallel.run with live checks, the CU reservation chosen per round from
+    the last round's checks, and without: the same rounds and the same r_star
+    bit for bit."""
+    from paper_2507_20802_amd import Engine, parallel
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, _ = fire_pair()
+    dg, K, P, n = 4e-3, 5, 4, 20
+    res = []
+    for adaptive in (True, False):
+        eng = Engine(dim, [len(types)] * parallel.slots_needed(1, P), L, dg, fire=fire)
+        g = parallel.layout(1, P)[0]
+        eng.set_replica(g.star, types, pos, 0)
+        out = parallel.run(eng, [g], n, K, P, live=True, adaptive_reservation=adaptive)
+        res.append(([(r["checks"], r["q"]) for r in g.rounds], eng.positions(g.star), out["accepted_steps"]))
+    assert res[0][0] == res[1][0] and res[0][2] == res[1][2] == n
+    assert np.array_equal(res[0][1], res[1][1])
