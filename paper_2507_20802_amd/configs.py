@@ -1,0 +1,137 @@
+"""Throughput of the engine on the workloads beside the benchmark's
+(3D, N = 32768, one round of P = 16 x K = 200, in bench.py):
+
+* small   2D binary LJ glass, N = 256, 50 sequential AQS steps of 1e-4
+          (one replica: launch-latency bound);
+* batch2d four 2D N = 4096 glasses, each one round of Algorithm 1 with
+          P = 8 chains of K = 100 steps of 1e-4 (level-I anchors 1e-2 apart),
+          all 32 chains in one batched launch sequence;
+* uneven  24 3D replicas, N log-uniform in [2048, 131072] and dgamma in
+          {1e-5, 1e-4} (seeded), 100 sequential AQS steps each, all in one
+          batch with graph-replayed iteration blocks and tuned knobs.
+
+Every glass is a seeded uniform random start quenched on the device (the
+paper's samples are not available); FIRE to max|F| < 1e-10.  Run as
+python -m paper_2507_20802_amd.configs [small batch2d uneven] (one JSON line
+each).  Times are wall-clock around the timed call, inputs resident on the
+device.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import autotune, parallel
+from .engine import Engine, Fire
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _quenched(eng, slot, smp):
+    eng.set_replica(slot, smp.types, smp.pos, 0)
+    rec = eng.minimize([slot])[0, 0]
+    if rec["status"] != 0:
+        raise RuntimeError(f"quench of slot {slot} failed (status {rec['status']})")
+
+
+def small(steps: int = 50, dgamma: float = 1e-4) -> dict:
+    import aqs_synth as S
+    smp = S.uniform_glass_start(2, 256, 1, 0)
+    eng = Engine(2, [256], smp.L, dgamma, fire=Fire(), tuning="auto")
+    _quenched(eng, 0, smp)
+    is_pos = eng.positions(0)
+    eng.minimize([0], n_steps=[3])                       # warm-up
+    eng.set_replica(0, smp.types, is_pos, 0)
+    _sync()
+    t = time.perf_counter()
+    rec = eng.minimize([0], n_steps=[steps])[0]
+    _sync()
+    dt = time.perf_counter() - t
+    it = rec["iters"][1:]
+    return {"config": "small", "workload": f"2D N=256, {steps} sequential AQS steps, dgamma={dgamma:g}",
+            "aqs_steps_per_s": steps / dt, "wall_s": dt, "fire_iters_per_step": float(it.mean()),
+            "us_per_iteration": 1e6 * dt / float(it.sum()), "all_converged": bool(np.all(rec["status"] == 0))}
+
+
+def batch2d(glasses: int = 4, P: int = 8, K: int = 100, dgamma: float = 1e-4) -> dict:
+    import aqs_synth as S
+    n = 4096
+    smps = [S.uniform_glass_start(2, n, 2, r) for r in range(glasses)]
+    per = parallel.slots_needed(1, P)
+    eng = Engine(2, [n] * (glasses * per), smps[0].L, dgamma, fire=Fire(), tuning="auto")
+    gl = parallel.layout(glasses, P)
+    pos = []
+    for g, smp in zip(gl, smps):
+        _quenched(eng, g.star, smp)
+        pos.append(eng.positions(g.star))
+    # warm-up round of short chains
+    parallel.run(eng, gl, P * 5, 5, P, max_rounds=1)
+    for g, smp, x in zip(gl, smps, pos):
+        eng.set_replica(g.star, smp.types, x, 0)
+    gl = parallel.layout(glasses, P)
+    _sync()
+    t = time.perf_counter()
+    out = parallel.run(eng, gl, P * K, K, P, max_rounds=1)
+    _sync()
+    dt = time.perf_counter() - t
+    return {"config": "batch2d", "workload": f"{glasses} x 2D N={n}, one round of P={P} x K={K}, "
+            f"dgamma={dgamma:g}, dgamma_c={K * dgamma:g}, {glasses * P} chains batched",
+            "accepted_steps_per_s": out["accepted_steps"] / dt, "computed_steps_per_s": out["computed_steps"] / dt,
+            "wall_s": dt, "accepted": out["accepted_steps"], "computed": out["computed_steps"],
+            "fire_iters_per_step": out["iters_mean"], "all_converged": out["statuses_ok"],
+            "checks": [r["checks"] for g in gl for r in g.rounds]}
+
+
+def uneven(steps: int = 100, reps: int = 24) -> dict:
+    import aqs_synth as S
+    rng = S.rng_for(5)
+    ns = [int(round(np.exp(rng.uniform(np.log(2048), np.log(131072))))) for _ in range(reps)]
+    dgs = [float(rng.choice([1e-5, 1e-4])) for _ in range(reps)]
+    smps = [S.uniform_glass_start(3, n, 5, r) for r, n in enumerate(ns)]
+    tn = autotune.tuned(3, ns, reps)
+    tn.use_graph = 1
+    eng = Engine(3, ns, np.array([[s.L] * 3 for s in smps]), dgs, fire=Fire(), tuning=tn)
+    for r, s in enumerate(smps):
+        eng.set_replica(r, s.types, s.pos, 0)
+    q = eng.minimize(list(range(reps)))
+    if np.any(q[:, 0]["status"] != 0):
+        raise RuntimeError("quench failed")
+    is_pos = [eng.positions(r) for r in range(reps)]
+    eng.minimize(list(range(reps)), n_steps=[2] * reps)    # warm-up
+    for r, s in enumerate(smps):
+        eng.set_replica(r, s.types, is_pos[r], 0)
+    _sync()
+    t = time.perf_counter()
+    rec = eng.minimize(list(range(reps)), n_steps=[steps] * reps)
+    _sync()
+    dt = time.perf_counter() - t
+    it = rec["iters"][:, 1:]
+    atoms = int(sum(ns))
+    return {"config": "uneven", "workload": f"{reps} 3D replicas, N log-uniform in [2048, 131072] "
+            f"({atoms} atoms), dgamma in {{1e-5, 1e-4}}, {steps} sequential AQS steps each",
+            "aqs_steps_per_s": reps * steps / dt, "atom_steps_per_s": atoms * steps / dt, "wall_s": dt,
+            "fire_iters_per_step": float(it.mean()), "all_converged": bool(np.all(rec["status"] == 0)),
+            "n_atoms": ns, "dgamma": dgs}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("configs", nargs="*", default=["small", "batch2d", "uneven"])
+    args = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    runs = {"small": small, "batch2d": batch2d, "uneven": uneven}
+    for name in args.configs:
+        print(json.dumps(runs[name]()), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -67,3 +67,11 @@ def test_short_speedup_run_with_the_papers_minimiser():
     assert res["minimizer"] == "cg"
     for row in res["table"]:
         assert row["final_equal"] == row["samples"] == 2
+
+
+@pytest.mark.gpu
+def test_small_workload_runner():
+    """The runner of the other workloads, on its smallest one (a few steps)."""
+    from paper_2507_20802_amd import configs
+    out = configs.small(steps=5)
+    assert out["all_converged"] and out["aqs_steps_per_s"] > 0.0
