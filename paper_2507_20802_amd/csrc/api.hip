@@ -812,10 +812,19 @@ aqs_status lane_poll(aqs_ctx* c, Lane& L, bool all_states, int& active) {
     if (ph == PH_REBUILD) rb.push_back(r);
     if (ph != PH_DONE) ++active;
   }
-  if (!active || rb.empty()) return AQS_OK;
-  st = rebuild(c, L, rb, true);
-  if (st) return st;
-  if (L.ftable_stale) return set_table(c, L, L.cur_sel);   // a grid changed its tile count
+  if (!active) return AQS_OK;
+  if (!rb.empty()) {
+    st = rebuild(c, L, rb, true);
+    if (st) return st;
+  }
+  // finished slots leave the launch tables (their blocks would only read
+  // their phase and exit); a grid that changed its tile count also re-tables
+  if (active < (int)L.cur_sel.size() || L.ftable_stale) {
+    std::vector<int32_t> left;
+    for (int r : L.cur_sel)
+      if (c->h_state[r].phase != PH_DONE) left.push_back(r);
+    return set_table(c, L, left);
+  }
   return AQS_OK;
 }
 
