@@ -33,7 +33,13 @@ sys.path.insert(0, ROOT)
 METRIC = "AQS steps/s & FIRE iters/step at N=32k, learned-start vs plain, max|F|<1e-10"
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 HBM_PEAK_GBS = 8000.0
-FLOPS_PER_PAIR = 29          # one in-cutoff pair, counted once
+# algorithmic FP64 work of one in-cutoff pair, counted once (Newton's third
+# law): the separation and r^2, the reciprocal, the LJ powers, U'(r)/r, the
+# shifted energy and the force components
+FLOPS_PER_PAIR = 29
+# algorithmic bytes per atom of the force kernel: positions and type in
+# (d x 8 + 1, rounded to the 4-byte type), forces out (d x 8), velocities in
+# for F.v (d x 8)
 FORCE_BYTES_PER_ATOM = {2: 49, 3: 73}
 
 
