@@ -212,3 +212,46 @@ def test_learned_chain_reaches_the_plain_inherent_structures():
     assert O.compare(eng.positions(0), x, O.strain_box(dim, L2, nst, dg))[0] < 1e-4
     assert set(starts) <= {1, 2}
     print("starts", starts, "iters", recs["iters"].tolist())
+
+
+def test_learned_start_gain_on_its_own_history():
+    """What the trained network gains over the method without it: trained on
+    the non-affine displacements of 24 plain AQS steps of a glass (small
+    elastic steps, dgamma = 1e-5), it starts the next 8 steps.  Every step
+    reaches the plain start's inherent structure (Eq. 20, energies to
+    1e-10), and the learned starts take fewer FIRE iterations in total."""
+    from paper_2507_20802_amd import AQS_START_LEARNED, AQS_START_PLAIN, learned
+    torch = _torch()
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, _ = fire_pair()
+    # 200 epochs: the start must beat the plain one in max |F_i| too, which
+    # needs the fit of the displacement field to be nearly exact (after 60
+    # epochs R^2 = 0.994 on the next step, and one atom's force still
+    # exceeds the plain start's)
+    dg, hist_steps, nst, epochs = 1e-5, 24, 8, 200
+    eng = engine(dim, [len(types)] * 2, L, dg, fire=fire)
+    eng.set_replica(0, types, pos, 0)
+    feat, tgt, _ = learned.collect_samples(eng, 0, 1, hist_steps)
+    start_is = eng.positions(0)
+    orders = torch.from_numpy(S.epoch_orders(feat.shape[0], epochs, 310)).cuda()
+    m = learned.make_mlp(dim, S.mlp_init(dim, 311))
+    loss = learned.train(m, feat, tgt, orders, learned.TrainParams(batch=256, epochs=epochs))
+    assert loss[-1] < 0.01 * loss[0]
+    out = {}
+    for mode in (AQS_START_PLAIN, AQS_START_LEARNED):
+        e = engine(dim, [len(types)], L, dg, fire=fire)
+        if mode == AQS_START_LEARNED:
+            e.learned_load(m)
+        e.set_replica(0, types, start_is, hist_steps)
+        rec = e.minimize([0], n_steps=[nst], start=mode)[0]
+        assert np.all(rec["status"] == 0)
+        out[mode] = (rec, e.positions(0))
+    rp, xp = out[AQS_START_PLAIN]
+    rl, xl = out[AQS_START_LEARNED]
+    assert np.allclose(rl["energy"], rp["energy"], rtol=E_REL_TOL, atol=0)
+    assert O.compare(xl, xp, O.strain_box(dim, L, hist_steps + nst, dg))[0] < 1e-6
+    it_p, it_l = int(rp["iters"][1:].sum()), int(rl["iters"][1:].sum())
+    used = int((rl["start"][1:] == 1).sum())
+    print(f"loss {loss[0]:.3g} -> {loss[-1]:.3g}; FIRE iterations plain {it_p} learned {it_l}; "
+          f"learned starts used {used}/{nst}")
+    assert used >= 1 and it_l < it_p
