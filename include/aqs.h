@@ -280,7 +280,9 @@ typedef struct {
  * next read-back (the live check the paper proposes in its discussion of
  * load balance, Sec. 4).  The chain whose end the next check needs runs on a
  * second stream of its own, the other chains in one batch on the context
- * stream, so the critical chain does not wait on the batch.  Decisions,
+ * stream, so the critical chain does not wait on the batch; the batch's
+ * force launches leave room for it on every compute unit
+ * (aqs_tuning.live_batch_blocks, aqs_set_live_batch_blocks).  Decisions,
  * accepted steps and every kept inherent structure are those of live = 0
  * (the minimisations do not depend on which slots share a launch).
  *
