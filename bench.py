@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # law): the separation and r^2, the reciprocal, the LJ powers, U'(r)/r, the
 # shifted energy and the force components
 FLOPS_PER_PAIR = 29
-# algorithmic bytes per atom of the force kernel: positions and type in
-# (d x 8 + 1, rounded to the 4-byte type), forces out (d x 8), velocities in
-# for F.v (d x 8)
+# algorithmic bytes per atom of the force kernel: positions (d doubles) and
+# the type (one byte) in, velocities in for F.v and forces out (d doubles
+# each): 24 d + 1
 FORCE_BYTES_PER_ATOM = {2: 49, 3: 73}
 
 
