@@ -1524,6 +1524,7 @@ aqs_status aqs_set_minimizer(aqs_ctx* c, int32_t minimizer, const aqs_cg_params*
   if (!c) return fail(AQS_EINVAL, "null context");
   if (minimizer == AQS_MIN_FIRE) {
     c->minimizer = kMinFire;
+    for (Lane& L : c->ln) drop_graph(L);   // captured launches hold the minimiser's kernels
     return AQS_OK;
   }
   if (minimizer != AQS_MIN_CG) return fail(AQS_EINVAL, "unknown minimizer %d", minimizer);
