@@ -8,12 +8,16 @@
           all 32 chains in one batched launch sequence;
 * uneven  24 3D replicas, N log-uniform in [2048, 131072] and dgamma in
           {1e-5, 1e-4} (seeded), 100 sequential AQS steps each, all in one
-          batch with graph-replayed iteration blocks and tuned knobs.
+          batch with graph-replayed iteration blocks and tuned knobs;
+* paper   the paper's benchmark problem (Sec. 2.2: 2D, N = 400, Eqs. 14-15,
+          dgamma = 1/200, 200 steps) for many samples at once: every sample's
+          sequential AQS in one batch, against one sample alone.
 
 Every glass is a seeded uniform random start quenched on the device (the
-paper's samples are not available); FIRE to max|F| < 1e-10.  Run as
-python -m paper_2507_20802_amd.configs [small batch2d uneven] (one JSON line
-each).  Times are wall-clock around the timed call, inputs resident on the
+paper's samples are not available; the paper's problem uses its cell,
+composition and potential); FIRE to max|F| < 1e-10.  Run as
+python -m paper_2507_20802_amd.configs [small batch2d uneven paper] (one JSON
+line each).  Times are wall-clock around the timed call, inputs resident on the
 device.
 """
 from __future__ import annotations
@@ -121,13 +125,48 @@ def uneven(steps: int = 100, reps: int = 24) -> dict:
             "n_atoms": ns, "dgamma": dgs}
 
 
+def paper(samples: int = 256, steps: int = 200) -> dict:
+    import aqs_synth as S
+    from . import speedup as SP
+    smps = [S.paper_sample_start(21, j) for j in range(samples)]
+    n = smps[0].n
+    eng = Engine(2, [n] * samples, smps[0].L, SP.DGAMMA, pot=SP.paper_potential(), fire=Fire())
+    for j, smp in enumerate(smps):
+        eng.set_replica(j, smp.types, smp.pos, 0)
+    q = eng.minimize(list(range(samples)))
+    if np.any(q[:, 0]["status"] != 0):
+        raise RuntimeError("quench failed")
+    is_pos = [eng.positions(j) for j in range(samples)]
+    # one sample alone
+    eng.set_replica(0, smps[0].types, is_pos[0], 0)
+    _sync()
+    t = time.perf_counter()
+    r1 = eng.minimize([0], n_steps=[steps])[0]
+    _sync()
+    t_one = time.perf_counter() - t
+    for j, smp in enumerate(smps):
+        eng.set_replica(j, smp.types, is_pos[j], 0)
+    _sync()
+    t = time.perf_counter()
+    rec = eng.minimize(list(range(samples)), n_steps=[steps] * samples)
+    _sync()
+    dt = time.perf_counter() - t
+    same0 = bool(np.array_equal(rec[0]["energy"], r1["energy"]))
+    return {"config": "paper", "workload": f"{samples} samples of the paper's 2D N={n} problem, "
+            f"{steps} sequential AQS steps of dgamma={SP.DGAMMA:g} each, in one batch",
+            "aqs_steps_per_s": samples * steps / dt, "wall_s": dt, "one_sample_wall_s": t_one,
+            "one_sample_aqs_steps_per_s": steps / t_one, "gain_over_one_at_a_time": samples * t_one / dt,
+            "fire_iters_per_step": float(rec["iters"][:, 1:].mean()),
+            "all_converged": bool(np.all(rec["status"] == 0)), "sample0_same_as_alone": same0}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("configs", nargs="*", default=["small", "batch2d", "uneven"])
+    ap.add_argument("configs", nargs="*", default=["small", "batch2d", "uneven", "paper"])
     args = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
-    runs = {"small": small, "batch2d": batch2d, "uneven": uneven}
+    runs = {"small": small, "batch2d": batch2d, "uneven": uneven, "paper": paper}
     for name in args.configs:
         print(json.dumps(runs[name]()), flush=True)
     return 0

@@ -75,3 +75,12 @@ def test_small_workload_runner():
     from paper_2507_20802_amd import configs
     out = configs.small(steps=5)
     assert out["all_converged"] and out["aqs_steps_per_s"] > 0.0
+
+
+@pytest.mark.gpu
+def test_paper_problem_batched_over_samples():
+    """Samples of the paper's problem in one batch: each converges, and the
+    first one's record equals its run alone bit for bit."""
+    from paper_2507_20802_amd import configs
+    out = configs.paper(samples=8, steps=4)
+    assert out["all_converged"] and out["sample0_same_as_alone"]
