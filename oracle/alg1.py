@@ -23,6 +23,12 @@ Readings where the paper is silent:
   * r_q is the end of chain q/K - 1: the incoming configuration at the first
     failed check, or the end of the last chain when every check passes.
 
+The dynamic choice of K that the paper's outlook proposes (Sec. 5) is an
+optional rule next_k(K, checks) -> K for the next round; adaptive_k is the
+one read here.  Every round's chains still start from the verified r_star
+and every accepted step is checked, so the accepted trajectory is the same
+for any K sequence; only the number of rounds and computed steps change.
+
 The operators are passed in, so the same procedure serves mocked equality
 outcomes (index arithmetic tests) and real minimisations (oracle FIRE).
 """
@@ -40,6 +46,7 @@ class Round:
     lengths: List[int]       # fine steps of each chain
     checks: List[bool]       # outcomes of the checks at i = 1 .. evaluated
     q: int                   # accepted steps
+    K: int = 0               # chain length of the round
 
 
 @dataclass
@@ -58,11 +65,30 @@ def chain_plan(remaining: int, K: int, P: int) -> List[int]:
     return [K] * (p - 1) + [remaining - (p - 1) * K]
 
 
+def adaptive_k(K: int, checks: List[bool], k_min: int, k_max: int) -> int:
+    """Chain length of the next round (the reading of the dynamic choice of
+    K): twice K after a round whose every check passed (longer chains lose
+    nothing while the anchors keep agreeing), half of K rounded up after a
+    round whose first check failed (anchors closer together), K otherwise;
+    then clamped to [k_min, k_max].  A round with one chain made no check
+    and keeps K."""
+    if not checks:
+        return K
+    if all(checks):
+        nxt = 2 * K
+    elif not checks[0]:
+        nxt = (K + 1) // 2
+    else:
+        nxt = K
+    return min(k_max, max(k_min, nxt))
+
+
 def aqs_parallel(r0: Any, n_steps: int, K: int, P: int,
                  level1: Callable[[Any, int], Any],
                  level2: Callable[[List[Any], List[int]], List[tuple]],
-                 equal: Callable[[Any, Any], bool]) -> Result:
-    """Algorithm 1.
+                 equal: Callable[[Any, Any], bool],
+                 next_k: Callable[[int, List[bool]], int] | None = None) -> Result:
+    """Algorithm 1 (with next_k: K chosen anew after every round).
 
     level1(r_star, m)       -> anchor F_N^(m dgamma) r_star (m = i K fine steps)
     level2(anchors, lengths)-> for each anchor i, (outgoing_i, end_i): the
@@ -95,9 +121,13 @@ def aqs_parallel(r0: Any, n_steps: int, K: int, P: int,
                 q = i * K
                 r_q = out[i - 1][1]
                 break
-        res.rounds.append(Round(n_cur, len(lengths), lengths, checks, q))
+        res.rounds.append(Round(n_cur, len(lengths), lengths, checks, q, K))
         r_star = r_q
         n_cur += q
+        if next_k is not None:
+            K = next_k(K, checks)
+            if K < 1:
+                raise ValueError("K must be >= 1")
     res.r_star = r_star
     res.n_current = n_cur
     return res

@@ -17,6 +17,12 @@ Readings (the paper is silent): the last round is clamped to the remaining
 steps (P' = ceil(R / K) chains, the last with R - (P'-1) K steps); a round
 with a single chain accepts it; r_q is the end of chain q/K - 1.
 
+dynamic_k=(k_min, k_max) chooses each glass's K anew after every round (the
+dynamic choice of K of the paper's outlook, Sec. 5; the rule, next_k, is a
+reading).  Chain 0 of a round always starts from the verified r_star and
+every accepted step is checked, so the accepted trajectory does not depend
+on the K sequence; only rounds and computed steps do.
+
 live=True runs each glass's round through aqs_run_round with live checks
 (the improvement the paper proposes in Sec. 4): a check is taken as soon as
 both of its configurations exist, the chain the next check waits on runs on a
@@ -29,7 +35,7 @@ from __future__ import annotations
 import math
 import time
 from dataclasses import dataclass, field
-from typing import List
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -89,6 +95,21 @@ def layout(n_glasses: int, P: int, first: int = 0) -> List[GlassRun]:
     return out
 
 
+def next_k(K: int, checks: List[bool], k_min: int, k_max: int) -> int:
+    """A glass's chain length for its next round: 2K when every check of the
+    round passed, ceil(K / 2) when its first check failed, else K; within
+    [k_min, k_max].  A round without checks (one chain) keeps K."""
+    if len(checks) == 0:
+        return K
+    if checks[0] and all(checks):
+        k = K * 2
+    elif checks[0]:
+        k = K
+    else:
+        k = -(-K // 2)
+    return max(k_min, min(k, k_max))
+
+
 def reservation_for(last_checks: List[bool]) -> int:
     """Batch force blocks per CU for the next live round (aqs_tuning
     live_batch_blocks) from the decided checks of the last round: speculation
@@ -107,15 +128,21 @@ def reservation_for(last_checks: List[bool]) -> int:
 
 def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq: float = 1e-4,
         start: int = AQS_START_PLAIN, max_rounds: int | None = None, log=None, live: bool = False,
-        adaptive_reservation: bool = True) -> dict:
+        adaptive_reservation: bool = True, dynamic_k: Optional[Tuple[int, int]] = None) -> dict:
     """Run Algorithm 1 to n_steps accepted fine steps for every glass (each
     glass's r_star must be loaded in its star slot as an inherent structure).
     With live checks and adaptive_reservation, each round's CU reservation
     for the critical chain follows the previous round's checks
-    (reservation_for).  Returns timing and counts; per-glass details are
-    filled into glasses."""
+    (reservation_for).  dynamic_k=(k_min, k_max): every glass starts with K
+    and takes next_k after each round.  Returns timing and counts; per-glass
+    details (each round's K among them) are filled into glasses."""
     if P < 2:
         raise ValueError("Algorithm 1 needs P >= 2 (Sec. 3.2)")
+    if K < 1:
+        raise ValueError("K must be >= 1")
+    if dynamic_k is not None and not 1 <= dynamic_k[0] <= dynamic_k[1]:
+        raise ValueError("dynamic_k needs 1 <= k_min <= k_max")
+    kg = [K] * len(glasses)
     t0 = time.perf_counter()
     rnd = 0
     t_min = 0.0
@@ -129,13 +156,13 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
         for gi, g in enumerate(glasses):
             if g.n_current >= n_steps:
                 continue
-            lengths = chain_plan(n_steps - g.n_current, K, P)
+            lengths = chain_plan(n_steps - g.n_current, kg[gi], P)
             plans[gi] = lengths
             for i, ln in enumerate(lengths):
                 engine.copy_replica(g.star, g.chains[i])
                 if i > 0:
                     aff.append(g.chains[i])
-                    dks.append(i * K)
+                    dks.append(i * kg[gi])
                 sel.append(g.chains[i])
                 nst.append(ln)
                 snp.append(g.snaps[i] if i > 0 else -1)
@@ -162,6 +189,7 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
         t_min += t2 - t1
         for gi, lengths in plans.items():
             g = glasses[gi]
+            Kr = kg[gi]
             q = lengths[0]
             last = 0
             checks = []
@@ -177,10 +205,10 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
                 g.decisions.append(d)
                 checks.append(eq)
                 if eq:
-                    q = i * K + lengths[i]
+                    q = i * Kr + lengths[i]
                     last = i
                 else:
-                    q = i * K
+                    q = i * Kr
                     last = i - 1
                     break
             # bookkeeping of iterations (fine steps are records 1..len of each
@@ -203,7 +231,9 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
                     g.sigma_xy.extend(float(x) for x in r["sigma_xy"][1: ln + 1])
             engine.copy_replica(g.chains[last], g.star)   # r_star <- r_q
             g.rounds.append({"round": rnd, "start": g.n_current, "lengths": lengths,
-                             "checks": checks, "q": q})
+                             "checks": checks, "q": q, "K": Kr})
+            if dynamic_k is not None:
+                kg[gi] = next_k(Kr, checks, dynamic_k[0], dynamic_k[1])
             last_checks.extend(checks)
             g.n_current += q
             if log:

@@ -10,7 +10,9 @@ is a seeded uniform random start minimised to an inherent structure.
 
 Every minimisation after the initial quench uses FIRE or, with
 --minimizer cg, the paper's own conjugate gradients; --start extrapolated
-starts every fine step from the extrapolated start.
+starts every fine step from the extrapolated start; --dynamic-k KMIN KMAX
+lets each run choose K anew after every round (parallel.next_k), starting
+from each K of the grid.
 
 For every sample j and every (P, K): C_j^(S) is the wall time of the 200
 sequential AQS steps (one chain run on the device), C_j^(P,K) that of
@@ -69,14 +71,16 @@ def inherent_structure(seed: int, fire: Fire | None = None):
 
 
 def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq: float = 1e-4,
-             fire: Fire | None = None, log=None, minimizer: str = "fire", start: int = AQS_START_PLAIN) -> dict:
+             fire: Fire | None = None, log=None, minimizer: str = "fire", start: int = AQS_START_PLAIN,
+             dynamic_k=None) -> dict:
     """S_j^(P,K) for every sample seed and (P, K); mu and sigma per (P, K).
     minimizer: "fire" or "cg" (the paper's conjugate gradients) for every
     minimisation after the initial quench; start: the start of every fine
-    step, sequential and parallel alike."""
+    step, sequential and parallel alike; dynamic_k: (k_min, k_max) for
+    parallel.run, K of the grid being the first round's."""
     fire = fire or Fire()
     pot = paper_potential()
-    per = {(P, K): {"S": [], "final_equal": [], "max_disp": [], "t_par": [], "computed": []}
+    per = {(P, K): {"S": [], "final_equal": [], "max_disp": [], "t_par": [], "computed": [], "rounds": []}
            for P in Ps for K in Ks}
     t_seq_all, seq_iters = [], []
     engines = {}
@@ -109,7 +113,8 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
                 eng.set_replica(g.star, smp.types, is_pos, 0)
                 _sync()
                 t = time.perf_counter()
-                out = parallel.run(eng, [g], n_steps, K, P, delta_eq=delta_eq, start=start, live=live)
+                out = parallel.run(eng, [g], n_steps, K, P, delta_eq=delta_eq, start=start, live=live,
+                                   dynamic_k=dynamic_k)
                 _sync()
                 t_par = time.perf_counter() - t
                 eng.set_replica(ref, smp.types, seq_final, n_steps)
@@ -120,6 +125,7 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
                 d["max_disp"].append(md)
                 d["t_par"].append(t_par)
                 d["computed"].append(out["computed_steps"])
+                d["rounds"].append(out["rounds"])
                 if log:
                     log(f"sample {seed} P {P} K {K}: S {t_seq / t_par:.2f} (seq {t_seq:.3f} s, par {t_par:.3f} s), "
                         f"final equal {bool(eq)}")
@@ -130,10 +136,12 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
                       "min": float(s.min()), "max": float(s.max()),
                       "final_equal": int(sum(d["final_equal"])), "samples": int(s.size),
                       "computed_steps_mean": float(np.mean(d["computed"])),
+                      "rounds_mean": float(np.mean(d["rounds"])),
                       "t_par_mean_s": float(np.mean(d["t_par"]))})
     it = np.asarray(seq_iters, dtype=np.float64)
     return {"table": table, "samples": len(list(seeds)), "n_steps": n_steps, "dgamma": DGAMMA,
             "live_checks": bool(live), "minimizer": minimizer, "start": int(start),
+            "dynamic_k": list(dynamic_k) if dynamic_k else None,
             "t_seq_mean_s": float(np.mean(t_seq_all)),
             "fire_iters_per_step": {"mean": float(it.mean()), "median": float(np.median(it)),
                                     "p95": float(np.percentile(it, 95))}}
@@ -148,12 +156,14 @@ def main(argv=None) -> int:
     ap.add_argument("--live", type=int, default=1)
     ap.add_argument("--minimizer", choices=("fire", "cg"), default="fire")
     ap.add_argument("--start", choices=("plain", "extrapolated"), default="plain")
+    ap.add_argument("--dynamic-k", type=int, nargs=2, metavar=("KMIN", "KMAX"), default=None)
     args = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
     res = speedups(range(args.samples), args.P, args.K, n_steps=args.steps, live=bool(args.live),
                    log=lambda s: print(s, file=sys.stderr, flush=True), minimizer=args.minimizer,
-                   start=AQS_START_EXTRAPOLATED if args.start == "extrapolated" else AQS_START_PLAIN)
+                   start=AQS_START_EXTRAPOLATED if args.start == "extrapolated" else AQS_START_PLAIN,
+                   dynamic_k=tuple(args.dynamic_k) if args.dynamic_k else None)
     print(json.dumps(res), flush=True)
     return 0
 

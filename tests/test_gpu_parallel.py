@@ -6,13 +6,13 @@ import pytest
 
 import oracle as O
 from gpu_common import fire_pair, load_glass
-from oracle.alg1 import aqs_parallel
+from oracle.alg1 import adaptive_k, aqs_parallel
 
 pytestmark = pytest.mark.gpu
 POT = O.kob_andersen()
 
 
-def oracle_run(pos, types, L, dim, dg, K, P, n, ofire, delta_eq):
+def oracle_run(pos, types, L, dim, dg, K, P, n, ofire, delta_eq, k_bounds=None):
     def step(x, k):
         return O.fire(O.affine(x, dg), types, O.strain_box(dim, L, k, dg), POT, ofire).pos
 
@@ -37,7 +37,8 @@ def oracle_run(pos, types, L, dim, dg, K, P, n, ofire, delta_eq):
         margins.append(d)
         return d < delta_eq
 
-    return aqs_parallel((0, pos), n, K, P, level1, level2, equal), margins
+    rule = None if k_bounds is None else (lambda k, c: adaptive_k(k, c, *k_bounds))
+    return aqs_parallel((0, pos), n, K, P, level1, level2, equal, rule), margins
 
 
 @pytest.mark.parametrize("dg,K,P,n", [(4e-3, 5, 4, 20), (1e-3, 3, 3, 12)])
@@ -110,6 +111,31 @@ def test_live_rounds_match_the_oracle(dg, K, P, n):
     assert [r["q"] for r in g.rounds] == [r.q for r in ref.rounds]
     assert out["accepted_steps"] == n and out["statuses_ok"]
     H = O.strain_box(dim, L, n, dg)
+    assert O.compare(eng.positions(g.star), ref.r_star[1], H)[0] < 1e-8
+
+
+@pytest.mark.parametrize("live", [False, True])
+def test_dynamic_k_matches_the_oracle(live):
+    """K chosen anew after every round (halved, doubled and kept on this
+    glass, the last round clamped): the oracle's K sequence, decisions and
+    accepted steps per round, and its final r_star."""
+    from paper_2507_20802_amd import Engine, parallel
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, ofire = fire_pair()
+    dg, K, P, n, kb = 2e-3, 4, 3, 40, (2, 16)
+    ref, _ = oracle_run(pos, types, L, dim, dg, K, P, n, ofire, 1e-4, kb)
+    eng = Engine(dim, [len(types)] * parallel.slots_needed(1, P), L, dg, fire=fire)
+    g = parallel.layout(1, P)[0]
+    eng.set_replica(g.star, types, pos, 0)
+    out = parallel.run(eng, [g], n, K, P, delta_eq=1e-4, live=live, dynamic_k=kb)
+    print("K per round", [r["K"] for r in g.rounds], "checks", [r["checks"] for r in g.rounds])
+    assert [r["K"] for r in g.rounds] == [r.K for r in ref.rounds]
+    assert len({r.K for r in ref.rounds}) > 1
+    assert [r["checks"] for r in g.rounds] == [r.checks for r in ref.rounds]
+    assert [r["q"] for r in g.rounds] == [r.q for r in ref.rounds]
+    assert out["accepted_steps"] == n and out["statuses_ok"]
+    H = O.strain_box(dim, L, n, dg)
+    assert eng.strain_index(g.star) == n
     assert O.compare(eng.positions(g.star), ref.r_star[1], H)[0] < 1e-8
 
 

@@ -9,7 +9,7 @@ import pytest
 
 import aqs_synth as S
 import oracle as O
-from oracle.alg1 import aqs_parallel, aqs_sequential, chain_plan
+from oracle.alg1 import adaptive_k, aqs_parallel, aqs_sequential, chain_plan
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -111,6 +111,47 @@ def test_clamped_last_round():
     assert res.n_current == 200
 
 
+def test_adaptive_k_rule():
+    assert adaptive_k(4, [True, True], 1, 16) == 8
+    assert adaptive_k(12, [True], 1, 16) == 16
+    assert adaptive_k(5, [False], 1, 16) == 3
+    assert adaptive_k(2, [False], 2, 16) == 2
+    assert adaptive_k(1, [False], 1, 16) == 1
+    assert adaptive_k(6, [True, False], 1, 16) == 6
+    assert adaptive_k(6, [True, True, False], 1, 16) == 6
+    assert adaptive_k(6, [], 1, 16) == 6
+
+
+def test_dynamic_k_doubles_while_every_anchor_agrees():
+    """Best case: the rounds' chains grow 2, 4, 8, 16, 16, ...; every step is
+    accepted and none is computed twice."""
+    m = Mock()
+    res = aqs_parallel((0, 0), 200, 2, 4, m.level1, m.level2, m.equal, lambda k, c: adaptive_k(k, c, 1, 16))
+    assert [r.K for r in res.rounds][:5] == [2, 4, 8, 16, 16]
+    assert [r.q for r in res.rounds][:4] == [8, 16, 32, 64]
+    assert res.n_current == 200 and res.computed_steps == 200 and res.r_star == (200, 0)
+
+
+def test_dynamic_k_halves_while_the_first_anchor_mispredicts():
+    """Worst case: K = 8, 4, 2, 1, 1, ...; each round accepts its chain 0."""
+    n = 30
+    m = Mock({k: 1 for k in range(1, n + 64)})
+    res = aqs_parallel((0, 0), n, 8, 4, m.level1, m.level2, m.equal, lambda k, c: adaptive_k(k, c, 1, 16))
+    assert [r.K for r in res.rounds][:5] == [8, 4, 2, 1, 1]
+    assert all(r.q == r.lengths[0] for r in res.rounds)
+    assert res.n_current == n and res.r_star == (n, 0)
+
+
+def test_dynamic_k_keeps_k_after_a_later_failure():
+    """The anchor at strain 12 mispredicts once: round 0 (K = 4) passes its
+    first two checks and fails the third, so K stays 4."""
+    m = Mock({12: 1})
+    res = aqs_parallel((0, 0), 40, 4, 4, m.level1, m.level2, m.equal, lambda k, c: adaptive_k(k, c, 1, 16))
+    r0, r1 = res.rounds[:2]
+    assert r0.checks == [True, True, False] and r0.q == 12 and r1.K == 4
+    assert r1.start == 12 and res.n_current == 40
+
+
 def test_algorithm_needs_two_threads():
     m = Mock()
     with pytest.raises(ValueError):
@@ -153,3 +194,7 @@ def test_parallel_equals_sequential_on_a_glass():
     assert res.n_current == n and res.r_star[0] == n
     H = O.strain_box(2, s.L, n, dg)
     assert O.compare(res.r_star[1], seq[-1][1], H)[0] < 1e-6
+    # the same with K chosen anew after every round
+    dyn = aqs_parallel((0, r0), n, K, P, level1, level2, equal, lambda k, c: adaptive_k(k, c, 2, 8))
+    assert dyn.n_current == n and len({r.K for r in dyn.rounds}) > 1
+    assert O.compare(dyn.r_star[1], seq[-1][1], H)[0] < 1e-6

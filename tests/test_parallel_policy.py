@@ -1,8 +1,13 @@
-"""The CU reservation policy of live rounds (parallel.reservation_for), CPU
-only: unthrottled speculation after rounds whose checks mostly passed, a
-tighter reservation after rounds whose checks mostly failed, the default
-otherwise and without history."""
-from paper_2507_20802_amd.parallel import reservation_for
+"""Host policies of the Algorithm 1 driver, CPU only.  The CU reservation of
+live rounds (parallel.reservation_for): unthrottled speculation after rounds
+whose checks mostly passed, a tighter reservation after rounds whose checks
+mostly failed, the default otherwise and without history.  The dynamic
+choice of K (parallel.next_k): doubled after a round whose checks all
+passed, halved (rounded up) after a failed first check, kept otherwise,
+within its bounds."""
+import pytest
+
+from paper_2507_20802_amd.parallel import next_k, reservation_for
 
 
 def test_reservation_follows_the_last_rounds_checks():
@@ -13,3 +18,11 @@ def test_reservation_follows_the_last_rounds_checks():
     assert reservation_for([True, False, False, False]) == 0
     assert reservation_for([False]) == 2
     assert reservation_for([True] + [False] * 4) == 2
+
+
+@pytest.mark.parametrize("K,checks,bounds,want", [
+    (4, [True, True], (1, 16), 8), (12, [True], (1, 16), 16), (5, [False], (1, 16), 3),
+    (2, [False, True], (2, 16), 2), (1, [False], (1, 16), 1), (6, [True, False], (1, 16), 6),
+    (6, [True, True, False], (1, 16), 6), (6, [], (1, 16), 6), (3, [True, True], (1, 4), 4)])
+def test_next_k_follows_the_rounds_checks(K, checks, bounds, want):
+    assert next_k(K, checks, *bounds) == want
