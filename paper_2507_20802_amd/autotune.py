@@ -26,7 +26,7 @@ from .engine import Engine, Fire, Tuning
 
 KNOBS = {
     "threads_per_atom": (2, 1, 4),
-    "skin": (0.3, 0.25, 0.35),
+    "skin": (0.3, 0.25, 0.35, 0.2, 0.15),
     "block_iters": (32, 16, 64),
 }
 DEFAULT = {k: v[0] for k, v in KNOBS.items()}
