@@ -16,8 +16,8 @@
 Every glass is a seeded uniform random start quenched on the device (the
 paper's samples are not available; the paper's problem uses its cell,
 composition and potential); FIRE to max|F| < 1e-10.  Run as
-python -m paper_2507_20802_amd.configs [small batch2d uneven paper] (one JSON
-line each).  Times are wall-clock around the timed call, inputs resident on the
+python -m paper_2507_20802_amd.configs [small batch2d uneven paper]
+[--paper-samples S --paper-steps K] (one JSON line each).  Times are wall-clock around the timed call, inputs resident on the
 device.
 """
 from __future__ import annotations
@@ -163,10 +163,13 @@ def paper(samples: int = 256, steps: int = 200) -> dict:
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("configs", nargs="*", default=["small", "batch2d", "uneven", "paper"])
+    ap.add_argument("--paper-samples", type=int, default=256)
+    ap.add_argument("--paper-steps", type=int, default=200)
     args = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
-    runs = {"small": small, "batch2d": batch2d, "uneven": uneven, "paper": paper}
+    runs = {"small": small, "batch2d": batch2d, "uneven": uneven,
+            "paper": lambda: paper(args.paper_samples, args.paper_steps)}
     for name in args.configs:
         print(json.dumps(runs[name]()), flush=True)
     return 0
