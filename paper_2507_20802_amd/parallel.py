@@ -101,7 +101,7 @@ def next_k(K: int, checks: List[bool], k_min: int, k_max: int) -> int:
     [k_min, k_max].  A round without checks (one chain) keeps K."""
     if len(checks) == 0:
         return K
-    if checks[0] and all(checks):
+    if all(checks):
         k = K * 2
     elif checks[0]:
         k = K
