@@ -139,6 +139,30 @@ def test_dynamic_k_matches_the_oracle(live):
     assert O.compare(eng.positions(g.star), ref.r_star[1], H)[0] < 1e-8
 
 
+def test_dynamic_k_per_glass_in_one_batch():
+    """Two glasses (different shear increments) in one batch, each choosing
+    its own K after every round: each matches its own oracle run."""
+    from paper_2507_20802_amd import Engine, parallel
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, ofire = fire_pair()
+    K, P, n, kb = 4, 3, 24, (2, 16)
+    dgs = [2e-3, 4e-3]
+    per = parallel.slots_needed(1, P)
+    eng = Engine(dim, [len(types)] * (2 * per), L, [dgs[0]] * per + [dgs[1]] * per, fire=fire)
+    gl = parallel.layout(2, P)
+    for g in gl:
+        eng.set_replica(g.star, types, pos, 0)
+    out = parallel.run(eng, gl, n, K, P, delta_eq=1e-4, dynamic_k=kb)
+    assert out["statuses_ok"] and out["accepted_steps"] == 2 * n
+    for g, dg in zip(gl, dgs):
+        ref, _ = oracle_run(pos, types, L, dim, dg, K, P, n, ofire, 1e-4, kb)
+        print(f"dgamma {dg}: K per round", [r["K"] for r in g.rounds])
+        assert [r["K"] for r in g.rounds] == [r.K for r in ref.rounds]
+        assert [r["checks"] for r in g.rounds] == [r.checks for r in ref.rounds]
+        H = O.strain_box(dim, L, n, dg)
+        assert O.compare(eng.positions(g.star), ref.r_star[1], H)[0] < 1e-8
+
+
 def _round(eng, g, P, K, dg_steps, delta_eq, live):
     """Level I from the glass in g.star, then one round through aqs_run_round."""
     for i in range(P):
