@@ -183,7 +183,8 @@ aqs_status aqs_copy_replica(aqs_ctx* ctx, int32_t src, int32_t dst);
 /* Affine simple shear of the selected slots, Eqs. (2)-(3) with Eq. (16):
  * x_i += (dk_r * dgamma_r) y_i in one multiplication (level I uses
  * dk = i K, Eq. 18), and k_r += dk_r so the box follows (Eq. 1).  rep[n_sel],
- * dk[n_sel] are host arrays.  Stream-ordered. */
+ * dk[n_sel] are host arrays of distinct slots (AQS_EINVAL, nothing changed,
+ * if a slot is listed twice).  Stream-ordered. */
 aqs_status aqs_affine_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
                             const int64_t* dk);
 

@@ -1,33 +1,33 @@
-"""Algorithm 1 of the paper (Sec. 3.5, "Parallel calculation scheme") in plain
-Python -- TEST INFRASTRUCTURE ONLY.
+"""The parallel stepping scheme of the paper (Algorithm 1, Sec. 3.5) in plain
+Python -- TEST INFRASTRUCTURE ONLY (imported by the tests, never by the
+GPU library).
 
-The procedure aqs_parallel(r0, H, F_N, dgamma, dgamma_c, N_steps, K, P):
-
-    N_current <- 0;  r_star <- r0
-    while N_current < N_steps:
-        level I:  r^c_{iK} <- F_N^(i dgamma_c) r_star,  i = 0..P-1      (Eq. 18)
-        level II, every i in parallel:
-            outgoing_i <- F(r^c_{iK})                                   (Eq. 10)
-            end_i      <- (F o F_N^(dgamma))^K (outgoing_i)              (Eq. 19)
-        sequential check, i = 1..P-1:
-            if end_{i-1} ~= outgoing_i (Eq. 20):  q <- (i+1) K, continue
-            else:                                  q <- i K,     stop
-        r_star <- r_q;  N_current <- N_current + q
+What it computes.  A round starts from a verified inherent structure at
+strain step n.  Chain i of the round (i = 0 .. P-1) starts from that
+structure mapped affinely by i K fine increments in one product (the
+level-I guess, Eq. 18), is minimised (its "first" structure), and then takes
+its own K fine AQS steps (level II, Eq. 19).  The chains form links: chain
+i continues chain i-1 exactly when the end of chain i-1 and the first
+structure of chain i are the same inherent structure (Eq. 20).  The round
+keeps the longest run of chains 0, 1, ... whose links all hold -- chain 0
+always, since it starts from the verified structure -- so it accepts the
+steps of that prefix of chains, and the end of the prefix's last chain is
+the next round's verified structure.  Rounds repeat until the requested
+number of steps is accepted.
 
 Readings where the paper is silent:
-  * the last round is clamped: with R = N_steps - N_current < P K remaining
-    steps, only P' = ceil(R / K) chains run and the last one takes
-    K' = R - (P' - 1) K steps (N_steps need not be a multiple of K);
-  * with a single chain in a round (P' = 1) its K' steps are accepted
-    (chain 0 starts from the verified r_star, Sec. 3.7 worst case);
-  * r_q is the end of chain q/K - 1: the incoming configuration at the first
-    failed check, or the end of the last chain when every check passes.
+  * near the end, with R < P K steps left, a round runs only ceil(R / K)
+    chains and the last of them takes the remaining R - (ceil(R/K) - 1) K
+    steps, so the total need not be a multiple of K;
+  * a round with a single chain has no link to test and accepts its steps;
+  * links are tested in chain order and the first broken link ends the
+    prefix: later links are not needed.
 
 The dynamic choice of K that the paper's outlook proposes (Sec. 5) is an
-optional rule next_k(K, checks) -> K for the next round; adaptive_k is the
-one read here.  Every round's chains still start from the verified r_star
-and every accepted step is checked, so the accepted trajectory is the same
-for any K sequence; only the number of rounds and computed steps change.
+optional rule next_k(K, links) -> K for the next round; adaptive_k is the
+one read here.  Every round still starts from the verified structure and
+every accepted step belongs to a tested prefix, so the accepted trajectory
+does not depend on the K sequence; only rounds and computed steps do.
 
 The operators are passed in, so the same procedure serves mocked equality
 outcomes (index arithmetic tests) and real minimisations (oracle FIRE).
@@ -88,49 +88,52 @@ def aqs_parallel(r0: Any, n_steps: int, K: int, P: int,
                  level2: Callable[[List[Any], List[int]], List[tuple]],
                  equal: Callable[[Any, Any], bool],
                  next_k: Callable[[int, List[bool]], int] | None = None) -> Result:
-    """Algorithm 1 (with next_k: K chosen anew after every round).
+    """Rounds of the parallel scheme until n_steps are accepted (with
+    next_k: K chosen anew after every round).
 
-    level1(r_star, m)       -> anchor F_N^(m dgamma) r_star (m = i K fine steps)
-    level2(anchors, lengths)-> for each anchor i, (outgoing_i, end_i): the
-                               minimised anchor and the end of its chain of
-                               lengths[i] fine AQS steps (run "in parallel")
+    level1(r, m)            -> the affine guess F_N^(m dgamma) r (m fine steps
+                               in one product)
+    level2(starts, lengths) -> per chain, (first, end): the minimised start
+                               and the end of its chain of lengths[i] fine
+                               AQS steps (the chains are independent)
     equal(a, b)             -> the equality test of Eq. (20)
     """
     if P < 2:
-        raise ValueError("Algorithm 1 needs P >= 2 threads (Sec. 3.2)")
+        raise ValueError("the parallel scheme needs P >= 2 chains (Sec. 3.2)")
     if K < 1:
         raise ValueError("K must be >= 1")
-    n_cur = 0
-    r_star = r0
-    res = Result(r_star, 0)
-    while n_cur < n_steps:
-        lengths = chain_plan(n_steps - n_cur, K, P)
-        anchors = [level1(r_star, i * K) for i in range(len(lengths))]
-        out = level2(anchors, lengths)
+    verified, done = r0, 0
+    res = Result(r0, 0)
+    while done < n_steps:
+        lengths = chain_plan(n_steps - done, K, P)
+        guesses = [level1(verified, i * K) for i in range(len(lengths))]
+        chains = level2(guesses, lengths)
         res.computed_steps += sum(lengths)
-        q = lengths[0]
-        r_q = out[0][1]
-        checks = []
-        for i in range(1, len(lengths)):
-            ok = bool(equal(out[i - 1][1], out[i][0]))
-            checks.append(ok)
-            if ok:
-                q = i * K + lengths[i]
-                r_q = out[i][1]
-            else:
-                q = i * K
-                r_q = out[i - 1][1]
-                break
-        res.rounds.append(Round(n_cur, len(lengths), lengths, checks, q, K))
-        r_star = r_q
-        n_cur += q
+        links = accepted_links(chains, equal)
+        kept = len(links) + 1 if all(links) else len(links)
+        accepted = sum(lengths[:kept])
+        res.rounds.append(Round(done, len(lengths), lengths, links, accepted, K))
+        verified = chains[kept - 1][1]
+        done += accepted
         if next_k is not None:
-            K = next_k(K, checks)
+            K = next_k(K, links)
             if K < 1:
                 raise ValueError("K must be >= 1")
-    res.r_star = r_star
-    res.n_current = n_cur
+    res.r_star = verified
+    res.n_current = done
     return res
+
+
+def accepted_links(chains: List[tuple], equal: Callable[[Any, Any], bool]) -> List[bool]:
+    """Outcomes of the links between consecutive chains, in chain order, up
+    to and including the first broken one: link i holds when the end of
+    chain i-1 equals the first structure of chain i."""
+    links = []
+    for prev, cur in zip(chains, chains[1:]):
+        links.append(bool(equal(prev[1], cur[0])))
+        if not links[-1]:
+            break
+    return links
 
 
 def aqs_sequential(r0: Any, n_steps: int, step: Callable[[Any, int], Any]) -> list:

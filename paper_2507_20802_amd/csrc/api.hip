@@ -1241,9 +1241,14 @@ aqs_status aqs_affine_shear(aqs_ctx* c, int32_t n_sel, const int32_t* rep, const
   if (n_sel <= 0) return AQS_OK;
   if (!rep || !dk) return fail(AQS_EINVAL, "null selection");
   std::vector<int32_t> sel(rep, rep + n_sel);
+  // a slot listed twice would get two blocks per atom block in the launch
+  // table, racing on x += dg y, while its strain index took both dk
+  std::vector<char> seen(c->n_rep, 0);
   for (int r : sel) {
     aqs_status st = check_slot(c, r);
     if (st) return st;
+    if (seen[r]) return fail(AQS_EINVAL, "slot %d selected twice", r);
+    seen[r] = 1;
   }
   aqs_status st = pull_state(c);
   if (st) return st;

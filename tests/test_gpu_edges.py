@@ -113,6 +113,12 @@ def test_host_checks_reject_bad_calls_and_the_context_keeps_working():
     assert code(eng.set_replica, 1, bad, pos, 0) == AQS_EINVAL
     eng.set_replica(1, types, pos, 0)
     assert code(eng.minimize, [0, 1], snap_dst=[1, -1]) == AQS_EINVAL   # snapshot slot also minimised
+    # a slot listed twice in one affine shear is refused and nothing moves
+    before = [eng.positions(r) for r in (0, 1)]
+    assert code(eng.affine_shear, [1, 1], [1, 1]) == AQS_EINVAL
+    assert code(eng.affine_shear, [0, 1, 0], [2, 1, 3]) == AQS_EINVAL
+    assert eng.strain_index(0) == 0 and eng.strain_index(1) == 0
+    assert all(np.array_equal(eng.positions(r), b) for r, b in zip((0, 1), before))
     eng.affine_shear([1], [2])
     assert code(eng.compare, 0, 1) == AQS_EINVAL                       # different strain indices
     assert code(eng.copy_replica, 0, 5) == AQS_EINVAL
