@@ -3,18 +3,24 @@
 
 Workload (default): a 3D binary Lennard-Jones glass, N = 32768 atoms
 (Kob-Andersen-type parameters, 80:20, density 1.2, cutoff 2.5 sigma_ab),
-quenched on the GPU from seeded uniform random positions.  One "step" is
-one round of Algorithm 1 (Sec. 3.5) with P = 16 level-II chains of K = 200
-fine AQS steps at dgamma = 5e-5 (level-I anchors at i * 1e-2), every
-minimisation run by FIRE to max|F| < 1e-10, all chains batched on the GPU.
+quenched on the GPU from seeded uniform random positions; its first plain
+AQS steps train the learned start.  One "step" is one round of Algorithm 1
+(Sec. 3.5) with P = 16 level-II chains of K = 200 fine AQS steps at
+dgamma = 5e-5 (level-I anchors at i * 1e-2), every minimisation run by FIRE
+to max|F| < 1e-10, the learned start with live checks (the headline form).
 Each step starts from the same inherent structure (already in HBM); the
 accepted steps of a round are q of Algorithm 1 (at least K), the computed
 ones P * K plus the anchor minimisations.
 
+Beside the timed steps: a few rounds of the plain start (learned vs plain),
+conventional sequential AQS of the same K steps from the same structure (the
+C^(S) of Eq. 21, for the speed-up S), and on request the extrapolated start,
+conjugate gradients and the batched round without live checks.
+
 Prints one JSON line: accepted AQS steps/s (value), FIRE iterations per AQS
 step, the roofline of the dominant kernel (the FP64 force kernel, timed with
-HIP events on its stream inside the timed region) and the CPU oracle timed
-on a bounded sample on the host cores.
+HIP events on the stream of each launch inside the timed steps) and the CPU
+oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
 
@@ -34,13 +40,13 @@ METRIC = "AQS steps/s & FIRE iters/step at N=32k, learned-start vs plain, max|F|
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 HBM_PEAK_GBS = 8000.0
 # algorithmic FP64 work of one in-cutoff pair, counted once (Newton's third
-# law): the separation and r^2, the reciprocal, the LJ powers, U'(r)/r, the
-# shifted energy and the force components
-FLOPS_PER_PAIR = 29
+# law): the separation (3), r^2 (5), the reciprocal (about 8), the LJ powers
+# and U'(r)/r (8), the shifted energy (3), the force components on both atoms
+# (6): 33 flops
+FLOPS_PER_PAIR = 33
 # algorithmic bytes per atom of the force kernel: positions (d doubles) and
-# the type (one byte) in, velocities in for F.v and forces out (d doubles
-# each): 24 d + 1
-FORCE_BYTES_PER_ATOM = {2: 49, 3: 73}
+# the type (one byte) in, forces out (d doubles): 16 d + 1
+FORCE_BYTES_PER_ATOM = {2: 33, 3: 49}
 
 
 TRAFFIC_SOURCES = ("md_kernels.hip", "cells.hip", "tiles.h", "engine.h")
@@ -90,31 +96,43 @@ def in_cutoff_neighbours(pos, types, L, pot) -> float:
     return 2.0 * inside.sum() / n
 
 
-def cpu_baseline(dim, n, dg, iters_per_step, seconds=20.0):
-    """Time the CPU oracle (sequential AQS, O(N^2) pair sums, all host
-    threads) on a bounded sample: a few force evaluations of the same
-    workload size; AQS steps/s = 1 / (t_eval * (iterations per step + 1))."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pos, types, L, dg, iters_per_step, seconds=15.0):
+    """Time the CPU oracle (sequential AQS: O(N^2) pair sums over all host
+    threads) on a bounded sample of the same workload: force evaluations of
+    the benchmark's own inherent structure after one affine increment, until
+    `seconds`/2 have passed (at least one); AQS steps/s = 1 / (t_eval x
+    (iterations per step + 1)), with the GPU-measured iterations."""
     import oracle as O
-    import aqs_synth as S
-    s = S.jittered_lattice_start(dim, round(n ** (1 / dim)), 3, 9) if round(n ** (1 / dim)) ** dim == n \
-        else S.uniform_glass_start(dim, n, 3, 9)
-    H = O.strain_box(dim, s.L, 1, dg)
-    x = O.affine(s.pos, dg)
+    dim = pos.shape[1]
+    H = O.strain_box(dim, L, 1, dg)
+    x = O.affine(pos, dg)
     pot = O.kob_andersen()
-    O.energy_forces(x[:64], s.types[:64], O.box_matrix(dim, 50.0, 0.0), pot)  # load
+    O.energy_forces(x[:64], types[:64], O.box_matrix(dim, 50.0, 0.0), pot)  # load the library
     t0 = time.perf_counter()
     evals = 0
     while True:
-        O.energy_forces(x, s.types, H, pot)
+        O.energy_forces(x, types, H, pot)
         evals += 1
         if time.perf_counter() - t0 > seconds / 2 or evals >= 50:
             break
     t_eval = (time.perf_counter() - t0) / evals
     rate = 1.0 / (t_eval * (iters_per_step + 1.0))
     return {"value": rate, "unit": "AQS steps/s", "cores": O.get_threads(), "kind": "oracle",
-            "sample": f"{evals} O(N^2) force evaluations of the N={n} {dim}D workload "
-                      f"({t_eval:.3f} s each) x (GPU-measured {iters_per_step:.1f} FIRE iterations + 1) "
-                      f"per sequential AQS step",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"{evals} O(N^2) force evaluations of the benchmark's N={len(types)} {dim}D inherent "
+                      f"structure after one increment ({t_eval:.3f} s each) x (GPU-measured "
+                      f"{iters_per_step:.1f} FIRE iterations + 1) per sequential AQS step",
             "t_eval_s": t_eval}
 
 
@@ -137,20 +155,17 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
-def train_network(eng, dim, n, dg, slot_a, slot_b, steps, epochs, seed):
-    """Learned start: descriptors and non-affine targets from `steps` plain
-    AQS steps of a separately seeded glass, then the network trained on the
-    GPU (Adam, Huber loss, batch 4096).  Returns the model and a summary."""
+def train_on_history(eng, star, spare, steps, epochs, seed, dim):
+    """Learned start trained online on the benchmark glass's own history:
+    `steps` plain AQS steps of the inherent structure in `star` (left at the
+    last one) give the descriptors and non-affine targets, then the network
+    is trained on the GPU (Adam, Huber loss, batch 4096).  Returns the model
+    and a summary."""
     import torch
     import aqs_synth as S
     from paper_2507_20802_amd import learned
-    s = S.uniform_glass_start(dim, n, 3, seed)
-    eng.set_replica(slot_a, s.types, s.pos, 0)
     t0 = time.perf_counter()
-    q = eng.minimize([slot_a])[0, 0]
-    if q["status"] != 0:
-        raise RuntimeError("quench of the training glass failed")
-    feat, tgt, recs = learned.collect_samples(eng, slot_a, slot_b, steps)
+    feat, tgt, recs = learned.collect_samples(eng, star, spare, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     orders = torch.from_numpy(S.epoch_orders(feat.shape[0], epochs, 3, seed, 7)).cuda()
@@ -159,39 +174,48 @@ def train_network(eng, dim, n, dg, slot_a, slot_b, steps, epochs, seed):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return model, {"samples": int(feat.shape[0]), "plain_steps": steps, "epochs": epochs,
+                   "history_iters": [int(r["iters"]) for r in recs],
                    "data_s": t1 - t0, "train_s": t2 - t1, "loss_first": float(hist[0]),
                    "loss_last": float(hist[-1])}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3,
+                    help="timed steps: rounds of Algorithm 1 of the headline form")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed rounds (of --warmup-K steps) first")
     ap.add_argument("--dim", type=int, default=3)
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--P", type=int, default=16)
     ap.add_argument("--K", type=int, default=200)
     ap.add_argument("--dgamma", type=float, default=5e-5)
     ap.add_argument("--warmup-K", type=int, default=20, help="fine steps per chain in warmup rounds")
-    ap.add_argument("--profile-every", type=int, default=4)
-    ap.add_argument("--train-steps", type=int, default=7, help="plain AQS steps of training data")
+    ap.add_argument("--profile-every", type=int, default=4,
+                    help="time every n-th block of iterations with HIP events (force-kernel roofline)")
+    ap.add_argument("--train-steps", type=int, default=7,
+                    help="plain AQS steps of the glass's own history that train the network")
     ap.add_argument("--epochs", type=int, default=50)
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain-start reference rounds")
-    ap.add_argument("--only-plain", action="store_true", help="time the plain start only (no network)")
-    ap.add_argument("--skin", type=float, default=0.3, help="Verlet skin (sigma_AA)")
+    ap.add_argument("--plain-rounds", type=int, default=2,
+                    help="rounds of the plain-start form timed beside the headline (0: none)")
+    ap.add_argument("--sequential", type=int, default=1,
+                    help="time conventional sequential AQS of the same K steps (1/0), Eq. 21's C^(S)")
+    ap.add_argument("--forms", default="",
+                    help="extra forms, comma-separated: extrapolated, cg, batched (one round each)")
+    ap.add_argument("--only-plain", action="store_true", help="headline with the plain start (no network)")
     ap.add_argument("--graph", type=int, default=0, help="replay iteration blocks as hipGraphs (1/0)")
     ap.add_argument("--live", type=int, default=1,
                     help="live checks (1/0): checks as soon as possible, the critical chain on a stream of "
-                         "its own, rejected chains stopped; the learned form is also timed without them")
+                         "its own, rejected chains stopped")
     ap.add_argument("--tuning", choices=("default", "auto", "autotune"), default="auto",
                     help="launch knobs: the defaults, the autotuner's cache, or tune when not cached")
-    ap.add_argument("--extrap", type=int, default=1,
-                    help="also time the extrapolated start (previous step's non-affine displacement) (1/0)")
-    ap.add_argument("--cg", type=int, default=1,
-                    help="also time the plain start with the conjugate-gradient minimiser (1/0)")
+    ap.add_argument("--skin", type=float, default=0.3, help="Verlet skin with --tuning default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only stream MIB MiB device-to-device (counter calibration) and exit")
     args = ap.parse_args()
@@ -202,12 +226,18 @@ def main() -> int:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
               f"(the multi-GPU sharding is design only).", file=sys.stderr)
         return 2
+    extra = [f for f in args.forms.split(",") if f]
+    for f in extra:
+        if f not in ("extrapolated", "cg", "batched"):
+            print(f"unknown form {f}", file=sys.stderr)
+            return 2
 
     import torch
     import aqs_synth as S
     from paper_2507_20802_amd import (AQS_START_EXTRAPOLATED, AQS_START_LEARNED, AQS_START_PLAIN, Cg, Engine,
                                       Fire, LJParams, Tuning, parallel)
 
+    t_job = time.perf_counter()
     torch.cuda.set_device(0)
     dim, n, P, K, dg = args.dim, args.n, args.P, args.K, args.dgamma
     pot = LJParams()
@@ -224,16 +254,21 @@ def main() -> int:
     if q["status"] != 0:
         print(f"quench failed: status {q['status']}", file=sys.stderr)
         return 1
-    is_pos = eng.positions(glass.star)
-    nb = in_cutoff_neighbours(is_pos, s.types, s.L, pot)
-    train_info = None
+    log(f"quenched N={n} {dim}D glass in {quench_s:.1f} s ({int(q['iters'])} iterations)")
+    train_info, k0 = None, 0
     if not args.only_plain:
-        model, train_info = train_network(eng, dim, n, dg, glass.chains[0], glass.chains[1],
-                                          args.train_steps, args.epochs, 1)
+        # the glass's own first plain steps train the network; the timed rounds start after them
+        model, train_info = train_on_history(eng, glass.star, glass.chains[0], args.train_steps,
+                                             args.epochs, 0, dim)
         eng.learned_load(model)
+        k0 = eng.strain_index(glass.star)
+        log(f"trained on {args.train_steps} plain steps of the glass ({train_info['samples']} samples): "
+            f"loss {train_info['loss_first']:.3f} -> {train_info['loss_last']:.3f}")
+    is_pos = eng.positions(glass.star)
+    nb = in_cutoff_neighbours(is_pos, s.types, s.L, pot)   # the box is still orthogonal to 1e-3
 
     def one_round(Kr, start, live):
-        eng.set_replica(glass.star, s.types, is_pos, 0)
+        eng.set_replica(glass.star, s.types, is_pos, k0)
         g = parallel.layout(1, P)[0]
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -241,155 +276,153 @@ def main() -> int:
         torch.cuda.synchronize()
         return time.perf_counter() - t, out, g
 
-    live = bool(args.live)
-    forms = ([] if args.no_plain else [("plain", AQS_START_PLAIN, live, "fire")]) + \
-        ([] if args.only_plain else [("learned", AQS_START_LEARNED, live, "fire")])
-    # the extrapolated start and the paper's own minimiser on the same round
-    if args.extrap and not args.no_plain:
-        forms.append(("extrapolated", AQS_START_EXTRAPOLATED, live, "fire"))
-    if args.cg and not args.no_plain:
-        forms.append(("cg", AQS_START_PLAIN, live, "cg"))
-    # the batched round without live checks, timed last: the force-kernel
-    # roofline is taken there (one stream, every chain in each launch)
-    main_form = "plain" if args.only_plain else "learned"
-    roof_form = main_form + "_batched" if live else main_form
-    if live:
-        forms.append((roof_form, AQS_START_PLAIN if args.only_plain else AQS_START_LEARNED, False, "fire"))
-    for _ in range(args.warmup):
-        for _, st, lv, mz in forms:
-            eng.set_minimizer(mz, Cg() if mz == "cg" else None)
-            one_round(args.warmup_K, st, lv)
-    res_forms = {}
-    for name, st, lv, mz in forms:
+    def timed_form(name, start, live, mz, rounds):
         eng.set_minimizer(mz, Cg() if mz == "cg" else None)
         eng.counters(reset=True)
         eng.set_profiling(args.profile_every)
-        tot_t, acc, comp, iters, ok, rounds, starts = 0.0, 0, 0, [], True, [], []
-        for _ in range(args.steps):
-            dt, out, g = one_round(K, st, lv)
+        tot_t, acc, comp, iters, ok, rr, starts = 0.0, 0, 0, [], True, [], []
+        for _ in range(rounds):
+            dt, out, g = one_round(K, start, live)
             tot_t += dt
             acc += out["accepted_steps"]
             comp += out["computed_steps"]
             iters.extend(g.step_iters)
             starts.extend(g.step_starts)
             ok = ok and out["statuses_ok"]
-            rounds.append({"wall_s": dt, "accepted": out["accepted_steps"], "computed": out["computed_steps"],
-                           "rounds_of_alg1": out["rounds"], "decisions": [d.equal for d in g.decisions],
-                           "anchor_iters": g.anchor_iters})
+            rr.append({"wall_s": dt, "accepted": out["accepted_steps"], "computed": out["computed_steps"],
+                       "decisions": [d.equal for d in g.decisions], "anchor_iters": g.anchor_iters})
+            log(f"{name} round {len(rr)}/{rounds}: {dt:.2f} s, {out['accepted_steps']} accepted")
         eng.set_profiling(0)
-        star_vs_plain = None
-        if name == "plain":
-            eng.copy_replica(glass.star, ref_slot)
-        elif "plain" in res_forms:
-            eq, md, de = eng.compare(glass.star, ref_slot, 1e-4)   # r_star after the last round (Eq. 20)
-            star_vs_plain = {"equal": bool(eq), "max_disp": md, "de_per_atom": de}
+        eng.set_minimizer("fire")
         it = np.asarray(iters, dtype=np.float64)
-        res_forms[name] = {"value": acc / tot_t, "ms_per_step": 1e3 * tot_t / args.steps,
-                           "computed_steps_per_s": comp / tot_t,
-                           "fire_iters_per_step": {"mean": float(it.mean()), "median": float(np.median(it)),
-                                                   "p95": float(np.percentile(it, 95))},
-                           "all_converged": bool(ok), "rounds": rounds, "counters": eng.counters(),
-                           "starts": {"plain": starts.count(0), "learned": starts.count(1),
-                                      "fallback": starts.count(2), "extrapolated": starts.count(3)},
-                           "live_checks": bool(lv), "minimizer": mz, "final_star_vs_plain": star_vs_plain}
-    eng.set_minimizer("fire")
-    cg_form = res_forms.pop("cg", None)
-    ex_form = res_forms.pop("extrapolated", None)
-    lr = res_forms[main_form]
-    cnt = res_forms[roof_form]["counters"]
-    # inherent-structure agreement of the two forms: same decisions, same final r_star (Eq. 20)
-    comparison = None
-    if "plain" in res_forms and "learned" in res_forms:
-        pl = res_forms["plain"]
-        same_dec = [r["decisions"] for r in lr["rounds"]] == [r["decisions"] for r in pl["rounds"]]
-        fs = lr["final_star_vs_plain"]
-        eq = all(f["final_star_vs_plain"]["equal"] for k, f in res_forms.items() if k != "plain")
-        same_all = all([r["decisions"] for r in f["rounds"]] == [r["decisions"] for r in pl["rounds"]]
-                       for f in res_forms.values())
-        comparison = {"same_decisions": bool(same_dec), "final_star_equal": bool(fs["equal"]),
-                      "final_star_max_disp": fs["max_disp"], "final_star_de_per_atom": fs["de_per_atom"],
-                      "every_form_same_decisions_and_final_star": bool(eq and same_all),
-                      "is_mismatches": int((not fs["equal"]) + (not same_dec)),
-                      "iters_ratio_learned_over_plain": lr["fire_iters_per_step"]["mean"]
-                      / pl["fire_iters_per_step"]["mean"],
-                      "wall_ratio_learned_over_plain": lr["ms_per_step"] / pl["ms_per_step"]}
-    # roofline of the force kernel in the batched round (one stream)
+        res = {"value": acc / tot_t, "ms_per_step": 1e3 * tot_t / rounds, "rounds": rounds,
+               "computed_steps_per_s": comp / tot_t,
+               "fire_iters_per_step": {"mean": float(it.mean()), "median": float(np.median(it)),
+                                       "p95": float(np.percentile(it, 95))},
+               "all_converged": bool(ok), "per_round": rr, "counters": eng.counters(),
+               "starts": {"plain": starts.count(0), "learned": starts.count(1),
+                          "fallback": starts.count(2), "extrapolated": starts.count(3)},
+               "live_checks": bool(live), "minimizer": mz}
+        log(f"{name}: {res['value']:.2f} accepted AQS steps/s, {res['ms_per_step']:.0f} ms per round, "
+            f"{res['fire_iters_per_step']['mean']:.0f} iterations per step")
+        return res
+
+    live = bool(args.live)
+    head_start = AQS_START_PLAIN if args.only_plain else AQS_START_LEARNED
+    # warmup: short rounds of the headline form
+    for w in range(args.warmup):
+        dt, _, _ = one_round(args.warmup_K, head_start, live)
+        log(f"warmup round {w + 1}/{args.warmup} (K={args.warmup_K}): {dt:.2f} s")
+    head = timed_form("headline", head_start, live, "fire", args.steps)
+    eng.copy_replica(glass.star, ref_slot)                       # r_star after the headline round
+
+    def star_vs_headline():
+        """The configuration in the star slot against the headline's r_star
+        (Eq. 20), when both are at the same strain index."""
+        if eng.strain_index(glass.star) != eng.strain_index(ref_slot):
+            return {"equal": None, "strain_indices": [eng.strain_index(glass.star), eng.strain_index(ref_slot)]}
+        eq, md, de = eng.compare(glass.star, ref_slot, 1e-4)
+        return {"equal": bool(eq), "max_disp": md, "de_per_atom": de}
+    forms = {}
+    if args.plain_rounds > 0 and not args.only_plain:
+        forms["plain"] = timed_form("plain", AQS_START_PLAIN, live, "fire", args.plain_rounds)
+        forms["plain"]["final_star_vs_headline"] = star_vs_headline()
+    for f in extra:
+        st = {"extrapolated": AQS_START_EXTRAPOLATED, "cg": AQS_START_PLAIN, "batched": head_start}[f]
+        forms[f] = timed_form(f, st, live and f != "batched", "cg" if f == "cg" else "fire", 1)
+        forms[f]["final_star_vs_headline"] = star_vs_headline()
+    seq = None
+    if args.sequential:
+        # conventional AQS (Eq. 12) of the same K steps from the same inherent
+        # structure: one replica alone on the GPU, plain start (C^(S) of Eq. 21)
+        eng.set_replica(glass.star, s.types, is_pos, k0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rec = eng.minimize([glass.star], n_steps=[K])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        it = rec["iters"][0, 1:].astype(np.float64)
+        seq = {"steps": K, "wall_s": dt, "value": K / dt,
+               "fire_iters_per_step": {"mean": float(it.mean()), "median": float(np.median(it))},
+               "all_converged": bool((rec["status"][0] == 0).all()),
+               "end_vs_headline_r_star": star_vs_headline()}
+        log(f"sequential: {seq['value']:.2f} AQS steps/s")
+
+    # roofline of the force kernel over the headline's timed launches (HIP
+    # events on the stream of each launch; both driver lanes with live checks)
+    cnt = head["counters"]
     flops_per_atom = 0.5 * nb * FLOPS_PER_PAIR
-    avg_ms = cnt["force_ms"] / max(cnt["force_timed"], 1)
-    evals = cnt.get("atom_evals", 0)
-    atom_evals_per_launch = evals / cnt["force_launches"] if evals and cnt["force_launches"] else P * n
-    # no HIP-event samples (--profile-every 0): no achieved rate
-    achieved_tflops = flops_per_atom * atom_evals_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else None
-    achieved_gbs = FORCE_BYTES_PER_ATOM[dim] * atom_evals_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
+    n_timed = cnt["force_timed"]
+    avg_ms = cnt["force_ms"] / n_timed if n_timed else 0.0
+    atoms_per_launch = cnt["timed_atom_evals"] / n_timed if n_timed else 0.0
+    achieved_tflops = flops_per_atom * atoms_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else None
+    achieved_gbs = FORCE_BYTES_PER_ATOM[dim] * atoms_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
+    traffic = force_traffic(dim, atoms_per_launch)
+    comparison = None
+    if "plain" in forms:
+        pl = forms["plain"]
+        same_dec = [r["decisions"] for r in head["per_round"][:pl["rounds"]]] == \
+            [r["decisions"] for r in pl["per_round"]]
+        fs = pl["final_star_vs_headline"]
+        comparison = {"same_decisions": bool(same_dec), "final_star_equal": fs["equal"],
+                      "final_star_max_disp": fs.get("max_disp"), "final_star_de_per_atom": fs.get("de_per_atom"),
+                      "is_mismatches": int((fs["equal"] is not True) + (not same_dec)),
+                      "iters_ratio_headline_over_plain": head["fire_iters_per_step"]["mean"]
+                      / pl["fire_iters_per_step"]["mean"],
+                      "wall_ratio_headline_over_plain": head["ms_per_step"] / pl["ms_per_step"]}
     res = {
         "metric": METRIC,
-        "value": lr["value"],
+        "value": head["value"],
         "unit": "accepted AQS steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": lr["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{dim}D binary LJ glass N={n}, Algorithm 1 round: P={P} chains x K={K} "
-                               f"fine AQS steps, dgamma={dg:g}, dgamma_c={K * dg:g}, FIRE to max|F|<1e-10, "
+        "config": {"workload": f"{dim}D binary LJ glass N={n}, one round of Algorithm 1 per step: P={P} chains x "
+                               f"K={K} fine AQS steps, dgamma={dg:g}, dgamma_c={K * dg:g}, FIRE to max|F|<1e-10, "
                                + ("plain start" if args.only_plain else
-                                  "learned start (plain start timed alongside)")
-                               + (", live checks" if live else ""),
+                                  f"learned start trained on the glass's first {args.train_steps} plain steps")
+                               + (", live checks" if live else ", batched checks"),
                    "dim": dim, "n_atoms": n, "P": P, "K": K, "dgamma": dg, "live_checks": live,
+                   "start_strain_index": k0,
                    "knobs": {"threads_per_atom": eng.tuning.threads_per_atom, "skin": eng.tuning.skin,
                              "block_iters": eng.tuning.block_iters, "use_graph": eng.tuning.use_graph,
                              "source": args.tuning}},
-        "computed_steps_per_s": lr["computed_steps_per_s"],
-        "fire_iters_per_step": lr["fire_iters_per_step"],
-        "all_converged": lr["all_converged"],
-        "learned_start": {"starts": lr["starts"], "training": train_info},
-        "plain": None if args.only_plain else
-        {k: v for k, v in res_forms.get("plain", {}).items() if k != "counters"},
-        "batched": None if not live else
-        {k: v for k, v in res_forms[roof_form].items() if k != "counters"},
+        "computed_steps_per_s": head["computed_steps_per_s"],
+        "fire_iters_per_step": head["fire_iters_per_step"],
+        "all_converged": head["all_converged"],
+        "starts": head["starts"],
+        "learned_start": {"training": train_info},
+        "per_round": head["per_round"],
+        "plain": None if "plain" not in forms else
+        {k: v for k, v in forms["plain"].items() if k not in ("counters",)},
         "learned_vs_plain": comparison,
-        "extrapolated": None if ex_form is None else
-        {"value": ex_form["value"], "ms_per_step": ex_form["ms_per_step"],
-         "computed_steps_per_s": ex_form["computed_steps_per_s"],
-         "fire_iters_per_step": ex_form["fire_iters_per_step"], "starts": ex_form["starts"],
-         "all_converged": ex_form["all_converged"], "final_star_vs_plain": ex_form["final_star_vs_plain"],
-         "same_decisions_as_plain": [r["decisions"] for r in ex_form["rounds"]]
-         == [r["decisions"] for r in res_forms["plain"]["rounds"]],
-         "iters_ratio_over_plain": ex_form["fire_iters_per_step"]["mean"]
-         / res_forms["plain"]["fire_iters_per_step"]["mean"],
-         "wall_ratio_over_plain": ex_form["ms_per_step"] / res_forms["plain"]["ms_per_step"],
-         "rounds": ex_form["rounds"]},
-        "cg": None if cg_form is None else
-        {"value": cg_form["value"], "ms_per_step": cg_form["ms_per_step"],
-         "computed_steps_per_s": cg_form["computed_steps_per_s"],
-         "iters_per_step": cg_form["fire_iters_per_step"], "all_converged": cg_form["all_converged"],
-         "final_star_vs_plain_fire": cg_form["final_star_vs_plain"],
-         "same_decisions_as_plain_fire": [r["decisions"] for r in cg_form["rounds"]]
-         == [r["decisions"] for r in res_forms["plain"]["rounds"]],
-         "iters_ratio_cg_over_fire": cg_form["fire_iters_per_step"]["mean"]
-         / res_forms["plain"]["fire_iters_per_step"]["mean"],
-         "wall_ratio_cg_over_fire": cg_form["ms_per_step"] / res_forms["plain"]["ms_per_step"],
-         "params": vars(Cg()),
-         "rounds": cg_form["rounds"]},
+        "sequential": seq,
+        "speedup_vs_sequential": None if seq is None else head["value"] / seq["value"],
+        "extra_forms": {f: {k: v for k, v in forms[f].items() if k != "counters"} for f in extra},
         "quench_s": quench_s,
         "mean_neighbours_in_cutoff": nb,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / FP64_PEAK_TFLOPS if achieved_tflops else None,
-                     "traffic": force_traffic(dim, atom_evals_per_launch),
-                     "kernel": f"k_force<{dim}>", "avg_launch_ms": avg_ms,
-                     "atoms_per_launch": atom_evals_per_launch,
+                     "traffic": traffic,
+                     "kernel": f"k_force<{dim}>", "avg_launch_ms": avg_ms, "timed_launches": n_timed,
+                     "atoms_per_launch": atoms_per_launch,
                      "algorithmic_flops_per_atom": flops_per_atom,
+                     "algorithmic_bytes_per_atom": FORCE_BYTES_PER_ATOM[dim],
                      "hbm_gbs_algorithmic": achieved_gbs,
-                     "hbm_frac": achieved_gbs / HBM_PEAK_GBS if achieved_gbs else None},
+                     "hbm_frac_algorithmic": achieved_gbs / HBM_PEAK_GBS if achieved_gbs else None,
+                     "traffic_bytes_per_atom": traffic / atoms_per_launch if traffic and atoms_per_launch else None},
         "counters": cnt,
-        "rounds": lr["rounds"],
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(dim, n, dg, float(lr["fire_iters_per_step"]["mean"]), args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(is_pos, s.types, s.L, dg, float(head["fire_iters_per_step"]["mean"]),
+                                           args.cpu_seconds)
+    res["job_wall_s"] = time.perf_counter() - t_job
     print(json.dumps(res), flush=True)
     return 0
 

@@ -326,9 +326,11 @@ typedef struct {
   int64_t rebuilds;         /* neighbour-list rebuild passes */
   int64_t host_polls;       /* state read-backs of the minimisation loop */
   int64_t atom_evals;       /* atoms whose force was evaluated, summed over launches */
+  int64_t timed_atom_evals; /* ... over the force launches timed (force_timed) */
 } aqs_counters;
 
-/* Time every n-th block of FIRE iterations (0 = no timing). */
+/* Time every n-th block of FIRE iterations (0 = no timing), on every
+ * driver lane's stream (aqs_run_round with live = 1 has two). */
 aqs_status aqs_set_profiling(aqs_ctx* ctx, int32_t every_nth_block);
 
 aqs_status aqs_get_counters(aqs_ctx* ctx, aqs_counters* out, int32_t reset);

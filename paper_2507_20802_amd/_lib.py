@@ -63,7 +63,8 @@ class aqs_counters(ctypes.Structure):
     _fields_ = [("force_ms", ctypes.c_double), ("force_timed", ctypes.c_int64),
                 ("update_ms", ctypes.c_double), ("update_timed", ctypes.c_int64),
                 ("force_launches", ctypes.c_int64), ("rebuilds", ctypes.c_int64),
-                ("host_polls", ctypes.c_int64), ("atom_evals", ctypes.c_int64)]
+                ("host_polls", ctypes.c_int64), ("atom_evals", ctypes.c_int64),
+                ("timed_atom_evals", ctypes.c_int64)]
 
 
 class aqs_mlp(ctypes.Structure):

@@ -197,7 +197,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   for (int a = 0; a < 3; ++a) lo.o_tdl[a] = take(sizeof(double) * A);
   lo.o_alt4 = take(sizeof(double4) * A);
   lo.o_talt4 = take(sizeof(double4) * A);
-  lo.o_evals = take(sizeof(unsigned long long));
+  lo.o_evals = take(2 * sizeof(unsigned long long));   // all evaluations, timed ones
   lo.o_xref4 = take(sizeof(double4) * A);
   lo.o_zbuf = take(sizeof(uint16_t) * kFeat * A);
   lo.o_lpart = take(sizeof(double) * kLearnParts * ((size_t)lo.blocks + 8));
@@ -237,6 +237,7 @@ struct Lane {
   int32_t g_pad = 0;               // its force launches' dynamic LDS
   bool in_flight = false;          // a block of iterations launched, not yet polled
   bool timed = false;              // ... with HIP events around its kernels
+  std::vector<hipEvent_t> ev;      // the lane's timing events (4 per iteration)
 };
 
 }  // namespace
@@ -294,7 +295,6 @@ struct aqs_ctx {
   // profiling
   int32_t prof_every = 0;
   int64_t block_count = 0;
-  std::vector<hipEvent_t> ev;
   aqs_counters cnt{};
 };
 
@@ -740,10 +740,10 @@ aqs_status lane_launch(aqs_ctx* c, Lane& L, int32_t start_mode, bool allow_timed
   const bool timed = allow_timed && c->prof_every > 0 && (c->block_count % c->prof_every) == 0;
   const int M = c->tn.block_iters;
   if (timed) {
-    while ((int)c->ev.size() < 4 * M) {
+    while ((int)L.ev.size() < 4 * M) {
       hipEvent_t e;
       HIPCHK(hipEventCreate(&e));
-      c->ev.push_back(e);
+      L.ev.push_back(e);
     }
   }
   if (start_mode == AQS_START_LEARNED || start_mode == AQS_START_EXTRAPOLATED) {
@@ -757,17 +757,18 @@ aqs_status lane_launch(aqs_ctx* c, Lane& L, int32_t start_mode, bool allow_timed
       if (st) return st;
     }
   }
-  const IterArgs a = iter_args(c, L);
+  IterArgs a = iter_args(c, L);
+  if (timed) a.tevals = c->evals + 1;   // atoms of the timed launches
   if (timed) {
     for (int it = 0; it < M; ++it) {
       // events bracket the force kernel alone and the update kernel alone
-      HIPCHK(hipEventRecord(c->ev[4 * it + 0], L.s));
+      HIPCHK(hipEventRecord(L.ev[4 * it + 0], L.s));
       launch_force(a, L.cur_ntiles, c->dim, L.s);
-      HIPCHK(hipEventRecord(c->ev[4 * it + 1], L.s));
+      HIPCHK(hipEventRecord(L.ev[4 * it + 1], L.s));
       launch_control(a, L.s);
-      HIPCHK(hipEventRecord(c->ev[4 * it + 2], L.s));
+      HIPCHK(hipEventRecord(L.ev[4 * it + 2], L.s));
       launch_update(a, L.cur_nblk, c->dim, L.s);
-      HIPCHK(hipEventRecord(c->ev[4 * it + 3], L.s));
+      HIPCHK(hipEventRecord(L.ev[4 * it + 3], L.s));
     }
   } else {
     aqs_status st = launch_block(c, L, a, M);
@@ -796,8 +797,8 @@ aqs_status lane_poll(aqs_ctx* c, Lane& L, bool all_states, int& active) {
     const int M = c->tn.block_iters;
     for (int it = 0; it < M; ++it) {
       float f = 0.f, u = 0.f;
-      HIPCHK(hipEventElapsedTime(&f, c->ev[4 * it + 0], c->ev[4 * it + 1]));
-      HIPCHK(hipEventElapsedTime(&u, c->ev[4 * it + 2], c->ev[4 * it + 3]));
+      HIPCHK(hipEventElapsedTime(&f, L.ev[4 * it + 0], L.ev[4 * it + 1]));
+      HIPCHK(hipEventElapsedTime(&u, L.ev[4 * it + 2], L.ev[4 * it + 3]));
       c->cnt.force_ms += f;
       c->cnt.update_ms += u;
     }
@@ -1104,7 +1105,8 @@ aqs_status aqs_destroy(aqs_ctx* c) {
     (void)hipStreamDestroy(c->ln[1].s);
   }
   for (Lane& L : c->ln) drop_graph(L);
-  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (Lane& L : c->ln)
+    for (hipEvent_t e : L.ev) (void)hipEventDestroy(e);
   free_pinned(c);
   delete c;
   return AQS_OK;
@@ -1356,7 +1358,7 @@ aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int3
   for (;;) {
     for (Lane* L : {&C, &B})
       if (!L->in_flight && lane_active(c, *L)) {
-        st = lane_launch(c, *L, start_mode, L == &B);
+        st = lane_launch(c, *L, start_mode, true);
         if (st) return st;
       }
     if (!C.in_flight && !B.in_flight) break;
@@ -1569,10 +1571,11 @@ aqs_status aqs_set_profiling(aqs_ctx* c, int32_t every_nth_block) {
 
 aqs_status aqs_get_counters(aqs_ctx* c, aqs_counters* out, int32_t reset) {
   if (!c) return fail(AQS_EINVAL, "null context");
-  unsigned long long ev = 0;
-  HIPCHK(hipMemcpyAsync(&ev, c->evals, sizeof ev, hipMemcpyDeviceToHost, c->stream));
+  unsigned long long ev[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(ev, c->evals, sizeof ev, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  c->cnt.atom_evals = (int64_t)ev;
+  c->cnt.atom_evals = (int64_t)ev[0];
+  c->cnt.timed_atom_evals = (int64_t)ev[1];
   if (out) *out = c->cnt;
   if (reset) {
     c->cnt = aqs_counters{};

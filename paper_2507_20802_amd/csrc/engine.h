@@ -181,6 +181,7 @@ struct IterArgs {
   double* upart;          // 1 per global block (max displacement of the update)
   uint32_t* counter;      // per slot, last-block detection
   unsigned long long* evals;  // atoms evaluated by force launches (statistics)
+  unsigned long long* tevals; // ... by the launches timed with events (null: not timed)
   StepRecord* log;        // per slot, log_cap records
   int32_t log_cap;
   int32_t max_nb;

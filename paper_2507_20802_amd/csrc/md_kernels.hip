@@ -671,7 +671,10 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
   }
   block_reduce<kForceParts + 1>(r, ops, red);
   if (tid == 0) {
-    if (compute) atomicAdd(a.evals, (unsigned long long)g.n);
+    if (compute) {
+      atomicAdd(a.evals, (unsigned long long)g.n);
+      if (a.tevals) atomicAdd(a.tevals, (unsigned long long)g.n);
+    }
     control<CG>(a, rep, g, r, phase);
   }
 }
