@@ -178,3 +178,20 @@ def test_nonfinite_input_is_reported():
     pos = np.array([[1.0, 1.0], [1.0, 1.0], [3.0, 3.0]])
     r = O.cg(pos, np.zeros(3, np.uint8), O.box_matrix(2, 12.0, 0.0), POT)
     assert r.status == O.NONFINITE and r.iters == 0
+
+
+@pytest.mark.parametrize("n_fail_max", [0, 1, 3])
+def test_stalled_after_n_fail_max_failed_line_searches(n_fail_max):
+    """On E = sum x^2 / 2 (stiffness 1) a line search along d = F from x
+    with trial step a has phi'(a) / phi'(0) = 1 - a, so the first trial
+    a_init = 0.01 leaves |phi'| = 0.99 |phi'(0)| > sigma |phi'(0)|.  With
+    ls_max = 0 every search fails at its first trial, restarts along the
+    new F with a_init (same ratio), and the (n_fail_max + 1)-th failure in a
+    row stops the minimiser: STALLED after n_fail_max + 1 iterations, each
+    a trial step x <- 0.99 x."""
+    x0 = np.array([[0.3, -0.2], [0.1, 0.25]])
+    kk = np.ones_like(x0)
+    p = O.CgParams(a_init=0.01, sigma=0.1, ls_max=0, n_fail_max=n_fail_max, dmax=10.0)
+    r = O.cg_quadratic(x0, kk, p)
+    assert r.status == O.STALLED and r.iters == n_fail_max + 1
+    np.testing.assert_allclose(r.pos, x0 * 0.99 ** (n_fail_max + 1), rtol=1e-14)

@@ -129,3 +129,69 @@ def test_perturbed_inherent_structure_relaxes_back(glass):
             assert 1e-4 < d < 1e-3 and r.E > E0 + 1e-7
     other = S.uniform_glass_start(2, 256, 1, 1)
     assert not O.equal_configs(other.pos, pos, H)
+
+
+# Curvature of the shifted pair energy at its minimum (closed form, also in
+# tests/golden/lj_closed_forms.txt): U''(r*) = 36 * 2^(2/3) for eps = sigma = 1.
+K_DIMER = 36.0 * 2.0 ** (2.0 / 3.0)
+
+
+@pytest.mark.parametrize("n_neg_max", [0, 1, 5, 40])
+def test_stalled_after_n_neg_max_overshooting_steps(n_neg_max):
+    """STALLED counts consecutive evaluations with P = F.v <= 0.  A dimer near
+    its minimum is a harmonic oscillator of the bond u = r - r* with
+    u'' = -2 k u.  With a constant time step (f_inc = f_dec = 1) and
+    c = 2 k dt^2 in (1, 4/3), every step overshoots: after the restart of
+    step 5 the bond follows u_(n+1) = (1 - c) u_n + (c / 2) u_(n-1) (u_(-1) = 0:
+    the first step starts from rest), whose dominant root is negative with
+    modulus below one, so u changes sign at every step, P < 0 at every
+    evaluation after the first (where v = 0, P = 0), and the amplitude decays
+    too slowly to converge before the stall.  Hence n_neg = it + 1 at
+    evaluation it, and the minimiser stops at evaluation it = n_neg_max with
+    STALLED, before that evaluation's update."""
+    c = 1.15
+    dt = math.sqrt(c / (2.0 * K_DIMER))
+    rstar = 2.0 ** (1.0 / 6.0)
+    u0 = 1e-3
+    pos = np.array([[3.0, 4.0], [3.0 + rstar + u0, 4.0]])
+    types = np.zeros(2, dtype=np.uint8)
+    p = O.FireParams(dt0=dt, dt_max=dt, dt_min=1e-6, f_inc=1.0, f_dec=1.0, alpha0=0.1, f_alpha=0.99,
+                     dmax=1.0, n_delay=5, n_neg_max=n_neg_max)
+    r = O.fire(pos, types, O.box_matrix(2, 12.0, 0.0), POT, p)
+    assert r.status == O.STALLED and r.iters == n_neg_max
+    # the bond alternates in sign and decays with the predicted root
+    lam = ((1 - c) - math.sqrt(1 + c * c)) / 2
+    assert -1.0 < lam < 0.0
+    # the same run with max_iter = n_neg_max stops at the same positions
+    # (the stall exits before moving)
+    if n_neg_max > 0:
+        q = O.fire(pos, types, O.box_matrix(2, 12.0, 0.0), POT,
+                   O.FireParams(**{**p.__dict__, "n_neg_max": 10 ** 6, "max_iter": n_neg_max}))
+        assert q.status == O.MAXITER and np.array_equal(q.pos, r.pos)
+    else:
+        assert np.array_equal(r.pos, pos)
+    # with a step inside the stable range (c < 1) the same start converges
+    ok = O.fire(pos, types, O.box_matrix(2, 12.0, 0.0), POT,
+                O.FireParams(**{**p.__dict__, "dt0": 0.5 * dt, "dt_max": 0.5 * dt, "n_neg_max": 2000}))
+    assert ok.status == O.CONVERGED
+
+
+def test_consecutive_count_resets_after_positive_power(glass):
+    """Relaxing a glass from a small perturbation of its inherent structure
+    has short runs of P <= 0 and many of them.  A bound of 1 stalls at the
+    first run of two (iteration i1), a bound of 2 at the first run of three
+    (i2 > i1 + 1, so a different run).  Counting the first evaluation (v = 0,
+    P = 0), at least 1 + 2 + 3 = 6 evaluations had P <= 0 by i2, so a
+    count that was not reset at P > 0 would pass a bound of 5 there; with
+    the reset, a bound of 5 changes nothing."""
+    pos, types, L = glass
+    H = O.box_matrix(2, L, 0.0)
+    x = pos + S.rng_for(2507, 20802, 91).normal(0.0, 0.02, size=pos.shape)
+    ref = O.fire(x, types, H, POT, TUNED)
+    run = {m: O.fire(x, types, H, POT, O.FireParams(**{**TUNED.__dict__, "n_neg_max": m})) for m in (1, 2, 5)}
+    assert ref.status == O.CONVERGED
+    assert run[1].status == O.STALLED and run[2].status == O.STALLED
+    i1, i2 = run[1].iters, run[2].iters
+    assert i2 > i1 + 1 and i2 < ref.iters
+    assert run[5].status == O.CONVERGED
+    assert run[5].iters == ref.iters and np.array_equal(run[5].pos, ref.pos)
