@@ -58,6 +58,8 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   Tune r;
   r.skin = (t && t->skin > 0.0) ? t->skin : 0.3;
   r.max_nb = (t && t->max_neighbors > 0) ? t->max_neighbors : (pot->dim == 3 ? 192 : 64);
+  // the packed list holds max_nb / kGroup groups, shared by up to kMaxTPA lanes
+  r.max_nb = (r.max_nb + kListAlign - 1) / kListAlign * kListAlign;
   r.block_iters = (t && t->block_iters > 0) ? t->block_iters : 32;
   r.use_graph = t ? t->use_graph : 0;
   r.log_cap = ((t && t->max_chain_steps > 0) ? t->max_chain_steps : 1024) + 1;
@@ -87,7 +89,7 @@ int segments_per_row(int n, int rows, int tpa) {
 
 struct Layout {
   size_t total = 0;
-  size_t o_geom, o_state, o_cgst, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_fpart, o_upart,
+  size_t o_geom, o_state, o_cgst, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_nbp, o_fpart, o_upart,
       o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl[2],
       o_tbl2[2], o_reps[2], o_nc3[2], o_overflow[2], o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_talt4, o_evals, o_xref4, o_ftbl[2], o_ttbl[2], o_thdr, o_hidx, o_sel[2],
       o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl[2], o_lftbl[2], o_lsel[2], o_tord;
@@ -165,6 +167,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_inv = take(sizeof(int32_t) * A);
   lo.o_nbc = take(sizeof(int32_t) * A);
   lo.o_nbl = take(sizeof(uint32_t) * (size_t)lo.nb_entries);
+  lo.o_nbp = take(sizeof(uint16_t) * (size_t)lo.nb_entries);
   lo.o_fpart = take(sizeof(double) * kForceParts * (size_t)lo.tiles);
   lo.o_thdr = take(sizeof(TileHdr) * (size_t)lo.tiles);
   lo.o_hidx = take(sizeof(uint32_t) * (size_t)halo_cap(dim) * (size_t)lo.tiles);
@@ -264,6 +267,7 @@ struct aqs_ctx {
   double *vx, *vy, *vz, *fx, *fy, *fz;
   int32_t *id, *inv, *nbc;
   uint32_t* nbl;
+  uint2* nbp;
   double *fpart, *upart;
   uint32_t* counter;
   StepRecord* log;
@@ -325,7 +329,7 @@ IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
   a.fx = c->fx; a.fy = c->fy; a.fz = c->fz;
   a.id = c->id; a.inv = c->inv;
-  a.nbc = c->nbc; a.nbl = c->nbl;
+  a.nbc = c->nbc; a.nbl = c->nbl; a.nbp = c->nbp;
   a.cell_start = c->cstart;
   a.thdr = c->thdr;
   a.hidx = c->hidx;
@@ -355,6 +359,7 @@ LearnArgs learn_args(aqs_ctx* c, const Lane& L, int mode, float* out = nullptr) 
   a.thdr = c->thdr;
   a.hidx = c->hidx;
   a.nbl = c->nbl;
+  a.nbp = c->nbp;
   a.nbc = c->nbc;
   a.tord = c->tord;
   a.max_nb = c->tn.max_nb;
@@ -562,7 +567,7 @@ aqs_status rebuild(aqs_ctx* c, Lane& L, const std::vector<int32_t>& sel, bool in
   a.xref4 = c->xref4;
   a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
   a.id = c->id; a.inv = c->inv;
-  a.nbc = c->nbc; a.nbl = c->nbl;
+  a.nbc = c->nbc; a.nbl = c->nbl; a.nbp = c->nbp;
   a.thdr = c->thdr; a.hidx = c->hidx; a.tord = c->tord;
   a.cell_count = c->ccount; a.cell_start = c->cstart; a.cell_of = c->cellof; a.order = c->order;
   a.tpos4 = c->tpos4; a.tvx = c->tvx; a.tvy = c->tvy; a.tvz = c->tvz; a.tid_ = c->tid;
@@ -1009,6 +1014,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->inv = at<int32_t>(w, lo.o_inv);
   c->nbc = at<int32_t>(w, lo.o_nbc);
   c->nbl = at<uint32_t>(w, lo.o_nbl);
+  c->nbp = at<uint2>(w, lo.o_nbp);
   c->fpart = at<double>(w, lo.o_fpart);
   c->upart = at<double>(w, lo.o_upart);
   c->counter = at<uint32_t>(w, lo.o_counter);

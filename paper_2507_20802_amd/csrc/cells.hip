@@ -13,8 +13,9 @@
 //   back   copy back; inverse permutation
 //   list   per force tile (tiles.h): its segment and halo run table, then
 //          per atom the 3^dim neighbouring cells, keeping every image pair
-//          within rc_ab + skin; the entry is the byte offset 8 h of the
-//          neighbour's halo slot h (or j | image code << 24)
+//          within rc_ab + skin; tiles with an LDS halo get the packed list
+//          (16-bit byte offsets 8 h of the neighbour's halo slot h), the
+//          others the word list (j | image code << 24); engine.h
 //   done   reset the validity bound of each rebuilt slot
 // Integer atomics only; the result does not depend on their order.
 #include <hip/hip_runtime.h>
@@ -342,40 +343,20 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
       }
     }
     a.nbc[gi] = na | (nb << 16);
+    // a tile with an LDS halo also needs the atom's A and B groups of the
+    // packed list to fit side by side
+    const int G = a.max_nb / kGroup;
+    if (cand && (na + kGroup - 1) / kGroup + (nb + kGroup - 1) / kGroup > G) over = true;
     if (over) atomicMax(a.overflow, na + nb);
   }
-  // The consumers walk the tile's atoms by decreasing list length (ties by
-  // position), so the lanes of a wavefront have lists of similar length:
-  // tord[a0 + k] is the k-th atom, and the list columns and counts are
-  // permuted to that order (column a0 + k holds that atom's list), so a
-  // wavefront still reads consecutive list words.
   __syncthreads();
-  __shared__ int s_src[kTileSort];
-  __shared__ uint32_t s_row[kTileSort];
+  // compact halo: the marked candidates, numbered in candidate order
   __shared__ int s_max[2];
-  int32_t* nbc = a.nbc + g.atom_off;
+  if (tid < kHaloWords) s_pre[tid] = __popc(s_bits[tid]);
   if (tid == 0) {
     s_max[0] = 0;
     s_max[1] = 0;
   }
-  __syncthreads();
-  for (int li = a0 + tid; li < a1; li += kBlock) {
-    const int ci = (nbc[li] & 0xffff) + (nbc[li] >> 16);
-    int rank = li - a0;
-    if (sortable) {
-      rank = 0;
-      for (int j = a0; j < a1; ++j) {
-        const int cj = (nbc[j] & 0xffff) + (nbc[j] >> 16);
-        rank += (cj > ci || (cj == ci && j < li)) ? 1 : 0;
-      }
-      s_src[rank] = li - a0;
-    }
-    a.tord[g.atom_off + a0 + rank] = li;
-    atomicMax(&s_max[0], nbc[li] & 0xffff);
-    atomicMax(&s_max[1], nbc[li] >> 16);
-  }
-  // compact halo: the marked candidates, numbered in candidate order
-  if (tid < kHaloWords) s_pre[tid] = __popc(s_bits[tid]);
   __syncthreads();
   if (tid == 0) {
     int acc = 0;
@@ -397,6 +378,28 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   __syncthreads();
   const bool lds = s_lds != 0;
   const int ncand = s_ncand;
+  // Walk order.  The consumers of a tile with an LDS halo walk its atoms by
+  // decreasing list length (ties by position), so the lanes of a wavefront
+  // have lists of similar length: tord[a0 + k] is the k-th atom, and its
+  // packed list and count sit in column a0 + k, so a wavefront still reads
+  // consecutive list words.  Other tiles keep their atoms in tile order.
+  __shared__ int s_src[kTileSort];
+  int32_t* nbc = a.nbc + g.atom_off;
+  for (int li = a0 + tid; li < a1; li += kBlock) {
+    const int ci = (nbc[li] & 0xffff) + (nbc[li] >> 16);
+    int rank = li - a0;
+    if (lds) {
+      rank = 0;
+      for (int j = a0; j < a1; ++j) {
+        const int cj = (nbc[j] & 0xffff) + (nbc[j] >> 16);
+        rank += (cj > ci || (cj == ci && j < li)) ? 1 : 0;
+      }
+      s_src[rank] = li - a0;
+    }
+    a.tord[g.atom_off + a0 + rank] = li;
+    atomicMax(&s_max[0], nbc[li] & 0xffff);
+    atomicMax(&s_max[1], nbc[li] >> 16);
+  }
   if (lds) {
     uint32_t* hx = a.hidx + tix * CAP;
     for (int hc = tid; hc < ncand; hc += kBlock) {
@@ -408,44 +411,75 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
           (uint32_t)(runs[r].src + (hc - runs[r].off)) | ((uint32_t)runs[r].code << kCodeShift);
     }
   }
-  if (!sortable) return;   // entries are global (cand is false)
-  // Entry of candidate number hc: the byte offset of its compact halo slot,
-  // or, for a tile whose compact halo does not fit, j | code.  Rows past an
-  // atom's count hold stale words; they are mapped too (bounded) and never read.
-  auto final_entry = [&](uint32_t hc) -> uint32_t {
-    if (!cand) return hc;
-    hc = min(hc, (uint32_t)(ncand > 0 ? ncand - 1 : 0));
-    const uint32_t w = s_bits[hc >> 5], bit = 1u << (hc & 31);
-    if (lds) return 8u * (uint32_t)(s_pre[hc >> 5] + __popc(w & (bit - 1u)));
-    for (int r = 0; r < kRuns; ++r)
-      if ((int)hc >= runs[r].off && (int)hc < runs[r].off + runs[r].count)
-        return (uint32_t)(runs[r].src + ((int)hc - runs[r].off)) |
-               ((uint32_t)runs[r].code << kCodeShift);
-    return 0u;
-  };
-  // counts, then every used row, through LDS
-  for (int k = tid; k < nt; k += kBlock) s_row[k] = (uint32_t)nbc[a0 + k];
   __syncthreads();
-  for (int k = tid; k < nt; k += kBlock) nbc[a0 + k] = (int32_t)s_row[s_src[k]];
+  if (!cand) return;   // entries are already j | code, columns in tile order
+  if (!lds) {
+    // the compact halo does not fit: candidate numbers -> j | code in place,
+    // each atom's own rows only (its A and B rows never overlap)
+    for (int li = a0 + tid; li < a1; li += kBlock) {
+      const int c = nbc[li], na = c & 0xffff, nb = c >> 16;
+      uint32_t* L = a.nbl + g.nb_off + li;
+      for (int q = 0; q < na + nb; ++q) {
+        const int64_t row = q < na ? q : a.max_nb - 1 - (q - na);
+        const int hc = min((int)L[row * g.npad], ncand - 1);
+        int r = 0;
+        while (r < kRuns - 1 && !(hc >= runs[r].off && hc < runs[r].off + runs[r].count)) ++r;
+        L[row * g.npad] =
+            (uint32_t)(runs[r].src + (hc - runs[r].off)) | ((uint32_t)runs[r].code << kCodeShift);
+      }
+    }
+    return;
+  }
+  // Tile with an LDS halo: counts in walk order, then the packed list.  The
+  // word list keeps the scan's candidate numbers (original columns); each
+  // pass stages kGroup rows per group row of the tile's atoms in LDS and
+  // writes the groups of every atom in its walk-order column, entry =
+  // byte offset 8 h of the candidate's compact halo slot h, the last group
+  // of a segment padded with the far fill slot.
+  __shared__ int s_cnt[kTileSort];
+  __shared__ uint32_t s_stage[kRowStage];
+  for (int k = tid; k < nt; k += kBlock) s_cnt[k] = nbc[a0 + s_src[k]];
   __syncthreads();
-  // the used rows (A rows up, then B rows down) go through LDS as many at a
-  // time as fit in s_row, so each thread keeps several loads in flight
-  uint32_t* Lt = a.nbl + g.nb_off + a0;
+  for (int k = tid; k < nt; k += kBlock) nbc[a0 + k] = s_cnt[k];
+  const int G = a.max_nb / kGroup;
   const int rows_a = min(s_max[0], a.max_nb), rows_b = min(s_max[1], a.max_nb);
-  const int nq = rows_a + rows_b;
-  const int per = max(1, kTileSort / max(nt, 1));
-  for (int q0 = 0; q0 < nq; q0 += per) {
-    const int ne = min(per, nq - q0) * nt;
+  const int ga = (rows_a + kGroup - 1) / kGroup, gb = (rows_b + kGroup - 1) / kGroup;
+  const int ng = ga + gb;
+  const int ntc = max(nt, 1);
+  const int pg = max(1, kRowStage / (kGroup * ntc));
+  const uint32_t* Lt = a.nbl + g.nb_off + a0;
+  uint2* Pk = a.nbp + g.nb_off / kGroup + a0;
+  const uint32_t fill = 8u * (uint32_t)(CAP - 1);
+  auto halo_offset = [&](uint32_t hc) -> uint32_t {
+    hc = min(hc, (uint32_t)(ncand - 1));
+    const uint32_t w = s_bits[hc >> 5], bit = 1u << (hc & 31);
+    return 8u * (uint32_t)(s_pre[hc >> 5] + __popc(w & (bit - 1u)));
+  };
+  for (int g0 = 0; g0 < ng; g0 += pg) {
+    const int cnt = min(pg, ng - g0);
+    const int ne = cnt * kGroup * nt;
     for (int e = tid; e < ne; e += kBlock) {
-      const int q = q0 + e / nt;
-      const int r = q < rows_a ? q : a.max_nb - 1 - (q - rows_a);
-      s_row[e] = Lt[(int64_t)r * g.npad + e % nt];
+      const int gq = g0 + e / (kGroup * nt), i = (e / nt) % kGroup, col = e % nt;
+      const bool isa = gq < ga;
+      const int q = kGroup * (isa ? gq : gq - ga) + i;
+      const bool ok = q < (isa ? rows_a : rows_b);
+      s_stage[e] = ok ? Lt[(int64_t)(isa ? q : a.max_nb - 1 - q) * g.npad + col] : 0u;
     }
     __syncthreads();
-    for (int e = tid; e < ne; e += kBlock) {
-      const int q = q0 + e / nt, k = e % nt;
-      const int r = q < rows_a ? q : a.max_nb - 1 - (q - rows_a);
-      Lt[(int64_t)r * g.npad + k] = final_entry(s_row[(e / nt) * nt + s_src[k]]);
+    for (int e = tid; e < cnt * nt; e += kBlock) {
+      const int gq = g0 + e / nt, k = e % nt;
+      const bool isa = gq < ga;
+      const int gs = isa ? gq : gq - ga;   // group of the atom's segment
+      const int nk = isa ? (s_cnt[k] & 0xffff) : (s_cnt[k] >> 16);
+      if (kGroup * gs >= nk) continue;     // not one of this atom's groups
+      const int src = s_src[k];
+      const int base = (e / nt) * kGroup * nt;
+      uint32_t o[kGroup];
+#pragma unroll
+      for (int i = 0; i < kGroup; ++i)
+        o[i] = (kGroup * gs + i < nk) ? halo_offset(s_stage[base + i * nt + src]) : fill;
+      Pk[(int64_t)(isa ? gs : G - 1 - gs) * g.npad + k] =
+          make_uint2(o[0] | (o[1] << 16), o[2] | (o[3] << 16));
     }
     __syncthreads();
   }

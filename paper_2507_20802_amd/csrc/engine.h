@@ -8,15 +8,23 @@
 //     id     int32, atom id held by each sorted position ("slot order")
 //     inv    int32, sorted position of each atom id
 //     nbc    int32, neighbour counts per atom (A | B << 16)
-//   neighbour list per slot: max_nb x npad uint32, column-major (row k of
-//     column c at k*npad + c) so a wavefront reads 64 consecutive words;
-//     column c belongs to atom tord[c] (each force tile's atoms ordered by
-//     decreasing list length; nbc is indexed by column too); the nA
-//     neighbours of type A fill rows 0.. upward, the nB of type B rows
-//     max_nb - 1 downward, nbc = nA | nB << 16 (the neighbour's type is
-//     that of its segment); entry = 8 x halo slot, the byte offset of the
-//     slot in the halo coordinate arrays (tiles with an LDS halo), or
-//     j | (image code << 24)
+//   neighbour lists per slot, the nA neighbours of type A first and the nB
+//     of type B second, nbc = nA | nB << 16 (the neighbour's type is that of
+//     its segment):
+//   - packed list (force tiles with an LDS halo): max_nb / 4 group rows x
+//     npad columns of 8 bytes, four 16-bit entries each, column-major (group
+//     row g of column c at g*npad + c) so a wavefront reads 512 consecutive
+//     bytes; entry = 8 x halo slot, the byte offset of the slot in the halo
+//     coordinate arrays; A neighbours fill group rows 0.. upward, B
+//     neighbours group rows max_nb/4 - 1 downward, the last group of each
+//     padded with the far fill slot; column c belongs to atom tord[c] (each
+//     tile's atoms ordered by decreasing list length; nbc is indexed by
+//     column too);
+//   - word list: max_nb x npad uint32, row k of column c at k*npad + c; A
+//     neighbours in rows 0.. upward, B neighbours rows max_nb - 1 downward;
+//     entry = j | (image code << 24) (tiles without an LDS halo, whose
+//     columns are the atoms in tile order), or, for tiles with a halo, the
+//     builder's candidate numbers (scratch)
 //   xref4  double4, positions at the last list build (validity test)
 //   per-block partial sums, per-slot counters, per-slot state and geometry.
 #pragma once
@@ -37,6 +45,8 @@ constexpr int kHaloCap2 = 1024;       // 2D
 __host__ __device__ constexpr int halo_cap(int dim) { return dim == 3 ? kHaloCap3 : kHaloCap2; }
 constexpr uint32_t kIdxMask = 0x00FFFFFFu;
 constexpr int kCodeShift = 24;
+constexpr int kGroup = 4;             // entries per 8-byte group of the packed list
+constexpr int kListAlign = 32;        // max_nb is a multiple of kGroup x kMaxTPA
 
 // phases of a slot's device state machine
 enum Phase : int32_t {
@@ -172,7 +182,8 @@ struct IterArgs {
   double* fx; double* fy; double* fz;
   int32_t* id; int32_t* inv;
   const int32_t* nbc;
-  const uint32_t* nbl;
+  const uint32_t* nbl;        // word lists (tiles without an LDS halo)
+  const uint2* nbp;           // packed lists (tiles with an LDS halo); slot at nb_off / 4
   const int32_t* cell_start;  // per slot: cell_off + c, cells of the current grid
   const void* thdr;           // TileHdr per force tile (tile_off + t)
   const uint32_t* hidx;       // compact halo per force tile (kHaloCap slots): j | code << 24

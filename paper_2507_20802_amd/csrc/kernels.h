@@ -24,6 +24,7 @@ struct RebuildArgs {
   int32_t* id; int32_t* inv;
   int32_t* nbc;
   uint32_t* nbl;
+  uint2* nbp;           // packed lists (engine.h)
   TileHdr* thdr;        // per force tile (tile_off + t)
   uint32_t* hidx;       // compact halo per force tile (kHaloCap slots): j | code << 24
   int32_t* tord;        // per atom: the tile's atoms by decreasing list length

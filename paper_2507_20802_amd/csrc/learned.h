@@ -46,7 +46,8 @@ struct LearnArgs {
   const int2* ftiles;       // (slot, force tile) launch table
   const void* thdr;         // TileHdr per force tile
   const uint32_t* hidx;     // compact halo per force tile (kHaloCap slots): j | code << 24
-  const uint32_t* nbl;      // neighbour lists (engine.h)
+  const uint32_t* nbl;      // word lists (engine.h): tiles without an LDS halo
+  const uint2* nbp;         // packed lists (engine.h): tiles with an LDS halo
   const int32_t* nbc;
   const int32_t* tord;      // per tile: atoms in list order (list column -> atom)
   int32_t max_nb;

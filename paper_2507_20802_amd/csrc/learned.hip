@@ -163,21 +163,28 @@ __global__ __launch_bounds__(kBlock) void k_ldesc(LearnArgs a) {
     const int32_t counts = live ? a.nbc[g.atom_off + colc] : 0;
     const int na = counts & 0xffff, nbn = (counts >> 16) & 0xffff;
     const uint32_t* L = a.nbl + g.nb_off + colc;
+    // packed list of the slot as 16-bit entries: group row q, column c,
+    // entry i at (q npad + c) kGroup + i
+    const uint16_t* Lp = reinterpret_cast<const uint16_t*>(a.nbp + g.nb_off / kGroup);
+    const int G = a.max_nb / kGroup;
     double acc[kFeat];
 #pragma unroll
     for (int f = 0; f < kFeat; ++f) acc[f] = 0.0;
-    // A neighbours in rows 0.., B neighbours in rows max_nb - 1 down
+    // A neighbours first (rows 0.. up), then B neighbours (rows from the top down)
     for (int kk = sub; kk < na + nbn; kk += kLDescTPA) {
-      const int k = kk < na ? kk : a.max_nb - 1 - (kk - na);
-      const uint32_t ent = L[(int64_t)k * g.npad];
       const int tj = kk < na ? 0 : 1;
       double dx, dy, dz;
       if (lds) {
-        const int h = (int)(ent >> 3);   // entries are byte offsets 8 h
+        const int q = kk < na ? kk : kk - na;
+        const int grow = kk < na ? q / kGroup : G - 1 - q / kGroup;
+        const uint32_t off = Lp[((int64_t)grow * g.npad + colc) * kGroup + q % kGroup];
+        const int h = (int)(off >> 3);   // entries are byte offsets 8 h
         dx = hx[h] - pi.x;
         dy = hy[h] - pi.y;
         dz = (D == 3) ? hz[h] - pi.z : 0.0;
       } else {
+        const int k = kk < na ? kk : a.max_nb - 1 - (kk - na);
+        const uint32_t ent = L[(int64_t)k * g.npad];
         const double4 pj = P[ent & kIdxMask];
         const int code = (int)((ent >> kCodeShift) & 31u);
         dx = (pj.x - pi.x) + sh[code][0];

@@ -145,27 +145,25 @@ __device__ __forceinline__ uint32_t list_entry(__amdgpu_buffer_rsrc_t rs, uint32
   return k < my ? raw : fill;
 }
 
-// One segment of a list: this lane's entry k (k = 0 .. my - 1) sits at byte
-// offset lb + sb + k ss of the slot's list (ss < 0 walks the B segment down
-// from the top); all neighbours of the segment have the same type, so the
-// pair parameters q are fixed.
-template <int D, bool WE, int TPA, bool LDS>
+// One segment of a word list (a tile without an LDS halo): this lane's
+// entry k (k = 0 .. my - 1) sits at byte offset lb + sb + k ss of the slot's
+// list (ss < 0 walks the B segment down from the top) and holds
+// j | image code << 24; all neighbours of the segment have the same type, so
+// the pair parameters q are fixed.
+template <int D, bool WE, int TPA>
 __device__ __forceinline__ void pair_segment(const double4 pi, __amdgpu_buffer_rsrc_t rs,
                                              uint32_t lb, uint32_t sb, uint32_t ss, int my,
                                              int kcap, uint32_t fill,
                                              const PairParams q, const double4* __restrict__ P,
-                                             const double (*sh)[4], const double* hx,
-                                             const double* hy, const double* hz, double& fx,
-                                             double& fy, double& fz, double& e, double& w) {
+                                             const double (*sh)[4], double& fx, double& fy,
+                                             double& fz, double& e, double& w) {
   uint32_t cur[kChunk];
 #pragma unroll
   for (int u = 0; u < kChunk; ++u) cur[u] = list_entry(rs, lb, sb, ss, u, my, kcap, fill);
   for (int k0 = 0; k0 < my; k0 += kChunk) {
     double4 pj[kChunk];
-    if (!LDS) {
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) pj[u] = P[cur[u] & kIdxMask];
-    }
+    for (int u = 0; u < kChunk; ++u) pj[u] = P[cur[u] & kIdxMask];
     uint32_t nxt[kChunk];
 #pragma unroll
     for (int u = 0; u < kChunk; ++u)
@@ -173,37 +171,44 @@ __device__ __forceinline__ void pair_segment(const double4 pi, __amdgpu_buffer_r
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) {
       const uint32_t ent = cur[u];
-      double dx, dy, dz;
-      if (LDS) {
-        dx = lds_at(hx, ent) - pi.x;
-        dy = lds_at(hy, ent) - pi.y;
-        dz = (D == 3) ? lds_at(hz, ent) - pi.z : 0.0;
-      } else {
-        const int code = (int)((ent >> kCodeShift) & 31u);
-        dx = (pj[u].x - pi.x) + sh[code][0];
-        dy = (pj[u].y - pi.y) + sh[code][1];
-        dz = (D == 3) ? (pj[u].z - pi.z) + sh[code][2] : 0.0;
-      }
-      pair_term<D, WE, !LDS>(k0 + u < my, dx, dy, dz, q, fx, fy, fz, e, w);
+      const int code = (int)((ent >> kCodeShift) & 31u);
+      const double dx = (pj[u].x - pi.x) + sh[code][0];
+      const double dy = (pj[u].y - pi.y) + sh[code][1];
+      const double dz = (D == 3) ? (pj[u].z - pi.z) + sh[code][2] : 0.0;
+      pair_term<D, WE, true>(k0 + u < my, dx, dy, dz, q, fx, fy, fz, e, w);
     }
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) cur[u] = nxt[u];
   }
 }
 
-// Lennard-Jones sum of one atom over its list, TPA lanes per atom.  The list
-// (engine.h) holds the nA neighbours of type A in rows 0 .. nA - 1 and the
-// nB of type B in rows max_nb - 1 down to max_nb - nB; lane sub takes rows
-// sub, sub + TPA, ... of each.  LDS: entries index the tile's halo (image
-// shifts applied when staged); else entries are j | image code.
-template <int D, bool WE, int TPA, bool LDS>
+// Combine the TPA lanes of an atom (fixed butterfly: every lane of the group
+// ends with the same bits).
+template <int D, bool WE, int TPA>
+__device__ __forceinline__ void combine_lanes(double& fx, double& fy, double& fz, double& e,
+                                              double& w) {
+#pragma unroll
+  for (int off = 1; off < TPA; off <<= 1) {
+    fx += __shfl_xor(fx, off, kWave);
+    fy += __shfl_xor(fy, off, kWave);
+    if (D == 3) fz += __shfl_xor(fz, off, kWave);
+    if (WE) {
+      e += __shfl_xor(e, off, kWave);
+      w += __shfl_xor(w, off, kWave);
+    }
+  }
+}
+
+// Lennard-Jones sum of one atom over its word list, TPA lanes per atom.  The
+// list (engine.h) holds the nA neighbours of type A in rows 0 .. nA - 1 and
+// the nB of type B in rows max_nb - 1 down to max_nb - nB; lane sub takes
+// rows sub, sub + TPA, ... of each.
+template <int D, bool WE, int TPA>
 __device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint32_t* __restrict__ Ls,
                                            int col, int64_t stride, int32_t counts, int max_nb,
                                            uint32_t fill, const double4* __restrict__ P,
-                                           const double (*sh)[4], const double* hx,
-                                           const double* hy, const double* hz,
-                                           const PairParams* pp, double& fx, double& fy,
-                                           double& fz, double& e, double& w) {
+                                           const double (*sh)[4], const PairParams* pp, double& fx,
+                                           double& fy, double& fz, double& e, double& w) {
   const int sub = (int)(threadIdx.x % TPA);
   const int na = counts & 0xffff, nb = (counts >> 16) & 0xffff;
   const int kcap = max_nb / TPA;
@@ -220,22 +225,94 @@ __device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint3
   const uint32_t step = (uint32_t)TPA * row_bytes;
   const uint32_t lba = 4u * (uint32_t)col + (uint32_t)sub * row_bytes;
   const uint32_t lbb = 4u * (uint32_t)col + (uint32_t)(TPA - 1 - sub) * row_bytes;
-  pair_segment<D, WE, TPA, LDS>(pi, rs, lba, 0u, step, my_a, kcap, fill, pp[2 * ti], P, sh, hx, hy,
-                                hz, fx, fy, fz, e, w);
-  pair_segment<D, WE, TPA, LDS>(pi, rs, lbb, (uint32_t)(max_nb - TPA) * row_bytes, 0u - step, my_b,
-                                kcap, fill, pp[2 * ti + 1], P, sh, hx, hy, hz, fx, fy, fz, e, w);
-  // combine the TPA lanes of the atom (fixed butterfly: every lane of the
-  // group ends with the same bits)
-#pragma unroll
-  for (int off = 1; off < TPA; off <<= 1) {
-    fx += __shfl_xor(fx, off, kWave);
-    fy += __shfl_xor(fy, off, kWave);
-    if (D == 3) fz += __shfl_xor(fz, off, kWave);
-    if (WE) {
-      e += __shfl_xor(e, off, kWave);
-      w += __shfl_xor(w, off, kWave);
-    }
+  pair_segment<D, WE, TPA>(pi, rs, lba, 0u, step, my_a, kcap, fill, pp[2 * ti], P, sh, fx, fy, fz,
+                           e, w);
+  pair_segment<D, WE, TPA>(pi, rs, lbb, (uint32_t)(max_nb - TPA) * row_bytes, 0u - step, my_b,
+                           kcap, fill, pp[2 * ti + 1], P, sh, fx, fy, fz, e, w);
+  combine_lanes<D, WE, TPA>(fx, fy, fz, e, w);
+}
+
+// Cache policy of the packed-list loads: non-temporal.  Each list word is
+// read once per launch, and streaming it through L2 at normal priority
+// evicts the halo positions, which every tile re-reads.
+constexpr int kListCachePolicy = 2;
+
+// Group k of this lane's share of a packed list segment: the 8 bytes (four
+// 16-bit entries) at byte offset lb + sb + k ss, k clamped below gcap so the
+// scalar part sb + k ss stays wave-uniform and inside the slot's list.
+__device__ __forceinline__ uint2 packed_group(__amdgpu_buffer_rsrc_t rs, uint32_t lb, uint32_t sb,
+                                              uint32_t ss, int k, int gcap) {
+  const uint32_t kk = (uint32_t)min(k, gcap - 1);
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)lb, (int)(sb + kk * ss),
+                                                      kListCachePolicy);
+  return make_uint2(v[0], v[1]);
+}
+
+// One pair from the LDS halo: `off` is the byte offset of the neighbour's
+// halo slot (another atom, or the far fill slot: always a positive
+// distance).
+template <int D, bool WE>
+__device__ __forceinline__ void halo_pair(uint32_t off, const double4& pi, const double* hx,
+                                          const double* hy, const double* hz, const PairParams& q,
+                                          double& fx, double& fy, double& fz, double& e,
+                                          double& w) {
+  const double dx = lds_at(hx, off) - pi.x;
+  const double dy = lds_at(hy, off) - pi.y;
+  const double dz = (D == 3) ? lds_at(hz, off) - pi.z : 0.0;
+  pair_term<D, WE, false>(true, dx, dy, dz, q, fx, fy, fz, e, w);
+}
+
+// One segment of a packed list: this lane's groups k = 0 .. my - 1, two
+// groups (eight entries) in flight ahead of the four pairs being summed.
+template <int D, bool WE>
+__device__ __forceinline__ void packed_segment(const double4 pi, __amdgpu_buffer_rsrc_t rs,
+                                               uint32_t lb, uint32_t sb, uint32_t ss, int my,
+                                               int gcap, const PairParams q, const double* hx,
+                                               const double* hy, const double* hz, double& fx,
+                                               double& fy, double& fz, double& e, double& w) {
+  if (my <= 0) return;
+  uint2 g0 = packed_group(rs, lb, sb, ss, 0, gcap);
+  uint2 g1 = packed_group(rs, lb, sb, ss, 1, gcap);
+  for (int k = 0; k < my; ++k) {
+    const uint2 g2 = packed_group(rs, lb, sb, ss, k + 2, gcap);
+    halo_pair<D, WE>(g0.x & 0xffffu, pi, hx, hy, hz, q, fx, fy, fz, e, w);
+    halo_pair<D, WE>(g0.x >> 16, pi, hx, hy, hz, q, fx, fy, fz, e, w);
+    halo_pair<D, WE>(g0.y & 0xffffu, pi, hx, hy, hz, q, fx, fy, fz, e, w);
+    halo_pair<D, WE>(g0.y >> 16, pi, hx, hy, hz, q, fx, fy, fz, e, w);
+    g0 = g1;
+    g1 = g2;
   }
+}
+
+// Lennard-Jones sum of one atom over its packed list (engine.h), TPA lanes
+// per atom: lane sub takes the A groups sub, sub + TPA, ... from group row 0
+// up and the B groups from group row G - 1 - sub down (G = max_nb / 4).
+template <int D, bool WE, int TPA>
+__device__ __forceinline__ void atom_pairs_packed(const double4 pi, int ti, const uint2* Lp, int col,
+                                                  int npad, int32_t counts, int max_nb,
+                                                  const double* hx, const double* hy,
+                                                  const double* hz, const PairParams* pp,
+                                                  double& fx, double& fy, double& fz, double& e,
+                                                  double& w) {
+  const int sub = (int)(threadIdx.x % TPA);
+  const int G = max_nb / kGroup;
+  const int na = counts & 0xffff, nb = (counts >> 16) & 0xffff;
+  const int ga = (na + kGroup - 1) / kGroup, gb = (nb + kGroup - 1) / kGroup;
+  const int gcap = G / TPA;
+  const int my_a = ga > sub ? (ga - sub + TPA - 1) / TPA : 0;
+  const int my_b = gb > sub ? (gb - sub + TPA - 1) / TPA : 0;
+  // group row of step k: A  k TPA + sub,  B  (G - TPA - k TPA) + (TPA - 1 - sub)
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint2*>(Lp), (short)0, (int)(8u * (uint32_t)npad * (uint32_t)G), kBufferFlags);
+  const uint32_t row_bytes = 8u * (uint32_t)npad;
+  const uint32_t step = (uint32_t)TPA * row_bytes;
+  const uint32_t lba = 8u * (uint32_t)col + (uint32_t)sub * row_bytes;
+  const uint32_t lbb = 8u * (uint32_t)col + (uint32_t)(TPA - 1 - sub) * row_bytes;
+  packed_segment<D, WE>(pi, rs, lba, 0u, step, my_a, gcap, pp[2 * ti], hx, hy, hz, fx, fy, fz, e,
+                        w);
+  packed_segment<D, WE>(pi, rs, lbb, (uint32_t)(G - TPA) * row_bytes, 0u - step, my_b, gcap,
+                        pp[2 * ti + 1], hx, hy, hz, fx, fy, fz, e, w);
+  combine_lanes<D, WE, TPA>(fx, fy, fz, e, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -527,15 +604,17 @@ __device__ __forceinline__ void force_atom(const IterArgs& a, const Geom& g, int
                                            const double (*sh)[4], const PairParams* spp,
                                            const double* hx, const double* hy, const double* hz,
                                            bool cg, double* part) {
-  constexpr int CAP = (D == 3) ? kHaloCap3 : kHaloCap2;
   const int64_t gi = g.atom_off + li;
   const double4 pi = a.pos4[gi];
   double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0;
-  atom_pairs<D, WE, TPA, LDS>(pi, (int)pi.w, a.nbl + g.nb_off, col, g.npad,
-                              a.nbc[g.atom_off + col], a.max_nb,
-                              LDS ? 8u * (uint32_t)(CAP - 1) : ((uint32_t)li | (13u << kCodeShift)),
-                              a.pos4 + g.atom_off,
-                              sh, hx, hy, hz, spp, fx, fy, fz, e, w);
+  if (LDS)
+    atom_pairs_packed<D, WE, TPA>(pi, (int)pi.w, a.nbp + g.nb_off / kGroup, col, g.npad,
+                                  a.nbc[g.atom_off + col], a.max_nb, hx, hy, hz, spp, fx, fy, fz,
+                                  e, w);
+  else
+    atom_pairs<D, WE, TPA>(pi, (int)pi.w, a.nbl + g.nb_off, col, g.npad, a.nbc[g.atom_off + col],
+                           a.max_nb, (uint32_t)li | (13u << kCodeShift), a.pos4 + g.atom_off, sh,
+                           spp, fx, fy, fz, e, w);
   if (threadIdx.x % TPA != 0) return;
   a.fx[gi] = fx;
   a.fy[gi] = fy;

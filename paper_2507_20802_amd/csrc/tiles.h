@@ -28,6 +28,8 @@ constexpr int kRuns = 27;  // (dz, dy, part): 3 x 3 x 3 (2D uses dz = 0 only)
 constexpr int kTileSort = 1024;  // tiles up to this many atoms are walked by list length
 constexpr int kHaloWords = 128;  // candidate bitmap of the builder: tiles with more candidates
                                  // (32 kHaloWords) keep global entries
+constexpr int kRowStage = 4096;  // list words the builder stages in LDS per pass (a pass holds
+                                 // whole groups: kGroup rows of up to kTileSort atoms)
 
 struct TileHdr {
   int32_t a0, a1;   // atom range [a0, a1) of the tile
