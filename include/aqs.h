@@ -423,6 +423,34 @@ aqs_status aqs_mlp_gradients(const aqs_mlp* model, int64_t n, const float* feat,
                              const float* target, float huber_delta, aqs_mlp* grad,
                              float* loss, void* stream);
 
+/* Limits of aqs_mlp_train_static and the size of its device array. */
+#define AQS_STATIC_TRAIN_MAX_SAMPLES 65536
+#define AQS_STATIC_TRAIN_MAX_BATCH 4096
+#define AQS_STATIC_TRAIN_MAX_EPOCHS 4096
+#define AQS_STATIC_TRAIN_SCRATCH_BYTES 16525568  /* 15.8 MiB per GPU */
+
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * training of aqs_mlp_train -- same arguments, same kernels, the same
+ * trained weights bit for bit -- with its buffers taken from a fixed array
+ * of AQS_STATIC_TRAIN_SCRATCH_BYTES inside this library instead of
+ * allocated.  Calls no hipMalloc, hipFree or other allocating routine.
+ *
+ * Each GPU the library runs on holds its own copy of the array from the
+ * first use until the process ends; the call uses the array of the current
+ * device (hipGetDevice), which must be the device of feat, target, order and
+ * stream.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (the call clears what must start at zero itself):
+ * calls that overlap on one GPU -- from two threads, or on two streams whose
+ * work interleaves -- race on it and must be serialised by the caller.
+ * AQS_ECAPACITY, nothing run, if n > AQS_STATIC_TRAIN_MAX_SAMPLES, if
+ * min(batch, n) > AQS_STATIC_TRAIN_MAX_BATCH or if epochs >
+ * AQS_STATIC_TRAIN_MAX_EPOCHS; otherwise the errors of aqs_mlp_train.
+ * Synchronises. */
+aqs_status aqs_mlp_train_static(const aqs_train_params* p, int64_t n, const float* feat,
+                                const float* target, const int32_t* order, aqs_mlp* model,
+                                float* loss_hist, void* stream);
+
 /* Human-readable description of the last error on this thread. */
 const char* aqs_last_error(void);
 

@@ -121,6 +121,9 @@ SIGNATURES = {
     "aqs_mlp_train": (ctypes.c_int32, [ctypes.POINTER(aqs_train_params), ctypes.c_int64, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(aqs_mlp),
                                        c_float_p, ctypes.c_void_p]),
+    "aqs_mlp_train_static": (ctypes.c_int32, [ctypes.POINTER(aqs_train_params), ctypes.c_int64, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(aqs_mlp),
+                                              c_float_p, ctypes.c_void_p]),
     "aqs_mlp_gradients": (ctypes.c_int32, [ctypes.POINTER(aqs_mlp), ctypes.c_int64, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_float, ctypes.POINTER(aqs_mlp),
                                            c_float_p, ctypes.c_void_p]),

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -1598,8 +1599,8 @@ aqs_status aqs_get_counters(aqs_ctx* c, aqs_counters* out, int32_t reset) {
 
 namespace {
 
-// Device buffers of one training or gradient call (freed by the destructor).
-struct TrainBufs {
+// Device buffers of one training or gradient call.
+struct TrainPtrs {
   uint16_t* z = nullptr;
   float *t = nullptr, *part = nullptr, *master = nullptr, *m = nullptr, *v = nullptr,
         *grad = nullptr;
@@ -1607,6 +1608,10 @@ struct TrainBufs {
   int32_t* order = nullptr;
   uint8_t* keep = nullptr;
   MlpDev* mlp = nullptr;
+};
+
+// ... allocated by the call itself (freed by the destructor).
+struct TrainBufs : TrainPtrs {
   ~TrainBufs() {
     void* ps[] = {z, t, stats, part, master, m, v, grad, stat_part, loss, order, keep, mlp};
     for (void* p : ps)
@@ -1741,9 +1746,12 @@ aqs_status aqs_learned_targets(aqs_ctx* c, int32_t rep_prev, int32_t rep_next, f
   return AQS_OK;
 }
 
-aqs_status aqs_mlp_train(const aqs_train_params* p, int64_t n, const float* feat,
-                         const float* target, const int32_t* order, aqs_mlp* model,
-                         float* loss_hist, void* stream) {
+}  // extern "C"
+
+namespace {
+
+aqs_status check_train(const aqs_train_params* p, int64_t n, const float* feat,
+                       const float* target, const int32_t* order, const aqs_mlp* model) {
   if (!p || !feat || !target || !order) return fail(AQS_EINVAL, "null argument");
   aqs_status st = check_mlp(model);
   if (st) return st;
@@ -1751,16 +1759,21 @@ aqs_status aqs_mlp_train(const aqs_train_params* p, int64_t n, const float* feat
     return fail(AQS_EINVAL, "bad training sizes");
   if (!(p->huber_delta > 0.0f) || !(p->lr > 0.0f))
     return fail(AQS_EINVAL, "bad training parameters");
-  hipStream_t s = (hipStream_t)stream;
+  return AQS_OK;
+}
+
+// The training of aqs_mlp_train on buffers b, sized for n samples, batches of
+// min(p->batch, n) and p->epochs epochs.  Adam's moments and the loss
+// accumulators are cleared here by a kernel.
+aqs_status train_run(const aqs_train_params* p, int64_t n, const float* feat,
+                     const float* target, const int32_t* order, aqs_mlp* model,
+                     float* loss_hist, hipStream_t s, const TrainPtrs& b) {
   const int32_t bsz = (int32_t)std::min<int64_t>(p->batch, n);
-  const int32_t maxblk = (bsz + 63) / 64;
-  TrainBufs b;
-  st = train_alloc(b, n, maxblk, p->epochs, true);
-  if (st) return st;
-  HIPCHK(hipMemsetAsync(b.m, 0, sizeof(float) * kNumParams, s));
-  HIPCHK(hipMemsetAsync(b.v, 0, sizeof(float) * kNumParams, s));
-  HIPCHK(hipMemsetAsync(b.loss, 0, sizeof(double) * p->epochs, s));
-  st = upload_mlp(s, model, b.master, b.mlp, false);
+  launch_zero_words(reinterpret_cast<uint32_t*>(b.m), kNumParams, s);
+  launch_zero_words(reinterpret_cast<uint32_t*>(b.v), kNumParams, s);
+  launch_zero_words(reinterpret_cast<uint32_t*>(b.loss), 2 * (int64_t)p->epochs, s);
+  HIPCHK(hipGetLastError());
+  aqs_status st = upload_mlp(s, model, b.master, b.mlp, false);
   if (st) return st;
   TrainArgs a{};
   a.feat = feat;
@@ -1820,6 +1833,108 @@ aqs_status aqs_mlp_train(const aqs_train_params* p, int64_t n, const float* feat
   if (loss_hist)
     for (int e = 0; e < p->epochs; ++e) loss_hist[e] = (float)(lh[e] / (double)batches);
   return AQS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Training without device allocation: the buffers of train_run live in a
+// fixed device array of this library, one per GPU.
+
+constexpr int64_t kStaticSamples = AQS_STATIC_TRAIN_MAX_SAMPLES;
+constexpr int64_t kStaticBatchBlocks = (AQS_STATIC_TRAIN_MAX_BATCH + 63) / 64;
+constexpr int64_t kStaticEpochs = AQS_STATIC_TRAIN_MAX_EPOCHS;
+
+constexpr size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+// byte offsets of the buffers in the array
+constexpr size_t kSoZ = 0;
+constexpr size_t kSoT = kSoZ + al256(sizeof(uint16_t) * kFeat * kStaticSamples);
+constexpr size_t kSoStats = kSoT + al256(sizeof(float) * 4 * kStaticSamples);
+constexpr size_t kSoStatPart = kSoStats + al256(sizeof(double) * 2 * 68);
+constexpr size_t kSoKeep = kSoStatPart + al256(sizeof(double) * 65 * 256);
+constexpr size_t kSoPart = kSoKeep + al256(sizeof(uint8_t) * kStaticSamples);
+constexpr size_t kSoMaster = kSoPart + al256(sizeof(float) * (size_t)(kNumParams + 1) * kStaticBatchBlocks);
+constexpr size_t kSoM = kSoMaster + al256(sizeof(float) * kNumParams);
+constexpr size_t kSoV = kSoM + al256(sizeof(float) * kNumParams);
+constexpr size_t kSoLoss = kSoV + al256(sizeof(float) * kNumParams);
+constexpr size_t kSoMlp = kSoLoss + al256(sizeof(double) * kStaticEpochs);
+constexpr size_t kScratchBytes = kSoMlp + al256(sizeof(MlpDev));
+static_assert(kScratchBytes == AQS_STATIC_TRAIN_SCRATCH_BYTES,
+              "the header states the size of the training scratch array");
+
+// Device addresses of the array, per device, taken once with that device
+// current (the host-side name of the array is not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+aqs_status scratch_address(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(AQS_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(AQS_EHIP, "hipGetSymbolAddress of the training scratch array failed: %s",
+                  hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return AQS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+aqs_status aqs_mlp_train(const aqs_train_params* p, int64_t n, const float* feat,
+                         const float* target, const int32_t* order, aqs_mlp* model,
+                         float* loss_hist, void* stream) {
+  aqs_status st = check_train(p, n, feat, target, order, model);
+  if (st) return st;
+  const int32_t bsz = (int32_t)std::min<int64_t>(p->batch, n);
+  const int32_t maxblk = (bsz + 63) / 64;
+  TrainBufs b;
+  st = train_alloc(b, n, maxblk, p->epochs, true);
+  if (st) return st;
+  return train_run(p, n, feat, target, order, model, loss_hist, (hipStream_t)stream, b);
+}
+
+aqs_status aqs_mlp_train_static(const aqs_train_params* p, int64_t n, const float* feat,
+                                const float* target, const int32_t* order, aqs_mlp* model,
+                                float* loss_hist, void* stream) {
+  aqs_status st = check_train(p, n, feat, target, order, model);
+  if (st) return st;
+  if (n > kStaticSamples || std::min<int64_t>(p->batch, n) > AQS_STATIC_TRAIN_MAX_BATCH ||
+      p->epochs > kStaticEpochs)
+    return fail(AQS_ECAPACITY,
+                "aqs_mlp_train_static holds at most %lld samples, batches of %d and %lld epochs "
+                "(asked: %lld, %d, %d)",
+                (long long)kStaticSamples, AQS_STATIC_TRAIN_MAX_BATCH, (long long)kStaticEpochs,
+                (long long)n, p->batch, p->epochs);
+  void* base = nullptr;
+  st = scratch_address(&base);
+  if (st) return st;
+  char* w = static_cast<char*>(base);
+  TrainPtrs b;
+  b.z = reinterpret_cast<uint16_t*>(w + kSoZ);
+  b.t = reinterpret_cast<float*>(w + kSoT);
+  b.stats = reinterpret_cast<double*>(w + kSoStats);
+  b.stat_part = reinterpret_cast<double*>(w + kSoStatPart);
+  b.keep = reinterpret_cast<uint8_t*>(w + kSoKeep);
+  b.part = reinterpret_cast<float*>(w + kSoPart);
+  b.master = reinterpret_cast<float*>(w + kSoMaster);
+  b.m = reinterpret_cast<float*>(w + kSoM);
+  b.v = reinterpret_cast<float*>(w + kSoV);
+  b.loss = reinterpret_cast<double*>(w + kSoLoss);
+  b.mlp = reinterpret_cast<MlpDev*>(w + kSoMlp);
+  return train_run(p, n, feat, target, order, model, loss_hist, (hipStream_t)stream, b);
 }
 
 aqs_status aqs_mlp_gradients(const aqs_mlp* model, int64_t n, const float* feat,

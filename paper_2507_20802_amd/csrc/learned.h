@@ -129,5 +129,8 @@ void launch_train_batch(const TrainArgs& a, hipStream_t s);
 void launch_train_update(const TrainArgs& a, hipStream_t s);
 // BF16 copies and biases of the device network from the FP32 masters
 void launch_mlp_sync(const float* master, MlpDev* mlp, hipStream_t s);
+// words 32-bit zeros from p on (a kernel, not a memset node, so that the call
+// may sit in a captured stream)
+void launch_zero_words(uint32_t* p, int64_t words, hipStream_t s);
 
 }  // namespace aqs

@@ -16,6 +16,7 @@
 // (i = 0..3).  Operands are stored "k contiguous" so every fragment is one
 // 16-byte load.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include "kernels.h"
 #include "learned.h"
@@ -866,7 +867,19 @@ __global__ __launch_bounds__(kBlock) void k_mlp_sync(const float* master, MlpDev
   if (p < kNumParams) sync_param(p, master[p], M);
 }
 
+__global__ __launch_bounds__(kBlock) void k_zero_words(uint32_t* p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * kBlock)
+    p[i] = 0u;
+}
+
 }  // namespace
+
+void launch_zero_words(uint32_t* p, int64_t words, hipStream_t s) {
+  if (words <= 0) return;
+  const int64_t nb = std::min<int64_t>((words + kBlock - 1) / kBlock, 1024);
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)nb), dim3(kBlock), 0, s, p, words);
+}
 
 void launch_ldesc(const LearnArgs& a, int32_t ntiles, int32_t dim, hipStream_t s) {
   if (ntiles <= 0) return;

@@ -94,10 +94,12 @@ def _check_dev(t, dtype, shape=None):
         raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
 
 
-def train(model: aqs_mlp, feat, target, orders, params: TrainParams | None = None) -> np.ndarray:
+def train(model: aqs_mlp, feat, target, orders, params: TrainParams | None = None,
+          static: bool = False) -> np.ndarray:
     """Train model in place on the GPU.  feat: (n, 64) float32 device tensor,
     target: (n, dim) float32, orders: (epochs, n) int32 (one sample order per
-    epoch).  Returns the mean batch loss of every epoch."""
+    epoch).  static: through aqs_mlp_train_static (no device allocation; at
+    most 65536 samples).  Returns the mean batch loss of every epoch."""
     import torch
     lib = _lib.load()
     params = params or TrainParams(epochs=int(orders.shape[0]))
@@ -107,10 +109,11 @@ def train(model: aqs_mlp, feat, target, orders, params: TrainParams | None = Non
     _check_dev(orders, torch.int32, (params.epochs, n))
     hist = np.zeros(params.epochs, dtype=np.float32)
     cp = params.to_c()
-    check(lib.aqs_mlp_train(ctypes.byref(cp), n, ctypes.c_void_p(feat.data_ptr()),
-                            ctypes.c_void_p(target.data_ptr()), ctypes.c_void_p(orders.data_ptr()),
-                            ctypes.byref(model), hist.ctypes.data_as(_lib.c_float_p), _stream_ptr(feat)),
-          "aqs_mlp_train")
+    name = "aqs_mlp_train_static" if static else "aqs_mlp_train"
+    check(getattr(lib, name)(ctypes.byref(cp), n, ctypes.c_void_p(feat.data_ptr()),
+                             ctypes.c_void_p(target.data_ptr()), ctypes.c_void_p(orders.data_ptr()),
+                             ctypes.byref(model), hist.ctypes.data_as(_lib.c_float_p), _stream_ptr(feat)),
+          name)
     return hist
 
 
