@@ -23,12 +23,16 @@ import oracle as O  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# (name, dim, n, seed words)
+# (name, dim, n, seed words); the paper's sample uses its own potential and
+# cell (Sec. 2.2, aqs_synth.paper_sample_start)
 GLASSES = [
     ("glass2d_256", 2, 256, (1, 0)),
     ("glass2d_1000", 2, 1000, (11, 0)),
     ("glass2d_1000b", 2, 1000, (11, 1)),
     ("glass3d_1500", 3, 1500, (13, 0)),
+    ("glass2d_4096", 2, 4096, (12, 0)),
+    ("glass3d_8192", 3, 8192, (14, 0)),
+    ("paper2d_400", 2, 400, (15, 0)),
 ]
 
 QUENCH = O.FireParams(dt0=0.005, dt_max=0.03, f_dec=0.9, alpha0=0.2, f_alpha=0.95, n_delay=5,
@@ -37,13 +41,16 @@ QUENCH = O.FireParams(dt0=0.005, dt_max=0.03, f_dec=0.9, alpha0=0.2, f_alpha=0.9
 
 def make(name, dim, n, seed):
     path = os.path.join(HERE, name + ".npz")
-    s = S.uniform_glass_start(dim, n, *seed)
+    if name.startswith("paper"):
+        s, pot = S.paper_sample_start(*seed), O.paper_binary()
+    else:
+        s, pot = S.uniform_glass_start(dim, n, *seed), O.kob_andersen()
     H = O.box_matrix(dim, s.L, 0.0)
     t = time.time()
-    r = O.fire(s.pos, s.types, H, O.kob_andersen(), QUENCH)
+    r = O.fire(s.pos, s.types, H, pot, QUENCH)
     if r.status != O.CONVERGED:
         raise RuntimeError(f"{name}: quench did not converge (status {r.status})")
-    fmax = O.max_force(r.pos, s.types, H, O.kob_andersen())
+    fmax = O.max_force(r.pos, s.types, H, pot)
     assert fmax < 1e-10, fmax
     np.savez(path, pos=r.pos, types=s.types, L=s.L, dim=dim, energy=r.E, iters=r.iters,
              seed=np.array(seed))

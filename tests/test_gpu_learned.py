@@ -94,7 +94,9 @@ def test_inference_matches_bf16_oracle(name):
     scale = np.abs(ref).max()
     err = np.abs(got - ref)
     print("inference max err / scale", err.max() / scale, "median", np.median(err) / scale)
-    assert err.max() <= 2e-3 * scale
+    # sums in another order can round a hidden activation to the neighbouring
+    # BF16 value (2^-8 relative) now and then; measured 1.2e-4 to 2.4e-4
+    assert err.max() <= 1e-3 * scale
     assert np.median(err) <= 1e-5 * scale
 
 
@@ -118,8 +120,11 @@ def test_gradients_match_bf16_oracle(dim, n):
     assert abs(loss - loss_ref) <= 1e-5 * abs(loss_ref)
     for k in Lr.MLP.PARAMS:
         rel = np.linalg.norm(g[k] - g_ref[k]) / np.linalg.norm(g_ref[k])
-        print(k, rel)
+        # element by element, against the largest gradient of the parameter
+        elem = np.abs(g[k] - g_ref[k]).max() / np.abs(g_ref[k]).max()
+        print(k, "norm", rel, "element", elem)
         assert rel <= 1e-3, (k, rel)
+        assert elem <= 1e-3, (k, elem)
 
 
 def test_training_steps_match_oracle():
@@ -146,10 +151,11 @@ def test_training_steps_match_oracle():
     assert abs(hist[0] - hist_ref[0]) <= 1e-4 * abs(hist_ref[0])
     for k in Lr.MLP.PARAMS:
         d = np.abs(got[k] - getattr(m, k))
+        print(k, "max", d.max(), "share > 1e-6", np.mean(d > 1e-6), "share > 1e-5", np.mean(d > 1e-5))
         # Adam moves every weight by about lr per step; rounding can only flip
         # the sign of steps whose gradient is at the rounding level
         assert d.max() <= 6.1e-3, (k, d.max())
-        assert np.mean(d > 1e-5) < 0.01, (k, np.mean(d > 1e-5))
+        assert np.mean(d > 1e-6) < 0.02, (k, np.mean(d > 1e-6))
 
 
 def test_training_learns_and_is_deterministic():
@@ -255,3 +261,102 @@ def test_learned_start_gain_on_its_own_history():
     print(f"loss {loss[0]:.3g} -> {loss[-1]:.3g}; FIRE iterations plain {it_p} learned {it_l}; "
           f"learned starts used {used}/{nst}")
     assert used >= 1 and it_l < it_p
+
+
+def _oracle_learned_chain(pos, types, L, dim, dg, k0, nst, m, ofire):
+    """The learned start in the oracle from the inherent structure pos at
+    strain index k0: at every inherent structure the descriptors and the
+    BF16-emulating network predict u_hat, the start follows learned_start /
+    choose_start, FIRE minimises.  Returns per step (E, start code, IS)."""
+    out, x = [], pos
+    for k in range(k0 + 1, k0 + nst + 1):
+        H = O.strain_box(dim, L, k, dg)
+        raw = Lr.descriptors(x, types, O.strain_box(dim, L, k - 1, dg), POT)
+        uh = Lr.predict(raw, m, emulate=True)
+        plain, start, ok = Lr.learned_start(x, uh, dg)
+        x0, which = Lr.choose_start(plain, start, ok, types, H, POT, O.energy_forces)
+        r = O.fire(x0, types, H, POT, ofire)
+        assert r.status == O.CONVERGED
+        out.append((r.E, which, r.pos))
+        x = r.pos
+    return out
+
+
+def _oracle_mlp(arrays, dim):
+    m = Lr.mlp_from_arrays(dim, {k: arrays[k] for k in Lr.MLP.PARAMS})
+    m.feat_mean, m.feat_std = arrays["feat_mean"], arrays["feat_std"]
+    m.tgt_mean = np.zeros(3, np.float32)
+    m.tgt_std = np.ones(3, np.float32)
+    m.tgt_mean[:dim], m.tgt_std[:dim] = arrays["tgt_mean"], arrays["tgt_std"]
+    return m
+
+
+def test_learned_chain_matches_the_oracle():
+    """The network trained on the GPU (on 24 plain steps of the glass's
+    history) starts 6 fine steps on the device and in the oracle (same
+    weights, the oracle's own BF16-emulating predictions): the same start
+    decision at every step (learned or fallback, choose_start's rule),
+    energies within 1e-10 relative and the final configuration within
+    1e-8 sigma, certified by the oracle's forces."""
+    from paper_2507_20802_amd import AQS_START_FALLBACK, AQS_START_LEARNED, learned
+    from gpu_common import FTOL, POS_TOL, certified_fmax
+    torch = _torch()
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, ofire = fire_pair()
+    dg, hist_steps, nst, epochs = 1e-5, 24, 6, 200
+    eng = engine(dim, [len(types)] * 2, L, dg, fire=fire)
+    eng.set_replica(0, types, pos, 0)
+    feat, tgt, _ = learned.collect_samples(eng, 0, 1, hist_steps)
+    start_is = eng.positions(0)
+    orders = torch.from_numpy(S.epoch_orders(feat.shape[0], epochs, 310)).cuda()
+    cm = learned.make_mlp(dim, S.mlp_init(dim, 311))
+    learned.train(cm, feat, tgt, orders, learned.TrainParams(batch=256, epochs=epochs))
+    m = _oracle_mlp(learned.mlp_arrays(cm), dim)
+    # both sides continue from the history's last inherent structure
+    ref = _oracle_learned_chain(start_is, types, L, dim, dg, hist_steps, nst, m, ofire)
+    e = engine(dim, [len(types)], L, dg, fire=fire)
+    e.learned_load(cm)
+    e.set_replica(0, types, start_is, hist_steps)
+    rec = e.minimize([0], n_steps=[nst], start=AQS_START_LEARNED)[0]
+    codes = []
+    for k in range(1, nst + 1):
+        E, which, _ = ref[k - 1]
+        want = AQS_START_LEARNED if which == Lr.LEARNED else AQS_START_FALLBACK
+        codes.append(int(rec[k]["start"]))
+        assert rec[k]["status"] == 0
+        assert rec[k]["start"] == want, (k, rec[k]["start"], want)
+        assert abs(rec[k]["energy"] - E) <= E_REL_TOL * abs(E)
+    H = O.strain_box(dim, L, hist_steps + nst, dg)
+    got = e.positions(0)
+    print("start codes", codes, "final distance", O.compare(got, ref[-1][2], H)[0])
+    assert O.compare(got, ref[-1][2], H)[0] <= POS_TOL
+    assert certified_fmax(got, types, H) < FTOL
+    assert AQS_START_LEARNED in codes
+
+
+def test_broken_network_falls_back_bit_for_bit():
+    """A network whose weights are not finite predicts non-finite
+    displacements: every fine step falls back to the plain start (record
+    AQS_START_FALLBACK), and the chain is the plain chain bit for bit --
+    the same iterations, energies and final positions."""
+    from paper_2507_20802_amd import AQS_START_FALLBACK, AQS_START_LEARNED, AQS_START_PLAIN, learned
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, _ = fire_pair()
+    dg, nst = 1e-4, 4
+    arrays = S.mlp_init(dim, 312)
+    arrays["w2"] = arrays["w2"].copy()
+    arrays["w2"][3, 5] = np.nan
+    bad = learned.make_mlp(dim, arrays)
+    out = {}
+    for mode in (AQS_START_PLAIN, AQS_START_LEARNED):
+        e = engine(dim, [len(types)], L, dg, fire=fire)
+        if mode == AQS_START_LEARNED:
+            e.learned_load(bad)
+        e.set_replica(0, types, pos, 0)
+        out[mode] = (e.minimize([0], n_steps=[nst], start=mode)[0], e.positions(0))
+    rp, xp = out[AQS_START_PLAIN]
+    rl, xl = out[AQS_START_LEARNED]
+    assert np.all(rl["start"][1:] == AQS_START_FALLBACK)
+    assert np.array_equal(rl["iters"], rp["iters"])
+    assert np.array_equal(rl["energy"], rp["energy"])
+    assert np.array_equal(xl, xp)
