@@ -211,6 +211,10 @@ def main() -> int:
     ap.add_argument("--live", type=int, default=1,
                     help="live checks (1/0): checks as soon as possible, the critical chain on a stream of "
                          "its own, rejected chains stopped")
+    ap.add_argument("--live-xcds", type=int, default=None,
+                    help="live rounds: XCDs (of 8) reserved for the critical chain (0: none; default: the tuning's)")
+    ap.add_argument("--live-blocks", type=int, default=None,
+                    help="live rounds: batch force blocks per CU beside the critical chain (0: 3; < 0: no limit)")
     ap.add_argument("--tuning", choices=("default", "auto", "autotune"), default="auto",
                     help="launch knobs: the defaults, the autotuner's cache, or tune when not cached")
     ap.add_argument("--skin", type=float, default=0.3, help="Verlet skin with --tuning default")
@@ -246,6 +250,12 @@ def main() -> int:
     ref_slot = nslots              # final r_star of the plain round, for the IS comparison
     tuning = Tuning(skin=args.skin, use_graph=args.graph) if args.tuning == "default" else args.tuning
     eng = Engine(dim, [n] * (nslots + 1), s.L, dg, pot=pot, fire=Fire(), tuning=tuning)
+    if args.live_xcds is not None:
+        eng.set_live_xcds(args.live_xcds)
+        eng.tuning.live_xcds = args.live_xcds
+    if args.live_blocks is not None:
+        eng.tuning.live_batch_blocks = args.live_blocks
+        eng.set_live_batch_blocks(args.live_blocks)
     glass = parallel.layout(1, P)[0]
     t0 = time.perf_counter()
     eng.set_replica(glass.star, s.types, s.pos, 0)
@@ -392,7 +402,8 @@ def main() -> int:
                    "start_strain_index": k0,
                    "knobs": {"threads_per_atom": eng.tuning.threads_per_atom, "skin": eng.tuning.skin,
                              "block_iters": eng.tuning.block_iters, "use_graph": eng.tuning.use_graph,
-                             "source": args.tuning}},
+                             "live_batch_blocks": eng.tuning.live_batch_blocks,
+                             "live_xcds": eng.tuning.live_xcds, "source": args.tuning}},
         "computed_steps_per_s": head["computed_steps_per_s"],
         "fire_iters_per_step": head["fire_iters_per_step"],
         "all_converged": head["all_converged"],

@@ -123,6 +123,15 @@ typedef struct {
                                most this many blocks per compute unit, so that every
                                compute unit keeps room for a block of the critical
                                chain (1-4; 0 = 3; < 0 = no limit).  Changes no result. */
+  int32_t live_xcds;        /* aqs_run_round with live = 1: the critical chain's blocks run
+                               on the last live_xcds of the 8 XCDs (accelerator dies; a
+                               launch deals block b to XCD b mod 8) and the batch's on
+                               the others, so that each keeps its own compute units and
+                               L2 (0-7; 0 = no partition).  Changes no result. */
+  int32_t pad_;
+  double tile_fill;         /* force tiles (cell-row segments) hold about tile_fill times
+                               the atoms a block's lanes take at once (256 /
+                               threads_per_atom); clamped to [0.5, 2]; 0 = 0.9 */
 } aqs_tuning;
 
 /* One record per minimisation of a chain (index 0 = the first minimisation,
@@ -257,6 +266,10 @@ aqs_status aqs_set_minimizer(aqs_ctx* ctx, int32_t minimizer, const aqs_cg_param
  * default for 0) for later live rounds, e.g. from how often earlier checks
  * passed.  Changes no result. */
 aqs_status aqs_set_live_batch_blocks(aqs_ctx* ctx, int32_t blocks);
+
+/* Change the tuning field live_xcds of ctx for later live rounds (0-7,
+ * AQS_EINVAL otherwise).  Changes no result. */
+aqs_status aqs_set_live_xcds(aqs_ctx* ctx, int32_t xcds);
 
 /* Outcome of check i of a round (Algorithm 1, Sec. 3.5): the end of chain
  * i-1 against the first inherent structure of chain i, Eq. (20). */

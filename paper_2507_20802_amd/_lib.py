@@ -46,7 +46,8 @@ class aqs_tuning(ctypes.Structure):
     _fields_ = [("skin", ctypes.c_double), ("max_neighbors", ctypes.c_int32),
                 ("block_iters", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("max_chain_steps", ctypes.c_int32), ("threads_per_atom", ctypes.c_int32),
-                ("live_batch_blocks", ctypes.c_int32)]
+                ("live_batch_blocks", ctypes.c_int32), ("live_xcds", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("tile_fill", ctypes.c_double)]
 
 
 class aqs_step_record(ctypes.Structure):
@@ -111,6 +112,7 @@ SIGNATURES = {
     "aqs_energy_forces": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p, c_double_p]),
     "aqs_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "aqs_set_live_batch_blocks": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "aqs_set_live_xcds": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "aqs_set_minimizer": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(aqs_cg_params)]),
     "aqs_get_counters": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_counters), ctypes.c_int32]),
     "aqs_learned_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_mlp)]),

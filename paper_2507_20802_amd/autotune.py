@@ -2,13 +2,22 @@
 
 The knobs change how the work is laid out, never what is computed beyond
 the rounding order of one atom's force sum: lanes per atom of the force
-kernel (which also sets the force-tile length), the Verlet skin (list length
-against rebuild frequency) and the FIRE iterations launched between state
-read-backs.  For a shape (dim, atoms per slot, slots) the tuner times short
-device chains of AQS steps of a seeded glass on the GPU (coordinate descent
-from the defaults), re-checks that the winner reaches the same inherent structure
-as the defaults, and caches the result as JSON keyed by the shape bucket and
-the device name.
+kernel (which also sets the force-tile length), the force tiles' fill of a
+block, the Verlet skin (list length against rebuild frequency), the FIRE
+iterations launched between state read-backs and their replay as a
+hipGraph; for live rounds of Algorithm 1 also the compute units left to the
+critical chain (XCDs reserved for it, batch force blocks per CU).  For a
+shape (dim, atoms per slot, slots) the tuner times short device chains of
+AQS steps of a seeded glass on the GPU (coordinate descent from the
+defaults), then, with enough slots for two chains and their snapshots,
+short live rounds; it re-checks that the winner reaches the same inherent
+structure as the defaults (and the live winner the same round, bit for
+bit), and caches the result as JSON keyed by the shape bucket and the
+device name.
+
+Compile-time shapes are not knobs: the 256-thread block (four wavefronts)
+and the force kernel's five waves per SIMD are fixed by its LDS halo (31 KB,
+five blocks per CU) and its register budget.
 
 Everything it times runs in libaqs.so; this module only chooses arguments.
 """
@@ -28,8 +37,16 @@ KNOBS = {
     "threads_per_atom": (2, 1, 4),
     "skin": (0.3, 0.25, 0.35, 0.2, 0.15),
     "block_iters": (32, 16, 64),
+    "tile_fill": (0.9, 0.7, 1.2),
+    "use_graph": (0, 1),
 }
 DEFAULT = {k: v[0] for k, v in KNOBS.items()}
+# knobs of live rounds only (aqs_run_round with live checks)
+LIVE_KNOBS = {
+    "live_xcds": (0, 2, 4),
+    "live_batch_blocks": (0, -1, 2),
+}
+LIVE_DEFAULT = {k: v[0] for k, v in LIVE_KNOBS.items()}
 
 
 def bucket_key(dim: int, n_atoms: int, n_rep: int, device: str = "") -> str:
@@ -138,8 +155,43 @@ def _same_inherent_structure(dim, n, s, is_pos, knobs, dg) -> dict:
     return {"ok": bool(ok), "energy_rel": float(rel), "max_disp": float(d)}
 
 
+def _live_trial(dim, n, n_rep, s, is_pos, knobs, dg, steps):
+    """Wall time and outcome of one live round: P = (n_rep - 1) // 2 chains
+    of `steps` fine steps from the inherent structure (level-I anchors
+    steps * dg apart), checked and cancelled live."""
+    import torch
+    from . import parallel
+    P = (n_rep - 1) // 2
+    eng = Engine(dim, [n] * parallel.slots_needed(1, P), s.L, dg, fire=Fire(), tuning=tuning_of(knobs))
+    g = parallel.layout(1, P)[0]
+    eng.set_replica(g.star, s.types, is_pos, 0)
+    for i in range(P):
+        eng.copy_replica(g.star, g.chains[i])
+    eng.affine_shear(g.chains[1:], [i * steps for i in range(1, P)])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    recs, checks = eng.run_round(g.chains, [-1] + g.snaps[1:], [steps] * P, live=True)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t, (recs, checks)
+
+
+def _same_round(a, b) -> bool:
+    """Two live rounds of the same chains: the same decisions and bitwise the
+    same records of every minimisation both finished."""
+    from ._lib import AQS_CANCELLED
+    (ra, ca), (rb, cb) = a, b
+    if [c[:2] for c in ca] != [c[:2] for c in cb]:
+        return False
+    for x, y in zip(ra, rb):
+        both = (x["status"] != AQS_CANCELLED) & (y["status"] != AQS_CANCELLED)
+        if not np.array_equal(x[both], y[both]):
+            return False
+    return True
+
+
 def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 5000, repeats: int = 2, passes: int = 1,
-         dg: float = 5e-5, seed: int = 11, cache: str | None = None, log=None) -> dict:
+         dg: float = 5e-5, seed: int = 11, cache: str | None = None, log=None,
+         live_steps: int = 20) -> dict:
     """Tune the knobs for the shape, store and return the cache entry."""
     s, is_pos = _glass(dim, n_atoms, seed)
     best = dict(DEFAULT)
@@ -166,6 +218,36 @@ def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 5000, repeats: int = 2
         best, best_t = dict(DEFAULT), run(DEFAULT)
     entry = {"knobs": best, "ms": best_t * 1e3, "default_ms": run(DEFAULT) * 1e3,
              "trials": len(timed), "max_iter": iters, "parity": check}
+    if n_rep >= 5:
+        # live rounds: the critical chain's share of the GPU, on top of the
+        # batched winner
+        live, ltimed, outcome = dict(LIVE_DEFAULT), {}, {}
+
+        def run_live(kn):
+            key = json.dumps(kn, sort_keys=True)
+            if key not in ltimed:
+                res = [_live_trial(dim, n_atoms, n_rep, s, is_pos, dict(best, **kn), dg, live_steps)
+                       for _ in range(repeats)]
+                ltimed[key] = min(r[0] for r in res)
+                outcome[key] = res[0][1]
+                if log:
+                    log(f"live {kn}: {ltimed[key] * 1e3:.1f} ms")
+            return ltimed[key]
+
+        live_t = run_live(live)
+        for name, values in LIVE_KNOBS.items():
+            for v in values:
+                kn = dict(live, **{name: v})
+                t = run_live(kn)
+                if t < live_t:
+                    live, live_t = kn, t
+        same = _same_round(outcome[json.dumps(live, sort_keys=True)],
+                           outcome[json.dumps(LIVE_DEFAULT, sort_keys=True)])
+        if not same:
+            live, live_t = dict(LIVE_DEFAULT), run_live(LIVE_DEFAULT)
+        entry["knobs"] = dict(best, **live)
+        entry["live"] = {"ms": live_t * 1e3, "default_ms": run_live(LIVE_DEFAULT) * 1e3,
+                         "trials": len(ltimed), "steps": live_steps, "same_round_as_default": bool(same)}
     key = bucket_key(dim, n_atoms, n_rep, device_name())
     entries = load_cache(cache)
     entries[key] = entry

@@ -49,10 +49,20 @@ double rc_max_of(const aqs_potential* p) {
   return m;
 }
 
+// Blocks of one launch are dealt to the XCDs round robin (hardware block b
+// runs on XCD b mod 8); a launch table places each entry by that rule.
+constexpr int kXcds = 8;
+constexpr uint32_t kAllXcds = (1u << kXcds) - 1u;
+
+// force tiles hold about fill x a block's atom lanes (tuning.tile_fill)
+constexpr double kFillDefault = 0.9, kFillMin = 0.5, kFillMax = 2.0;
+
 struct Tune {
   double skin;
   int max_nb, block_iters, use_graph, log_cap, tpa;
   int live_blocks;   // batch force blocks per CU beside a critical chain (0: no limit)
+  int live_xcds;     // XCDs reserved for the critical chain of a live round (0: none)
+  double tile_fill;  // force-tile atoms per block's atom lanes
 };
 
 Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
@@ -68,6 +78,10 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   r.tpa = (tp == 1 || tp == 2 || tp == 4 || tp == 8) ? tp : 2;
   const int lb = t ? t->live_batch_blocks : 0;
   r.live_blocks = lb < 0 ? 0 : (lb == 0 ? 3 : std::min(lb, 4));
+  const int lx = t ? t->live_xcds : 0;
+  r.live_xcds = std::max(0, std::min(lx, kXcds - 1));
+  const double tf = t ? t->tile_fill : 0.0;
+  r.tile_fill = tf > 0.0 ? std::max(kFillMin, std::min(tf, kFillMax)) : kFillDefault;
   return r;
 }
 
@@ -80,13 +94,17 @@ void cell_grid(int dim, const double* L, double tilt, double rl, int* nc) {
   nc[2] = dim == 3 ? (int)std::floor(L[2] / rl) : 1;
 }
 
-// Segments per cell row of the force tiles: about 90% of a block's atom
-// lanes (kBlock / threads_per_atom) per segment on average.
-int segments_per_row(int n, int rows, int tpa) {
+// Segments per cell row of the force tiles: about `fill` times a block's
+// atom lanes (kBlock / threads_per_atom) per segment on average.
+int segments_per_row(int n, int rows, int tpa, double fill) {
   const int per = kBlock / tpa;
   const double mean_row = (double)n / rows;
-  return std::max(1, (int)std::ceil(mean_row / (0.9 * per)));
+  return std::max(1, (int)std::ceil(mean_row / (fill * per)));
 }
+
+// Entries of a launch table over n items spread over any subset of the XCDs
+// (at most kXcds (n + 1)).
+size_t table_cap(int64_t n) { return (size_t)kXcds * ((size_t)n + 1); }
 
 struct Layout {
   size_t total = 0;
@@ -139,7 +157,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
     g.cell_off = cell_off;
     // force tiles: rows x segments; rows are fixed by the grid in y, z
     g.tile_off = lo.tiles;
-    g.tile_cap = nc[1] * nc[2] * segments_per_row(n, nc[1] * nc[2], 8);
+    g.tile_cap = nc[1] * nc[2] * segments_per_row(n, nc[1] * nc[2], kMaxTPA, kFillMin);
     lo.tiles += g.tile_cap;
     lo.max_cells = std::max(lo.max_cells, g.cell_cap);
     atom_off += g.npad;
@@ -183,16 +201,16 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   for (int a = 0; a < 3; ++a) lo.o_tv[a] = take(sizeof(double) * A);
   lo.o_tid = take(sizeof(int32_t) * A);
   for (int l = 0; l < 2; ++l) {   // per driver lane
-    lo.o_tbl[l] = take(sizeof(int2) * ((size_t)lo.blocks + 8));
-    lo.o_tbl2[l] = take(sizeof(int2) * ((size_t)lo.blocks + 8));
+    lo.o_tbl[l] = take(sizeof(int2) * table_cap(lo.blocks));
+    lo.o_tbl2[l] = take(sizeof(int2) * table_cap(lo.blocks));
     lo.o_reps[l] = take(sizeof(int32_t) * n_rep);
     lo.o_sel[l] = take(sizeof(int32_t) * n_rep);
     lo.o_nc3[l] = take(sizeof(int32_t) * kGridInts * n_rep);
     lo.o_overflow[l] = take(sizeof(int32_t));
-    lo.o_ftbl[l] = take(sizeof(int2) * ((size_t)lo.tiles + 8));
-    lo.o_ttbl[l] = take(sizeof(int2) * ((size_t)lo.tiles + 8));
-    lo.o_ltbl[l] = take(sizeof(int2) * ((size_t)lo.blocks + 8));
-    lo.o_lftbl[l] = take(sizeof(int2) * ((size_t)lo.tiles + 8));
+    lo.o_ftbl[l] = take(sizeof(int2) * table_cap(lo.tiles));
+    lo.o_ttbl[l] = take(sizeof(int2) * table_cap(lo.tiles));
+    lo.o_ltbl[l] = take(sizeof(int2) * table_cap(lo.blocks));
+    lo.o_lftbl[l] = take(sizeof(int2) * table_cap(lo.tiles));
     lo.o_lsel[l] = take(sizeof(int32_t) * n_rep);
   }
   lo.o_dg = take(sizeof(double) * n_rep);
@@ -241,6 +259,7 @@ struct Lane {
   int32_t g_pad = 0;               // its force launches' dynamic LDS
   bool in_flight = false;          // a block of iterations launched, not yet polled
   bool timed = false;              // ... with HIP events around its kernels
+  uint32_t xcd_mask = kAllXcds;    // XCDs its launch tables place blocks on
   std::vector<hipEvent_t> ev;      // the lane's timing events (4 per iteration)
 };
 
@@ -391,16 +410,17 @@ LearnArgs learn_args(aqs_ctx* c, const Lane& L, int mode, float* out = nullptr) 
   return a;
 }
 
-std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, int per_block = 1);
-std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel);
+std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, uint32_t xcds,
+                             int per_block = 1);
+std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel, uint32_t xcds);
 
 // Learned (or extrapolated) start of the slots waiting in PH_LDESC (known
 // from the last state read-back): descriptors and network, or the
 // extrapolation; plain start and the checks, with launch tables over exactly
 // those slots.
 aqs_status learned_group(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls, bool extrap) {
-  const std::vector<int2> tb = make_table(c, ls);
-  const std::vector<int2> ft = make_tile_table(c, ls);
+  const std::vector<int2> tb = make_table(c, ls, L.xcd_mask);
+  const std::vector<int2> ft = make_tile_table(c, ls, L.xcd_mask);
   std::copy(tb.begin(), tb.end(), L.h_ltbl);
   std::copy(ft.begin(), ft.end(), L.h_lftbl);
   std::copy(ls.begin(), ls.end(), L.h_lsel);
@@ -424,39 +444,47 @@ aqs_status learned_group(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls, bo
   return AQS_OK;
 }
 
-// Launch table over the blocks of the given slots, in an order that gives
-// each of the 8 XCDs (hardware block b runs on XCD b mod 8) a contiguous run
-// of blocks, so neighbouring tiles share that XCD's L2.
-std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, int per_block) {
-  std::vector<int2> logical;
-  for (int r : sel) {
-    const Geom& g = c->lo.geom[r];
-    for (int b = 0; b < g.nblocks * per_block; ++b) logical.push_back(make_int2(r, b));
+// Launch table of the items `logical` on the XCDs of the mask: position b
+// (hardware block b, on XCD b mod 8) holds an item only if that XCD is in
+// the mask, and each of those XCDs gets a contiguous run of items, so
+// neighbouring tiles share its L2; other positions hold slot -1 (the block
+// exits at once).
+std::vector<int2> xcd_table(const std::vector<int2>& logical, uint32_t xcds) {
+  int rank[kXcds], nx = 0;
+  for (int x = 0; x < kXcds; ++x) rank[x] = ((xcds >> x) & 1u) ? nx++ : -1;
+  if (nx == 0) {   // no XCD named: all of them
+    for (int x = 0; x < kXcds; ++x) rank[x] = x;
+    nx = kXcds;
   }
   const size_t nb = logical.size();
-  const size_t per = (nb + 7) / 8;
-  std::vector<int2> tbl(per * 8, make_int2(-1, 0));
+  const size_t per = (nb + nx - 1) / nx;
+  std::vector<int2> tbl(per * kXcds, make_int2(-1, 0));
   for (size_t b = 0; b < tbl.size(); ++b) {
-    const size_t lk = (b % 8) * per + b / 8;
+    const int xr = rank[b % kXcds];
+    if (xr < 0) continue;
+    const size_t lk = (size_t)xr * per + b / kXcds;
     if (lk < nb) tbl[b] = logical[lk];
   }
   return tbl;
 }
 
-// Launch table over the force tiles of the given slots' current grids,
-// XCD-contiguous.
-std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel) {
+// Launch table over the 256-atom blocks of the given slots.
+std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, uint32_t xcds,
+                             int per_block) {
+  std::vector<int2> logical;
+  for (int r : sel) {
+    const Geom& g = c->lo.geom[r];
+    for (int b = 0; b < g.nblocks * per_block; ++b) logical.push_back(make_int2(r, b));
+  }
+  return xcd_table(logical, xcds);
+}
+
+// Launch table over the force tiles of the given slots' current grids.
+std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel, uint32_t xcds) {
   std::vector<int2> logical;
   for (int r : sel)
     for (int t = 0; t < c->tiles_now[r]; ++t) logical.push_back(make_int2(r, t));
-  const size_t nb = logical.size();
-  const size_t per = (nb + 7) / 8;
-  std::vector<int2> tbl(per * 8, make_int2(-1, 0));
-  for (size_t b = 0; b < tbl.size(); ++b) {
-    const size_t lk = (b % 8) * per + b / 8;
-    if (lk < nb) tbl[b] = logical[lk];
-  }
-  return tbl;
+  return xcd_table(logical, xcds);
 }
 
 // Host copy of every slot's state (and lane 0's overflow flag), on the
@@ -533,7 +561,7 @@ aqs_status rebuild(aqs_ctx* c, Lane& L, const std::vector<int32_t>& sel, bool in
       return fail(AQS_EINVAL, "slot %d: cell grid exceeds capacity", r);
     int32_t* q = &nc3[kGridInts * i];
     for (int a = 0; a < 3; ++a) q[a] = nc[a];
-    q[3] = segments_per_row(g.n, nc[1] * nc[2], c->tn.tpa);
+    q[3] = segments_per_row(g.n, nc[1] * nc[2], c->tn.tpa, c->tn.tile_fill);
     q[4] = q[3] * nc[1] * nc[2];
     if (q[4] > g.tile_cap) return fail(AQS_EINVAL, "slot %d: force tiles exceed capacity", r);
     q[5] = list_mode;
@@ -543,8 +571,8 @@ aqs_status rebuild(aqs_ctx* c, Lane& L, const std::vector<int32_t>& sel, bool in
         L.ftable_stale = true;
     }
   }
-  std::vector<int2> tbl = make_table(c, sel);
-  std::vector<int2> ttbl = make_tile_table(c, sel);
+  std::vector<int2> tbl = make_table(c, sel, L.xcd_mask);
+  std::vector<int2> ttbl = make_tile_table(c, sel, L.xcd_mask);
   std::copy(tbl.begin(), tbl.end(), L.h_tbl2);
   std::copy(ttbl.begin(), ttbl.end(), L.h_ttbl);
   HIPCHK(hipMemcpyAsync(L.ttbl, L.h_ttbl, sizeof(int2) * ttbl.size(), hipMemcpyHostToDevice, L.s));
@@ -648,8 +676,8 @@ aqs_status launch_block(aqs_ctx* c, Lane& L, const IterArgs& a, int M) {
 }
 
 aqs_status set_table(aqs_ctx* c, Lane& L, const std::vector<int32_t>& sel) {
-  std::vector<int2> tbl = make_table(c, sel);
-  std::vector<int2> ftbl = make_tile_table(c, sel);
+  std::vector<int2> tbl = make_table(c, sel, L.xcd_mask);
+  std::vector<int2> ftbl = make_tile_table(c, sel, L.xcd_mask);
   std::copy(tbl.begin(), tbl.end(), L.h_tbl);
   std::copy(ftbl.begin(), ftbl.end(), L.h_ftbl);
   HIPCHK(hipMemcpyAsync(L.tbl, L.h_tbl, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice, L.s));
@@ -1058,7 +1086,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->mlpw = at<float>(w, lo.o_mlpw);
   c->tord = at<int32_t>(w, lo.o_tord);
 
-  const size_t tcap = std::max((size_t)lo.blocks, (size_t)lo.tiles) + 16;
+  const size_t tcap = table_cap(std::max(lo.blocks, lo.tiles));
   bool pinned = hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) == hipSuccess &&
                 hipHostMalloc((void**)&c->h_dg, sizeof(double) * n_rep, hipHostMallocDefault) == hipSuccess;
   for (Lane& L : c->ln)
@@ -1267,8 +1295,8 @@ aqs_status aqs_affine_shear(aqs_ctx* c, int32_t n_sel, const int32_t* rep, const
     dg[sel[i]] = (double)dk[i] * c->lo.geom[sel[i]].dgamma;
     c->h_state[sel[i]].k += dk[i];
   }
-  std::vector<int2> tbl = make_table(c, sel);
   Lane& L = c->ln[0];
+  std::vector<int2> tbl = make_table(c, sel, L.xcd_mask);
   std::copy(tbl.begin(), tbl.end(), L.h_tbl2);
   std::copy(dg.begin(), dg.end(), c->h_dg);
   HIPCHK(hipMemcpyAsync(L.tbl2, L.h_tbl2, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
@@ -1348,6 +1376,20 @@ aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int3
   // after it.
   Lane& C = c->ln[1];
   if (!C.s) HIPCHK(hipStreamCreateWithFlags(&C.s, hipStreamNonBlocking));
+  c->live = true;
+  struct LiveOff {
+    aqs_ctx* c;
+    ~LiveOff() {
+      c->live = false;
+      for (Lane& L : c->ln) L.xcd_mask = kAllXcds;
+    }
+  } live_off{c};
+  if (c->tn.live_xcds > 0) {
+    // the critical chain's blocks on the last live_xcds XCDs, the batch's on
+    // the others: each keeps its own compute units and L2
+    C.xcd_mask = kAllXcds & ~((1u << (kXcds - c->tn.live_xcds)) - 1u);
+    B.xcd_mask = kAllXcds & ~C.xcd_mask;
+  }
   st = set_table(c, C, std::vector<int32_t>{chain[0]});
   if (st) return st;
   st = set_table(c, B, std::vector<int32_t>(chain + 1, chain + P));
@@ -1357,11 +1399,6 @@ aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int3
     HIPCHK(hipGetLastError());
   }
   int next = 1;   // next check
-  c->live = true;
-  struct LiveOff {
-    aqs_ctx* c;
-    ~LiveOff() { c->live = false; }
-  } live_off{c};
   for (;;) {
     for (Lane* L : {&C, &B})
       if (!L->in_flight && lane_active(c, *L)) {
@@ -1566,6 +1603,13 @@ aqs_status aqs_set_live_batch_blocks(aqs_ctx* c, int32_t blocks) {
   if (!c) return fail(AQS_EINVAL, "null context");
   c->tn.live_blocks = blocks < 0 ? 0 : (blocks == 0 ? 3 : std::min(blocks, 4));
   c->live_pad = -1;   // recomputed for the new limit at the next live launch
+  return AQS_OK;
+}
+
+aqs_status aqs_set_live_xcds(aqs_ctx* c, int32_t xcds) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (xcds < 0 || xcds >= kXcds) return fail(AQS_EINVAL, "live_xcds %d outside [0, %d]", xcds, kXcds - 1);
+  c->tn.live_xcds = xcds;
   return AQS_OK;
 }
 

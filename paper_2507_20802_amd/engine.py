@@ -102,6 +102,8 @@ class Tuning:
     max_chain_steps: int = 1024
     threads_per_atom: int = 0
     live_batch_blocks: int = 0   # live rounds: batch force blocks per CU (0: 3; < 0: no limit)
+    live_xcds: int = 0           # live rounds: XCDs reserved for the critical chain (0: none)
+    tile_fill: float = 0.0       # force-tile atoms per block's atom lanes (0: 0.9)
 
     def to_c(self) -> aqs_tuning:
         t = aqs_tuning()
@@ -112,6 +114,8 @@ class Tuning:
         t.max_chain_steps = self.max_chain_steps
         t.threads_per_atom = self.threads_per_atom
         t.live_batch_blocks = self.live_batch_blocks
+        t.live_xcds = self.live_xcds
+        t.tile_fill = self.tile_fill
         return t
 
 
@@ -330,6 +334,11 @@ class Engine:
         """Batch force blocks per CU beside the critical chain of later live
         rounds (0: the default, 3; < 0: no limit); changes no result."""
         check(self._lib.aqs_set_live_batch_blocks(self._ctx, int(blocks)), "aqs_set_live_batch_blocks")
+
+    def set_live_xcds(self, xcds: int) -> None:
+        """XCDs of the 8 reserved for the critical chain of later live rounds
+        (0: no partition); changes no result."""
+        check(self._lib.aqs_set_live_xcds(self._ctx, int(xcds)), "aqs_set_live_xcds")
 
     def set_profiling(self, every_nth_block: int) -> None:
         check(self._lib.aqs_set_profiling(self._ctx, int(every_nth_block)), "aqs_set_profiling")

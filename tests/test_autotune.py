@@ -48,3 +48,17 @@ def test_tuning_run_picks_a_checked_winner(tmp_path):
         assert eng.tuning.skin == entry["knobs"]["skin"]
     finally:
         del os.environ["AQS_TUNE_CACHE"]
+
+
+@pytest.mark.gpu
+def test_live_tuning_keeps_the_round(tmp_path):
+    """With slots for two chains and their snapshots the tuner also times
+    live rounds over the critical chain's share of the GPU; the winner makes
+    the same decisions and minimisations as the default."""
+    path = str(tmp_path / "tune.json")
+    entry = A.tune(2, 1000, 5, iters=400, repeats=1, cache=path, live_steps=3)
+    assert entry["parity"]["ok"] and entry["live"]["same_round_as_default"]
+    for k, v in entry["knobs"].items():
+        assert v in (A.KNOBS.get(k) or A.LIVE_KNOBS[k])
+    assert set(A.LIVE_KNOBS) <= set(entry["knobs"])
+    assert entry["live"]["ms"] <= entry["live"]["default_ms"] * 1.0001

@@ -211,18 +211,19 @@ def test_live_round_equals_batched_round(delta_eq):
 
 def test_live_cu_reservation_changes_no_result():
     """The batch's force launches yield compute units to the critical chain
-    during live rounds (live_batch_blocks); with no limit, the default and
-    the tightest limit the decisions, every minimisation both runs finished
-    and the ends of the chains that ran to completion are bitwise the same.  3D slots, so that the force launches
-    fill the GPU."""
+    during live rounds (live_batch_blocks), or the two take separate XCDs
+    (live_xcds: only the launch tables change); with no limit, the default,
+    the tightest limit and two partitions the decisions, every minimisation
+    both runs finished and the ends of the chains that ran to completion are
+    bitwise the same.  3D slots, so that the force launches fill the GPU."""
     from paper_2507_20802_amd import Engine, Tuning, parallel
     pos, types, L, dim = load_glass("glass3d_1500")
     fire, _ = fire_pair()
     P, K, dg = 4, 5, 1e-3
     out = []
-    for blocks in (-1, 0, 1):
+    for blocks, xcds in ((-1, 0), (0, 0), (1, 0), (0, 2), (-1, 4)):
         eng = Engine(dim, [len(types)] * parallel.slots_needed(1, P), L, dg, fire=fire,
-                     tuning=Tuning(live_batch_blocks=blocks))
+                     tuning=Tuning(live_batch_blocks=blocks, live_xcds=xcds))
         g = parallel.layout(1, P)[0]
         eng.set_replica(g.star, types, pos, 0)
         recs, checks = _round(eng, g, P, K, K, 1e-4, live=True)

@@ -45,9 +45,10 @@ def test_workspace_grows_with_the_slots():
 
 def test_workspace_of_the_benchmark_shape():
     """33 slots of the 3D N = 32768 glass (sixteen chains, their snapshots and
-    r_star): about 1.9 GB (the word and packed neighbour lists, 6 bytes per
-    entry, are 1.25 GB of it), 0.7 % of the GPU's 288 GB."""
+    r_star): about 2.1 GB (the word and packed neighbour lists, 6 bytes per
+    entry, are 1.25 GB of it; the compact halos of force tiles sized for the
+    smallest tile fill, 0.36 GB), 0.7 % of the GPU's 288 GB."""
     L = (32768 / 1.2) ** (1.0 / 3.0)
     nbytes, _ = _ws(3, [32768] * 33, [[L] * 3] * 33)
     lists = 33 * 32768 * 192 * 6
-    assert lists < nbytes < lists + 0.8e9
+    assert lists < nbytes < lists + 1.0e9
