@@ -8,14 +8,17 @@ AQS steps train the learned start.  One "step" is one round of Algorithm 1
 (Sec. 3.5) with P = 16 level-II chains of K = 200 fine AQS steps at
 dgamma = 5e-5 (level-I anchors at i * 1e-2), every minimisation run by FIRE
 to max|F| < 1e-10, the learned start with live checks (the headline form).
+A stress drop in the chain a check waits on (a plastic event) stops the
+chains after it before that check, which then counts as failed (--abandon).
 Each step starts from the same inherent structure (already in HBM); the
 accepted steps of a round are q of Algorithm 1 (at least K), the computed
 ones P * K plus the anchor minimisations.
 
 Beside the timed steps: a few rounds of the plain start (learned vs plain),
 conventional sequential AQS of the same K steps from the same structure (the
-C^(S) of Eq. 21, for the speed-up S), and on request the extrapolated start,
-conjugate gradients and the batched round without live checks.
+C^(S) of Eq. 21, for the speed-up S), one round with live checks but no
+abandonment, and on request the extrapolated start, conjugate gradients and
+the batched round without live checks.
 
 Prints one JSON line: accepted AQS steps/s (value), FIRE iterations per AQS
 step, the roofline of the dominant kernel (the FP64 force kernel, timed with
@@ -204,8 +207,12 @@ def main() -> int:
                     help="rounds of the plain-start form timed beside the headline (0: none)")
     ap.add_argument("--sequential", type=int, default=1,
                     help="time conventional sequential AQS of the same K steps (1/0), Eq. 21's C^(S)")
-    ap.add_argument("--forms", default="",
-                    help="extra forms, comma-separated: extrapolated, cg, batched (one round each)")
+    ap.add_argument("--abandon", type=int, default=1,
+                    help="live rounds: a stress drop (plastic event) in the critical chain stops the chains "
+                         "after it before their check (1/0)")
+    ap.add_argument("--forms", default="live1",
+                    help="extra forms, comma-separated: live1 (live checks without abandonment), "
+                         "extrapolated, cg, batched (one round each)")
     ap.add_argument("--only-plain", action="store_true", help="headline with the plain start (no network)")
     ap.add_argument("--graph", type=int, default=0, help="replay iteration blocks as hipGraphs (1/0)")
     ap.add_argument("--live", type=int, default=1,
@@ -232,7 +239,7 @@ def main() -> int:
         return 2
     extra = [f for f in args.forms.split(",") if f]
     for f in extra:
-        if f not in ("extrapolated", "cg", "batched"):
+        if f not in ("live1", "extrapolated", "cg", "batched"):
             print(f"unknown form {f}", file=sys.stderr)
             return 2
 
@@ -277,22 +284,22 @@ def main() -> int:
     is_pos = eng.positions(glass.star)
     nb = in_cutoff_neighbours(is_pos, s.types, s.L, pot)   # the box is still orthogonal to 1e-3
 
-    def one_round(Kr, start, live):
+    def one_round(Kr, start, live, abandon):
         eng.set_replica(glass.star, s.types, is_pos, k0)
         g = parallel.layout(1, P)[0]
         torch.cuda.synchronize()
         t = time.perf_counter()
-        out = parallel.run(eng, [g], P * Kr, Kr, P, start=start, max_rounds=1, live=live)
+        out = parallel.run(eng, [g], P * Kr, Kr, P, start=start, max_rounds=1, live=live, abandon=abandon)
         torch.cuda.synchronize()
         return time.perf_counter() - t, out, g
 
-    def timed_form(name, start, live, mz, rounds):
+    def timed_form(name, start, live, mz, rounds, abandon):
         eng.set_minimizer(mz, Cg() if mz == "cg" else None)
         eng.counters(reset=True)
         eng.set_profiling(args.profile_every)
         tot_t, acc, comp, iters, ok, rr, starts = 0.0, 0, 0, [], True, [], []
         for _ in range(rounds):
-            dt, out, g = one_round(K, start, live)
+            dt, out, g = one_round(K, start, live, abandon)
             tot_t += dt
             acc += out["accepted_steps"]
             comp += out["computed_steps"]
@@ -300,7 +307,9 @@ def main() -> int:
             starts.extend(g.step_starts)
             ok = ok and out["statuses_ok"]
             rr.append({"wall_s": dt, "accepted": out["accepted_steps"], "computed": out["computed_steps"],
-                       "decisions": [d.equal for d in g.decisions], "anchor_iters": g.anchor_iters})
+                       "decisions": [d.equal for d in g.decisions],
+                       "predicted": [bool(np.isnan(d.max_disp)) for d in g.decisions],
+                       "anchor_iters": g.anchor_iters})
             log(f"{name} round {len(rr)}/{rounds}: {dt:.2f} s, {out['accepted_steps']} accepted")
         eng.set_profiling(0)
         eng.set_minimizer("fire")
@@ -312,18 +321,19 @@ def main() -> int:
                "all_converged": bool(ok), "per_round": rr, "counters": eng.counters(),
                "starts": {"plain": starts.count(0), "learned": starts.count(1),
                           "fallback": starts.count(2), "extrapolated": starts.count(3)},
-               "live_checks": bool(live), "minimizer": mz}
+               "live_checks": bool(live), "abandon": bool(abandon and live), "minimizer": mz}
         log(f"{name}: {res['value']:.2f} accepted AQS steps/s, {res['ms_per_step']:.0f} ms per round, "
             f"{res['fire_iters_per_step']['mean']:.0f} iterations per step")
         return res
 
     live = bool(args.live)
+    abandon = bool(args.abandon) and live
     head_start = AQS_START_PLAIN if args.only_plain else AQS_START_LEARNED
     # warmup: short rounds of the headline form
     for w in range(args.warmup):
-        dt, _, _ = one_round(args.warmup_K, head_start, live)
+        dt, _, _ = one_round(args.warmup_K, head_start, live, abandon)
         log(f"warmup round {w + 1}/{args.warmup} (K={args.warmup_K}): {dt:.2f} s")
-    head = timed_form("headline", head_start, live, "fire", args.steps)
+    head = timed_form("headline", head_start, live, "fire", args.steps, abandon)
     eng.copy_replica(glass.star, ref_slot)                       # r_star after the headline round
 
     def star_vs_headline():
@@ -335,11 +345,13 @@ def main() -> int:
         return {"equal": bool(eq), "max_disp": md, "de_per_atom": de}
     forms = {}
     if args.plain_rounds > 0 and not args.only_plain:
-        forms["plain"] = timed_form("plain", AQS_START_PLAIN, live, "fire", args.plain_rounds)
+        forms["plain"] = timed_form("plain", AQS_START_PLAIN, live, "fire", args.plain_rounds, abandon)
         forms["plain"]["final_star_vs_headline"] = star_vs_headline()
     for f in extra:
-        st = {"extrapolated": AQS_START_EXTRAPOLATED, "cg": AQS_START_PLAIN, "batched": head_start}[f]
-        forms[f] = timed_form(f, st, live and f != "batched", "cg" if f == "cg" else "fire", 1)
+        st = {"live1": head_start, "extrapolated": AQS_START_EXTRAPOLATED, "cg": AQS_START_PLAIN,
+              "batched": head_start}[f]
+        forms[f] = timed_form(f, st, live and f != "batched", "cg" if f == "cg" else "fire", 1,
+                              abandon and f not in ("live1", "batched"))
         forms[f]["final_star_vs_headline"] = star_vs_headline()
     seq = None
     if args.sequential:
@@ -397,8 +409,10 @@ def main() -> int:
                                f"K={K} fine AQS steps, dgamma={dg:g}, dgamma_c={K * dg:g}, FIRE to max|F|<1e-10, "
                                + ("plain start" if args.only_plain else
                                   f"learned start trained on the glass's first {args.train_steps} plain steps")
-                               + (", live checks" if live else ", batched checks"),
+                               + (", live checks" if live else ", batched checks")
+                               + (", speculation stopped at a stress drop of the critical chain" if abandon else ""),
                    "dim": dim, "n_atoms": n, "P": P, "K": K, "dgamma": dg, "live_checks": live,
+                   "abandon_on_stress_drop": abandon,
                    "start_strain_index": k0,
                    "knobs": {"threads_per_atom": eng.tuning.threads_per_atom, "skin": eng.tuning.skin,
                              "block_iters": eng.tuning.block_iters, "use_graph": eng.tuning.use_graph,
@@ -415,6 +429,8 @@ def main() -> int:
         "learned_vs_plain": comparison,
         "sequential": seq,
         "speedup_vs_sequential": None if seq is None else head["value"] / seq["value"],
+        "speedup_vs_sequential_live1": None if seq is None or "live1" not in forms
+        else forms["live1"]["value"] / seq["value"],
         "extra_forms": {f: {k: v for k, v in forms[f].items() if k != "counters"} for f in extra},
         "quench_s": quench_s,
         "mean_neighbours_in_cutoff": nb,

@@ -274,7 +274,8 @@ aqs_status aqs_set_live_xcds(aqs_ctx* ctx, int32_t xcds);
 /* Outcome of check i of a round (Algorithm 1, Sec. 3.5): the end of chain
  * i-1 against the first inherent structure of chain i, Eq. (20). */
 typedef struct {
-  int32_t decided;     /* 1: evaluated; 0: not reached (a check before it failed) */
+  int32_t decided;     /* 1: evaluated; 0: not reached (a check before it failed);
+                          2: not evaluated, predicted to fail (live = 2) */
   int32_t equal;       /* max_disp < delta_eq */
   double max_disp;     /* max over atom ids of the minimum-image distance */
   double de_per_atom;  /* (E_end(i-1) - E_first(i)) / N */
@@ -299,6 +300,15 @@ typedef struct {
  * (aqs_tuning.live_batch_blocks, aqs_set_live_batch_blocks).  Decisions,
  * accepted steps and every kept inherent structure are those of live = 0
  * (the minimisations do not depend on which slots share a launch).
+ * live = 2: as live = 1, and a fine step of the critical chain whose
+ * inherent structure carries less shear stress sigma_xy than the step before
+ * (a plastic event: an elastic branch under growing shear only gains stress)
+ * predicts that the check on that chain's end fails, as the paper's
+ * conclusion asks to recognise mispredictions beforehand: the chains after it
+ * are stopped at once (check decided = 2, equal = 0) and the critical chain
+ * runs on alone.  Every accepted step is still a step of sequential AQS from
+ * the verified structure; the round may accept fewer steps than with live =
+ * 1 (when the predicted check would have passed).
  *
  * chain[P], snap[P] (snap[0] unused), n_steps[P]: host arrays; distinct slots
  * of equal atom count.  records: host, P x (max n_steps + 1), as in

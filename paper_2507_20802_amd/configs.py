@@ -11,7 +11,10 @@
           batch with graph-replayed iteration blocks and tuned knobs;
 * paper   the paper's benchmark problem (Sec. 2.2: 2D, N = 400, Eqs. 14-15,
           dgamma = 1/200, 200 steps) for many samples at once: every sample's
-          sequential AQS in one batch, against one sample alone.
+          sequential AQS in one batch, against one sample alone;
+* learned4 the learned start on 2D N = 4096 glasses: trained on 49 plain
+          steps of one glass, evaluated on another (iterations, accepted
+          starts, inherent-structure mismatches against the plain start).
 
 Every glass is a seeded uniform random start quenched on the device (the
 paper's samples are not available; the paper's problem uses its cell,
@@ -160,6 +163,78 @@ def paper(samples: int = 256, steps: int = 200) -> dict:
             "all_converged": bool(np.all(rec["status"] == 0)), "sample0_same_as_alone": same0}
 
 
+def learned4(train_steps: int = 49, eval_steps: int = 50, epochs: int = 50, dgamma: float = 1e-4) -> dict:
+    """The learned start on 2D N = 4096 glasses: the network is trained on
+    the GPU on train_steps plain AQS steps of one glass (49 x 4096 = 200 704
+    samples), then a second glass runs eval_steps steps from its inherent
+    structure with the plain, the learned and the extrapolated start (whole
+    chains, timed), and step by step: from every inherent structure of the
+    plain chain one learned step, compared with the plain step (Eq. 20)."""
+    import aqs_synth as S
+    import torch
+    from . import learned
+    from ._lib import AQS_START_EXTRAPOLATED, AQS_START_FALLBACK, AQS_START_LEARNED, AQS_START_PLAIN
+    n = 4096
+    tr, ev = S.uniform_glass_start(2, n, 4, 0), S.uniform_glass_start(2, n, 4, 1)
+    eng = Engine(2, [n] * 3, tr.L, dgamma, fire=Fire(), tuning="auto")
+    _quenched(eng, 0, tr)
+    _sync()
+    t = time.perf_counter()
+    feat, tgt, _ = learned.collect_samples(eng, 0, 1, train_steps)
+    orders = torch.from_numpy(S.epoch_orders(feat.shape[0], epochs, 4, 2)).cuda()
+    model = learned.make_mlp(2, S.mlp_init(2, 4, 3))
+    hist = learned.train(model, feat, tgt, orders, learned.TrainParams(batch=4096, epochs=epochs))
+    _sync()
+    t_train = time.perf_counter() - t
+    eng.learned_load(model)
+    _quenched(eng, 0, ev)
+    x0 = eng.positions(0)
+    chains = {}
+    for name, mode in (("plain", AQS_START_PLAIN), ("learned", AQS_START_LEARNED),
+                       ("extrapolated", AQS_START_EXTRAPOLATED)):
+        eng.set_replica(0, ev.types, x0, 0)
+        _sync()
+        t = time.perf_counter()
+        rec = eng.minimize([0], n_steps=[eval_steps], start=mode)[0]
+        _sync()
+        dt = time.perf_counter() - t
+        st = rec["start"][1:]
+        chains[name] = {"wall_s": dt, "aqs_steps_per_s": eval_steps / dt,
+                        "fire_iters_per_step": float(rec["iters"][1:].mean()),
+                        "predicted_starts_accepted": int(np.sum((st == AQS_START_LEARNED) |
+                                                                (st == AQS_START_EXTRAPOLATED))),
+                        "fallbacks": int(np.sum(st == AQS_START_FALLBACK)),
+                        "all_converged": bool(np.all(rec["status"] == 0)),
+                        "final": eng.positions(0)}
+    # step by step from the plain chain's inherent structures
+    eng.set_replica(0, ev.types, x0, 0)
+    mism, accepted, dists, it_p, it_l = 0, 0, [], 0, 0
+    for k in range(eval_steps):
+        eng.copy_replica(0, 1)
+        rp = eng.minimize([0], n_steps=[1])[0, 1]
+        rl = eng.minimize([1], n_steps=[1], start=AQS_START_LEARNED)[0, 1]
+        eq, md, _ = eng.compare(0, 1, 1e-4)
+        mism += int(not eq)
+        accepted += int(rl["start"] == AQS_START_LEARNED)
+        dists.append(md)
+        it_p += int(rp["iters"])
+        it_l += int(rl["iters"])
+    same = {}
+    for name in ("learned", "extrapolated"):
+        eng.set_replica(1, ev.types, chains[name].pop("final"), eval_steps)
+        eng.set_replica(2, ev.types, chains["plain"]["final"], eval_steps)
+        same[name] = bool(eng.compare(1, 2, 1e-4)[0])
+    chains["plain"].pop("final")
+    return {"config": "learned4", "workload": f"2D N={n}: network trained on {train_steps} plain AQS steps "
+            f"({feat.shape[0]} samples, {epochs} epochs) of one glass, evaluated on {eval_steps} steps of "
+            f"another, dgamma={dgamma:g}, FIRE to max|F|<1e-10",
+            "train_s": t_train, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+            "chains": chains, "final_is_equal_to_plain": same,
+            "stepwise": {"steps": eval_steps, "learned_accepted": accepted, "is_mismatches": mism,
+                         "fire_iters_plain": it_p, "fire_iters_learned": it_l,
+                         "max_distance": float(max(dists))}}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("configs", nargs="*", default=["small", "batch2d", "uneven", "paper"])
@@ -169,7 +244,7 @@ def main(argv=None) -> int:
     import torch
     torch.cuda.set_device(0)
     runs = {"small": small, "batch2d": batch2d, "uneven": uneven,
-            "paper": lambda: paper(args.paper_samples, args.paper_steps)}
+            "paper": lambda: paper(args.paper_samples, args.paper_steps), "learned4": learned4}
     for name in args.configs:
         print(json.dumps(runs[name]()), flush=True)
     return 0

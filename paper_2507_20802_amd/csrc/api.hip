@@ -343,6 +343,7 @@ IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   a.nsel = (int32_t)L.cur_sel.size();
   a.tpa = c->tn.tpa;
   a.lds_pad = batch_pad(c, L);
+  a.prio = (c->live && &L == &c->ln[1]) ? 1 : 0;
   a.geom = c->d_geom;
   a.state = c->d_state;
   a.pos4 = c->pos4;
@@ -757,6 +758,8 @@ aqs_status start_chains(aqs_ctx* c, const std::vector<int32_t>& sel, int32_t sta
     s.do_snap = 0;
     s.start_mode = start_mode;
     s.start_used = AQS_START_PLAIN;
+    s.drops = 0;
+    s.sxy_prev = 0.0;
   }
   return push_state(c);
 }
@@ -1349,6 +1352,8 @@ aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int3
   if (st) return st;
   std::vector<char> cancelled(P, 0);
   Lane& B = c->ln[0];
+  if (live < 0 || live > 2) return fail(AQS_EINVAL, "live must be 0, 1 or 2 (got %d)", live);
+  const bool abandon = (live == 2);
   if (!live || P == 1) {
     // all chains to completion on the context stream, then the checks in order
     st = set_table(c, B, sel);
@@ -1423,6 +1428,30 @@ aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int3
     int active = 0;
     st = lane_poll(c, *done, false, active);
     if (st) return st;
+    // a plastic event in the critical chain, still running, predicts that
+    // the check on its end fails: the chains after it are stopped now (once
+    // the chain is done, the check itself is taken below)
+    if (abandon && next < P && done == &C && c->h_state[chain[next - 1]].drops > 0 &&
+        c->h_state[chain[next - 1]].phase != PH_DONE) {
+      if (B.in_flight) {
+        HIPCHK(hipStreamSynchronize(B.s));
+        st = lane_poll(c, B, false, active);
+        if (st) return st;
+      }
+      std::vector<int32_t> stop;
+      for (int j = next; j < P; ++j)
+        if (c->h_state[chain[j]].phase != PH_DONE) {
+          c->h_state[chain[j]].phase = PH_DONE;
+          cancelled[j] = 1;
+          stop.push_back(chain[j]);
+        }
+      st = push_slots(c, B, stop);
+      if (st) return st;
+      checks[next] = aqs_check{2, 0, 0.0, 0.0};
+      next = P;
+      st = set_table(c, B, std::vector<int32_t>{});
+      if (st) return st;
+    }
     // checks whose configurations are ready, in order
     while (next < P) {
       const int i = next;

@@ -283,15 +283,44 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   // cand: entries hold candidate numbers during the scan and become compact
   // halo offsets (or global entries) below
   const bool cand = s_cand != 0;
+  const int ncand = s_ncand;
+  // Work area: the staged candidates during the scan, the staged list rows
+  // in the final pass.  Candidates are FP32 offsets from the tile's first
+  // atom with their image shift applied, and their types.
+  __shared__ __align__(16) unsigned char s_work[kCandCap * (4 * D + 1)];
+  float* s_cx = reinterpret_cast<float*>(s_work);
+  float* s_cy = s_cx + kCandCap;
+  float* s_cz = s_cy + kCandCap;                      // 3D only
+  uint8_t* s_ct = reinterpret_cast<uint8_t*>(s_cx + D * kCandCap);
+  __shared__ int s_cnt0[kTileSort];   // list counts in tile order
+  const double4 ref = nt > 0 ? P[a0] : make_double4(0.0, 0.0, 0.0, 0.0);
+  if (cand) {
+    for (int hc = tid; hc < ncand; hc += kBlock) {
+      int r = 0;
+      while (r < kRuns - 1 && !(hc >= runs[r].off && hc < runs[r].off + runs[r].count)) ++r;
+      const double4 pj = P[runs[r].src + (hc - runs[r].off)];
+      double sft[3];
+      code_shift(runs[r].code, g.L[0], g.L[1], g.L[2], t, sft);
+      s_cx[hc] = (float)((pj.x + sft[0]) - ref.x);
+      s_cy[hc] = (float)((pj.y + sft[1]) - ref.y);
+      if (D == 3) s_cz[hc] = (float)((pj.z + sft[2]) - ref.z);
+      s_ct[hc] = (uint8_t)pj.w;
+    }
+    __syncthreads();
+  }
   for (int li = a0 + tid; li < a1; li += kBlock) {
     const int64_t gi = g.atom_off + li;
     const double4 pi = P[li];
     const int tyi = (int)pi.w;
     double rl2[2];
+    float rl2f[2];
     for (int b = 0; b < 2; ++b) {
       const double rc = sqrt(a.pp[2 * tyi + b].rc2) + a.skin;
       rl2[b] = rc * rc;
+      rl2f[b] = (float)((rc + kListMargin) * (rc + kListMargin));
     }
+    const float pix = (float)(pi.x - ref.x), piy = (float)(pi.y - ref.y),
+                piz = (D == 3) ? (float)(pi.z - ref.z) : 0.0f;
     int c3[3];
     cell_of_pos<D>(g, nc, t, pi, c3);
     uint32_t* L = a.nbl + g.nb_off + li;
@@ -319,6 +348,28 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
           const double sz = (double)iz * g.L[2];
           const int c = (cz2 * nc[1] + cy2) * nc[0] + cx;
           const int jb = cs[c], je = cs[c + 1];
+          if (cand) {
+            // staged candidates, FP32 with the margin
+            const int hb = rr.off + (jb - rr.src);
+            for (int q = 0; q < je - jb; ++q) {
+              if (jb + q == li && code == 13) continue;
+              const int hc = hb + q;
+              const float fx = s_cx[hc] - pix, fy = s_cy[hc] - piy;
+              const float fz = (D == 3) ? s_cz[hc] - piz : 0.0f;
+              const int tj = s_ct[hc];
+              if (fx * fx + fy * fy + fz * fz < rl2f[tj]) {
+                atomicOr(&s_bits[hc >> 5], 1u << (hc & 31));
+                if (na + nb < a.max_nb) {
+                  const int row = (tj == 0) ? na : a.max_nb - 1 - nb;
+                  L[(int64_t)row * g.npad] = (uint32_t)hc;
+                } else {
+                  over = true;
+                }
+                if (tj == 0) ++na; else ++nb;
+              }
+            }
+            continue;
+          }
           for (int j = jb; j < je; ++j) {
             if (j == li && code == 13) continue;
             const double4 pj = P[j];
@@ -343,6 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
       }
     }
     a.nbc[gi] = na | (nb << 16);
+    if (sortable) s_cnt0[li - a0] = na | (nb << 16);
     // a tile with an LDS halo also needs the atom's A and B groups of the
     // packed list to fit side by side
     const int G = a.max_nb / kGroup;
@@ -377,7 +429,6 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   }
   __syncthreads();
   const bool lds = s_lds != 0;
-  const int ncand = s_ncand;
   // Walk order.  The consumers of a tile with an LDS halo walk its atoms by
   // decreasing list length (ties by position), so the lanes of a wavefront
   // have lists of similar length: tord[a0 + k] is the k-th atom, and its
@@ -388,11 +439,11 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   for (int li = a0 + tid; li < a1; li += kBlock) {
     const int ci = (nbc[li] & 0xffff) + (nbc[li] >> 16);
     int rank = li - a0;
-    if (lds) {
+    if (lds) {   // lds implies cand, so the tile is sortable and s_cnt0 is set
       rank = 0;
-      for (int j = a0; j < a1; ++j) {
-        const int cj = (nbc[j] & 0xffff) + (nbc[j] >> 16);
-        rank += (cj > ci || (cj == ci && j < li)) ? 1 : 0;
+      for (int k = 0; k < nt; ++k) {
+        const int cj = (s_cnt0[k] & 0xffff) + (s_cnt0[k] >> 16);
+        rank += (cj > ci || (cj == ci && k < li - a0)) ? 1 : 0;
       }
       s_src[rank] = li - a0;
     }
@@ -437,8 +488,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   // byte offset 8 h of the candidate's compact halo slot h, the last group
   // of a segment padded with the far fill slot.
   __shared__ int s_cnt[kTileSort];
-  __shared__ uint32_t s_stage[kRowStage];
-  for (int k = tid; k < nt; k += kBlock) s_cnt[k] = nbc[a0 + s_src[k]];
+  uint32_t* s_stage = reinterpret_cast<uint32_t*>(s_work);   // the candidates are dead now
+  for (int k = tid; k < nt; k += kBlock) s_cnt[k] = s_cnt0[s_src[k]];
   __syncthreads();
   for (int k = tid; k < nt; k += kBlock) nbc[a0 + k] = s_cnt[k];
   const int G = a.max_nb / kGroup;

@@ -127,6 +127,8 @@ struct State {
   int32_t ntiles;     // force tiles of the current grid
   int32_t list_mode;  // 0: tiles index their LDS halo; 1: global indices only
   int32_t resume_phase;  // phase to resume after a neighbour-list rebuild
+  int32_t drops;      // fine steps of this call whose shear stress fell below the step before's
+  double sxy_prev;    // shear stress of the last finished minimisation
 };
 
 // Conjugate-gradient state of a slot, kept apart from State so that the FIRE
@@ -175,6 +177,7 @@ struct IterArgs {
   int32_t nsel;
   int32_t tpa;            // threads per atom of the force kernel
   int32_t lds_pad;        // dynamic LDS bytes added to each force block (CU reservation)
+  int32_t prio;           // 1: the critical chain of a live round (its waves issue first)
   const Geom* geom;
   State* state;
   double4* pos4;

@@ -262,8 +262,15 @@ __device__ __forceinline__ void halo_pair(uint32_t off, const double4& pi, const
   pair_term<D, WE, false>(true, dx, dy, dz, q, fx, fy, fz, e, w);
 }
 
-// One segment of a packed list: this lane's groups k = 0 .. my - 1, two
-// groups (eight entries) in flight ahead of the four pairs being summed.
+// Groups of the packed list in flight ahead of the one being summed: a
+// lane's share of a list is about a dozen groups, and with one wavefront
+// per SIMD (a single chain fills the GPU about once) every round trip to
+// memory that is not overlapped shows in the launch time.
+constexpr int kGroupsAhead = 4;
+
+// One segment of a packed list: this lane's groups k = 0 .. my - 1, with
+// kGroupsAhead groups (16 entries) in flight ahead of the four pairs being
+// summed.
 template <int D, bool WE>
 __device__ __forceinline__ void packed_segment(const double4 pi, __amdgpu_buffer_rsrc_t rs,
                                                uint32_t lb, uint32_t sb, uint32_t ss, int my,
@@ -271,16 +278,18 @@ __device__ __forceinline__ void packed_segment(const double4 pi, __amdgpu_buffer
                                                const double* hy, const double* hz, double& fx,
                                                double& fy, double& fz, double& e, double& w) {
   if (my <= 0) return;
-  uint2 g0 = packed_group(rs, lb, sb, ss, 0, gcap);
-  uint2 g1 = packed_group(rs, lb, sb, ss, 1, gcap);
+  uint2 ahead[kGroupsAhead];
+#pragma unroll
+  for (int u = 0; u < kGroupsAhead; ++u) ahead[u] = packed_group(rs, lb, sb, ss, u, gcap);
   for (int k = 0; k < my; ++k) {
-    const uint2 g2 = packed_group(rs, lb, sb, ss, k + 2, gcap);
-    halo_pair<D, WE>(g0.x & 0xffffu, pi, hx, hy, hz, q, fx, fy, fz, e, w);
-    halo_pair<D, WE>(g0.x >> 16, pi, hx, hy, hz, q, fx, fy, fz, e, w);
-    halo_pair<D, WE>(g0.y & 0xffffu, pi, hx, hy, hz, q, fx, fy, fz, e, w);
-    halo_pair<D, WE>(g0.y >> 16, pi, hx, hy, hz, q, fx, fy, fz, e, w);
-    g0 = g1;
-    g1 = g2;
+    const uint2 cur = ahead[0];
+#pragma unroll
+    for (int u = 0; u + 1 < kGroupsAhead; ++u) ahead[u] = ahead[u + 1];
+    ahead[kGroupsAhead - 1] = packed_group(rs, lb, sb, ss, k + kGroupsAhead, gcap);
+    halo_pair<D, WE>(cur.x & 0xffffu, pi, hx, hy, hz, q, fx, fy, fz, e, w);
+    halo_pair<D, WE>(cur.x >> 16, pi, hx, hy, hz, q, fx, fy, fz, e, w);
+    halo_pair<D, WE>(cur.y & 0xffffu, pi, hx, hy, hz, q, fx, fy, fz, e, w);
+    halo_pair<D, WE>(cur.y >> 16, pi, hx, hy, hz, q, fx, fy, fz, e, w);
   }
 }
 
@@ -333,6 +342,13 @@ __device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
   rec.status = status;
   rec.start = s.start_used;
   if (s.step < a.log_cap) a.log[(int64_t)rep * a.log_cap + s.step] = rec;
+  // a fine step whose inherent structure carries less shear stress than the
+  // one before: under growing shear an elastic branch only gains stress, so
+  // this marks a plastic event (aqs_run_round with live = 2 reads it)
+  if (status == 0) {
+    if (s.step >= 1 && rec.sigma_xy < s.sxy_prev) s.drops += 1;
+    s.sxy_prev = rec.sigma_xy;
+  }
   s.status = status;
   s.do_snap = (s.step == 0 && s.snap_dst >= 0) ? 1 : 0;
   if (s.do_snap) {
@@ -655,8 +671,15 @@ __device__ __forceinline__ void force_tile(const IterArgs& a, const Geom& g, int
 // LDS (image shifts applied), then TPA lanes per atom walk each neighbour
 // list.  Writes F and the tile partials (force_atom); k_control combines
 // them.
+// The critical chain of a live round shares compute units with the batch:
+// its waves take the highest issue priority of their SIMD.
+__device__ __forceinline__ void critical_priority(const IterArgs& a) {
+  if (a.prio) __builtin_amdgcn_s_setprio(3);
+}
+
 template <int D, int TPA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_force(IterArgs a) {
+  critical_priority(a);
   const int2 bt = a.ftiles[blockIdx.x];
   const int rep = bt.x;
   if (rep < 0) return;
@@ -721,6 +744,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 // The tile partials are combined in tile order, then a fixed tree.
 template <bool CG>
 __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
+  critical_priority(a);
   const int rep = a.sel[blockIdx.x];
   const State* stp = a.state + rep;
   const int phase = stp->phase;
@@ -765,6 +789,7 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
 
 template <int D, bool CG>
 __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
+  critical_priority(a);
   const int2 bt = a.blocks[blockIdx.x];
   const int rep = bt.x;
   if (rep < 0) return;

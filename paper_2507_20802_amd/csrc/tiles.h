@@ -30,6 +30,12 @@ constexpr int kHaloWords = 128;  // candidate bitmap of the builder: tiles with 
                                  // (32 kHaloWords) keep global entries
 constexpr int kRowStage = 4096;  // list words the builder stages in LDS per pass (a pass holds
                                  // whole groups: kGroup rows of up to kTileSort atoms)
+constexpr int kCandCap = 32 * kHaloWords;  // candidates a tile may have and still number them
+// FP32 distance test of the list builder: pairs within rc_ab + skin + this
+// margin (sigma_AA) are kept, far more than the FP32 rounding of candidate
+// offsets within a few cells of the tile (below 1e-5); the extra pairs lie
+// beyond the cutoff and the force loop's FP64 test drops them
+constexpr double kListMargin = 1e-3;
 
 struct TileHdr {
   int32_t a0, a1;   // atom range [a0, a1) of the tile

@@ -271,14 +271,16 @@ class Engine:
         return _records(recs, r.size, width)
 
     def run_round(self, chains, snaps, n_steps, start: int = AQS_START_PLAIN, delta_eq: float = 1e-4,
-                  live: bool = False):
+                  live: bool = False, abandon: bool = False):
         """Level II and the checks of one round of Algorithm 1 (aqs_run_round):
         chain i (already at its level-I start) is minimised, then runs
         n_steps[i] fine steps; check i compares the end of chain i-1 with the
         first inherent structure of chain i, copied into snaps[i].  With live,
         checks are taken as soon as possible and chains after a failed check
-        stop.  Returns (records (P, max n_steps + 1), checks) where checks[i] =
-        (decided, equal, max_disp, dE/N) for i >= 1."""
+        stop; with abandon also, a stress drop in the critical chain stops the
+        chains after it before its check (decided = 2).  Returns (records (P,
+        max n_steps + 1), checks) where checks[i] = (decided, equal, max_disp,
+        dE/N) for i >= 1."""
         c = _i32(np.atleast_1d(chains))
         P = int(c.size)
         sn = _i32(np.broadcast_to(np.atleast_1d(snaps), c.shape))
@@ -289,9 +291,9 @@ class Engine:
             x.status = -1
         chk = (aqs_check * P)()
         check(self._lib.aqs_run_round(self._ctx, P, _p(c, ctypes.c_int32), _p(sn, ctypes.c_int32),
-                                      _p(ns, ctypes.c_int32), int(start), float(delta_eq), int(bool(live)),
-                                      recs, chk), "aqs_run_round")
-        checks = [(bool(x.decided), bool(x.equal), x.max_disp, x.de_per_atom) for x in chk]
+                                      _p(ns, ctypes.c_int32), int(start), float(delta_eq),
+                                      (2 if abandon else 1) if live else 0, recs, chk), "aqs_run_round")
+        checks = [(int(x.decided), bool(x.equal), x.max_disp, x.de_per_atom) for x in chk]
         return _records(recs, P, width), checks
 
     def compare(self, a: int, b: int, delta_eq: float = 1e-4):

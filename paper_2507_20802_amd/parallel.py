@@ -128,14 +128,18 @@ def reservation_for(last_checks: List[bool]) -> int:
 
 def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq: float = 1e-4,
         start: int = AQS_START_PLAIN, max_rounds: int | None = None, log=None, live: bool = False,
-        adaptive_reservation: bool = True, dynamic_k: Optional[Tuple[int, int]] = None) -> dict:
+        adaptive_reservation: bool = True, dynamic_k: Optional[Tuple[int, int]] = None,
+        abandon: bool = False) -> dict:
     """Run Algorithm 1 to n_steps accepted fine steps for every glass (each
     glass's r_star must be loaded in its star slot as an inherent structure).
     With live checks and adaptive_reservation, each round's CU reservation
     for the critical chain follows the previous round's checks
     (reservation_for).  dynamic_k=(k_min, k_max): every glass starts with K
     and takes next_k after each round.  Returns timing and counts; per-glass
-    details (each round's K among them) are filled into glasses."""
+    details (each round's K among them) are filled into glasses.
+    abandon (with live): a stress drop in the critical chain stops the chains
+    after it before their check, which counts as failed (predicted, not
+    evaluated: the decision's max_disp is NaN)."""
     if P < 2:
         raise ValueError("Algorithm 1 needs P >= 2 (Sec. 3.2)")
     if K < 1:
@@ -178,10 +182,11 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
                 g = glasses[gi]
                 p = len(lengths)
                 recs, chk = engine.run_round(g.chains[:p], [-1] + g.snaps[1:p], lengths, start=start,
-                                             delta_eq=delta_eq, live=True)
+                                             delta_eq=delta_eq, live=True, abandon=abandon)
                 for i in range(p):
                     rows[g.chains[i]] = recs[i]
-                outcomes[gi] = [(c[1], c[2], c[3]) for c in chk[1:] if c[0]]
+                outcomes[gi] = [(c[1], c[2] if c[0] == 1 else float("nan"), c[3] if c[0] == 1 else float("nan"))
+                                for c in chk[1:] if c[0]]
         else:
             recs = engine.minimize(sel, n_steps=nst, snap_dst=snp, start=start)   # level II
             rows = {s: recs[j] for j, s in enumerate(sel)}
@@ -200,7 +205,7 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
                     eq, md, de = outcomes[gi][i - 1]
                 else:
                     eq, md, de = engine.compare(g.chains[i - 1], g.snaps[i], delta_eq)   # Eq. (20)
-                k = engine.strain_index(g.snaps[i])
+                k = engine.strain_index(g.star) + i * Kr   # both configurations of check i
                 d = Decision(rnd, i, k, eq, md, de)
                 g.decisions.append(d)
                 checks.append(eq)

@@ -257,3 +257,50 @@ def test_adaptive_reservation_changes_no_result():
         res.append(([(r["checks"], r["q"]) for r in g.rounds], eng.positions(g.star), out["accepted_steps"]))
     assert res[0][0] == res[1][0] and res[0][2] == res[1][2] == n
     assert np.array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("dg,K", [(4e-3, 6), (1e-5, 3)])
+def test_live_round_abandons_after_a_stress_drop(dg, K):
+    """live = 2: a fine step of the critical chain whose inherent structure
+    carries less shear stress than the step before stops the chains after it
+    before their check (decided = 2).  The oracle's chain 0 from the same
+    glass says whether such a drop happens (at dgamma = 4e-3 the stress falls
+    at step 4, at 1e-5 it only grows); chain 0 is bitwise the batched
+    round's; without a drop the round is the live = 1 round."""
+    from paper_2507_20802_amd import Engine, parallel
+    from paper_2507_20802_amd._lib import AQS_CANCELLED
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, ofire = fire_pair()
+    x, sig = pos, []
+    for k in range(K + 1):
+        if k:
+            x = O.fire(O.affine(x, dg), types, O.strain_box(dim, L, k, dg), POT, ofire).pos
+        sig.append(O.energy_forces(x, types, O.strain_box(dim, L, k, dg), POT)[2][0, 1])
+    drop = any(sig[s] < sig[s - 1] for s in range(1, K + 1))
+    P = 4
+    eng = Engine(dim, [len(types)] * parallel.slots_needed(1, P), L, dg, fire=fire)
+    g = parallel.layout(1, P)[0]
+    eng.set_replica(g.star, types, pos, 0)
+    rb, cb = _round(eng, g, P, K, K, 1e-4, live=False)
+    end0 = eng.positions(g.chains[0])
+    assert drop == any(rb[0]["sigma_xy"][s] < rb[0]["sigma_xy"][s - 1] for s in range(1, K + 1))
+    r1, c1 = _round(eng, g, P, K, K, 1e-4, live=True)
+    for i in range(P):
+        eng.copy_replica(g.star, g.chains[i])
+    eng.affine_shear(g.chains[1:P], [i * K for i in range(1, P)])
+    r2, c2 = eng.run_round(g.chains[:P], [-1] + g.snaps[1:P], [K] * P, delta_eq=1e-4, live=True,
+                           abandon=True)
+    print("oracle stress", ["%.4f" % v for v in sig], "checks", [c[:2] for c in c2])
+    assert np.array_equal(r2[0], rb[0]) and np.array_equal(eng.positions(g.chains[0]), end0)
+    if drop:
+        assert c2[1][0] == 2 and not c2[1][1]
+        assert all(c[0] == 0 for c in c2[2:])
+        for i in range(1, P):
+            ran = r2[i]["status"] != AQS_CANCELLED
+            assert np.array_equal(r2[i][ran], rb[i][ran])
+            assert not ran[int(ran.sum()):].any()
+    else:
+        assert [c[:2] for c in c2] == [c[:2] for c in c1]
+        for i in range(P):
+            ran = (r2[i]["status"] != AQS_CANCELLED) & (r1[i]["status"] != AQS_CANCELLED)
+            assert np.array_equal(r2[i][ran], r1[i][ran])
