@@ -207,12 +207,15 @@ def main() -> int:
                     help="rounds of the plain-start form timed beside the headline (0: none)")
     ap.add_argument("--sequential", type=int, default=1,
                     help="time conventional sequential AQS of the same K steps (1/0), Eq. 21's C^(S)")
+    ap.add_argument("--kernel-K", type=int, default=5,
+                    help="fine steps per chain of the kernel form's batched round")
     ap.add_argument("--abandon", type=int, default=1,
                     help="live rounds: a stress drop (plastic event) in the critical chain stops the chains "
                          "after it before their check (1/0)")
-    ap.add_argument("--forms", default="live1",
-                    help="extra forms, comma-separated: live1 (live checks without abandonment), "
-                         "extrapolated, cg, batched (one round each)")
+    ap.add_argument("--forms", default="live1,kernel",
+                    help="extra forms, comma-separated: live1 (live checks without abandonment), kernel "
+                         "(a short batched round, every force launch timed: the force kernel on all "
+                         "chains at once), extrapolated, cg, batched (one round each)")
     ap.add_argument("--only-plain", action="store_true", help="headline with the plain start (no network)")
     ap.add_argument("--graph", type=int, default=0, help="replay iteration blocks as hipGraphs (1/0)")
     ap.add_argument("--live", type=int, default=1,
@@ -239,7 +242,7 @@ def main() -> int:
         return 2
     extra = [f for f in args.forms.split(",") if f]
     for f in extra:
-        if f not in ("live1", "extrapolated", "cg", "batched"):
+        if f not in ("live1", "kernel", "extrapolated", "cg", "batched"):
             print(f"unknown form {f}", file=sys.stderr)
             return 2
 
@@ -293,13 +296,13 @@ def main() -> int:
         torch.cuda.synchronize()
         return time.perf_counter() - t, out, g
 
-    def timed_form(name, start, live, mz, rounds, abandon):
+    def timed_form(name, start, live, mz, rounds, abandon, k=None, every=None):
         eng.set_minimizer(mz, Cg() if mz == "cg" else None)
         eng.counters(reset=True)
-        eng.set_profiling(args.profile_every)
+        eng.set_profiling(args.profile_every if every is None else every)
         tot_t, acc, comp, iters, ok, rr, starts = 0.0, 0, 0, [], True, [], []
         for _ in range(rounds):
-            dt, out, g = one_round(K, start, live, abandon)
+            dt, out, g = one_round(K if k is None else k, start, live, abandon)
             tot_t += dt
             acc += out["accepted_steps"]
             comp += out["computed_steps"]
@@ -348,6 +351,9 @@ def main() -> int:
         forms["plain"] = timed_form("plain", AQS_START_PLAIN, live, "fire", args.plain_rounds, abandon)
         forms["plain"]["final_star_vs_headline"] = star_vs_headline()
     for f in extra:
+        if f == "kernel":
+            forms[f] = timed_form(f, AQS_START_PLAIN, False, "fire", 1, False, k=args.kernel_K, every=1)
+            continue
         st = {"live1": head_start, "extrapolated": AQS_START_EXTRAPOLATED, "cg": AQS_START_PLAIN,
               "batched": head_start}[f]
         forms[f] = timed_form(f, st, live and f != "batched", "cg" if f == "cg" else "fire", 1,
@@ -380,6 +386,20 @@ def main() -> int:
     achieved_tflops = flops_per_atom * atoms_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else None
     achieved_gbs = FORCE_BYTES_PER_ATOM[dim] * atoms_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
     traffic = force_traffic(dim, atoms_per_launch)
+    kernel_form = None
+    if "kernel" in forms:
+        kc = forms["kernel"]["counters"]
+        kms = kc["force_ms"] / kc["force_timed"]
+        katoms = kc["timed_atom_evals"] / kc["force_timed"]
+        ktf = flops_per_atom * katoms / (kms * 1e-3) / 1e12
+        kernel_form = {"kernel": f"k_force<{dim}>", "avg_launch_ms": kms, "timed_launches": kc["force_timed"],
+                       "atoms_per_launch": katoms, "achieved_tflops": ktf, "frac_fp64": ktf / FP64_PEAK_TFLOPS,
+                       "hbm_gbs_algorithmic": FORCE_BYTES_PER_ATOM[dim] * katoms / (kms * 1e-3) / 1e9,
+                       "traffic_bytes_per_atom": (force_traffic(dim, katoms) / katoms)
+                       if force_traffic(dim, katoms) else None,
+                       "update_avg_ms": kc["update_ms"] / kc["update_timed"],
+                       "round": f"plain start, batched (no live checks), P={P} x K={args.kernel_K}, "
+                                f"every force launch timed"}
     comparison = None
     if "plain" in forms:
         pl = forms["plain"]
@@ -431,7 +451,7 @@ def main() -> int:
         "speedup_vs_sequential": None if seq is None else head["value"] / seq["value"],
         "speedup_vs_sequential_live1": None if seq is None or "live1" not in forms
         else forms["live1"]["value"] / seq["value"],
-        "extra_forms": {f: {k: v for k, v in forms[f].items() if k != "counters"} for f in extra},
+        "extra_forms": {f: {k: v for k, v in forms[f].items() if k != "counters"} for f in extra if f != "kernel"},
         "quench_s": quench_s,
         "mean_neighbours_in_cutoff": nb,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -445,6 +465,7 @@ def main() -> int:
                      "hbm_frac_algorithmic": achieved_gbs / HBM_PEAK_GBS if achieved_gbs else None,
                      "traffic_bytes_per_atom": traffic / atoms_per_launch if traffic and atoms_per_launch else None},
         "counters": cnt,
+        "force_kernel_all_chains": kernel_form,
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(is_pos, s.types, s.L, dg, float(head["fire_iters_per_step"]["mean"]),

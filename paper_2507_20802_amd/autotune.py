@@ -265,3 +265,34 @@ def tuned(dim: int, n_atoms, n_rep: int, cache: str | None = None, run_if_missin
     if entry is None and run_if_missing:
         entry = tune(dim, n, n_rep, cache=cache, log=log)
     return tuning_of(entry["knobs"]) if entry else Tuning()
+
+
+# shapes of the shipped tuning: the benchmark's batch (3D, 16 chains of 32768
+# atoms with their snapshots and r_star), the 2D batch of four glasses, one
+# small 2D replica, the uneven 3D batch (largest replica) and the paper's
+# problem batched over samples
+SHIPPED_SHAPES = ((3, 32768, 33), (3, 32768, 16), (2, 4096, 32), (2, 256, 1), (3, 131072, 24), (2, 400, 256))
+
+
+def main(argv=None) -> int:
+    """Tune shapes on the GPU and store them (default: the shipped shapes
+    into the packaged file)."""
+    import argparse
+    import torch
+    ap = argparse.ArgumentParser(description="tune the engine's knobs for workload shapes")
+    ap.add_argument("--shape", action="append", default=[], metavar="DIM,N,SLOTS")
+    ap.add_argument("--cache", default=PACKAGED)
+    ap.add_argument("--repeats", type=int, default=2)
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    shapes = [tuple(int(v) for v in s.split(",")) for s in args.shape] or SHIPPED_SHAPES
+    for dim, n, reps in shapes:
+        entry = tune(dim, n, reps, repeats=args.repeats, cache=args.cache,
+                     log=lambda m: print(f"[tune {dim}D n={n} x{reps}] {m}", flush=True))
+        print(json.dumps({"shape": [dim, n, reps], **entry}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    import sys
+    sys.exit(main())

@@ -114,15 +114,16 @@ def reservation_for(last_checks: List[bool]) -> int:
     """Batch force blocks per CU for the next live round (aqs_tuning
     live_batch_blocks) from the decided checks of the last round: speculation
     that paid (at least three quarters passed) runs unthrottled (-1); checks
-    that mostly failed (under a quarter passed) leave two blocks per CU to
-    the batch; otherwise, and with no history, the default (0, i.e. 3)."""
+    that mostly failed (under a quarter passed), and the first round, leave
+    one block per CU to the batch, so that the critical chain keeps most of
+    its own speed; otherwise the default (0, i.e. 3)."""
     if not last_checks:
-        return 0
+        return 1
     f = sum(bool(c) for c in last_checks) / len(last_checks)
     if f >= 0.75:
         return -1
     if f < 0.25:
-        return 2
+        return 1
     return 0
 
 

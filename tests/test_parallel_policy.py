@@ -1,7 +1,7 @@
 """Host policies of the Algorithm 1 driver, CPU only.  The CU reservation of
 live rounds (parallel.reservation_for): unthrottled speculation after rounds
-whose checks mostly passed, a tighter reservation after rounds whose checks
-mostly failed, the default otherwise and without history.  The dynamic
+whose checks mostly passed, one batch block per CU after rounds whose
+checks mostly failed and for the first round, the default otherwise.  The dynamic
 choice of K (parallel.next_k): doubled after a round whose checks all
 passed, halved (rounded up) after a failed first check, kept otherwise,
 within its bounds."""
@@ -11,13 +11,13 @@ from paper_2507_20802_amd.parallel import next_k, reservation_for
 
 
 def test_reservation_follows_the_last_rounds_checks():
-    assert reservation_for([]) == 0
+    assert reservation_for([]) == 1
     assert reservation_for([True]) == -1
     assert reservation_for([True, True, True, False]) == -1
     assert reservation_for([True, False]) == 0
     assert reservation_for([True, False, False, False]) == 0
-    assert reservation_for([False]) == 2
-    assert reservation_for([True] + [False] * 4) == 2
+    assert reservation_for([False]) == 1
+    assert reservation_for([True] + [False] * 4) == 1
 
 
 @pytest.mark.parametrize("K,checks,bounds,want", [
