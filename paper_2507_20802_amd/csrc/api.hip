@@ -413,7 +413,8 @@ LearnArgs learn_args(aqs_ctx* c, const Lane& L, int mode, float* out = nullptr) 
 
 std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, uint32_t xcds,
                              int per_block = 1);
-std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel, uint32_t xcds);
+std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel, uint32_t xcds,
+                                  bool global = true);
 
 // Learned (or extrapolated) start of the slots waiting in PH_LDESC (known
 // from the last state read-back): descriptors and network, or the
@@ -480,11 +481,16 @@ std::vector<int2> make_table(aqs_ctx* c, const std::vector<int32_t>& sel, uint32
   return xcd_table(logical, xcds);
 }
 
-// Launch table over the force tiles of the given slots' current grids.
-std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel, uint32_t xcds) {
+// Launch table over the force tiles of the given slots' current grids:
+// entries (slot, global tile index tile_off + t) for the force and
+// descriptor kernels, (slot, t) for the list builder (global = false).
+std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel, uint32_t xcds,
+                                  bool global) {
   std::vector<int2> logical;
-  for (int r : sel)
-    for (int t = 0; t < c->tiles_now[r]; ++t) logical.push_back(make_int2(r, t));
+  for (int r : sel) {
+    const int off = global ? c->lo.geom[r].tile_off : 0;
+    for (int t = 0; t < c->tiles_now[r]; ++t) logical.push_back(make_int2(r, off + t));
+  }
   return xcd_table(logical, xcds);
 }
 
@@ -573,7 +579,7 @@ aqs_status rebuild(aqs_ctx* c, Lane& L, const std::vector<int32_t>& sel, bool in
     }
   }
   std::vector<int2> tbl = make_table(c, sel, L.xcd_mask);
-  std::vector<int2> ttbl = make_tile_table(c, sel, L.xcd_mask);
+  std::vector<int2> ttbl = make_tile_table(c, sel, L.xcd_mask, false);
   std::copy(tbl.begin(), tbl.end(), L.h_tbl2);
   std::copy(ttbl.begin(), ttbl.end(), L.h_ttbl);
   HIPCHK(hipMemcpyAsync(L.ttbl, L.h_ttbl, sizeof(int2) * ttbl.size(), hipMemcpyHostToDevice, L.s));

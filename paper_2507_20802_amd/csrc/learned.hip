@@ -132,15 +132,15 @@ __global__ __launch_bounds__(kBlock) void k_ldesc(LearnArgs a) {
   if (rep < 0) return;
   const State* st = a.state + rep;
   if (a.mode == 0 && st->phase != PH_LDESC) return;
-  if (bt.y >= st->ntiles) return;
   const Geom g = a.geom[rep];
+  if (bt.y - g.tile_off >= st->ntiles) return;   // entries hold global tile indices
   const int tid = threadIdx.x;
   constexpr int CAP = (D == 3) ? kHaloCap3 : kHaloCap2;
   __shared__ double hx[CAP];
   __shared__ double hy[CAP];
   __shared__ double hz[D == 3 ? CAP : 1];
   __shared__ double sh[32][4];
-  const int64_t tix = g.tile_off + bt.y;
+  const int64_t tix = bt.y;
   const TileHdr hdr = reinterpret_cast<const TileHdr*>(a.thdr)[tix];
   const double t = strain_of(st->k, g.dgamma) * g.L[1];
   if (tid >= 32 && tid < 32 + 27) code_shift(tid - 32, g.L[0], g.L[1], g.L[2], t, sh[tid - 32]);

@@ -277,7 +277,8 @@ __device__ __forceinline__ void packed_segment(const double4 pi, __amdgpu_buffer
                                                int gcap, const PairParams q, const double* hx,
                                                const double* hy, const double* hz, double& fx,
                                                double& fy, double& fz, double& e, double& w) {
-  if (my <= 0) return;
+  // the first groups are requested before the count is needed (in bounds:
+  // clamped to the list)
   uint2 ahead[kGroupsAhead];
 #pragma unroll
   for (int u = 0; u < kGroupsAhead; ++u) ahead[u] = packed_group(rs, lb, sb, ss, u, gcap);
@@ -472,8 +473,8 @@ __device__ bool control_cg(const CgParams& c, CgState& q, double fmx, int64_t it
 }
 
 template <bool CG>
-__device__ void control(const IterArgs& a, int rep, const Geom& g, const double* r, int phase) {
-  State s = a.state[rep];
+__device__ void control(const IterArgs& a, int rep, const Geom& g, const double* r, int phase,
+                        State s) {
   if (phase == PH_FINISH || phase == PH_STOP) {
     s.phase = PH_DONE;
     a.state[rep] = s;
@@ -680,20 +681,34 @@ __device__ __forceinline__ void critical_priority(const IterArgs& a) {
 template <int D, int TPA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_force(IterArgs a) {
   critical_priority(a);
-  const int2 bt = a.ftiles[blockIdx.x];
+  // (slot, global tile index), read in one load
+  const uint64_t ent = reinterpret_cast<const uint64_t*>(a.ftiles)[blockIdx.x];
+  const int2 bt = make_int2((int)(uint32_t)ent, (int)(uint32_t)(ent >> 32));
   const int rep = bt.x;
   if (rep < 0) return;
-  const State* stp = a.state + rep;
-  const int phase = stp->phase;
-  const bool we = phase_energy(phase);
-  const bool compute = phase_force(phase);
-  if (!compute) return;
-  const bool cg = (phase == PH_CG);
-  const int ntiles = stp->ntiles;
-  if (bt.y >= ntiles) return;
-  const Geom g = a.geom[rep];
   const int tid = threadIdx.x;
   constexpr int CAP = (D == 3) ? kHaloCap3 : kHaloCap2;
+  constexpr int SU = (CAP + kBlock - 1) / kBlock;
+  // Everything that needs only the table entry is requested at once -- the
+  // slot's state and geometry, the tile header, this thread's compact-halo
+  // indices (in bounds whatever the halo size) -- so that the chain of
+  // dependent loads before the pair loop is table -> these -> positions.
+  const int64_t tix = bt.y;
+  const TileHdr hdr = reinterpret_cast<const TileHdr*>(a.thdr)[tix];
+  uint32_t hent[SU];
+#pragma unroll
+  for (int u = 0; u < SU; ++u) {
+    const int h = tid + u * kBlock;
+    hent[u] = h < CAP ? a.hidx[tix * CAP + h] : 0u;
+  }
+  const State* stp = a.state + rep;
+  const int phase = stp->phase;
+  const int ntiles = stp->ntiles;
+  const Geom g = a.geom[rep];
+  const bool we = phase_energy(phase);
+  const bool compute = phase_force(phase);
+  if (!compute || tix - g.tile_off >= ntiles) return;
+  const bool cg = (phase == PH_CG);
 
   __shared__ double hx[CAP];
   __shared__ double hy[CAP];
@@ -705,14 +720,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 
   double part[kForceParts] = {0, 0, 0, 0, 0, 0, 0, 0};
   {
-    const int64_t tix = g.tile_off + bt.y;
-    const TileHdr hdr = reinterpret_cast<const TileHdr*>(a.thdr)[tix];
     const double t = slot_tilt(g, stp);
     if (tid >= 32 && tid < 32 + 27) code_shift(tid - 32, g.L[0], g.L[1], g.L[2], t, sh[tid - 32]);
     if (tid >= 64 && tid < 68) spp[tid - 64] = a.pp[tid - 64];
     __syncthreads();
     if (hdr.halo >= 0) {
-      stage_halo<D, CAP>(hdr, a.hidx + tix * CAP, sh, a.pos4 + g.atom_off, hx, hy, hz);
+      stage_halo_from<D, CAP>(hdr, hent, sh, a.pos4 + g.atom_off, hx, hy, hz);
       if (tid == kBlock - 1) {   // the far fill slot (the builder keeps halos below CAP)
         hx[CAP - 1] = kFarFill;
         hy[CAP - 1] = kFarFill;
@@ -747,12 +760,15 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
   critical_priority(a);
   const int rep = a.sel[blockIdx.x];
   const State* stp = a.state + rep;
+  const int tid = threadIdx.x;
+  // the control's copy of the slot state, in flight while the partials are summed
+  State s0;
+  if (tid == 0) s0 = *stp;
   const int phase = stp->phase;
   const bool compute = phase_force(phase);
   const bool counted = compute || phase == PH_FINISH || phase == PH_STOP;
   if (!counted) return;
   const Geom g = a.geom[rep];
-  const int tid = threadIdx.x;
   const int ntiles = stp->ntiles;
   // r: the tile partials 0-6, the update's max displacement, max |v_i|^2
   __shared__ double red[kForceParts + 1][kBlock / kWave];
@@ -778,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
       atomicAdd(a.evals, (unsigned long long)g.n);
       if (a.tevals) atomicAdd(a.tevals, (unsigned long long)g.n);
     }
-    control<CG>(a, rep, g, r, phase);
+    control<CG>(a, rep, g, r, phase, s0);
   }
 }
 

@@ -142,6 +142,33 @@ __device__ __forceinline__ void stage_halo(const TileHdr& hdr, const uint32_t* h
   }
 }
 
+// stage_halo with this thread's compact-halo entries already loaded: ent[u]
+// holds slot tid + u kBlock of the tile's compact halo (any value past the
+// halo size, which is not read).
+template <int D, int CAP>
+__device__ __forceinline__ void stage_halo_from(const TileHdr& hdr, const uint32_t* ent,
+                                                const double (*sh)[4], const double4* P, double* hx,
+                                                double* hy, double* hz) {
+  const int tid = threadIdx.x;
+  constexpr int SU = (CAP + kBlock - 1) / kBlock;
+  double4 p[SU];
+#pragma unroll
+  for (int u = 0; u < SU; ++u) {
+    const int h = tid + u * kBlock;
+    if (h < hdr.halo) p[u] = P[ent[u] & kIdxMask];
+  }
+#pragma unroll
+  for (int u = 0; u < SU; ++u) {
+    const int h = tid + u * kBlock;
+    if (h < hdr.halo) {
+      const int code = (int)(ent[u] >> kCodeShift);
+      hx[h] = p[u].x + sh[code][0];
+      hy[h] = p[u].y + sh[code][1];
+      if (D == 3) hz[h] = p[u].z + sh[code][2];
+    }
+  }
+}
+
 // Atom range of segment s of row `row` (rows cut into m segments).
 __device__ __forceinline__ void segment(const int* nc, int m, const int32_t* cs, int t, int& a0,
                                         int& a1, int& cy, int& cz) {
