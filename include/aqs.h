@@ -114,7 +114,8 @@ typedef struct {
 typedef struct {
   double skin;              /* Verlet skin added to each pair cutoff; 0 = 0.3 */
   int32_t max_neighbors;    /* list capacity per atom; 0 = 64 (2D) / 192 (3D) */
-  int32_t block_iters;      /* FIRE iterations launched between host polls; 0 = 32 */
+  int32_t block_iters;      /* FIRE iterations launched between host polls, rounded up to
+                               an even number; 0 = 32 */
   int32_t use_graph;        /* 1: replay each block of iterations as a hipGraph */
   int32_t max_chain_steps;  /* largest n_steps accepted by aqs_minimize_batch; 0 = 1024 */
   int32_t threads_per_atom; /* force kernel: 1, 2, 4 or 8 lanes per atom; 0 = 2 */

@@ -71,7 +71,8 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   r.max_nb = (t && t->max_neighbors > 0) ? t->max_neighbors : (pot->dim == 3 ? 192 : 64);
   // the packed list holds max_nb / kGroup groups, shared by up to kMaxTPA lanes
   r.max_nb = (r.max_nb + kListAlign - 1) / kListAlign * kListAlign;
-  r.block_iters = (t && t->block_iters > 0) ? t->block_iters : 32;
+  // even: a block's iterations alternate the state buffers and end in the home one
+  r.block_iters = (t && t->block_iters > 0) ? (t->block_iters + 1) / 2 * 2 : 32;
   r.use_graph = t ? t->use_graph : 0;
   r.log_cap = ((t && t->max_chain_steps > 0) ? t->max_chain_steps : 1024) + 1;
   const int tp = t ? t->threads_per_atom : 0;
@@ -108,8 +109,8 @@ size_t table_cap(int64_t n) { return (size_t)kXcds * ((size_t)n + 1); }
 
 struct Layout {
   size_t total = 0;
-  size_t o_geom, o_state, o_cgst, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_nbp, o_fpart, o_upart,
-      o_counter, o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl[2],
+  size_t o_geom, o_state, o_state2, o_cgst, o_cgst2, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_nbp, o_fpart, o_upart, o_upart2,
+      o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl[2],
       o_tbl2[2], o_reps[2], o_nc3[2], o_overflow[2], o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_talt4, o_evals, o_xref4, o_ftbl[2], o_ttbl[2], o_thdr, o_hidx, o_sel[2],
       o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl[2], o_lftbl[2], o_lsel[2], o_tord;
   int64_t atoms = 0;      // padded atoms over all slots
@@ -178,7 +179,9 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   const size_t A = (size_t)lo.atoms;
   lo.o_geom = take(sizeof(Geom) * n_rep);
   lo.o_state = take(sizeof(State) * n_rep);
+  lo.o_state2 = take(sizeof(State) * n_rep);
   lo.o_cgst = take(sizeof(CgState) * n_rep);
+  lo.o_cgst2 = take(sizeof(CgState) * n_rep);
   lo.o_pos4 = take(sizeof(double4) * A);
   for (int a = 0; a < 3; ++a) lo.o_v[a] = take(sizeof(double) * A);
   for (int a = 0; a < 3; ++a) lo.o_f[a] = take(sizeof(double) * A);
@@ -191,7 +194,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_thdr = take(sizeof(TileHdr) * (size_t)lo.tiles);
   lo.o_hidx = take(sizeof(uint32_t) * (size_t)halo_cap(dim) * (size_t)lo.tiles);
   lo.o_upart = take(sizeof(double) * (size_t)lo.blocks);
-  lo.o_counter = take(sizeof(uint32_t) * n_rep);
+  lo.o_upart2 = take(sizeof(double) * (size_t)lo.blocks);
   lo.o_log = take(sizeof(StepRecord) * (size_t)n_rep * tn.log_cap);
   lo.o_ccount = take(sizeof(int32_t) * (size_t)lo.cells);
   lo.o_cstart = take(sizeof(int32_t) * (size_t)lo.cells);
@@ -281,15 +284,15 @@ struct aqs_ctx {
   Layout lo;
   // device views
   Geom* d_geom;
-  State* d_state;
-  CgState* cgst;
+  State* d_state;            // home buffer of the slot states (see IterArgs)
+  State* d_state2;           // second buffer, written by odd iterations of a block
+  CgState *cgst, *cgst2;
   double4* pos4;
   double *vx, *vy, *vz, *fx, *fy, *fz;
   int32_t *id, *inv, *nbc;
   uint32_t* nbl;
   uint2* nbp;
-  double *fpart, *upart;
-  uint32_t* counter;
+  double *fpart, *upart, *upart2;
   StepRecord* log;
   int32_t *ccount, *cstart, *cellof, *order, *tid;
   double4* tpos4;
@@ -346,6 +349,8 @@ IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   a.prio = (c->live && &L == &c->ln[1]) ? 1 : 0;
   a.geom = c->d_geom;
   a.state = c->d_state;
+  a.state_out = c->d_state2;
+  a.state_home = c->d_state;
   a.pos4 = c->pos4;
   a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
   a.fx = c->fx; a.fy = c->fy; a.fz = c->fz;
@@ -355,13 +360,14 @@ IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   a.thdr = c->thdr;
   a.hidx = c->hidx;
   a.tord = c->tord;
-  a.fpart = c->fpart; a.upart = c->upart; a.counter = c->counter;
+  a.fpart = c->fpart; a.upart = c->upart; a.upart_out = c->upart2;
   a.log = c->log; a.log_cap = c->tn.log_cap;
   a.max_nb = c->tn.max_nb;
   for (int t = 0; t < 4; ++t) a.pp[t] = c->pp[t];
   a.fire = c->fire;
   a.cg = c->cg;
   a.cgst = c->cgst;
+  a.cgst_out = c->cgst2;
   a.minimizer = c->minimizer;
   a.skin = c->tn.skin;
   a.rc_max = c->rc_max;
@@ -642,11 +648,23 @@ void drop_graph(Lane& L) {
   L.g_iters = 0;
 }
 
-// M FIRE iterations (force, control, update per iteration) on the context
-// stream: replayed from a captured hipGraph when use_graph is set and the
-// stream can be captured, else launched directly.  The captured graph holds
-// kernel launches only (no memset nodes).
+// The arguments of the next iteration: the in and out buffers of the state,
+// conjugate-gradient state and displacement partials swapped.
+IterArgs swapped(const IterArgs& a) {
+  IterArgs b = a;
+  std::swap(b.state, b.state_out);
+  std::swap(b.cgst, b.cgst_out);
+  std::swap(b.upart, b.upart_out);
+  return b;
+}
+
+// M FIRE iterations (force, then control and move, per iteration; M even, so
+// the block ends with everything in the home buffers) on the lane's stream:
+// replayed from a captured hipGraph when use_graph is set and the stream can
+// be captured, else launched directly.  The captured graph holds kernel
+// launches only (no memset nodes).
 aqs_status launch_block(aqs_ctx* c, Lane& L, const IterArgs& a, int M) {
+  const IterArgs ab[2] = {a, swapped(a)};
   if (c->tn.use_graph && L.s != nullptr) {
     if (!L.gexec || L.g_iters != M || L.g_pad != a.lds_pad) {
       drop_graph(L);
@@ -654,9 +672,8 @@ aqs_status launch_block(aqs_ctx* c, Lane& L, const IterArgs& a, int M) {
       hipGraph_t graph = nullptr;
       HIPCHK(hipStreamBeginCapture(L.s, hipStreamCaptureModeThreadLocal));
       for (int it = 0; it < M; ++it) {
-        launch_force(a, L.cur_ntiles, c->dim, L.s);
-        launch_control(a, L.s);
-        launch_update(a, L.cur_nblk, c->dim, L.s);
+        launch_force(ab[it & 1], L.cur_ntiles, c->dim, L.s);
+        launch_step(ab[it & 1], L.cur_nblk, c->dim, L.s);
       }
       const hipError_t ce = hipStreamEndCapture(L.s, &graph);
       if (ce != hipSuccess) {
@@ -675,9 +692,8 @@ aqs_status launch_block(aqs_ctx* c, Lane& L, const IterArgs& a, int M) {
     return AQS_OK;
   }
   for (int it = 0; it < M; ++it) {
-    launch_force(a, L.cur_ntiles, c->dim, L.s);
-    launch_control(a, L.s);
-    launch_update(a, L.cur_nblk, c->dim, L.s);
+    launch_force(ab[it & 1], L.cur_ntiles, c->dim, L.s);
+    launch_step(ab[it & 1], L.cur_nblk, c->dim, L.s);
   }
   return AQS_OK;
 }
@@ -803,14 +819,14 @@ aqs_status lane_launch(aqs_ctx* c, Lane& L, int32_t start_mode, bool allow_timed
   IterArgs a = iter_args(c, L);
   if (timed) a.tevals = c->evals + 1;   // atoms of the timed launches
   if (timed) {
+    const IterArgs ab[2] = {a, swapped(a)};
     for (int it = 0; it < M; ++it) {
-      // events bracket the force kernel alone and the update kernel alone
+      // events bracket the force kernel alone and the step kernel alone
       HIPCHK(hipEventRecord(L.ev[4 * it + 0], L.s));
-      launch_force(a, L.cur_ntiles, c->dim, L.s);
+      launch_force(ab[it & 1], L.cur_ntiles, c->dim, L.s);
       HIPCHK(hipEventRecord(L.ev[4 * it + 1], L.s));
-      launch_control(a, L.s);
       HIPCHK(hipEventRecord(L.ev[4 * it + 2], L.s));
-      launch_update(a, L.cur_nblk, c->dim, L.s);
+      launch_step(ab[it & 1], L.cur_nblk, c->dim, L.s);
       HIPCHK(hipEventRecord(L.ev[4 * it + 3], L.s));
     }
   } else {
@@ -1044,7 +1060,9 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   char* w = c->ws;
   c->d_geom = at<Geom>(w, lo.o_geom);
   c->d_state = at<State>(w, lo.o_state);
+  c->d_state2 = at<State>(w, lo.o_state2);
   c->cgst = at<CgState>(w, lo.o_cgst);
+  c->cgst2 = at<CgState>(w, lo.o_cgst2);
   c->pos4 = at<double4>(w, lo.o_pos4);
   c->vx = at<double>(w, lo.o_v[0]); c->vy = at<double>(w, lo.o_v[1]); c->vz = at<double>(w, lo.o_v[2]);
   c->fx = at<double>(w, lo.o_f[0]); c->fy = at<double>(w, lo.o_f[1]); c->fz = at<double>(w, lo.o_f[2]);
@@ -1055,7 +1073,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->nbp = at<uint2>(w, lo.o_nbp);
   c->fpart = at<double>(w, lo.o_fpart);
   c->upart = at<double>(w, lo.o_upart);
-  c->counter = at<uint32_t>(w, lo.o_counter);
+  c->upart2 = at<double>(w, lo.o_upart2);
   c->log = at<StepRecord>(w, lo.o_log);
   c->ccount = at<int32_t>(w, lo.o_ccount);
   c->cstart = at<int32_t>(w, lo.o_cstart);

@@ -99,7 +99,7 @@ struct Geom {
   double dgamma;      // fine strain increment
 };
 
-// dynamic per-slot state (written by the force kernel's last block)
+// dynamic per-slot state (written by the control)
 struct State {
   int64_t k;          // strain index: gamma = k * dgamma
   int64_t it;         // FIRE updates in the current minimisation
@@ -179,7 +179,15 @@ struct IterArgs {
   int32_t lds_pad;        // dynamic LDS bytes added to each force block (CU reservation)
   int32_t prio;           // 1: the critical chain of a live round (its waves issue first)
   const Geom* geom;
+  // State, conjugate-gradient state and displacement partials are
+  // double-buffered over the iterations of a block: an iteration reads the
+  // in buffers (state, cgst, upart) and writes the out buffers, and the host
+  // swaps the two for the next iteration.  Home (the first buffer) is where
+  // they are between blocks (blocks have an even number of iterations) and
+  // where slots outside the launch keep them.
   State* state;
+  State* state_out;
+  State* state_home;
   double4* pos4;
   double* vx; double* vy; double* vz;
   double* fx; double* fy; double* fz;
@@ -193,7 +201,7 @@ struct IterArgs {
   const int32_t* tord;        // list column -> atom: each tile's atoms by decreasing list length
   double* fpart;          // kForceParts per force tile (tile_off + tile)
   double* upart;          // 1 per global block (max displacement of the update)
-  uint32_t* counter;      // per slot, last-block detection
+  double* upart_out;
   unsigned long long* evals;  // atoms evaluated by force launches (statistics)
   unsigned long long* tevals; // ... by the launches timed with events (null: not timed)
   StepRecord* log;        // per slot, log_cap records
@@ -203,6 +211,7 @@ struct IterArgs {
   FireParams fire;
   CgParams cg;
   CgState* cgst;          // per slot (conjugate gradients)
+  CgState* cgst_out;
   int32_t minimizer;      // kMinFire or kMinCG: every slot of the launch
   double skin, rc_max;
   // learned start (null when unused)

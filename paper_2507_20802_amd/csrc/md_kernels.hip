@@ -334,26 +334,77 @@ __device__ __forceinline__ void atom_pairs_packed(const double4 pi, int ti, cons
 // PH_ENERGY: one more evaluation at the same positions that also sums the
 // energy and the shear virial, after which the pending outcome is recorded.
 
-__device__ void finish_min(const IterArgs& a, int rep, State& s, int status) {
-  StepRecord rec;
-  rec.iters = s.it;
-  rec.energy = s.E;
-  rec.max_f = s.fmax;
-  rec.sigma_xy = s.sxy;
-  rec.status = status;
-  rec.start = s.start_used;
-  if (s.step < a.log_cap) a.log[(int64_t)rep * a.log_cap + s.step] = rec;
+// Field-by-field copy of a slot state: an aggregate copy of the struct goes
+// through scratch memory, a round trip on the control's critical path.
+static_assert(sizeof(State) == 224, "copy_state copies every field of State");
+__device__ __forceinline__ void copy_state(State& d, const State& s) {
+  d.k = s.k;
+  d.it = s.it;
+  d.dt = s.dt;
+  d.alpha = s.alpha;
+  d.cv = s.cv;
+  d.cf = s.cf;
+  d.E = s.E;
+  d.fmax = s.fmax;
+  d.sxy = s.sxy;
+  d.ubound = s.ubound;
+  d.gamma_build = s.gamma_build;
+  d.E_plain = s.E_plain;
+  d.fmax_plain = s.fmax_plain;
+  d.lmean[0] = s.lmean[0];
+  d.lmean[1] = s.lmean[1];
+  d.lmean[2] = s.lmean[2];
+  d.npos = s.npos;
+  d.nneg = s.nneg;
+  d.restart = s.restart;
+  d.phase = s.phase;
+  d.status = s.status;
+  d.step = s.step;
+  d.n_steps = s.n_steps;
+  d.snap_dst = s.snap_dst;
+  d.do_snap = s.do_snap;
+  d.nc[0] = s.nc[0];
+  d.nc[1] = s.nc[1];
+  d.nc[2] = s.nc[2];
+  d.start_mode = s.start_mode;
+  d.start_used = s.start_used;
+  d.learn_ok = s.learn_ok;
+  d.pending = s.pending;
+  d.tiles_x = s.tiles_x;
+  d.ntiles = s.ntiles;
+  d.list_mode = s.list_mode;
+  d.resume_phase = s.resume_phase;
+  d.drops = s.drops;
+  d.sxy_prev = s.sxy_prev;
+}
+
+// End of a minimisation with the given status: the step record, the
+// snapshot slot's scalars, then the next fine step of the chain or the
+// finish.  owner: this block records (every block of the slot computes the
+// same new state; one of them writes what lives outside it).
+__device__ __forceinline__ void finish_min(const IterArgs& a, int rep, State& s, int status,
+                                           bool owner) {
+  if (owner && s.step < a.log_cap) {
+    StepRecord* rec = a.log + (int64_t)rep * a.log_cap + s.step;
+    rec->iters = s.it;
+    rec->energy = s.E;
+    rec->max_f = s.fmax;
+    rec->sigma_xy = s.sxy;
+    rec->status = status;
+    rec->start = s.start_used;
+  }
   // a fine step whose inherent structure carries less shear stress than the
   // one before: under growing shear an elastic branch only gains stress, so
   // this marks a plastic event (aqs_run_round with live = 2 reads it)
   if (status == 0) {
-    if (s.step >= 1 && rec.sigma_xy < s.sxy_prev) s.drops += 1;
-    s.sxy_prev = rec.sigma_xy;
+    if (s.step >= 1 && s.sxy < s.sxy_prev) s.drops += 1;
+    s.sxy_prev = s.sxy;
   }
   s.status = status;
   s.do_snap = (s.step == 0 && s.snap_dst >= 0) ? 1 : 0;
-  if (s.do_snap) {
-    State* d = a.state + s.snap_dst;
+  if (s.do_snap && owner) {
+    // the snapshot slot is not in the launch, so its state lives in the home buffer
+    State* d = a.state_home + s.snap_dst;
     d->k = s.k;
     d->E = s.E;
     d->fmax = s.fmax;
@@ -472,12 +523,14 @@ __device__ bool control_cg(const CgParams& c, CgState& q, double fmx, int64_t it
   return true;
 }
 
+// The control of one iteration from the slot's sums r: advances the slot's
+// state s and conjugate-gradient state q in place (owner: this block writes
+// the records, see finish_min).
 template <bool CG>
-__device__ void control(const IterArgs& a, int rep, const Geom& g, const double* r, int phase,
-                        State s) {
+__device__ __forceinline__ void control(const IterArgs& a, int rep, const Geom& g, const double* r,
+                                        int phase, State& s, CgState& q, bool owner) {
   if (phase == PH_FINISH || phase == PH_STOP) {
     s.phase = PH_DONE;
-    a.state[rep] = s;
     return;
   }
   // Validity of the neighbour list.  With r_i = F x_ref,i + u_i (F the shear
@@ -493,7 +546,6 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
                          ? phase
                          : (cg ? PH_CG : PH_FIRE);
     s.phase = PH_REBUILD;
-    a.state[rep] = s;
     return;
   }
   s.ubound = ub;
@@ -504,12 +556,11 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     if (phase == PH_EVAL) {
       s.phase = PH_DONE;
     } else if (s.pending == 1) {  // max_iter reached: record, then apply the last step
-      finish_min(a, rep, s, 1);
+      finish_min(a, rep, s, 1, owner);
       s.phase = PH_STOP;
     } else {
-      finish_min(a, rep, s, s.pending);
+      finish_min(a, rep, s, s.pending, owner);
     }
-    a.state[rep] = s;
     return;
   }
   // learned start: the plain start's E and max |F| are the reference; the
@@ -519,7 +570,6 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     s.fmax_plain = s.fmax;
     if (s.learn_ok && r[6] == 0.0 && isfinite(r[0]) && isfinite(r[4])) {
       s.phase = PH_LMOVE;
-      a.state[rep] = s;
       return;
     }
     s.start_used = kStartFallback;
@@ -529,7 +579,6 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     if (worse) {
       s.start_used = kStartFallback;
       s.phase = PH_LREVERT;
-      a.state[rep] = s;
       return;
     }
     s.start_used = (s.start_mode == kStartExtrap) ? kStartExtrap : kStartLearned;
@@ -538,20 +587,16 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
   if (r[6] != 0.0 || !isfinite(r[1]) || !isfinite(r[2])) {
     s.E = NAN;
     s.sxy = NAN;
-    finish_min(a, rep, s, 3);
-    a.state[rep] = s;
+    finish_min(a, rep, s, 3, owner);
     return;
   }
   if (s.fmax < (cg ? a.cg.ftol : a.fire.ftol)) {
     s.pending = 0;
     s.phase = PH_ENERGY;
-    a.state[rep] = s;
     return;
   }
   if (cg) {
-    CgState q = a.cgst[rep];
     const bool going = control_cg(a.cg, q, s.fmax, s.it, r);
-    a.cgst[rep] = q;
     if (!going) {
       s.pending = 2;
       s.phase = PH_ENERGY;
@@ -562,7 +607,6 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
         s.phase = PH_ENERGY;  // energy at these positions, then the last step
       }
     }
-    a.state[rep] = s;
     return;
   }
   const FireParams& f = a.fire;
@@ -581,7 +625,6 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     if (s.nneg > f.n_neg_max) {
       s.pending = 2;
       s.phase = PH_ENERGY;
-      a.state[rep] = s;
       return;
     }
     if (!(f.initial_delay && s.it < f.n_delay)) {
@@ -605,7 +648,7 @@ __device__ void control(const IterArgs& a, int rep, const Geom& g, const double*
     s.pending = 1;
     s.phase = PH_ENERGY;  // energy at these positions, then the last step
   }
-  a.state[rep] = s;
+  return;
 }
 
 // ---------------------------------------------------------------------------
@@ -751,29 +794,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   }
 }
 
-// Per-slot reduction and FIRE control, one block per slot of the running
-// selection, launched after the force kernel (the kernel boundary makes the
-// tile partials visible; no device-scope fences inside the force kernel).
-// The tile partials are combined in tile order, then a fixed tree.
-template <bool CG>
-__global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
-  critical_priority(a);
-  const int rep = a.sel[blockIdx.x];
-  const State* stp = a.state + rep;
-  const int tid = threadIdx.x;
-  // the control's copy of the slot state, in flight while the partials are summed
-  State s0;
-  if (tid == 0) s0 = *stp;
-  const int phase = stp->phase;
-  const bool compute = phase_force(phase);
-  const bool counted = compute || phase == PH_FINISH || phase == PH_STOP;
-  if (!counted) return;
-  const Geom g = a.geom[rep];
-  const int ntiles = stp->ntiles;
-  // r: the tile partials 0-6, the update's max displacement, max |v_i|^2
-  __shared__ double red[kForceParts + 1][kBlock / kWave];
+// The slot's sums of one iteration, in thread 0: the force tiles' partials
+// in tile order, then a fixed tree (E, |F|^2, F.v, |v|^2, max |F_i|^2, W_xy,
+// non-finite), the update's max displacement (r[7], from upart) and max
+// |d_i|^2 (r[8]).  The kernel boundary after the force kernel makes the
+// partials visible; no device-scope fences inside the force kernel.
+__device__ __forceinline__ void slot_sums(const IterArgs& a, const Geom& g, int ntiles, bool compute,
+                                          double* r, double (*red)[kBlock / kWave]) {
   constexpr int ops[kForceParts + 1] = {0, 0, 0, 0, 1, 0, 1, 1, 1};
-  double r[kForceParts + 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < kForceParts + 1; ++c) r[c] = 0.0;
   if (compute) {
     for (int b = tid; b < ntiles; b += kBlock) {
       const double* src = a.fpart + ((int64_t)g.tile_off + b) * kForceParts;
@@ -789,44 +820,132 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
     for (int b = tid; b < g.nblocks; b += kBlock) r[7] = fmax(r[7], a.upart[g.block0 + b]);
   }
   block_reduce<kForceParts + 1>(r, ops, red);
+}
+
+// Control alone, one block per slot of the selection, the state updated in
+// place: the single force evaluation of aqs_energy_forces (PH_EVAL).
+template <bool CG>
+__global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
+  const int rep = a.sel[blockIdx.x];
+  const State* stp = a.state + rep;
+  const int tid = threadIdx.x;
+  State s0;
+  if (tid == 0) copy_state(s0, *stp);
+  const int phase = stp->phase;
+  const bool compute = phase_force(phase);
+  const bool counted = compute || phase == PH_FINISH || phase == PH_STOP;
+  if (!counted) return;
+  const Geom g = a.geom[rep];
+  __shared__ double red[kForceParts + 1][kBlock / kWave];
+  double r[kForceParts + 1];
+  slot_sums(a, g, stp->ntiles, compute, r, red);
   if (tid == 0) {
-    if (compute) {
-      atomicAdd(a.evals, (unsigned long long)g.n);
-      if (a.tevals) atomicAdd(a.tevals, (unsigned long long)g.n);
-    }
-    control<CG>(a, rep, g, r, phase, s0);
+    if (compute) atomicAdd(a.evals, (unsigned long long)g.n);
+    CgState q;
+    if (CG) q = a.cgst[rep];
+    control<CG>(a, rep, g, r, phase, s0, q, true);
+    copy_state(a.state[rep], s0);
+    if (CG) a.cgst[rep] = q;
   }
 }
 
 // ---------------------------------------------------------------------------
-// FIRE update (steps 5-9 of the minimiser), the conjugate-gradient move, or
-// the fine affine step of the chain, per atom; per-block max
-// |u_i| = |r_i - F x_ref,i| for the list test.
-
+// One iteration's control and move, after the force kernel.  Every block of
+// a slot sums the slot's tile partials and runs the control on them (the same
+// fixed-order sums, so every block reaches the same new state), then applies
+// to its 256 atoms the FIRE update (steps 5-9 of the minimiser), the
+// conjugate-gradient move, the fine affine step of the chain or the learned
+// start's move, and records its max |u_i| = |r_i - F x_ref,i| for the list
+// test.  State, conjugate-gradient state and displacement partials are
+// double-buffered: the blocks read a.state, a.cgst and a.upart and write
+// a.state_out, a.cgst_out (block 0 of the slot) and a.upart_out, and the host
+// swaps the two buffers from one iteration to the next, so no block reads
+// what another block of the same launch writes.  Every block of the table
+// writes its outputs, also when its slot is idle, so the out buffers always
+// hold the latest values.
 template <int D, bool CG>
-__global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
+__global__ __launch_bounds__(kBlock) void k_step(IterArgs a) {
   critical_priority(a);
   const int2 bt = a.blocks[blockIdx.x];
   const int rep = bt.x;
   if (rep < 0) return;
-  const State* st = a.state + rep;
-  const int phase = st->phase;
+  const int tid = threadIdx.x;
+  const bool owner = (bt.y == 0);
+  const State* sin = a.state + rep;
+  State s0;
+  if (tid == 0) copy_state(s0, *sin);
+  const int phase0 = sin->phase;
+  const int ntiles = sin->ntiles;
+  const Geom g = a.geom[rep];
+  const int ub = g.block0 + bt.y;
+  const bool compute = phase_force(phase0);
+  const bool counted = compute || phase0 == PH_FINISH || phase0 == PH_STOP;
+  if (!counted) {
+    // nothing to control or move: carry the slot over to the out buffers
+    if (tid == 0) {
+      a.upart_out[ub] = a.upart[ub];
+      if (owner) {
+        copy_state(a.state_out[rep], s0);
+        if (CG) a.cgst_out[rep] = a.cgst[rep];
+      }
+    }
+    return;
+  }
+  const int li = bt.y * kBlock + tid;
+  const bool mine = li < g.n;
+  const int64_t gi = g.atom_off + li;
+  // this thread's atom, in flight while the control runs
+  double4 p = make_double4(0.0, 0.0, 0.0, 0.0), x0 = p;
+  double vx = 0.0, vy = 0.0, vz = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+  if (mine) {
+    p = a.pos4[gi];
+    x0 = a.xref4[gi];
+    vx = a.vx[gi];
+    vy = a.vy[gi];
+    if (D == 3) vz = a.vz[gi];
+    fx = a.fx[gi];
+    fy = a.fy[gi];
+    if (D == 3) fz = a.fz[gi];
+  }
+  __shared__ double red[kForceParts + 1][kBlock / kWave];
+  __shared__ State ss;
+  __shared__ CgState sq;
+  {
+    double r[kForceParts + 1];
+    slot_sums(a, g, ntiles, compute, r, red);
+    if (tid == 0) {
+      CgState q;
+      if (CG) q = a.cgst[rep];
+      if (owner && compute) {
+        atomicAdd(a.evals, (unsigned long long)g.n);
+        if (a.tevals) atomicAdd(a.tevals, (unsigned long long)g.n);
+      }
+      control<CG>(a, rep, g, r, phase0, s0, q, owner);
+      copy_state(ss, s0);
+      if (CG) sq = q;
+      if (owner) {
+        copy_state(a.state_out[rep], s0);
+        if (CG) a.cgst_out[rep] = q;
+      }
+    }
+    __syncthreads();
+  }
+  const int phase = ss.phase;
   const bool fire = !CG && (phase == PH_FIRE || phase == PH_STOP);
   const bool cg = CG && (phase == PH_CG || phase == PH_STOP);
   const bool adv = (phase == PH_ADVANCE);
   // learned start: move to F r + dgamma (u_hat - mean u_hat), or back
   const bool lmove = (phase == PH_LMOVE || phase == PH_LREVERT);
-  if (!(fire || cg || adv || lmove || phase == PH_FINISH)) return;
-  const Geom g = a.geom[rep];
-  const int tid = threadIdx.x;
-  const int li = bt.y * kBlock + tid;
-  __shared__ double red[kForceParts][kBlock / kWave];
+  const bool moves = fire || cg || adv || lmove;
+  if (!moves) {
+    // no move: the displacement since the build is unchanged
+    if (tid == 0) a.upart_out[ub] = a.upart[ub];
+    if (phase != PH_FINISH) return;
+  }
   double m[1] = {0.0};
-  if (li < g.n) {
-    const int64_t gi = g.atom_off + li;
-    double4 p = a.pos4[gi];
-    if (st->do_snap && (adv || phase == PH_FINISH)) {  // first inherent structure -> snap_dst
-      const Geom gd = a.geom[st->snap_dst];
+  if (mine) {
+    if (ss.do_snap && (adv || phase == PH_FINISH)) {  // first inherent structure -> snap_dst
+      const Geom gd = a.geom[ss.snap_dst];
       const int64_t di = gd.atom_off + li;
       a.pos4[di] = p;
       const int32_t aid = a.id[gi];
@@ -834,10 +953,8 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       a.inv[gd.atom_off + aid] = li;
     }
     if (fire) {
-      const double dt = st->dt, cv = st->cv, cf = st->cf, dmax = a.fire.dmax;
-      double vx = a.vx[gi], vy = a.vy[gi], vz = (D == 3) ? a.vz[gi] : 0.0;
-      const double fx = a.fx[gi], fy = a.fy[gi], fz = (D == 3) ? a.fz[gi] : 0.0;
-      if (st->restart) {
+      const double dt = ss.dt, cv = ss.cv, cf = ss.cf, dmax = a.fire.dmax;
+      if (ss.restart) {
         p.x -= 0.5 * dt * vx;
         p.y -= 0.5 * dt * vy;
         if (D == 3) p.z -= 0.5 * dt * vz;
@@ -867,11 +984,9 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       if (D == 3) a.vz[gi] = vz;
     } else if (cg) {
       // conjugate gradients: d lives in v; a new direction also saves F0
-      const CgState* q = a.cgst + rep;
-      double dx = a.vx[gi], dy = a.vy[gi], dz = (D == 3) ? a.vz[gi] : 0.0;
-      if (q->newdir) {
-        const double fx = a.fx[gi], fy = a.fy[gi], fz = (D == 3) ? a.fz[gi] : 0.0;
-        const double b = q->beta;
+      double dx = vx, dy = vy, dz = vz;
+      if (sq.newdir) {
+        const double b = sq.beta;
         if (b == 0.0) {
           dx = fx;
           dy = fy;
@@ -888,7 +1003,7 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
         a.vy[gi] = dy;
         if (D == 3) a.vz[gi] = dz;
       }
-      const double da = q->step;
+      const double da = sq.step;
       p.x += da * dx;
       p.y += da * dy;
       if (D == 3) p.z += da * dz;
@@ -900,9 +1015,9 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       a.vy[gi] = 0.0;
       if (D == 3) a.vz[gi] = 0.0;
     } else if (lmove) {
-      const double ux = g.dgamma * (a.dlx[gi] - st->lmean[0]);
-      const double uy = g.dgamma * (a.dly[gi] - st->lmean[1]);
-      const double uz = (D == 3) ? g.dgamma * (a.dlz[gi] - st->lmean[2]) : 0.0;
+      const double ux = g.dgamma * (a.dlx[gi] - ss.lmean[0]);
+      const double uy = g.dgamma * (a.dly[gi] - ss.lmean[1]);
+      const double uz = (D == 3) ? g.dgamma * (a.dlz[gi] - ss.lmean[2]) : 0.0;
       if (phase == PH_LMOVE) {
         p.x += ux;
         p.y += uy;
@@ -915,17 +1030,16 @@ __global__ __launch_bounds__(kBlock) void k_update(IterArgs a) {
       }
       a.pos4[gi] = p;
     }
-    if (fire || cg || adv || lmove) {
-      const double4 x0 = a.xref4[gi];
-      const double gd = strain_of(st->k, g.dgamma) - st->gamma_build;
+    if (moves) {
+      const double gd = strain_of(ss.k, g.dgamma) - ss.gamma_build;
       const double ux = p.x - (x0.x + gd * x0.y), uy = p.y - x0.y, uz = p.z - x0.z;
       m[0] = sqrt(ux * ux + uy * uy + uz * uz);
     }
   }
-  if (fire || cg || adv || lmove) {
+  if (moves) {
     const int op[1] = {1};
     block_reduce<1>(m, op, red);
-    if (tid == 0) a.upart[g.block0 + bt.y] = m[0];
+    if (tid == 0) a.upart_out[ub] = m[0];
   }
 }
 
@@ -992,19 +1106,19 @@ void launch_control(const IterArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_control<false>, dim3(a.nsel), dim3(kBlock), 0, s, a);
 }
 
-void launch_update(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
+void launch_step(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
   if (nblk <= 0) return;
   const bool cg = (a.minimizer == kMinCG);
   if (dim == 3) {
     if (cg)
-      hipLaunchKernelGGL((k_update<3, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_step<3, true>), dim3(nblk), dim3(kBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((k_update<3, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_step<3, false>), dim3(nblk), dim3(kBlock), 0, s, a);
   } else {
     if (cg)
-      hipLaunchKernelGGL((k_update<2, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_step<2, true>), dim3(nblk), dim3(kBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((k_update<2, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_step<2, false>), dim3(nblk), dim3(kBlock), 0, s, a);
   }
 }
 
