@@ -49,9 +49,8 @@ double rc_max_of(const aqs_potential* p) {
   return m;
 }
 
-// Blocks of one launch are dealt to the XCDs round robin (hardware block b
-// runs on XCD b mod 8); a launch table places each entry by that rule.
-constexpr int kXcds = 8;
+// A launch table places each entry on an XCD by the round-robin rule of
+// kXcds (engine.h).
 constexpr uint32_t kAllXcds = (1u << kXcds) - 1u;
 
 // force tiles hold about fill x a block's atom lanes (tuning.tile_fill)
@@ -347,6 +346,14 @@ IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   a.tpa = c->tn.tpa;
   a.lds_pad = batch_pad(c, L);
   a.prio = (c->live && &L == &c->ln[1]) ? 1 : 0;
+  a.one_rep = -1;
+  if (L.cur_sel.size() == 1 && L.xcd_mask == kAllXcds) {
+    const int r = L.cur_sel[0];
+    a.one_rep = r;
+    a.one_ntiles = c->tiles_now[r];
+    a.one_nblk = c->lo.geom[r].nblocks;
+    a.one_tile0 = c->lo.geom[r].tile_off;
+  }
   a.geom = c->d_geom;
   a.state = c->d_state;
   a.state_out = c->d_state2;

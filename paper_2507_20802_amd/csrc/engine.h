@@ -47,6 +47,18 @@ constexpr uint32_t kIdxMask = 0x00FFFFFFu;
 constexpr int kCodeShift = 24;
 constexpr int kGroup = 4;             // entries per 8-byte group of the packed list
 constexpr int kListAlign = 32;        // max_nb is a multiple of kGroup x kMaxTPA
+// Blocks of one launch are dealt to the XCDs (dies, each with its own L2)
+// round robin: hardware block b runs on XCD b mod kXcds.
+constexpr int kXcds = 8;
+
+// Item of hardware block b in a launch over the n items of one slot, placed
+// like the launch tables over all XCDs: each XCD takes a contiguous run of
+// ceil(n / kXcds) items.  -1: no item (the block exits).
+__host__ __device__ inline int one_slot_item(int b, int n) {
+  const int per = (n + kXcds - 1) / kXcds;
+  const int t = (b % kXcds) * per + b / kXcds;
+  return t < n ? t : -1;
+}
 
 // phases of a slot's device state machine
 enum Phase : int32_t {
@@ -178,6 +190,12 @@ struct IterArgs {
   int32_t tpa;            // threads per atom of the force kernel
   int32_t lds_pad;        // dynamic LDS bytes added to each force block (CU reservation)
   int32_t prio;           // 1: the critical chain of a live round (its waves issue first)
+  // a lane of one slot over all XCDs: the iteration kernels compute their
+  // launch-table entries (one_slot_item) instead of loading them
+  int32_t one_rep;        // the slot, or -1: load the tables
+  int32_t one_ntiles;     // its force tiles (current grid)
+  int32_t one_nblk;       // its 256-atom blocks
+  int32_t one_tile0;      // its first global tile index
   const Geom* geom;
   // State, conjugate-gradient state and displacement partials are
   // double-buffered over the iterations of a block: an iteration reads the

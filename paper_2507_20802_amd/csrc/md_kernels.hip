@@ -459,6 +459,7 @@ __device__ __forceinline__ void finish_min(const IterArgs& a, int rep, State& s,
 // Returns false if the minimisation has stalled.
 __device__ bool control_cg(const CgParams& c, CgState& q, double fmx, int64_t it,
                            const double* r) {
+#pragma clang fp contract(off)
   if (it == 0) {  // first evaluation of a minimisation
     q.dir = 0;
     q.nfail = 0;
@@ -529,6 +530,9 @@ __device__ bool control_cg(const CgParams& c, CgState& q, double fmx, int64_t it
 template <bool CG>
 __device__ __forceinline__ void control(const IterArgs& a, int rep, const Geom& g, const double* r,
                                         int phase, State& s, CgState& q, bool owner) {
+  // written-out arithmetic only (no fused multiply-adds): the control's
+  // rounding does not depend on where the compiler keeps the state
+#pragma clang fp contract(off)
   if (phase == PH_FINISH || phase == PH_STOP) {
     s.phase = PH_DONE;
     return;
@@ -724,9 +728,15 @@ __device__ __forceinline__ void critical_priority(const IterArgs& a) {
 template <int D, int TPA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_force(IterArgs a) {
   critical_priority(a);
-  // (slot, global tile index), read in one load
-  const uint64_t ent = reinterpret_cast<const uint64_t*>(a.ftiles)[blockIdx.x];
-  const int2 bt = make_int2((int)(uint32_t)ent, (int)(uint32_t)(ent >> 32));
+  // (slot, global tile index): computed for a lane of one slot, else read in one load
+  int2 bt;
+  if (a.one_rep >= 0) {
+    const int t = one_slot_item(blockIdx.x, a.one_ntiles);
+    bt = make_int2(t < 0 ? -1 : a.one_rep, a.one_tile0 + t);
+  } else {
+    const uint64_t ent = reinterpret_cast<const uint64_t*>(a.ftiles)[blockIdx.x];
+    bt = make_int2((int)(uint32_t)ent, (int)(uint32_t)(ent >> 32));
+  }
   const int rep = bt.x;
   if (rep < 0) return;
   const int tid = threadIdx.x;
@@ -794,14 +804,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
   }
 }
 
-// The slot's sums of one iteration, in thread 0: the force tiles' partials
-// in tile order, then a fixed tree (E, |F|^2, F.v, |v|^2, max |F_i|^2, W_xy,
-// non-finite), the update's max displacement (r[7], from upart) and max
-// |d_i|^2 (r[8]).  The kernel boundary after the force kernel makes the
-// partials visible; no device-scope fences inside the force kernel.
-__device__ __forceinline__ void slot_sums(const IterArgs& a, const Geom& g, int ntiles, bool compute,
-                                          double* r, double (*red)[kBlock / kWave]) {
-  constexpr int ops[kForceParts + 1] = {0, 0, 0, 0, 1, 0, 1, 1, 1};
+// The slot's sums of one iteration: each thread's share of the force
+// tiles' partials (E, |F|^2, F.v, |v|^2, max |F_i|^2, W_xy, non-finite, max
+// |d_i|^2 in r[8]) and of the update's max displacements (r[7], from upart),
+// in tile order; slot_reduce then combines the threads by a fixed tree
+// (result in thread 0).  The kernel boundary after the force kernel makes
+// the partials visible; no device-scope fences inside the force kernel.
+__device__ __forceinline__ void slot_partials(const IterArgs& a, const Geom& g, int ntiles,
+                                              bool compute, double* r) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int c = 0; c < kForceParts + 1; ++c) r[c] = 0.0;
@@ -819,6 +829,10 @@ __device__ __forceinline__ void slot_sums(const IterArgs& a, const Geom& g, int 
     }
     for (int b = tid; b < g.nblocks; b += kBlock) r[7] = fmax(r[7], a.upart[g.block0 + b]);
   }
+}
+
+__device__ __forceinline__ void slot_reduce(double* r, double (*red)[kBlock / kWave]) {
+  constexpr int ops[kForceParts + 1] = {0, 0, 0, 0, 1, 0, 1, 1, 1};
   block_reduce<kForceParts + 1>(r, ops, red);
 }
 
@@ -838,7 +852,8 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
   const Geom g = a.geom[rep];
   __shared__ double red[kForceParts + 1][kBlock / kWave];
   double r[kForceParts + 1];
-  slot_sums(a, g, stp->ntiles, compute, r, red);
+  slot_partials(a, g, stp->ntiles, compute, r);
+  slot_reduce(r, red);
   if (tid == 0) {
     if (compute) atomicAdd(a.evals, (unsigned long long)g.n);
     CgState q;
@@ -862,18 +877,35 @@ __global__ __launch_bounds__(kBlock) void k_control(IterArgs a) {
 // swaps the two buffers from one iteration to the next, so no block reads
 // what another block of the same launch writes.  Every block of the table
 // writes its outputs, also when its slot is idle, so the out buffers always
-// hold the latest values.
-template <int D, bool CG>
+// hold the latest values.  The states pass through LDS one dword per thread
+// (the control, in thread 0, works on the LDS copy), which keeps the kernel's
+// registers, and so its blocks per CU, for the batch.  PF: the atoms' data
+// are loaded before the control (a lane of one slot, latency-bound); without
+// it they are loaded after it, with fewer registers held meanwhile.
+constexpr int kStateWords = (int)(sizeof(State) / 4);
+constexpr int kCgWords = (int)(sizeof(CgState) / 4);
+static_assert(sizeof(State) % 4 == 0 && sizeof(CgState) % 4 == 0 && kStateWords <= kBlock &&
+                  kCgWords <= kBlock, "states move as dwords, one per thread");
+
+template <int D, bool CG, bool PF>
 __global__ __launch_bounds__(kBlock) void k_step(IterArgs a) {
   critical_priority(a);
-  const int2 bt = a.blocks[blockIdx.x];
+  int2 bt;
+  if (a.one_rep >= 0) {
+    const int b = one_slot_item(blockIdx.x, a.one_nblk);
+    bt = make_int2(b < 0 ? -1 : a.one_rep, b);
+  } else {
+    bt = a.blocks[blockIdx.x];
+  }
   const int rep = bt.x;
   if (rep < 0) return;
   const int tid = threadIdx.x;
   const bool owner = (bt.y == 0);
   const State* sin = a.state + rep;
-  State s0;
-  if (tid == 0) copy_state(s0, *sin);
+  // this thread's dwords of the slot's state and conjugate-gradient state
+  uint32_t sw = 0u, qw = 0u;
+  if (tid < kStateWords) sw = reinterpret_cast<const uint32_t*>(sin)[tid];
+  if (CG && tid < kCgWords) qw = reinterpret_cast<const uint32_t*>(a.cgst + rep)[tid];
   const int phase0 = sin->phase;
   const int ntiles = sin->ntiles;
   const Geom g = a.geom[rep];
@@ -882,12 +914,10 @@ __global__ __launch_bounds__(kBlock) void k_step(IterArgs a) {
   const bool counted = compute || phase0 == PH_FINISH || phase0 == PH_STOP;
   if (!counted) {
     // nothing to control or move: carry the slot over to the out buffers
-    if (tid == 0) {
-      a.upart_out[ub] = a.upart[ub];
-      if (owner) {
-        copy_state(a.state_out[rep], s0);
-        if (CG) a.cgst_out[rep] = a.cgst[rep];
-      }
+    if (tid == 0) a.upart_out[ub] = a.upart[ub];
+    if (owner) {
+      if (tid < kStateWords) reinterpret_cast<uint32_t*>(a.state_out + rep)[tid] = sw;
+      if (CG && tid < kCgWords) reinterpret_cast<uint32_t*>(a.cgst_out + rep)[tid] = qw;
     }
     return;
   }
@@ -897,39 +927,44 @@ __global__ __launch_bounds__(kBlock) void k_step(IterArgs a) {
   // this thread's atom, in flight while the control runs
   double4 p = make_double4(0.0, 0.0, 0.0, 0.0), x0 = p;
   double vx = 0.0, vy = 0.0, vz = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-  if (mine) {
-    p = a.pos4[gi];
-    x0 = a.xref4[gi];
-    vx = a.vx[gi];
-    vy = a.vy[gi];
-    if (D == 3) vz = a.vz[gi];
-    fx = a.fx[gi];
-    fy = a.fy[gi];
-    if (D == 3) fz = a.fz[gi];
-  }
+  auto load_atom = [&]() {
+    if (mine) {
+      p = a.pos4[gi];
+      x0 = a.xref4[gi];
+      vx = a.vx[gi];
+      vy = a.vy[gi];
+      if (D == 3) vz = a.vz[gi];
+      fx = a.fx[gi];
+      fy = a.fy[gi];
+      if (D == 3) fz = a.fz[gi];
+    }
+  };
+  if (PF) load_atom();
   __shared__ double red[kForceParts + 1][kBlock / kWave];
   __shared__ State ss;
   __shared__ CgState sq;
   {
     double r[kForceParts + 1];
-    slot_sums(a, g, ntiles, compute, r, red);
+    slot_partials(a, g, ntiles, compute, r);
+    if (tid < kStateWords) reinterpret_cast<uint32_t*>(&ss)[tid] = sw;
+    if (CG && tid < kCgWords) reinterpret_cast<uint32_t*>(&sq)[tid] = qw;
+    slot_reduce(r, red);   // its barriers also publish ss and sq
     if (tid == 0) {
-      CgState q;
-      if (CG) q = a.cgst[rep];
       if (owner && compute) {
         atomicAdd(a.evals, (unsigned long long)g.n);
         if (a.tevals) atomicAdd(a.tevals, (unsigned long long)g.n);
       }
-      control<CG>(a, rep, g, r, phase0, s0, q, owner);
-      copy_state(ss, s0);
-      if (CG) sq = q;
-      if (owner) {
-        copy_state(a.state_out[rep], s0);
-        if (CG) a.cgst_out[rep] = q;
-      }
+      control<CG>(a, rep, g, r, phase0, ss, sq, owner);
     }
     __syncthreads();
   }
+  if (owner) {
+    if (tid < kStateWords)
+      reinterpret_cast<uint32_t*>(a.state_out + rep)[tid] = reinterpret_cast<const uint32_t*>(&ss)[tid];
+    if (CG && tid < kCgWords)
+      reinterpret_cast<uint32_t*>(a.cgst_out + rep)[tid] = reinterpret_cast<const uint32_t*>(&sq)[tid];
+  }
+  if (!PF) load_atom();
   const int phase = ss.phase;
   const bool fire = !CG && (phase == PH_FIRE || phase == PH_STOP);
   const bool cg = CG && (phase == PH_CG || phase == PH_STOP);
@@ -1106,19 +1141,28 @@ void launch_control(const IterArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_control<false>, dim3(a.nsel), dim3(kBlock), 0, s, a);
 }
 
+template <int D, bool CG>
+void launch_step_d(const IterArgs& a, int32_t nblk, hipStream_t s) {
+  // a lane of one slot is latency-bound: its atoms' data load during the control
+  if (a.one_rep >= 0)
+    hipLaunchKernelGGL((k_step<D, CG, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_step<D, CG, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+}
+
 void launch_step(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
   if (nblk <= 0) return;
   const bool cg = (a.minimizer == kMinCG);
   if (dim == 3) {
     if (cg)
-      hipLaunchKernelGGL((k_step<3, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+      launch_step_d<3, true>(a, nblk, s);
     else
-      hipLaunchKernelGGL((k_step<3, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+      launch_step_d<3, false>(a, nblk, s);
   } else {
     if (cg)
-      hipLaunchKernelGGL((k_step<2, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+      launch_step_d<2, true>(a, nblk, s);
     else
-      hipLaunchKernelGGL((k_step<2, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+      launch_step_d<2, false>(a, nblk, s);
   }
 }
 
