@@ -171,13 +171,47 @@ def box_matrix(dim: int, L, gamma: float) -> np.ndarray:
     return H
 
 
-def strain_box(dim: int, L, k: int, dgamma: float) -> np.ndarray:
-    """Box at strain index k: gamma = k * dgamma, computed in one product so
-    that equal indices give bit-identical boxes."""
+def strain_box(dim: int, L, k: int, dgamma: float, dgamma_y: float = 0.0) -> np.ndarray:
+    """Box at strain index k.  Simple shear (dgamma_y = 0): gamma = k * dgamma,
+    computed in one product so that equal indices give bit-identical boxes.
+    Pure shear (Eq. 17, dgamma_y != 0): H_k = F^k diag(L) with
+    F = [[1, dgamma], [dgamma_y, 1]] acting on (x, y) and z unchanged, F^k by
+    deformation_power."""
     Ls = np.broadcast_to(np.asarray(L, dtype=np.float64), (dim,))
     H = np.diag(Ls).astype(np.float64)
-    H[0, 1] = (float(k) * dgamma) * Ls[1]
+    if dgamma_y == 0.0:
+        H[0, 1] = (float(k) * dgamma) * Ls[1]
+        return H
+    M = deformation_power(dgamma, dgamma_y, k)
+    H[0, 0] = M[0][0] * Ls[0]
+    H[0, 1] = M[0][1] * Ls[1]
+    H[1, 0] = M[1][0] * Ls[0]
+    H[1, 1] = M[1][1] * Ls[1]
     return H
+
+
+def deformation_power(a: float, b: float, k: int):
+    """F^k for the 2x2 map F = [[1, a], [b, 1]] of Eq. (17), k >= 0, as nested
+    lists of Python floats (FP64, no fused operations).  Square and multiply
+    over the bits of k from the lowest: R <- R B when the bit is set, then
+    B <- B B; each entry of a product is X[i][0] Y[0][j] + X[i][1] Y[1][j].
+    Pinned by repeated multiplication, the eigenvalues 1 +- sqrt(ab), the
+    determinant (1 - ab)^k and the simple-shear case b = 0 (F^k = [[1, ka], [0, 1]])."""
+    if k < 0:
+        raise ValueError("the strain index of a pure shear must be >= 0")
+
+    def mul(X, Y):
+        return [[X[0][0] * Y[0][0] + X[0][1] * Y[1][0], X[0][0] * Y[0][1] + X[0][1] * Y[1][1]],
+                [X[1][0] * Y[0][0] + X[1][1] * Y[1][0], X[1][0] * Y[0][1] + X[1][1] * Y[1][1]]]
+
+    R = [[1.0, 0.0], [0.0, 1.0]]
+    B = [[1.0, float(a)], [float(b), 1.0]]
+    while k:
+        if k & 1:
+            R = mul(R, B)
+        B = mul(B, B)
+        k >>= 1
+    return R
 
 
 def pair(pot: Potential, ti: int, tj: int, r: float):
@@ -207,7 +241,7 @@ def energy_forces(pos: np.ndarray, types: np.ndarray, H: np.ndarray, pot: Potent
                         ctypes.byref(pot.c(dim)), 1 if image_sum else 0, int(image_range),
                         ctypes.byref(E), _d(F), _d(S), _d(ea))
     if rc != 0:
-        raise ValueError(f"orc_eval failed ({rc}): box not upper triangular or too small for the cutoff")
+        raise ValueError(f"orc_eval failed ({rc}): box with a z coupling or too small for the cutoff")
     return E.value, F, S, ea
 
 
@@ -230,13 +264,21 @@ def min_image_valid(H: np.ndarray, pot: Potential) -> bool:
     return bool(lib().orc_min_image_valid(dim, _d(np.ascontiguousarray(H, dtype=np.float64)), ctypes.byref(pot.c(dim))))
 
 
-def affine(pos: np.ndarray, dgamma: float) -> np.ndarray:
-    """x_i <- x_i + dgamma y_i (Eqs. 2-3, 16).  Returns a new array.  Pinned by
-    the composition law F(a) F(b) = F(a + b) and the energy invariance under
-    a shear by a full box period."""
+def affine(pos: np.ndarray, dgamma: float, dgamma_y: float = 0.0, steps: int = 1) -> np.ndarray:
+    """The affine map of `steps` increments.  Simple shear (dgamma_y = 0):
+    x_i <- x_i + (steps dgamma) y_i (Eqs. 2-3, 16).  Pure shear (Eq. 17):
+    (x_i, y_i) <- F^steps (x_i, y_i), z unchanged.  Returns a new array.
+    Pinned by the composition law F(a) F(b) = F(a + b), the energy invariance
+    under a shear by a full box period and, for the pure shear, the box
+    sequence (fractional coordinates unchanged)."""
     out = np.ascontiguousarray(pos, dtype=np.float64).copy()
     n, dim = out.shape
-    lib().orc_affine(dim, n, _d(out), ctypes.c_double(dgamma))
+    if dgamma_y == 0.0:
+        lib().orc_affine(dim, n, _d(out), ctypes.c_double(float(steps) * dgamma if steps != 1 else dgamma))
+        return out
+    M = deformation_power(dgamma, dgamma_y, steps)
+    Mc = np.ascontiguousarray([M[0][0], M[0][1], M[1][0], M[1][1]], dtype=np.float64)
+    lib().orc_linear_xy(dim, n, _d(out), _d(Mc))
     return out
 
 

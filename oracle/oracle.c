@@ -18,7 +18,8 @@
  * Conventions
  *   pos    atom-major, pos[i*dim + a], a = x, y (, z)
  *   H      dim x dim, row-major, columns are the Bravais vectors h_1..h_d
- *          (Sec. 2.1, "Formalism"); simple shear keeps H upper triangular
+ *          (Sec. 2.1, "Formalism"); simple shear keeps H upper triangular,
+ *          the pure shear of Eq. (17) gives a general (x, y) block
  *   type   0 (A) or 1 (B)
  */
 #include <math.h>
@@ -120,6 +121,14 @@ static int upper_triangular(int dim, const double* H) {
   return 1;
 }
 
+/* The boxes here: upper triangular (simple shear), or a general (x, y)
+ * block with z neutral (the pure shear of Eq. 17, whose map also has a
+ * lower off-diagonal entry).  A z coupling is not supported.               */
+static int supported_box(int dim, const double* H) {
+  if (dim == 2) return 1;
+  return H[2] == 0.0 && H[5] == 0.0 && H[6] == 0.0 && H[7] == 0.0;
+}
+
 /* inverse of an upper-triangular matrix by back substitution */
 static void inv_upper(int dim, const double* H, double* Hi) {
   memset(Hi, 0, sizeof(double) * dim * dim);
@@ -141,11 +150,34 @@ static double det_upper(int dim, const double* H) {
   return d;
 }
 
+/* Inverse and determinant of a supported box: back substitution when upper
+ * triangular, else the 2x2 (x, y) block by its adjugate (and 1/Lz).         */
+static void inv_box(int dim, const double* H, double* Hi) {
+  if (upper_triangular(dim, H)) {
+    inv_upper(dim, H, Hi);
+    return;
+  }
+  memset(Hi, 0, sizeof(double) * dim * dim);
+  const double a = H[0], b = H[1], c = H[dim], d = H[dim + 1];
+  const double det = a * d - b * c;
+  Hi[0] = d / det;
+  Hi[1] = -b / det;
+  Hi[dim] = -c / det;
+  Hi[dim + 1] = a / det;
+  if (dim == 3) Hi[8] = 1.0 / H[8];
+}
+
+static double det_box(int dim, const double* H) {
+  if (upper_triangular(dim, H)) return det_upper(dim, H);
+  const double d2 = H[0] * H[dim + 1] - H[1] * H[dim];
+  return dim == 3 ? d2 * H[8] : d2;
+}
+
 /* Perpendicular widths of the cell spanned by the columns of H: the distance
  * between the two faces that do not contain h_a, i.e. |det H| / |area of the
  * other vectors|.                                                           */
 void orc_perp_widths(int dim, const double* H, double* w) {
-  double vol = fabs(det_upper(dim, H));
+  double vol = fabs(det_box(dim, H));
   if (dim == 2) {
     double h0 = sqrt(H[0] * H[0] + H[2] * H[2]);
     double h1 = sqrt(H[1] * H[1] + H[3] * H[3]);
@@ -288,11 +320,11 @@ int orc_eval(int dim, int n, const double* pos, const uint8_t* type,
              const double* H, const orc_pot* p, int image_mode,
              int image_range, double* E, double* F, double* S,
              double* e_atom) {
-  if (!upper_triangular(dim, H)) return -1;
+  if (!supported_box(dim, H)) return -1;
   if (image_mode == 0 && !orc_min_image_valid(dim, H, p)) return -2;
   double Hi[9];
-  inv_upper(dim, H, Hi);
-  const double vol = fabs(det_upper(dim, H));
+  inv_box(dim, H, Hi);
+  const double vol = fabs(det_box(dim, H));
   pair_table tab;
   make_table(p, &tab);
 
@@ -342,10 +374,10 @@ int orc_eval(int dim, int n, const double* pos, const uint8_t* type,
 int orc_forces_on(int dim, int n, const double* pos, const uint8_t* type,
                   const double* H, const orc_pot* p, int nsel,
                   const int64_t* sel, double* F) {
-  if (!upper_triangular(dim, H)) return -1;
+  if (!supported_box(dim, H)) return -1;
   if (!orc_min_image_valid(dim, H, p)) return -2;
   double Hi[9];
-  inv_upper(dim, H, Hi);
+  inv_box(dim, H, Hi);
   pair_table tab;
   make_table(p, &tab);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -374,6 +406,16 @@ int orc_forces_on(int dim, int n, const double* pos, const uint8_t* type,
  * and leaves z alone.  The caller updates the box H <- F H.                 */
 void orc_affine(int dim, int n, double* pos, double dgamma) {
   for (int i = 0; i < n; ++i) pos[i * dim + 0] += dgamma * pos[i * dim + 1];
+}
+
+/* A general linear map of (x, y), z unchanged: r_i <- M r_i with M row-major
+ * 2x2 (the pure shear of Eq. 17 and its powers).                            */
+void orc_linear_xy(int dim, int n, double* pos, const double* M) {
+  for (int i = 0; i < n; ++i) {
+    const double x = pos[i * dim + 0], y = pos[i * dim + 1];
+    pos[i * dim + 0] = M[0] * x + M[1] * y;
+    pos[i * dim + 1] = M[2] * x + M[3] * y;
+  }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -719,9 +761,9 @@ int orc_cg_quadratic(int dim, int n, double* x, const double* kk, const orc_cg_p
  * the same box, and the mean displacement vector (a rigid-translation check).*/
 int orc_compare(int dim, int n, const double* a, const double* b,
                 const double* H, double* max_disp, double* mean_disp) {
-  if (!upper_triangular(dim, H)) return -1;
+  if (!supported_box(dim, H)) return -1;
   double Hi[9];
-  inv_upper(dim, H, Hi);
+  inv_box(dim, H, Hi);
   double m = 0.0, mean[3] = {0, 0, 0};
   for (int i = 0; i < n; ++i) {
     double d[3] = {0, 0, 0};
