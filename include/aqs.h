@@ -5,7 +5,8 @@
  * deformation stepping of molecular systems", arXiv 2507.20802.
  *
  * One context holds a batch of independent replicas ("slots") of a binary
- * Lennard-Jones system in a periodic, simply sheared box.  The calls below
+ * Lennard-Jones system in a periodic, simply sheared box (or, per slot, a
+ * pure-sheared one, Eq. 17).  The calls below
  * are the operators of the paper, applied to any subset of slots at once:
  *
  *   aqs_affine_shear     F_N^(dk * dgamma), Eqs. (2), (3), (16)
@@ -24,7 +25,9 @@
  *     order; the device keeps its own cell-sorted order internally.
  *   - Box: the unstrained box of slot r is diag(L_r); at strain index k the
  *     box is H = F^(gamma) diag(L_r) with gamma = k * dgamma_r computed in one
- *     product, columns (Lx,0,0), (gamma*Ly, Ly, 0), (0,0,Lz) (Eq. 1).
+ *     product, columns (Lx,0,0), (gamma*Ly, Ly, 0), (0,0,Lz) (Eq. 1); for a
+ *     slot set to the pure shear of Eq. (17) (aqs_set_pure_shear) it is
+ *     F^k diag(L_r) with F acting on (x, y); aqs_get_box returns it.
  *   - Calls that return values to the host synchronise the context's stream;
  *     the others are stream-ordered on it.
  *   - No call throws.  A return value < 0 is an error; aqs_last_error()
@@ -186,15 +189,22 @@ aqs_status aqs_get_positions(aqs_ctx* ctx, int32_t rep, double* pos);
 
 aqs_status aqs_get_strain_index(aqs_ctx* ctx, int32_t rep, int64_t* k);
 
+/* Bravais tensor of slot rep at its current strain index (Eq. 1; columns are
+ * the box vectors), dim x dim row-major into the host array H: simple shear
+ * (Eq. 16) or the slot's pure shear (Eq. 17, aqs_set_pure_shear). */
+aqs_status aqs_get_box(aqs_ctx* ctx, int32_t rep, double* H);
+
 /* Copy slot src into slot dst (same atom count): positions, types, order,
  * strain index and last energy.  Level I anchors and snapshots. */
 aqs_status aqs_copy_replica(aqs_ctx* ctx, int32_t src, int32_t dst);
 
 /* Affine simple shear of the selected slots, Eqs. (2)-(3) with Eq. (16):
  * x_i += (dk_r * dgamma_r) y_i in one multiplication (level I uses
- * dk = i K, Eq. 18), and k_r += dk_r so the box follows (Eq. 1).  rep[n_sel],
- * dk[n_sel] are host arrays of distinct slots (AQS_EINVAL, nothing changed,
- * if a slot is listed twice).  Stream-ordered. */
+ * dk = i K, Eq. 18), and k_r += dk_r so the box follows (Eq. 1).  A slot set
+ * to pure shear (aqs_set_pure_shear) takes (x_i, y_i) <- F^dk (x_i, y_i)
+ * instead, dk >= 0 only.  rep[n_sel], dk[n_sel] are host arrays of distinct
+ * slots (AQS_EINVAL, nothing changed, if a slot is listed twice or a pure
+ * shear would go backwards).  Stream-ordered. */
 aqs_status aqs_affine_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
                             const int64_t* dk);
 
@@ -271,6 +281,27 @@ aqs_status aqs_set_live_batch_blocks(aqs_ctx* ctx, int32_t blocks);
 /* Change the tuning field live_xcds of ctx for later live rounds (0-7,
  * AQS_EINVAL otherwise).  Changes no result. */
 aqs_status aqs_set_live_xcds(aqs_ctx* ctx, int32_t xcds);
+
+/* The deformation of the selected slots: dgamma_y[i] = 0 keeps the simple
+ * shear of Eq. (16); otherwise the pure (pull-push) shear of Eq. (17),
+ * F = [[1, dgamma_r], [dgamma_y, 1]] acting on (x, y) (z unchanged, also in
+ * 3D), dgamma_r the slot's increment from aqs_create.  The box at strain
+ * index k is then H_k = F^k diag(Lx, Ly[, Lz]), F^k formed by square and
+ * multiply over the bits of k (from the lowest bit: R <- R B if set, then
+ * B <- B B) without fused multiply-adds, so that any plain FP64 evaluation in
+ * that order gives the same box; the fine affine step of a chain is
+ * (x, y) <- F (x, y), the level-I step F^dk (aqs_affine_shear), the learned
+ * and extrapolated starts use the same map and take dgamma_r as the strain of
+ * a step, and the stress divides by the deformed volume |det H_k|.  The
+ * strain index of a pure-shear slot stays >= 0.  Positions given to
+ * aqs_set_replica or aqs_set_positions afterwards are read in the box of the
+ * slot's mode at its strain index.  Copies, comparisons, snapshots and
+ * learned targets need slots of the same mode.  rep[n_sel], dgamma_y[n_sel]:
+ * host arrays; the slots must not be running (AQS_ESTATE otherwise);
+ * AQS_EINVAL for a slot out of range or a non-finite dgamma_y or
+ * |dgamma_r dgamma_y| >= 1 (F would not be invertible).  Synchronises. */
+aqs_status aqs_set_pure_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
+                              const double* dgamma_y);
 
 /* Outcome of check i of a round (Algorithm 1, Sec. 3.5): the end of chain
  * i-1 against the first inherent structure of chain i, Eq. (20). */

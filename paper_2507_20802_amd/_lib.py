@@ -99,6 +99,7 @@ SIGNATURES = {
     "aqs_set_positions": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p]),
     "aqs_get_positions": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p]),
     "aqs_get_strain_index": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int64_p]),
+    "aqs_get_box": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_double_p]),
     "aqs_copy_replica": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "aqs_affine_shear": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int32_p, c_int64_p]),
     "aqs_minimize_batch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int32_p, ctypes.c_int32,
@@ -113,6 +114,7 @@ SIGNATURES = {
     "aqs_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "aqs_set_live_batch_blocks": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "aqs_set_live_xcds": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "aqs_set_pure_shear": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int32_p, c_double_p]),
     "aqs_set_minimizer": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(aqs_cg_params)]),
     "aqs_get_counters": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_counters), ctypes.c_int32]),
     "aqs_learned_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_mlp)]),

@@ -85,13 +85,20 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   return r;
 }
 
-// Cells per axis of a slot's grid: the perpendicular width of the (sheared)
-// box divided by the list cutoff, at least 3 (the 3^dim stencil).
-void cell_grid(int dim, const double* L, double tilt, double rl, int* nc) {
-  const double wx = L[0] * L[1] / std::sqrt(L[1] * L[1] + tilt * tilt);
-  nc[0] = (int)std::floor(wx / rl);
-  nc[1] = (int)std::floor(L[1] / rl);
-  nc[2] = dim == 3 ? (int)std::floor(L[2] / rl) : 1;
+// Cells per axis of a slot's grid: the perpendicular width of the deformed
+// box along each Bravais vector (|det| over the length of the other edge in
+// the (x, y) block) divided by the list cutoff, at least 3 (the 3^dim stencil).
+void cell_grid(int dim, const Box& b, double rl, int* nc) {
+  if (b.h10 == 0.0) {
+    const double wx = b.h00 * b.h11 / std::sqrt(b.h11 * b.h11 + b.h01 * b.h01);
+    nc[0] = (int)std::floor(wx / rl);
+    nc[1] = (int)std::floor(b.h11 / rl);
+  } else {
+    const double det = std::fabs(b.h00 * b.h11 - b.h01 * b.h10);
+    nc[0] = (int)std::floor(det / std::sqrt(b.h01 * b.h01 + b.h11 * b.h11) / rl);
+    nc[1] = (int)std::floor(det / std::sqrt(b.h00 * b.h00 + b.h10 * b.h10) / rl);
+  }
+  nc[2] = dim == 3 ? (int)std::floor(b.h22 / rl) : 1;
 }
 
 // Segments per cell row of the force tiles: about `fill` times a block's
@@ -142,8 +149,9 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
     g.nblocks = g.npad / kBlock;
     for (int a = 0; a < 3; ++a) g.L[a] = (a < dim) ? box_len[r * dim + a] : 1.0;
     g.dgamma = dgamma ? dgamma[r] : 0.0;
+    g.dgamma_y = 0.0;
     int nc[3];
-    cell_grid(dim, g.L, 0.0, rl, nc);
+    cell_grid(dim, box_at(g, 0), rl, nc);
     for (int a = 0; a < dim; ++a)
       if (nc[a] < 3)
         return fail(AQS_EINVAL,
@@ -215,7 +223,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
     lo.o_lftbl[l] = take(sizeof(int2) * table_cap(lo.tiles));
     lo.o_lsel[l] = take(sizeof(int32_t) * n_rep);
   }
-  lo.o_dg = take(sizeof(double) * n_rep);
+  lo.o_dg = take(sizeof(double) * 4 * n_rep);
   lo.o_red = take(sizeof(double) * 10 * ((size_t)lo.blocks + 8));
   for (int a = 0; a < 3; ++a) lo.o_dl[a] = take(sizeof(double) * A);
   for (int a = 0; a < 3; ++a) lo.o_tdl[a] = take(sizeof(double) * A);
@@ -557,10 +565,7 @@ aqs_status push_state(aqs_ctx* c) {
   return AQS_OK;
 }
 
-double tilt_of(aqs_ctx* c, int r, int64_t k) {
-  const Geom& g = c->lo.geom[r];
-  return strain_of(k, g.dgamma) * g.L[1];
-}
+Box box_of(aqs_ctx* c, int r, int64_t k) { return box_at(c->lo.geom[r], k); }
 
 // Rebuild cell order and neighbour lists of the given slots (positions as
 // they are on the device; h_state must be current).
@@ -573,7 +578,7 @@ aqs_status rebuild(aqs_ctx* c, Lane& L, const std::vector<int32_t>& sel, bool in
     const int r = sel[i];
     const Geom& g = c->lo.geom[r];
     int nc[3];
-    cell_grid(c->dim, g.L, tilt_of(c, r, c->h_state[r].k), rl, nc);
+    cell_grid(c->dim, box_of(c, r, c->h_state[r].k), rl, nc);
     for (int a = 0; a < c->dim; ++a)
       if (nc[a] < 3)
         return fail(AQS_EINVAL, "slot %d: sheared box too thin for the cell stencil", r);
@@ -764,7 +769,8 @@ aqs_status start_chains(aqs_ctx* c, const std::vector<int32_t>& sel, int32_t sta
       return fail(AQS_ECAPACITY, "n_steps %d outside [0, %d]", ns, c->tn.log_cap - 1);
     if (snap_dst && snap_dst[i] >= 0) {
       const int d = snap_dst[i];
-      if (d >= c->n_rep || c->lo.geom[d].n != c->lo.geom[sel[i]].n)
+      if (d >= c->n_rep || c->lo.geom[d].n != c->lo.geom[sel[i]].n ||
+          c->lo.geom[d].dgamma_y != c->lo.geom[sel[i]].dgamma_y)
         return fail(AQS_EINVAL, "snapshot slot %d invalid for slot %d", d, sel[i]);
     }
   }
@@ -906,8 +912,8 @@ aqs_status compare_slots(aqs_ctx* c, Lane& L, int32_t ra, int32_t rb, double del
     return fail(AQS_EINVAL, "slots %d and %d are at different strain indices (%lld vs %lld)", ra,
                 rb, (long long)c->h_state[ra].k, (long long)c->h_state[rb].k);
   const int nb = (g.n + kBlock - 1) / kBlock;
-  launch_compare(c->d_geom, ra, rb, g.n, c->pos4, c->inv, g.L[0], g.L[1], g.L[2],
-                 tilt_of(c, ra, c->h_state[ra].k), c->dim, c->red, L.s);
+  launch_compare(c->d_geom, ra, rb, g.n, c->pos4, c->inv, box_of(c, ra, c->h_state[ra].k), c->dim,
+                 c->red, L.s);
   HIPCHK(hipGetLastError());
   std::vector<double> part(nb);
   HIPCHK(hipMemcpyAsync(part.data(), c->red, sizeof(double) * nb, hipMemcpyDeviceToHost, L.s));
@@ -1122,7 +1128,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
 
   const size_t tcap = table_cap(std::max(lo.blocks, lo.tiles));
   bool pinned = hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) == hipSuccess &&
-                hipHostMalloc((void**)&c->h_dg, sizeof(double) * n_rep, hipHostMallocDefault) == hipSuccess;
+                hipHostMalloc((void**)&c->h_dg, sizeof(double) * 4 * n_rep, hipHostMallocDefault) == hipSuccess;
   for (Lane& L : c->ln)
     pinned = pinned &&
              hipHostMalloc((void**)&L.h_tbl, sizeof(int2) * tcap, hipHostMallocDefault) == hipSuccess &&
@@ -1280,6 +1286,22 @@ aqs_status aqs_get_strain_index(aqs_ctx* c, int32_t rep, int64_t* k) {
   return AQS_OK;
 }
 
+aqs_status aqs_get_box(aqs_ctx* c, int32_t rep, double* H) {
+  if (!c || !H) return fail(AQS_EINVAL, "null argument");
+  if (rep < 0 || rep >= c->n_rep) return fail(AQS_EINVAL, "slot %d out of range [0, %d)", rep, c->n_rep);
+  aqs_status st = pull_state(c);
+  if (st) return st;
+  const Box b = box_of(c, rep, c->h_state[rep].k);
+  const int d = c->dim;
+  for (int x = 0; x < d * d; ++x) H[x] = 0.0;
+  H[0] = b.h00;
+  H[1] = b.h01;
+  H[d] = b.h10;
+  H[d + 1] = b.h11;
+  if (d == 3) H[8] = b.h22;
+  return AQS_OK;
+}
+
 aqs_status aqs_copy_replica(aqs_ctx* c, int32_t src, int32_t dst) {
   aqs_status st = check_slot(c, src);
   if (st) return st;
@@ -1287,6 +1309,8 @@ aqs_status aqs_copy_replica(aqs_ctx* c, int32_t src, int32_t dst) {
   if (dst == src) return AQS_OK;
   if (c->lo.geom[src].n != c->lo.geom[dst].n)
     return fail(AQS_EINVAL, "slots %d and %d differ in atom count", src, dst);
+  if (c->lo.geom[src].dgamma_y != c->lo.geom[dst].dgamma_y)
+    return fail(AQS_EINVAL, "slots %d and %d differ in their deformation (simple or pure shear)", src, dst);
   st = pull_state(c);
   if (st) return st;
   launch_copy_slot(c->d_geom, src, dst, c->lo.geom[src].n, c->pos4, c->id, c->inv, c->stream);
@@ -1323,10 +1347,26 @@ aqs_status aqs_affine_shear(aqs_ctx* c, int32_t n_sel, const int32_t* rep, const
   }
   aqs_status st = pull_state(c);
   if (st) return st;
-  std::vector<double> dg(c->n_rep, 0.0);
   for (int i = 0; i < n_sel; ++i) {
-    // one multiplication F^(dk dgamma) (level I, Eq. 18)
-    dg[sel[i]] = (double)dk[i] * c->lo.geom[sel[i]].dgamma;
+    const Geom& g = c->lo.geom[sel[i]];
+    if (g.dgamma_y != 0.0 && (dk[i] < 0 || c->h_state[sel[i]].k + dk[i] < 0))
+      return fail(AQS_EINVAL, "slot %d: a pure shear is only applied forward (dk %lld)", sel[i],
+                  (long long)dk[i]);
+  }
+  // per slot the 2x2 map of (x, y): simple shear F^dk = [[1, dk dgamma], [0, 1]]
+  // with dk dgamma in one multiplication (level I, Eq. 18); the pure shear's
+  // F^dk by the same square-and-multiply as its box
+  std::vector<double> dg(4 * (size_t)c->n_rep, 0.0);
+  for (int i = 0; i < n_sel; ++i) {
+    const Geom& g = c->lo.geom[sel[i]];
+    double* M = &dg[4 * (size_t)sel[i]];
+    if (g.dgamma_y == 0.0) {
+      M[0] = 1.0;
+      M[1] = (double)dk[i] * g.dgamma;
+      M[3] = 1.0;
+    } else {
+      deformation_power(g.dgamma, g.dgamma_y, dk[i], M);
+    }
     c->h_state[sel[i]].k += dk[i];
   }
   Lane& L = c->ln[0];
@@ -1335,7 +1375,7 @@ aqs_status aqs_affine_shear(aqs_ctx* c, int32_t n_sel, const int32_t* rep, const
   std::copy(dg.begin(), dg.end(), c->h_dg);
   HIPCHK(hipMemcpyAsync(L.tbl2, L.h_tbl2, sizeof(int2) * tbl.size(), hipMemcpyHostToDevice,
                         c->stream));
-  HIPCHK(hipMemcpyAsync(c->dg_d, c->h_dg, sizeof(double) * c->n_rep, hipMemcpyHostToDevice,
+  HIPCHK(hipMemcpyAsync(c->dg_d, c->h_dg, sizeof(double) * 4 * c->n_rep, hipMemcpyHostToDevice,
                         c->stream));
   launch_affine(L.tbl2, (int32_t)tbl.size(), c->d_geom, c->pos4, c->dg_d, c->stream);
   HIPCHK(hipGetLastError());
@@ -1535,14 +1575,16 @@ aqs_status aqs_compare_configs(aqs_ctx* c, int32_t ra, int32_t rb, double delta_
   if (st) return st;
   const Geom& g = c->lo.geom[ra];
   if (g.n != c->lo.geom[rb].n) return fail(AQS_EINVAL, "slots differ in atom count");
+  if (g.dgamma_y != c->lo.geom[rb].dgamma_y || g.dgamma != c->lo.geom[rb].dgamma)
+    return fail(AQS_EINVAL, "slots differ in their deformation");
   st = pull_state(c);
   if (st) return st;
   if (c->h_state[ra].k != c->h_state[rb].k)
     return fail(AQS_EINVAL, "slots %d and %d are at different strain indices (%lld vs %lld)", ra,
                 rb, (long long)c->h_state[ra].k, (long long)c->h_state[rb].k);
   const int nb = (g.n + kBlock - 1) / kBlock;
-  launch_compare(c->d_geom, ra, rb, g.n, c->pos4, c->inv, g.L[0], g.L[1], g.L[2],
-                 tilt_of(c, ra, c->h_state[ra].k), c->dim, c->red, c->stream);
+  launch_compare(c->d_geom, ra, rb, g.n, c->pos4, c->inv, box_of(c, ra, c->h_state[ra].k), c->dim,
+                 c->red, c->stream);
   HIPCHK(hipGetLastError());
   std::vector<double> part(nb);
   HIPCHK(hipMemcpyAsync(part.data(), c->red, sizeof(double) * nb, hipMemcpyDeviceToHost,
@@ -1566,8 +1608,8 @@ aqs_status aqs_stress(aqs_ctx* c, int32_t rep, double* sigma, double* energy) {
   if (st) return st;
   const Geom& g = c->lo.geom[rep];
   IterArgs a = iter_args(c, c->ln[0]);
-  launch_virial(a, rep, g.nblocks, c->dim, g.L[0], g.L[1], g.L[2], tilt_of(c, rep, c->h_state[rep].k),
-                c->red, c->stream);
+  const Box bx = box_of(c, rep, c->h_state[rep].k);
+  launch_virial(a, rep, g.nblocks, c->dim, bx, c->red, c->stream);
   HIPCHK(hipGetLastError());
   std::vector<double> part((size_t)g.nblocks * 10);
   HIPCHK(hipMemcpyAsync(part.data(), c->red, sizeof(double) * part.size(), hipMemcpyDeviceToHost,
@@ -1576,7 +1618,9 @@ aqs_status aqs_stress(aqs_ctx* c, int32_t rep, double* sigma, double* energy) {
   double tot[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = 0; b < g.nblocks; ++b)
     for (int k = 0; k < 10; ++k) tot[k] += part[(size_t)b * 10 + k];
-  const double vol = g.L[0] * g.L[1] * g.L[2];
+  // simple shear keeps V = Lx Ly Lz; the pure shear of Eq. (17) scales the (x, y) area
+  const double vol = (bx.h10 == 0.0) ? g.L[0] * g.L[1] * g.L[2]
+                                     : std::fabs(bx.h00 * bx.h11 - bx.h01 * bx.h10) * bx.h22;
   const int d = c->dim;
   if (sigma)
     for (int x = 0; x < d; ++x)
@@ -1670,6 +1714,37 @@ aqs_status aqs_set_live_xcds(aqs_ctx* c, int32_t xcds) {
   if (!c) return fail(AQS_EINVAL, "null context");
   if (xcds < 0 || xcds >= kXcds) return fail(AQS_EINVAL, "live_xcds %d outside [0, %d]", xcds, kXcds - 1);
   c->tn.live_xcds = xcds;
+  return AQS_OK;
+}
+
+aqs_status aqs_set_pure_shear(aqs_ctx* c, int32_t n_sel, const int32_t* rep,
+                              const double* dgamma_y) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (n_sel <= 0) return AQS_OK;
+  if (!rep || !dgamma_y) return fail(AQS_EINVAL, "null selection");
+  for (int i = 0; i < n_sel; ++i) {
+    const int r = rep[i];
+    if (r < 0 || r >= c->n_rep) return fail(AQS_EINVAL, "slot %d out of range [0, %d)", r, c->n_rep);
+    const double b = dgamma_y[i];
+    if (!std::isfinite(b) || !(std::fabs(c->lo.geom[r].dgamma * b) < 1.0))
+      return fail(AQS_EINVAL, "slot %d: dgamma_y %g gives a singular deformation", r, b);
+  }
+  aqs_status st = pull_state(c);
+  if (st) return st;
+  for (int i = 0; i < n_sel; ++i) {
+    const int ph = c->h_state[rep[i]].phase;
+    if (ph != PH_IDLE && ph != PH_DONE)
+      return fail(AQS_ESTATE, "slot %d is running (phase %d)", rep[i], ph);
+    if (dgamma_y[i] != 0.0 && c->h_state[rep[i]].k < 0)
+      return fail(AQS_EINVAL, "slot %d: pure shear needs a strain index >= 0", rep[i]);
+  }
+  for (int i = 0; i < n_sel; ++i) {
+    c->lo.geom[rep[i]].dgamma_y = dgamma_y[i];
+    c->dirty[rep[i]] = 1;
+  }
+  HIPCHK(hipMemcpyAsync(c->d_geom, c->lo.geom.data(), sizeof(Geom) * c->n_rep, hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return AQS_OK;
 }
 
@@ -1836,15 +1911,21 @@ aqs_status aqs_learned_targets(aqs_ctx* c, int32_t rep_prev, int32_t rep_next, f
   const Geom& ga = c->lo.geom[rep_prev];
   const Geom& gb = c->lo.geom[rep_next];
   if (ga.n != gb.n) return fail(AQS_EINVAL, "slots %d and %d differ in size", rep_prev, rep_next);
-  if (ga.dgamma != gb.dgamma) return fail(AQS_EINVAL, "slots differ in dgamma");
+  if (ga.dgamma != gb.dgamma || ga.dgamma_y != gb.dgamma_y)
+    return fail(AQS_EINVAL, "slots differ in their deformation");
   st = pull_state(c);
   if (st) return st;
   const int64_t steps = c->h_state[rep_next].k - c->h_state[rep_prev].k;
   if (steps <= 0 || ga.dgamma == 0.0)
     return fail(AQS_EINVAL, "slot %d is not strained beyond slot %d", rep_next, rep_prev);
-  launch_ltargets(c->d_geom, rep_prev, rep_next, ga.n, c->pos4, c->inv, c->dim,
-                  (double)steps * ga.dgamma, gb.L[0], gb.L[1], gb.L[2],
-                  tilt_of(c, rep_next, c->h_state[rep_next].k), target, c->stream);
+  AffineMap f{1.0, (double)steps * ga.dgamma, 0.0, 1.0, (double)steps * ga.dgamma};
+  if (ga.dgamma_y != 0.0) {
+    double M[4];
+    deformation_power(ga.dgamma, ga.dgamma_y, steps, M);
+    f = AffineMap{M[0], M[1], M[2], M[3], (double)steps * ga.dgamma};
+  }
+  launch_ltargets(c->d_geom, rep_prev, rep_next, ga.n, c->pos4, c->inv, c->dim, f,
+                  box_of(c, rep_next, c->h_state[rep_next].k), target, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   return AQS_OK;

@@ -62,27 +62,28 @@ __global__ __launch_bounds__(kBlock) void k_rb_bin(RebuildArgs a) {
   const int li = bt.y * kBlock + threadIdx.x;
   if (li >= g.n) return;
   const int64_t gi = g.atom_off + li;
-  const double t = strain_of(st->k, g.dgamma) * g.L[1];
+  const Box b = box_at(g, st->k);
   double4 p = a.pos4[gi];
   double s[3];
-  frac(g, t, p.x, p.y, (D == 3) ? p.z : 0.0, s);
+  frac(b, p.x, p.y, (D == 3) ? p.z : 0.0, s);
   const double nx = floor(s[0]), ny = floor(s[1]), nz = (D == 3) ? floor(s[2]) : 0.0;
   if (nx != 0.0 || ny != 0.0 || nz != 0.0) {
-    p.x -= nx * g.L[0] + ny * t;
-    p.y -= ny * g.L[1];
-    if (D == 3) p.z -= nz * g.L[2];
+    // back into the box: r -= H n
+    p.x -= nx * b.h00 + ny * b.h01;
+    p.y -= (b.h10 == 0.0) ? ny * b.h11 : nx * b.h10 + ny * b.h11;
+    if (D == 3) p.z -= nz * b.h22;
     a.pos4[gi] = p;
     if (a.alt4) {
       double4 q = a.alt4[gi];
-      q.x -= nx * g.L[0] + ny * t;
-      q.y -= ny * g.L[1];
-      if (D == 3) q.z -= nz * g.L[2];
+      q.x -= nx * b.h00 + ny * b.h01;
+      q.y -= (b.h10 == 0.0) ? ny * b.h11 : nx * b.h10 + ny * b.h11;
+      if (D == 3) q.z -= nz * b.h22;
       a.alt4[gi] = q;
     }
   }
   int c3[3];
   const int nc[3] = {st->nc[0], st->nc[1], st->nc[2]};
-  const int c = cell_of_pos<D>(g, nc, t, p, c3);
+  const int c = cell_of_pos<D>(b, nc, p, c3);
   a.cell_of[gi] = c;
   atomicAdd(a.cell_count + g.cell_off + c, 1);
 }
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
   const State* st = a.state + bt.x;
   if (bt.y >= st->ntiles) return;
   const Geom g = a.geom[bt.x];
-  const double t = strain_of(st->k, g.dgamma) * g.L[1];
+  const Box bx = box_at(g, st->k);
   const int nc[3] = {st->nc[0], st->nc[1], st->nc[2]};
   const int32_t* cs = a.cell_start + g.cell_off;
   const double4* P = a.pos4 + g.atom_off;
@@ -256,9 +257,9 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
     s_cx0 = 0;
     s_cx1 = 0;
     if (a1 > a0) {
-      cell_of_pos<D>(g, nc, t, P[a0], c3);
+      cell_of_pos<D>(bx, nc, P[a0], c3);
       s_cx0 = c3[0];
-      cell_of_pos<D>(g, nc, t, P[a1 - 1], c3);
+      cell_of_pos<D>(bx, nc, P[a1 - 1], c3);
       s_cx1 = c3[0];
     }
   }
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
       while (r < kRuns - 1 && !(hc >= runs[r].off && hc < runs[r].off + runs[r].count)) ++r;
       const double4 pj = P[runs[r].src + (hc - runs[r].off)];
       double sft[3];
-      code_shift(runs[r].code, g.L[0], g.L[1], g.L[2], t, sft);
+      code_shift(runs[r].code, bx, sft);
       s_cx[hc] = (float)((pj.x + sft[0]) - ref.x);
       s_cy[hc] = (float)((pj.y + sft[1]) - ref.y);
       if (D == 3) s_cz[hc] = (float)((pj.z + sft[2]) - ref.z);
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
     const float pix = (float)(pi.x - ref.x), piy = (float)(pi.y - ref.y),
                 piz = (D == 3) ? (float)(pi.z - ref.z) : 0.0f;
     int c3[3];
-    cell_of_pos<D>(g, nc, t, pi, c3);
+    cell_of_pos<D>(bx, nc, pi, c3);
     uint32_t* L = a.nbl + g.nb_off + li;
     int na = 0, nb = 0;   // A neighbours from row 0 up, B neighbours from row max_nb - 1 down
     bool over = false;
@@ -343,9 +344,9 @@ __global__ __launch_bounds__(kBlock) void k_rb_list(RebuildArgs a) {
           else if (cx >= nc[0]) { cx -= nc[0]; ix = 1; }
           const int code = (ix + 1) + 3 * (iy + 1) + 9 * (iz + 1);
           const TileRun& rr = runs[run_of(c3[0], dx, dy, dz, nc[0])];
-          const double sx = (double)ix * g.L[0] + (double)iy * t;
-          const double sy = (double)iy * g.L[1];
-          const double sz = (double)iz * g.L[2];
+          double sh[3];
+          box_shift(bx, ix, iy, iz, sh);
+          const double sx = sh[0], sy = sh[1], sz = sh[2];
           const int c = (cz2 * nc[1] + cy2) * nc[0] + cx;
           const int jb = cs[c], je = cs[c + 1];
           if (cand) {
@@ -544,6 +545,7 @@ __global__ void k_rb_done(RebuildArgs a) {
   if (threadIdx.x == 0) {
     st->ubound = 0.0;
     st->gamma_build = strain_of(st->k, g.dgamma);
+    st->k_build = st->k;
     if (a.resume && st->phase == PH_REBUILD)
       st->phase = (st->resume_phase == PH_LPLAIN || st->resume_phase == PH_LMOVE ||
                    st->resume_phase == PH_LREVERT || st->resume_phase == PH_CG)

@@ -108,7 +108,9 @@ struct Geom {
   int32_t tile_off;   // first force tile of this slot in the tile arrays
   int32_t tile_cap;   // force tiles reserved
   double L[3];        // unstrained box edges
-  double dgamma;      // fine strain increment
+  double dgamma;      // fine strain increment (simple shear: x += dgamma y)
+  double dgamma_y;    // 0: simple shear; else the pure shear of Eq. (17),
+                      // F = [[1, dgamma], [dgamma_y, 1]] on (x, y), z unchanged
 };
 
 // dynamic per-slot state (written by the control)
@@ -141,6 +143,7 @@ struct State {
   int32_t resume_phase;  // phase to resume after a neighbour-list rebuild
   int32_t drops;      // fine steps of this call whose shear stress fell below the step before's
   double sxy_prev;    // shear stress of the last finished minimisation
+  int64_t k_build;    // strain index at the last neighbour-list build
 };
 
 // Conjugate-gradient state of a slot, kept apart from State so that the FIRE
@@ -244,6 +247,113 @@ struct IterArgs {
 
 __host__ __device__ inline double strain_of(int64_t k, double dgamma) {
   return (double)k * dgamma;
+}
+
+// The (x, y) block of a box H (columns are the Bravais vectors) and its z
+// edge: H = [[h00, h01, 0], [h10, h11, 0], [0, 0, h22]].  Simple shear keeps
+// h10 = 0; the pure shear of Eq. (17) does not.
+struct Box {
+  double h00, h01, h10, h11, h22;
+};
+
+// F^k for F = [[1, a], [b, 1]], k >= 0, row-major into M: square and multiply
+// over the bits of k from the lowest (R <- R B when the bit is set, then
+// B <- B B), each product entry X[i][0] Y[0][j] + X[i][1] Y[1][j], with no
+// fused multiply-adds, so host, device and any plain FP64 evaluation in the
+// same order agree bit for bit.
+__host__ __device__ inline void deformation_power(double a, double b, int64_t k, double* M) {
+#pragma clang fp contract(off)
+  double r00 = 1.0, r01 = 0.0, r10 = 0.0, r11 = 1.0;
+  double b00 = 1.0, b01 = a, b10 = b, b11 = 1.0;
+  while (k > 0) {
+    if (k & 1) {
+      const double t00 = r00 * b00 + r01 * b10, t01 = r00 * b01 + r01 * b11;
+      const double t10 = r10 * b00 + r11 * b10, t11 = r10 * b01 + r11 * b11;
+      r00 = t00;
+      r01 = t01;
+      r10 = t10;
+      r11 = t11;
+    }
+    const double u00 = b00 * b00 + b01 * b10, u01 = b00 * b01 + b01 * b11;
+    const double u10 = b10 * b00 + b11 * b10, u11 = b10 * b01 + b11 * b11;
+    b00 = u00;
+    b01 = u01;
+    b10 = u10;
+    b11 = u11;
+    k >>= 1;
+  }
+  M[0] = r00;
+  M[1] = r01;
+  M[2] = r10;
+  M[3] = r11;
+}
+
+// The box of a slot at strain index k: simple shear (Eq. 16) H = [[Lx, k dgamma
+// Ly], [0, Ly]] with the tilt formed in one product; pure shear (Eq. 17)
+// H = F^k diag(Lx, Ly); z unchanged.
+__host__ __device__ inline Box box_at(const Geom& g, int64_t k) {
+#pragma clang fp contract(off)
+  Box b;
+  b.h22 = g.L[2];
+  if (g.dgamma_y == 0.0) {
+    b.h00 = g.L[0];
+    b.h01 = strain_of(k, g.dgamma) * g.L[1];
+    b.h10 = 0.0;
+    b.h11 = g.L[1];
+    return b;
+  }
+  double M[4];
+  deformation_power(g.dgamma, g.dgamma_y, k, M);
+  b.h00 = M[0] * g.L[0];
+  b.h01 = M[1] * g.L[1];
+  b.h10 = M[2] * g.L[0];
+  b.h11 = M[3] * g.L[1];
+  return b;
+}
+
+// Deformation of the (x, y) block since the list build, G = H_k H_kb^-1,
+// row-major; z is not deformed.
+__host__ __device__ inline void strain_since(const Geom& g, int64_t k, int64_t kb, double* G) {
+#pragma clang fp contract(off)
+  const Box h = box_at(g, k), b = box_at(g, kb);
+  const double det = b.h00 * b.h11 - b.h01 * b.h10;
+  const double i00 = b.h11 / det, i01 = -b.h01 / det, i10 = -b.h10 / det, i11 = b.h00 / det;
+  G[0] = h.h00 * i00 + h.h01 * i10;
+  G[1] = h.h00 * i01 + h.h01 * i11;
+  G[2] = h.h10 * i00 + h.h11 * i10;
+  G[3] = h.h10 * i01 + h.h11 * i11;
+}
+
+// Largest singular value of G^-1 (the most a separation can have shrunk
+// under G): sigma^2 = (f + sqrt(f^2 - 4 det^2)) / 2 for the 2x2 inverse with
+// squared Frobenius norm f.
+__host__ __device__ inline double inverse_strain_norm(const Geom& g, int64_t k, int64_t kb) {
+  double G[4];
+  strain_since(g, k, kb, G);
+  const double det = G[0] * G[3] - G[1] * G[2];
+  const double j00 = G[3] / det, j01 = -G[1] / det, j10 = -G[2] / det, j11 = G[0] / det;
+  const double f = j00 * j00 + j01 * j01 + j10 * j10 + j11 * j11;
+  const double dj = j00 * j11 - j01 * j10;
+  const double disc = fmax(f * f - 4.0 * dj * dj, 0.0);
+  return fmax(1.0, sqrt(0.5 * (f + sqrt(disc))));
+}
+
+// An affine map of (x, y) (z unchanged) and the strain scale of the step it
+// makes (the divisor of non-affine displacements per unit strain).
+struct AffineMap {
+  double m00, m01, m10, m11, scale;
+};
+
+// Image shift H (ix, iy, iz).
+__host__ __device__ inline void box_shift(const Box& b, int ix, int iy, int iz, double* s) {
+  if (b.h10 == 0.0) {
+    s[0] = (double)ix * b.h00 + (double)iy * b.h01;
+    s[1] = (double)iy * b.h11;
+  } else {
+    s[0] = (double)ix * b.h00 + (double)iy * b.h01;
+    s[1] = (double)ix * b.h10 + (double)iy * b.h11;
+  }
+  s[2] = (double)iz * b.h22;
 }
 
 }  // namespace aqs

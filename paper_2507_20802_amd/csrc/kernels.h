@@ -80,11 +80,10 @@ void launch_copy_slot(const Geom* geom, int32_t src, int32_t dst, int32_t n, dou
 
 // Max minimum-image distance per block between two slots (atom-id order).
 void launch_compare(const Geom* geom, int32_t ra, int32_t rb, int32_t n, const double4* pos4,
-                    const int32_t* inv, double Lx, double Ly, double Lz, double tilt,
-                    int32_t dim, double* part, hipStream_t s);
+                    const int32_t* inv, const Box& box, int32_t dim, double* part, hipStream_t s);
 
 // Energy and full virial per block of one slot: 1 + 9 doubles per block.
-void launch_virial(const IterArgs& a, int32_t rep, int32_t nblocks, int32_t dim, double Lx,
-                   double Ly, double Lz, double tilt, double* part, hipStream_t s);
+void launch_virial(const IterArgs& a, int32_t rep, int32_t nblocks, int32_t dim, const Box& box,
+                   double* part, hipStream_t s);
 
 }  // namespace aqs

@@ -92,12 +92,12 @@ void launch_lextrap(const LearnArgs& a, int32_t nblk, int32_t dim, hipStream_t s
 // per slot of the selection in PH_LDESC: mean u_hat, checks, k + 1, PH_LPLAIN
 void launch_lctl(const LearnArgs& a, hipStream_t s);
 
-// u / (steps dgamma) per atom (atom-id order, FP32 [n][dim]) from slot ra
-// (earlier inherent structure) to slot rb (later one, box tilt tilt_b),
-// u = minimg(r_b - F r_a), F the shear by shear = steps dgamma.
+// u / f.scale per atom (atom-id order, FP32 [n][dim]) from slot ra (earlier
+// inherent structure) to slot rb (later one, in the box `box`),
+// u = minimg(r_b - F r_a), F the affine map f of the steps between them.
 void launch_ltargets(const Geom* geom, int32_t ra, int32_t rb, int32_t n, const double4* pos4,
-                     const int32_t* inv, int32_t dim, double shear, double Lx, double Ly,
-                     double Lz, double tilt_b, float* out, hipStream_t s);
+                     const int32_t* inv, int32_t dim, const AffineMap& f, const Box& box, float* out,
+                     hipStream_t s);
 
 // ---- training -------------------------------------------------------------
 struct TrainArgs {

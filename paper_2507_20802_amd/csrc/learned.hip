@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 #include <algorithm>
 
+#include "cellgeom.h"
 #include "kernels.h"
 #include "learned.h"
 #include "tiles.h"
@@ -142,8 +143,8 @@ __global__ __launch_bounds__(kBlock) void k_ldesc(LearnArgs a) {
   __shared__ double sh[32][4];
   const int64_t tix = bt.y;
   const TileHdr hdr = reinterpret_cast<const TileHdr*>(a.thdr)[tix];
-  const double t = strain_of(st->k, g.dgamma) * g.L[1];
-  if (tid >= 32 && tid < 32 + 27) code_shift(tid - 32, g.L[0], g.L[1], g.L[2], t, sh[tid - 32]);
+  const Box bx = box_at(g, st->k);
+  if (tid >= 32 && tid < 32 + 27) code_shift(tid - 32, bx, sh[tid - 32]);
   __syncthreads();
   const double4* P = a.pos4 + g.atom_off;
   const bool lds = hdr.halo >= 0;
@@ -311,16 +312,38 @@ __device__ void predicted_start(const LearnArgs& a, const State* st, const Geom&
       a.id[di] = aid;
       a.inv[gd.atom_off + aid] = li;
     }
-    p.x += g.dgamma * p.y;  // plain start, Eq. (16)
+    if (g.dgamma_y == 0.0) {
+      // plain start, Eq. (16), written out as in the move kernel's fine step
+#pragma clang fp contract(off)
+      p.x += g.dgamma * p.y;
+    } else {
+      const double x = p.x, y = p.y;   // plain start under the pure shear of Eq. (17)
+      p.x = x + g.dgamma * y;
+      p.y = g.dgamma_y * x + y;
+    }
     a.pos4[gi] = p;
     a.alt4[gi] = p;          // restored bit for bit if the predicted start is rejected
     a.vx[gi] = 0.0;
     a.vy[gi] = 0.0;
     if (D == 3) a.vz[gi] = 0.0;
     const double4 x0 = a.xref4[gi];
-    const double gdl = strain_of(st->k + 1, g.dgamma) - st->gamma_build;
-    const double dx = p.x - (x0.x + gdl * x0.y), dy = p.y - x0.y, dz = p.z - x0.z;
-    part[5] = sqrt(dx * dx + dy * dy + dz * dz);
+    // the displacement since the build, written out as in the move kernel
+    {
+#pragma clang fp contract(off)
+      double dx, dy;
+      if (g.dgamma_y == 0.0) {
+        const double gdl = strain_of(st->k + 1, g.dgamma) - st->gamma_build;
+        dx = p.x - (x0.x + gdl * x0.y);
+        dy = p.y - x0.y;
+      } else {
+        double G[4];
+        strain_since(g, st->k + 1, st->k_build, G);
+        dx = p.x - (G[0] * x0.x + G[1] * x0.y);
+        dy = p.y - (G[2] * x0.x + G[3] * x0.y);
+      }
+      const double dz = p.z - x0.z;
+      part[5] = sqrt(dx * dx + dy * dy + dz * dz);
+    }
   }
   const int ops[kLearnParts] = {0, 0, 0, 1, 1, 1};
   block_reduce_fixed<kLearnParts>(part, ops, red);
@@ -489,24 +512,36 @@ __global__ __launch_bounds__(kBlock) void k_lctl(LearnArgs a) {
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_ltargets(const Geom* geom, int ra, int rb, int n,
                                                      const double4* pos4, const int32_t* inv,
-                                                     double shear, double Lx, double Ly,
-                                                     double Lz, double tb, float* out) {
+                                                     AffineMap f, Box bx, float* out) {
   const int aid = blockIdx.x * kBlock + threadIdx.x;
   if (aid >= n) return;
   const Geom ga = geom[ra], gb = geom[rb];
   const double4 pa = pos4[ga.atom_off + inv[ga.atom_off + aid]];
   const double4 pb = pos4[gb.atom_off + inv[gb.atom_off + aid]];
-  const double xa = pa.x + shear * pa.y;
-  double dx = pb.x - xa, dy = pb.y - pa.y, dz = (D == 3) ? pb.z - pa.z : 0.0;
-  double sy = dy / Ly;
-  double sx = (dx - tb * sy) / Lx;
-  double sz = (D == 3) ? dz / Lz : 0.0;
+  double xa, ya;
+  if (f.m10 == 0.0 && f.m00 == 1.0 && f.m11 == 1.0) {
+    xa = pa.x + f.m01 * pa.y;
+    ya = pa.y;
+  } else {
+    xa = f.m00 * pa.x + f.m01 * pa.y;
+    ya = f.m10 * pa.x + f.m11 * pa.y;
+  }
+  double dx = pb.x - xa, dy = pb.y - ya, dz = (D == 3) ? pb.z - pa.z : 0.0;
+  double sf[3];
+  frac(bx, dx, dy, dz, sf);
+  double sx = sf[0], sy = sf[1], sz = (D == 3) ? sf[2] : 0.0;
   sx -= rint(sx);
   sy -= rint(sy);
   sz -= rint(sz);
-  dx = Lx * sx + tb * sy;
-  dy = Ly * sy;
-  dz = Lz * sz;
+  if (bx.h10 == 0.0) {
+    dx = bx.h00 * sx + bx.h01 * sy;
+    dy = bx.h11 * sy;
+  } else {
+    dx = bx.h00 * sx + bx.h01 * sy;
+    dy = bx.h10 * sx + bx.h11 * sy;
+  }
+  dz = bx.h22 * sz;
+  const double shear = f.scale;
   float* o = out + (int64_t)aid * D;
   o[0] = (float)(dx / shear);
   o[1] = (float)(dy / shear);
@@ -911,15 +946,15 @@ void launch_lctl(const LearnArgs& a, hipStream_t s) {
 }
 
 void launch_ltargets(const Geom* geom, int32_t ra, int32_t rb, int32_t n, const double4* pos4,
-                     const int32_t* inv, int32_t dim, double shear, double Lx, double Ly,
-                     double Lz, double tilt_b, float* out, hipStream_t s) {
+                     const int32_t* inv, int32_t dim, const AffineMap& f, const Box& box, float* out,
+                     hipStream_t s) {
   const int nb = (n + kBlock - 1) / kBlock;
   if (dim == 3)
-    hipLaunchKernelGGL(k_ltargets<3>, dim3(nb), dim3(kBlock), 0, s, geom, ra, rb, n, pos4, inv,
-                       shear, Lx, Ly, Lz, tilt_b, out);
+    hipLaunchKernelGGL(k_ltargets<3>, dim3(nb), dim3(kBlock), 0, s, geom, ra, rb, n, pos4, inv, f,
+                       box, out);
   else
-    hipLaunchKernelGGL(k_ltargets<2>, dim3(nb), dim3(kBlock), 0, s, geom, ra, rb, n, pos4, inv,
-                       shear, Lx, Ly, Lz, tilt_b, out);
+    hipLaunchKernelGGL(k_ltargets<2>, dim3(nb), dim3(kBlock), 0, s, geom, ra, rb, n, pos4, inv, f,
+                       box, out);
 }
 
 void launch_train_stats(const TrainArgs& a, hipStream_t s) {

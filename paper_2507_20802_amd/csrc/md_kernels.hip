@@ -14,6 +14,7 @@
 
 #include <algorithm>
 
+#include "cellgeom.h"
 #include "kernels.h"
 #include "tiles.h"
 
@@ -65,12 +66,11 @@ __device__ __forceinline__ void block_reduce(double* v, const int* op, double (*
 }
 
 // ---------------------------------------------------------------------------
-// box geometry: H = [[Lx, t, 0], [0, Ly, 0], [0, 0, Lz]], t = gamma Ly (Eq. 1,
-// Eq. 16).  Image code c = (ix+1) + 3 (iy+1) + 9 (iz+1); shift = H (ix,iy,iz).
+// box geometry: H = box_at(g, k) (engine.h): simple shear [[Lx, t, 0], [0, Ly,
+// 0], [0, 0, Lz]], t = gamma Ly (Eq. 1, Eq. 16), or the pure shear of Eq. (17).
+// Image code c = (ix+1) + 3 (iy+1) + 9 (iz+1); shift = H (ix, iy, iz).
 
-__device__ __forceinline__ double slot_tilt(const Geom& g, const State* st) {
-  return strain_of(st->k, g.dgamma) * g.L[1];
-}
+
 
 // ---------------------------------------------------------------------------
 // Lennard-Jones pair loop of one atom over its neighbour list, Eq. (13).
@@ -336,7 +336,7 @@ __device__ __forceinline__ void atom_pairs_packed(const double4 pi, int ti, cons
 
 // Field-by-field copy of a slot state: an aggregate copy of the struct goes
 // through scratch memory, a round trip on the control's critical path.
-static_assert(sizeof(State) == 224, "copy_state copies every field of State");
+static_assert(sizeof(State) == 232, "copy_state copies every field of State");
 __device__ __forceinline__ void copy_state(State& d, const State& s) {
   d.k = s.k;
   d.it = s.it;
@@ -376,6 +376,7 @@ __device__ __forceinline__ void copy_state(State& d, const State& s) {
   d.resume_phase = s.resume_phase;
   d.drops = s.drops;
   d.sxy_prev = s.sxy_prev;
+  d.k_build = s.k_build;
 }
 
 // End of a minimisation with the given status: the step record, the
@@ -540,12 +541,21 @@ __device__ __forceinline__ void control(const IterArgs& a, int rep, const Geom& 
   // Validity of the neighbour list.  With r_i = F x_ref,i + u_i (F the shear
   // since the build, |gamma - gamma_build| = gd) every pair now closer than
   // its cutoff was within cutoff + skin at the build if
-  //   gd rc_max + 2 (1 + gd) max_i |u_i| < skin.
+  //   gd rc_max + 2 (1 + gd) max_i |u_i| < skin
+  // (simple shear; the pure shear bounds it by the norm of F^-1).
   const double ub = r[7];
-  const double gam = strain_of(s.k, g.dgamma);
-  const double gd = fabs(gam - s.gamma_build);
   constexpr bool cg = CG;
-  if (!(gd * a.rc_max + 2.0 * (1.0 + gd) * ub < a.skin)) {
+  bool valid;
+  if (g.dgamma_y == 0.0) {
+    const double gam = strain_of(s.k, g.dgamma);
+    const double gd = fabs(gam - s.gamma_build);
+    valid = gd * a.rc_max + 2.0 * (1.0 + gd) * ub < a.skin;
+  } else {
+    // pure shear: r_i = G x_ref,i + u_i with G = H_k H_build^-1, so a pair now
+    // closer than its cutoff had |d_build| <= |G^-1| (rc + 2 max |u_i|)
+    valid = inverse_strain_norm(g, s.k, s.k_build) * (a.rc_max + 2.0 * ub) < a.rc_max + a.skin;
+  }
+  if (!valid) {
     s.resume_phase = (phase == PH_LPLAIN || phase == PH_LMOVE || phase == PH_LREVERT)
                          ? phase
                          : (cg ? PH_CG : PH_FIRE);
@@ -556,7 +566,12 @@ __device__ __forceinline__ void control(const IterArgs& a, int rep, const Geom& 
   s.fmax = sqrt(r[4]);
   if (phase == PH_EVAL || phase == PH_ENERGY) {
     s.E = r[0];
-    s.sxy = r[5] / (g.L[0] * g.L[1] * g.L[2]);  // simple shear keeps V = Lx Ly Lz
+    if (g.dgamma_y == 0.0) {
+      s.sxy = r[5] / (g.L[0] * g.L[1] * g.L[2]);  // simple shear keeps V = Lx Ly Lz
+    } else {
+      const Box bx = box_at(g, s.k);   // the pure shear scales the (x, y) area
+      s.sxy = r[5] / (fabs(bx.h00 * bx.h11 - bx.h01 * bx.h10) * bx.h22);
+    }
     if (phase == PH_EVAL) {
       s.phase = PH_DONE;
     } else if (s.pending == 1) {  // max_iter reached: record, then apply the last step
@@ -773,8 +788,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 
   double part[kForceParts] = {0, 0, 0, 0, 0, 0, 0, 0};
   {
-    const double t = slot_tilt(g, stp);
-    if (tid >= 32 && tid < 32 + 27) code_shift(tid - 32, g.L[0], g.L[1], g.L[2], t, sh[tid - 32]);
+    const Box bx = box_at(g, stp->k);
+    if (tid >= 32 && tid < 32 + 27) code_shift(tid - 32, bx, sh[tid - 32]);
     if (tid >= 64 && tid < 68) spp[tid - 64] = a.pp[tid - 64];
     __syncthreads();
     if (hdr.halo >= 0) {
@@ -1044,7 +1059,18 @@ __global__ __launch_bounds__(kBlock) void k_step(IterArgs a) {
       if (D == 3) p.z += da * dz;
       a.pos4[gi] = p;
     } else if (adv) {
-      p.x += g.dgamma * p.y;  // Eq. (16): x <- x + dgamma y
+      if (g.dgamma_y == 0.0) {
+        // Eq. (16): x <- x + dgamma y, written out (no fused multiply-add), as
+        // the learned start's plain move does, so both give the same bits
+#pragma clang fp contract(off)
+        p.x += g.dgamma * p.y;
+      } else {
+        // Eq. (17): (x, y) <- F (x, y), both from the old coordinates
+#pragma clang fp contract(off)
+        const double x = p.x, y = p.y;
+        p.x = x + g.dgamma * y;
+        p.y = g.dgamma_y * x + y;
+      }
       a.pos4[gi] = p;
       a.vx[gi] = 0.0;
       a.vy[gi] = 0.0;
@@ -1066,8 +1092,21 @@ __global__ __launch_bounds__(kBlock) void k_step(IterArgs a) {
       a.pos4[gi] = p;
     }
     if (moves) {
-      const double gd = strain_of(ss.k, g.dgamma) - ss.gamma_build;
-      const double ux = p.x - (x0.x + gd * x0.y), uy = p.y - x0.y, uz = p.z - x0.z;
+      // written out, as in the learned start's plain move: both paths take
+      // the same list-rebuild decisions bit for bit
+#pragma clang fp contract(off)
+      double ux, uy;
+      if (g.dgamma_y == 0.0) {
+        const double gd = strain_of(ss.k, g.dgamma) - ss.gamma_build;
+        ux = p.x - (x0.x + gd * x0.y);
+        uy = p.y - x0.y;
+      } else {
+        double G[4];
+        strain_since(g, ss.k, ss.k_build, G);
+        ux = p.x - (G[0] * x0.x + G[1] * x0.y);
+        uy = p.y - (G[2] * x0.x + G[3] * x0.y);
+      }
+      const double uz = p.z - x0.z;
       m[0] = sqrt(ux * ux + uy * uy + uz * uz);
     }
   }
@@ -1179,7 +1218,16 @@ __global__ __launch_bounds__(kBlock) void k_affine(const int2* blocks, const Geo
   const int li = bt.y * kBlock + threadIdx.x;
   if (li >= g.n) return;
   double4 p = pos4[g.atom_off + li];
-  p.x += dg[bt.x] * p.y;
+  const double* M = dg + 4 * (int64_t)bt.x;
+  if (g.dgamma_y == 0.0) {
+    p.x += M[1] * p.y;
+  } else {
+    // the pure shear's F^dk (Eq. 17), formed on the host
+#pragma clang fp contract(off)
+    const double x = p.x, y = p.y;
+    p.x = M[0] * x + M[1] * y;
+    p.y = M[2] * x + M[3] * y;
+  }
   pos4[g.atom_off + li] = p;
 }
 
@@ -1236,8 +1284,7 @@ void launch_copy_slot(const Geom* geom, int32_t src, int32_t dst, int32_t n, dou
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_compare(const Geom* geom, int ra, int rb, int n,
                                                      const double4* pos4, const int32_t* inv,
-                                                     double Lx, double Ly, double Lz, double t,
-                                                     double* part) {
+                                                     Box bx, double* part) {
   __shared__ double red[kForceParts][kBlock / kWave];
   const int idx = blockIdx.x * kBlock + threadIdx.x;
   double m[1] = {0.0};
@@ -1248,15 +1295,20 @@ __global__ __launch_bounds__(kBlock) void k_compare(const Geom* geom, int ra, in
     const double4 pb = pos4[gb.atom_off + inv[gb.atom_off + idx]];
     double dx = pa.x - pb.x, dy = pa.y - pb.y, dz = (D == 3) ? pa.z - pb.z : 0.0;
     // fractional coordinates, nearest integer, back (Sec. 2.1 periodicity)
-    double sy = dy / Ly;
-    double sx = (dx - t * sy) / Lx;
-    double sz = (D == 3) ? dz / Lz : 0.0;
+    double sf[3];
+    frac(bx, dx, dy, dz, sf);
+    double sx = sf[0], sy = sf[1], sz = (D == 3) ? sf[2] : 0.0;
     sx -= rint(sx);
     sy -= rint(sy);
     sz -= rint(sz);
-    dx = Lx * sx + t * sy;
-    dy = Ly * sy;
-    dz = Lz * sz;
+    if (bx.h10 == 0.0) {
+      dx = bx.h00 * sx + bx.h01 * sy;
+      dy = bx.h11 * sy;
+    } else {
+      dx = bx.h00 * sx + bx.h01 * sy;
+      dy = bx.h10 * sx + bx.h11 * sy;
+    }
+    dz = bx.h22 * sz;
     m[0] = sqrt(dx * dx + dy * dy + dz * dz);
   }
   const int op[1] = {1};
@@ -1265,16 +1317,15 @@ __global__ __launch_bounds__(kBlock) void k_compare(const Geom* geom, int ra, in
 }
 
 void launch_compare(const Geom* geom, int32_t ra, int32_t rb, int32_t n, const double4* pos4,
-                    const int32_t* inv, double Lx, double Ly, double Lz, double tilt,
-                    int32_t dim, double* part, hipStream_t s) {
+                    const int32_t* inv, const Box& box, int32_t dim, double* part, hipStream_t s) {
   const int nb = (n + kBlock - 1) / kBlock;
   if (nb <= 0) return;
   if (dim == 3)
-    hipLaunchKernelGGL(k_compare<3>, dim3(nb), dim3(kBlock), 0, s, geom, ra, rb, n, pos4, inv, Lx,
-                       Ly, Lz, tilt, part);
+    hipLaunchKernelGGL(k_compare<3>, dim3(nb), dim3(kBlock), 0, s, geom, ra, rb, n, pos4, inv, box,
+                       part);
   else
-    hipLaunchKernelGGL(k_compare<2>, dim3(nb), dim3(kBlock), 0, s, geom, ra, rb, n, pos4, inv, Lx,
-                       Ly, Lz, tilt, part);
+    hipLaunchKernelGGL(k_compare<2>, dim3(nb), dim3(kBlock), 0, s, geom, ra, rb, n, pos4, inv, box,
+                       part);
 }
 
 // ---------------------------------------------------------------------------
@@ -1282,14 +1333,13 @@ void launch_compare(const Geom* geom, int32_t ra, int32_t rb, int32_t n, const d
 // neighbour list; per block: E then W row-major 3x3.
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_virial(IterArgs a, int rep, double Lx, double Ly,
-                                                    double Lz, double t, double* part) {
+__global__ __launch_bounds__(kBlock) void k_virial(IterArgs a, int rep, Box bx, double* part) {
   __shared__ double sh[27][4];
   __shared__ PairParams spp[4];
   __shared__ double red[kForceParts][kBlock / kWave];
   const Geom g = a.geom[rep];
   const int tid = threadIdx.x;
-  if (tid < 27) code_shift(tid, Lx, Ly, Lz, t, sh[tid]);
+  if (tid < 27) code_shift(tid, bx, sh[tid]);
   if (tid < 4) spp[tid] = a.pp[tid];
   __syncthreads();
   const int col = blockIdx.x * kBlock + tid;   // list column (the tiles' walk order)
@@ -1343,15 +1393,13 @@ __global__ __launch_bounds__(kBlock) void k_virial(IterArgs a, int rep, double L
   }
 }
 
-void launch_virial(const IterArgs& a, int32_t rep, int32_t nblocks, int32_t dim, double Lx,
-                   double Ly, double Lz, double tilt, double* part, hipStream_t s) {
+void launch_virial(const IterArgs& a, int32_t rep, int32_t nblocks, int32_t dim, const Box& box,
+                   double* part, hipStream_t s) {
   if (nblocks <= 0) return;
   if (dim == 3)
-    hipLaunchKernelGGL(k_virial<3>, dim3(nblocks), dim3(kBlock), 0, s, a, rep, Lx, Ly, Lz, tilt,
-                       part);
+    hipLaunchKernelGGL(k_virial<3>, dim3(nblocks), dim3(kBlock), 0, s, a, rep, box, part);
   else
-    hipLaunchKernelGGL(k_virial<2>, dim3(nblocks), dim3(kBlock), 0, s, a, rep, Lx, Ly, Lz, tilt,
-                       part);
+    hipLaunchKernelGGL(k_virial<2>, dim3(nblocks), dim3(kBlock), 0, s, a, rep, box, part);
 }
 
 }  // namespace aqs

@@ -97,14 +97,10 @@ __device__ __forceinline__ int run_of(int cx, int dx, int dy, int dz, int nc0) {
   return ((dz + 1) * 3 + (dy + 1)) * 3 + part;
 }
 
-// Image code c = (ix+1) + 3 (iy+1) + 9 (iz+1); shift = H (ix, iy, iz) for the
-// box H = [[Lx, t, 0], [0, Ly, 0], [0, 0, Lz]] (t = gamma Ly).
-__device__ __forceinline__ void code_shift(int code, double Lx, double Ly, double Lz, double t,
-                                           double* s) {
+// Image code c = (ix+1) + 3 (iy+1) + 9 (iz+1); shift = H (ix, iy, iz).
+__device__ __forceinline__ void code_shift(int code, const Box& b, double* s) {
   const int ix = code % 3 - 1, iy = (code / 3) % 3 - 1, iz = code / 9 - 1;
-  s[0] = (double)ix * Lx + (double)iy * t;
-  s[1] = (double)iy * Ly;
-  s[2] = (double)iz * Lz;
+  box_shift(b, ix, iy, iz, s);
 }
 
 // Stage a tile's compact halo into LDS (image shifts sh[code] applied), by

@@ -238,10 +238,10 @@ class Engine:
         return int(k.value)
 
     def box(self, rep: int) -> np.ndarray:
-        """Bravais tensor of slot rep at its current strain index (Eq. 1)."""
-        L = self.box_len[rep]
-        H = np.diag(L).astype(np.float64)
-        H[0, 1] = (float(self.strain_index(rep)) * float(self.dgamma[rep])) * L[1]
+        """Bravais tensor of slot rep at its current strain index (Eq. 1), from
+        the library (simple or pure shear)."""
+        H = np.zeros((self.dim, self.dim), dtype=np.float64)
+        check(self._lib.aqs_get_box(self._ctx, int(rep), H.ctypes.data_as(_lib.c_double_p)), "aqs_get_box")
         return H
 
     def copy_replica(self, src: int, dst: int) -> None:
@@ -341,6 +341,15 @@ class Engine:
         """XCDs of the 8 reserved for the critical chain of later live rounds
         (0: no partition); changes no result."""
         check(self._lib.aqs_set_live_xcds(self._ctx, int(xcds)), "aqs_set_live_xcds")
+
+    def set_pure_shear(self, slots, dgamma_y) -> None:
+        """Deformation of the slots: dgamma_y = 0 simple shear (Eq. 16), else
+        the pure shear of Eq. (17), F = [[1, dgamma], [dgamma_y, 1]] on (x, y).
+        Slots must be idle; set it before loading positions."""
+        sel = _i32(slots)
+        dy = np.ascontiguousarray(np.broadcast_to(np.asarray(dgamma_y, dtype=np.float64), sel.shape))
+        check(self._lib.aqs_set_pure_shear(self._ctx, int(sel.size), sel.ctypes.data_as(_lib.c_int32_p),
+                                           dy.ctypes.data_as(_lib.c_double_p)), "aqs_set_pure_shear")
 
     def set_profiling(self, every_nth_block: int) -> None:
         check(self._lib.aqs_set_profiling(self._ctx, int(every_nth_block)), "aqs_set_profiling")
