@@ -132,7 +132,8 @@ typedef struct {
                                launch deals block b to XCD b mod 8) and the batch's on
                                the others, so that each keeps its own compute units and
                                L2 (0-7; 0 = no partition).  Changes no result. */
-  int32_t pad_;
+  int32_t force_waves;      /* occupancy target of the force kernel: 4 or 5 wavefronts per
+                               SIMD (4 leaves it up to 128 VGPRs, 5 up to 102); 0 = 5 */
   double tile_fill;         /* force tiles (cell-row segments) hold about tile_fill times
                                the atoms a block's lanes take at once (256 /
                                threads_per_atom); clamped to [0.5, 2]; 0 = 0.9 */

@@ -47,7 +47,7 @@ class aqs_tuning(ctypes.Structure):
                 ("block_iters", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("max_chain_steps", ctypes.c_int32), ("threads_per_atom", ctypes.c_int32),
                 ("live_batch_blocks", ctypes.c_int32), ("live_xcds", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("tile_fill", ctypes.c_double)]
+                ("force_waves", ctypes.c_int32), ("tile_fill", ctypes.c_double)]
 
 
 class aqs_step_record(ctypes.Structure):

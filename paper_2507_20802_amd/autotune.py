@@ -39,6 +39,7 @@ KNOBS = {
     "block_iters": (32, 16, 64),
     "tile_fill": (0.9, 0.7, 1.2),
     "use_graph": (0, 1),
+    "force_waves": (5, 4),
 }
 DEFAULT = {k: v[0] for k, v in KNOBS.items()}
 # knobs of live rounds only (aqs_run_round with live checks)

@@ -62,6 +62,7 @@ struct Tune {
   int live_blocks;   // batch force blocks per CU beside a critical chain (0: no limit)
   int live_xcds;     // XCDs reserved for the critical chain of a live round (0: none)
   double tile_fill;  // force-tile atoms per block's atom lanes
+  int force_waves;   // force kernel occupancy target (waves per SIMD): 4 or 5
 };
 
 Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
@@ -82,6 +83,7 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   r.live_xcds = std::max(0, std::min(lx, kXcds - 1));
   const double tf = t ? t->tile_fill : 0.0;
   r.tile_fill = tf > 0.0 ? std::max(kFillMin, std::min(tf, kFillMax)) : kFillDefault;
+  r.force_waves = (t && t->force_waves == 4) ? 4 : 5;
   return r;
 }
 
@@ -352,6 +354,7 @@ IterArgs iter_args(aqs_ctx* c, const Lane& L) {
   a.sel = L.sel_d;
   a.nsel = (int32_t)L.cur_sel.size();
   a.tpa = c->tn.tpa;
+  a.waves = c->tn.force_waves;
   a.lds_pad = batch_pad(c, L);
   a.prio = (c->live && &L == &c->ln[1]) ? 1 : 0;
   a.one_rep = -1;

@@ -191,6 +191,7 @@ struct IterArgs {
   const int32_t* sel;     // slots of the running selection (control kernel)
   int32_t nsel;
   int32_t tpa;            // threads per atom of the force kernel
+  int32_t waves;          // force kernel instantiation: 4 or 5 waves per SIMD
   int32_t lds_pad;        // dynamic LDS bytes added to each force block (CU reservation)
   int32_t prio;           // 1: the critical chain of a live round (its waves issue first)
   // a lane of one slot over all XCDs: the iteration kernels compute their

@@ -740,8 +740,8 @@ __device__ __forceinline__ void critical_priority(const IterArgs& a) {
   if (a.prio) __builtin_amdgcn_s_setprio(3);
 }
 
-template <int D, int TPA>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_force(IterArgs a) {
+template <int D, int TPA, int W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W))) void k_force(IterArgs a) {
   critical_priority(a);
   // (slot, global tile index): computed for a lane of one slot, else read in one load
   int2 bt;
@@ -1117,13 +1117,21 @@ __global__ __launch_bounds__(kBlock) void k_step(IterArgs a) {
   }
 }
 
+template <int D, int TPA>
+void launch_force_t(const IterArgs& a, int32_t ntiles, hipStream_t s) {
+  if (a.waves == 4)
+    hipLaunchKernelGGL((k_force<D, TPA, 4>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a);
+  else
+    hipLaunchKernelGGL((k_force<D, TPA, 5>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a);
+}
+
 template <int D>
 void launch_force_d(const IterArgs& a, int32_t ntiles, int32_t tpa, hipStream_t s) {
   switch (tpa) {
-    case 1: hipLaunchKernelGGL((k_force<D, 1>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a); break;
-    case 2: hipLaunchKernelGGL((k_force<D, 2>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a); break;
-    case 4: hipLaunchKernelGGL((k_force<D, 4>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a); break;
-    default: hipLaunchKernelGGL((k_force<D, 8>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a); break;
+    case 1: launch_force_t<D, 1>(a, ntiles, s); break;
+    case 2: launch_force_t<D, 2>(a, ntiles, s); break;
+    case 4: launch_force_t<D, 4>(a, ntiles, s); break;
+    default: launch_force_t<D, 8>(a, ntiles, s); break;
   }
 }
 
@@ -1135,7 +1143,7 @@ template <int D, int TPA>
 int32_t force_pad_d(int32_t blocks) {
   hipFuncAttributes fa{};
   int dev = 0, cu_lds = 0;
-  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_force<D, TPA>)) != hipSuccess ||
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_force<D, TPA, 5>)) != hipSuccess ||
       hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
           hipSuccess)

@@ -104,6 +104,7 @@ class Tuning:
     live_batch_blocks: int = 0   # live rounds: batch force blocks per CU (0: 3; < 0: no limit)
     live_xcds: int = 0           # live rounds: XCDs reserved for the critical chain (0: none)
     tile_fill: float = 0.0       # force-tile atoms per block's atom lanes (0: 0.9)
+    force_waves: int = 0         # force kernel occupancy target, waves per SIMD: 4 or 5 (0: 5)
 
     def to_c(self) -> aqs_tuning:
         t = aqs_tuning()
@@ -116,6 +117,7 @@ class Tuning:
         t.live_batch_blocks = self.live_batch_blocks
         t.live_xcds = self.live_xcds
         t.tile_fill = self.tile_fill
+        t.force_waves = self.force_waves
         return t
 
 

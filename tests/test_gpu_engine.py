@@ -209,6 +209,32 @@ def test_threads_per_atom_variants_agree(tpa):
     assert O.compare(eng2.positions(0), ref.pos, H)[0] <= POS_TOL
 
 
+@pytest.mark.parametrize("tpa", [1, 2])
+def test_force_occupancy_variants_agree_bit_for_bit(tpa):
+    """The force kernel built for 4 or 5 wavefronts per SIMD (tuning
+    force_waves) only changes register allocation: the same forces and the
+    same minimisation bit for bit, and the oracle's forces."""
+    from paper_2507_20802_amd import Tuning
+    pos, types, L, dim = load_glass("glass3d_1500")
+    dg = 1e-3
+    x = O.affine(pos, dg)
+    H = O.strain_box(dim, L, 1, dg)
+    fire, _ = fire_pair()
+    out = {}
+    for w in (5, 4):
+        eng = engine(dim, [len(types)], L, dg, fire=fire, tuning=Tuning(threads_per_atom=tpa, force_waves=w))
+        eng.set_replica(0, types, x, 1)
+        E, F = eng.energy_forces(0)
+        rec = eng.minimize([0])[0, 0]
+        out[w] = (E, F, rec, eng.positions(0))
+    Eo, Fo, _, _ = O.energy_forces(x, types, H, POT)
+    assert abs(out[4][0] - Eo) <= 1e-12 * abs(Eo)
+    assert np.abs(out[4][1] - Fo).max() <= 1e-11 * max(1.0, np.abs(Fo).max())
+    assert out[4][0] == out[5][0] and np.array_equal(out[4][1], out[5][1])
+    assert out[4][2]["iters"] == out[5][2]["iters"] and out[4][2]["energy"] == out[5][2]["energy"]
+    assert np.array_equal(out[4][3], out[5][3])
+
+
 def test_full_size_forces_sampled_and_inherent_structure_certified():
     """The benchmark's workload size (3D, 32768 atoms, 16 slots in one
     launch, the default lane split): sampled forces at a strained state
