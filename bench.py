@@ -21,8 +21,9 @@ abandonment, and on request the extrapolated start, conjugate gradients and
 the batched round without live checks.
 
 Prints one JSON line: accepted AQS steps/s (value), FIRE iterations per AQS
-step, the roofline of the dominant kernel (the FP64 force kernel, timed with
-HIP events on the stream of each launch inside the timed steps) and the CPU
+step, the roofline of the dominant kernel (the FP64 force kernel, its own
+start and end recorded by HIP events with the dispatches of every 64th block
+of iterations inside the timed steps, on each launch's stream) and the CPU
 oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
@@ -198,8 +199,9 @@ def main() -> int:
     ap.add_argument("--K", type=int, default=200)
     ap.add_argument("--dgamma", type=float, default=5e-5)
     ap.add_argument("--warmup-K", type=int, default=20, help="fine steps per chain in warmup rounds")
-    ap.add_argument("--profile-every", type=int, default=4,
-                    help="time every n-th block of iterations with HIP events (force-kernel roofline)")
+    ap.add_argument("--profile-every", type=int, default=64,
+                    help="time every n-th block of iterations with HIP events (force-kernel roofline); "
+                         "a timed kernel costs the critical chain about 5 us, so the headline samples sparsely")
     ap.add_argument("--train-steps", type=int, default=7,
                     help="plain AQS steps of the glass's own history that train the network")
     ap.add_argument("--epochs", type=int, default=50)
@@ -223,6 +225,8 @@ def main() -> int:
                          "its own, rejected chains stopped")
     ap.add_argument("--live-xcds", type=int, default=None,
                     help="live rounds: XCDs (of 8) reserved for the critical chain (0: none; default: the tuning's)")
+    ap.add_argument("--live-duty", type=int, default=None,
+                    help="duty cycle of the speculative batch in live rounds (default: the first-round policy)")
     ap.add_argument("--live-blocks", type=int, default=None,
                     help="live rounds: batch force blocks per CU beside the critical chain (0: 3; < 0: no limit)")
     ap.add_argument("--tuning", choices=("default", "auto", "autotune"), default="auto",
@@ -292,7 +296,8 @@ def main() -> int:
         g = parallel.layout(1, P)[0]
         torch.cuda.synchronize()
         t = time.perf_counter()
-        out = parallel.run(eng, [g], P * Kr, Kr, P, start=start, max_rounds=1, live=live, abandon=abandon)
+        out = parallel.run(eng, [g], P * Kr, Kr, P, start=start, max_rounds=1, live=live, abandon=abandon,
+                           live_duty=args.live_duty)
         torch.cuda.synchronize()
         return time.perf_counter() - t, out, g
 
@@ -377,7 +382,8 @@ def main() -> int:
         log(f"sequential: {seq['value']:.2f} AQS steps/s")
 
     # roofline of the force kernel over the headline's timed launches (HIP
-    # events on the stream of each launch; both driver lanes with live checks)
+    # events recorded with the dispatches, on the stream of each launch; both
+    # driver lanes with live checks)
     cnt = head["counters"]
     flops_per_atom = 0.5 * nb * FLOPS_PER_PAIR
     n_timed = cnt["force_timed"]

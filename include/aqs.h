@@ -283,6 +283,15 @@ aqs_status aqs_set_live_batch_blocks(aqs_ctx* ctx, int32_t blocks);
  * AQS_EINVAL otherwise).  Changes no result. */
 aqs_status aqs_set_live_xcds(aqs_ctx* ctx, int32_t xcds);
 
+/* Duty cycle of the speculative batch in later live rounds (aqs_run_round
+ * with live = 1 or 2): while a chain runs alone on the second stream, after
+ * each block of iterations of the batch that took wall time T the batch
+ * waits (duty - 1) T, so that the critical chain runs alone that share of the
+ * time (1 = the batch runs whenever it can, the default; at most 64,
+ * AQS_EINVAL otherwise).  Changes no result, only when the speculative
+ * chains get their work done. */
+aqs_status aqs_set_live_duty(aqs_ctx* ctx, int32_t duty);
+
 /* The deformation of the selected slots: dgamma_y[i] = 0 keeps the simple
  * shear of Eq. (16); otherwise the pure (pull-push) shear of Eq. (17),
  * F = [[1, dgamma_r], [dgamma_y, 1]] acting on (x, y) (z unchanged, also in

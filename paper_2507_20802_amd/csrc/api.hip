@@ -63,6 +63,7 @@ struct Tune {
   int live_xcds;     // XCDs reserved for the critical chain of a live round (0: none)
   double tile_fill;  // force-tile atoms per block's atom lanes
   int force_waves;   // force kernel occupancy target (waves per SIMD): 4 or 5
+  int live_duty;     // live rounds: the batch runs one block in live_duty (1: every block)
 };
 
 Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
@@ -84,6 +85,7 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   const double tf = t ? t->tile_fill : 0.0;
   r.tile_fill = tf > 0.0 ? std::max(kFillMin, std::min(tf, kFillMax)) : kFillDefault;
   r.force_waves = (t && t->force_waves == 4) ? 4 : 5;
+  r.live_duty = 1;
   return r;
 }
 
@@ -837,13 +839,10 @@ aqs_status lane_launch(aqs_ctx* c, Lane& L, int32_t start_mode, bool allow_timed
   if (timed) {
     const IterArgs ab[2] = {a, swapped(a)};
     for (int it = 0; it < M; ++it) {
-      // events bracket the force kernel alone and the step kernel alone
-      HIPCHK(hipEventRecord(L.ev[4 * it + 0], L.s));
-      launch_force(ab[it & 1], L.cur_ntiles, c->dim, L.s);
-      HIPCHK(hipEventRecord(L.ev[4 * it + 1], L.s));
-      HIPCHK(hipEventRecord(L.ev[4 * it + 2], L.s));
-      launch_step(ab[it & 1], L.cur_nblk, c->dim, L.s);
-      HIPCHK(hipEventRecord(L.ev[4 * it + 3], L.s));
+      // the force kernel's and the step kernel's own start and end times,
+      // recorded with their dispatches (no marker packets in between)
+      launch_force(ab[it & 1], L.cur_ntiles, c->dim, L.s, L.ev[4 * it + 0], L.ev[4 * it + 1]);
+      launch_step(ab[it & 1], L.cur_nblk, c->dim, L.s, L.ev[4 * it + 2], L.ev[4 * it + 3]);
     }
   } else {
     aqs_status st = launch_block(c, L, a, M);
@@ -1478,13 +1477,24 @@ aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int3
     HIPCHK(hipGetLastError());
   }
   int next = 1;   // next check
+  // duty cycle of the batch while a critical chain runs (live_duty D > 1):
+  // after a block of the batch that took T, the batch waits (D - 1) T, so the
+  // critical chain runs alone that long
+  using clk = std::chrono::steady_clock;
+  clk::time_point b_start = clk::now(), b_idle_until = b_start;
   for (;;) {
     for (Lane* L : {&C, &B})
       if (!L->in_flight && lane_active(c, *L)) {
+        if (L == &B && c->tn.live_duty > 1 && lane_active(c, C) && clk::now() < b_idle_until)
+          continue;
         st = lane_launch(c, *L, start_mode, true);
         if (st) return st;
+        if (L == &B) b_start = clk::now();
       }
-    if (!C.in_flight && !B.in_flight) break;
+    if (!C.in_flight && !B.in_flight) {
+      if (!lane_active(c, B) || !lane_active(c, C)) break;
+      continue;   // the batch waits out its idle time while the critical chain is between blocks
+    }
     // wait for either lane's block
     Lane* done = nullptr;
     while (!done) {
@@ -1502,6 +1512,10 @@ aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int3
     int active = 0;
     st = lane_poll(c, *done, false, active);
     if (st) return st;
+    if (done == &B && c->tn.live_duty > 1) {
+      const clk::time_point now = clk::now();
+      b_idle_until = now + (now - b_start) * (c->tn.live_duty - 1);
+    }
     // a plastic event in the critical chain, still running, predicts that
     // the check on its end fails: the chains after it are stopped now (once
     // the chain is done, the check itself is taken below)
@@ -1717,6 +1731,13 @@ aqs_status aqs_set_live_xcds(aqs_ctx* c, int32_t xcds) {
   if (!c) return fail(AQS_EINVAL, "null context");
   if (xcds < 0 || xcds >= kXcds) return fail(AQS_EINVAL, "live_xcds %d outside [0, %d]", xcds, kXcds - 1);
   c->tn.live_xcds = xcds;
+  return AQS_OK;
+}
+
+aqs_status aqs_set_live_duty(aqs_ctx* c, int32_t duty) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (duty < 1 || duty > 64) return fail(AQS_EINVAL, "live duty %d outside [1, 64]", duty);
+  c->tn.live_duty = duty;
   return AQS_OK;
 }
 

@@ -55,13 +55,16 @@ void launch_rebuild(const RebuildArgs& a, int32_t max_cells_per_slot, hipStream_
 
 // One FIRE iteration: force + control over the force tiles (a.ftiles), then
 // the update over the 256-atom blocks (a.blocks).
-void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s);
+// with events e0, e1: the kernel's own start and end (hipExtLaunchKernelGGL)
+void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s,
+                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // per-slot reduction of the force partials and the control, state updated in
 // place (after launch_force; the single evaluation of aqs_energy_forces)
 void launch_control(const IterArgs& a, hipStream_t s);
 // one iteration's control and move over the update table (after launch_force):
 // reads a.state / a.cgst / a.upart, writes a.state_out / a.cgst_out / a.upart_out
-void launch_step(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s);
+void launch_step(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // dynamic LDS bytes per force block that leave at most `blocks` force blocks
 // per CU plus room for one more (0 if none can)
 int32_t force_lds_pad(int32_t dim, int32_t tpa, int32_t blocks);

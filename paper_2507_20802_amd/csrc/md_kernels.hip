@@ -11,6 +11,7 @@
 // block of a slot combines the partials in block order.  Cell order within a
 // cell is by atom id, so a rebuild gives the same sorted order every run.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 
@@ -1117,21 +1118,35 @@ __global__ __launch_bounds__(kBlock) void k_step(IterArgs a) {
   }
 }
 
-template <int D, int TPA>
-void launch_force_t(const IterArgs& a, int32_t ntiles, hipStream_t s) {
-  if (a.waves == 4)
-    hipLaunchKernelGGL((k_force<D, TPA, 4>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a);
+// A launch, timed by the runtime from the kernel's start to its end when
+// events are given (hipExtLaunchKernelGGL records them with the dispatch
+// itself: no marker packets between the kernels, and no dispatch gap in the
+// interval).
+template <typename K>
+void launch_timed(K kernel, int32_t grid, int32_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                  const IterArgs& a) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), (uint32_t)lds, s, e0, e1, 0u, a);
   else
-    hipLaunchKernelGGL((k_force<D, TPA, 5>), dim3(ntiles), dim3(kBlock), a.lds_pad, s, a);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), lds, s, a);
+}
+
+template <int D, int TPA>
+void launch_force_t(const IterArgs& a, int32_t ntiles, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (a.waves == 4)
+    launch_timed(k_force<D, TPA, 4>, ntiles, a.lds_pad, s, e0, e1, a);
+  else
+    launch_timed(k_force<D, TPA, 5>, ntiles, a.lds_pad, s, e0, e1, a);
 }
 
 template <int D>
-void launch_force_d(const IterArgs& a, int32_t ntiles, int32_t tpa, hipStream_t s) {
+void launch_force_d(const IterArgs& a, int32_t ntiles, int32_t tpa, hipStream_t s, hipEvent_t e0,
+                    hipEvent_t e1) {
   switch (tpa) {
-    case 1: launch_force_t<D, 1>(a, ntiles, s); break;
-    case 2: launch_force_t<D, 2>(a, ntiles, s); break;
-    case 4: launch_force_t<D, 4>(a, ntiles, s); break;
-    default: launch_force_t<D, 8>(a, ntiles, s); break;
+    case 1: launch_force_t<D, 1>(a, ntiles, s, e0, e1); break;
+    case 2: launch_force_t<D, 2>(a, ntiles, s, e0, e1); break;
+    case 4: launch_force_t<D, 4>(a, ntiles, s, e0, e1); break;
+    default: launch_force_t<D, 8>(a, ntiles, s, e0, e1); break;
   }
 }
 
@@ -1173,12 +1188,13 @@ int32_t force_lds_pad(int32_t dim, int32_t tpa, int32_t blocks) {
   }
 }
 
-void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s) {
+void launch_force(const IterArgs& a, int32_t ntiles, int32_t dim, hipStream_t s, hipEvent_t e0,
+                  hipEvent_t e1) {
   if (ntiles <= 0) return;
   if (dim == 3)
-    launch_force_d<3>(a, ntiles, a.tpa, s);
+    launch_force_d<3>(a, ntiles, a.tpa, s, e0, e1);
   else
-    launch_force_d<2>(a, ntiles, a.tpa, s);
+    launch_force_d<2>(a, ntiles, a.tpa, s, e0, e1);
 }
 
 void launch_control(const IterArgs& a, hipStream_t s) {
@@ -1189,27 +1205,28 @@ void launch_control(const IterArgs& a, hipStream_t s) {
 }
 
 template <int D, bool CG>
-void launch_step_d(const IterArgs& a, int32_t nblk, hipStream_t s) {
+void launch_step_d(const IterArgs& a, int32_t nblk, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   // a lane of one slot is latency-bound: its atoms' data load during the control
   if (a.one_rep >= 0)
-    hipLaunchKernelGGL((k_step<D, CG, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+    launch_timed(k_step<D, CG, true>, nblk, 0, s, e0, e1, a);
   else
-    hipLaunchKernelGGL((k_step<D, CG, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+    launch_timed(k_step<D, CG, false>, nblk, 0, s, e0, e1, a);
 }
 
-void launch_step(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s) {
+void launch_step(const IterArgs& a, int32_t nblk, int32_t dim, hipStream_t s, hipEvent_t e0,
+                 hipEvent_t e1) {
   if (nblk <= 0) return;
   const bool cg = (a.minimizer == kMinCG);
   if (dim == 3) {
     if (cg)
-      launch_step_d<3, true>(a, nblk, s);
+      launch_step_d<3, true>(a, nblk, s, e0, e1);
     else
-      launch_step_d<3, false>(a, nblk, s);
+      launch_step_d<3, false>(a, nblk, s, e0, e1);
   } else {
     if (cg)
-      launch_step_d<2, true>(a, nblk, s);
+      launch_step_d<2, true>(a, nblk, s, e0, e1);
     else
-      launch_step_d<2, false>(a, nblk, s);
+      launch_step_d<2, false>(a, nblk, s, e0, e1);
   }
 }
 

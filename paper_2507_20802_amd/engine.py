@@ -344,6 +344,12 @@ class Engine:
         (0: no partition); changes no result."""
         check(self._lib.aqs_set_live_xcds(self._ctx, int(xcds)), "aqs_set_live_xcds")
 
+    def set_live_duty(self, duty: int) -> None:
+        """Later live rounds: the batch of speculative chains runs one block of
+        iterations in `duty` while a critical chain runs (1: always); changes no
+        result."""
+        check(self._lib.aqs_set_live_duty(self._ctx, int(duty)), "aqs_set_live_duty")
+
     def set_pure_shear(self, slots, dgamma_y) -> None:
         """Deformation of the slots: dgamma_y = 0 simple shear (Eq. 16), else
         the pure shear of Eq. (17), F = [[1, dgamma], [dgamma_y, 1]] on (x, y).

@@ -127,10 +127,31 @@ def reservation_for(last_checks: List[bool]) -> int:
     return 0
 
 
+# duty cycle of the speculative batch in the first live round, before any
+# check has been seen (aqs_set_live_duty)
+FIRST_ROUND_DUTY = 1
+
+
+def duty_for(last_checks: List[bool]) -> int:
+    """Duty cycle of the speculative batch for the next live round (the batch
+    runs one block of iterations in this many while a critical chain runs):
+    every block when at least three quarters of the last round's decided
+    checks passed; one in four when under a quarter passed; one in two
+    otherwise; FIRST_ROUND_DUTY before any round."""
+    if not last_checks:
+        return FIRST_ROUND_DUTY
+    f = sum(bool(c) for c in last_checks) / len(last_checks)
+    if f >= 0.75:
+        return 1
+    if f < 0.25:
+        return 4
+    return 2
+
+
 def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq: float = 1e-4,
         start: int = AQS_START_PLAIN, max_rounds: int | None = None, log=None, live: bool = False,
         adaptive_reservation: bool = True, dynamic_k: Optional[Tuple[int, int]] = None,
-        abandon: bool = False) -> dict:
+        abandon: bool = False, live_duty: Optional[int] = None) -> dict:
     """Run Algorithm 1 to n_steps accepted fine steps for every glass (each
     glass's r_star must be loaded in its star slot as an inherent structure).
     With live checks and adaptive_reservation, each round's CU reservation
@@ -177,6 +198,9 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
         rows, outcomes = {}, {}
         if live and adaptive_reservation:
             engine.set_live_batch_blocks(reservation_for(last_checks))
+        if live:
+            engine.set_live_duty(live_duty if live_duty is not None
+                                 else (duty_for(last_checks) if adaptive_reservation else 1))
         last_checks = []
         if live:
             for gi, lengths in plans.items():        # level II + live checks, glass by glass

@@ -26,3 +26,14 @@ def test_reservation_follows_the_last_rounds_checks():
     (6, [True, True, False], (1, 16), 6), (6, [], (1, 16), 6), (3, [True, True], (1, 4), 4)])
 def test_next_k_follows_the_rounds_checks(K, checks, bounds, want):
     assert next_k(K, checks, *bounds) == want
+
+
+def test_duty_follows_the_last_rounds_checks():
+    """The speculative batch's duty cycle for the next live round: every block
+    after a round where speculation paid, one in four after one where it did
+    not, one in two in between, the first-round value before any round."""
+    from paper_2507_20802_amd import parallel
+    assert parallel.duty_for([]) == parallel.FIRST_ROUND_DUTY
+    assert parallel.duty_for([True, True, True, False]) == 1
+    assert parallel.duty_for([False] * 5) == 4
+    assert parallel.duty_for([True, False]) == 2
