@@ -273,6 +273,7 @@ struct Lane {
   int32_t g_pad = 0;               // its force launches' dynamic LDS
   bool in_flight = false;          // a block of iterations launched, not yet polled
   bool timed = false;              // ... with HIP events around its kernels
+  bool prefetched = false;         // ... with its slots' states copied back behind it
   uint32_t xcd_mask = kAllXcds;    // XCDs its launch tables place blocks on
   std::vector<hipEvent_t> ev;      // the lane's timing events (4 per iteration)
 };
@@ -851,6 +852,16 @@ aqs_status lane_launch(aqs_ctx* c, Lane& L, int32_t start_mode, bool allow_timed
   HIPCHK(hipGetLastError());
   c->cnt.force_launches += M;
   if (allow_timed) ++c->block_count;
+  L.prefetched = false;
+  if (c->live) {
+    // the lane's states and overflow flag copied back behind the block, so the
+    // read-back after it costs no second round trip
+    for (int r : L.cur_sel)
+      HIPCHK(hipMemcpyAsync(c->h_state + r, c->d_state + r, sizeof(State), hipMemcpyDeviceToHost,
+                            L.s));
+    HIPCHK(hipMemcpyAsync(L.h_over, L.overflow, sizeof(int32_t), hipMemcpyDeviceToHost, L.s));
+    L.prefetched = true;
+  }
   L.in_flight = true;
   L.timed = timed;
   return AQS_OK;
@@ -861,8 +872,10 @@ aqs_status lane_launch(aqs_ctx* c, Lane& L, int32_t start_mode, bool allow_timed
 // rebuilds its slots asked for (they resume on the device).  active: slots
 // of the lane not yet done.
 aqs_status lane_poll(aqs_ctx* c, Lane& L, bool all_states, int& active) {
-  aqs_status st = all_states ? pull_state(c) : pull_slots(c, L, L.cur_sel);
+  // (a prefetched lane's stream has completed: its copies are in host memory)
+  aqs_status st = all_states ? pull_state(c) : (L.prefetched ? AQS_OK : pull_slots(c, L, L.cur_sel));
   if (st) return st;
+  L.prefetched = false;
   st = check_overflow(c, L);
   if (st) return st;
   ++c->cnt.host_polls;
@@ -1495,8 +1508,14 @@ aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int3
       if (!lane_active(c, B) || !lane_active(c, C)) break;
       continue;   // the batch waits out its idle time while the critical chain is between blocks
     }
-    // wait for either lane's block
+    // wait for either lane's block: a blocking wait when one lane is in flight,
+    // else both polled without sleeping (a sleep's wake-up latency would idle
+    // the critical chain between its blocks)
     Lane* done = nullptr;
+    if (C.in_flight != B.in_flight) {
+      done = C.in_flight ? &C : &B;
+      HIPCHK(hipStreamSynchronize(done->s));
+    }
     while (!done) {
       for (Lane* L : {&C, &B}) {
         if (!L->in_flight) continue;
@@ -1507,7 +1526,7 @@ aqs_status aqs_run_round(aqs_ctx* c, int32_t P, const int32_t* chain, const int3
         }
         if (q != hipErrorNotReady) return fail(AQS_EHIP, "hipStreamQuery: %s", hipGetErrorString(q));
       }
-      if (!done) std::this_thread::sleep_for(std::chrono::microseconds(20));
+      if (!done) std::this_thread::yield();
     }
     int active = 0;
     st = lane_poll(c, *done, false, active);
