@@ -29,6 +29,24 @@ one read here.  Every round still starts from the verified structure and
 every accepted step belongs to a tested prefix, so the accepted trajectory
 does not depend on the K sequence; only rounds and computed steps do.
 
+The dynamic step sizing of the same outlook is read as a dyadic ladder
+(aqs_parallel_dyadic): a round runs at level m, its strain increment
+2^m dgamma, with dgamma the finest; strain is counted in fine increments and
+a level-m round starts on a multiple of 2^m.  A plastic event shows as a
+shear stress below the previous step's, or as a broken link (the anchor
+lands elsewhere than the chain before it).  A round at level m > 0 keeps its
+chains only up to the first one that holds an event; the level is then 0
+until the accepted strain has passed the end of that chain, so events are
+always stepped through at the finest increment.  Otherwise a round without
+an event raises the level by one (up to
+m_max, and only as far as the strain reached is a multiple of); a round at
+level 0 with an event stays at level 0.  So that the level can rise, a round
+below m_max that would end on an odd multiple of its increment gives its
+last chain one increment fewer (drops that chain if it has only one), unless
+the round reaches the target strain.  In elastic stretches the coarse
+steps reach the same inherent structures as the fine ones (adiabatic
+continuation), which the glass test below checks against conventional AQS.
+
 The operators are passed in, so the same procedure serves mocked equality
 outcomes (index arithmetic tests) and real minimisations (oracle FIRE).
 """
@@ -145,3 +163,87 @@ def aqs_sequential(r0: Any, n_steps: int, step: Callable[[Any, int], Any]) -> li
         r = step(r, k)
         traj.append(r)
     return traj
+
+
+@dataclass
+class DyadicRound:
+    start: int               # fine steps accepted before the round
+    level: int               # the round's increment is 2^level fine increments
+    lengths: List[int]       # increments of each chain at that level
+    checks: List[bool]       # outcomes of the links evaluated
+    q: int                   # fine steps accepted
+    cut: bool                # kept chains cut before a plastic event (level > 0)
+
+
+@dataclass
+class DyadicResult:
+    r_star: Any
+    n_current: int
+    rounds: List[DyadicRound] = field(default_factory=list)
+    computed_steps: int = 0  # minimised increments over all chains (any level)
+
+
+def has_drop(stress: List[float]) -> bool:
+    """A plastic event within one chain: some step's shear stress is below
+    the one before (stress[0] is the chain's first, minimised structure)."""
+    return any(stress[j] < stress[j - 1] for j in range(1, len(stress)))
+
+
+def aqs_parallel_dyadic(r0: Any, n_steps: int, K: int, P: int, m_max: int,
+                        level1: Callable[[Any, int, int], Any],
+                        level2: Callable[[List[Any], List[int], int], List[tuple]],
+                        equal: Callable[[Any, Any], bool]) -> DyadicResult:
+    """Rounds of the parallel scheme with the dyadic step sizing read above,
+    until n_steps fine increments are accepted.
+
+    level1(r, m, h)            -> F_N^(m h dgamma) r in one product
+    level2(starts, lengths, h) -> per chain (first, end, stress): lengths[i]
+                                  AQS steps of h fine increments each after
+                                  the first minimisation; stress[j] the shear
+                                  stress after step j (stress[0]: first)
+    equal(a, b)                -> the equality test of Eq. (20)
+    With m_max = 0 every round is level 0 and the rounds are those of
+    aqs_parallel with the same K and P."""
+    if P < 2:
+        raise ValueError("the parallel scheme needs P >= 2 chains (Sec. 3.2)")
+    if K < 1 or m_max < 0:
+        raise ValueError("K must be >= 1 and m_max >= 0")
+    verified, done, m = r0, 0, 0
+    hold = 0                                 # level 0 until the strain passes this
+    res = DyadicResult(r0, 0)
+    while done < n_steps:
+        while n_steps - done < (1 << m):     # do not overshoot the target strain
+            m -= 1
+        h = 1 << m
+        lengths = chain_plan((n_steps - done) // h, K, P)
+        ends_odd = (done // h + sum(lengths)) % 2 == 1
+        if m < m_max and ends_odd and done + sum(lengths) * h < n_steps:
+            if lengths[-1] > 1:
+                lengths[-1] -= 1
+            elif len(lengths) > 1:
+                lengths.pop()
+        chains = level2([level1(verified, i * K, h) for i in range(len(lengths))], lengths, h)
+        res.computed_steps += sum(lengths)
+        links = accepted_links(chains, equal)
+        kept = len(links) + 1 if all(links) else len(links)
+        # chains of the kept prefix holding an event; a broken link after
+        # chain c means chain c crossed one
+        marked = [c for c in range(kept) if has_drop(chains[c][2])]
+        if kept < len(lengths):
+            marked.append(kept - 1)
+        cut = m > 0 and bool(marked)
+        if cut:
+            kept = min(marked)
+            hold = done + sum(lengths[:kept + 1]) * h
+        q = sum(lengths[:kept]) * h
+        res.rounds.append(DyadicRound(done, m, lengths, links, q, cut))
+        if kept > 0:
+            verified = chains[kept - 1][1]
+        done += q
+        nxt = 0 if marked or done < hold else min(m + 1, m_max)
+        while nxt > 0 and done % (1 << nxt):
+            nxt -= 1
+        m = nxt
+    res.r_star = verified
+    res.n_current = done
+    return res

@@ -9,7 +9,7 @@ import pytest
 
 import aqs_synth as S
 import oracle as O
-from oracle.alg1 import adaptive_k, aqs_parallel, aqs_sequential, chain_plan
+from oracle.alg1 import adaptive_k, aqs_parallel, aqs_parallel_dyadic, aqs_sequential, chain_plan
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -198,3 +198,156 @@ def test_parallel_equals_sequential_on_a_glass():
     dyn = aqs_parallel((0, r0), n, K, P, level1, level2, equal, lambda k, c: adaptive_k(k, c, 2, 8))
     assert dyn.n_current == n and len({r.K for r in dyn.rounds}) > 1
     assert O.compare(dyn.r_star[1], seq[-1][1], H)[0] < 1e-6
+
+
+class DyadicMock:
+    """Configurations are (fine strain index, basin) pairs; the shear stress
+    rises by one per fine increment and falls by 1000 at every fine index in
+    `events`; an anchor minimisation at a fine index in `wrong` lands in
+    basin 1 (a misprediction), fine steps keep the basin."""
+
+    def __init__(self, events=(), wrong=()):
+        self.events, self.wrong = tuple(events), set(wrong)
+        self.calls = []
+
+    def stress(self, k):
+        return k - 1000 * sum(e <= k for e in self.events)
+
+    def level1(self, r, m, h):
+        k, b = r
+        return (k, b) if m == 0 else (k + m * h, "anchor")
+
+    def level2(self, starts, lengths, h):
+        out = []
+        for (k, tag), ln in zip(starts, lengths):
+            basin = (1 if k in self.wrong else 0) if tag == "anchor" else tag
+            out.append(((k, basin), (k + ln * h, basin), [self.stress(k + j * h) for j in range(ln + 1)]))
+        self.calls.append((h, list(lengths)))
+        return out
+
+    equal = staticmethod(Mock.equal)
+
+
+def check_ladder(res, n, m_max, events):
+    """Invariants of any dyadic run: rounds tile the strain from 0 to n, a
+    level-m round starts on a multiple of 2^m and accepts whole increments,
+    levels stay in [0, m_max], and every event is accepted in a level-0
+    round (stepped through at the finest increment)."""
+    assert res.n_current == n and res.r_star[0] == n
+    at = 0
+    for r in res.rounds:
+        assert r.start == at and 0 <= r.level <= m_max
+        assert r.start % (1 << r.level) == 0 and r.q % (1 << r.level) == 0
+        at += r.q
+    assert at == n
+    for e in events:
+        if e > n:
+            continue
+        (r,) = [r for r in res.rounds if r.start < e <= r.start + r.q]
+        assert r.level == 0, (e, r)
+
+
+@pytest.mark.parametrize("wrong", [(), (8,), (4, 8), (28, 56, 57, 80)])
+def test_dyadic_without_levels_is_algorithm_1(wrong):
+    # m_max = 0: every round at the finest increment, the rounds of the plain scheme
+    n, K, P = 100, 4, 4
+    m = DyadicMock(wrong=wrong)
+    dy = aqs_parallel_dyadic((0, 0), n, K, P, 0, m.level1, m.level2, m.equal)
+    plain = aqs_parallel((0, 0), n, K, P, lambda r, i: m.level1(r, i, 1),
+                         lambda a, ln: [c[:2] for c in m.level2(a, ln, 1)], m.equal)
+    assert [(r.start, r.lengths, r.checks, r.q) for r in dy.rounds] == \
+        [(r.start, r.lengths, r.checks, r.q) for r in plain.rounds]
+    assert all(r.level == 0 and not r.cut for r in dy.rounds)
+    assert dy.r_star == plain.r_star and dy.computed_steps == plain.computed_steps
+
+
+def test_dyadic_climbs_the_ladder_while_elastic():
+    n, K, P, m_max = 400, 4, 3, 3
+    m = DyadicMock()
+    res = aqs_parallel_dyadic((0, 0), n, K, P, m_max, m.level1, m.level2, m.equal)
+    check_ladder(res, n, m_max, ())
+    lv = [r.level for r in res.rounds]
+    assert lv[:4] == [0, 1, 2, 3] and set(lv[3:-2]) == {3}
+    # worked by hand: 12 fine steps at level 0, 24 at level 1, then level 2
+    # starts at 36 = 9 * 4 and trims its last chain to end at 80 = 10 * 8
+    assert [(r.start, r.lengths, r.q) for r in res.rounds[:4]] == \
+        [(0, [4, 4, 4], 12), (12, [4, 4, 4], 24), (36, [4, 4, 3], 44), (80, [4, 4, 4], 96)]
+    assert res.computed_steps < n // 4
+
+
+def test_dyadic_cuts_before_an_event_and_steps_through_it_finely():
+    n, K, P, m_max = 200, 4, 3, 2
+    m = DyadicMock(events=(50,))
+    res = aqs_parallel_dyadic((0, 0), n, K, P, m_max, m.level1, m.level2, m.equal)
+    check_ladder(res, n, m_max, (50,))
+    # level 2 from fine 36: chains [36, 52], [52, 68], [68, 80]; the event at 50
+    # lies in chain 0, so nothing is kept, and the level is 0 from 36 until the
+    # strain has passed 52 (rounds to 48 and to 60, the second holding the
+    # event, so one more level-0 round before level 1)
+    cut = [r for r in res.rounds if r.cut]
+    assert [(r.start, r.level, r.q) for r in cut] == [(36, 2, 0)]
+    i = res.rounds.index(cut[0])
+    assert [(r.start, r.level, r.q) for r in res.rounds[i + 1: i + 5]] == \
+        [(36, 0, 12), (48, 0, 12), (60, 0, 12), (72, 1, 24)]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dyadic_invariants_under_random_events(seed):
+    rng = np.random.default_rng(seed)
+    n, K, P, m_max = 300, int(rng.integers(1, 6)), int(rng.integers(2, 6)), int(rng.integers(1, 4))
+    events = sorted(rng.choice(np.arange(1, n + 1), size=6, replace=False).tolist())
+    wrong = rng.choice(np.arange(1, n + 1), size=10, replace=False).tolist()
+    m = DyadicMock(events=events, wrong=wrong)
+    res = aqs_parallel_dyadic((0, 0), n, K, P, m_max, m.level1, m.level2, m.equal)
+    check_ladder(res, n, m_max, events)
+    for a, b in zip(res.rounds, res.rounds[1:]):
+        if a.cut:
+            assert b.level == 0 and a.level > 0
+
+
+@pytest.mark.slow
+def test_dyadic_equals_sequential_on_a_glass():
+    """Through the elastic stretches the coarse steps reach the inherent
+    structures of the fine ones, and every plastic event is stepped through
+    at the fine increment: the dyadic run ends where conventional AQS does."""
+    from gpu_common import fire_pair, load_glass
+    pos, types, L, dim = load_glass("glass2d_256")
+    fp = fire_pair()[1]
+    pot = O.kob_andersen()
+    dg, n, K, P, m_max = 2e-4, 96, 4, 3, 2
+
+    def box(k):
+        return O.strain_box(dim, L, k, dg)
+
+    def step(x, k, h):   # to fine index k from k - h
+        return O.fire(O.affine(x, h * dg), types, box(k), pot, fp).pos
+
+    seq = aqs_sequential((0, pos), n, lambda r, k: (k, step(r[1], k, 1)))
+
+    def level1(r, m, h):
+        return (r[0] + m * h, O.affine(r[1], m * h * dg))
+
+    def level2(starts, lengths, h):
+        out = []
+        for (k, x), ln in zip(starts, lengths):
+            y = O.fire(x, types, box(k), pot, fp).pos
+            first, st = (k, y), [O.energy_forces(y, types, box(k), pot)[2][0, 1]]
+            for j in range(1, ln + 1):
+                y = step(y, k + j * h, h)
+                st.append(O.energy_forces(y, types, box(k + j * h), pot)[2][0, 1])
+            out.append((first, (k + ln * h, y), st))
+        return out
+
+    def equal(a, b):
+        assert a[0] == b[0]
+        return O.compare(a[1], b[1], box(a[0]))[0] < 1e-4
+
+    res = aqs_parallel_dyadic((0, pos), n, K, P, m_max, level1, level2, equal)
+    drops = [k for k in range(1, n + 1)
+             if O.energy_forces(seq[k][1], types, box(k), pot)[2][0, 1]
+             < O.energy_forces(seq[k - 1][1], types, box(k - 1), pot)[2][0, 1]]
+    assert drops                                         # the stretch holds plastic events
+    check_ladder(res, n, m_max, drops)
+    assert {r.level for r in res.rounds} == {0, 1, 2}
+    assert any(r.cut for r in res.rounds)
+    assert O.compare(res.r_star[1], seq[-1][1], box(n))[0] < 1e-8
