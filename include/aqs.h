@@ -283,6 +283,16 @@ aqs_status aqs_set_live_batch_blocks(aqs_ctx* ctx, int32_t blocks);
  * AQS_EINVAL otherwise).  Changes no result. */
 aqs_status aqs_set_live_xcds(aqs_ctx* ctx, int32_t xcds);
 
+/* New fine strain increments dgamma[i] for the selected slots (dynamic step
+ * sizing, Sec. 5): a slot's strain k dgamma is kept exactly, so its strain
+ * index becomes k' = k dgamma_old / dgamma_new, which must be an integer
+ * whose strain k' dgamma_new equals k dgamma_old bit for bit (a dyadic ladder
+ * dgamma_0 / 2^m always converts forward; AQS_EINVAL otherwise, nothing
+ * changed).  Simple-shear slots only (a pure shear's box depends on dgamma);
+ * the slots must not be running (AQS_ESTATE).  Lists are rebuilt at the next
+ * call.  Synchronises. */
+aqs_status aqs_set_dgamma(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep, const double* dgamma);
+
 /* Duty cycle of the speculative batch in later live rounds (aqs_run_round
  * with live = 1 or 2): while a chain runs alone on the second stream, after
  * each block of iterations of the batch that took wall time T the batch

@@ -116,6 +116,7 @@ SIGNATURES = {
     "aqs_set_live_xcds": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "aqs_set_pure_shear": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int32_p, c_double_p]),
     "aqs_set_live_duty": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "aqs_set_dgamma": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int32_p, c_double_p]),
     "aqs_set_minimizer": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(aqs_cg_params)]),
     "aqs_get_counters": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_counters), ctypes.c_int32]),
     "aqs_learned_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_mlp)]),

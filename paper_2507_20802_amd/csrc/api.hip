@@ -776,7 +776,8 @@ aqs_status start_chains(aqs_ctx* c, const std::vector<int32_t>& sel, int32_t sta
     if (snap_dst && snap_dst[i] >= 0) {
       const int d = snap_dst[i];
       if (d >= c->n_rep || c->lo.geom[d].n != c->lo.geom[sel[i]].n ||
-          c->lo.geom[d].dgamma_y != c->lo.geom[sel[i]].dgamma_y)
+          c->lo.geom[d].dgamma_y != c->lo.geom[sel[i]].dgamma_y ||
+          c->lo.geom[d].dgamma != c->lo.geom[sel[i]].dgamma)
         return fail(AQS_EINVAL, "snapshot slot %d invalid for slot %d", d, sel[i]);
     }
   }
@@ -1324,8 +1325,9 @@ aqs_status aqs_copy_replica(aqs_ctx* c, int32_t src, int32_t dst) {
   if (dst == src) return AQS_OK;
   if (c->lo.geom[src].n != c->lo.geom[dst].n)
     return fail(AQS_EINVAL, "slots %d and %d differ in atom count", src, dst);
-  if (c->lo.geom[src].dgamma_y != c->lo.geom[dst].dgamma_y)
-    return fail(AQS_EINVAL, "slots %d and %d differ in their deformation (simple or pure shear)", src, dst);
+  if (c->lo.geom[src].dgamma_y != c->lo.geom[dst].dgamma_y ||
+      c->lo.geom[src].dgamma != c->lo.geom[dst].dgamma)
+    return fail(AQS_EINVAL, "slots %d and %d differ in their deformation (shear mode or dgamma)", src, dst);
   st = pull_state(c);
   if (st) return st;
   launch_copy_slot(c->d_geom, src, dst, c->lo.geom[src].n, c->pos4, c->id, c->inv, c->stream);
@@ -1750,6 +1752,55 @@ aqs_status aqs_set_live_xcds(aqs_ctx* c, int32_t xcds) {
   if (!c) return fail(AQS_EINVAL, "null context");
   if (xcds < 0 || xcds >= kXcds) return fail(AQS_EINVAL, "live_xcds %d outside [0, %d]", xcds, kXcds - 1);
   c->tn.live_xcds = xcds;
+  return AQS_OK;
+}
+
+aqs_status aqs_set_dgamma(aqs_ctx* c, int32_t n_sel, const int32_t* rep, const double* dgamma) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (n_sel <= 0) return AQS_OK;
+  if (!rep || !dgamma) return fail(AQS_EINVAL, "null selection");
+  aqs_status st = pull_state(c);
+  if (st) return st;
+  std::vector<int64_t> knew(n_sel, 0), kbnew(n_sel, 0);
+  for (int i = 0; i < n_sel; ++i) {
+    const int r = rep[i];
+    if (r < 0 || r >= c->n_rep) return fail(AQS_EINVAL, "slot %d out of range [0, %d)", r, c->n_rep);
+    const Geom& g = c->lo.geom[r];
+    const double d = dgamma[i];
+    if (!std::isfinite(d) || d == 0.0) return fail(AQS_EINVAL, "slot %d: dgamma %g", r, d);
+    if (g.dgamma_y != 0.0) return fail(AQS_EINVAL, "slot %d is pure-sheared: its box depends on dgamma", r);
+    const State& s = c->h_state[r];
+    if (s.phase != PH_IDLE && s.phase != PH_DONE)
+      return fail(AQS_ESTATE, "slot %d is running (phase %d)", r, s.phase);
+    // the strain k dgamma is kept exactly: the new index is an integer and
+    // forms the same strain (and so the same box) in one product
+    for (int w = 0; w < 2; ++w) {
+      const int64_t k = w == 0 ? s.k : s.k_build;
+      const double kd = std::nearbyint((double)k * g.dgamma / d);
+      const int64_t kn = (int64_t)kd;
+      if (strain_of(kn, d) != strain_of(k, g.dgamma)) {
+        if (w == 1) {   // the list is rebuilt at the next call anyway
+          kbnew[i] = kn;
+          continue;
+        }
+        return fail(AQS_EINVAL, "slot %d: strain %g is not a multiple of dgamma %g", r,
+                    strain_of(k, g.dgamma), d);
+      }
+      (w == 0 ? knew : kbnew)[i] = kn;
+    }
+  }
+  for (int i = 0; i < n_sel; ++i) {
+    const int r = rep[i];
+    c->lo.geom[r].dgamma = dgamma[i];
+    c->h_state[r].k = knew[i];
+    c->h_state[r].k_build = kbnew[i];
+    c->dirty[r] = 1;
+  }
+  st = push_state(c);
+  if (st) return st;
+  HIPCHK(hipMemcpyAsync(c->d_geom, c->lo.geom.data(), sizeof(Geom) * c->n_rep, hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return AQS_OK;
 }
 

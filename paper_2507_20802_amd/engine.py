@@ -168,7 +168,7 @@ class Engine:
             bl = np.repeat(bl[:, None], self.dim, axis=1) if bl.size == self.n_rep else np.tile(bl, (self.n_rep, 1))
         self.box_len = _f64(bl.reshape(self.n_rep, self.dim))
         dg = np.asarray(dgamma, dtype=np.float64)
-        self.dgamma = _f64(np.broadcast_to(dg, (self.n_rep,)))
+        self.dgamma = np.array(np.broadcast_to(dg, (self.n_rep,)), dtype=np.float64)   # own, writable copy
         self.pot = pot or LJParams()
         self.fire = fire or Fire()
         self.minimizer, self.cg = "fire", None
@@ -343,6 +343,15 @@ class Engine:
         """XCDs of the 8 reserved for the critical chain of later live rounds
         (0: no partition); changes no result."""
         check(self._lib.aqs_set_live_xcds(self._ctx, int(xcds)), "aqs_set_live_xcds")
+
+    def set_dgamma(self, slots, dgamma) -> None:
+        """New fine strain increments of the slots, their strains kept exactly
+        (the strain index converts; dynamic step sizing)."""
+        sel = _i32(slots)
+        dg = np.ascontiguousarray(np.broadcast_to(np.asarray(dgamma, dtype=np.float64), sel.shape))
+        check(self._lib.aqs_set_dgamma(self._ctx, int(sel.size), sel.ctypes.data_as(_lib.c_int32_p),
+                                       dg.ctypes.data_as(_lib.c_double_p)), "aqs_set_dgamma")
+        self.dgamma[sel] = dg
 
     def set_live_duty(self, duty: int) -> None:
         """Later live rounds: the batch of speculative chains runs one block of

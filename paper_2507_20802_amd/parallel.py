@@ -23,6 +23,19 @@ reading).  Chain 0 of a round always starts from the verified r_star and
 every accepted step is checked, so the accepted trajectory does not depend
 on the K sequence; only rounds and computed steps do.
 
+dynamic_dgamma=m_max sizes the strain increment per glass and round (the
+dynamic step sizing of the same outlook; the rule, a reading, is
+next_level): a round runs at level m with increment 2^m dgamma (dgamma the
+slots' increment when the run starts, the finest), steps are counted in
+fine increments, and a level-m round starts on a multiple of 2^m of them.
+A plastic event shows as a shear stress below the step before's, or as a
+failed check; a round at level m > 0 keeps its chains only up to the first
+that holds one, and the glass stays at level 0 until its strain has passed
+the end of that chain, so every event is stepped through at the finest
+increment; rounds without an event climb one level at a time.  Levels
+change through aqs_set_dgamma, which keeps each slot's strain exactly; at
+the end of run() every slot is back at the finest increment.
+
 live=True runs each glass's round through aqs_run_round with live checks
 (the improvement the paper proposes in Sec. 4): a check is taken as soon as
 both of its configurations exist, the chain the next check waits on runs on a
@@ -76,6 +89,10 @@ class GlassRun:
     sigma_xy: List[float] = field(default_factory=list)
     statuses_ok: bool = True
     computed_steps: int = 0
+    accepted_strain: List[int] = field(default_factory=list)  # fine strain index of every accepted step
+    level: int = 0              # the slots' increment is dgamma0 2^level (dynamic_dgamma)
+    dgamma0: float = 0.0        # the finest increment (dynamic_dgamma)
+    hold: int = 0               # level 0 until n_current reaches this (dynamic_dgamma)
 
 
 def slots_needed(n_glasses: int, P: int) -> int:
@@ -108,6 +125,24 @@ def next_k(K: int, checks: List[bool], k_min: int, k_max: int) -> int:
     else:
         k = -(-K // 2)
     return max(k_min, min(k, k_max))
+
+
+def chain_drops(sigma_xy, length: int) -> bool:
+    """A plastic event in a chain: one of its fine steps ends at a shear
+    stress below the one before (entry 0 is the chain's first minimisation)."""
+    s = np.asarray(sigma_xy[: length + 1], dtype=np.float64)
+    return bool(np.any(s[1:] < s[:-1]))
+
+
+def next_level(level: int, marked: bool, n_current: int, hold: int, fine_index: int, m_max: int) -> int:
+    """A glass's level for its next round (dynamic_dgamma): 0 when the round
+    marked an event or the strain is still short of the hold point; else one
+    higher, at most m_max, and lowered until the fine strain index reached is
+    a multiple of its increment."""
+    lv = 0 if marked or n_current < hold else min(level + 1, m_max)
+    while lv > 0 and fine_index % (1 << lv):
+        lv -= 1
+    return lv
 
 
 def reservation_for(last_checks: List[bool]) -> int:
@@ -148,10 +183,22 @@ def duty_for(last_checks: List[bool]) -> int:
     return 2
 
 
+def set_level(engine, g: GlassRun, level: int) -> None:
+    """Every slot of the glass to the increment dgamma0 2^level, strains kept:
+    the chains and snapshots first take r_star's configuration (their
+    leftover strain indices need not convert)."""
+    for s in g.chains + g.snaps[1:]:
+        engine.copy_replica(g.star, s)
+    slots = [g.star] + g.chains + g.snaps[1:]
+    engine.set_dgamma(slots, g.dgamma0 * float(1 << level))
+    g.level = level
+
+
 def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq: float = 1e-4,
         start: int = AQS_START_PLAIN, max_rounds: int | None = None, log=None, live: bool = False,
         adaptive_reservation: bool = True, dynamic_k: Optional[Tuple[int, int]] = None,
-        abandon: bool = False, live_duty: Optional[int] = None) -> dict:
+        abandon: bool = False, live_duty: Optional[int] = None,
+        dynamic_dgamma: Optional[int] = None) -> dict:
     """Run Algorithm 1 to n_steps accepted fine steps for every glass (each
     glass's r_star must be loaded in its star slot as an inherent structure).
     With live checks and adaptive_reservation, each round's CU reservation
@@ -161,13 +208,22 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
     details (each round's K among them) are filled into glasses.
     abandon (with live): a stress drop in the critical chain stops the chains
     after it before their check, which counts as failed (predicted, not
-    evaluated: the decision's max_disp is NaN)."""
+    evaluated: the decision's max_disp is NaN).
+    dynamic_dgamma=m_max (simple shear only): increments dgamma 2^m, m in
+    [0, m_max], chosen per glass and round (next_level); n_steps, N_current,
+    q and the decisions' strain indices count fine increments."""
     if P < 2:
         raise ValueError("Algorithm 1 needs P >= 2 (Sec. 3.2)")
     if K < 1:
         raise ValueError("K must be >= 1")
     if dynamic_k is not None and not 1 <= dynamic_k[0] <= dynamic_k[1]:
         raise ValueError("dynamic_k needs 1 <= k_min <= k_max")
+    m_max = int(dynamic_dgamma or 0)
+    if m_max < 0:
+        raise ValueError("dynamic_dgamma needs m_max >= 0")
+    for g in glasses:
+        if m_max and g.level == 0:
+            g.dgamma0 = float(engine.dgamma[g.star])
     kg = [K] * len(glasses)
     t0 = time.perf_counter()
     rnd = 0
@@ -182,7 +238,21 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
         for gi, g in enumerate(glasses):
             if g.n_current >= n_steps:
                 continue
-            lengths = chain_plan(n_steps - g.n_current, kg[gi], P)
+            rem = n_steps - g.n_current
+            lv = g.level
+            while rem < (1 << lv):                  # no overshoot of the target strain
+                lv -= 1
+            if lv != g.level:
+                set_level(engine, g, lv)
+            h = 1 << lv
+            lengths = chain_plan(rem // h, kg[gi], P)
+            k_lv = engine.strain_index(g.star)
+            if lv < m_max and (k_lv + sum(lengths)) % 2 and sum(lengths) * h < rem:
+                # end on an even index so that the next round can climb
+                if lengths[-1] > 1:
+                    lengths[-1] -= 1
+                elif len(lengths) > 1:
+                    lengths.pop()
             plans[gi] = lengths
             for i, ln in enumerate(lengths):
                 engine.copy_replica(g.star, g.chains[i])
@@ -220,6 +290,9 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
         for gi, lengths in plans.items():
             g = glasses[gi]
             Kr = kg[gi]
+            lv = g.level
+            h = 1 << lv
+            k0 = engine.strain_index(g.star)         # in increments of the round's level
             q = lengths[0]
             last = 0
             checks = []
@@ -230,7 +303,7 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
                     eq, md, de = outcomes[gi][i - 1]
                 else:
                     eq, md, de = engine.compare(g.chains[i - 1], g.snaps[i], delta_eq)   # Eq. (20)
-                k = engine.strain_index(g.star) + i * Kr   # both configurations of check i
+                k = (k0 + i * Kr) << lv     # fine index of both configurations of check i
                 d = Decision(rnd, i, k, eq, md, de)
                 g.decisions.append(d)
                 checks.append(eq)
@@ -241,6 +314,18 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
                     q = i * Kr
                     last = i - 1
                     break
+            cut = False
+            if m_max:
+                # chains of the accepted prefix holding an event; a failed
+                # check after chain c means chain c crossed one
+                marked = [c for c in range(last + 1) if chain_drops(rows[g.chains[c]]["sigma_xy"], lengths[c])]
+                if last + 1 < len(lengths) and checks and not checks[-1]:
+                    marked.append(last)
+                if lv > 0 and marked:
+                    cut = True
+                    last = min(marked) - 1
+                    q = sum(lengths[: last + 1])
+                    g.hold = g.n_current + sum(lengths[: last + 2]) * h
             # bookkeeping of iterations (fine steps are records 1..len of each
             # chain; a chain stopped after a failed check keeps its finished ones)
             for i, ln in enumerate(lengths):
@@ -256,22 +341,32 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
                 g.step_starts.extend(int(r["start"][s]) for s in fine)
                 g.computed_steps += int(fine.size)
                 if i <= last:
+                    g.accepted_strain.extend(((k0 + i * Kr + j) << lv) for j in range(1, ln + 1))
                     g.accepted_iters.extend(int(x) for x in r["iters"][1: ln + 1])
                     g.energies.extend(float(x) for x in r["energy"][1: ln + 1])
                     g.sigma_xy.extend(float(x) for x in r["sigma_xy"][1: ln + 1])
-            engine.copy_replica(g.chains[last], g.star)   # r_star <- r_q
+            if last >= 0:
+                engine.copy_replica(g.chains[last], g.star)   # r_star <- r_q
+            q *= h
             g.rounds.append({"round": rnd, "start": g.n_current, "lengths": lengths,
-                             "checks": checks, "q": q, "K": Kr})
+                             "checks": checks, "q": q, "K": Kr, "level": lv, "cut": cut})
             if dynamic_k is not None:
                 kg[gi] = next_k(Kr, checks, dynamic_k[0], dynamic_k[1])
             last_checks.extend(checks)
             g.n_current += q
+            if m_max:
+                nl = next_level(lv, bool(marked), g.n_current, g.hold, (k0 << lv) + q, m_max)
+                if nl != lv:
+                    set_level(engine, g, nl)
             if log:
                 log(f"round {rnd} glass {gi}: checks {checks} q {q} -> N_current {g.n_current}")
         t_check += time.perf_counter() - t2
         rnd += 1
     if live and adaptive_reservation:
         engine.set_live_batch_blocks(engine.tuning.live_batch_blocks)
+    for g in glasses:
+        if g.level:
+            set_level(engine, g, 0)
     wall = time.perf_counter() - t0
     acc = sum(g.n_current for g in glasses)
     comp = sum(g.computed_steps for g in glasses)

@@ -4,10 +4,12 @@ whose checks mostly passed, one batch block per CU after rounds whose
 checks mostly failed and for the first round, the default otherwise.  The dynamic
 choice of K (parallel.next_k): doubled after a round whose checks all
 passed, halved (rounded up) after a failed first check, kept otherwise,
-within its bounds."""
+within its bounds.  The dynamic step sizing (parallel.next_level,
+parallel.chain_drops): level 0 after an event or short of the hold point,
+else one level up, within m_max and the alignment of the strain index."""
 import pytest
 
-from paper_2507_20802_amd.parallel import next_k, reservation_for
+from paper_2507_20802_amd.parallel import chain_drops, next_k, next_level, reservation_for
 
 
 def test_reservation_follows_the_last_rounds_checks():
@@ -37,3 +39,19 @@ def test_duty_follows_the_last_rounds_checks():
     assert parallel.duty_for([True, True, True, False]) == 1
     assert parallel.duty_for([False] * 5) == 4
     assert parallel.duty_for([True, False]) == 2
+
+
+@pytest.mark.parametrize("level,marked,n,hold,fine,m_max,want", [
+    (0, False, 12, 0, 12, 2, 1), (1, False, 36, 0, 36, 2, 2), (2, False, 80, 0, 80, 2, 2),
+    (2, False, 84, 0, 84, 3, 2), (2, False, 88, 0, 88, 3, 3), (1, False, 38, 0, 38, 2, 1),
+    (0, False, 13, 0, 13, 2, 0), (2, True, 80, 0, 80, 2, 0), (0, False, 48, 52, 48, 2, 0),
+    (0, False, 52, 52, 52, 2, 1), (0, False, 12, 0, 12, 0, 0), (0, False, 1012, 0, 1000, 3, 1)])
+def test_next_level(level, marked, n, hold, fine, m_max, want):
+    assert next_level(level, marked, n, hold, fine, m_max) == want
+
+
+def test_chain_drops_reads_only_the_chains_steps():
+    assert not chain_drops([0.1, 0.2, 0.3, 0.0], 2)     # entry 3 is past the chain
+    assert chain_drops([0.1, 0.2, 0.15, 0.3], 3)
+    assert chain_drops([0.3, 0.2], 1)                   # below the first minimisation
+    assert not chain_drops([0.2, 0.2, 0.25], 2)         # equal is no drop
