@@ -33,8 +33,11 @@ The dynamic step sizing of the same outlook is read as a dyadic ladder
 (aqs_parallel_dyadic): a round runs at level m, its strain increment
 2^m dgamma, with dgamma the finest; strain is counted in fine increments and
 a level-m round starts on a multiple of 2^m.  A plastic event shows as a
-shear stress below the previous step's, or as a broken link (the anchor
-lands elsewhere than the chain before it).  A round at level m > 0 keeps its
+shear stress below the previous step's, as energy released within a step
+(on an elastic branch dE/dgamma = V sigma_xy, so a step's energy change is
+the trapezoidal work V h dgamma (sigma_(j-1) + sigma_j) / 2 up to third
+order in the step; an event falls short of it), or as a broken link (the
+anchor lands elsewhere than the chain before it).  A round at level m > 0 keeps its
 chains only up to the first one that holds an event; the level is then 0
 until the accepted strain has passed the end of that chain, so events are
 always stepped through at the finest increment.  Otherwise a round without
@@ -183,25 +186,42 @@ class DyadicResult:
     computed_steps: int = 0  # minimised increments over all chains (any level)
 
 
-def has_drop(stress: List[float]) -> bool:
-    """A plastic event within one chain: some step's shear stress is below
-    the one before (stress[0] is the chain's first, minimised structure)."""
-    return any(stress[j] < stress[j - 1] for j in range(1, len(stress)))
+def has_event(stress: List[float], energy: List[float] | None = None, work: float | None = None,
+              tol: float | None = None) -> bool:
+    """A plastic event within one chain (entry 0 is the chain's first,
+    minimised structure, entry j the structure after step j): some step's
+    shear stress is below the one before; or, given the energies, the
+    volume times the step's strain `work` and `tol`, some step's energy
+    change E_j - E_(j-1) falls below the trapezoidal work
+    work (s_(j-1) + s_j) / 2 by more than tol work (|s_(j-1)| + |s_j|) / 2."""
+    for j in range(1, len(stress)):
+        if stress[j] < stress[j - 1]:
+            return True
+        if energy is not None and tol is not None:
+            w = work * (stress[j - 1] + stress[j]) / 2.0
+            scale = work * (abs(stress[j - 1]) + abs(stress[j])) / 2.0
+            if energy[j] - energy[j - 1] < w - tol * scale:
+                return True
+    return False
 
 
 def aqs_parallel_dyadic(r0: Any, n_steps: int, K: int, P: int, m_max: int,
                         level1: Callable[[Any, int, int], Any],
                         level2: Callable[[List[Any], List[int], int], List[tuple]],
-                        equal: Callable[[Any, Any], bool]) -> DyadicResult:
+                        equal: Callable[[Any, Any], bool], v_dgamma: float | None = None,
+                        event_tol: float | None = None) -> DyadicResult:
     """Rounds of the parallel scheme with the dyadic step sizing read above,
     until n_steps fine increments are accepted.
 
     level1(r, m, h)            -> F_N^(m h dgamma) r in one product
-    level2(starts, lengths, h) -> per chain (first, end, stress): lengths[i]
-                                  AQS steps of h fine increments each after
-                                  the first minimisation; stress[j] the shear
-                                  stress after step j (stress[0]: first)
+    level2(starts, lengths, h) -> per chain (first, end, stress[, energy]):
+                                  lengths[i] AQS steps of h fine increments
+                                  each after the first minimisation; stress[j]
+                                  and energy[j] after step j (entry 0: first)
     equal(a, b)                -> the equality test of Eq. (20)
+    v_dgamma, event_tol        -> volume times dgamma, and the tolerance of
+                                  the energy balance (has_event); None: the
+                                  stress drop alone marks events
     With m_max = 0 every round is level 0 and the rounds are those of
     aqs_parallel with the same K and P."""
     if P < 2:
@@ -228,7 +248,9 @@ def aqs_parallel_dyadic(r0: Any, n_steps: int, K: int, P: int, m_max: int,
         kept = len(links) + 1 if all(links) else len(links)
         # chains of the kept prefix holding an event; a broken link after
         # chain c means chain c crossed one
-        marked = [c for c in range(kept) if has_drop(chains[c][2])]
+        marked = [c for c in range(kept)
+                  if has_event(chains[c][2], chains[c][3] if len(chains[c]) > 3 else None,
+                               None if v_dgamma is None else v_dgamma * h, event_tol)]
         if kept < len(lengths):
             marked.append(kept - 1)
         cut = m > 0 and bool(marked)

@@ -9,7 +9,7 @@ import pytest
 
 import aqs_synth as S
 import oracle as O
-from oracle.alg1 import adaptive_k, aqs_parallel, aqs_parallel_dyadic, aqs_sequential, chain_plan
+from oracle.alg1 import adaptive_k, aqs_parallel, aqs_parallel_dyadic, aqs_sequential, chain_plan, has_event
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -327,27 +327,64 @@ def test_dyadic_equals_sequential_on_a_glass():
     def level1(r, m, h):
         return (r[0] + m * h, O.affine(r[1], m * h * dg))
 
+    def e_s(y, k):
+        E, _, S_, _ = O.energy_forces(y, types, box(k), pot)
+        return E, S_[0, 1]
+
     def level2(starts, lengths, h):
         out = []
         for (k, x), ln in zip(starts, lengths):
             y = O.fire(x, types, box(k), pot, fp).pos
-            first, st = (k, y), [O.energy_forces(y, types, box(k), pot)[2][0, 1]]
+            first = (k, y)
+            en, st = [e_s(y, k)[0]], [e_s(y, k)[1]]
             for j in range(1, ln + 1):
                 y = step(y, k + j * h, h)
-                st.append(O.energy_forces(y, types, box(k + j * h), pot)[2][0, 1])
-            out.append((first, (k + ln * h, y), st))
+                e, sg = e_s(y, k + j * h)
+                en.append(e)
+                st.append(sg)
+            out.append((first, (k + ln * h, y), st, en))
         return out
 
     def equal(a, b):
         assert a[0] == b[0]
         return O.compare(a[1], b[1], box(a[0]))[0] < 1e-4
 
-    res = aqs_parallel_dyadic((0, pos), n, K, P, m_max, level1, level2, equal)
-    drops = [k for k in range(1, n + 1)
-             if O.energy_forces(seq[k][1], types, box(k), pot)[2][0, 1]
-             < O.energy_forces(seq[k - 1][1], types, box(k - 1), pot)[2][0, 1]]
+    drops = [k for k in range(1, n + 1) if e_s(seq[k][1], k)[1] < e_s(seq[k - 1][1], k - 1)[1]]
     assert drops                                         # the stretch holds plastic events
-    check_ladder(res, n, m_max, drops)
-    assert {r.level for r in res.rounds} == {0, 1, 2}
-    assert any(r.cut for r in res.rounds)
-    assert O.compare(res.r_star[1], seq[-1][1], box(n))[0] < 1e-8
+    for tol in (None, 1e-2):                             # stress drops alone; and the energy balance
+        res = aqs_parallel_dyadic((0, pos), n, K, P, m_max, level1, level2, equal, v_dgamma=L * L * dg,
+                                  event_tol=tol)
+        check_ladder(res, n, m_max, drops)
+        assert {r.level for r in res.rounds} == {0, 1, 2}
+        assert any(r.cut for r in res.rounds)
+        assert O.compare(res.r_star[1], seq[-1][1], box(n))[0] < 1e-8
+
+
+def test_energy_balance_marks_released_energy():
+    # E(g) = e0 + V (s0 g + c g^2 / 2), s = dE/dg / V: the trapezoid is exact
+    # for a quadratic energy, so no step is marked; releasing 2 % of a step's
+    # work marks it at tol 1e-2, not at 5e-2
+    V, s0, c, h = 400.0, 0.3, 12.0, 1e-3
+    g = h * np.arange(6)
+    s = list(s0 + c * g)
+    e = -1000.0 + V * (s0 * g + c * g * g / 2)
+    assert not has_event(s, list(e), V * h, 1e-2)
+    e2 = e.copy()
+    e2[3:] -= 0.02 * V * h * (s[2] + s[3]) / 2
+    assert has_event(s, list(e2), V * h, 1e-2)
+    assert not has_event(s, list(e2), V * h, 5e-2)
+    assert not has_event(s, list(e2), V * h, None)
+    # on a real elastic stretch (the first fine steps of a glass) the balance
+    # holds to far better than 1e-2 of the work
+    from gpu_common import fire_pair, load_glass
+    pos, types, L, dim = load_glass("glass2d_256")
+    fp, pot, dg = fire_pair()[1], O.kob_andersen(), 1e-5
+    x, en, st = pos, [], []
+    for k in range(0, 6):
+        H = O.strain_box(dim, L, k, dg)
+        x = O.fire(O.affine(x, dg) if k else x, types, H, pot, fp).pos
+        E, _, S_, _ = O.energy_forces(x, types, H, pot)
+        en.append(E)
+        st.append(S_[0, 1])
+    assert all(b > a for a, b in zip(st, st[1:]))
+    assert not has_event(st, en, L * L * dg, 1e-3)
