@@ -195,8 +195,9 @@ aqs_status aqs_get_strain_index(aqs_ctx* ctx, int32_t rep, int64_t* k);
  * (Eq. 16) or the slot's pure shear (Eq. 17, aqs_set_pure_shear). */
 aqs_status aqs_get_box(aqs_ctx* ctx, int32_t rep, double* H);
 
-/* Copy slot src into slot dst (same atom count): positions, types, order,
- * strain index and last energy.  Level I anchors and snapshots. */
+/* Copy slot src into slot dst (same atom count, shear mode and dgamma):
+ * positions, types, order, strain index and last energy.  Level I anchors
+ * and snapshots.  AQS_EINVAL if the slots differ in any of these. */
 aqs_status aqs_copy_replica(aqs_ctx* ctx, int32_t src, int32_t dst);
 
 /* Affine simple shear of the selected slots, Eqs. (2)-(3) with Eq. (16):
@@ -242,7 +243,8 @@ aqs_status aqs_affine_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
  * n_steps[n_sel]  host, fine steps after the first minimisation; NULL = all 0
  * snap_dst[n_sel] host, slot that receives a copy of the first inherent
  *                 structure (the "outgoing" configuration of Sec. 3.3), or -1;
- *                 NULL = none.  Must have the same atom count.
+ *                 NULL = none.  Must have the same atom count, shear mode and
+ *                 dgamma.
  * records         host, n_sel x (max_s n_steps + 1) records, row r for
  *                 rep[r]; entries past a slot's last minimisation are left
  *                 untouched.  May be NULL.

@@ -28,8 +28,11 @@ dynamic step sizing of the same outlook; the rule, a reading, is
 next_level): a round runs at level m with increment 2^m dgamma (dgamma the
 slots' increment when the run starts, the finest), steps are counted in
 fine increments, and a level-m round starts on a multiple of 2^m of them.
-A plastic event shows as a shear stress below the step before's, or as a
-failed check; a round at level m > 0 keeps its chains only up to the first
+A plastic event shows as a shear stress below the step before's, as
+energy released within a step (chain_events: on an elastic branch
+dE/dgamma = V sigma_xy, so a step's energy change is the trapezoidal work of
+the stress up to third order in the step), or as a failed check; a round at
+level m > 0 keeps its chains only up to the first
 that holds one, and the glass stays at level 0 until its strain has passed
 the end of that chain, so every event is stepped through at the finest
 increment; rounds without an event climb one level at a time.  Levels
@@ -127,11 +130,20 @@ def next_k(K: int, checks: List[bool], k_min: int, k_max: int) -> int:
     return max(k_min, min(k, k_max))
 
 
-def chain_drops(sigma_xy, length: int) -> bool:
-    """A plastic event in a chain: one of its fine steps ends at a shear
-    stress below the one before (entry 0 is the chain's first minimisation)."""
+def chain_events(sigma_xy, length: int, energy=None, work: float = 0.0, tol: Optional[float] = None) -> bool:
+    """A plastic event in a chain (entry 0 is the chain's first
+    minimisation, entry j its step j): a step ends at a shear stress below
+    the one before; or, with energies, `work` = volume x the step's strain
+    and `tol`, a step's energy change falls short of the trapezoidal work
+    work (s_(j-1) + s_j) / 2 by more than tol work (|s_(j-1)| + |s_j|) / 2."""
     s = np.asarray(sigma_xy[: length + 1], dtype=np.float64)
-    return bool(np.any(s[1:] < s[:-1]))
+    if np.any(s[1:] < s[:-1]):
+        return True
+    if energy is None or tol is None:
+        return False
+    e = np.asarray(energy[: length + 1], dtype=np.float64)
+    lo = work * (s[1:] + s[:-1]) / 2.0 - tol * work * (np.abs(s[1:]) + np.abs(s[:-1])) / 2.0
+    return bool(np.any(e[1:] - e[:-1] < lo))
 
 
 def next_level(level: int, marked: bool, n_current: int, hold: int, fine_index: int, m_max: int) -> int:
@@ -198,7 +210,7 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
         start: int = AQS_START_PLAIN, max_rounds: int | None = None, log=None, live: bool = False,
         adaptive_reservation: bool = True, dynamic_k: Optional[Tuple[int, int]] = None,
         abandon: bool = False, live_duty: Optional[int] = None,
-        dynamic_dgamma: Optional[int] = None) -> dict:
+        dynamic_dgamma: Optional[int] = None, event_tol: Optional[float] = 1e-2) -> dict:
     """Run Algorithm 1 to n_steps accepted fine steps for every glass (each
     glass's r_star must be loaded in its star slot as an inherent structure).
     With live checks and adaptive_reservation, each round's CU reservation
@@ -211,7 +223,9 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
     evaluated: the decision's max_disp is NaN).
     dynamic_dgamma=m_max (simple shear only): increments dgamma 2^m, m in
     [0, m_max], chosen per glass and round (next_level); n_steps, N_current,
-    q and the decisions' strain indices count fine increments."""
+    q and the decisions' strain indices count fine increments; event_tol:
+    tolerance of the energy balance that marks events (chain_events; None:
+    stress drops and failed checks only)."""
     if P < 2:
         raise ValueError("Algorithm 1 needs P >= 2 (Sec. 3.2)")
     if K < 1:
@@ -318,7 +332,10 @@ def run(engine, glasses: List[GlassRun], n_steps: int, K: int, P: int, delta_eq:
             if m_max:
                 # chains of the accepted prefix holding an event; a failed
                 # check after chain c means chain c crossed one
-                marked = [c for c in range(last + 1) if chain_drops(rows[g.chains[c]]["sigma_xy"], lengths[c])]
+                work = float(np.prod(engine.box_len[g.star])) * float(engine.dgamma[g.star])
+                marked = [c for c in range(last + 1)
+                          if chain_events(rows[g.chains[c]]["sigma_xy"], lengths[c], rows[g.chains[c]]["energy"],
+                                          work, event_tol)]
                 if last + 1 < len(lengths) and checks and not checks[-1]:
                     marked.append(last)
                 if lv > 0 and marked:

@@ -12,7 +12,10 @@ Every minimisation after the initial quench uses FIRE or, with
 --minimizer cg, the paper's own conjugate gradients; --start extrapolated
 starts every fine step from the extrapolated start; --dynamic-k KMIN KMAX
 lets each run choose K anew after every round (parallel.next_k), starting
-from each K of the grid.
+from each K of the grid; --dynamic-dgamma M lets each run coarsen its
+strain increment to 2^m dgamma, m <= M, between plastic events
+(parallel.next_level); --dgamma replaces the paper's increment (the strain
+reached is steps x dgamma, the sequential run's steps stay fine).
 
 For every sample j and every (P, K): C_j^(S) is the wall time of the 200
 sequential AQS steps (one chain run on the device), C_j^(P,K) that of
@@ -72,15 +75,17 @@ def inherent_structure(seed: int, fire: Fire | None = None):
 
 def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq: float = 1e-4,
              fire: Fire | None = None, log=None, minimizer: str = "fire", start: int = AQS_START_PLAIN,
-             dynamic_k=None) -> dict:
+             dynamic_k=None, dynamic_dgamma=None, dgamma: float = DGAMMA) -> dict:
     """S_j^(P,K) for every sample seed and (P, K); mu and sigma per (P, K).
     minimizer: "fire" or "cg" (the paper's conjugate gradients) for every
     minimisation after the initial quench; start: the start of every fine
     step, sequential and parallel alike; dynamic_k: (k_min, k_max) for
-    parallel.run, K of the grid being the first round's."""
+    parallel.run, K of the grid being the first round's; dynamic_dgamma:
+    m_max for parallel.run; dgamma: the fine strain increment."""
     fire = fire or Fire()
     pot = paper_potential()
-    per = {(P, K): {"S": [], "final_equal": [], "max_disp": [], "t_par": [], "computed": [], "rounds": []}
+    per = {(P, K): {"S": [], "final_equal": [], "max_disp": [], "t_par": [], "computed": [], "rounds": [],
+                    "levels": []}
            for P in Ps for K in Ks}
     t_seq_all, seq_iters = [], []
     engines = {}
@@ -88,7 +93,7 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
         smp, is_pos = inherent_structure(seed, fire)
         n = smp.n
         # sequential AQS: one chain of n_steps fine steps on the device
-        seq = Engine(2, [n], smp.L, DGAMMA, pot=pot, fire=fire)
+        seq = Engine(2, [n], smp.L, dgamma, pot=pot, fire=fire)
         seq.set_minimizer(minimizer, Cg() if minimizer == "cg" else None)
         seq.set_replica(0, smp.types, is_pos, 0)
         seq.minimize([0], n_steps=[2], start=start)         # warm-up
@@ -103,7 +108,7 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
         seq_iters.extend(int(x) for x in rec[0]["iters"][1:])
         for P in Ps:
             if P not in engines:
-                engines[P] = Engine(2, [n] * (parallel.slots_needed(1, P) + 1), smp.L, DGAMMA, pot=pot,
+                engines[P] = Engine(2, [n] * (parallel.slots_needed(1, P) + 1), smp.L, dgamma, pot=pot,
                                     fire=fire)
                 engines[P].set_minimizer(minimizer, Cg() if minimizer == "cg" else None)
             eng = engines[P]
@@ -114,7 +119,7 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
                 _sync()
                 t = time.perf_counter()
                 out = parallel.run(eng, [g], n_steps, K, P, delta_eq=delta_eq, start=start, live=live,
-                                   dynamic_k=dynamic_k)
+                                   dynamic_k=dynamic_k, dynamic_dgamma=dynamic_dgamma)
                 _sync()
                 t_par = time.perf_counter() - t
                 eng.set_replica(ref, smp.types, seq_final, n_steps)
@@ -126,6 +131,7 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
                 d["t_par"].append(t_par)
                 d["computed"].append(out["computed_steps"])
                 d["rounds"].append(out["rounds"])
+                d["levels"].append(sum(r["level"] * r["q"] for r in g.rounds) / max(1, out["accepted_steps"]))
                 if log:
                     log(f"sample {seed} P {P} K {K}: S {t_seq / t_par:.2f} (seq {t_seq:.3f} s, par {t_par:.3f} s), "
                         f"final equal {bool(eq)}")
@@ -137,11 +143,12 @@ def speedups(seeds, Ps, Ks, n_steps: int = N_STEPS, live: bool = True, delta_eq:
                       "final_equal": int(sum(d["final_equal"])), "samples": int(s.size),
                       "computed_steps_mean": float(np.mean(d["computed"])),
                       "rounds_mean": float(np.mean(d["rounds"])),
+                      "accepted_level_mean": float(np.mean(d["levels"])),
                       "t_par_mean_s": float(np.mean(d["t_par"]))})
     it = np.asarray(seq_iters, dtype=np.float64)
-    return {"table": table, "samples": len(list(seeds)), "n_steps": n_steps, "dgamma": DGAMMA,
+    return {"table": table, "samples": len(list(seeds)), "n_steps": n_steps, "dgamma": dgamma,
             "live_checks": bool(live), "minimizer": minimizer, "start": int(start),
-            "dynamic_k": list(dynamic_k) if dynamic_k else None,
+            "dynamic_k": list(dynamic_k) if dynamic_k else None, "dynamic_dgamma": dynamic_dgamma,
             "t_seq_mean_s": float(np.mean(t_seq_all)),
             "fire_iters_per_step": {"mean": float(it.mean()), "median": float(np.median(it)),
                                     "p95": float(np.percentile(it, 95))}}
@@ -157,13 +164,16 @@ def main(argv=None) -> int:
     ap.add_argument("--minimizer", choices=("fire", "cg"), default="fire")
     ap.add_argument("--start", choices=("plain", "extrapolated"), default="plain")
     ap.add_argument("--dynamic-k", type=int, nargs=2, metavar=("KMIN", "KMAX"), default=None)
+    ap.add_argument("--dynamic-dgamma", type=int, default=None, metavar="M")
+    ap.add_argument("--dgamma", type=float, default=DGAMMA)
     args = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
     res = speedups(range(args.samples), args.P, args.K, n_steps=args.steps, live=bool(args.live),
                    log=lambda s: print(s, file=sys.stderr, flush=True), minimizer=args.minimizer,
                    start=AQS_START_EXTRAPOLATED if args.start == "extrapolated" else AQS_START_PLAIN,
-                   dynamic_k=tuple(args.dynamic_k) if args.dynamic_k else None)
+                   dynamic_k=tuple(args.dynamic_k) if args.dynamic_k else None,
+                   dynamic_dgamma=args.dynamic_dgamma, dgamma=args.dgamma)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -74,8 +74,8 @@ def test_steps_after_a_new_increment_use_it():
 _REF = {}
 
 
-def oracle_dyadic(pos, types, L, dim, dg, n, K, P, m_max, ofire, delta_eq):
-    key = (dg, n, K, P, m_max)
+def oracle_dyadic(pos, types, L, dim, dg, n, K, P, m_max, ofire, delta_eq, event_tol):
+    key = (dg, n, K, P, m_max, event_tol)
     if key in _REF:
         return _REF[key]
 
@@ -88,37 +88,46 @@ def oracle_dyadic(pos, types, L, dim, dg, n, K, P, m_max, ofire, delta_eq):
     def level1(r, m, h):
         return (r[0] + m * h, O.affine(r[1], m * h * dg))
 
+    def e_s(y, k):
+        E, _, S_, _ = O.energy_forces(y, types, box(k), POT)
+        return E, S_[0, 1]
+
     def level2(starts, lengths, h):
         out = []
         for (k, x), ln in zip(starts, lengths):
             y = O.fire(x, types, box(k), POT, ofire).pos
-            first, st = (k, y), [O.energy_forces(y, types, box(k), POT)[2][0, 1]]
+            first = (k, y)
+            en, st = [e_s(y, k)[0]], [e_s(y, k)[1]]
             for j in range(1, ln + 1):
                 y = step(y, k + j * h, h)
-                st.append(O.energy_forces(y, types, box(k + j * h), POT)[2][0, 1])
-            out.append((first, (k + ln * h, y), st))
+                e, sg = e_s(y, k + j * h)
+                en.append(e)
+                st.append(sg)
+            out.append((first, (k + ln * h, y), st, en))
         return out
 
     def equal(a, b):
         return O.compare(a[1], b[1], box(a[0]))[0] < delta_eq
 
-    ref = aqs_parallel_dyadic((0, pos), n, K, P, m_max, level1, level2, equal)
+    ref = aqs_parallel_dyadic((0, pos), n, K, P, m_max, level1, level2, equal, v_dgamma=L ** dim * dg,
+                              event_tol=event_tol)
     seq = aqs_sequential((0, pos), n, lambda r, k: (k, step(r[1], k, 1)))
     _REF[key] = (ref, seq[-1][1])
     return _REF[key]
 
 
-@pytest.mark.parametrize("live", [False, True])
-def test_dyadic_run_matches_the_oracle(live):
+@pytest.mark.parametrize("live,event_tol", [(False, 1e-2), (True, 1e-2), (False, None)])
+def test_dyadic_run_matches_the_oracle(live, event_tol):
     from paper_2507_20802_amd import Engine, parallel
     pos, types, L, dim = load_glass("glass2d_256")
     fire, ofire = fire_pair()
     dg, n, K, P, m_max = 2e-4, 96, 4, 3, 2
-    ref, seq_end = oracle_dyadic(pos, types, L, dim, dg, n, K, P, m_max, ofire, 1e-4)
+    ref, seq_end = oracle_dyadic(pos, types, L, dim, dg, n, K, P, m_max, ofire, 1e-4, event_tol)
     eng = Engine(dim, [len(types)] * parallel.slots_needed(1, P), L, dg, fire=fire)
     g = parallel.layout(1, P)[0]
     eng.set_replica(g.star, types, pos, 0)
-    out = parallel.run(eng, [g], n, K, P, delta_eq=1e-4, live=live, dynamic_dgamma=m_max)
+    out = parallel.run(eng, [g], n, K, P, delta_eq=1e-4, live=live, dynamic_dgamma=m_max,
+                       event_tol=event_tol)
     got = [(r["start"], r["level"], r["lengths"], r["checks"], r["q"], r["cut"]) for r in g.rounds]
     want = [(r.start, r.level, r.lengths, r.checks, r.q, r.cut) for r in ref.rounds]
     print("levels", [r[1] for r in got], "cuts", [r[5] for r in got])

@@ -5,11 +5,13 @@ checks mostly failed and for the first round, the default otherwise.  The dynami
 choice of K (parallel.next_k): doubled after a round whose checks all
 passed, halved (rounded up) after a failed first check, kept otherwise,
 within its bounds.  The dynamic step sizing (parallel.next_level,
-parallel.chain_drops): level 0 after an event or short of the hold point,
+parallel.chain_events): level 0 after an event or short of the hold point,
 else one level up, within m_max and the alignment of the strain index."""
 import pytest
 
-from paper_2507_20802_amd.parallel import chain_drops, next_k, next_level, reservation_for
+import numpy as np
+
+from paper_2507_20802_amd.parallel import chain_events, next_k, next_level, reservation_for
 
 
 def test_reservation_follows_the_last_rounds_checks():
@@ -50,8 +52,25 @@ def test_next_level(level, marked, n, hold, fine, m_max, want):
     assert next_level(level, marked, n, hold, fine, m_max) == want
 
 
-def test_chain_drops_reads_only_the_chains_steps():
-    assert not chain_drops([0.1, 0.2, 0.3, 0.0], 2)     # entry 3 is past the chain
-    assert chain_drops([0.1, 0.2, 0.15, 0.3], 3)
-    assert chain_drops([0.3, 0.2], 1)                   # below the first minimisation
-    assert not chain_drops([0.2, 0.2, 0.25], 2)         # equal is no drop
+def test_chain_events_reads_only_the_chains_steps():
+    assert not chain_events([0.1, 0.2, 0.3, 0.0], 2)     # entry 3 is past the chain
+    assert chain_events([0.1, 0.2, 0.15, 0.3], 3)
+    assert chain_events([0.3, 0.2], 1)                   # below the first minimisation
+    assert not chain_events([0.2, 0.2, 0.25], 2)         # equal is no drop
+
+
+def test_chain_events_energy_balance():
+    # E(g) = e0 + V (s0 g + c g^2 / 2): s(g) = s0 + c g, and the trapezoid is
+    # exact for a quadratic energy, so no step is marked
+    V, s0, c, h = 400.0, 0.3, 12.0, 1e-3
+    g = h * np.arange(6)
+    s = s0 + c * g
+    e = -1000.0 + V * (s0 * g + c * g * g / 2)
+    assert not chain_events(s, 5, e, V * h, 1e-2)
+    # release 2 % of step 3's work: marked at tol 1e-2, not at 5e-2
+    e2 = e.copy()
+    e2[3:] -= 0.02 * V * h * (s[2] + s[3]) / 2
+    assert chain_events(s, 5, e2, V * h, 1e-2)
+    assert not chain_events(s, 5, e2, V * h, 5e-2)
+    assert not chain_events(s, 5, e2, V * h, None)
+    assert not chain_events(s, 2, e2, V * h, 1e-2)       # the release is past the chain
