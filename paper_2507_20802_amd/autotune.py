@@ -3,9 +3,9 @@
 The knobs change how the work is laid out, never what is computed beyond
 the rounding order of one atom's force sum: lanes per atom of the force
 kernel (which also sets the force-tile length), the force tiles' fill of a
-block, the Verlet skin (list length against rebuild frequency), the FIRE
-iterations launched between state read-backs and their replay as a
-hipGraph; for live rounds of Algorithm 1 also the compute units left to the
+block, the force kernel's occupancy hint (waves per SIMD), the Verlet skin
+(list length against rebuild frequency), the FIRE iterations launched
+between state read-backs and their replay as a hipGraph; for live rounds of Algorithm 1 also the compute units left to the
 critical chain (XCDs reserved for it, batch force blocks per CU).  For a
 shape (dim, atoms per slot, slots) the tuner times short device chains of
 AQS steps of a seeded glass on the GPU (coordinate descent from the
@@ -16,8 +16,9 @@ bit), and caches the result as JSON keyed by the shape bucket and the
 device name.
 
 Compile-time shapes are not knobs: the 256-thread block (four wavefronts)
-and the force kernel's five waves per SIMD are fixed by its LDS halo (31 KB,
-five blocks per CU) and its register budget.
+is fixed by the force kernel's LDS halo (31 KB, five blocks per CU) and its
+register budget; of the occupancy hint only the two instantiations built
+(five and four waves per SIMD) are candidates.
 
 Everything it times runs in libaqs.so; this module only chooses arguments.
 """
