@@ -72,10 +72,12 @@ typedef int32_t aqs_status;
 /* start of the minimisation after each fine affine step */
 #define AQS_START_PLAIN 0    /* the affine image F r (Eq. 12) */
 #define AQS_START_LEARNED 1  /* F r + predicted non-affine displacement */
-#define AQS_START_FALLBACK 2 /* record only: learned or extrapolated start
-                                rejected, F r used */
+#define AQS_START_FALLBACK 2 /* record only: learned, extrapolated or
+                                linear-response start rejected, F r used */
 #define AQS_START_EXTRAPOLATED 3 /* F r + the previous step's non-affine
                                     displacement (see aqs_minimize_batch) */
+#define AQS_START_LINEAR 4   /* F r + u, H u = f(F r): the linear response of
+                                Eqs. (7)-(8) (see aqs_minimize_batch) */
 
 /* Binary truncated-and-shifted Lennard-Jones pair potential, Eq. (13):
  * U_ab(r) = 4 eps_ab [(sigma_ab/r)^12 - (sigma_ab/r)^6] - U_ab(rc_ab) for
@@ -239,7 +241,20 @@ aqs_status aqs_affine_shear(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep,
  *                 (r(IS_(s-1)) - F r(IS_(s-2))) / dgamma, the non-affine
  *                 displacement of the step before, with the acceptance rules
  *                 of the learned start; step 1 has no history and starts from
- *                 F r (record AQS_START_FALLBACK)
+ *                 F r (record AQS_START_FALLBACK).  AQS_START_LINEAR (the
+ *                 equilibrium condition of Sec. 2.1, Eqs. 7-8, as a start):
+ *                 every fine step starts from x0 + u, x0 = F r, where u
+ *                 solves H u = f(x0), H the Hessian at x0, by conjugate
+ *                 gradients from u = 0 (residual r = f(x0) - H u, direction
+ *                 p; H p by central differences of the forces,
+ *                 (f(x0 - s p) - f(x0 + s p)) / (2 h) max_i |p_i| with
+ *                 s = h / max_i |p_i|; stop at |r|^2 <= tol^2 |f(x0)|^2, at
+ *                 p.Hp <= 0 before the update, or after max_cg updates;
+ *                 aqs_set_linear_start), with the acceptance rules of the
+ *                 learned start (max_i |u_i| <= 0.1 sigma_AA, E and max_i
+ *                 |F_i| no worse than at x0; else x0, record
+ *                 AQS_START_FALLBACK).  Each update costs two force
+ *                 evaluations, counted in aqs_counters.atom_evals.
  * n_steps[n_sel]  host, fine steps after the first minimisation; NULL = all 0
  * snap_dst[n_sel] host, slot that receives a copy of the first inherent
  *                 structure (the "outgoing" configuration of Sec. 3.3), or -1;
@@ -294,6 +309,13 @@ aqs_status aqs_set_live_xcds(aqs_ctx* ctx, int32_t xcds);
  * the slots must not be running (AQS_ESTATE).  Lists are rebuilt at the next
  * call.  Synchronises. */
 aqs_status aqs_set_dgamma(aqs_ctx* ctx, int32_t n_sel, const int32_t* rep, const double* dgamma);
+
+/* Parameters of the linear-response start (AQS_START_LINEAR): at most
+ * max_cg updates of the conjugate-gradient solve, stop at |r| <= tol
+ * |f(x0)|, probe length h (sigma_AA, max norm) of the Hessian-vector
+ * products.  Defaults 50, 1e-3, 1e-5.  AQS_EINVAL for max_cg outside
+ * [1, 100000], tol outside (0, 1) or h outside (0, 0.1). */
+aqs_status aqs_set_linear_start(aqs_ctx* ctx, int32_t max_cg, double tol, double probe);
 
 /* Duty cycle of the speculative batch in later live rounds (aqs_run_round
  * with live = 1 or 2): while a chain runs alone on the second stream, after

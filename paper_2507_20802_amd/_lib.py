@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libaqs.so")
 
 AQS_OK, AQS_EINVAL, AQS_EHIP, AQS_ENOMEM, AQS_ECAPACITY, AQS_ESTATE = 0, -1, -2, -3, -4, -5
 AQS_CONVERGED, AQS_MAXITER, AQS_STALLED, AQS_NONFINITE, AQS_CANCELLED = 0, 1, 2, 3, 4
-AQS_START_PLAIN, AQS_START_LEARNED, AQS_START_FALLBACK, AQS_START_EXTRAPOLATED = 0, 1, 2, 3
+AQS_START_PLAIN, AQS_START_LEARNED, AQS_START_FALLBACK, AQS_START_EXTRAPOLATED, AQS_START_LINEAR = 0, 1, 2, 3, 4
 AQS_MIN_FIRE, AQS_MIN_CG = 0, 1
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -117,6 +117,7 @@ SIGNATURES = {
     "aqs_set_pure_shear": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int32_p, c_double_p]),
     "aqs_set_live_duty": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "aqs_set_dgamma": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, c_int32_p, c_double_p]),
+    "aqs_set_linear_start": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_double]),
     "aqs_set_minimizer": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(aqs_cg_params)]),
     "aqs_get_counters": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_counters), ctypes.c_int32]),
     "aqs_learned_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(aqs_mlp)]),

@@ -16,6 +16,7 @@
 #include "aqs.h"
 #include "kernels.h"
 #include "learned.h"
+#include "linear.h"
 
 using namespace aqs;
 
@@ -64,6 +65,9 @@ struct Tune {
   double tile_fill;  // force-tile atoms per block's atom lanes
   int force_waves;   // force kernel occupancy target (waves per SIMD): 4 or 5
   int live_duty;     // live rounds: the batch runs one block in live_duty (1: every block)
+  int lin_max_cg;    // linear-response start: updates of the solve at most
+  double lin_tol;    // ... stop at |r| <= lin_tol |f(x0)|
+  double lin_probe;  // ... probe length of the Hessian-vector products
 };
 
 Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
@@ -86,6 +90,9 @@ Tune resolve(const aqs_potential* pot, const aqs_tuning* t) {
   r.tile_fill = tf > 0.0 ? std::max(kFillMin, std::min(tf, kFillMax)) : kFillDefault;
   r.force_waves = (t && t->force_waves == 4) ? 4 : 5;
   r.live_duty = 1;
+  r.lin_max_cg = 50;
+  r.lin_tol = 1e-3;
+  r.lin_probe = 1e-5;
   return r;
 }
 
@@ -122,7 +129,7 @@ struct Layout {
   size_t o_geom, o_state, o_state2, o_cgst, o_cgst2, o_pos4, o_v[3], o_f[3], o_id, o_inv, o_nbc, o_nbl, o_nbp, o_fpart, o_upart, o_upart2,
       o_log, o_ccount, o_cstart, o_cellof, o_order, o_tpos4, o_tv[3], o_tid, o_tbl[2],
       o_tbl2[2], o_reps[2], o_nc3[2], o_overflow[2], o_dg, o_red, o_dl[3], o_tdl[3], o_alt4, o_talt4, o_evals, o_xref4, o_ftbl[2], o_ttbl[2], o_thdr, o_hidx, o_sel[2],
-      o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl[2], o_lftbl[2], o_lsel[2], o_tord;
+      o_zbuf, o_lpart, o_mlp, o_mlpw, o_ltbl[2], o_lftbl[2], o_lsel[2], o_tord, o_lin;
   int64_t atoms = 0;      // padded atoms over all slots
   int64_t nb_entries = 0;
   int32_t blocks = 0;
@@ -240,6 +247,7 @@ aqs_status make_layout(const aqs_potential* pot, const Tune& tn, int n_rep, cons
   lo.o_mlp = take(sizeof(MlpDev));
   lo.o_mlpw = take(sizeof(float) * kNumParams);
   lo.o_tord = take(sizeof(int32_t) * A);
+  lo.o_lin = take(sizeof(LinState) * n_rep);
   lo.total = off;
   return AQS_OK;
 }
@@ -322,6 +330,8 @@ struct aqs_ctx {
   MlpDev* mlp;
   float* mlpw;
   int32_t* tord;             // per tile: atoms by decreasing list length
+  LinState* lin;             // linear-response start: per-slot solve scalars
+  int64_t lin_evals = 0;     // atom evaluations of its solves (host count)
   int mlp_dim = 0;           // 0: no network loaded
   double rd[4], rd2[4], dirs[16][3];
   // host mirrors
@@ -447,7 +457,11 @@ std::vector<int2> make_tile_table(aqs_ctx* c, const std::vector<int32_t>& sel, u
 // from the last state read-back): descriptors and network, or the
 // extrapolation; plain start and the checks, with launch tables over exactly
 // those slots.
-aqs_status learned_group(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls, bool extrap) {
+// The lane's start tables over the slots ls: 256-atom blocks, force tiles
+// of their current grids, the slots.  Returns the block and tile counts.
+// Uses the lane's pinned staging: the lane must be synchronised.
+aqs_status start_tables(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls, int32_t* nblk,
+                        int32_t* ntiles) {
   const std::vector<int2> tb = make_table(c, ls, L.xcd_mask);
   const std::vector<int2> ft = make_tile_table(c, ls, L.xcd_mask);
   std::copy(tb.begin(), tb.end(), L.h_ltbl);
@@ -457,19 +471,156 @@ aqs_status learned_group(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls, bo
   HIPCHK(hipMemcpyAsync(L.lftbl, L.h_lftbl, sizeof(int2) * ft.size(), hipMemcpyHostToDevice, L.s));
   HIPCHK(hipMemcpyAsync(L.lsel_d, L.h_lsel, sizeof(int32_t) * ls.size(), hipMemcpyHostToDevice,
                         L.s));
+  *nblk = (int32_t)tb.size();
+  *ntiles = (int32_t)ft.size();
+  return AQS_OK;
+}
+
+aqs_status learned_group(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls, bool extrap) {
+  int32_t nb = 0, nt = 0;
+  aqs_status st = start_tables(c, L, ls, &nb, &nt);
+  if (st) return st;
   LearnArgs la = learn_args(c, L, 0);
   la.blocks = L.ltbl;
   la.ftiles = L.lftbl;
   la.sel = L.lsel_d;
   la.nsel = (int32_t)ls.size();
   if (extrap) {
-    launch_lextrap(la, (int32_t)tb.size(), c->dim, L.s);
+    launch_lextrap(la, nb, c->dim, L.s);
   } else {
-    launch_ldesc(la, (int32_t)ft.size(), c->dim, L.s);
-    launch_lmlp(la, (int32_t)tb.size(), c->dim, L.s);
+    launch_ldesc(la, nt, c->dim, L.s);
+    launch_lmlp(la, nb, c->dim, L.s);
   }
   launch_lctl(la, L.s);
   HIPCHK(hipGetLastError());
+  return AQS_OK;
+}
+
+aqs_status rebuild(aqs_ctx* c, Lane& L, const std::vector<int32_t>& sel, bool in_loop,
+                   int list_mode);
+aqs_status pull_slots(aqs_ctx* c, Lane& L, const std::vector<int32_t>& slots);
+aqs_status set_table(aqs_ctx* c, Lane& L, const std::vector<int32_t>& sel);
+IterArgs iter_args(aqs_ctx* c, const Lane& L);
+
+// Linear-response start (Eqs. 7-8, linear.hip) of the slots waiting in
+// PH_LDESC: the plain start and k + 1 (the extrapolation kernels with u = 0),
+// a list rebuild where a probe could leave the list's validity, then the
+// conjugate-gradient solve of H u = f(x0), driven from here: per update two
+// probes of the forces and three vector kernels, the stop flags read back
+// every few updates; then u in the start's displacement arrays and the
+// pre-check, phase PH_LPLAIN.
+aqs_status linear_group(aqs_ctx* c, Lane& L, const std::vector<int32_t>& ls) {
+  int32_t nb = 0, nt = 0;
+  aqs_status st = start_tables(c, L, ls, &nb, &nt);
+  if (st) return st;
+  {
+    LearnArgs la = learn_args(c, L, 0);
+    la.blocks = L.ltbl;
+    la.ftiles = L.lftbl;
+    la.sel = L.lsel_d;
+    la.nsel = (int32_t)ls.size();
+    launch_lextrap(la, nb, c->dim, L.s);
+    launch_lctl(la, L.s);
+    HIPCHK(hipGetLastError());
+  }
+  // the probes move atoms by at most lin_probe beyond the plain start: the
+  // list test of the control with that margin, else a rebuild now
+  st = pull_slots(c, L, ls);
+  if (st) return st;
+  std::vector<int32_t> stale;
+  std::vector<std::vector<double>> up(ls.size());
+  for (size_t i = 0; i < ls.size(); ++i) {
+    const Geom& g = c->lo.geom[ls[i]];
+    up[i].resize(g.nblocks);
+    HIPCHK(hipMemcpyAsync(up[i].data(), c->upart + g.block0, sizeof(double) * g.nblocks,
+                          hipMemcpyDeviceToHost, L.s));
+  }
+  HIPCHK(hipStreamSynchronize(L.s));
+  for (size_t i = 0; i < ls.size(); ++i) {
+    const int r = ls[i];
+    const Geom& g = c->lo.geom[r];
+    double ub = 0.0;
+    for (double u : up[i]) ub = std::max(ub, u);
+    ub += c->tn.lin_probe;
+    const State& s = c->h_state[r];
+    bool valid;
+    if (g.dgamma_y == 0.0) {
+      const double gd = std::fabs(strain_of(s.k, g.dgamma) - s.gamma_build);
+      valid = gd * c->rc_max + 2.0 * (1.0 + gd) * ub < c->tn.skin;
+    } else {
+      valid = inverse_strain_norm(g, s.k, s.k_build) * (c->rc_max + 2.0 * ub) < c->rc_max + c->tn.skin;
+    }
+    if (!valid) stale.push_back(r);
+  }
+  if (!stale.empty()) {
+    st = rebuild(c, L, stale, false, 0);
+    if (st) return st;
+    if (L.ftable_stale) {   // the lane's own tables, as after a rebuild in the loop
+      const std::vector<int32_t> keep = L.cur_sel;
+      st = set_table(c, L, keep);
+      if (st) return st;
+    }
+    HIPCHK(hipStreamSynchronize(L.s));
+    st = start_tables(c, L, ls, &nb, &nt);   // the rebuilt grids' tiles
+    if (st) return st;
+  }
+  LinArgs a{};
+  a.blocks = L.ltbl;
+  a.sel = L.lsel_d;
+  a.nsel = (int32_t)ls.size();
+  a.geom = c->d_geom;
+  a.state = c->d_state;
+  a.lin = c->lin;
+  a.pos4 = c->pos4;
+  a.x0 = c->alt4;
+  a.fx = c->fx; a.fy = c->fy; a.fz = c->fz;
+  a.ux = c->dlx; a.uy = c->dly; a.uz = c->dlz;
+  a.px = c->vx; a.py = c->vy; a.pz = c->vz;
+  a.r4 = c->tpos4;
+  a.hx = c->tvx; a.hy = c->tvy; a.hz = c->tvz;
+  a.part = c->lpart;
+  a.probe = c->tn.lin_probe;
+  a.tol = c->tn.lin_tol;
+  a.max_move = 0.1;
+  IterArgs fa = iter_args(c, L);
+  fa.ftiles = L.lftbl;
+  fa.one_rep = -1;
+  launch_lin_begin(a, L.s);
+  launch_force(fa, nt, c->dim, L.s);   // f(x0)
+  launch_lin_init(a, nb, c->dim, L.s);
+  launch_lin_start(a, L.s);
+  int64_t pairs = 0;
+  for (int it = 0; it < c->tn.lin_max_cg; ++it) {
+    a.it = it;
+    launch_lin_probe(a, 1, nb, c->dim, L.s);
+    launch_force(fa, nt, c->dim, L.s);
+    launch_lin_probe(a, -1, nb, c->dim, L.s);
+    launch_force(fa, nt, c->dim, L.s);
+    launch_lin_hp(a, nb, c->dim, L.s);
+    launch_lin_update(a, nb, c->dim, L.s);
+    launch_lin_direction(a, nb, c->dim, L.s);
+    HIPCHK(hipGetLastError());
+    ++pairs;
+    if ((it + 1) % 4 == 0 && it + 1 < c->tn.lin_max_cg) {   // stop once every solve has
+      std::vector<LinState> cur(ls.size());
+      for (size_t i = 0; i < ls.size(); ++i)
+        HIPCHK(hipMemcpyAsync(&cur[i], c->lin + ls[i], sizeof(LinState), hipMemcpyDeviceToHost, L.s));
+      HIPCHK(hipStreamSynchronize(L.s));
+      bool all = true;
+      for (const LinState& q : cur) all = all && q.done;
+      if (all) break;
+    }
+  }
+  launch_lin_finish(a, nb, c->dim, L.s);
+  HIPCHK(hipGetLastError());
+  // evaluations for the counters: f(x0) and two per Hessian-vector product
+  std::vector<LinState> fin(ls.size());
+  for (size_t i = 0; i < ls.size(); ++i)
+    HIPCHK(hipMemcpyAsync(&fin[i], c->lin + ls[i], sizeof(LinState), hipMemcpyDeviceToHost, L.s));
+  HIPCHK(hipStreamSynchronize(L.s));
+  for (size_t i = 0; i < ls.size(); ++i)
+    c->lin_evals += (int64_t)c->lo.geom[ls[i]].n * (1 + 2 * (int64_t)fin[i].probes);
+  c->cnt.force_launches += 1 + 2 * pairs;
   return AQS_OK;
 }
 
@@ -758,8 +909,7 @@ void reset_minimizer(aqs_ctx* c, State& s);
 // snapshot slot snap_dst[i]; lists are rebuilt.
 aqs_status start_chains(aqs_ctx* c, const std::vector<int32_t>& sel, int32_t start_mode,
                         const int32_t* n_steps, const int32_t* snap_dst) {
-  if (start_mode != AQS_START_PLAIN && start_mode != AQS_START_LEARNED &&
-      start_mode != AQS_START_EXTRAPOLATED)
+  if (start_mode != AQS_START_PLAIN && !predicted_start_mode(start_mode))
     return fail(AQS_EINVAL, "unknown start mode %d", start_mode);
   if (start_mode == AQS_START_LEARNED && c->mlp_dim != c->dim)
     return fail(AQS_ESTATE, "the learned start needs a network (aqs_learned_load)");
@@ -825,14 +975,16 @@ aqs_status lane_launch(aqs_ctx* c, Lane& L, int32_t start_mode, bool allow_timed
       L.ev.push_back(e);
     }
   }
-  if (start_mode == AQS_START_LEARNED || start_mode == AQS_START_EXTRAPOLATED) {
+  if (predicted_start_mode(start_mode)) {
     // slots that finished a minimisation since the last read-back wait in
     // PH_LDESC: the predicted displacement and plain start for them now
     std::vector<int32_t> ls;
     for (int r : L.cur_sel)
       if (c->h_state[r].phase == PH_LDESC) ls.push_back(r);
     if (!ls.empty()) {
-      aqs_status st = learned_group(c, L, ls, start_mode == AQS_START_EXTRAPOLATED);
+      aqs_status st = (start_mode == AQS_START_LINEAR)
+                          ? linear_group(c, L, ls)
+                          : learned_group(c, L, ls, start_mode == AQS_START_EXTRAPOLATED);
       if (st) return st;
     }
   }
@@ -1141,6 +1293,7 @@ aqs_status aqs_create(const aqs_potential* pot, const aqs_fire_params* fire,
   c->mlp = at<MlpDev>(w, lo.o_mlp);
   c->mlpw = at<float>(w, lo.o_mlpw);
   c->tord = at<int32_t>(w, lo.o_tord);
+  c->lin = at<LinState>(w, lo.o_lin);
 
   const size_t tcap = table_cap(std::max(lo.blocks, lo.tiles));
   bool pinned = hipHostMalloc((void**)&c->h_state, sizeof(State) * n_rep, hipHostMallocDefault) == hipSuccess &&
@@ -1804,6 +1957,17 @@ aqs_status aqs_set_dgamma(aqs_ctx* c, int32_t n_sel, const int32_t* rep, const d
   return AQS_OK;
 }
 
+aqs_status aqs_set_linear_start(aqs_ctx* c, int32_t max_cg, double tol, double probe) {
+  if (!c) return fail(AQS_EINVAL, "null context");
+  if (max_cg < 1 || max_cg > 100000) return fail(AQS_EINVAL, "max_cg %d outside [1, 100000]", max_cg);
+  if (!(tol > 0.0 && tol < 1.0)) return fail(AQS_EINVAL, "tol %g outside (0, 1)", tol);
+  if (!(probe > 0.0 && probe < 0.1)) return fail(AQS_EINVAL, "probe %g outside (0, 0.1)", probe);
+  c->tn.lin_max_cg = max_cg;
+  c->tn.lin_tol = tol;
+  c->tn.lin_probe = probe;
+  return AQS_OK;
+}
+
 aqs_status aqs_set_live_duty(aqs_ctx* c, int32_t duty) {
   if (!c) return fail(AQS_EINVAL, "null context");
   if (duty < 1 || duty > 64) return fail(AQS_EINVAL, "live duty %d outside [1, 64]", duty);
@@ -1854,11 +2018,12 @@ aqs_status aqs_get_counters(aqs_ctx* c, aqs_counters* out, int32_t reset) {
   unsigned long long ev[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(ev, c->evals, sizeof ev, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  c->cnt.atom_evals = (int64_t)ev[0];
+  c->cnt.atom_evals = (int64_t)ev[0] + c->lin_evals;
   c->cnt.timed_atom_evals = (int64_t)ev[1];
   if (out) *out = c->cnt;
   if (reset) {
     c->cnt = aqs_counters{};
+    c->lin_evals = 0;
     HIPCHK(hipMemsetAsync(c->evals, 0, sizeof ev, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }

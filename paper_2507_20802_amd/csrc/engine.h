@@ -77,6 +77,8 @@ enum Phase : int32_t {
   PH_LREVERT = 10,  // learned start rejected: update restores the plain start
   PH_LPLAIN = 12,   // learned start: evaluate at the plain start (reference E, max |F|)
   PH_CG = 13,       // evaluate forces; conjugate-gradient control; CG update
+  PH_LPROBE = 14,   // linear-response start: forces at a probe of the Hessian
+                    // solve (the host drives the solve; no control)
 };
 
 // minimiser of a slot (State::minimizer; AQS_MIN_* of the public header)
@@ -85,15 +87,33 @@ constexpr int32_t kMinFire = 0, kMinCG = 1;
 // start of a minimisation (StepRecord::start; State::start_mode): the affine
 // image, the learned start, the affine image after a learned or extrapolated
 // start was rejected, the extrapolated start
-constexpr int32_t kStartPlain = 0, kStartLearned = 1, kStartFallback = 2, kStartExtrap = 3;
+constexpr int32_t kStartPlain = 0, kStartLearned = 1, kStartFallback = 2, kStartExtrap = 3,
+                  kStartLinear = 4;
+
+// a start predicted at each inherent structure before the next fine step
+__host__ __device__ inline bool predicted_start_mode(int32_t m) {
+  return m == kStartLearned || m == kStartExtrap || m == kStartLinear;
+}
 
 __host__ __device__ inline bool phase_energy(int32_t ph) {  // evaluation also sums E
   return ph == PH_EVAL || ph == PH_ENERGY || ph == PH_LPLAIN || ph == PH_LMOVE;
 }
 __host__ __device__ inline bool phase_force(int32_t ph) {   // the force kernel evaluates
   return phase_energy(ph) || ph == PH_FIRE || ph == PH_CG || ph == PH_ADVANCE ||
-         ph == PH_LREVERT;
+         ph == PH_LREVERT || ph == PH_LPROBE;
 }
+
+// Scalars of a slot's linear-response solve (conjugate gradients on
+// H u = f(x0), Eqs. 7-8): written by the owner block of its kernels, read by
+// every block of the next.
+struct LinState {
+  double rr[2];   // |r|^2 of the current residual, by parity of the iteration
+  double bb;      // |f(x0)|^2
+  int32_t iters;  // completed updates of u
+  int32_t done;   // the solve has stopped (converged or non-positive curvature)
+  int32_t probes; // Hessian-vector products formed (two force evaluations each)
+  int32_t pad_;
+};
 
 // static per-slot geometry
 struct Geom {

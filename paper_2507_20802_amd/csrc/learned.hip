@@ -437,7 +437,8 @@ __global__ __launch_bounds__(kBlock) void k_lmlp(LearnArgs a) {
 // wrapped with the atoms by every list rebuild), so u is a plain difference.
 // From the second fine step of a call on; before that there is no history
 // and u = 0 (k_lctl then rejects the start).  Same tail as the network:
-// dl, partials, snapshot, plain start.
+// dl, partials, snapshot, plain start.  Slots of the linear-response start
+// take u = 0 here: the plain start only (the solve follows, linear.hip).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_lextrap(LearnArgs a) {
   const int2 bt = a.blocks[blockIdx.x];
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_lextrap(LearnArgs a) {
   const int li = bt.y * kBlock + threadIdx.x;
   const bool live = li < g.n;
   double ux = 0.0, uy = 0.0, uz = 0.0;
-  if (live && st->step >= 2) {
+  if (live && st->start_mode == kStartExtrap && st->step >= 2) {
     const int64_t gi = g.atom_off + li;
     const double4 p = a.pos4[gi], q = a.alt4[gi];
     ux = (p.x - q.x) / g.dgamma;

@@ -423,10 +423,10 @@ __device__ __forceinline__ void finish_min(const IterArgs& a, int rep, State& s,
     s.restart = 0;
     s.cv = 1.0;
     s.cf = 0.0;
-    if (s.start_mode == kStartLearned || s.start_mode == kStartExtrap) {
+    if (predicted_start_mode(s.start_mode)) {
       // the predicted displacement at this inherent structure first (the
-      // network or the extrapolation); the strain index advances with the
-      // plain start (learned kernels)
+      // network, the extrapolation or the linear response); the strain
+      // index advances with the plain start (learned kernels)
       s.start_used = kStartFallback;
       s.phase = PH_LDESC;
     } else {
@@ -601,7 +601,7 @@ __device__ __forceinline__ void control(const IterArgs& a, int rep, const Geom& 
       s.phase = PH_LREVERT;
       return;
     }
-    s.start_used = (s.start_mode == kStartExtrap) ? kStartExtrap : kStartLearned;
+    s.start_used = s.start_mode;   // the predicted start is kept
   }
   s.phase = cg ? PH_CG : PH_FIRE;
   if (r[6] != 0.0 || !isfinite(r[1]) || !isfinite(r[2])) {
@@ -1077,9 +1077,12 @@ __global__ __launch_bounds__(kBlock) void k_step(IterArgs a) {
       a.vy[gi] = 0.0;
       if (D == 3) a.vz[gi] = 0.0;
     } else if (lmove) {
-      const double ux = g.dgamma * (a.dlx[gi] - ss.lmean[0]);
-      const double uy = g.dgamma * (a.dly[gi] - ss.lmean[1]);
-      const double uz = (D == 3) ? g.dgamma * (a.dlz[gi] - ss.lmean[2]) : 0.0;
+      // dl holds u_hat per unit strain (network, extrapolation), or the
+      // displacement itself (linear response, lmean = 0: exactly x0 + u)
+      const double sc = (ss.start_mode == kStartLinear) ? 1.0 : g.dgamma;
+      const double ux = sc * (a.dlx[gi] - ss.lmean[0]);
+      const double uy = sc * (a.dly[gi] - ss.lmean[1]);
+      const double uz = (D == 3) ? sc * (a.dlz[gi] - ss.lmean[2]) : 0.0;
       if (phase == PH_LMOVE) {
         p.x += ux;
         p.y += uy;

@@ -353,6 +353,13 @@ class Engine:
                                        dg.ctypes.data_as(_lib.c_double_p)), "aqs_set_dgamma")
         self.dgamma[sel] = dg
 
+    def set_linear_start(self, max_cg: int = 50, tol: float = 1e-3, probe: float = 1e-5) -> None:
+        """Parameters of the linear-response start (AQS_START_LINEAR): at most
+        max_cg conjugate-gradient updates, stop at |r| <= tol |f(x0)|, probe
+        length of the Hessian-vector products."""
+        check(self._lib.aqs_set_linear_start(self._ctx, int(max_cg), float(tol), float(probe)),
+              "aqs_set_linear_start")
+
     def set_live_duty(self, duty: int) -> None:
         """Later live rounds: the batch of speculative chains runs one block of
         iterations in `duty` while a critical chain runs (1: always); changes no
