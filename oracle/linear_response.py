@@ -10,7 +10,7 @@ start x0.  Here H = H(x0), and H v comes from central differences of the
 forces, H v ~ (f(x0 - h v^) - f(x0 + h v^)) / (2 h) * max_i |v_i| with
 v^ = v / max_i |v_i| (probe h in the max norm).
 
-Steps, in order (the GPU follows the same ones):
+Steps, in order (the GPU's AQS_START_LINEAR takes the same ones):
   1  b = f(x0); r = b; p = r; u = 0; rr = |r|^2; bb = rr
   2  repeat at most max_cg times:
        pmax = max_i |p_i|; Hp from the probes x0 -/+ (h / pmax) p
