@@ -89,3 +89,49 @@ def test_linear_start_parameters_are_checked():
         with pytest.raises(AQSError):
             eng.set_linear_start(*bad)
     eng.set_linear_start(10, 1e-2, 1e-6)
+
+
+@pytest.mark.parametrize("live", [False, True])
+def test_algorithm1_with_the_linear_start_matches_the_oracle(live):
+    """Algorithm 1 whose every fine step starts from the linear response
+    (batched, and live: the critical chain's solves on its own stream beside
+    the batch's): the oracle's decisions, q per round and final r_star."""
+    from paper_2507_20802_amd import AQS_START_LINEAR, Engine, parallel
+    from oracle.alg1 import aqs_parallel
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, ofire = fire_pair()
+    dg, K, P, n = 1e-4, 4, 3, 12
+
+    def box(k):
+        return O.strain_box(dim, L, k, dg)
+
+    def step(x, k):
+        start = linear_response_start(O.affine(x, dg), types, box(k), POT)[0]
+        return O.fire(start, types, box(k), POT, ofire).pos
+
+    def level1(r, m):
+        return (r[0] + m, O.affine(r[1], m * dg))
+
+    def level2(anchors, lengths):
+        out = []
+        for (k, x), ln in zip(anchors, lengths):
+            y = O.fire(x, types, box(k), POT, ofire).pos
+            first = (k, y)
+            for j in range(1, ln + 1):
+                y = step(y, k + j)
+            out.append((first, (k + ln, y)))
+        return out
+
+    def equal(a, b):
+        return O.compare(a[1], b[1], box(a[0]))[0] < 1e-4
+
+    ref = aqs_parallel((0, pos), n, K, P, level1, level2, equal)
+    eng = Engine(dim, [len(types)] * parallel.slots_needed(1, P), L, dg, fire=fire)
+    g = parallel.layout(1, P)[0]
+    eng.set_replica(g.star, types, pos, 0)
+    out = parallel.run(eng, [g], n, K, P, delta_eq=1e-4, start=AQS_START_LINEAR, live=live)
+    assert [r["checks"] for r in g.rounds] == [r.checks for r in ref.rounds]
+    assert [r["q"] for r in g.rounds] == [r.q for r in ref.rounds]
+    assert out["accepted_steps"] == n and out["statuses_ok"]
+    assert AQS_START_LINEAR in g.step_starts
+    assert O.compare(eng.positions(g.star), ref.r_star[1], box(n))[0] < 1e-8
