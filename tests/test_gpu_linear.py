@@ -135,3 +135,41 @@ def test_algorithm1_with_the_linear_start_matches_the_oracle(live):
     assert out["accepted_steps"] == n and out["statuses_ok"]
     assert AQS_START_LINEAR in g.step_starts
     assert O.compare(eng.positions(g.star), ref.r_star[1], box(n))[0] < 1e-8
+
+
+@pytest.mark.parametrize("kind", ["pure_shear", "cg"])
+def test_linear_response_start_under_pure_shear_and_with_cg(kind):
+    """The same solve for a pure-sheared slot (Eq. 17: the plain start and
+    the list test of the general box) and under the conjugate-gradient
+    minimiser: the oracle's start decisions, energies and end state."""
+    from paper_2507_20802_amd import AQS_START_FALLBACK, AQS_START_LINEAR, Cg, Engine
+    pos, types, L, dim = load_glass("glass2d_256")
+    fire, ofire = fire_pair()
+    dg, nst = 1e-4, 3
+    dgy = 5e-5 if kind == "pure_shear" else 0.0
+    cg = Cg()
+    ocg = O.CgParams(**{k: getattr(cg, k) for k in O.CgParams.__dataclass_fields__})
+    out, x = [], pos
+    for k in range(1, nst + 1):
+        H = O.strain_box(dim, L, k, dg, dgy)
+        start, iters, ok, _ = linear_response_start(O.affine(x, dg, dgy), types, H, POT)
+        r = O.cg(start, types, H, POT, ocg) if kind == "cg" else O.fire(start, types, H, POT, ofire)
+        assert r.status == O.CONVERGED
+        out.append((r.E, ok, r.pos))
+        x = r.pos
+    eng = Engine(dim, [len(types)], L, dg, fire=fire)
+    if kind == "cg":
+        eng.set_minimizer("cg", cg)
+    else:
+        eng.set_pure_shear([0], dgy)
+    eng.set_replica(0, types, pos, 0)
+    recs = eng.minimize([0], n_steps=[nst], start=AQS_START_LINEAR)[0]
+    for k in range(1, nst + 1):
+        E, ok, _ = out[k - 1]
+        assert recs[k]["status"] == 0
+        assert recs[k]["start"] == (AQS_START_LINEAR if ok else AQS_START_FALLBACK), k
+        assert abs(recs[k]["energy"] - E) <= E_REL_TOL * abs(E)
+    H = O.strain_box(dim, L, nst, dg, dgy)
+    got = eng.positions(0)
+    assert O.compare(got, out[-1][2], H)[0] <= POS_TOL
+    assert certified_fmax(got, types, H) < FTOL
