@@ -263,15 +263,16 @@ __device__ __forceinline__ void halo_pair(uint32_t off, const double4& pi, const
   pair_term<D, WE, false>(true, dx, dy, dz, q, fx, fy, fz, e, w);
 }
 
-// Groups of the packed list in flight ahead of the one being summed: a
-// lane's share of a list is about a dozen groups, and with one wavefront
-// per SIMD (a single chain fills the GPU about once) every round trip to
-// memory that is not overlapped shows in the launch time.
-constexpr int kGroupsAhead = 4;
+// Groups of the packed list in flight ahead of the one being summed.
+// Measured on one 32768-atom replica and on a batch of 16 (3D, two lanes
+// per atom): one group ahead is the fastest, 2 % and 3 % faster per
+// iteration than four; six, eight and twelve are slower still (the extra
+// loads in flight cost more than the latency they hide).
+constexpr int kGroupsAhead = 1;
 
 // One segment of a packed list: this lane's groups k = 0 .. my - 1, with
-// kGroupsAhead groups (16 entries) in flight ahead of the four pairs being
-// summed.
+// kGroupsAhead groups (four entries each) in flight ahead of the four pairs
+// being summed.
 template <int D, bool WE>
 __device__ __forceinline__ void packed_segment(const double4 pi, __amdgpu_buffer_rsrc_t rs,
                                                uint32_t lb, uint32_t sb, uint32_t ss, int my,
