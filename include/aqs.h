@@ -150,8 +150,9 @@ typedef struct {
   double sigma_xy;    /* shear stress at the last force evaluation */
   int32_t status;     /* AQS_CONVERGED ... */
   int32_t start;      /* start used: AQS_START_PLAIN, AQS_START_LEARNED,
-                         AQS_START_EXTRAPOLATED, or AQS_START_FALLBACK (a
-                         predicted start asked for and rejected) */
+                         AQS_START_EXTRAPOLATED, AQS_START_LINEAR, or
+                         AQS_START_FALLBACK (a predicted start asked for and
+                         rejected) */
 } aqs_step_record;
 
 /* Bytes of device workspace a context with these slots needs.  n_atoms:
