@@ -241,8 +241,8 @@ def main() -> int:
         return copy_calibration(args.copy_calibration)
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(the multi-GPU sharding is design only).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the engine "
+              f"drives one GPU; sharding over several is described, not implemented).", file=sys.stderr)
         return 2
     extra = [f for f in args.forms.split(",") if f]
     for f in extra:
