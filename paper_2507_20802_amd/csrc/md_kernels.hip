@@ -233,10 +233,12 @@ __device__ __forceinline__ void atom_pairs(const double4 pi, int ti, const uint3
   combine_lanes<D, WE, TPA>(fx, fy, fz, e, w);
 }
 
-// Cache policy of the packed-list loads: non-temporal.  Each list word is
-// read once per launch, and streaming it through L2 at normal priority
-// evicts the halo positions, which every tile re-reads.
-constexpr int kListCachePolicy = 2;
+// Cache policy of the packed-list loads: the default (cached in L2).  The
+// lists stay the same between rebuilds, hundreds of iterations, and with
+// each lane loading only its own groups a 16-replica batch keeps enough of
+// them in the XCDs' L2s: 67 against 73 us per launch with non-temporal
+// loads; one replica runs within 1 % either way.
+constexpr int kListCachePolicy = 0;
 
 // Group k of this lane's share of a packed list segment: the 8 bytes (four
 // 16-bit entries) at byte offset lb + sb + k ss, k clamped below gcap so the
