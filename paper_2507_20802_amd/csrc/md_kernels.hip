@@ -265,34 +265,22 @@ __device__ __forceinline__ void halo_pair(uint32_t off, const double4& pi, const
   pair_term<D, WE, false>(true, dx, dy, dz, q, fx, fy, fz, e, w);
 }
 
-// Groups of the packed list in flight ahead of the one being summed.
-// Measured on one 32768-atom replica and on a batch of 16 (3D, two lanes
-// per atom), each lane loading only its own groups: one group ahead is the
-// fastest for one replica (two and four ahead 0.5 % and 1.5 % slower per
-// iteration) and within 0.3 % of the best for the batch.
-constexpr int kGroupsAhead = 1;
-
-// One segment of a packed list: this lane's groups k = 0 .. my - 1, with
-// kGroupsAhead groups (four entries each) in flight ahead of the four pairs
-// being summed.
+// One segment of a packed list: this lane's groups k = 0 .. my - 1, each
+// summed while the next one is in flight (one group ahead: measured on one
+// 32768-atom replica and on a batch of 16, 3D, two lanes per atom, deeper
+// prefetch is no faster).  `next` is the segment's first group, requested
+// by the caller together with the other segment's, so that neither segment
+// starts on a cold load; only the lane's own groups are loaded.
 template <int D, bool WE>
 __device__ __forceinline__ void packed_segment(const double4 pi, __amdgpu_buffer_rsrc_t rs,
                                                uint32_t lb, uint32_t sb, uint32_t ss, int my,
-                                               int gcap, const PairParams q, const double* hx,
-                                               const double* hy, const double* hz, double& fx,
-                                               double& fy, double& fz, double& e, double& w) {
-  // only the lane's own groups are loaded (a group past its last would be
-  // fetched for nothing)
-  uint2 ahead[kGroupsAhead];
-#pragma unroll
-  for (int u = 0; u < kGroupsAhead; ++u)
-    ahead[u] = u < my ? packed_group(rs, lb, sb, ss, u, gcap) : make_uint2(0u, 0u);
+                                               int gcap, uint2 next, const PairParams q,
+                                               const double* hx, const double* hy,
+                                               const double* hz, double& fx, double& fy,
+                                               double& fz, double& e, double& w) {
   for (int k = 0; k < my; ++k) {
-    const uint2 cur = ahead[0];
-#pragma unroll
-    for (int u = 0; u + 1 < kGroupsAhead; ++u) ahead[u] = ahead[u + 1];
-    if (k + kGroupsAhead < my)
-      ahead[kGroupsAhead - 1] = packed_group(rs, lb, sb, ss, k + kGroupsAhead, gcap);
+    const uint2 cur = next;
+    if (k + 1 < my) next = packed_group(rs, lb, sb, ss, k + 1, gcap);
     halo_pair<D, WE>(cur.x & 0xffffu, pi, hx, hy, hz, q, fx, fy, fz, e, w);
     halo_pair<D, WE>(cur.x >> 16, pi, hx, hy, hz, q, fx, fy, fz, e, w);
     halo_pair<D, WE>(cur.y & 0xffffu, pi, hx, hy, hz, q, fx, fy, fz, e, w);
@@ -324,10 +312,13 @@ __device__ __forceinline__ void atom_pairs_packed(const double4 pi, int ti, cons
   const uint32_t step = (uint32_t)TPA * row_bytes;
   const uint32_t lba = 8u * (uint32_t)col + (uint32_t)sub * row_bytes;
   const uint32_t lbb = 8u * (uint32_t)col + (uint32_t)(TPA - 1 - sub) * row_bytes;
-  packed_segment<D, WE>(pi, rs, lba, 0u, step, my_a, gcap, pp[2 * ti], hx, hy, hz, fx, fy, fz, e,
-                        w);
-  packed_segment<D, WE>(pi, rs, lbb, (uint32_t)(G - TPA) * row_bytes, 0u - step, my_b, gcap,
-                        pp[2 * ti + 1], hx, hy, hz, fx, fy, fz, e, w);
+  const uint32_t sbb = (uint32_t)(G - TPA) * row_bytes;
+  const uint2 first_a = my_a > 0 ? packed_group(rs, lba, 0u, step, 0, gcap) : make_uint2(0u, 0u);
+  const uint2 first_b = my_b > 0 ? packed_group(rs, lbb, sbb, 0u - step, 0, gcap) : make_uint2(0u, 0u);
+  packed_segment<D, WE>(pi, rs, lba, 0u, step, my_a, gcap, first_a, pp[2 * ti], hx, hy, hz, fx, fy,
+                        fz, e, w);
+  packed_segment<D, WE>(pi, rs, lbb, sbb, 0u - step, my_b, gcap, first_b, pp[2 * ti + 1], hx, hy, hz,
+                        fx, fy, fz, e, w);
   combine_lanes<D, WE, TPA>(fx, fy, fz, e, w);
 }
 
