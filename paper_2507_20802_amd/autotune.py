@@ -6,7 +6,11 @@ kernel (which also sets the force-tile length), the force tiles' fill of a
 block, the force kernel's occupancy hint (waves per SIMD), the Verlet skin
 (list length against rebuild frequency), the FIRE iterations launched
 between state read-backs and their replay as a hipGraph; for live rounds of Algorithm 1 also the compute units left to the
-critical chain (XCDs reserved for it, batch force blocks per CU).  For a
+critical chain (XCDs reserved for it, batch force blocks per CU).  Graph
+replay is chosen twice: first on the batch, then, for shapes that hold live
+rounds, on one replica alone -- the critical chain, which sets a live
+round's time and runs bound by launch latency, so replay can pay there when
+it does not in the batch.  For a
 shape (dim, atoms per slot, slots) the tuner times short device chains of
 AQS steps of a seeded glass on the GPU (coordinate descent from the
 defaults), then, with enough slots for two chains and their snapshots,
@@ -193,7 +197,7 @@ def _same_round(a, b) -> bool:
 
 def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 5000, repeats: int = 2, passes: int = 1,
          dg: float = 5e-5, seed: int = 11, cache: str | None = None, log=None,
-         live_steps: int = 20) -> dict:
+         live_steps: int = 20, crit_steps: int = 10) -> dict:
     """Tune the knobs for the shape, store and return the cache entry."""
     s, is_pos = _glass(dim, n_atoms, seed)
     best = dict(DEFAULT)
@@ -218,8 +222,25 @@ def tune(dim: int, n_atoms: int, n_rep: int, iters: int = 5000, repeats: int = 2
     check = _same_inherent_structure(dim, n_atoms, s, is_pos, best, dg)
     if not check["ok"]:
         best, best_t = dict(DEFAULT), run(DEFAULT)
+    crit = None
+    if n_rep >= 5:
+        # the critical chain of a live round: one replica alone; graph replay
+        # leaves every result bitwise unchanged, so only time decides
+        crit = {}
+        for g in KNOBS["use_graph"]:
+            crit[g] = min(_trial(dim, n_atoms, 1, s, is_pos, dict(best, use_graph=g), iters, dg,
+                                 steps=crit_steps) for _ in range(repeats))
+            if log:
+                log(f"critical chain use_graph={g}: {crit[g] * 1e3:.1f} ms")
+        g = min(crit, key=crit.get)
+        if g != best["use_graph"]:
+            best = dict(best, use_graph=g)
+            best_t = run(best)
     entry = {"knobs": best, "ms": best_t * 1e3, "default_ms": run(DEFAULT) * 1e3,
              "trials": len(timed), "max_iter": iters, "parity": check}
+    if crit is not None:
+        entry["critical_chain"] = {"steps": crit_steps,
+                                   "ms_by_use_graph": {str(k): v * 1e3 for k, v in crit.items()}}
     if n_rep >= 5:
         # live rounds: the critical chain's share of the GPU, on top of the
         # batched winner

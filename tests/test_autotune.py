@@ -52,12 +52,16 @@ def test_tuning_run_picks_a_checked_winner(tmp_path):
 
 @pytest.mark.gpu
 def test_live_tuning_keeps_the_round(tmp_path):
-    """With slots for two chains and their snapshots the tuner also times
-    live rounds over the critical chain's share of the GPU; the winner makes
-    the same decisions and minimisations as the default."""
+    """With slots for two chains and their snapshots the tuner also chooses
+    graph replay on one replica alone (the critical chain) and times live
+    rounds over the critical chain's share of the GPU; the winner makes the
+    same decisions and minimisations as the default."""
     path = str(tmp_path / "tune.json")
-    entry = A.tune(2, 1000, 5, iters=400, repeats=1, cache=path, live_steps=3)
+    entry = A.tune(2, 1000, 5, iters=400, repeats=1, cache=path, live_steps=3, crit_steps=3)
     assert entry["parity"]["ok"] and entry["live"]["same_round_as_default"]
+    crit = entry["critical_chain"]["ms_by_use_graph"]
+    assert set(crit) == {"0", "1"}
+    assert crit[str(entry["knobs"]["use_graph"])] == min(crit.values())
     for k, v in entry["knobs"].items():
         assert v in (A.KNOBS.get(k) or A.LIVE_KNOBS[k])
     assert set(A.LIVE_KNOBS) <= set(entry["knobs"])
