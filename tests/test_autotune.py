@@ -66,3 +66,32 @@ def test_live_tuning_keeps_the_round(tmp_path):
         assert v in (A.KNOBS.get(k) or A.LIVE_KNOBS[k])
     assert set(A.LIVE_KNOBS) <= set(entry["knobs"])
     assert entry["live"]["ms"] <= entry["live"]["default_ms"] * 1.0001
+
+
+def test_graph_replay_is_chosen_on_the_critical_chain(tmp_path, monkeypatch):
+    """Host logic of the tuner with stubbed timings: for a shape that holds
+    live rounds, graph replay is decided by one replica's chain (the
+    critical chain), not by the batch, and the batch's winner is kept for
+    every other knob; a shape without live rounds keeps the batch's choice."""
+    def trial(dim, n, n_rep, s, is_pos, knobs, iters, dg, steps=3):
+        if n_rep == 1:                       # one replica: replay pays
+            return 1.0 if knobs["use_graph"] else 1.2
+        t = 2.0 - (0.1 if knobs["skin"] == 0.25 else 0.0)
+        return t + (0.01 if knobs["use_graph"] else 0.0)   # the batch: replay costs a little
+
+    monkeypatch.setattr(A, "_glass", lambda dim, n, seed: (None, None))
+    monkeypatch.setattr(A, "_trial", trial)
+    monkeypatch.setattr(A, "_same_inherent_structure",
+                        lambda *a, **k: {"ok": True, "energy_rel": 0.0, "max_disp": 0.0})
+    monkeypatch.setattr(A, "_live_trial", lambda dim, n, n_rep, s, is_pos, knobs, dg, steps:
+                        (1.0 + 0.1 * knobs["live_xcds"], ([], [])))
+    monkeypatch.setattr(A, "_same_round", lambda a, b: True)
+    monkeypatch.setattr(A, "device_name", lambda: "stub")
+    path = str(tmp_path / "t.json")
+    live = A.tune(3, 1000, 5, repeats=1, cache=path)
+    assert live["knobs"]["use_graph"] == 1 and live["knobs"]["skin"] == 0.25
+    assert live["critical_chain"]["ms_by_use_graph"] == {"0": 1200.0, "1": 1000.0}
+    assert live["knobs"]["live_xcds"] == 0
+    batch = A.tune(3, 1000, 4, repeats=1, cache=path)
+    assert batch["knobs"]["use_graph"] == 0 and "critical_chain" not in batch
+    assert set(A.load_cache(path)) == {A.bucket_key(3, 1000, 5, "stub"), A.bucket_key(3, 1000, 4, "stub")}
