@@ -28,3 +28,20 @@ def test_unknown_form_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--forms", "nonsense"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and r.stdout == ""
+
+
+def test_committed_traffic_counters_match_the_kernel_sources():
+    """The force kernel's copy-calibrated counter summary under profiles/ was
+    taken with the kernel sources as they are (same hash), so the benchmark
+    line carries its traffic; and that traffic is (read + written bytes per
+    atom) x atoms per launch."""
+    import json
+    sys.path.insert(0, ROOT)
+    import bench
+    with open(os.path.join(ROOT, "profiles", "k_force_3d_hbm_traffic.txt")) as fh:
+        t = [json.loads(line.split(":", 1)[1]) for line in fh if line.startswith("traffic_json:")]
+    assert len(t) == 1 and t[0]["sources_sha256"] == bench.kernel_sources_sha256()
+    per_atom = t[0]["fetch_bytes_per_atom"] + t[0]["write_bytes_per_atom"]
+    assert per_atom > bench.FORCE_BYTES_PER_ATOM[3]
+    assert bench.force_traffic(3, 1000.0) == per_atom * 1000.0
+    assert bench.force_traffic(2, 1000.0) is None or bench.force_traffic(2, 1000.0) > 0
